@@ -1,0 +1,274 @@
+"""ctypes binding of the plain FP64 CPU oracle (``pd_oracle.c``).
+
+TEST INFRASTRUCTURE ONLY: the test-suite, the smoke check and the CPU-baseline
+leg of the benchmark use it.  The product path (the HIP library and its
+Python binding) never imports this package.
+
+Position vectors are numpy arrays of shape (n_v, 3) in the scene's original
+vertex order.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+import subprocess
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+_SRC = os.path.join(_HERE, "pd_oracle.c")
+_LIB = os.path.join(_HERE, "libpdoracle.so")
+_lib = None
+
+_dp = ctypes.POINTER(ctypes.c_double)
+_ip = ctypes.POINTER(ctypes.c_int)
+
+
+def build(force: bool = True) -> str:
+    """Compile the oracle with gcc (plain IEEE FP64: no fast-math, no FMA contraction)."""
+    if force or not os.path.exists(_LIB) or os.path.getmtime(_LIB) < os.path.getmtime(_SRC):
+        tmp = _LIB + ".tmp"
+        subprocess.check_call(["gcc", "-O2", "-ffp-contract=off", "-fno-fast-math", "-fPIC", "-shared",
+                               "-o", tmp, _SRC, "-lm"])
+        os.replace(tmp, _LIB)
+    return _LIB
+
+
+def lib():
+    global _lib
+    if _lib is None:
+        if not os.path.exists(_LIB) or os.path.getmtime(_LIB) < os.path.getmtime(_SRC):
+            build(force=True)
+        L = ctypes.CDLL(_LIB)
+        L.or_scene_create.restype = ctypes.c_void_p
+        L.or_scene_create.argtypes = [ctypes.c_int, ctypes.c_int, _dp, _ip, ctypes.c_char_p, _dp, _dp, _dp]
+        L.or_scene_destroy.argtypes = [ctypes.c_void_p]
+        L.or_scene_nfree.argtypes = [ctypes.c_void_p]
+        L.or_scene_info.argtypes = [ctypes.c_void_p, _dp, _dp, _dp, _dp, _dp]
+        L.or_svd3.argtypes = [_dp, _dp, _dp, _dp]
+        L.or_prox_stretch.argtypes = [_dp, ctypes.c_double, ctypes.c_double, ctypes.c_double, _dp]
+        L.or_prox_map.argtypes = [_dp, ctypes.c_double, ctypes.c_double, ctypes.c_double, _dp]
+        L.or_prox_jacobian.argtypes = [_dp, ctypes.c_double, ctypes.c_double, ctypes.c_double, ctypes.c_double, _dp]
+        L.or_psi_nh.restype = ctypes.c_double
+        L.or_psi_nh.argtypes = [_dp, ctypes.c_double, ctypes.c_double]
+        L.or_sym3_eig.argtypes = [_dp, _dp, _dp]
+        L.or_tr_filter.argtypes = [_dp, ctypes.c_double, ctypes.c_double, _dp, _dp]
+        L.or_aa_step.argtypes = [ctypes.c_int, ctypes.c_int, _dp, _dp, _ip, _dp, _dp, ctypes.c_char_p, _dp, _dp]
+        L.or_local_rhs.argtypes = [ctypes.c_void_p, _dp, _dp]
+        L.or_const_rhs.argtypes = [ctypes.c_void_p, _dp, _dp, _dp, _dp, _dp]
+        L.or_apply_Ainv.argtypes = [ctypes.c_void_p, _dp, _dp]
+        L.or_apply_A.argtypes = [ctypes.c_void_p, _dp, _dp]
+        L.or_apply_K.argtypes = [ctypes.c_void_p, _dp, ctypes.c_double, _dp, _dp]
+        L.or_primal_phi.restype = ctypes.c_double
+        L.or_primal_phi.argtypes = [ctypes.c_void_p, _dp, _dp]
+        L.or_step_forward.argtypes = [ctypes.c_void_p, _dp, _dp, _dp, _dp, _dp, _dp, _dp, ctypes.c_int, ctypes.c_int,
+                                      ctypes.c_int, _dp, _ip, _dp]
+        L.or_step_backward.argtypes = [ctypes.c_void_p, _dp, _dp, _dp, _dp, _dp, _dp, _dp, _dp, _dp, _dp, _dp,
+                                       ctypes.c_int, ctypes.c_double, _ip, _dp]
+        _lib = L
+    return _lib
+
+
+def _p(a):
+    if a is None:
+        return None
+    assert a.dtype == np.float64 and a.flags["C_CONTIGUOUS"]
+    return a.ctypes.data_as(_dp)
+
+
+def _f(a) -> np.ndarray:
+    return np.ascontiguousarray(a, dtype=np.float64)
+
+
+# ---------------------------------------------------------------- element level
+def svd3(F):
+    F = _f(F).reshape(3, 3)
+    U, S, V = np.zeros((3, 3)), np.zeros(3), np.zeros((3, 3))
+    lib().or_svd3(_p(F), _p(U), _p(S), _p(V))
+    return U, S, V
+
+
+def prox_stretch(sF, mu, lam, k):
+    sF = _f(sF)
+    out = np.zeros(3)
+    it = lib().or_prox_stretch(_p(sF), mu, lam, k, _p(out))
+    return out, it
+
+
+def prox_map(F, mu, lam, k):
+    F = _f(F).reshape(3, 3)
+    P = np.zeros((3, 3))
+    lib().or_prox_map(_p(F), mu, lam, k, _p(P))
+    return P
+
+
+def prox_jacobian(F, mu, lam, k, tau):
+    F = _f(F).reshape(3, 3)
+    J = np.zeros((9, 9))
+    lib().or_prox_jacobian(_p(F), mu, lam, k, tau, _p(J))
+    return J
+
+
+def psi_nh(F, mu, lam):
+    return lib().or_psi_nh(_p(_f(F).reshape(3, 3)), mu, lam)
+
+
+def sym3_eig(H):
+    H = _f(H).reshape(3, 3)
+    k, Q = np.zeros(3), np.zeros((3, 3))
+    lib().or_sym3_eig(_p(H), _p(k), _p(Q))
+    return k, Q
+
+
+def tr_filter(H, tau, k=1.0):
+    H = _f(H).reshape(3, 3)
+    Ht, Dinv = np.zeros((3, 3)), np.zeros((3, 3))
+    lib().or_tr_filter(_p(H), float(tau), float(k), _p(Ht), _p(Dinv))
+    return Ht, Dinv
+
+
+class AAHistory:
+    """Anderson history for :func:`aa_step` on vectors of length n."""
+
+    def __init__(self, n, m):
+        self.n, self.m = n, m
+        self.Hq = np.zeros((m + 1, n))
+        self.Hg = np.zeros((m + 1, n))
+        self.hn = ctypes.c_int(0)
+
+    def step(self, q, qhat, mask=None):
+        qn = np.zeros(self.n)
+        gam = np.zeros(8)
+        mk = None if mask is None else np.ascontiguousarray(mask, dtype=np.uint8)
+        reset = lib().or_aa_step(self.n, self.m, _p(self.Hq), _p(self.Hg), ctypes.byref(self.hn), _p(_f(q)),
+                                 _p(_f(qhat)), mk.ctypes.data_as(ctypes.c_char_p) if mk is not None else None,
+                                 _p(qn), _p(gam))
+        return qn, bool(reset), gam
+
+
+# ---------------------------------------------------------------- scene level
+class OracleScene:
+    """Oracle scene built from a :class:`paper_2605_14526_amd.scenes.Scene`-like object."""
+
+    def __init__(self, sc, m=None, eps_rel=None, eps_abs=None, kmax_fwd=1000, kmax_bwd=1000, eps_adj=1e-6,
+                 eps_tr=0.1, log_E=None, frozen=None):
+        L = lib()
+        self.sc = sc
+        self.nv = int(sc.X.shape[0])
+        self.ne = int(sc.tets.shape[0])
+        X = _f(sc.X)
+        tets = np.ascontiguousarray(sc.tets, dtype=np.int32)
+        pinned = np.ascontiguousarray(sc.pinned, dtype=np.uint8)
+        logE = _f(sc.log_E if log_E is None else log_E)
+        g = np.asarray(sc.gravity, float)
+        params = _f([sc.nu, sc.rho, sc.alpha, sc.beta0, sc.h, g[0], g[1], g[2]])
+        fr = (0.0, 0.0, 0.0) if frozen is None else tuple(frozen)
+        solver = _f([sc.aa_window if m is None else m, sc.eps_rel if eps_rel is None else eps_rel,
+                     sc.eps_abs if eps_abs is None else eps_abs, kmax_fwd, kmax_bwd, eps_adj, eps_tr,
+                     fr[0], fr[1], fr[2]])
+        self.h = float(sc.h)
+        self._keep = (X, tets, pinned, logE, params, solver)
+        self.ptr = L.or_scene_create(self.nv, self.ne, _p(X), tets.ctypes.data_as(_ip),
+                                     pinned.ctypes.data_as(ctypes.c_char_p), _p(logE), _p(params), _p(solver))
+        self.nf = L.or_scene_nfree(self.ptr)
+        self.pinned = pinned.astype(bool)
+
+    def __del__(self):
+        if getattr(self, "ptr", None):
+            lib().or_scene_destroy(self.ptr)
+            self.ptr = None
+
+    def info(self):
+        vol, w, beta, mass, means = np.zeros(self.ne), np.zeros(self.ne), np.zeros(self.ne), np.zeros(self.nv), np.zeros(4)
+        lib().or_scene_info(self.ptr, _p(vol), _p(w), _p(beta), _p(mass), _p(means))
+        return dict(vol=vol, w=w, beta=beta, mass=mass, mu_bar=means[0], lam_bar=means[1], k_bar=means[2],
+                    mu_ref=means[3])
+
+    def local_rhs(self, q):
+        q = _f(q)
+        b = np.zeros_like(q)
+        lib().or_local_rhs(self.ptr, _p(q), _p(b))
+        return b
+
+    def const_rhs(self, q_t, v_t, f_ext=None):
+        q_t, v_t = _f(q_t), _f(v_t)
+        c, qt = np.zeros_like(q_t), np.zeros_like(q_t)
+        lib().or_const_rhs(self.ptr, _p(q_t), _p(v_t), _p(_f(f_ext)) if f_ext is not None else None, _p(c), _p(qt))
+        return c, qt
+
+    def apply_Ainv(self, r):
+        r = _f(r)
+        x = np.zeros_like(r)
+        lib().or_apply_Ainv(self.ptr, _p(r), _p(x))
+        return x
+
+    def apply_A(self, x):
+        x = _f(x)
+        y = np.zeros_like(x)
+        lib().or_apply_A(self.ptr, _p(x), _p(y))
+        return y
+
+    def apply_K(self, q, tau, x):
+        q, x = _f(q), _f(x)
+        y = np.zeros_like(x)
+        lib().or_apply_K(self.ptr, _p(q), tau, _p(x), _p(y))
+        return y
+
+    def phi(self, q, qtilde):
+        return lib().or_primal_phi(self.ptr, _p(_f(q)), _p(_f(qtilde)))
+
+    def step_forward(self, q_t, v_t, f_ext=None, q0=None, force_iters=0, m=-1, record=0):
+        q_t, v_t = _f(q_t), _f(v_t)
+        qn, vn, qm1 = np.zeros_like(q_t), np.zeros_like(q_t), np.zeros_like(q_t)
+        ist = np.zeros(5, dtype=np.int32)
+        dst = np.zeros(4)
+        rec = np.zeros((record,) + q_t.shape) if record else None
+        lib().or_step_forward(self.ptr, _p(q_t), _p(v_t), _p(_f(f_ext)) if f_ext is not None else None,
+                              _p(_f(q0)) if q0 is not None else None, _p(qn), _p(vn), _p(qm1), int(force_iters),
+                              int(m), int(record), _p(rec) if rec is not None else None,
+                              ist.ctypes.data_as(_ip), _p(dst))
+        st = dict(iters=int(ist[0]), resets=int(ist[1]), newton_capped=int(ist[2]), newton_max=int(ist[3]),
+                  status=int(ist[4]), gate=dst.copy())
+        if record:
+            st["record"] = rec
+        return qn, vn, qm1, st
+
+    def step_backward(self, q_t, v_t, f_ext, q_star, q_star_m1, gq_next, gv_next, g_logE=None, adj_mode=0,
+                      tau_force=-1.0):
+        q_t, v_t = _f(q_t), _f(v_t)
+        gq, gv, gf = np.zeros_like(q_t), np.zeros_like(q_t), np.zeros_like(q_t)
+        gl = np.zeros(self.ne) if g_logE is None else g_logE
+        ist = np.zeros(2, dtype=np.int32)
+        dst = np.zeros(4)
+        lib().or_step_backward(self.ptr, _p(q_t), _p(v_t), _p(_f(f_ext)) if f_ext is not None else None,
+                               _p(_f(q_star)), _p(_f(q_star_m1)), _p(_f(gq_next)), _p(_f(gv_next)), _p(gq), _p(gv),
+                               _p(gf), _p(gl), int(adj_mode), float(tau_force), ist.ctypes.data_as(_ip), _p(dst))
+        st = dict(adj_iters=int(ist[0]), status=int(ist[1]), rho=dst[0], tau=dst[1], dphi_act=dst[2],
+                  dphi_mod=dst[3])
+        return gq, gv, gf, gl, st
+
+
+def rollout(osc: OracleScene, steps: int, record_ckpt: bool = True, **kw):
+    """Forward rollout of the scene; returns final (q, v), checkpoints and stats."""
+    sc = osc.sc
+    q, v = sc.q0(), sc.v0()
+    ckpts, stats = [], []
+    for t in range(steps):
+        f = sc.f_ext(t)
+        qn, vn, qm1, st = osc.step_forward(q, v, f, **kw)
+        if record_ckpt:
+            ckpts.append((q.copy(), v.copy(), f.copy(), qn.copy(), qm1.copy()))
+        stats.append(st)
+        q, v = qn, vn
+    return q, v, ckpts, stats
+
+
+def rollout_backward(osc: OracleScene, ckpts, gq_T, gv_T, adj_mode=0, tau_force=-1.0):
+    """Reverse sweep over checkpoints; returns dL/dq0, dL/dv0, dL/dlogE and stats."""
+    gq, gv = gq_T.copy(), gv_T.copy()
+    gl = np.zeros(osc.ne)
+    stats = []
+    for (q_t, v_t, f, qs, qsm1) in reversed(ckpts):
+        gq, gv, _gf, gl, st = osc.step_backward(q_t, v_t, f, qs, qsm1, gq, gv, gl, adj_mode, tau_force)
+        stats.append(st)
+    return gq, gv, gl, stats[::-1]

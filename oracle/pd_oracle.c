@@ -1,0 +1,1147 @@
+/*
+ * Plain FP64 CPU oracle: differentiable Projective Dynamics (PD) with the
+ * Neo-Hookean proximal local step, stiffness-routed projective weights,
+ * Rayleigh damping folded into the system matrix, bounded type-II Anderson
+ * acceleration with the dual-gate stop, and the adjoint backward step with the
+ * trust-region eigenvalue filter on the proximal-map Hessian.
+ *
+ * TEST INFRASTRUCTURE ONLY.  The GPU library never links, loads or calls this
+ * file; only the test-suite, the smoke check and the CPU-baseline leg of the
+ * benchmark do.  Every routine is written for clarity, not speed: plain loops,
+ * FP64, round-to-nearest, no fused multiply-add contraction (build with
+ * -ffp-contract=off), serial.
+ *
+ * Citations name the paper's sections and equations (arXiv 2605.14526,
+ * "DiffPhD").  Readings of places where the paper is silent or inconsistent are
+ * marked READING and listed in the design notes of the repository.
+ */
+#include "pd_oracle.h"
+
+#include <math.h>
+#include <stdlib.h>
+#include <string.h>
+
+/* ------------------------------------------------------------------------ */
+/* small dense helpers                                                       */
+/* ------------------------------------------------------------------------ */
+
+static void mat3_mul(const double A[9], const double B[9], double C[9]) {
+  for (int i = 0; i < 3; ++i)
+    for (int j = 0; j < 3; ++j) {
+      double s = 0.0;
+      for (int k = 0; k < 3; ++k) s += A[3 * i + k] * B[3 * k + j];
+      C[3 * i + j] = s;
+    }
+}
+
+static void mat3_mul_tn(const double A[9], const double B[9], double C[9]) { /* A^T B */
+  for (int i = 0; i < 3; ++i)
+    for (int j = 0; j < 3; ++j) {
+      double s = 0.0;
+      for (int k = 0; k < 3; ++k) s += A[3 * k + i] * B[3 * k + j];
+      C[3 * i + j] = s;
+    }
+}
+
+static void mat3_mul_nt(const double A[9], const double B[9], double C[9]) { /* A B^T */
+  for (int i = 0; i < 3; ++i)
+    for (int j = 0; j < 3; ++j) {
+      double s = 0.0;
+      for (int k = 0; k < 3; ++k) s += A[3 * i + k] * B[3 * j + k];
+      C[3 * i + j] = s;
+    }
+}
+
+static double det3(const double A[9]) {
+  return A[0] * (A[4] * A[8] - A[5] * A[7]) - A[1] * (A[3] * A[8] - A[5] * A[6]) +
+         A[2] * (A[3] * A[7] - A[4] * A[6]);
+}
+
+static void inv3(const double A[9], double B[9]) {
+  double d = det3(A);
+  B[0] = (A[4] * A[8] - A[5] * A[7]) / d;
+  B[1] = (A[2] * A[7] - A[1] * A[8]) / d;
+  B[2] = (A[1] * A[5] - A[2] * A[4]) / d;
+  B[3] = (A[5] * A[6] - A[3] * A[8]) / d;
+  B[4] = (A[0] * A[8] - A[2] * A[6]) / d;
+  B[5] = (A[2] * A[3] - A[0] * A[5]) / d;
+  B[6] = (A[3] * A[7] - A[4] * A[6]) / d;
+  B[7] = (A[1] * A[6] - A[0] * A[7]) / d;
+  B[8] = (A[0] * A[4] - A[1] * A[3]) / d;
+}
+
+/* Cholesky of a small SPD matrix (n <= 8) in place (lower); returns 0 if not PD */
+static int small_chol(double* A, int n) {
+  for (int j = 0; j < n; ++j) {
+    double d = A[j * n + j];
+    for (int k = 0; k < j; ++k) d -= A[j * n + k] * A[j * n + k];
+    if (!(d > 0.0)) return 0;
+    d = sqrt(d);
+    A[j * n + j] = d;
+    for (int i = j + 1; i < n; ++i) {
+      double s = A[i * n + j];
+      for (int k = 0; k < j; ++k) s -= A[i * n + k] * A[j * n + k];
+      A[i * n + j] = s / d;
+    }
+  }
+  return 1;
+}
+
+static void small_chol_solve(const double* L, int n, const double* b, double* x) {
+  double y[16];
+  for (int i = 0; i < n; ++i) {
+    double s = b[i];
+    for (int k = 0; k < i; ++k) s -= L[i * n + k] * y[k];
+    y[i] = s / L[i * n + i];
+  }
+  for (int i = n - 1; i >= 0; --i) {
+    double s = y[i];
+    for (int k = i + 1; k < n; ++k) s -= L[k * n + i] * x[k];
+    x[i] = s / L[i * n + i];
+  }
+}
+
+/* ------------------------------------------------------------------------ */
+/* 3x3 symmetric eigendecomposition: cyclic Jacobi (used by the TR filter,   */
+/* Sec. 4.4 "closed-form Jacobi sweep on 3x3 matrices")                      */
+/* H = Q diag(kappa) Q^T, Q columns are eigenvectors.                         */
+/* ------------------------------------------------------------------------ */
+void or_sym3_eig(const double Hin[9], double kappa[3], double Q[9]) {
+  double A[9];
+  memcpy(A, Hin, sizeof(A));
+  for (int i = 0; i < 9; ++i) Q[i] = (i % 4 == 0) ? 1.0 : 0.0;
+  for (int sweep = 0; sweep < 50; ++sweep) {
+    double off = A[1] * A[1] + A[2] * A[2] + A[5] * A[5];
+    double diag = A[0] * A[0] + A[4] * A[4] + A[8] * A[8];
+    if (off <= 1e-40 * diag || off == 0.0) break;
+    for (int p = 0; p < 2; ++p)
+      for (int r = p + 1; r < 3; ++r) {
+        double apr = A[3 * p + r];
+        if (apr == 0.0) continue;
+        double theta = (A[3 * r + r] - A[3 * p + p]) / (2.0 * apr);
+        double t = (theta >= 0 ? 1.0 : -1.0) / (fabs(theta) + sqrt(theta * theta + 1.0));
+        double c = 1.0 / sqrt(t * t + 1.0), s = t * c;
+        /* A <- J^T A J with J the rotation in plane (p, r) */
+        for (int k = 0; k < 3; ++k) {
+          double akp = A[3 * k + p], akr = A[3 * k + r];
+          A[3 * k + p] = c * akp - s * akr;
+          A[3 * k + r] = s * akp + c * akr;
+        }
+        for (int k = 0; k < 3; ++k) {
+          double apk = A[3 * p + k], ark = A[3 * r + k];
+          A[3 * p + k] = c * apk - s * ark;
+          A[3 * r + k] = s * apk + c * ark;
+        }
+        for (int k = 0; k < 3; ++k) {
+          double qkp = Q[3 * k + p], qkr = Q[3 * k + r];
+          Q[3 * k + p] = c * qkp - s * qkr;
+          Q[3 * k + r] = s * qkp + c * qkr;
+        }
+      }
+  }
+  for (int i = 0; i < 3; ++i) kappa[i] = A[4 * i];
+}
+
+/* ------------------------------------------------------------------------ */
+/* Signed SVD of a 3x3 matrix (one-sided Jacobi, Hestenes).                  */
+/* F = U diag(sig) V^T with U, V in SO(3), sig1 >= sig2 >= |sig3|, the sign  */
+/* of det F carried by sig3 (used by the local step, Sec. 4.1 Eq. nh_prox).  */
+/* ------------------------------------------------------------------------ */
+void or_svd3(const double F[9], double U[9], double sig[3], double V[9]) {
+  double W[9]; /* columns w_j = F v_j */
+  memcpy(W, F, sizeof(W));
+  for (int i = 0; i < 9; ++i) V[i] = (i % 4 == 0) ? 1.0 : 0.0;
+  for (int sweep = 0; sweep < 60; ++sweep) {
+    int rotated = 0;
+    for (int p = 0; p < 2; ++p)
+      for (int r = p + 1; r < 3; ++r) {
+        double a = 0, b = 0, g = 0;
+        for (int k = 0; k < 3; ++k) {
+          a += W[3 * k + p] * W[3 * k + p];
+          b += W[3 * k + r] * W[3 * k + r];
+          g += W[3 * k + p] * W[3 * k + r];
+        }
+        if (fabs(g) <= 1e-15 * sqrt(a * b) || g == 0.0) continue;
+        rotated = 1;
+        double zeta = (b - a) / (2.0 * g);
+        double t = (zeta >= 0 ? 1.0 : -1.0) / (fabs(zeta) + sqrt(1.0 + zeta * zeta));
+        double c = 1.0 / sqrt(1.0 + t * t), s = c * t;
+        for (int k = 0; k < 3; ++k) {
+          double wp = W[3 * k + p], wr = W[3 * k + r];
+          W[3 * k + p] = c * wp - s * wr;
+          W[3 * k + r] = s * wp + c * wr;
+          double vp = V[3 * k + p], vr = V[3 * k + r];
+          V[3 * k + p] = c * vp - s * vr;
+          V[3 * k + r] = s * vp + c * vr;
+        }
+      }
+    if (!rotated) break;
+  }
+  /* sort columns by norm, descending */
+  double nrm[3];
+  for (int j = 0; j < 3; ++j) nrm[j] = sqrt(W[j] * W[j] + W[3 + j] * W[3 + j] + W[6 + j] * W[6 + j]);
+  int ord[3] = {0, 1, 2};
+  for (int i = 0; i < 3; ++i)
+    for (int j = i + 1; j < 3; ++j)
+      if (nrm[ord[j]] > nrm[ord[i]]) { int t = ord[i]; ord[i] = ord[j]; ord[j] = t; }
+  double Ws[9], Vs[9], ns[3];
+  for (int j = 0; j < 3; ++j) {
+    ns[j] = nrm[ord[j]];
+    for (int k = 0; k < 3; ++k) { Ws[3 * k + j] = W[3 * k + ord[j]]; Vs[3 * k + j] = V[3 * k + ord[j]]; }
+  }
+  /* make V a rotation: flipping v3 together with w3 leaves F unchanged */
+  if (det3(Vs) < 0.0)
+    for (int k = 0; k < 3; ++k) { Vs[3 * k + 2] = -Vs[3 * k + 2]; Ws[3 * k + 2] = -Ws[3 * k + 2]; }
+  /* U: u1 = w1/|w1|, u2 = w2 orthogonalised, u3 = u1 x u2; sig3 = w3 . u3 (signed) */
+  double u1[3], u2[3], u3[3];
+  if (ns[0] > 0.0) {
+    for (int k = 0; k < 3; ++k) u1[k] = Ws[3 * k] / ns[0];
+  } else {
+    u1[0] = 1; u1[1] = 0; u1[2] = 0;
+  }
+  double d12 = 0;
+  for (int k = 0; k < 3; ++k) { u2[k] = Ws[3 * k + 1]; d12 += u1[k] * u2[k]; }
+  for (int k = 0; k < 3; ++k) u2[k] -= d12 * u1[k];
+  double n2 = sqrt(u2[0] * u2[0] + u2[1] * u2[1] + u2[2] * u2[2]);
+  if (n2 <= 1e-300 || ns[1] <= 1e-14 * ns[0]) {
+    /* rank <= 1: any unit vector orthogonal to u1 */
+    double e[3] = {fabs(u1[0]) < 0.9 ? 1.0 : 0.0, fabs(u1[0]) < 0.9 ? 0.0 : 1.0, 0.0};
+    double d = e[0] * u1[0] + e[1] * u1[1] + e[2] * u1[2];
+    for (int k = 0; k < 3; ++k) u2[k] = e[k] - d * u1[k];
+    n2 = sqrt(u2[0] * u2[0] + u2[1] * u2[1] + u2[2] * u2[2]);
+  }
+  for (int k = 0; k < 3; ++k) u2[k] /= n2;
+  u3[0] = u1[1] * u2[2] - u1[2] * u2[1];
+  u3[1] = u1[2] * u2[0] - u1[0] * u2[2];
+  u3[2] = u1[0] * u2[1] - u1[1] * u2[0];
+  for (int k = 0; k < 3; ++k) { U[3 * k] = u1[k]; U[3 * k + 1] = u2[k]; U[3 * k + 2] = u3[k]; }
+  memcpy(V, Vs, sizeof(Vs));
+  /* singular values as diagonal of U^T F V (exact up to rounding) */
+  double T[9], S[9];
+  mat3_mul_tn(U, F, T);
+  mat3_mul(T, V, S);
+  sig[0] = S[0];
+  sig[1] = S[4];
+  sig[2] = S[8];
+}
+
+/* ------------------------------------------------------------------------ */
+/* Neo-Hookean energy, Sec. 3.2 Eq. neohookean:                               */
+/* psi = mu/2 (|F|^2 - 3) - mu ln J + lam/2 (ln J)^2, +inf for J <= 0.        */
+/* ------------------------------------------------------------------------ */
+double or_psi_nh(const double F[9], double mu, double lam) {
+  double J = det3(F);
+  if (!(J > 0.0)) return INFINITY;
+  double I1 = 0.0;
+  for (int i = 0; i < 9; ++i) I1 += F[i] * F[i];
+  double lj = log(J);
+  return 0.5 * mu * (I1 - 3.0) - mu * lj + 0.5 * lam * lj * lj;
+}
+
+/* Stretch-space objective of the proximal step, Sec. 4.1 Eq. nh_prox reduced
+ * by the SVD:  f(s) = k/2 |s - sF|^2 + psi(s),
+ * psi(s) = mu/2 (sum s^2 - 3) - mu sum ln s + lam/2 (sum ln s)^2.
+ * READING: V_e is dropped from the prox (the same stretch-space map in every
+ * element, Sec. 4.2); the stationarity form grad f = 0 is solved (the printed
+ * normal equation is its quadratic special case). */
+static double prox_obj(const double s[3], const double sF[3], double mu, double lam, double k) {
+  if (!(s[0] > 0 && s[1] > 0 && s[2] > 0)) return INFINITY;
+  double q = 0, ss = 0, sl = 0;
+  for (int i = 0; i < 3; ++i) {
+    q += (s[i] - sF[i]) * (s[i] - sF[i]);
+    ss += s[i] * s[i];
+    sl += log(s[i]);
+  }
+  return 0.5 * k * q + 0.5 * mu * (ss - 3.0) - mu * sl + 0.5 * lam * sl * sl;
+}
+
+/* gradient and Hessian of psi in stretch space.
+ * READING of Eq. nh_hessian_stretch: the diagonal term is mu (1 + s^-2), the
+ * exact second derivative of Eq. neohookean (the printed s^-4 is a typo). */
+static void psi_stretch_grad_hess(const double s[3], double mu, double lam, double g[3], double H[9]) {
+  double l = log(s[0]) + log(s[1]) + log(s[2]);
+  for (int i = 0; i < 3; ++i) g[i] = mu * s[i] - mu / s[i] + lam * l / s[i];
+  for (int i = 0; i < 3; ++i)
+    for (int j = 0; j < 3; ++j) {
+      if (i == j)
+        H[3 * i + j] = mu * (1.0 + 1.0 / (s[i] * s[i])) + lam * (1.0 - l) / (s[i] * s[i]);
+      else
+        H[3 * i + j] = lam / (s[i] * s[j]);
+    }
+}
+
+/* Proximal stretches, Sec. 4.1 Eqs. nh_prox / nh_prox_normal: Newton with
+ * backtracking line search and positivity enforcement.
+ * READING (constants the paper does not give): start max(sF, 0.1); direction
+ * from a Cholesky of k I + H_psi, else of its absolute-value filtered form;
+ * fraction-to-boundary step 0.9; Armijo c1 = 1e-4 with halving (<= 30) and a
+ * rounding slack of 1e-13 k (1 + |s|^2);
+ * stop at |g|_inf <= 1e-13 k max(1, |sF|_inf), a relative step <= 1e-15, or
+ * 50 iterations.  Returns the iteration count (negative if the cap was hit). */
+int or_prox_stretch(const double sF[3], double mu, double lam, double k, double s_out[3]) {
+  double s[3];
+  for (int i = 0; i < 3; ++i) s[i] = sF[i] > 0.1 ? sF[i] : 0.1;
+  double sfmax = 1.0;
+  for (int i = 0; i < 3; ++i) if (fabs(sF[i]) > sfmax) sfmax = fabs(sF[i]);
+  double gtol = 1e-13 * k * sfmax;
+  int it;
+  for (it = 0; it < 50; ++it) {
+    double gp[3], H[9], g[3];
+    psi_stretch_grad_hess(s, mu, lam, gp, H);
+    double gmax = 0;
+    for (int i = 0; i < 3; ++i) {
+      g[i] = k * (s[i] - sF[i]) + gp[i];
+      H[4 * i] += k;
+      if (fabs(g[i]) > gmax) gmax = fabs(g[i]);
+    }
+    if (gmax <= gtol) break;
+    double L[9], d[3], mg[3] = {-g[0], -g[1], -g[2]};
+    memcpy(L, H, sizeof(L));
+    if (small_chol(L, 3)) {
+      small_chol_solve(L, 3, mg, d);
+    } else {
+      double kap[3], Q[9], t[3];
+      or_sym3_eig(H, kap, Q);
+      for (int i = 0; i < 3; ++i) {
+        double a = 0;
+        for (int j = 0; j < 3; ++j) a += Q[3 * j + i] * mg[j];
+        double ak = fabs(kap[i]) > 1e-300 ? fabs(kap[i]) : 1e-300;
+        t[i] = a / ak;
+      }
+      for (int i = 0; i < 3; ++i) d[i] = Q[3 * i] * t[0] + Q[3 * i + 1] * t[1] + Q[3 * i + 2] * t[2];
+    }
+    double a0 = 1.0;
+    for (int i = 0; i < 3; ++i)
+      if (d[i] < 0.0) {
+        double lim = 0.9 * s[i] / (-d[i]);
+        if (lim < a0) a0 = lim;
+      }
+    double f0 = prox_obj(s, sF, mu, lam, k);
+    double slack = 1e-13 * k * (1.0 + s[0] * s[0] + s[1] * s[1] + s[2] * s[2]);
+    double slope = g[0] * d[0] + g[1] * d[1] + g[2] * d[2];
+    double a = a0, sn[3];
+    int accepted = 0;
+    for (int ls = 0; ls <= 30; ++ls) {
+      for (int i = 0; i < 3; ++i) sn[i] = s[i] + a * d[i];
+      double f1 = prox_obj(sn, sF, mu, lam, k);
+      /* the slack 1e-13 k (1 + |s|^2), the rounding level of the terms of f,
+       * keeps the test meaningful once the decrease falls below what f can
+       * resolve (close to the minimiser) */
+      if (f1 <= f0 + 1e-4 * a * slope + slack) { accepted = 1; break; }
+      a *= 0.5;
+    }
+    if (!accepted)
+      for (int i = 0; i < 3; ++i) sn[i] = s[i] + a * d[i];
+    double step = 0, nrm = 0;
+    for (int i = 0; i < 3; ++i) {
+      step += (sn[i] - s[i]) * (sn[i] - s[i]);
+      nrm += sn[i] * sn[i];
+      s[i] = sn[i];
+    }
+    if (sqrt(step) <= 1e-15 * sqrt(nrm)) { ++it; break; }
+  }
+  for (int i = 0; i < 3; ++i) s_out[i] = s[i];
+  return it >= 50 ? -it : it;
+}
+
+/* p* = U diag(s*) V^T, Sec. 4.1 */
+void or_prox_map(const double F[9], double mu, double lam, double k, double P[9]) {
+  double U[9], V[9], sF[3], ss[3], T[9];
+  or_svd3(F, U, sF, V);
+  or_prox_stretch(sF, mu, lam, k, ss);
+  for (int i = 0; i < 3; ++i)
+    for (int j = 0; j < 3; ++j) T[3 * i + j] = U[3 * i + j] * ss[j];
+  mat3_mul_nt(T, V, P);
+}
+
+/* Filtered proximal-map differential dp*_dF (9x9, row-major in (i,j) pairs):
+ * Sec. 4.4 Eqs. Hprox, tr_blend, tr_ift and the SVD differential.
+ * H_prox = H_psi(s*) + k I; H~ = (1 - tau) H_prox + tau |H_prox|;
+ * D = k H~^+ (READING: pseudo-inverse, eigenvalues <= 1e-12 max are dropped);
+ * in the (U, V) frame with A = U^T dF V: diagonal d p^_ii = sum_j D_ij A_jj;
+ * for i < j with sym = (A_ij + A_ji)/2, skw = (A_ij - A_ji)/2:
+ * d p^_ij = c1 sym + c2 skw, d p^_ji = c1 sym - c2 skw,
+ * c1 = (s*_i - s*_j)/(sF_i - sF_j)  (limit (D_ii + D_jj)/2 - D_ij when the
+ * two stretches coincide), c2 = (s*_i + s*_j)/(sF_i + sF_j) (denominator kept
+ * away from zero by 1e-8 with its sign).  dp = U dp^ V^T. */
+/* Trust-region blend of a symmetric 3x3 matrix, Eq. tr_blend:
+ * H~(tau) = (1 - tau) H + tau |H| with |H| = Q diag(|kappa|) Q^T.
+ * Returns H~ and, in Dinv, k times its pseudo-inverse (READING: eigenvalues
+ * of H~ at most 1e-12 of the largest are treated as zero). */
+void or_tr_filter(const double H[9], double tau, double k, double Ht[9], double Dinv[9]) {
+  double kap[3], Q[9];
+  or_sym3_eig(H, kap, Q);
+  double kt[3], kmax = 0;
+  for (int i = 0; i < 3; ++i) {
+    kt[i] = (1.0 - tau) * kap[i] + tau * fabs(kap[i]);
+    if (fabs(kt[i]) > kmax) kmax = fabs(kt[i]);
+  }
+  double inv[3];
+  for (int i = 0; i < 3; ++i) inv[i] = (fabs(kt[i]) <= 1e-12 * kmax) ? 0.0 : 1.0 / kt[i];
+  for (int i = 0; i < 3; ++i)
+    for (int j = 0; j < 3; ++j) {
+      double s = 0, t = 0;
+      for (int l = 0; l < 3; ++l) {
+        s += Q[3 * i + l] * inv[l] * Q[3 * j + l];
+        t += Q[3 * i + l] * kt[l] * Q[3 * j + l];
+      }
+      if (Dinv) Dinv[3 * i + j] = k * s;
+      if (Ht) Ht[3 * i + j] = t;
+    }
+}
+
+static void prox_diff_coeffs(const double sF[3], const double ss[3], double mu, double lam, double k, double tau,
+                             double D[9], double c1[3], double c2[3]) {
+  double gp[3], H[9];
+  psi_stretch_grad_hess(ss, mu, lam, gp, H);
+  for (int i = 0; i < 3; ++i) H[4 * i] += k;
+  /* H_prox = H_psi(s*) + k I (Eq. Hprox); D = k H~^+ solves Eq. tr_ift */
+  or_tr_filter(H, tau, k, NULL, D);
+  const int P0[3] = {0, 0, 1}, P1[3] = {1, 2, 2};
+  double sfmax = 1.0;
+  for (int i = 0; i < 3; ++i) if (fabs(sF[i]) > sfmax) sfmax = fabs(sF[i]);
+  for (int p = 0; p < 3; ++p) {
+    int i = P0[p], j = P1[p];
+    double dsf = sF[i] - sF[j];
+    if (fabs(dsf) <= 1e-7 * sfmax)
+      c1[p] = 0.5 * (D[3 * i + i] + D[3 * j + j]) - D[3 * i + j];
+    else
+      c1[p] = (ss[i] - ss[j]) / dsf;
+    double den = sF[i] + sF[j];
+    if (fabs(den) < 1e-8) den = den < 0 ? -1e-8 : 1e-8;
+    c2[p] = (ss[i] + ss[j]) / den;
+  }
+}
+
+static void prox_diff_apply(const double U[9], const double V[9], const double D[9], const double c1[3],
+                            const double c2[3], const double dF[9], double dP[9]) {
+  double T[9], A[9], B[9];
+  mat3_mul_tn(U, dF, T);
+  mat3_mul(T, V, A);
+  for (int i = 0; i < 3; ++i) {
+    double s = 0;
+    for (int j = 0; j < 3; ++j) s += D[3 * i + j] * A[4 * j];
+    B[4 * i] = s;
+  }
+  const int P0[3] = {0, 0, 1}, P1[3] = {1, 2, 2};
+  for (int p = 0; p < 3; ++p) {
+    int i = P0[p], j = P1[p];
+    double sym = 0.5 * (A[3 * i + j] + A[3 * j + i]);
+    double skw = 0.5 * (A[3 * i + j] - A[3 * j + i]);
+    B[3 * i + j] = c1[p] * sym + c2[p] * skw;
+    B[3 * j + i] = c1[p] * sym - c2[p] * skw;
+  }
+  mat3_mul(U, B, T);
+  mat3_mul_nt(T, V, dP);
+}
+
+void or_prox_jacobian(const double F[9], double mu, double lam, double k, double tau, double J[81]) {
+  double U[9], V[9], sF[3], ss[3], D[9], c1[3], c2[3];
+  or_svd3(F, U, sF, V);
+  or_prox_stretch(sF, mu, lam, k, ss);
+  prox_diff_coeffs(sF, ss, mu, lam, k, tau, D, c1, c2);
+  for (int col = 0; col < 9; ++col) {
+    double dF[9] = {0}, dP[9];
+    dF[col] = 1.0;
+    prox_diff_apply(U, V, D, c1, c2, dF, dP);
+    for (int r = 0; r < 9; ++r) J[9 * r + col] = dP[r];
+  }
+}
+
+/* ------------------------------------------------------------------------ */
+/* scene                                                                     */
+/* ------------------------------------------------------------------------ */
+struct or_scene {
+  int nv, ne, nf;
+  double* X;
+  int* tets;
+  unsigned char* pinned;
+  double* logE;
+  double nu, rho, alpha, beta0, h, grav[3];
+  int m, kmax_fwd, kmax_bwd;
+  double eps_rel, eps_abs, eps_adj, eps_tr;
+  /* derived (Sec. 3.1, 4.1, 4.2, 4.5) */
+  double* Bhat;   /* ne x 4 x 3 shape gradients: F = sum_a x_a (x) Bhat_a */
+  double* vol;    /* ne */
+  double *mu, *lam, *w, *beta;
+  double mu_bar, lam_bar, k_bar, mu_ref;
+  double* mass; /* nv */
+  int* fidx;    /* nv -> free index or -1 */
+  int* fvert;   /* nf -> vertex */
+  unsigned char* fmask3; /* 3 nv: 1 on the coordinates of free vertices */
+  /* A~ restricted to free vertices, envelope (profile) storage */
+  int* first;   /* nf: first column of row i */
+  long* rowptr; /* nf+1: offset of row i's entries (columns first..i) */
+  double* Aenv; /* assembled A~ (lower envelope) */
+  double* Lenv; /* its Cholesky factor */
+};
+
+int or_scene_nfree(const or_scene* s) { return s->nf; }
+
+void or_scene_info(const or_scene* s, double* vol, double* w, double* beta, double* mass, double* means4) {
+  if (vol) memcpy(vol, s->vol, sizeof(double) * s->ne);
+  if (w) memcpy(w, s->w, sizeof(double) * s->ne);
+  if (beta) memcpy(beta, s->beta, sizeof(double) * s->ne);
+  if (mass) memcpy(mass, s->mass, sizeof(double) * s->nv);
+  if (means4) { means4[0] = s->mu_bar; means4[1] = s->lam_bar; means4[2] = s->k_bar; means4[3] = s->mu_ref; }
+}
+
+static double* env_at(double* env, const or_scene* s, int i, int j) { /* j <= i, j >= first[i] */
+  return env + s->rowptr[i] + (j - s->first[i]);
+}
+
+/* deformation gradient F_e = sum_a q_a (x) Bhat_a (G_e q), Sec. 3.1 */
+static void element_F(const or_scene* s, int e, const double* q, double F[9]) {
+  for (int i = 0; i < 9; ++i) F[i] = 0.0;
+  for (int a = 0; a < 4; ++a) {
+    int v = s->tets[4 * e + a];
+    const double* B = s->Bhat + 12 * e + 3 * a;
+    for (int i = 0; i < 3; ++i)
+      for (int j = 0; j < 3; ++j) F[3 * i + j] += q[3 * v + i] * B[j];
+  }
+}
+
+/* y += coef * G_e^T P (P a 3x3 matrix), over all 4 vertices */
+static void element_scatter(const or_scene* s, int e, double coef, const double P[9], double* y) {
+  for (int a = 0; a < 4; ++a) {
+    int v = s->tets[4 * e + a];
+    const double* B = s->Bhat + 12 * e + 3 * a;
+    for (int i = 0; i < 3; ++i) {
+      double t = 0;
+      for (int j = 0; j < 3; ++j) t += P[3 * i + j] * B[j];
+      y[3 * v + i] += coef * t;
+    }
+  }
+}
+
+or_scene* or_scene_create(int nv, int ne, const double* X, const int* tets, const unsigned char* pinned,
+                          const double* logE, const double* params, const double* solver) {
+  or_scene* s = (or_scene*)calloc(1, sizeof(or_scene));
+  s->nv = nv;
+  s->ne = ne;
+  s->X = (double*)malloc(sizeof(double) * 3 * nv);
+  memcpy(s->X, X, sizeof(double) * 3 * nv);
+  s->tets = (int*)malloc(sizeof(int) * 4 * ne);
+  memcpy(s->tets, tets, sizeof(int) * 4 * ne);
+  s->pinned = (unsigned char*)malloc(nv);
+  memcpy(s->pinned, pinned, nv);
+  s->logE = (double*)malloc(sizeof(double) * ne);
+  memcpy(s->logE, logE, sizeof(double) * ne);
+  s->nu = params[0]; s->rho = params[1]; s->alpha = params[2]; s->beta0 = params[3]; s->h = params[4];
+  s->grav[0] = params[5]; s->grav[1] = params[6]; s->grav[2] = params[7];
+  s->m = (int)solver[0]; s->eps_rel = solver[1]; s->eps_abs = solver[2];
+  s->kmax_fwd = (int)solver[3]; s->kmax_bwd = (int)solver[4]; s->eps_adj = solver[5]; s->eps_tr = solver[6];
+
+  /* rest shape: tets reoriented to det D_m > 0; V_e = det/6; Bhat from D_m^-1 */
+  s->Bhat = (double*)malloc(sizeof(double) * 12 * ne);
+  s->vol = (double*)malloc(sizeof(double) * ne);
+  for (int e = 0; e < ne; ++e) {
+    int* t = s->tets + 4 * e;
+    double Dm[9];
+    for (int a = 1; a < 4; ++a)
+      for (int i = 0; i < 3; ++i) Dm[3 * i + (a - 1)] = X[3 * t[a] + i] - X[3 * t[0] + i];
+    if (det3(Dm) < 0.0) {
+      int tmp = t[1]; t[1] = t[2]; t[2] = tmp;
+      for (int a = 1; a < 4; ++a)
+        for (int i = 0; i < 3; ++i) Dm[3 * i + (a - 1)] = X[3 * t[a] + i] - X[3 * t[0] + i];
+    }
+    double Bi[9];
+    inv3(Dm, Bi);
+    s->vol[e] = det3(Dm) / 6.0;
+    double* B = s->Bhat + 12 * e;
+    for (int j = 0; j < 3; ++j) {
+      B[3 * 1 + j] = Bi[3 * 0 + j];
+      B[3 * 2 + j] = Bi[3 * 1 + j];
+      B[3 * 3 + j] = Bi[3 * 2 + j];
+      B[j] = -(Bi[j] + Bi[3 + j] + Bi[6 + j]);
+    }
+  }
+  /* Lame parameters, Eq. lame; weights w_e = 2 mu_e + lam_e (READING of Eq.
+   * pd_weight: the rest tangent modulus of the Neo-Hookean energy, Sec. 7.2);
+   * mesh means for the local prox (Sec. 4.2); beta_e = beta0 mu_e / mu_ref
+   * with mu_ref = max mu_e (Sec. 4.5 Eq. rayleigh). */
+  s->mu = (double*)malloc(sizeof(double) * ne);
+  s->lam = (double*)malloc(sizeof(double) * ne);
+  s->w = (double*)malloc(sizeof(double) * ne);
+  s->beta = (double*)malloc(sizeof(double) * ne);
+  double smu = 0, slam = 0, mref = 0;
+  for (int e = 0; e < ne; ++e) {
+    double E = exp(logE[e]);
+    s->mu[e] = E / (2.0 * (1.0 + s->nu));
+    s->lam[e] = E * s->nu / ((1.0 + s->nu) * (1.0 - 2.0 * s->nu));
+    s->w[e] = 2.0 * s->mu[e] + s->lam[e];
+    smu += s->mu[e];
+    slam += s->lam[e];
+    if (s->mu[e] > mref) mref = s->mu[e];
+  }
+  s->mu_bar = smu / ne;
+  s->lam_bar = slam / ne;
+  s->mu_ref = mref;
+  /* optional frozen constants (finite-difference checks hold them fixed) */
+  if (solver[7] > 0.0) { s->mu_bar = solver[7]; s->lam_bar = solver[8]; s->mu_ref = solver[9]; }
+  s->k_bar = 2.0 * s->mu_bar + s->lam_bar;
+  for (int e = 0; e < ne; ++e) s->beta[e] = s->beta0 * s->mu[e] / s->mu_ref;
+  /* lumped mass m_v = sum_e rho V_e / 4 */
+  s->mass = (double*)calloc(nv, sizeof(double));
+  for (int e = 0; e < ne; ++e)
+    for (int a = 0; a < 4; ++a) s->mass[s->tets[4 * e + a]] += s->rho * s->vol[e] / 4.0;
+  /* free vertex numbering (original order) */
+  s->fidx = (int*)malloc(sizeof(int) * nv);
+  s->fvert = (int*)malloc(sizeof(int) * nv);
+  s->nf = 0;
+  for (int v = 0; v < nv; ++v) {
+    if (pinned[v]) s->fidx[v] = -1;
+    else { s->fidx[v] = s->nf; s->fvert[s->nf] = v; s->nf++; }
+  }
+  s->fmask3 = (unsigned char*)malloc(3 * (size_t)nv);
+  for (int v = 0; v < nv; ++v) for (int ax = 0; ax < 3; ++ax) s->fmask3[3 * v + ax] = pinned[v] ? 0 : 1;
+  /* envelope of A~ */
+  int nf = s->nf;
+  s->first = (int*)malloc(sizeof(int) * (nf > 0 ? nf : 1));
+  for (int i = 0; i < nf; ++i) s->first[i] = i;
+  for (int e = 0; e < ne; ++e)
+    for (int a = 0; a < 4; ++a)
+      for (int b = 0; b < 4; ++b) {
+        int i = s->fidx[s->tets[4 * e + a]], j = s->fidx[s->tets[4 * e + b]];
+        if (i >= 0 && j >= 0 && j < s->first[i]) s->first[i] = j;
+      }
+  s->rowptr = (long*)malloc(sizeof(long) * (nf + 1));
+  s->rowptr[0] = 0;
+  for (int i = 0; i < nf; ++i) s->rowptr[i + 1] = s->rowptr[i] + (i - s->first[i] + 1);
+  s->Aenv = (double*)calloc(s->rowptr[nf] > 0 ? s->rowptr[nf] : 1, sizeof(double));
+  s->Lenv = (double*)calloc(s->rowptr[nf] > 0 ? s->rowptr[nf] : 1, sizeof(double));
+  /* A~ = (1 + alpha h) M / h^2 + sum_e (w_e + beta_e / h) V_e Bhat Bhat^T
+   * (Sec. 4.5 Eq. A_damped; A = I_3 (x) A~ since |F|^2 separates by rows). */
+  double h = s->h;
+  for (int i = 0; i < nf; ++i) *env_at(s->Aenv, s, i, i) += (1.0 + s->alpha * h) * s->mass[s->fvert[i]] / (h * h);
+  for (int e = 0; e < ne; ++e) {
+    double c = (s->w[e] + s->beta[e] / h) * s->vol[e];
+    const double* B = s->Bhat + 12 * e;
+    for (int a = 0; a < 4; ++a)
+      for (int b = 0; b < 4; ++b) {
+        int i = s->fidx[s->tets[4 * e + a]], j = s->fidx[s->tets[4 * e + b]];
+        if (i < 0 || j < 0 || j > i) continue;
+        double d = B[3 * a] * B[3 * b] + B[3 * a + 1] * B[3 * b + 1] + B[3 * a + 2] * B[3 * b + 2];
+        *env_at(s->Aenv, s, i, j) += c * d;
+      }
+  }
+  /* envelope Cholesky A~ = L L^T (any ordering; the original one) */
+  for (int i = 0; i < nf; ++i) {
+    for (int j = s->first[i]; j <= i; ++j) {
+      double sum = *env_at(s->Aenv, s, i, j);
+      int k0 = s->first[i] > s->first[j] ? s->first[i] : s->first[j];
+      for (int k = k0; k < j; ++k) sum -= *env_at(s->Lenv, s, i, k) * *env_at(s->Lenv, s, j, k);
+      if (j < i) *env_at(s->Lenv, s, i, j) = sum / *env_at(s->Lenv, s, j, j);
+      else *env_at(s->Lenv, s, i, i) = sqrt(sum);
+    }
+  }
+  return s;
+}
+
+void or_scene_destroy(or_scene* s) {
+  if (!s) return;
+  free(s->X); free(s->tets); free(s->pinned); free(s->logE); free(s->Bhat); free(s->vol);
+  free(s->mu); free(s->lam); free(s->w); free(s->beta); free(s->mass); free(s->fidx); free(s->fvert); free(s->fmask3);
+  free(s->first); free(s->rowptr); free(s->Aenv); free(s->Lenv);
+  free(s);
+}
+
+/* x = A~^{-1} r per axis, free rows only (Sec. 4.6: exact application of the
+ * inverse from one factor; here an envelope Cholesky, forward + backward). */
+void or_apply_Ainv(const or_scene* s, const double* r_all, double* x_all) {
+  int nf = s->nf;
+  double* y = (double*)malloc(sizeof(double) * (nf > 0 ? nf : 1));
+  for (int v = 0; v < s->nv; ++v)
+    if (s->fidx[v] < 0) x_all[3 * v] = x_all[3 * v + 1] = x_all[3 * v + 2] = 0.0;
+  for (int ax = 0; ax < 3; ++ax) {
+    for (int i = 0; i < nf; ++i) {
+      double sum = r_all[3 * s->fvert[i] + ax];
+      for (int k = s->first[i]; k < i; ++k) sum -= *env_at(s->Lenv, s, i, k) * y[k];
+      y[i] = sum / *env_at(s->Lenv, s, i, i);
+    }
+    for (int i = nf - 1; i >= 0; --i) {
+      double v = y[i] / *env_at(s->Lenv, s, i, i);
+      y[i] = v;
+      for (int k = s->first[i]; k < i; ++k) y[k] -= *env_at(s->Lenv, s, i, k) * v;
+    }
+    for (int i = 0; i < nf; ++i) x_all[3 * s->fvert[i] + ax] = y[i];
+  }
+  free(y);
+}
+
+void or_apply_A(const or_scene* s, const double* x_all, double* y_all) {
+  for (int i = 0; i < 3 * s->nv; ++i) y_all[i] = 0.0;
+  for (int i = 0; i < s->nf; ++i) {
+    int vi = s->fvert[i];
+    for (int j = s->first[i]; j <= i; ++j) {
+      int vj = s->fvert[j];
+      double a = *env_at(s->Aenv, s, i, j);
+      for (int ax = 0; ax < 3; ++ax) {
+        y_all[3 * vi + ax] += a * x_all[3 * vj + ax];
+        if (j != i) y_all[3 * vj + ax] += a * x_all[3 * vi + ax];
+      }
+    }
+  }
+}
+
+/* b(q) without its constant part: sum_e w_e V_e G_e^T p*_e(G_e q), Eq. A_basic */
+static void local_rhs_stats(const or_scene* s, const double* q, double* b_all, int* capped, int* maxit) {
+  for (int i = 0; i < 3 * s->nv; ++i) b_all[i] = 0.0;
+  for (int e = 0; e < s->ne; ++e) {
+    double F[9], U[9], V[9], sF[3], ss[3], T[9], P[9];
+    element_F(s, e, q, F);
+    or_svd3(F, U, sF, V);
+    int it = or_prox_stretch(sF, s->mu_bar, s->lam_bar, s->k_bar, ss);
+    if (it < 0) { if (capped) (*capped)++; it = -it; }
+    if (maxit && it > *maxit) *maxit = it;
+    for (int i = 0; i < 3; ++i)
+      for (int j = 0; j < 3; ++j) T[3 * i + j] = U[3 * i + j] * ss[j];
+    mat3_mul_nt(T, V, P);
+    element_scatter(s, e, s->w[e] * s->vol[e], P, b_all);
+  }
+}
+
+void or_local_rhs(const or_scene* s, const double* q, double* b_all) { local_rhs_stats(s, q, b_all, NULL, NULL); }
+
+/* y = K x with K = db/dq = sum_e w_e V_e G_e^T (d p* / d F) G_e, Eq. db_dq */
+void or_apply_K(const or_scene* s, const double* q, double tau, const double* x_all, double* y_all) {
+  double* xf = (double*)malloc(sizeof(double) * 3 * s->nv);
+  for (int v = 0; v < s->nv; ++v)
+    for (int ax = 0; ax < 3; ++ax) xf[3 * v + ax] = s->fidx[v] >= 0 ? x_all[3 * v + ax] : 0.0;
+  for (int i = 0; i < 3 * s->nv; ++i) y_all[i] = 0.0;
+  for (int e = 0; e < s->ne; ++e) {
+    double F[9], U[9], V[9], sF[3], ss[3], D[9], c1[3], c2[3], dF[9], dP[9];
+    element_F(s, e, q, F);
+    or_svd3(F, U, sF, V);
+    or_prox_stretch(sF, s->mu_bar, s->lam_bar, s->k_bar, ss);
+    prox_diff_coeffs(sF, ss, s->mu_bar, s->lam_bar, s->k_bar, tau, D, c1, c2);
+    element_F(s, e, xf, dF);
+    prox_diff_apply(U, V, D, c1, c2, dF, dP);
+    element_scatter(s, e, s->w[e] * s->vol[e], dP, y_all);
+  }
+  for (int v = 0; v < s->nv; ++v)
+    if (s->fidx[v] < 0) y_all[3 * v] = y_all[3 * v + 1] = y_all[3 * v + 2] = 0.0;
+  free(xf);
+}
+
+/* Per-element filtered prox differential at q (Alg. 2 element loop), stored
+ * as U, V, D, c1, c2 (33 numbers per element) and applied to many vectors. */
+static double* prox_diff_all(const or_scene* s, const double* q, double tau) {
+  double* st = (double*)malloc(sizeof(double) * 33 * (size_t)s->ne);
+  for (int e = 0; e < s->ne; ++e) {
+    double F[9], sF[3], ss[3];
+    double* c = st + 33 * (size_t)e;
+    element_F(s, e, q, F);
+    or_svd3(F, c, sF, c + 9);
+    or_prox_stretch(sF, s->mu_bar, s->lam_bar, s->k_bar, ss);
+    prox_diff_coeffs(sF, ss, s->mu_bar, s->lam_bar, s->k_bar, tau, c + 18, c + 27, c + 30);
+  }
+  return st;
+}
+
+static void apply_K_stored(const or_scene* s, const double* st, const double* x_all, double* y_all) {
+  double* xf = (double*)malloc(sizeof(double) * 3 * s->nv);
+  for (int v = 0; v < s->nv; ++v)
+    for (int ax = 0; ax < 3; ++ax) xf[3 * v + ax] = s->fidx[v] >= 0 ? x_all[3 * v + ax] : 0.0;
+  for (int i = 0; i < 3 * s->nv; ++i) y_all[i] = 0.0;
+  for (int e = 0; e < s->ne; ++e) {
+    const double* c = st + 33 * (size_t)e;
+    double dF[9], dP[9];
+    element_F(s, e, xf, dF);
+    prox_diff_apply(c, c + 9, c + 18, c + 27, c + 30, dF, dP);
+    element_scatter(s, e, s->w[e] * s->vol[e], dP, y_all);
+  }
+  for (int v = 0; v < s->nv; ++v)
+    if (s->fidx[v] < 0) y_all[3 * v] = y_all[3 * v + 1] = y_all[3 * v + 2] = 0.0;
+  free(xf);
+}
+
+/* Primal objective Phi, Eq. primal, with the true per-element mu_e, lam_e */
+double or_primal_phi(const or_scene* s, const double* q, const double* qtilde) {
+  double phi = 0.0, h = s->h;
+  for (int v = 0; v < s->nv; ++v)
+    for (int ax = 0; ax < 3; ++ax) {
+      double d = q[3 * v + ax] - qtilde[3 * v + ax];
+      phi += 0.5 / (h * h) * s->mass[v] * d * d;
+    }
+  for (int e = 0; e < s->ne; ++e) {
+    double F[9];
+    element_F(s, e, q, F);
+    phi += s->vol[e] * or_psi_nh(F, s->mu[e], s->lam[e]);
+  }
+  return phi;
+}
+
+/* Constant part of the right-hand side (Alg. 1 prologue, Eq. freefall, and
+ * READING of the damping terms from Eq. dynamics with v = (q - q_t)/h):
+ * qtilde = q_t + h v_t + h^2 M^-1 f_ext + h^2 g,
+ * c = M/h^2 qtilde + (alpha/h) M q_t + (1/h) B_beta q_t - A~_{free,pinned} q_pinned.
+ * Pinned vertices are held at their rest positions. */
+void or_const_rhs(const or_scene* s, const double* q_t, const double* v_t, const double* f_ext, double* c_all,
+                  double* qtilde_all) {
+  double h = s->h;
+  for (int v = 0; v < s->nv; ++v)
+    for (int ax = 0; ax < 3; ++ax) {
+      double f = f_ext ? f_ext[3 * v + ax] : 0.0;
+      double qt = q_t[3 * v + ax] + h * v_t[3 * v + ax] + h * h * (f / s->mass[v] + s->grav[ax]);
+      if (qtilde_all) qtilde_all[3 * v + ax] = qt;
+      c_all[3 * v + ax] = s->mass[v] / (h * h) * qt + s->alpha / h * s->mass[v] * q_t[3 * v + ax];
+    }
+  for (int e = 0; e < s->ne; ++e) {
+    const double* B = s->Bhat + 12 * e;
+    for (int a = 0; a < 4; ++a) {
+      int va = s->tets[4 * e + a];
+      for (int b = 0; b < 4; ++b) {
+        int vb = s->tets[4 * e + b];
+        double d = B[3 * a] * B[3 * b] + B[3 * a + 1] * B[3 * b + 1] + B[3 * a + 2] * B[3 * b + 2];
+        double cb = s->beta[e] / h * s->vol[e] * d;                   /* (1/h) B_beta q_t */
+        double cp = (s->w[e] + s->beta[e] / h) * s->vol[e] * d;       /* A~ coupling to pinned */
+        for (int ax = 0; ax < 3; ++ax) {
+          c_all[3 * va + ax] += cb * q_t[3 * vb + ax];
+          if (s->pinned[vb]) c_all[3 * va + ax] -= cp * s->X[3 * vb + ax];
+        }
+      }
+    }
+  }
+  /* the pinned part of q is the rest position, so the A~ term on the pinned
+   * block cancels the other pinned terms; pinned rows are never used. */
+}
+
+static double dot_free(const or_scene* s, const double* a, const double* b) {
+  double r = 0.0;
+  for (int v = 0; v < s->nv; ++v)
+    if (s->fidx[v] >= 0)
+      for (int ax = 0; ax < 3; ++ax) r += a[3 * v + ax] * b[3 * v + ax];
+  return r;
+}
+
+/* One bounded type-II Anderson step on vectors of length n (Sec. 4.3, Eqs.
+ * aa_dG, aa_dQ, aa_gamma, aa_update and the reliability guard).  The history
+ * holds at most m+1 pairs (q^j, g^j), oldest first, in Hq, Hg (n x (m+1)), with
+ * *hn pairs (READING: m+1 pairs give the m difference columns).  The pair
+ * (q, g = qhat - q) is appended; with at least two pairs,
+ *   gamma = (dG^T dG + rho I)^-1 dG^T g,  rho = max(1e-6 |dG|_F^2 / m_c, 1e-12),
+ * m_c the current number of columns, and q_new = qhat - (dQ + dG) gamma; when
+ * |gamma|_2 > 10 the history is dropped (the current pair included) and
+ * q_new = qhat.  Inner products run over the entries with mask[i] != 0 (all if
+ * mask is NULL).  gamma_out (may be NULL) receives gamma.  Returns 1 on a
+ * reset, else 0. */
+int or_aa_step(int n, int m, double* Hq, double* Hg, int* hn, const double* q, const double* qhat,
+               const unsigned char* mask, double* qnew, double* gamma_out) {
+  int hcap = m + 1, reset = 0;
+  if (m <= 0) {
+    memcpy(qnew, qhat, sizeof(double) * n);
+    return 0;
+  }
+  if (*hn == hcap) {
+    memmove(Hq, Hq + n, sizeof(double) * n * (hcap - 1));
+    memmove(Hg, Hg + n, sizeof(double) * n * (hcap - 1));
+    (*hn)--;
+  }
+  double* gq = Hq + (size_t)(*hn) * n;
+  double* gg = Hg + (size_t)(*hn) * n;
+  for (int i = 0; i < n; ++i) { gq[i] = q[i]; gg[i] = qhat[i] - q[i]; }
+  (*hn)++;
+  if (*hn < 2) {
+    memcpy(qnew, qhat, sizeof(double) * n);
+    return 0;
+  }
+  int mc = *hn - 1;
+  double G[64], rhs[8], gam[8], L[64];
+  const double* g = Hg + (size_t)mc * n;
+  double* dG = (double*)malloc(sizeof(double) * n * mc);
+  double* dQ = (double*)malloc(sizeof(double) * n * mc);
+  for (int j = 0; j < mc; ++j)
+    for (int i = 0; i < n; ++i) {
+      dG[(size_t)j * n + i] = Hg[(size_t)(j + 1) * n + i] - Hg[(size_t)j * n + i];
+      dQ[(size_t)j * n + i] = Hq[(size_t)(j + 1) * n + i] - Hq[(size_t)j * n + i];
+    }
+  double fro = 0;
+  for (int a = 0; a < mc; ++a) {
+    for (int c = 0; c < mc; ++c) {
+      double d = 0;
+      for (int i = 0; i < n; ++i) if (!mask || mask[i]) d += dG[(size_t)a * n + i] * dG[(size_t)c * n + i];
+      G[a * mc + c] = d;
+    }
+    double d = 0;
+    for (int i = 0; i < n; ++i) if (!mask || mask[i]) d += dG[(size_t)a * n + i] * g[i];
+    rhs[a] = d;
+    fro += G[a * mc + a];
+  }
+  double rho = 1e-6 * fro / mc;
+  if (rho < 1e-12) rho = 1e-12;
+  for (int a = 0; a < mc; ++a) G[a * mc + a] += rho;
+  memcpy(L, G, sizeof(double) * mc * mc);
+  double gn = INFINITY;
+  if (small_chol(L, mc)) {
+    small_chol_solve(L, mc, rhs, gam);
+    gn = 0;
+    for (int a = 0; a < mc; ++a) gn += gam[a] * gam[a];
+    gn = sqrt(gn);
+  }
+  if (gn <= 10.0) {
+    for (int i = 0; i < n; ++i) {
+      double t = qhat[i];
+      for (int j = 0; j < mc; ++j) t -= (dQ[(size_t)j * n + i] + dG[(size_t)j * n + i]) * gam[j];
+      qnew[i] = t;
+    }
+    if (gamma_out) for (int a = 0; a < mc; ++a) gamma_out[a] = gam[a];
+  } else {
+    memcpy(qnew, qhat, sizeof(double) * n);
+    *hn = 0;
+    reset = 1;
+  }
+  free(dG);
+  free(dQ);
+  return reset;
+}
+
+/* ------------------------------------------------------------------------ */
+/* forward step, Alg. 1 (no contact)                                         */
+/* ------------------------------------------------------------------------ */
+int or_step_forward(const or_scene* s, const double* q_t, const double* v_t, const double* f_ext, const double* q0,
+                    double* q_next, double* v_next, double* q_star_m1, int force_iters, int m_override,
+                    int rec_max, double* rec, int* istats, double* dstats) {
+  int nv = s->nv, n3 = 3 * nv;
+  int m = m_override >= 0 ? m_override : s->m;
+  double* c = (double*)malloc(sizeof(double) * n3);
+  double* q = (double*)malloc(sizeof(double) * n3);
+  double* qprev = (double*)malloc(sizeof(double) * n3);
+  double* b = (double*)malloc(sizeof(double) * n3);
+  double* bprev = (double*)malloc(sizeof(double) * n3);
+  double* qhat = (double*)malloc(sizeof(double) * n3);
+  double* g = (double*)malloc(sizeof(double) * n3);
+  /* history H of (q, g) pairs, at most m+1 entries (READING: m difference
+   * columns), stored oldest first */
+  int hcap = m + 1;
+  double* Hq = (double*)malloc(sizeof(double) * n3 * (hcap > 0 ? hcap : 1));
+  double* Hg = (double*)malloc(sizeof(double) * n3 * (hcap > 0 ? hcap : 1));
+  int hn = 0;
+  or_const_rhs(s, q_t, v_t, f_ext, c, NULL);
+  /* q^0 = q_t (or the supplied warm start), pinned entries at rest */
+  for (int v = 0; v < nv; ++v)
+    for (int ax = 0; ax < 3; ++ax) {
+      double x = q0 ? q0[3 * v + ax] : q_t[3 * v + ax];
+      q[3 * v + ax] = s->pinned[v] ? s->X[3 * v + ax] : x;
+    }
+  memcpy(qprev, q, sizeof(double) * n3);
+  int k, status = 1, resets = 0, capped = 0, maxit = 0;
+  double gate[4] = {0, 0, 0, 0};
+  int kmax = force_iters > 0 ? force_iters + 1 : s->kmax_fwd;
+  for (k = 0; k < kmax; ++k) {
+    if (rec && k < rec_max) memcpy(rec + (size_t)k * n3, q, sizeof(double) * n3);
+    /* local step and right-hand side, Alg. 1 */
+    local_rhs_stats(s, q, b, &capped, &maxit);
+    for (int i = 0; i < n3; ++i) b[i] += c[i];
+    /* dual gate, Eq. convergence_dual, evaluated once b(q^k) exists: it
+     * compares q^k with q^{k-1} and b^k with b^{k-1}; the paper's "k >= 1"
+     * at loop index k-1 means k >= 2 here. */
+    if (k >= 1) {
+      double dq = 0, nq = 0, db = 0, nb = 0;
+      for (int v = 0; v < nv; ++v) {
+        if (s->fidx[v] < 0) continue;
+        for (int ax = 0; ax < 3; ++ax) {
+          int i = 3 * v + ax;
+          dq += (q[i] - qprev[i]) * (q[i] - qprev[i]);
+          nq += qprev[i] * qprev[i];
+          db += (b[i] - bprev[i]) * (b[i] - bprev[i]);
+          nb += bprev[i] * bprev[i];
+        }
+      }
+      gate[0] = sqrt(dq); gate[1] = sqrt(nq); gate[2] = sqrt(db); gate[3] = sqrt(nb);
+      int pass = gate[0] <= s->eps_rel * gate[1] + s->eps_abs && gate[2] <= s->eps_rel * gate[3] + s->eps_abs;
+      if (force_iters <= 0 && k >= 2 && pass) { status = 0; break; }
+    }
+    if (force_iters > 0 && k == force_iters) { status = 0; break; }
+    if (force_iters <= 0 && k == kmax - 1) break; /* not converged */
+    /* global solve q^ = A^-1 b, Eq. two_spmv (role) */
+    or_apply_Ainv(s, b, qhat);
+    /* bounded type-II Anderson acceleration, Eqs. aa_dG..aa_update */
+    memcpy(qprev, q, sizeof(double) * n3);
+    memcpy(bprev, b, sizeof(double) * n3);
+    memcpy(g, q, sizeof(double) * n3);
+    if (or_aa_step(n3, m, Hq, Hg, &hn, g, qhat, s->fmask3, q, NULL)) resets++;
+    /* Dirichlet vertices stay at rest */
+    for (int v = 0; v < nv; ++v)
+      if (s->pinned[v]) for (int ax = 0; ax < 3; ++ax) q[3 * v + ax] = s->X[3 * v + ax];
+  }
+  for (int i = 0; i < n3; ++i) {
+    q_next[i] = q[i];
+    v_next[i] = (q[i] - q_t[i]) / s->h;
+    if (q_star_m1) q_star_m1[i] = qprev[i];
+  }
+  if (istats) { istats[0] = k; istats[1] = resets; istats[2] = capped; istats[3] = maxit; istats[4] = status; }
+  if (dstats) for (int i = 0; i < 4; ++i) dstats[i] = gate[i];
+  free(c); free(q); free(qprev); free(b); free(bprev); free(qhat); free(g); free(Hq); free(Hg);
+  return status;
+}
+
+/* dense LU with partial pivoting, in place; solves A x = b (n small) */
+static int dense_lu_solve(double* A, int n, double* b) {
+  for (int k = 0; k < n; ++k) {
+    int p = k;
+    for (int i = k + 1; i < n; ++i) if (fabs(A[(size_t)i * n + k]) > fabs(A[(size_t)p * n + k])) p = i;
+    if (A[(size_t)p * n + k] == 0.0) return 0;
+    if (p != k) {
+      for (int j = 0; j < n; ++j) { double t = A[(size_t)k * n + j]; A[(size_t)k * n + j] = A[(size_t)p * n + j]; A[(size_t)p * n + j] = t; }
+      double t = b[k]; b[k] = b[p]; b[p] = t;
+    }
+    for (int i = k + 1; i < n; ++i) {
+      double f = A[(size_t)i * n + k] / A[(size_t)k * n + k];
+      if (f == 0.0) continue;
+      for (int j = k; j < n; ++j) A[(size_t)i * n + j] -= f * A[(size_t)k * n + j];
+      b[i] -= f * b[k];
+    }
+  }
+  for (int i = n - 1; i >= 0; --i) {
+    double sum = b[i];
+    for (int j = i + 1; j < n; ++j) sum -= A[(size_t)i * n + j] * b[j];
+    b[i] = sum / A[(size_t)i * n + i];
+  }
+  return 1;
+}
+
+/* ------------------------------------------------------------------------ */
+/* backward step, Alg. 2 (no contact)                                        */
+/* ------------------------------------------------------------------------ */
+int or_step_backward(const or_scene* s, const double* q_t, const double* v_t, const double* f_ext,
+                     const double* q_star, const double* q_star_m1, const double* gq_next, const double* gv_next,
+                     double* gq_t, double* gv_t, double* gf_ext, double* g_logE, int adj_mode, double tau_force,
+                     int* istats, double* dstats) {
+  int nv = s->nv, n3 = 3 * nv;
+  double h = s->h;
+  double* qbar = (double*)malloc(sizeof(double) * n3);
+  double* qtilde = (double*)malloc(sizeof(double) * n3);
+  double* c = (double*)malloc(sizeof(double) * n3);
+  double* dq = (double*)malloc(sizeof(double) * n3);
+  double* Adq = (double*)malloc(sizeof(double) * n3);
+  /* q^bar = q^bar_{t+h} + v^bar_{t+h} / h on free vertices (Alg. 2) */
+  for (int v = 0; v < nv; ++v)
+    for (int ax = 0; ax < 3; ++ax) {
+      int i = 3 * v + ax;
+      qbar[i] = s->fidx[v] >= 0 ? gq_next[i] + gv_next[i] / h : 0.0;
+    }
+  or_const_rhs(s, q_t, v_t, f_ext, c, qtilde);
+  /* trust-region ratio on the last fixed-point increment, Eqs. tr_step,
+   * tr_decreases, tr_ratio, tr_rule.  READING: Phi(q*-1) - Phi(q*) is summed as
+   * per-vertex and per-element differences (the same sum, regrouped). */
+  double dphi_act = 0.0;
+  for (int v = 0; v < nv; ++v)
+    for (int ax = 0; ax < 3; ++ax) {
+      int i = 3 * v + ax;
+      double a = q_star_m1[i], b = q_star[i];
+      dphi_act += 0.5 / (h * h) * s->mass[v] * (a - b) * (a + b - 2.0 * qtilde[i]);
+    }
+  for (int e = 0; e < s->ne; ++e) {
+    double Fa[9], Fb[9];
+    element_F(s, e, q_star_m1, Fa);
+    element_F(s, e, q_star, Fb);
+    double pa = or_psi_nh(Fa, s->mu[e], s->lam[e]), pb = or_psi_nh(Fb, s->mu[e], s->lam[e]);
+    dphi_act += s->vol[e] * (pa - pb);
+  }
+  for (int v = 0; v < nv; ++v)
+    for (int ax = 0; ax < 3; ++ax) dq[3 * v + ax] = s->fidx[v] >= 0 ? q_star[3 * v + ax] - q_star_m1[3 * v + ax] : 0.0;
+  or_apply_A(s, dq, Adq);
+  double dphi_mod = 0.5 * fabs(dot_free(s, dq, Adq));
+  double rho = dphi_mod < 1e-12 ? 1.0 : dphi_act / dphi_mod;
+  double tau = fabs(rho - 1.0) <= s->eps_tr ? 0.5 : 1.0;
+  if (tau_force >= 0.0) tau = tau_force;
+  /* adjoint: (A - K) mu = q^bar (Eqs. adjoint_system, Rqq, db_dq with the
+   * filtered prox differential; A, K symmetric).  READING: solved to
+   * tolerance, by the fixed-point iteration mu <- A^-1 (q^bar + K mu), or, for
+   * small meshes, by a dense direct solve. */
+  double* mu = (double*)calloc(n3, sizeof(double));
+  double* kst = prox_diff_all(s, q_star, tau);
+  int iters = 0, status = 0;
+  if (adj_mode == 1) {
+    int nf = s->nf, N = 3 * nf;
+    double* Mat = (double*)malloc(sizeof(double) * (size_t)N * N);
+    double* col = (double*)calloc(n3, sizeof(double));
+    double* Ac = (double*)malloc(sizeof(double) * n3);
+    double* Kc = (double*)malloc(sizeof(double) * n3);
+    for (int j = 0; j < N; ++j) {
+      int vj = s->fvert[j / 3], aj = j % 3;
+      col[3 * vj + aj] = 1.0;
+      or_apply_A(s, col, Ac);
+      apply_K_stored(s, kst, col, Kc);
+      col[3 * vj + aj] = 0.0;
+      for (int i = 0; i < N; ++i) {
+        int vi = s->fvert[i / 3], ai = i % 3;
+        Mat[(size_t)i * N + j] = Ac[3 * vi + ai] - Kc[3 * vi + ai];
+      }
+    }
+    double* rhs = (double*)malloc(sizeof(double) * N);
+    for (int i = 0; i < N; ++i) rhs[i] = qbar[3 * s->fvert[i / 3] + i % 3];
+    if (!dense_lu_solve(Mat, N, rhs)) status = -1;
+    for (int i = 0; i < N; ++i) mu[3 * s->fvert[i / 3] + i % 3] = rhs[i];
+    free(Mat); free(col); free(Ac); free(Kc); free(rhs);
+  } else {
+    double* t = (double*)malloc(sizeof(double) * n3);
+    double* mun = (double*)malloc(sizeof(double) * n3);
+    status = 1;
+    for (iters = 1; iters <= s->kmax_bwd; ++iters) {
+      apply_K_stored(s, kst, mu, t);
+      for (int i = 0; i < n3; ++i) t[i] += qbar[i];
+      or_apply_Ainv(s, t, mun);
+      double d = 0, nrm = 0;
+      for (int i = 0; i < n3; ++i) {
+        d += (mun[i] - mu[i]) * (mun[i] - mu[i]);
+        nrm += mun[i] * mun[i];
+      }
+      memcpy(mu, mun, sizeof(double) * n3);
+      if (sqrt(d) <= s->eps_adj * sqrt(nrm)) { status = 0; break; }
+    }
+    if (iters > s->kmax_bwd) iters = s->kmax_bwd;
+    free(t); free(mun);
+  }
+  /* gradient routing (Eqs. dl_dq, dl_dv_dfext, dl_dwe).  READING: the
+   * implicit-function theorem on A q - b(q) - c(theta) = 0 gives
+   * dL/dq_t = (M/h^2 + alpha M/h + B_beta/h) mu - v^bar/h, dL/dv_t = M mu / h,
+   * dL/df_ext = mu; per element dL/dw_e = V_e <G mu, p* - G q*> and
+   * dL/dbeta_e = (V_e/h) <G mu, G (q_t - q*)>; w_e and beta_e scale with E_e,
+   * the mesh means and mu_ref are held fixed. */
+  double* Bmu = (double*)calloc(n3, sizeof(double));
+  for (int e = 0; e < s->ne; ++e) {
+    double Gm[9], F[9], Fd[9], P[9], U[9], V[9], sF[3], ss[3], T[9];
+    double qd[12];
+    element_F(s, e, mu, Gm);
+    element_F(s, e, q_star, F);
+    or_svd3(F, U, sF, V);
+    or_prox_stretch(sF, s->mu_bar, s->lam_bar, s->k_bar, ss);
+    for (int i = 0; i < 3; ++i)
+      for (int j = 0; j < 3; ++j) T[3 * i + j] = U[3 * i + j] * ss[j];
+    mat3_mul_nt(T, V, P);
+    double gw = 0.0;
+    for (int i = 0; i < 9; ++i) gw += Gm[i] * (P[i] - F[i]);
+    gw *= s->vol[e];
+    /* G (q_t - q*) */
+    for (int i = 0; i < 9; ++i) Fd[i] = 0.0;
+    for (int a = 0; a < 4; ++a) {
+      int v = s->tets[4 * e + a];
+      for (int ax = 0; ax < 3; ++ax) qd[3 * a + ax] = q_t[3 * v + ax] - q_star[3 * v + ax];
+      if (s->pinned[v]) for (int ax = 0; ax < 3; ++ax) qd[3 * a + ax] = 0.0;
+      const double* B = s->Bhat + 12 * e + 3 * a;
+      for (int i = 0; i < 3; ++i)
+        for (int j = 0; j < 3; ++j) Fd[3 * i + j] += qd[3 * a + i] * B[j];
+    }
+    double gb = 0.0;
+    for (int i = 0; i < 9; ++i) gb += Gm[i] * Fd[i];
+    gb *= s->vol[e] / h;
+    g_logE[e] += s->w[e] * gw + s->beta[e] * gb;
+    /* B_beta mu = sum_e beta_e V_e G^T G mu */
+    element_scatter(s, e, s->beta[e] * s->vol[e], Gm, Bmu);
+  }
+  for (int v = 0; v < nv; ++v)
+    for (int ax = 0; ax < 3; ++ax) {
+      int i = 3 * v + ax;
+      if (s->fidx[v] < 0) { gq_t[i] = 0; gv_t[i] = 0; gf_ext[i] = 0; continue; }
+      double m = s->mass[v];
+      gq_t[i] = (m / (h * h) + s->alpha * m / h) * mu[i] + Bmu[i] / h - gv_next[i] / h;
+      gv_t[i] = m / h * mu[i];
+      gf_ext[i] = mu[i];
+    }
+  if (istats) { istats[0] = iters; istats[1] = status; }
+  if (dstats) { dstats[0] = rho; dstats[1] = tau; dstats[2] = dphi_act; dstats[3] = dphi_mod; }
+  free(qbar); free(qtilde); free(c); free(dq); free(Adq); free(mu); free(Bmu); free(kst);
+  return status;
+}

@@ -1,0 +1,72 @@
+/*
+ * Plain FP64 CPU oracle for differentiable Projective Dynamics with a
+ * Neo-Hookean proximal local step (test infrastructure only).
+ *
+ * This library is the reference the HIP path is checked against.  Only the
+ * test-suite, the smoke check and the CPU-baseline leg of the benchmark may
+ * load it.  It shares no code with the GPU library.
+ *
+ * Vectors of positions are vertex-major: q[3*v + axis], original vertex order.
+ */
+#ifndef PD_ORACLE_H
+#define PD_ORACLE_H
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct or_scene or_scene;
+
+/* params: nu, rho, alpha, beta0, h, gx, gy, gz
+ * solver: m (AA window), eps_rel, eps_abs, kmax_fwd, kmax_bwd, eps_adj, eps_tr,
+ *         then mu_bar, lam_bar, mu_ref (frozen if mu_bar > 0, else computed) */
+or_scene* or_scene_create(int nv, int ne, const double* X, const int* tets, const unsigned char* pinned,
+                          const double* logE, const double* params, const double* solver);
+void or_scene_destroy(or_scene* s);
+int or_scene_nfree(const or_scene* s);
+/* per-element / per-vertex quantities after setup (any may be NULL) */
+void or_scene_info(const or_scene* s, double* vol, double* w, double* beta, double* mass, double* means4);
+
+/* --- element level --- */
+void or_svd3(const double F[9], double U[9], double sig[3], double V[9]);
+int or_prox_stretch(const double sF[3], double mu, double lam, double k, double s_out[3]);
+void or_prox_map(const double F[9], double mu, double lam, double k, double P[9]);
+void or_prox_jacobian(const double F[9], double mu, double lam, double k, double tau, double J[81]);
+double or_psi_nh(const double F[9], double mu, double lam);
+void or_sym3_eig(const double H[9], double kappa[3], double Q[9]);
+void or_tr_filter(const double H[9], double tau, double k, double Ht[9], double Dinv[9]);
+int or_aa_step(int n, int m, double* Hq, double* Hg, int* hn, const double* q, const double* qhat,
+               const unsigned char* mask, double* qnew, double* gamma_out);
+
+/* --- global level --- */
+/* b(q) over all vertices (3*nv), without the constant part c; pinned rows included */
+void or_local_rhs(const or_scene* s, const double* q, double* b_all);
+/* constant part of the right-hand side over all vertices (pinned rows meaningless) */
+void or_const_rhs(const or_scene* s, const double* q_t, const double* v_t, const double* f_ext, double* c_all,
+                  double* qtilde_all);
+/* x = A~^{-1} r on free vertices, per axis (r, x over all vertices; pinned entries ignored / zeroed) */
+void or_apply_Ainv(const or_scene* s, const double* r_all, double* x_all);
+/* y = A~ x over all vertices (free rows and columns only) */
+void or_apply_A(const or_scene* s, const double* x_all, double* y_all);
+/* y = K x, K = db/dq at configuration q with TR parameter tau (free rows/cols only) */
+void or_apply_K(const or_scene* s, const double* q, double tau, const double* x_all, double* y_all);
+double or_primal_phi(const or_scene* s, const double* q, const double* qtilde);
+
+/* istats: [0] iterations, [1] AA resets, [2] newton cap hits, [3] max newton iters, [4] status
+ * dstats: [0..3] last gate norms (dq, q, db, b)
+ * force_iters > 0 runs exactly that many PD iterations (gate ignored);
+ * record: if non-NULL, iterates q^k (k = 0..rec_max-1) are stored there. */
+int or_step_forward(const or_scene* s, const double* q_t, const double* v_t, const double* f_ext, const double* q0,
+                    double* q_next, double* v_next, double* q_star_m1, int force_iters, int m_override,
+                    int rec_max, double* rec, int* istats, double* dstats);
+
+/* istats: [0] adjoint iterations, [1] status; dstats: [0] rho, [1] tau, [2] dphi_act, [3] dphi_mod
+ * adj_mode 0: fixed-point iteration to eps_adj; 1: dense direct solve (small meshes) */
+int or_step_backward(const or_scene* s, const double* q_t, const double* v_t, const double* f_ext,
+                     const double* q_star, const double* q_star_m1, const double* gq_next, const double* gv_next,
+                     double* gq_t, double* gv_t, double* gf_ext, double* g_logE, int adj_mode, double tau_force,
+                     int* istats, double* dstats);
+
+#ifdef __cplusplus
+}
+#endif
+#endif

@@ -1,0 +1,257 @@
+"""Seeded synthetic scene generators (inputs only).
+
+This module builds the meshes, material fields, force schedules and loss
+targets that stand in for the paper's scenes (Sec. 5, Table of examples: the
+cantilever, the contact drops).  It holds none of the solver's arithmetic: no
+Lame parameters, masses, weights or projections are computed here, only
+geometry (vertex grids, the 5-tet cube split, orientation of each tet), random
+fields and schedules.  Both the CPU oracle and the HIP library consume these
+arrays, so it is the only code the two share.
+
+Conventions
+-----------
+* ``X``      rest positions, float64, shape (n_v, 3), vertex-major.
+* ``tets``   int32, shape (n_e, 4), positively oriented
+             (det[x1-x0, x2-x0, x3-x0] > 0).
+* ``pinned`` uint8, shape (n_v,), 1 for a Dirichlet vertex held at rest.
+* ``log_E``  float64, shape (n_e,), natural log of Young's modulus in Pa.
+* Seeds use ``numpy.random.Generator(PCG64(seed))``.
+"""
+from __future__ import annotations
+
+import dataclasses
+from typing import Callable, Optional
+
+import numpy as np
+
+
+def _rng(seed: int) -> np.random.Generator:
+    return np.random.Generator(np.random.PCG64(seed))
+
+
+# The 5-tet split of a unit cube.  Corners are indexed by (i, j, k) in {0,1}^3.
+# Even-parity cubes cut off the corners (0,0,0), (1,1,0), (1,0,1), (0,1,1) and
+# keep the central tet on the other four corners; odd-parity cubes mirror that
+# choice, so shared faces carry the same diagonal and the mesh is conforming.
+_EVEN_CORNERS = [(0, 0, 0), (1, 1, 0), (1, 0, 1), (0, 1, 1)]
+_ODD_CORNERS = [(1, 0, 0), (0, 1, 0), (0, 0, 1), (1, 1, 1)]
+
+
+def _cube_tets(parity: int):
+    corners = _EVEN_CORNERS if parity == 0 else _ODD_CORNERS
+    tets = []
+    for c in corners:
+        nb = [(c[0] ^ 1, c[1], c[2]), (c[0], c[1] ^ 1, c[2]), (c[0], c[1], c[2] ^ 1)]
+        tets.append([c] + nb)
+    # central tet: the four corners not cut off
+    other = _ODD_CORNERS if parity == 0 else _EVEN_CORNERS
+    tets.append(list(other))
+    return tets
+
+
+def _orient(X: np.ndarray, tets: np.ndarray) -> np.ndarray:
+    d1 = X[tets[:, 1]] - X[tets[:, 0]]
+    d2 = X[tets[:, 2]] - X[tets[:, 0]]
+    d3 = X[tets[:, 3]] - X[tets[:, 0]]
+    det = np.einsum("ij,ij->i", d1, np.cross(d2, d3))
+    out = tets.copy()
+    neg = det < 0
+    out[neg, 1], out[neg, 2] = tets[neg, 2], tets[neg, 1]
+    return out
+
+
+def voxel_tet_mesh(occ: np.ndarray, edge: float, origin=(0.0, 0.0, 0.0)):
+    """Tetrahedralise the occupied voxels of a boolean grid ``occ[nx, ny, nz]``.
+
+    Each voxel is split into 5 tets with parity (i + j + k) mod 2.  Vertices
+    are numbered with x the slowest index, then y, then z; vertices not used by
+    any tet are dropped (numbering order is kept).
+    """
+    occ = np.asarray(occ, dtype=bool)
+    nx, ny, nz = occ.shape
+    vid = lambda i, j, k: (i * (ny + 1) + j) * (nz + 1) + k  # noqa: E731
+    templ = [_cube_tets(0), _cube_tets(1)]
+    tl = []
+    idx = np.argwhere(occ)
+    for (i, j, k) in idx:
+        for t in templ[(i + j + k) & 1]:
+            tl.append([vid(i + a, j + b, k + c) for (a, b, c) in t])
+    tets = np.asarray(tl, dtype=np.int64).reshape(-1, 4)
+    gi, gj, gk = np.meshgrid(np.arange(nx + 1), np.arange(ny + 1), np.arange(nz + 1), indexing="ij")
+    Xall = np.stack([gi.ravel(), gj.ravel(), gk.ravel()], axis=1).astype(np.float64) * edge
+    Xall += np.asarray(origin, dtype=np.float64)
+    used = np.zeros(Xall.shape[0], dtype=bool)
+    used[tets.ravel()] = True
+    remap = -np.ones(Xall.shape[0], dtype=np.int64)
+    remap[used] = np.arange(int(used.sum()))
+    X = Xall[used].copy()
+    tets = remap[tets]
+    tets = _orient(X, tets).astype(np.int32)
+    return X, tets
+
+
+def box_tet_mesh(nx: int, ny: int, nz: int, edge: float):
+    return voxel_tet_mesh(np.ones((nx, ny, nz), dtype=bool), edge)
+
+
+def gaussian_blob_field(points: np.ndarray, lo, hi, n_blobs: int, rng, sig_lo=0.1, sig_hi=0.3):
+    """Sum of ``n_blobs`` isotropic Gaussians with uniform centres in [lo, hi]."""
+    lo = np.asarray(lo, float)
+    hi = np.asarray(hi, float)
+    field = np.zeros(points.shape[0])
+    for _ in range(n_blobs):
+        c = lo + (hi - lo) * rng.random(3)
+        s = sig_lo + (sig_hi - sig_lo) * rng.random()
+        r2 = ((points - c) ** 2).sum(axis=1)
+        field += np.exp(-0.5 * r2 / (s * s))
+    return field
+
+
+def two_phase_log_E(field: np.ndarray, frac_stiff: float, E_soft: float, E_stiff: float) -> np.ndarray:
+    """Exactly ``round(frac_stiff * n)`` entries with the largest field are stiff."""
+    n = field.shape[0]
+    n_stiff = int(round(frac_stiff * n))
+    order = np.argsort(-field, kind="stable")
+    logE = np.full(n, np.log(E_soft))
+    logE[order[:n_stiff]] = np.log(E_stiff)
+    return logE
+
+
+@dataclasses.dataclass
+class Scene:
+    name: str
+    X: np.ndarray
+    tets: np.ndarray
+    pinned: np.ndarray
+    log_E: np.ndarray
+    nu: float
+    rho: float
+    alpha: float
+    beta0: float
+    h: float
+    gravity: np.ndarray
+    aa_window: int
+    steps: int
+    force_fn: Optional[Callable[[int], np.ndarray]]
+    target_centroid: np.ndarray
+    fd_tets: np.ndarray = dataclasses.field(default_factory=lambda: np.zeros(0, np.int64))
+    eps_rel: float = 1e-6
+    eps_abs: float = 1e-12
+
+    @property
+    def n_v(self) -> int:
+        return int(self.X.shape[0])
+
+    @property
+    def n_e(self) -> int:
+        return int(self.tets.shape[0])
+
+    def f_ext(self, t: int) -> np.ndarray:
+        if self.force_fn is None:
+            return np.zeros((self.n_v, 3))
+        return self.force_fn(t)
+
+    def q0(self) -> np.ndarray:
+        return self.X.copy()
+
+    def v0(self) -> np.ndarray:
+        return np.zeros((self.n_v, 3))
+
+
+def centroid_loss(q: np.ndarray, target: np.ndarray):
+    """Loss ||mean_v q_v - target||^2 and its gradient w.r.t. q (harness, not solver)."""
+    c = q.mean(axis=0)
+    d = c - target
+    g = np.broadcast_to(2.0 * d / q.shape[0], q.shape).copy()
+    return float(d @ d), g
+
+
+def cantilever_c1() -> Scene:
+    """Plain PD beam: 16x4x4 unit cubes along x, edge 0.05 m, 1280 tets / 425 verts.
+
+    Homogeneous E = 1e5 Pa, nu = 0.45, rho = 1000, x = 0 face pinned, gravity,
+    h = 0.01 s, 20 steps, Anderson window 5, no damping.
+    """
+    X, tets = box_tet_mesh(16, 4, 4, 0.05)
+    pinned = (np.abs(X[:, 0]) < 1e-12).astype(np.uint8)
+    logE = np.full(tets.shape[0], np.log(1e5))
+    rng = _rng(1001)
+    target = X.mean(axis=0) + rng.uniform(-0.05, 0.05, 3)
+    return Scene("c1_cantilever", X, tets, pinned, logE, nu=0.45, rho=1000.0, alpha=0.0, beta0=0.0,
+                 h=0.01, gravity=np.array([0.0, 0.0, -9.81]), aa_window=5, steps=20, force_fn=None,
+                 target_centroid=target)
+
+
+def _tip_force_fn(X: np.ndarray, total: float, seed: int, ramp: int, hold: int):
+    L = X[:, 0].max()
+    face = np.abs(X[:, 0] - L) < 1e-12
+    nface = int(face.sum())
+    rng = _rng(seed)
+    th = 2.0 * np.pi * rng.random()
+    d = np.array([0.2, np.cos(th), np.sin(th)])
+    d /= np.linalg.norm(d)
+    base = np.zeros_like(X)
+    base[face] = d * (total / nface)
+
+    def fn(t: int) -> np.ndarray:
+        if t < ramp:
+            s = (t + 1) / ramp
+        elif t < hold:
+            s = 1.0
+        else:
+            s = 0.0
+        return base * s
+
+    return fn
+
+
+def hetero_beam_c2(nx: int = 40, ny: int = 10, nz: int = 10, steps: int = 100) -> Scene:
+    """Heterogeneous beam: 40x10x10 cubes (edge 0.05 m) = 20000 tets / 4961 verts.
+
+    Two-phase E in {1e4, 1e6} Pa from 8 seeded Gaussian blobs (30 % stiff),
+    nu = 0.49, rho = 1000, Rayleigh alpha = 0.01 and beta0 = 1e-2 s * E_max,
+    x = 0 face pinned, no gravity, 50 N seeded tip force ramped over steps
+    0-19, held to step 59, then released; h = 0.005 s, 100 steps, window 1.
+    """
+    edge = 0.05
+    X, tets = box_tet_mesh(nx, ny, nz, edge)
+    pinned = (np.abs(X[:, 0]) < 1e-12).astype(np.uint8)
+    cen = X[tets].mean(axis=1)
+    rng = _rng(2001)
+    field = gaussian_blob_field(cen, X.min(axis=0), X.max(axis=0), 8, rng)
+    logE = two_phase_log_E(field, 0.3, 1e4, 1e6)
+    force = _tip_force_fn(X, 50.0, 2002, 20, 60)
+    rng3 = _rng(2003)
+    target = X.mean(axis=0) + rng3.uniform(-0.05, 0.05, 3)
+    fd = _rng(2004).choice(tets.shape[0], size=16, replace=False)
+    return Scene("c2_hetero_beam", X, tets, pinned, logE, nu=0.49, rho=1000.0, alpha=0.01,
+                 beta0=1e-2 * 1e6, h=0.005, gravity=np.zeros(3), aa_window=1, steps=steps,
+                 force_fn=force, target_centroid=target, fd_tets=fd)
+
+
+def small_beam(nx: int, ny: int, nz: int, seed: int = 7, contrast: float = 100.0, nu: float = 0.45,
+               alpha: float = 0.01, beta_rel: float = 1e-2, h: float = 0.01, gravity=(0.0, 0.0, -9.81),
+               tip_force: float = 5.0, aa_window: int = 1, steps: int = 5) -> Scene:
+    """Small heterogeneous beam for parity tests (C2-shaped, a few hundred tets)."""
+    edge = 0.05
+    X, tets = box_tet_mesh(nx, ny, nz, edge)
+    pinned = (np.abs(X[:, 0]) < 1e-12).astype(np.uint8)
+    cen = X[tets].mean(axis=1)
+    rng = _rng(seed)
+    field = gaussian_blob_field(cen, X.min(axis=0), X.max(axis=0), 3, rng, 0.03, 0.1)
+    E_soft = 1e4
+    logE = two_phase_log_E(field, 0.3, E_soft, E_soft * contrast)
+    force = _tip_force_fn(X, tip_force, seed + 1, 2, 4) if tip_force else None
+    target = X.mean(axis=0) + _rng(seed + 2).uniform(-0.05, 0.05, 3)
+    fd = _rng(seed + 3).choice(tets.shape[0], size=min(4, tets.shape[0]), replace=False)
+    return Scene(f"small_beam_{nx}x{ny}x{nz}", X, tets, pinned, logE, nu=nu, rho=1000.0, alpha=alpha,
+                 beta0=beta_rel * E_soft * contrast, h=h, gravity=np.asarray(gravity, float),
+                 aa_window=aa_window, steps=steps, force_fn=force, target_centroid=target, fd_tets=fd)
+
+
+def config(name: str) -> Scene:
+    if name in ("c1", "c1_cantilever"):
+        return cantilever_c1()
+    if name in ("c2", "c2_hetero_beam"):
+        return hetero_beam_c2()
+    raise KeyError(name)

@@ -1,0 +1,187 @@
+/*
+ * pdhot: MI355X (gfx950) library for the hot path of differentiable Projective
+ * Dynamics (PD) on heterogeneous Neo-Hookean tetrahedral meshes
+ * (arXiv 2605.14526, "DiffPhD").
+ *
+ * The library owns every internal buffer (factor blocks, element and vertex
+ * arrays, Anderson history, scratch).  Per-step inputs and outputs are
+ * caller-owned DEVICE buffers of doubles.  Every position-like vector is laid
+ * out as n_verts x 3 (vertex-major, x y z per vertex) in the caller's vertex
+ * numbering; the library reorders internally.
+ *
+ * Return values: PD_OK (0), PD_NOT_CONVERGED (1, a warning: results and
+ * statistics are still written), or a negative error code.  No C++ exception
+ * crosses this interface; pd_last_error() returns a message for the last
+ * failing call of the calling thread.
+ *
+ * All entry points are synchronous with respect to the host on return unless
+ * stated otherwise; `stream` is a hipStream_t passed as void* (NULL = the
+ * default stream).
+ */
+#ifndef PDHOT_H
+#define PDHOT_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+enum {
+  PD_OK = 0,
+  PD_NOT_CONVERGED = 1,
+  PD_ERR_INVALID_ARG = -1,
+  PD_ERR_DEGENERATE_TET = -2,
+  PD_ERR_NONFINITE = -3,
+  PD_ERR_STALE_FACTOR = -4,
+  PD_ERR_FACTOR_NOT_SPD = -5,
+  PD_ERR_HIP = -6,
+  PD_ERR_ALLOC = -7
+};
+
+typedef struct pd_scene pd_scene;
+
+/* Mesh (host pointers, copied by pd_scene_create).
+ * rest_xyz: n_verts x 3 rest positions.  tets: n_tets x 4 vertex indices; a
+ * tet with negative rest volume is reoriented, one with zero volume is an
+ * error (PD_ERR_DEGENERATE_TET).  pinned: n_verts flags, 1 = Dirichlet vertex
+ * held at its rest position. */
+typedef struct pd_mesh_desc {
+  int32_t n_verts;
+  int32_t n_tets;
+  const double* rest_xyz;
+  const int32_t* tets;
+  const uint8_t* pinned;
+} pd_mesh_desc;
+
+/* Material (host pointers, copied).  Per-tet Young's modulus E_e = exp(log_E[e])
+ * with a shared Poisson ratio nu gives the Lame parameters of Sec. 3.1
+ * Eq. lame; rho is the density; alpha (1/s) and beta0 (Pa s) are the Rayleigh
+ * coefficients of Sec. 4.5 Eq. rayleigh, beta_e = beta0 mu_e / max_e mu_e. */
+typedef struct pd_material_desc {
+  const double* log_E;
+  double nu;
+  double rho;
+  double alpha;
+  double beta0;
+} pd_material_desc;
+
+/* Solver options.
+ * h: time step (s).  gravity: acceleration added to every free vertex.
+ * aa_window: Anderson window m (Sec. 4.3; 0 = plain local-global iteration).
+ * eps_rel, eps_abs: dual-gate tolerances (Eq. convergence_dual).
+ * kmax_fwd: PD iteration cap (PD_NOT_CONVERGED beyond it).
+ * eps_adj, kmax_bwd: adjoint tolerance (relative preconditioned residual) and cap.
+ * eps_tr: trust-region tolerance of Eq. tr_rule (0.1 in the paper).
+ * adj_method: 0 = conjugate gradients preconditioned by the PD factor,
+ *             1 = the fixed-point iteration mu <- A^-1 (qbar + K mu).
+ * max_sub: largest subdomain (vertices) of the two-level partitioned inverse
+ *          (0 = library default).
+ * iters_per_check: PD iterations issued between convergence checks of the
+ *          host (0 = adaptive). */
+typedef struct pd_solver_opts {
+  double h;
+  double gravity[3];
+  int32_t aa_window;
+  double eps_rel;
+  double eps_abs;
+  int32_t kmax_fwd;
+  int32_t kmax_bwd;
+  double eps_adj;
+  double eps_tr;
+  int32_t adj_method;
+  int32_t max_sub;
+  int32_t iters_per_check;
+} pd_solver_opts;
+
+/* Forward statistics. gate[0..3] = |q^k - q^{k-1}|, |q^{k-1}|, |b^k - b^{k-1}|,
+ * |b^{k-1}| at exit; iters = number of global solves. */
+typedef struct pd_fwd_stats {
+  int32_t iters;
+  int32_t aa_resets;
+  int32_t status;
+  int32_t newton_max_iters;
+  double gate[4];
+} pd_fwd_stats;
+
+/* Backward statistics: adjoint iterations, trust-region ratio rho and the
+ * chosen tau (Eqs. tr_ratio, tr_rule), the two decreases of Eq. tr_decreases. */
+typedef struct pd_bwd_stats {
+  int32_t adj_iters;
+  int32_t status;
+  double rho;
+  double tau;
+  double dphi_act;
+  double dphi_mod;
+  double residual;
+} pd_bwd_stats;
+
+/* Create a scene: validates and copies the mesh and material, builds the
+ * library vertex order (nested-dissection subdomains, interface last, pinned
+ * vertices at the end) and the element arrays, and factorizes (so a new scene
+ * is ready to step).  Setup follows Alg. 1's stale-A branch (Secs. 4.1, 4.2,
+ * 4.5, 4.6).  Allocates device memory on the current HIP device. */
+int pd_scene_create(const pd_mesh_desc* mesh, const pd_material_desc* mat, const pd_solver_opts* opts,
+                    pd_scene** out);
+int pd_scene_destroy(pd_scene* scene);
+
+/* Replace the per-tet log Young's moduli (host pointer, n_tets values).  The
+ * factor becomes stale (refactorization policy, Sec. 4.6): stepping before
+ * pd_scene_factorize returns PD_ERR_STALE_FACTOR. */
+int pd_scene_set_material(pd_scene* scene, const double* log_E_host);
+
+/* Assemble A = (1 + alpha h) M / h^2 + sum_e (w_e + beta_e / h) V_e G_e^T G_e
+ * (Sec. 4.5 Eq. A_damped, Dirichlet vertices eliminated), freeze the mesh means
+ * mu_bar, lam_bar, k_bar and mu_ref, and build the partitioned inverse used by
+ * every solve (Sec. 4.6 Eq. Ainv_STS in role).  Host work plus one upload. */
+int pd_scene_factorize(pd_scene* scene, void* stream);
+
+/* Scene facts. info[0..6] = n_verts, n_tets, n_free, n_subdomains,
+ * n_interface, aa_window, factor bytes on the device (as double). means[0..3] =
+ * mu_bar, lam_bar, k_bar, mu_ref (may be NULL). */
+int pd_scene_info(const pd_scene* scene, double* info, double* means);
+
+/* Bytes of one checkpoint record (q_t, q tilde, q*, q*-1 of one step). */
+size_t pd_ckpt_bytes(const pd_scene* scene);
+
+/* One forward step (Alg. 1, no contact).
+ * q_t, v_t: current state; f_ext: external force per vertex (NULL = none;
+ * gravity from the options is added); q0: initial iterate (NULL = q_t,
+ * e.g. a learned warm start); outputs q_next, v_next (may alias nothing else);
+ * ckpt: caller-allocated device buffer of pd_ckpt_bytes() bytes or NULL.
+ * Pinned vertices are held at their rest positions.  Runs the local step,
+ * RHS assembly, dual gate, global solve and Anderson mixing until the gate
+ * holds (Secs. 4.1-4.3). */
+int pd_step_forward(pd_scene* scene, const double* q_t, const double* v_t, const double* f_ext,
+                    const double* q0, double* q_next, double* v_next, void* ckpt, pd_fwd_stats* stats,
+                    void* stream);
+
+/* One backward step (Alg. 2, no contact) from a checkpoint written by
+ * pd_step_forward.  gq_next, gv_next: dL/dq_{t+h}, dL/dv_{t+h}.  Outputs
+ * dL/dq_t, dL/dv_t, dL/df_ext (overwritten; zero on pinned vertices) and
+ * g_logE_accum += dL/dlog E_e (n_tets, caller's tet order).  Any output
+ * pointer may be NULL.  Implements the trust-region selection (Sec. 4.4),
+ * the filtered prox differential, the adjoint solve and the gradient routing
+ * (Sec. 4.8). */
+int pd_step_backward(pd_scene* scene, const void* ckpt, const double* gq_next, const double* gv_next,
+                     double* gq_t, double* gv_t, double* gf_ext, double* g_logE_accum, pd_bwd_stats* stats,
+                     void* stream);
+
+/* Diagnostic entry points (stage parity), all device pointers, n_verts x 3.
+ * pd_debug_local_rhs: b = sum_e w_e V_e G_e^T p*_e(G_e q) (Eq. A_basic without
+ *   its constant part), free rows (pinned rows zero).
+ * pd_debug_apply_Ainv: x = A~^{-1} r per axis on free vertices (pinned zero).
+ * pd_debug_apply_K: y = K x, K = sum_e w_e V_e G_e^T (d p* / d F)_tau G_e
+ *   (Eq. db_dq with the filtered differential of Eq. tr_ift), free rows/cols. */
+int pd_debug_local_rhs(pd_scene* scene, const double* q, double* b, void* stream);
+int pd_debug_apply_Ainv(pd_scene* scene, const double* r, double* x, void* stream);
+int pd_debug_apply_K(pd_scene* scene, const double* q, double tau, const double* x, double* y, void* stream);
+
+/* Message of the last failing call on this thread ("" if none). */
+const char* pd_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* PDHOT_H */

@@ -1,0 +1,216 @@
+"""ctypes binding of the pdhot C ABI (include/pdhot.h).
+
+Argument marshalling only: every step of the hot path runs in the HIP
+library.  PyTorch provides device memory (float64 tensors on ``cuda``) and the
+stream.  Loading fails loudly when the compiled library is missing; there is no
+CPU fallback.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+from typing import Optional
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libpdhot.so")
+
+PD_OK = 0
+PD_NOT_CONVERGED = 1
+ERRORS = {-1: "PD_ERR_INVALID_ARG", -2: "PD_ERR_DEGENERATE_TET", -3: "PD_ERR_NONFINITE",
+          -4: "PD_ERR_STALE_FACTOR", -5: "PD_ERR_FACTOR_NOT_SPD", -6: "PD_ERR_HIP", -7: "PD_ERR_ALLOC"}
+
+EXPORTED = ["pd_scene_create", "pd_scene_destroy", "pd_scene_set_material", "pd_scene_factorize", "pd_scene_info",
+            "pd_ckpt_bytes", "pd_step_forward", "pd_step_backward", "pd_debug_local_rhs", "pd_debug_apply_Ainv",
+            "pd_debug_apply_K", "pd_last_error"]
+
+
+class pd_mesh_desc(ctypes.Structure):
+    _fields_ = [("n_verts", ctypes.c_int32), ("n_tets", ctypes.c_int32), ("rest_xyz", ctypes.c_void_p),
+                ("tets", ctypes.c_void_p), ("pinned", ctypes.c_void_p)]
+
+
+class pd_material_desc(ctypes.Structure):
+    _fields_ = [("log_E", ctypes.c_void_p), ("nu", ctypes.c_double), ("rho", ctypes.c_double),
+                ("alpha", ctypes.c_double), ("beta0", ctypes.c_double)]
+
+
+class pd_solver_opts(ctypes.Structure):
+    _fields_ = [("h", ctypes.c_double), ("gravity", ctypes.c_double * 3), ("aa_window", ctypes.c_int32),
+                ("eps_rel", ctypes.c_double), ("eps_abs", ctypes.c_double), ("kmax_fwd", ctypes.c_int32),
+                ("kmax_bwd", ctypes.c_int32), ("eps_adj", ctypes.c_double), ("eps_tr", ctypes.c_double),
+                ("adj_method", ctypes.c_int32), ("max_sub", ctypes.c_int32), ("iters_per_check", ctypes.c_int32)]
+
+
+class pd_fwd_stats(ctypes.Structure):
+    _fields_ = [("iters", ctypes.c_int32), ("aa_resets", ctypes.c_int32), ("status", ctypes.c_int32),
+                ("newton_max_iters", ctypes.c_int32), ("gate", ctypes.c_double * 4)]
+
+
+class pd_bwd_stats(ctypes.Structure):
+    _fields_ = [("adj_iters", ctypes.c_int32), ("status", ctypes.c_int32), ("rho", ctypes.c_double),
+                ("tau", ctypes.c_double), ("dphi_act", ctypes.c_double), ("dphi_mod", ctypes.c_double),
+                ("residual", ctypes.c_double)]
+
+
+_lib = None
+
+
+def lib() -> ctypes.CDLL:
+    """Load libpdhot.so (raises if it has not been built)."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(LIB_PATH):
+        raise RuntimeError(f"pdhot: {LIB_PATH} is missing; build it with paper_2605_14526_amd/build.py "
+                           "(there is no fallback path)")
+    L = ctypes.CDLL(LIB_PATH)
+    vp, i32, dbl = ctypes.c_void_p, ctypes.c_int, ctypes.c_double
+    L.pd_scene_create.argtypes = [ctypes.POINTER(pd_mesh_desc), ctypes.POINTER(pd_material_desc),
+                                  ctypes.POINTER(pd_solver_opts), ctypes.POINTER(vp)]
+    L.pd_scene_destroy.argtypes = [vp]
+    L.pd_scene_set_material.argtypes = [vp, vp]
+    L.pd_scene_factorize.argtypes = [vp, vp]
+    L.pd_scene_info.argtypes = [vp, vp, vp]
+    L.pd_ckpt_bytes.argtypes = [vp]
+    L.pd_ckpt_bytes.restype = ctypes.c_size_t
+    L.pd_step_forward.argtypes = [vp, vp, vp, vp, vp, vp, vp, vp, ctypes.POINTER(pd_fwd_stats), vp]
+    L.pd_step_backward.argtypes = [vp, vp, vp, vp, vp, vp, vp, vp, ctypes.POINTER(pd_bwd_stats), vp]
+    L.pd_debug_local_rhs.argtypes = [vp, vp, vp, vp]
+    L.pd_debug_apply_Ainv.argtypes = [vp, vp, vp, vp]
+    L.pd_debug_apply_K.argtypes = [vp, vp, dbl, vp, vp, vp]
+    L.pd_last_error.restype = ctypes.c_char_p
+    for name in EXPORTED:
+        getattr(L, name)
+    _ = i32
+    _lib = L
+    return L
+
+
+def check(rc: int, what: str) -> int:
+    if rc < 0:
+        msg = lib().pd_last_error().decode()
+        raise RuntimeError(f"{what} failed with {ERRORS.get(rc, rc)}: {msg}")
+    return rc
+
+
+def _ptr(t) -> Optional[int]:
+    if t is None:
+        return None
+    return t.data_ptr()
+
+
+def _stream():
+    import torch
+    return ctypes.c_void_p(torch.cuda.current_stream().cuda_stream)
+
+
+class Scene:
+    """A pdhot scene on the current GPU (wraps pd_scene_create ... pd_scene_destroy)."""
+
+    def __init__(self, X, tets, pinned, log_E, nu, rho, alpha, beta0, h, gravity=(0.0, 0.0, 0.0), aa_window=1,
+                 eps_rel=1e-6, eps_abs=1e-12, kmax_fwd=1000, kmax_bwd=1000, eps_adj=1e-6, eps_tr=0.1,
+                 adj_method=0, max_sub=0, iters_per_check=0):
+        L = lib()
+        self._X = np.ascontiguousarray(X, dtype=np.float64)
+        self._tets = np.ascontiguousarray(tets, dtype=np.int32)
+        self._pinned = np.ascontiguousarray(pinned, dtype=np.uint8)
+        self._logE = np.ascontiguousarray(log_E, dtype=np.float64)
+        self.n_verts = int(self._X.shape[0])
+        self.n_tets = int(self._tets.shape[0])
+        mesh = pd_mesh_desc(self.n_verts, self.n_tets, self._X.ctypes.data, self._tets.ctypes.data,
+                            self._pinned.ctypes.data)
+        mat = pd_material_desc(self._logE.ctypes.data, nu, rho, alpha, beta0)
+        opts = pd_solver_opts(h, (ctypes.c_double * 3)(*gravity), aa_window, eps_rel, eps_abs, kmax_fwd, kmax_bwd,
+                              eps_adj, eps_tr, adj_method, max_sub, iters_per_check)
+        self.h = float(h)
+        ptr = ctypes.c_void_p()
+        check(L.pd_scene_create(ctypes.byref(mesh), ctypes.byref(mat), ctypes.byref(opts), ctypes.byref(ptr)),
+              "pd_scene_create")
+        self.ptr = ptr
+
+    @classmethod
+    def from_scene(cls, sc, **kw):
+        args = dict(aa_window=sc.aa_window, eps_rel=sc.eps_rel, eps_abs=sc.eps_abs)
+        args.update(kw)
+        return cls(sc.X, sc.tets, sc.pinned, sc.log_E, sc.nu, sc.rho, sc.alpha, sc.beta0, sc.h,
+                   tuple(np.asarray(sc.gravity, float)), **args)
+
+    def close(self):
+        if getattr(self, "ptr", None) is not None and self.ptr.value:
+            lib().pd_scene_destroy(self.ptr)
+        self.ptr = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def info(self):
+        info = (ctypes.c_double * 7)()
+        means = (ctypes.c_double * 4)()
+        check(lib().pd_scene_info(self.ptr, info, means), "pd_scene_info")
+        keys = ["n_verts", "n_tets", "n_free", "n_subdomains", "n_interface", "aa_window", "factor_bytes"]
+        d = {k: info[i] for i, k in enumerate(keys)}
+        d.update(mu_bar=means[0], lam_bar=means[1], k_bar=means[2], mu_ref=means[3])
+        return d
+
+    def set_material(self, log_E):
+        self._logE = np.ascontiguousarray(log_E, dtype=np.float64)
+        check(lib().pd_scene_set_material(self.ptr, self._logE.ctypes.data), "pd_scene_set_material")
+
+    def factorize(self):
+        check(lib().pd_scene_factorize(self.ptr, _stream()), "pd_scene_factorize")
+
+    def ckpt_bytes(self) -> int:
+        return int(lib().pd_ckpt_bytes(self.ptr))
+
+    def new_ckpt(self):
+        import torch
+        return torch.empty(self.ckpt_bytes() // 8, dtype=torch.float64, device="cuda")
+
+    def step_forward(self, q_t, v_t, f_ext=None, q0=None, q_next=None, v_next=None, ckpt=None):
+        import torch
+        q_next = torch.empty_like(q_t) if q_next is None else q_next
+        v_next = torch.empty_like(q_t) if v_next is None else v_next
+        st = pd_fwd_stats()
+        rc = check(lib().pd_step_forward(self.ptr, _ptr(q_t), _ptr(v_t), _ptr(f_ext), _ptr(q0), _ptr(q_next),
+                                         _ptr(v_next), _ptr(ckpt), ctypes.byref(st), _stream()), "pd_step_forward")
+        return q_next, v_next, dict(iters=st.iters, aa_resets=st.aa_resets, status=st.status, rc=rc,
+                                    newton_max=st.newton_max_iters, gate=list(st.gate))
+
+    def step_backward(self, ckpt, gq_next, gv_next, g_logE=None, gq_t=None, gv_t=None, gf_ext=None):
+        import torch
+        gq_t = torch.empty_like(gq_next) if gq_t is None else gq_t
+        gv_t = torch.empty_like(gq_next) if gv_t is None else gv_t
+        gf_ext = torch.empty_like(gq_next) if gf_ext is None else gf_ext
+        if g_logE is None:
+            g_logE = torch.zeros(self.n_tets, dtype=torch.float64, device=gq_next.device)
+        st = pd_bwd_stats()
+        rc = check(lib().pd_step_backward(self.ptr, _ptr(ckpt), _ptr(gq_next), _ptr(gv_next), _ptr(gq_t),
+                                          _ptr(gv_t), _ptr(gf_ext), _ptr(g_logE), ctypes.byref(st), _stream()),
+                   "pd_step_backward")
+        return gq_t, gv_t, gf_ext, g_logE, dict(adj_iters=st.adj_iters, status=st.status, rho=st.rho, tau=st.tau,
+                                                  dphi_act=st.dphi_act, dphi_mod=st.dphi_mod,
+                                                  residual=st.residual, rc=rc)
+
+    def debug_local_rhs(self, q):
+        import torch
+        b = torch.empty_like(q)
+        check(lib().pd_debug_local_rhs(self.ptr, _ptr(q), _ptr(b), _stream()), "pd_debug_local_rhs")
+        return b
+
+    def debug_apply_Ainv(self, r):
+        import torch
+        x = torch.empty_like(r)
+        check(lib().pd_debug_apply_Ainv(self.ptr, _ptr(r), _ptr(x), _stream()), "pd_debug_apply_Ainv")
+        return x
+
+    def debug_apply_K(self, q, tau, x):
+        import torch
+        y = torch.empty_like(x)
+        check(lib().pd_debug_apply_K(self.ptr, _ptr(q), float(tau), _ptr(x), _ptr(y), _stream()),
+              "pd_debug_apply_K")
+        return y

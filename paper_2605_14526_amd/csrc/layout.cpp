@@ -1,0 +1,155 @@
+// Host-side vertex ordering for the partitioned inverse: nested dissection by
+// coordinate bisection with vertex separators.  The free vertices are split
+// recursively at the median coordinate of the longest bounding-box axis; the
+// vertices of the lower half that touch the upper half form the separator.
+// Recursion stops at subdomains of at most max_sub vertices.  No subdomain
+// vertex is adjacent to another subdomain, so A~ restricted to the subdomains
+// is block diagonal and its Schur complement lives on the separators only.
+#include <algorithm>
+#include <cmath>
+#include <numeric>
+#include <stdexcept>
+
+#include "pd_internal.h"
+
+namespace pdhot {
+
+namespace {
+
+struct Graph {
+  std::vector<int> ptr, adj;  // over all vertices, free-free edges only
+};
+
+Graph free_graph(int nv, int ne, const int32_t* tets, const uint8_t* pinned) {
+  std::vector<std::vector<int>> nb(nv);
+  for (int e = 0; e < ne; ++e)
+    for (int a = 0; a < 4; ++a)
+      for (int b = 0; b < 4; ++b) {
+        int u = tets[4 * e + a], v = tets[4 * e + b];
+        if (u != v && !pinned[u] && !pinned[v]) nb[u].push_back(v);
+      }
+  Graph g;
+  g.ptr.assign(nv + 1, 0);
+  for (int v = 0; v < nv; ++v) {
+    auto& l = nb[v];
+    std::sort(l.begin(), l.end());
+    l.erase(std::unique(l.begin(), l.end()), l.end());
+    g.ptr[v + 1] = g.ptr[v] + (int)l.size();
+  }
+  g.adj.reserve(g.ptr[nv]);
+  for (int v = 0; v < nv; ++v) g.adj.insert(g.adj.end(), nb[v].begin(), nb[v].end());
+  return g;
+}
+
+struct ND {
+  const double* X;
+  const Graph* g;
+  int max_sub;
+  std::vector<int> side;  // scratch membership marks
+  std::vector<std::vector<int>> subs;
+  std::vector<int> interface;
+
+  void run(std::vector<int> set) {
+    if ((int)set.size() <= max_sub) {
+      if (!set.empty()) subs.push_back(std::move(set));
+      return;
+    }
+    double lo[3] = {1e300, 1e300, 1e300}, hi[3] = {-1e300, -1e300, -1e300};
+    for (int v : set)
+      for (int a = 0; a < 3; ++a) {
+        lo[a] = std::min(lo[a], X[3 * v + a]);
+        hi[a] = std::max(hi[a], X[3 * v + a]);
+      }
+    int ax = 0;
+    for (int a = 1; a < 3; ++a)
+      if (hi[a] - lo[a] > hi[ax] - lo[ax]) ax = a;
+    std::vector<int> sorted = set;
+    std::stable_sort(sorted.begin(), sorted.end(), [&](int a, int b) { return X[3 * a + ax] < X[3 * b + ax]; });
+    double cval = X[3 * sorted[sorted.size() / 2] + ax];
+    std::vector<int> Lw, Rw;
+    for (int v : set) (X[3 * v + ax] <= cval ? Lw : Rw).push_back(v);
+    if (Rw.empty()) {  // all on one side of the median plane: split by position
+      Lw.assign(sorted.begin(), sorted.begin() + sorted.size() / 2);
+      Rw.assign(sorted.begin() + sorted.size() / 2, sorted.end());
+    }
+    for (int v : Rw) side[v] = 2;
+    std::vector<int> Ls, S;
+    for (int v : Lw) {
+      bool touches = false;
+      for (int k = g->ptr[v]; k < g->ptr[v + 1] && !touches; ++k) touches = side[g->adj[k]] == 2;
+      (touches ? S : Ls).push_back(v);
+    }
+    for (int v : Rw) side[v] = 0;
+    if (Ls.empty() && Rw.size() == set.size() - S.size() && S.size() == set.size()) {
+      throw std::runtime_error("nested dissection made no progress");
+    }
+    run(std::move(Ls));
+    run(std::move(Rw));
+    interface.insert(interface.end(), S.begin(), S.end());
+  }
+};
+
+}  // namespace
+
+void build_layout(int nv, int ne, const double* X, const int32_t* tets, const uint8_t* pinned, int max_sub,
+                  Layout& L) {
+  L.nv = nv;
+  L.ne = ne;
+  Graph g = free_graph(nv, ne, tets, pinned);
+  std::vector<int> free_set;
+  for (int v = 0; v < nv; ++v)
+    if (!pinned[v]) free_set.push_back(v);
+  ND nd{X, &g, std::max(1, max_sub), std::vector<int>(nv, 0), {}, {}};
+  nd.run(free_set);
+
+  L.lib2orig.clear();
+  L.sub_begin.clear();
+  for (auto& s : nd.subs) {
+    L.sub_begin.push_back((int)L.lib2orig.size());
+    L.lib2orig.insert(L.lib2orig.end(), s.begin(), s.end());
+  }
+  L.nsub = (int)nd.subs.size();
+  L.nB = (int)L.lib2orig.size();
+  L.sub_begin.push_back(L.nB);
+  L.lib2orig.insert(L.lib2orig.end(), nd.interface.begin(), nd.interface.end());
+  L.nf = (int)L.lib2orig.size();
+  L.nT = L.nf - L.nB;
+  for (int v = 0; v < nv; ++v)
+    if (pinned[v]) L.lib2orig.push_back(v);
+  L.orig2lib.assign(nv, -1);
+  for (int i = 0; i < nv; ++i) L.orig2lib[L.lib2orig[i]] = i;
+
+  // interface rows coupled to each subdomain; check the block structure
+  std::vector<int> sub_of(nv, -1);
+  for (int s = 0; s < L.nsub; ++s)
+    for (int i = L.sub_begin[s]; i < L.sub_begin[s + 1]; ++i) sub_of[L.lib2orig[i]] = s;
+  L.Irows.assign(L.nsub, {});
+  for (int s = 0; s < L.nsub; ++s) {
+    std::vector<int>& I = L.Irows[s];
+    for (int i = L.sub_begin[s]; i < L.sub_begin[s + 1]; ++i) {
+      int v = L.lib2orig[i];
+      for (int k = g.ptr[v]; k < g.ptr[v + 1]; ++k) {
+        int u = g.adj[k];
+        int lu = L.orig2lib[u];
+        if (sub_of[u] == s) continue;
+        if (sub_of[u] >= 0 || lu < L.nB) throw std::runtime_error("subdomains are not separated");
+        I.push_back(lu - L.nB);
+      }
+    }
+    std::sort(I.begin(), I.end());
+    I.erase(std::unique(I.begin(), I.end()), I.end());
+  }
+
+  // tets sorted by their smallest library vertex (locality of the gathers)
+  std::vector<int> key(ne);
+  for (int e = 0; e < ne; ++e) {
+    int k = nv;
+    for (int a = 0; a < 4; ++a) k = std::min(k, L.orig2lib[tets[4 * e + a]]);
+    key[e] = k;
+  }
+  L.tet_lib2orig.resize(ne);
+  std::iota(L.tet_lib2orig.begin(), L.tet_lib2orig.end(), 0);
+  std::stable_sort(L.tet_lib2orig.begin(), L.tet_lib2orig.end(), [&](int a, int b) { return key[a] < key[b]; });
+}
+
+}  // namespace pdhot

@@ -1,0 +1,837 @@
+// Host runtime of the pdhot library: scene setup, the factorization into the
+// two-level partitioned inverse, and the forward / backward step drivers that
+// issue the HIP kernels.  Implements the C ABI declared in include/pdhot.h.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <new>
+#include <stdexcept>
+#include <string>
+#include <vector>
+
+#include "../../include/pdhot.h"
+#include "kernels.h"
+#include "pd_internal.h"
+
+using namespace pdhot;
+
+struct pd_scene {
+  Scene S;
+};
+
+namespace {
+
+thread_local std::string g_err;
+
+struct PdError {
+  int code;
+  std::string msg;
+};
+
+#define PD_HIP(x)                                                                                   \
+  do {                                                                                              \
+    hipError_t e_ = (x);                                                                            \
+    if (e_ != hipSuccess) throw PdError{PD_ERR_HIP, std::string(#x) + ": " + hipGetErrorString(e_)}; \
+  } while (0)
+
+template <class T>
+T* dalloc(size_t n) {
+  if (n == 0) n = 1;
+  void* p = nullptr;
+  PD_HIP(hipMalloc(&p, n * sizeof(T)));
+  return static_cast<T*>(p);
+}
+
+template <class T>
+void upload(T* d, const std::vector<T>& h) {
+  if (!h.empty()) PD_HIP(hipMemcpy(d, h.data(), h.size() * sizeof(T), hipMemcpyHostToDevice));
+}
+
+template <class T>
+void dfree(T*& p) {
+  if (p) (void)hipFree(p);
+  p = nullptr;
+}
+
+// ---------------------------------------------------------------- dense SPD
+// In-place inverse of a symmetric positive definite matrix (row-major, full):
+// A = L L^T, W = L^{-1}, A^{-1} = W^T W.  Returns false if A is not SPD.
+bool spd_inverse(std::vector<double>& A, int n) {
+  std::vector<double> L(A);
+  for (int j = 0; j < n; ++j) {
+    double* Lj = &L[(size_t)j * n];
+    double d = Lj[j];
+    for (int k = 0; k < j; ++k) d -= Lj[k] * Lj[k];
+    if (!(d > 0.0) || !std::isfinite(d)) return false;
+    d = std::sqrt(d);
+    Lj[j] = d;
+    const double inv = 1.0 / d;
+    for (int i = j + 1; i < n; ++i) {
+      double* Li = &L[(size_t)i * n];
+      double s = Li[j];
+      for (int k = 0; k < j; ++k) s -= Li[k] * Lj[k];
+      Li[j] = s * inv;
+    }
+  }
+  std::vector<double> W((size_t)n * n, 0.0), acc(n);
+  for (int i = 0; i < n; ++i) {
+    const double* Li = &L[(size_t)i * n];
+    std::fill(acc.begin(), acc.begin() + i, 0.0);
+    for (int k = 0; k < i; ++k) {
+      const double c = Li[k];
+      const double* Wk = &W[(size_t)k * n];
+      for (int j = 0; j <= k; ++j) acc[j] += c * Wk[j];
+    }
+    const double inv = 1.0 / Li[i];
+    double* Wi = &W[(size_t)i * n];
+    for (int j = 0; j < i; ++j) Wi[j] = -acc[j] * inv;
+    Wi[i] = inv;
+  }
+  std::fill(A.begin(), A.end(), 0.0);
+  for (int k = 0; k < n; ++k) {
+    const double* Wk = &W[(size_t)k * n];
+    for (int i = 0; i <= k; ++i) {
+      const double c = Wk[i];
+      if (c == 0.0) continue;
+      double* Ai = &A[(size_t)i * n];
+      for (int j = 0; j <= i; ++j) Ai[j] += c * Wk[j];
+    }
+  }
+  for (int i = 0; i < n; ++i)
+    for (int j = i + 1; j < n; ++j) A[(size_t)i * n + j] = A[(size_t)j * n + i];
+  return true;
+}
+
+double det3(const double* A) {
+  return A[0] * (A[4] * A[8] - A[5] * A[7]) - A[1] * (A[3] * A[8] - A[5] * A[6]) + A[2] * (A[3] * A[7] - A[4] * A[6]);
+}
+
+void free_device(Scene& S) {
+  dfree(S.tv); dfree(S.Bm); dfree(S.wV); dfree(S.bV); dfree(S.muV); dfree(S.lamV); dfree(S.tet_orig);
+  dfree(S.v_orig); dfree(S.mass); dfree(S.rest); dfree(S.cpin); dfree(S.inc_ptr); dfree(S.inc_idx);
+  dfree(S.S.Zs); dfree(S.S.Et); dfree(S.S.Z); dfree(S.S.zs_off64); dfree(S.S.et_off64); dfree(S.S.sub_begin);
+  dfree(S.S.ir_off); dfree(S.S.irows); dfree(S.S.slot_of); dfree(S.S.row_slot_ptr); dfree(S.S.t_slots);
+  dfree(S.S.bottom_items);
+  dfree(S.contrib); dfree(S.qt); dfree(S.vt); dfree(S.qtil); dfree(S.c); dfree(S.q_cur); dfree(S.q_prev);
+  dfree(S.b_cur); dfree(S.b_prev); dfree(S.qhat); dfree(S.q_last); dfree(S.g_last); dfree(S.dQ); dfree(S.dG);
+  dfree(S.gate_part); dfree(S.aa_part); dfree(S.ctl); dfree(S.dstat); dfree(S.jac); dfree(S.mu); dfree(S.r);
+  dfree(S.z); dfree(S.p); dfree(S.Ap); dfree(S.wv); dfree(S.qbar); dfree(S.red_part);
+  if (S.hctl) (void)hipHostFree(S.hctl);
+  if (S.hdstat) (void)hipHostFree(S.hdstat);
+  S.hctl = nullptr;
+  S.hdstat = nullptr;
+}
+
+// ---------------------------------------------------------------- argument blocks
+ElemArgs elem_args(const Scene& S) {
+  ElemArgs E;
+  E.ne = S.ne;
+  E.tv = S.tv; E.Bm = S.Bm; E.wV = S.wV; E.bV = S.bV; E.muV = S.muV; E.lamV = S.lamV; E.tet_orig = S.tet_orig;
+  E.mu_bar = S.mu_bar; E.lam_bar = S.lam_bar; E.k_bar = S.k_bar;
+  return E;
+}
+
+VertArgs vert_args(const Scene& S) {
+  VertArgs V;
+  V.nv = S.nv; V.nf = S.L.nf; V.ne = S.ne; V.max_sub = 0;
+  for (int s = 0; s < S.L.nsub; ++s) V.max_sub = std::max(V.max_sub, S.L.sub_begin[s + 1] - S.L.sub_begin[s]);
+  V.v_orig = S.v_orig; V.mass = S.mass; V.rest = S.rest; V.cpin = S.cpin; V.inc_ptr = S.inc_ptr; V.inc_idx = S.inc_idx;
+  V.h = S.h; V.alpha = S.alpha;
+  for (int a = 0; a < 3; ++a) V.grav[a] = S.grav[a];
+  return V;
+}
+
+SolveArgs solve_args(const Scene& S) {
+  SolveArgs A;
+  const Layout& L = S.L;
+  A.nsub = L.nsub; A.nB = L.nB; A.nT = L.nT;
+  A.n_bottom_items = S.S.n_bottom_items; A.n_top_blocks = S.S.n_top_blocks; A.top_rows = S.S.top_rows;
+  A.max_ns = 0; A.max_nI = 0;
+  for (int s = 0; s < L.nsub; ++s) {
+    A.max_ns = std::max(A.max_ns, L.sub_begin[s + 1] - L.sub_begin[s]);
+    A.max_nI = std::max(A.max_nI, (int)L.Irows[s].size());
+  }
+  A.Zs = S.S.Zs; A.Et = S.S.Et; A.Z = S.S.Z; A.zs_off = S.S.zs_off64; A.et_off = S.S.et_off64;
+  A.sub_begin = S.S.sub_begin; A.ir_off = S.S.ir_off; A.irows = S.S.irows; A.slot_of = S.S.slot_of;
+  A.row_slot_ptr = S.S.row_slot_ptr; A.t_slots = S.S.t_slots; A.bottom_items = S.S.bottom_items;
+  return A;
+}
+
+StepState step_state(Scene& S) {
+  StepState T;
+  T.m = S.m; T.kmax = S.kmax_fwd; T.eps_rel = S.eps_rel; T.eps_abs = S.eps_abs;
+  T.n_gate_blocks = S.n_gather_blocks; T.n_aa_blocks = S.n_bottom_blocks;
+  T.contrib = S.contrib; T.qt = S.qt; T.vt = S.vt; T.qtil = S.qtil; T.c = S.c;
+  T.q_cur = S.q_cur; T.q_prev = S.q_prev; T.b_cur = S.b_cur; T.b_prev = S.b_prev; T.qhat = S.qhat;
+  T.q_last = S.q_last; T.g_last = S.g_last; T.dQ = S.dQ; T.dG = S.dG;
+  T.gate_part = S.gate_part; T.aa_part = S.aa_part; T.ctl = S.ctl; T.done = S.ctl + kCtlDone; T.dstat = S.dstat;
+  return T;
+}
+
+// ---------------------------------------------------------------- setup
+void setup_scene(Scene& S, const pd_mesh_desc* mesh, const pd_material_desc* mat, const pd_solver_opts* o) {
+  if (!mesh || !mat || !o) throw PdError{PD_ERR_INVALID_ARG, "null descriptor"};
+  const int nv = mesh->n_verts, ne = mesh->n_tets;
+  if (nv <= 0 || ne <= 0 || !mesh->rest_xyz || !mesh->tets || !mesh->pinned || !mat->log_E)
+    throw PdError{PD_ERR_INVALID_ARG, "empty mesh or null array"};
+  if (!(o->h > 0.0) || o->aa_window < 0 || o->aa_window > kMaxWindow || !(o->eps_rel >= 0.0) || o->kmax_fwd < 3 ||
+      o->kmax_bwd < 1 || !(o->eps_adj > 0.0))
+    throw PdError{PD_ERR_INVALID_ARG, "invalid solver options (h > 0, 0 <= aa_window <= 5, kmax_fwd >= 3)"};
+  if (!(mat->nu > -1.0 && mat->nu < 0.5) || !(mat->rho > 0.0) || !(mat->alpha >= 0.0) || !(mat->beta0 >= 0.0))
+    throw PdError{PD_ERR_INVALID_ARG, "invalid material constants"};
+  S.nv = nv;
+  S.ne = ne;
+  S.X.assign(mesh->rest_xyz, mesh->rest_xyz + 3 * (size_t)nv);
+  S.tets.assign(mesh->tets, mesh->tets + 4 * (size_t)ne);
+  S.pinned.assign(mesh->pinned, mesh->pinned + nv);
+  S.logE.assign(mat->log_E, mat->log_E + ne);
+  for (double x : S.X)
+    if (!std::isfinite(x)) throw PdError{PD_ERR_NONFINITE, "non-finite rest position"};
+  for (double x : S.logE)
+    if (!std::isfinite(x)) throw PdError{PD_ERR_NONFINITE, "non-finite log E"};
+  for (int v : S.tets)
+    if (v < 0 || v >= nv) throw PdError{PD_ERR_INVALID_ARG, "tet vertex index out of range"};
+  S.nu = mat->nu; S.rho = mat->rho; S.alpha = mat->alpha; S.beta0 = mat->beta0;
+  S.h = o->h;
+  for (int a = 0; a < 3; ++a) S.grav[a] = o->gravity[a];
+  S.m = o->aa_window; S.eps_rel = o->eps_rel; S.eps_abs = o->eps_abs; S.kmax_fwd = o->kmax_fwd;
+  S.kmax_bwd = o->kmax_bwd; S.eps_adj = o->eps_adj; S.eps_tr = o->eps_tr; S.adj_method = o->adj_method;
+  S.max_sub = o->max_sub > 0 ? o->max_sub : 256;
+  S.iters_per_check = o->iters_per_check;
+  // orientation (reorient negative tets), degenerate check
+  for (int e = 0; e < ne; ++e) {
+    int* t = &S.tets[4 * (size_t)e];
+    double Dm[9];
+    for (int a = 1; a < 4; ++a)
+      for (int i = 0; i < 3; ++i) Dm[3 * i + a - 1] = S.X[3 * t[a] + i] - S.X[3 * t[0] + i];
+    double d = det3(Dm);
+    if (d < 0.0) std::swap(t[1], t[2]), d = -d;
+    double scale = 0.0;
+    for (int i = 0; i < 9; ++i) scale = std::max(scale, std::fabs(Dm[i]));
+    if (!(d > 1e-14 * scale * scale * scale)) throw PdError{PD_ERR_DEGENERATE_TET, "zero-volume tet " + std::to_string(e)};
+    if (t[0] == t[1] || t[0] == t[2] || t[0] == t[3] || t[1] == t[2] || t[1] == t[3] || t[2] == t[3])
+      throw PdError{PD_ERR_DEGENERATE_TET, "repeated vertex in tet " + std::to_string(e)};
+  }
+  build_layout(nv, ne, S.X.data(), S.tets.data(), S.pinned.data(), S.max_sub, S.L);
+  if (S.L.nf == 0) throw PdError{PD_ERR_INVALID_ARG, "no free vertex"};
+  const Layout& L = S.L;
+  // element geometry in library order
+  std::vector<int> tv(4 * (size_t)ne);
+  std::vector<double> Bm(9 * (size_t)ne), vol(ne);
+  std::vector<int> tet_orig(ne);
+  for (int t = 0; t < ne; ++t) {
+    const int e = L.tet_lib2orig[t];
+    tet_orig[t] = e;
+    const int* tt = &S.tets[4 * (size_t)e];
+    double Dm[9];
+    for (int a = 1; a < 4; ++a)
+      for (int i = 0; i < 3; ++i) Dm[3 * i + a - 1] = S.X[3 * tt[a] + i] - S.X[3 * tt[0] + i];
+    const double d = det3(Dm);
+    vol[t] = d / 6.0;
+    double Bi[9];
+    Bi[0] = (Dm[4] * Dm[8] - Dm[5] * Dm[7]) / d;
+    Bi[1] = (Dm[2] * Dm[7] - Dm[1] * Dm[8]) / d;
+    Bi[2] = (Dm[1] * Dm[5] - Dm[2] * Dm[4]) / d;
+    Bi[3] = (Dm[5] * Dm[6] - Dm[3] * Dm[8]) / d;
+    Bi[4] = (Dm[0] * Dm[8] - Dm[2] * Dm[6]) / d;
+    Bi[5] = (Dm[2] * Dm[3] - Dm[0] * Dm[5]) / d;
+    Bi[6] = (Dm[3] * Dm[7] - Dm[4] * Dm[6]) / d;
+    Bi[7] = (Dm[1] * Dm[6] - Dm[0] * Dm[7]) / d;
+    Bi[8] = (Dm[0] * Dm[4] - Dm[1] * Dm[3]) / d;
+    for (int i = 0; i < 9; ++i) Bm[(size_t)i * ne + t] = Bi[i];
+    for (int a = 0; a < 4; ++a) tv[(size_t)a * ne + t] = L.orig2lib[tt[a]];
+  }
+  S.tv = dalloc<int>(4 * (size_t)ne);
+  upload(S.tv, tv);
+  S.Bm = dalloc<double>(9 * (size_t)ne);
+  upload(S.Bm, Bm);
+  S.tet_orig = dalloc<int>(ne);
+  upload(S.tet_orig, tet_orig);
+  // vertex arrays
+  std::vector<int> v_orig(L.lib2orig.begin(), L.lib2orig.end());
+  S.v_orig = dalloc<int>(nv);
+  upload(S.v_orig, v_orig);
+  std::vector<double> rest(3 * (size_t)nv);
+  for (int i = 0; i < nv; ++i)
+    for (int a = 0; a < 3; ++a) rest[(size_t)a * nv + i] = S.X[3 * (size_t)L.lib2orig[i] + a];
+  S.rest = dalloc<double>(3 * (size_t)nv);
+  upload(S.rest, rest);
+  // incidence of free vertices: (tet, slot) in tet order
+  const int nf = L.nf;
+  std::vector<int> cnt(nf + 1, 0);
+  for (int t = 0; t < ne; ++t)
+    for (int a = 0; a < 4; ++a) {
+      const int i = tv[(size_t)a * ne + t];
+      if (i < nf) cnt[i + 1]++;
+    }
+  for (int i = 0; i < nf; ++i) cnt[i + 1] += cnt[i];
+  std::vector<int> inc(cnt[nf]), fill(cnt.begin(), cnt.end() - 1);
+  for (int t = 0; t < ne; ++t)
+    for (int a = 0; a < 4; ++a) {
+      const int i = tv[(size_t)a * ne + t];
+      if (i < nf) inc[fill[i]++] = 4 * t + a;
+    }
+  S.inc_ptr = dalloc<int>(nf + 1);
+  upload(S.inc_ptr, cnt);
+  S.inc_idx = dalloc<int>(inc.size());
+  upload(S.inc_idx, inc);
+  // element-material arrays and iteration buffers (sized once)
+  S.wV = dalloc<double>(ne); S.bV = dalloc<double>(ne); S.muV = dalloc<double>(ne); S.lamV = dalloc<double>(ne);
+  S.mass = dalloc<double>(nv);
+  S.cpin = dalloc<double>(3 * (size_t)nv);
+  const size_t V3 = 3 * (size_t)nv;
+  S.contrib = dalloc<double>(12 * (size_t)ne);
+  S.qt = dalloc<double>(V3); S.vt = dalloc<double>(V3); S.qtil = dalloc<double>(V3); S.c = dalloc<double>(V3);
+  S.q_cur = dalloc<double>(V3); S.q_prev = dalloc<double>(V3); S.b_cur = dalloc<double>(V3);
+  S.b_prev = dalloc<double>(V3); S.qhat = dalloc<double>(V3); S.q_last = dalloc<double>(V3);
+  S.g_last = dalloc<double>(V3);
+  const int mm = std::max(1, S.m);
+  S.dQ = dalloc<double>(mm * V3); S.dG = dalloc<double>(mm * V3);
+  PD_HIP(hipMemset(S.b_cur, 0, V3 * sizeof(double)));
+  S.ctl = dalloc<int>(kCtlTotal);
+  S.dstat = dalloc<double>(32);
+  PD_HIP(hipHostMalloc((void**)&S.hctl, kCtlTotal * sizeof(int)));
+  PD_HIP(hipHostMalloc((void**)&S.hdstat, 32 * sizeof(double)));
+  S.jac = dalloc<double>(33 * (size_t)ne);
+  S.mu = dalloc<double>(V3); S.r = dalloc<double>(V3); S.z = dalloc<double>(V3); S.p = dalloc<double>(V3);
+  S.Ap = dalloc<double>(V3); S.wv = dalloc<double>(V3); S.qbar = dalloc<double>(V3);
+  S.n_vert_blocks = (nf + kBlock - 1) / kBlock;
+  S.n_tet_blocks = (ne + kBlock - 1) / kBlock;
+  const int n_red = std::max(S.n_vert_blocks, S.n_tet_blocks + S.n_vert_blocks) + 4;
+  S.red_part = dalloc<double>(8 * (size_t)n_red);
+  S.stale = true;
+}
+
+void factorize(Scene& S) {
+  const Layout& L = S.L;
+  const int nv = S.nv, ne = S.ne, nf = L.nf, nB = L.nB, nT = L.nT;
+  const double h = S.h;
+  // materials (Sec. 3.1 Eq. lame; Sec. 4.1 Eq. pd_weight read as the rest
+  // tangent modulus w_e = 2 mu_e + lam_e; Sec. 4.2 mesh means; Sec. 4.5)
+  std::vector<double> mu(ne), lam(ne), w(ne), beta(ne), vol(ne);
+  double smu = 0.0, slam = 0.0, mref = 0.0;
+  for (int e = 0; e < ne; ++e) {
+    const double E = std::exp(S.logE[e]);
+    mu[e] = E / (2.0 * (1.0 + S.nu));
+    lam[e] = E * S.nu / ((1.0 + S.nu) * (1.0 - 2.0 * S.nu));
+    w[e] = 2.0 * mu[e] + lam[e];
+    smu += mu[e];
+    slam += lam[e];
+    mref = std::max(mref, mu[e]);
+  }
+  S.mu_bar = smu / ne;
+  S.lam_bar = slam / ne;
+  S.k_bar = 2.0 * S.mu_bar + S.lam_bar;
+  S.mu_ref = mref;
+  for (int e = 0; e < ne; ++e) beta[e] = S.beta0 * mu[e] / mref;
+  // per-tet data in library order
+  std::vector<double> Bm(9 * (size_t)ne), wV(ne), bV(ne), muV(ne), lamV(ne);
+  std::vector<int> tv(4 * (size_t)ne);
+  PD_HIP(hipMemcpy(Bm.data(), S.Bm, Bm.size() * sizeof(double), hipMemcpyDeviceToHost));
+  PD_HIP(hipMemcpy(tv.data(), S.tv, tv.size() * sizeof(int), hipMemcpyDeviceToHost));
+  std::vector<double> mass(nv, 0.0);
+  for (int t = 0; t < ne; ++t) {
+    const int e = L.tet_lib2orig[t];
+    const int* tt = &S.tets[4 * (size_t)e];
+    double Dm[9];
+    for (int a = 1; a < 4; ++a)
+      for (int i = 0; i < 3; ++i) Dm[3 * i + a - 1] = S.X[3 * tt[a] + i] - S.X[3 * tt[0] + i];
+    vol[t] = det3(Dm) / 6.0;
+    wV[t] = w[e] * vol[t];
+    bV[t] = beta[e] * vol[t] / h;
+    muV[t] = mu[e] * vol[t];
+    lamV[t] = lam[e] * vol[t];
+    for (int a = 0; a < 4; ++a) mass[tv[(size_t)a * ne + t]] += S.rho * vol[t] / 4.0;
+  }
+  upload(S.wV, wV); upload(S.bV, bV); upload(S.muV, muV); upload(S.lamV, lamV);
+  upload(S.mass, mass);
+  // assemble A~ (Sec. 4.5 Eq. A_damped) into the block structure
+  const int nsub = L.nsub;
+  std::vector<std::vector<double>> Ass(nsub), AIs(nsub);
+  std::vector<int> sub_of(nf, -1);
+  for (int s = 0; s < nsub; ++s) {
+    const int ns = L.sub_begin[s + 1] - L.sub_begin[s];
+    Ass[s].assign((size_t)ns * ns, 0.0);
+    AIs[s].assign(L.Irows[s].size() * (size_t)ns, 0.0);
+    for (int i = L.sub_begin[s]; i < L.sub_begin[s + 1]; ++i) sub_of[i] = s;
+  }
+  if ((size_t)nT * nT > (size_t)1 << 28) throw PdError{PD_ERR_ALLOC, "interface too large for the dense Schur block"};
+  std::vector<double> ATT((size_t)nT * nT, 0.0);
+  std::vector<double> cpin(3 * (size_t)nv, 0.0);
+  auto ipos = [&](int s, int iface) {
+    const auto& I = L.Irows[s];
+    return (int)(std::lower_bound(I.begin(), I.end(), iface) - I.begin());
+  };
+  for (int i = 0; i < nf; ++i) {
+    const double d = (1.0 + S.alpha * h) * mass[i] / (h * h);
+    if (i < nB) {
+      const int s = sub_of[i], b = L.sub_begin[s], ns = L.sub_begin[s + 1] - b;
+      Ass[s][(size_t)(i - b) * ns + (i - b)] += d;
+    } else {
+      ATT[(size_t)(i - nB) * nT + (i - nB)] += d;
+    }
+  }
+  for (int t = 0; t < ne; ++t) {
+    const double cst = (wV[t] + bV[t]);
+    double Bh[4][3];
+    for (int j = 0; j < 3; ++j) {
+      Bh[1][j] = Bm[(size_t)(0 + j) * ne + t];
+      Bh[2][j] = Bm[(size_t)(3 + j) * ne + t];
+      Bh[3][j] = Bm[(size_t)(6 + j) * ne + t];
+      Bh[0][j] = -(Bh[1][j] + Bh[2][j] + Bh[3][j]);
+    }
+    for (int a = 0; a < 4; ++a) {
+      const int i = tv[(size_t)a * ne + t];
+      if (i >= nf) continue;
+      for (int b = 0; b < 4; ++b) {
+        const int j = tv[(size_t)b * ne + t];
+        const double val = cst * (Bh[a][0] * Bh[b][0] + Bh[a][1] * Bh[b][1] + Bh[a][2] * Bh[b][2]);
+        if (j >= nf) {  // coupling to a pinned vertex (held at rest)
+          for (int ax = 0; ax < 3; ++ax) {
+            const double xr = S.X[3 * (size_t)L.lib2orig[j] + ax];
+            cpin[(size_t)ax * nv + i] -= val * xr;
+          }
+          continue;
+        }
+        if (i < nB && j < nB) {
+          const int s = sub_of[i];
+          if (sub_of[j] != s) throw PdError{PD_ERR_INVALID_ARG, "layout: coupled subdomains"};
+          const int b0 = L.sub_begin[s], ns = L.sub_begin[s + 1] - b0;
+          Ass[s][(size_t)(i - b0) * ns + (j - b0)] += val;
+        } else if (i >= nB && j < nB) {
+          const int s = sub_of[j], b0 = L.sub_begin[s], ns = L.sub_begin[s + 1] - b0;
+          AIs[s][(size_t)ipos(s, i - nB) * ns + (j - b0)] += val;
+        } else if (i >= nB && j >= nB) {
+          ATT[(size_t)(i - nB) * nT + (j - nB)] += val;
+        }
+      }
+    }
+  }
+  upload(S.cpin, cpin);
+  // partitioned inverse: Zs = A_ss^{-1}, E_s = A_{I s} Zs, S = A_TT - sum E_s A_{s I}, Z = S^{-1}
+  std::vector<long long> zs_off(nsub + 1, 0), et_off(nsub + 1, 0);
+  for (int s = 0; s < nsub; ++s) {
+    const long long ns = L.sub_begin[s + 1] - L.sub_begin[s];
+    zs_off[s + 1] = zs_off[s] + ns * ns;
+    et_off[s + 1] = et_off[s] + ns * (long long)L.Irows[s].size();
+  }
+  std::vector<double> Zs_all(zs_off[nsub]), Et_all(et_off[nsub]);
+  for (int s = 0; s < nsub; ++s) {
+    const int ns = L.sub_begin[s + 1] - L.sub_begin[s];
+    const int nI = (int)L.Irows[s].size();
+    std::vector<double> Z = Ass[s];
+    if (!spd_inverse(Z, ns)) throw PdError{PD_ERR_FACTOR_NOT_SPD, "subdomain block not SPD"};
+    std::copy(Z.begin(), Z.end(), Zs_all.begin() + zs_off[s]);
+    // E_s (nI x ns) = A_Is (nI x ns) Z (ns x ns)
+    std::vector<double> Es((size_t)nI * ns, 0.0);
+    for (int p = 0; p < nI; ++p) {
+      const double* a = &AIs[s][(size_t)p * ns];
+      double* e = &Es[(size_t)p * ns];
+      for (int u = 0; u < ns; ++u) {
+        if (a[u] == 0.0) continue;
+        const double* zr = &Z[(size_t)u * ns];
+        for (int v = 0; v < ns; ++v) e[v] += a[u] * zr[v];
+      }
+    }
+    for (int v = 0; v < ns; ++v)
+      for (int p = 0; p < nI; ++p) Et_all[et_off[s] + (size_t)v * nI + p] = Es[(size_t)p * ns + v];
+    // Schur update on the interface rows of s
+    for (int p = 0; p < nI; ++p) {
+      const double* e = &Es[(size_t)p * ns];
+      const int ip = L.Irows[s][p];
+      for (int q = 0; q < nI; ++q) {
+        const double* a = &AIs[s][(size_t)q * ns];
+        double d = 0.0;
+        for (int v = 0; v < ns; ++v) d += e[v] * a[v];
+        ATT[(size_t)ip * nT + L.Irows[s][q]] -= d;
+      }
+    }
+  }
+  if (nT > 0 && !spd_inverse(ATT, nT)) throw PdError{PD_ERR_FACTOR_NOT_SPD, "interface Schur complement not SPD"};
+  // upload the solve structure
+  DeviceSolve& D = S.S;
+  dfree(D.Zs); dfree(D.Et); dfree(D.Z); dfree(D.zs_off64); dfree(D.et_off64); dfree(D.sub_begin); dfree(D.ir_off);
+  dfree(D.irows); dfree(D.slot_of); dfree(D.row_slot_ptr); dfree(D.t_slots); dfree(D.bottom_items);
+  D.Zs = dalloc<double>(Zs_all.size()); upload(D.Zs, Zs_all);
+  D.Et = dalloc<double>(Et_all.size()); upload(D.Et, Et_all);
+  D.Z = dalloc<double>(ATT.size()); upload(D.Z, ATT);
+  D.zs_off64 = dalloc<long long>(nsub + 1); upload(D.zs_off64, zs_off);
+  D.et_off64 = dalloc<long long>(nsub + 1); upload(D.et_off64, et_off);
+  D.sub_begin = dalloc<int>(nsub + 1); upload(D.sub_begin, L.sub_begin);
+  std::vector<int> ir_off(nsub + 1, 0), irows;
+  for (int s = 0; s < nsub; ++s) {
+    ir_off[s + 1] = ir_off[s] + (int)L.Irows[s].size();
+    irows.insert(irows.end(), L.Irows[s].begin(), L.Irows[s].end());
+  }
+  std::vector<int> rcount(nT + 1, 0);
+  for (int v : irows) rcount[v + 1]++;
+  for (int i = 0; i < nT; ++i) rcount[i + 1] += rcount[i];
+  std::vector<int> rfill(rcount.begin(), rcount.end() - 1), slot_of(irows.size());
+  for (size_t k = 0; k < irows.size(); ++k) slot_of[k] = rfill[irows[k]]++;
+  D.nslots = (int)irows.size();
+  D.ir_off = dalloc<int>(nsub + 1); upload(D.ir_off, ir_off);
+  D.irows = dalloc<int>(irows.size()); upload(D.irows, irows);
+  D.slot_of = dalloc<int>(slot_of.size()); upload(D.slot_of, slot_of);
+  D.row_slot_ptr = dalloc<int>(nT + 1); upload(D.row_slot_ptr, rcount);
+  D.t_slots = dalloc<double>(3 * (size_t)std::max(1, D.nslots));
+  // work lists: subdomain row chunks of 16 rows; interface rows spread over blocks
+  std::vector<int> items;
+  const int rows_per_item = 16;
+  for (int s = 0; s < nsub; ++s) {
+    const int ns = L.sub_begin[s + 1] - L.sub_begin[s];
+    for (int r = 0; r < ns; r += rows_per_item) {
+      items.push_back(s);
+      items.push_back(r);
+      items.push_back(std::min(ns, r + rows_per_item));
+    }
+  }
+  D.n_bottom_items = (int)items.size() / 3;
+  D.bottom_items = dalloc<int>(items.size()); upload(D.bottom_items, items);
+  D.top_rows = std::max(4, (nT + 255) / 256);
+  D.n_top_blocks = nT > 0 ? (nT + D.top_rows - 1) / D.top_rows : 0;
+  D.bytes = (Zs_all.size() + Et_all.size() + ATT.size()) * sizeof(double);
+  if (3 * (size_t)nT * sizeof(double) > 150 * 1024) throw PdError{PD_ERR_ALLOC, "interface exceeds the LDS budget"};
+  // per-block partial buffers
+  S.n_gather_blocks = nsub + (nT + kBlock - 1) / kBlock;
+  S.n_bottom_blocks = D.n_bottom_items + (nT + kBlock - 1) / kBlock;
+  dfree(S.gate_part); dfree(S.aa_part);
+  S.gate_part = dalloc<double>(4 * (size_t)std::max(1, S.n_gather_blocks));
+  S.aa_part = dalloc<double>(kAAPart * (size_t)std::max(1, S.n_bottom_blocks));
+  PD_HIP(hipDeviceSynchronize());
+  S.stale = false;
+}
+
+AdjState adj_state(Scene& S) {
+  AdjState A;
+  A.n_vert_blocks = S.n_vert_blocks; A.kmax = S.kmax_bwd; A.eps = S.eps_adj;
+  A.contrib = S.contrib; A.qbar = S.qbar; A.mu = S.mu; A.r = S.r; A.z = S.z; A.p = S.p; A.Ap = S.Ap; A.w = S.wv;
+  A.part = S.red_part; A.scal = S.dstat + 8; A.ctl = S.ctl + kCtlAdj; A.done = S.ctl + kCtlAdj + 2; A.dstat = S.dstat + 16;
+  return A;
+}
+
+void solve_plain(Scene& S, const double* rhs, double* out, const int* done, hipStream_t st) {
+  const VertArgs V = vert_args(S);
+  const SolveArgs A = solve_args(S);
+  StepState T = step_state(S);
+  T.done = const_cast<int*>(done);
+  launch_gather_E(kModePlain, V, A, T, rhs, nullptr, 0, st);
+  launch_top(kModePlain, V, A, T, rhs, out, 0, st);
+  launch_bottom(kModePlain, V, A, T, rhs, out, 0, st);
+}
+
+}  // namespace
+
+// ================================================================= C ABI
+#define PD_TRY try {
+#define PD_CATCH                                   \
+  }                                                \
+  catch (const PdError& e) {                       \
+    g_err = e.msg;                                 \
+    return e.code;                                 \
+  }                                                \
+  catch (const std::bad_alloc&) {                  \
+    g_err = "host allocation failed";              \
+    return PD_ERR_ALLOC;                           \
+  }                                                \
+  catch (const std::exception& e) {                \
+    g_err = e.what();                              \
+    return PD_ERR_INVALID_ARG;                     \
+  }
+
+extern "C" {
+
+const char* pd_last_error(void) { return g_err.c_str(); }
+
+int pd_scene_create(const pd_mesh_desc* mesh, const pd_material_desc* mat, const pd_solver_opts* opts,
+                    pd_scene** out) {
+  if (!out) {
+    g_err = "null output pointer";
+    return PD_ERR_INVALID_ARG;
+  }
+  *out = nullptr;
+  pd_scene* sc = nullptr;
+  PD_TRY
+  sc = new pd_scene();
+  setup_scene(sc->S, mesh, mat, opts);
+  factorize(sc->S);
+  *out = sc;
+  g_err.clear();
+  return PD_OK;
+  }
+  catch (const PdError& e) {
+    g_err = e.msg;
+    if (sc) { free_device(sc->S); delete sc; }
+    return e.code;
+  }
+  catch (const std::exception& e) {
+    g_err = e.what();
+    if (sc) { free_device(sc->S); delete sc; }
+    return PD_ERR_INVALID_ARG;
+  }
+}
+
+int pd_scene_destroy(pd_scene* scene) {
+  if (!scene) return PD_OK;
+  free_device(scene->S);
+  delete scene;
+  return PD_OK;
+}
+
+int pd_scene_set_material(pd_scene* scene, const double* log_E_host) {
+  if (!scene || !log_E_host) {
+    g_err = "null argument";
+    return PD_ERR_INVALID_ARG;
+  }
+  for (int e = 0; e < scene->S.ne; ++e)
+    if (!std::isfinite(log_E_host[e])) {
+      g_err = "non-finite log E";
+      return PD_ERR_NONFINITE;
+    }
+  scene->S.logE.assign(log_E_host, log_E_host + scene->S.ne);
+  scene->S.stale = true;
+  return PD_OK;
+}
+
+int pd_scene_factorize(pd_scene* scene, void* stream) {
+  if (!scene) {
+    g_err = "null scene";
+    return PD_ERR_INVALID_ARG;
+  }
+  (void)stream;
+  PD_TRY
+  factorize(scene->S);
+  return PD_OK;
+  PD_CATCH
+}
+
+int pd_scene_info(const pd_scene* scene, double* info, double* means) {
+  if (!scene) {
+    g_err = "null scene";
+    return PD_ERR_INVALID_ARG;
+  }
+  const Scene& S = scene->S;
+  if (info) {
+    info[0] = S.nv; info[1] = S.ne; info[2] = S.L.nf; info[3] = S.L.nsub; info[4] = S.L.nT; info[5] = S.m;
+    info[6] = (double)S.S.bytes;
+  }
+  if (means) { means[0] = S.mu_bar; means[1] = S.lam_bar; means[2] = S.k_bar; means[3] = S.mu_ref; }
+  return PD_OK;
+}
+
+size_t pd_ckpt_bytes(const pd_scene* scene) {
+  return scene ? (size_t)kCheckpointVecs * 3 * (size_t)scene->S.nv * sizeof(double) : 0;
+}
+
+int pd_step_forward(pd_scene* scene, const double* q_t, const double* v_t, const double* f_ext, const double* q0,
+                    double* q_next, double* v_next, void* ckpt, pd_fwd_stats* stats, void* stream) {
+  if (!scene || !q_t || !v_t || !q_next || !v_next) {
+    g_err = "null argument";
+    return PD_ERR_INVALID_ARG;
+  }
+  Scene& S = scene->S;
+  if (S.stale) {
+    g_err = "factor is stale: call pd_scene_factorize after pd_scene_set_material";
+    return PD_ERR_STALE_FACTOR;
+  }
+  PD_TRY
+  hipStream_t st = (hipStream_t)stream;
+  const ElemArgs E = elem_args(S);
+  const VertArgs V = vert_args(S);
+  const SolveArgs A = solve_args(S);
+  const StepState T = step_state(S);
+  // prologue: (1/h) B_beta q_t element terms, then q~, c, q^0
+  launch_to_lib(V, q_t, S.qt, 0, st);
+  launch_elem_GtG(E, S.qt, S.nv, S.bV, S.contrib, st);
+  launch_prologue(V, q_t, v_t, f_ext, q0, S.contrib, T, st);
+  PD_HIP(hipMemsetAsync(S.ctl, 0, (kCtlSize) * sizeof(int), st));
+  int k = 0;
+  int chunk = S.iters_per_check > 0 ? S.iters_per_check : std::max(3, S.last_fwd_iters + 1);
+  for (;;) {
+    const int kend = std::min(k + chunk, S.kmax_fwd);
+    for (; k < kend; ++k) {
+      launch_local(E, S.q_cur, S.nv, S.contrib, T.done, S.ctl + kCtlNewton, st);
+      launch_gather_E(kModeFwd, V, A, T, nullptr, nullptr, k, st);
+      launch_top(kModeFwd, V, A, T, nullptr, nullptr, k, st);
+      launch_bottom(kModeFwd, V, A, T, nullptr, nullptr, k, st);
+      launch_aa_update(V, T, k, st);
+    }
+    PD_HIP(hipMemcpyAsync(S.hctl, S.ctl, kCtlSize * sizeof(int), hipMemcpyDeviceToHost, st));
+    PD_HIP(hipStreamSynchronize(st));
+    if (S.hctl[kCtlDone] || k >= S.kmax_fwd) break;
+    chunk = S.iters_per_check > 0 ? S.iters_per_check : 2;
+  }
+  launch_epilogue(V, T, q_next, v_next, (double*)ckpt, st);
+  PD_HIP(hipMemcpyAsync(S.hdstat, S.dstat, 8 * sizeof(double), hipMemcpyDeviceToHost, st));
+  PD_HIP(hipMemcpyAsync(S.hctl, S.ctl, kCtlSize * sizeof(int), hipMemcpyDeviceToHost, st));
+  PD_HIP(hipStreamSynchronize(st));
+  PD_HIP(hipGetLastError());
+  const int iters = S.hctl[kCtlIters], status = S.hctl[kCtlStatus];
+  if (S.hctl[kCtlDone]) S.last_fwd_iters = iters;
+  if (stats) {
+    stats->iters = iters;
+    stats->aa_resets = S.hctl[kCtlResets];
+    stats->status = status;
+    stats->newton_max_iters = S.hctl[kCtlNewton];
+    for (int j = 0; j < 4; ++j) stats->gate[j] = S.hdstat[j];
+  }
+  if (!S.hctl[kCtlDone]) throw PdError{PD_ERR_HIP, "forward loop ended without a decision"};
+  return status == 0 ? PD_OK : PD_NOT_CONVERGED;
+  PD_CATCH
+}
+
+static void adjoint_solve(Scene& S, hipStream_t st, double tau_force, double* bstat_host, const double* ck) {
+  const ElemArgs E = elem_args(S);
+  const VertArgs V = vert_args(S);
+  const AdjState Ad = adj_state(S);
+  const int n_part = tr_partial_blocks(E, V);
+  launch_tr_partials(E, V, ck, S.red_part, st);
+  launch_bwd_elem(E, V, ck, S.red_part, n_part, S.eps_tr, tau_force, S.jac, S.dstat + 4, st);
+  PD_HIP(hipMemsetAsync(S.ctl + kCtlAdj, 0, 4 * sizeof(int), st));
+  const int mode = S.adj_method == 1 ? kModeFixed : kModePCG;
+  if (mode == kModePCG) {
+    solve_plain(S, S.r, S.z, Ad.done, st);
+    launch_pcg_start(V, Ad, st);
+  }
+  int it = 0;
+  int chunk = 8;
+  for (;;) {
+    const int iend = std::min(it + chunk, S.kmax_bwd);
+    for (; it < iend; ++it) {
+      if (mode == kModePCG) {
+        launch_apply_K(E, V, S.jac, S.p, S.contrib, Ad.done, st);
+        launch_adj_gather(kModePCG, V, Ad, it, st);
+        launch_pcg_alpha(V, Ad, it, st);
+        solve_plain(S, S.r, S.z, Ad.done, st);
+        launch_adj_dots(kModePCG, V, Ad, it, st);
+        launch_adj_next(kModePCG, V, Ad, it, st);
+      } else {
+        launch_apply_K(E, V, S.jac, S.mu, S.contrib, Ad.done, st);
+        launch_adj_gather(kModeFixed, V, Ad, it, st);
+        solve_plain(S, S.r, S.z, Ad.done, st);
+        launch_adj_dots(kModeFixed, V, Ad, it, st);
+        launch_adj_next(kModeFixed, V, Ad, it, st);
+      }
+    }
+    PD_HIP(hipMemcpyAsync(S.hctl, S.ctl, kCtlTotal * sizeof(int), hipMemcpyDeviceToHost, st));
+    PD_HIP(hipStreamSynchronize(st));
+    if (S.hctl[kCtlAdj + 2] || it >= S.kmax_bwd) break;
+    chunk = 4;
+  }
+  PD_HIP(hipMemcpyAsync(S.hdstat, S.dstat, 32 * sizeof(double), hipMemcpyDeviceToHost, st));
+  PD_HIP(hipStreamSynchronize(st));
+  if (bstat_host) {
+    for (int j = 0; j < 4; ++j) bstat_host[j] = S.hdstat[4 + j];
+    bstat_host[4] = S.hdstat[16];
+  }
+}
+
+int pd_step_backward(pd_scene* scene, const void* ckpt, const double* gq_next, const double* gv_next, double* gq_t,
+                     double* gv_t, double* gf_ext, double* g_logE_accum, pd_bwd_stats* stats, void* stream) {
+  if (!scene || !ckpt) {
+    g_err = "null argument";
+    return PD_ERR_INVALID_ARG;
+  }
+  Scene& S = scene->S;
+  if (S.stale) {
+    g_err = "factor is stale: call pd_scene_factorize after pd_scene_set_material";
+    return PD_ERR_STALE_FACTOR;
+  }
+  PD_TRY
+  hipStream_t st = (hipStream_t)stream;
+  const ElemArgs E = elem_args(S);
+  const VertArgs V = vert_args(S);
+  const AdjState Ad = adj_state(S);
+  const double* ck = (const double*)ckpt;
+  launch_bwd_prologue(V, Ad, gq_next, gv_next, st);
+  double bs[5] = {0, 0, 0, 0, 0};
+  adjoint_solve(S, st, -1.0, bs, ck);
+  launch_grad_elem(E, V, ck, S.jac, S.mu, S.contrib, g_logE_accum, st);
+  launch_grad_vert(V, S.mu, S.contrib, gv_next, gq_t, gv_t, gf_ext, st);
+  PD_HIP(hipStreamSynchronize(st));
+  PD_HIP(hipGetLastError());
+  const int status = S.hctl[kCtlAdj + 1];
+  if (stats) {
+    stats->adj_iters = S.hctl[kCtlAdj];
+    stats->status = status;
+    stats->rho = bs[0]; stats->tau = bs[1]; stats->dphi_act = bs[2]; stats->dphi_mod = bs[3];
+    stats->residual = bs[4];
+  }
+  return status == 0 ? PD_OK : PD_NOT_CONVERGED;
+  PD_CATCH
+}
+
+int pd_debug_local_rhs(pd_scene* scene, const double* q, double* b, void* stream) {
+  if (!scene || !q || !b) {
+    g_err = "null argument";
+    return PD_ERR_INVALID_ARG;
+  }
+  Scene& S = scene->S;
+  if (S.stale) { g_err = "factor is stale"; return PD_ERR_STALE_FACTOR; }
+  PD_TRY
+  hipStream_t st = (hipStream_t)stream;
+  const ElemArgs E = elem_args(S);
+  const VertArgs V = vert_args(S);
+  const SolveArgs A = solve_args(S);
+  StepState T = step_state(S);
+  T.done = nullptr;
+  launch_to_lib(V, q, S.z, 0, st);
+  launch_local(E, S.z, S.nv, S.contrib, nullptr, nullptr, st);
+  launch_gather_E(kModeDebugGather, V, A, T, nullptr, S.wv, 0, st);
+  launch_from_lib(V, S.wv, b, 1, st);
+  PD_HIP(hipStreamSynchronize(st));
+  PD_HIP(hipGetLastError());
+  return PD_OK;
+  PD_CATCH
+}
+
+int pd_debug_apply_Ainv(pd_scene* scene, const double* r, double* x, void* stream) {
+  if (!scene || !r || !x) {
+    g_err = "null argument";
+    return PD_ERR_INVALID_ARG;
+  }
+  Scene& S = scene->S;
+  if (S.stale) { g_err = "factor is stale"; return PD_ERR_STALE_FACTOR; }
+  PD_TRY
+  hipStream_t st = (hipStream_t)stream;
+  const VertArgs V = vert_args(S);
+  launch_to_lib(V, r, S.r, 1, st);
+  solve_plain(S, S.r, S.z, nullptr, st);
+  launch_from_lib(V, S.z, x, 1, st);
+  PD_HIP(hipStreamSynchronize(st));
+  PD_HIP(hipGetLastError());
+  return PD_OK;
+  PD_CATCH
+}
+
+int pd_debug_apply_K(pd_scene* scene, const double* q, double tau, const double* x, double* y, void* stream) {
+  if (!scene || !q || !x || !y) {
+    g_err = "null argument";
+    return PD_ERR_INVALID_ARG;
+  }
+  Scene& S = scene->S;
+  if (S.stale) { g_err = "factor is stale"; return PD_ERR_STALE_FACTOR; }
+  PD_TRY
+  hipStream_t st = (hipStream_t)stream;
+  const ElemArgs E = elem_args(S);
+  const VertArgs V = vert_args(S);
+  const AdjState Ad = adj_state(S);
+  // a checkpoint-shaped scratch whose q* slot holds q
+  double* ck = dalloc<double>(12 * (size_t)S.nv);
+  launch_to_lib(V, q, ck + 6 * (size_t)S.nv, 0, st);
+  launch_bwd_elem(E, V, ck, S.red_part, 0, S.eps_tr, tau, S.jac, S.dstat + 4, st);
+  launch_to_lib(V, x, S.p, 1, st);
+  launch_apply_K(E, V, S.jac, S.p, S.contrib, nullptr, st);
+  PD_HIP(hipMemsetAsync(S.ctl + kCtlAdj + 2, 0, sizeof(int), st));
+  launch_adj_gather(kModeDebugGather, V, Ad, 0, st);
+  launch_from_lib(V, S.wv, y, 1, st);
+  PD_HIP(hipStreamSynchronize(st));
+  (void)hipFree(ck);
+  PD_HIP(hipGetLastError());
+  return PD_OK;
+  PD_CATCH
+}
+
+}  // extern "C"

@@ -1,0 +1,157 @@
+"""Benchmark: forward + backward differentiable-PD time steps per second on one
+MI355X, on the heterogeneous-beam workload (40x10x10 cubes, 20000 tets, 4961
+vertices, FP64, h = 5 ms, dual-gate and adjoint tolerance 1e-6).
+
+One bench step = one PD time step solved forward to the dual gate plus its
+adjoint step (trust-region selection, filtered prox differential, adjoint
+solve to 1e-6, gradient routing).  The timed region runs K forward steps of the
+rollout (with checkpoints) and then the K backward steps from the gradient of a
+centroid loss, all inputs resident in HBM.  Prints ONE JSON line.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "fwd+bwd PD steps/sec at 1e-6 residual (plain vs warm-started); % HBM roofline"
+HBM_PEAK_GBS = 8000.0
+FP64_VECTOR_PEAK_TFLOPS = 78.6
+
+# kernel ids understood by pd_kernel_timer (see include/pdhot.h)
+KERNELS = {"local": 0, "gather_E": 1, "top": 2, "bottom": 3, "aa_update": 4, "apply_K": 5}
+
+
+def parse():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=100)
+    ap.add_argument("--warmup", type=int, default=5)
+    ap.add_argument("--config", default="c2")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--cpu-sample-steps", type=int, default=20)
+    ap.add_argument("--timed-kernel", default="top", choices=sorted(KERNELS))
+    ap.add_argument("--max-sub", type=int, default=0)
+    return ap.parse_args()
+
+
+def ensure_built():
+    from paper_2605_14526_amd import binding
+    if not os.path.exists(binding.LIB_PATH):
+        from paper_2605_14526_amd import build
+        build.build()
+
+
+def rollout_fwd_bwd(g, sc, K, torch, dev, timed_kernel=None):
+    """K forward steps with checkpoints, then K backward steps."""
+    q = dev(sc.q0())
+    v = dev(sc.v0())
+    forces = [dev(sc.f_ext(t)) for t in range(K)]
+    ckpts = [g.new_ckpt() for _ in range(K)]
+    qs = [torch.empty_like(q) for _ in range(K + 1)]
+    vs = [torch.empty_like(q) for _ in range(K + 1)]
+    qs[0].copy_(q)
+    vs[0].copy_(v)
+    g_logE = torch.zeros(sc.n_e, dtype=torch.float64, device="cuda")
+    gq_t, gv_t, gf = torch.empty_like(q), torch.empty_like(q), torch.empty_like(q)
+    target = torch.tensor(sc.target_centroid, dtype=torch.float64, device="cuda")
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    fiters, biters = [], []
+    for t in range(K):
+        _, _, st = g.step_forward(qs[t], vs[t], forces[t], q_next=qs[t + 1], v_next=vs[t + 1], ckpt=ckpts[t])
+        fiters.append(st["iters"])
+    # loss = |mean(q_K) - target|^2 (the gradient is formed on the device)
+    c = qs[K].mean(dim=0)
+    gq = (2.0 * (c - target) / sc.n_v).expand_as(qs[K]).contiguous()
+    gv = torch.zeros_like(gq)
+    for t in reversed(range(K)):
+        g.step_backward(ckpts[t], gq, gv, g_logE=g_logE, gq_t=gq_t, gv_t=gv_t, gf_ext=gf)
+        gq, gq_t = gq_t, gq
+        gv, gv_t = gv_t, gv
+        biters.append(g.last_bwd_stats["adj_iters"])
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    return t1 - t0, fiters, biters, g_logE
+
+
+def cpu_baseline(sc, steps):
+    """The FP64 CPU oracle (serial C) on the first `steps` steps of the same rollout."""
+    import oracle as O
+    t0 = time.perf_counter()
+    osc = O.OracleScene(sc)
+    q, v, ck, _ = O.rollout(osc, steps)
+    from paper_2605_14526_amd import scenes
+    _, gq = scenes.centroid_loss(q, sc.target_centroid)
+    O.rollout_backward(osc, ck, gq, np.zeros_like(gq))
+    t1 = time.perf_counter()
+    return t1 - t0
+
+
+def main():
+    args = parse()
+    if args.gpus != 1:
+        print(f"bench.py runs on exactly one GPU (asked for {args.gpus}); this build has no multi-GPU path.",
+              file=sys.stderr)
+        sys.exit(2)
+    import torch
+    ensure_built()
+    from paper_2605_14526_amd import scenes
+    from paper_2605_14526_amd.binding import Scene
+
+    sc = scenes.config(args.config)
+    dev = lambda a: torch.tensor(np.ascontiguousarray(a), dtype=torch.float64, device="cuda")  # noqa: E731
+    g = Scene.from_scene(sc, eps_adj=1e-6, max_sub=args.max_sub)
+    info = g.info()
+    print(f"[bench] scene {sc.name}: {info}", file=sys.stderr, flush=True)
+    # warmup (untimed)
+    if args.warmup > 0:
+        rollout_fwd_bwd(g, sc, args.warmup, torch, dev)
+        print("[bench] warmup done", file=sys.stderr, flush=True)
+    # timed region, with per-launch HIP-event timing of one kernel on the
+    # library's stream
+    kid = KERNELS[args.timed_kernel]
+    g.kernel_timer(kid)
+    dt, fiters, biters, g_logE = rollout_fwd_bwd(g, sc, args.steps, torch, dev)
+    ktime_ms, kcount, kwork = g.kernel_timer_read()
+    g.kernel_timer(-1)
+    assert torch.isfinite(g_logE).all()
+    print(f"[bench] timed {args.steps} fwd+bwd steps in {dt:.4f} s; fwd iters/step {np.mean(fiters):.2f}, "
+          f"adjoint iters/step {np.mean(biters):.2f}", file=sys.stderr, flush=True)
+    value = args.steps / dt
+    # roofline of the timed kernel: algorithmic bytes of the launches that did
+    # work over the summed launch durations
+    bytes_per_unit = g.kernel_bytes(kid)
+    achieved = (kwork * bytes_per_unit) / (ktime_ms * 1e-3) / 1e9 if ktime_ms > 0 else 0.0
+    roof = {"kernel": args.timed_kernel, "bound": "hbm", "achieved": round(achieved, 2), "peak": HBM_PEAK_GBS,
+            "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None,
+            "avg_launch_us": round(1000.0 * ktime_ms / max(kcount, 1), 3), "launches": int(kcount),
+            "working_launches": int(kwork), "algorithmic_bytes_per_launch": int(bytes_per_unit)}
+    out = {"metric": METRIC, "value": round(value, 3), "unit": "steps/s", "n_gpus": 1, "steps": args.steps,
+           "warmup": args.warmup, "ms_per_step": round(1000.0 * dt / args.steps, 4), "higher_is_better": True,
+           "scaling": "weak", "vs_baseline": None, "dtype": "f64", "data": "synthetic",
+           "config": {"workload": f"{sc.name}: 40x10x10 cubes, {sc.n_e} tets, {sc.n_v} verts, two-phase E 1e4/1e6, "
+                                  f"nu 0.49, h {sc.h}, rollout of {args.steps} steps, AA window {sc.aa_window}, "
+                                  "gate and adjoint 1e-6, plain q0 = q_t",
+                      "fwd_iters_per_step": round(float(np.mean(fiters)), 3),
+                      "adj_iters_per_step": round(float(np.mean(biters)), 3),
+                      "n_subdomains": int(info["n_subdomains"]), "n_interface": int(info["n_interface"])},
+           "roofline": roof}
+    if not args.no_cpu_baseline:
+        n = args.cpu_sample_steps
+        t = cpu_baseline(sc, n)
+        out["cpu_baseline"] = {"value": round(n / t, 4), "unit": "steps/s", "cores": 1, "kind": "oracle",
+                               "sample": f"first {n} fwd+bwd steps of the same rollout, serial FP64 C oracle "
+                                         f"(fixed-point adjoint), {t:.2f} s"}
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

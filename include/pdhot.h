@@ -178,6 +178,19 @@ int pd_debug_local_rhs(pd_scene* scene, const double* q, double* b, void* stream
 int pd_debug_apply_Ainv(pd_scene* scene, const double* r, double* x, void* stream);
 int pd_debug_apply_K(pd_scene* scene, const double* q, double tau, const double* x, double* y, void* stream);
 
+/* Kernel timing for roofline reports: HIP events recorded on the caller's
+ * stream around every launch of one kernel inside pd_step_forward /
+ * pd_step_backward.  kernel: 0 local step, 1 gather and coupling products,
+ * 2 interface (Schur) solve, 3 subdomain solve, 4 Anderson update, 5 K apply;
+ * -1 stops timing.  Resets the totals.  Instrumentation only: it adds two
+ * event records per launch of the chosen kernel. */
+int pd_kernel_timer(pd_scene* scene, int kernel);
+/* Totals since pd_kernel_timer: summed launch durations (ms), launches timed,
+ * launches that did work (the others exit at once after convergence), and
+ * the algorithmic bytes of one working launch of that kernel. */
+int pd_kernel_timer_read(pd_scene* scene, double* total_ms, int64_t* launches, int64_t* working,
+                         double* bytes_per_launch);
+
 /* Message of the last failing call on this thread ("" if none). */
 const char* pd_last_error(void);
 

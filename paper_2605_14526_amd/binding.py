@@ -23,7 +23,7 @@ ERRORS = {-1: "PD_ERR_INVALID_ARG", -2: "PD_ERR_DEGENERATE_TET", -3: "PD_ERR_NON
 
 EXPORTED = ["pd_scene_create", "pd_scene_destroy", "pd_scene_set_material", "pd_scene_factorize", "pd_scene_info",
             "pd_ckpt_bytes", "pd_step_forward", "pd_step_backward", "pd_debug_local_rhs", "pd_debug_apply_Ainv",
-            "pd_debug_apply_K", "pd_last_error"]
+            "pd_debug_apply_K", "pd_kernel_timer", "pd_kernel_timer_read", "pd_last_error"]
 
 
 class pd_mesh_desc(ctypes.Structure):
@@ -80,6 +80,8 @@ def lib() -> ctypes.CDLL:
     L.pd_debug_local_rhs.argtypes = [vp, vp, vp, vp]
     L.pd_debug_apply_Ainv.argtypes = [vp, vp, vp, vp]
     L.pd_debug_apply_K.argtypes = [vp, vp, dbl, vp, vp, vp]
+    L.pd_kernel_timer.argtypes = [vp, i32]
+    L.pd_kernel_timer_read.argtypes = [vp, vp, vp, vp, vp]
     L.pd_last_error.restype = ctypes.c_char_p
     for name in EXPORTED:
         getattr(L, name)
@@ -192,9 +194,24 @@ class Scene:
         rc = check(lib().pd_step_backward(self.ptr, _ptr(ckpt), _ptr(gq_next), _ptr(gv_next), _ptr(gq_t),
                                           _ptr(gv_t), _ptr(gf_ext), _ptr(g_logE), ctypes.byref(st), _stream()),
                    "pd_step_backward")
-        return gq_t, gv_t, gf_ext, g_logE, dict(adj_iters=st.adj_iters, status=st.status, rho=st.rho, tau=st.tau,
-                                                  dphi_act=st.dphi_act, dphi_mod=st.dphi_mod,
-                                                  residual=st.residual, rc=rc)
+        self.last_bwd_stats = dict(adj_iters=st.adj_iters, status=st.status, rho=st.rho, tau=st.tau,
+                                   dphi_act=st.dphi_act, dphi_mod=st.dphi_mod, residual=st.residual, rc=rc)
+        return gq_t, gv_t, gf_ext, g_logE, self.last_bwd_stats
+
+    def kernel_timer(self, kernel: int):
+        check(lib().pd_kernel_timer(self.ptr, int(kernel)), "pd_kernel_timer")
+
+    def kernel_timer_read(self):
+        ms = ctypes.c_double()
+        n, w = ctypes.c_int64(), ctypes.c_int64()
+        b = ctypes.c_double()
+        check(lib().pd_kernel_timer_read(self.ptr, ctypes.byref(ms), ctypes.byref(n), ctypes.byref(w),
+                                         ctypes.byref(b)), "pd_kernel_timer_read")
+        self._last_bytes = b.value
+        return ms.value, n.value, w.value
+
+    def kernel_bytes(self, kernel: int) -> float:
+        return getattr(self, "_last_bytes", 0.0)
 
     def debug_local_rhs(self, q):
         import torch

@@ -55,6 +55,15 @@ struct DeviceSolve {
   size_t bytes = 0;
 };
 
+// Per-launch timing of one kernel with HIP events (roofline instrumentation).
+struct KernelTimer {
+  int which = -1;
+  std::vector<hipEvent_t> ev;  // begin/end pairs
+  int used = 0;
+  double total_ms = 0.0;
+  long long launches = 0, working = 0;
+};
+
 struct Scene {
   // --- host copies
   int nv = 0, ne = 0;
@@ -103,6 +112,7 @@ struct Scene {
   double *mu = nullptr, *r = nullptr, *z = nullptr, *p = nullptr, *Ap = nullptr, *wv = nullptr, *qbar = nullptr;
   double* red_part = nullptr;  // generic per-block partials (n_red_blocks x 8)
   int n_gather_blocks = 0, n_bottom_blocks = 0, n_vert_blocks = 0, n_tet_blocks = 0;
+  KernelTimer kt;
 };
 
 }  // namespace pdhot

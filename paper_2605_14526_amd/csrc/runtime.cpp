@@ -123,7 +123,59 @@ void free_device(Scene& S) {
   if (S.hdstat) (void)hipHostFree(S.hdstat);
   S.hctl = nullptr;
   S.hdstat = nullptr;
+  for (hipEvent_t e : S.kt.ev) (void)hipEventDestroy(e);
+  S.kt.ev.clear();
 }
+
+
+// ---------------------------------------------------------------- kernel timer
+enum { kKLocal = 0, kKGather = 1, kKTop = 2, kKBottom = 3, kKAA = 4, kKApplyK = 5, kKCount = 6 };
+constexpr int kTimerPairs = 1024;
+
+void kt_flush(Scene& S) {
+  KernelTimer& T = S.kt;
+  for (int i = 0; i < T.used; ++i) {
+    float ms = 0.0f;
+    PD_HIP(hipEventElapsedTime(&ms, T.ev[2 * i], T.ev[2 * i + 1]));
+    T.total_ms += ms;
+    T.launches++;
+  }
+  T.used = 0;
+}
+
+inline void kt_begin(Scene& S, int id, hipStream_t st) {
+  KernelTimer& T = S.kt;
+  if (T.which != id) return;
+  if (T.used == kTimerPairs) {
+    PD_HIP(hipStreamSynchronize(st));
+    kt_flush(S);
+  }
+  PD_HIP(hipEventRecord(T.ev[2 * T.used], st));
+}
+
+inline void kt_end(Scene& S, int id, hipStream_t st) {
+  KernelTimer& T = S.kt;
+  if (T.which != id) return;
+  PD_HIP(hipEventRecord(T.ev[2 * T.used + 1], st));
+  T.used++;
+}
+
+inline void kt_work(Scene& S, int id, long long n) {
+  if (S.kt.which == id) S.kt.working += n;
+}
+
+void kt_destroy(Scene& S) {
+  for (hipEvent_t e : S.kt.ev) (void)hipEventDestroy(e);
+  S.kt.ev.clear();
+  S.kt.which = -1;
+}
+
+#define PD_TIMED(S, id, st, call) \
+  do {                            \
+    kt_begin(S, id, st);          \
+    call;                         \
+    kt_end(S, id, st);            \
+  } while (0)
 
 // ---------------------------------------------------------------- argument blocks
 ElemArgs elem_args(const Scene& S) {
@@ -517,12 +569,43 @@ void solve_plain(Scene& S, const double* rhs, double* out, const int* done, hipS
   const SolveArgs A = solve_args(S);
   StepState T = step_state(S);
   T.done = const_cast<int*>(done);
-  launch_gather_E(kModePlain, V, A, T, rhs, nullptr, 0, st);
-  launch_top(kModePlain, V, A, T, rhs, out, 0, st);
-  launch_bottom(kModePlain, V, A, T, rhs, out, 0, st);
+  PD_TIMED(S, kKGather, st, launch_gather_E(kModePlain, V, A, T, rhs, nullptr, 0, st));
+  PD_TIMED(S, kKTop, st, launch_top(kModePlain, V, A, T, rhs, out, 0, st));
+  PD_TIMED(S, kKBottom, st, launch_bottom(kModePlain, V, A, T, rhs, out, 0, st));
 }
 
 }  // namespace
+
+
+// Algorithmic bytes of one working launch of each timed kernel: what the
+// operation must read and write once (matrix blocks, element data, vectors),
+// not what the implementation re-reads.
+static double kernel_bytes(const Scene& S, int id) {
+  const Layout& L = S.L;
+  const double nf = L.nf, nT = L.nT, ne = S.ne, nv = S.nv;
+  double zs = 0, et = 0;
+  for (int s = 0; s < L.nsub; ++s) {
+    const double ns = L.sub_begin[s + 1] - L.sub_begin[s];
+    zs += ns * ns;
+    et += ns * (double)L.Irows[s].size();
+  }
+  switch (id) {
+    case kKLocal:  // tet indices, D_m^-1, weight, positions in, 12 contributions out
+      return ne * (16.0 + 72.0 + 8.0 + 96.0) + 24.0 * nv;
+    case kKGather:  // contributions and constant part in, b out, E blocks, coupling slots out
+      return ne * 96.0 + 24.0 * nf * 2 + 8.0 * et + 24.0 * (double)S.S.nslots;
+    case kKTop:  // inverse Schur block, interface right-hand side in, solution out
+      return 8.0 * nT * nT + 24.0 * nT * 2 + 24.0 * (double)S.S.nslots;
+    case kKBottom:  // subdomain inverses and couplings, right-hand sides, solution out
+      return 8.0 * (zs + et) + 24.0 * (L.nB * 2 + nT);
+    case kKAA:  // q^, q, m difference pairs in, q out
+      return 24.0 * nf * (3 + 2 * std::max(1, S.m));
+    case kKApplyK:  // tet indices, D_m^-1, weight, 30 Jacobian values, x in, contributions out
+      return ne * (16.0 + 72.0 + 8.0 + 240.0 + 96.0) + 24.0 * nv;
+    default:
+      return 0.0;
+  }
+}
 
 // ================================================================= C ABI
 #define PD_TRY try {
@@ -652,14 +735,15 @@ int pd_step_forward(pd_scene* scene, const double* q_t, const double* v_t, const
   for (;;) {
     const int kend = std::min(k + chunk, S.kmax_fwd);
     for (; k < kend; ++k) {
-      launch_local(E, S.q_cur, S.nv, S.contrib, T.done, S.ctl + kCtlNewton, st);
-      launch_gather_E(kModeFwd, V, A, T, nullptr, nullptr, k, st);
-      launch_top(kModeFwd, V, A, T, nullptr, nullptr, k, st);
-      launch_bottom(kModeFwd, V, A, T, nullptr, nullptr, k, st);
-      launch_aa_update(V, T, k, st);
+      PD_TIMED(S, kKLocal, st, launch_local(E, S.q_cur, S.nv, S.contrib, T.done, S.ctl + kCtlNewton, st));
+      PD_TIMED(S, kKGather, st, launch_gather_E(kModeFwd, V, A, T, nullptr, nullptr, k, st));
+      PD_TIMED(S, kKTop, st, launch_top(kModeFwd, V, A, T, nullptr, nullptr, k, st));
+      PD_TIMED(S, kKBottom, st, launch_bottom(kModeFwd, V, A, T, nullptr, nullptr, k, st));
+      PD_TIMED(S, kKAA, st, launch_aa_update(V, T, k, st));
     }
     PD_HIP(hipMemcpyAsync(S.hctl, S.ctl, kCtlSize * sizeof(int), hipMemcpyDeviceToHost, st));
     PD_HIP(hipStreamSynchronize(st));
+    kt_flush(S);
     if (S.hctl[kCtlDone] || k >= S.kmax_fwd) break;
     chunk = S.iters_per_check > 0 ? S.iters_per_check : 2;
   }
@@ -670,6 +754,13 @@ int pd_step_forward(pd_scene* scene, const double* q_t, const double* v_t, const
   PD_HIP(hipGetLastError());
   const int iters = S.hctl[kCtlIters], status = S.hctl[kCtlStatus];
   if (S.hctl[kCtlDone]) S.last_fwd_iters = iters;
+  // launches that did work: local step and gather at k = 0..iters, the
+  // interface solve, subdomain solve and mixing at k = 0..iters-1
+  kt_work(S, kKLocal, iters + 1);
+  kt_work(S, kKGather, iters + 1);
+  kt_work(S, kKTop, iters);
+  kt_work(S, kKBottom, iters);
+  kt_work(S, kKAA, iters);
   if (stats) {
     stats->iters = iters;
     stats->aa_resets = S.hctl[kCtlResets];
@@ -701,14 +792,14 @@ static void adjoint_solve(Scene& S, hipStream_t st, double tau_force, double* bs
     const int iend = std::min(it + chunk, S.kmax_bwd);
     for (; it < iend; ++it) {
       if (mode == kModePCG) {
-        launch_apply_K(E, V, S.jac, S.p, S.contrib, Ad.done, st);
+        PD_TIMED(S, kKApplyK, st, launch_apply_K(E, V, S.jac, S.p, S.contrib, Ad.done, st));
         launch_adj_gather(kModePCG, V, Ad, it, st);
         launch_pcg_alpha(V, Ad, it, st);
         solve_plain(S, S.r, S.z, Ad.done, st);
         launch_adj_dots(kModePCG, V, Ad, it, st);
         launch_adj_next(kModePCG, V, Ad, it, st);
       } else {
-        launch_apply_K(E, V, S.jac, S.mu, S.contrib, Ad.done, st);
+        PD_TIMED(S, kKApplyK, st, launch_apply_K(E, V, S.jac, S.mu, S.contrib, Ad.done, st));
         launch_adj_gather(kModeFixed, V, Ad, it, st);
         solve_plain(S, S.r, S.z, Ad.done, st);
         launch_adj_dots(kModeFixed, V, Ad, it, st);
@@ -717,6 +808,7 @@ static void adjoint_solve(Scene& S, hipStream_t st, double tau_force, double* bs
     }
     PD_HIP(hipMemcpyAsync(S.hctl, S.ctl, kCtlTotal * sizeof(int), hipMemcpyDeviceToHost, st));
     PD_HIP(hipStreamSynchronize(st));
+    kt_flush(S);
     if (S.hctl[kCtlAdj + 2] || it >= S.kmax_bwd) break;
     chunk = 4;
   }
@@ -726,6 +818,12 @@ static void adjoint_solve(Scene& S, hipStream_t st, double tau_force, double* bs
     for (int j = 0; j < 4; ++j) bstat_host[j] = S.hdstat[4 + j];
     bstat_host[4] = S.hdstat[16];
   }
+  const int n_it = S.hctl[kCtlAdj];
+  const int n_solves = (mode == kModePCG) ? n_it + 1 : n_it;
+  kt_work(S, kKApplyK, n_it);
+  kt_work(S, kKGather, n_solves);
+  kt_work(S, kKTop, n_solves);
+  kt_work(S, kKBottom, n_solves);
 }
 
 int pd_step_backward(pd_scene* scene, const void* ckpt, const double* gq_next, const double* gv_next, double* gq_t,
@@ -830,6 +928,44 @@ int pd_debug_apply_K(pd_scene* scene, const double* q, double tau, const double*
   PD_HIP(hipStreamSynchronize(st));
   (void)hipFree(ck);
   PD_HIP(hipGetLastError());
+  return PD_OK;
+  PD_CATCH
+}
+
+int pd_kernel_timer(pd_scene* scene, int kernel) {
+  if (!scene || kernel < -1 || kernel >= kKCount) {
+    g_err = "invalid scene or kernel id";
+    return PD_ERR_INVALID_ARG;
+  }
+  PD_TRY
+  KernelTimer& T = scene->S.kt;
+  if (T.ev.empty() && kernel >= 0) {
+    T.ev.resize(2 * kTimerPairs);
+    for (auto& e : T.ev) PD_HIP(hipEventCreate(&e));
+  }
+  T.which = kernel;
+  T.used = 0;
+  T.total_ms = 0.0;
+  T.launches = 0;
+  T.working = 0;
+  return PD_OK;
+  PD_CATCH
+}
+
+int pd_kernel_timer_read(pd_scene* scene, double* total_ms, int64_t* launches, int64_t* working,
+                         double* bytes_per_launch) {
+  if (!scene) {
+    g_err = "null scene";
+    return PD_ERR_INVALID_ARG;
+  }
+  PD_TRY
+  Scene& S = scene->S;
+  PD_HIP(hipDeviceSynchronize());
+  kt_flush(S);
+  if (total_ms) *total_ms = S.kt.total_ms;
+  if (launches) *launches = S.kt.launches;
+  if (working) *working = S.kt.working;
+  if (bytes_per_launch) *bytes_per_launch = S.kt.which >= 0 ? kernel_bytes(S, S.kt.which) : 0.0;
   return PD_OK;
   PD_CATCH
 }

@@ -26,7 +26,7 @@ HBM_PEAK_GBS = 8000.0
 FP64_VECTOR_PEAK_TFLOPS = 78.6
 
 # kernel ids understood by pd_kernel_timer (see include/pdhot.h)
-KERNELS = {"local": 0, "gather_E": 1, "top": 2, "bottom": 3, "aa_update": 4, "apply_K": 5}
+KERNELS = {"local": 0, "gather": 1, "top": 2, "bottom": 3, "Eb": 4, "apply_K": 5}
 
 
 def parse():

@@ -180,8 +180,9 @@ int pd_debug_apply_K(pd_scene* scene, const double* q, double tau, const double*
 
 /* Kernel timing for roofline reports: HIP events recorded on the caller's
  * stream around every launch of one kernel inside pd_step_forward /
- * pd_step_backward.  kernel: 0 local step, 1 gather and coupling products,
- * 2 interface (Schur) solve, 3 subdomain solve, 4 Anderson update, 5 K apply;
+ * pd_step_backward.  kernel: 0 local step, 1 right-hand-side gather,
+ * 2 interface (Schur) solve, 3 subdomain solve, 4 interface right-hand side
+ * (coupling products), 5 K apply;
  * -1 stops timing.  Resets the totals.  Instrumentation only: it adds two
  * event records per launch of the chosen kernel. */
 int pd_kernel_timer(pd_scene* scene, int kernel);

@@ -35,6 +35,19 @@ __device__ __forceinline__ void jacobi_rotate(double& app, double& aqq, double& 
   }
 }
 
+// Jacobi sweeps that accumulate into the rotation Q given on entry.
+__device__ __forceinline__ void jacobi_sweeps(double& a00, double& a11, double& a22, double& a01, double& a02,
+                                              double& a12, double Q[9]) {
+  for (int sweep = 0; sweep < 12; ++sweep) {
+    const double off = a01 * a01 + a02 * a02 + a12 * a12;
+    const double dia = a00 * a00 + a11 * a11 + a22 * a22;
+    if (off <= 1e-32 * dia) break;
+    jacobi_rotate(a00, a11, a01, a02, a12, Q, 0, 1);
+    jacobi_rotate(a00, a22, a02, a01, a12, Q, 0, 2);
+    jacobi_rotate(a11, a22, a12, a01, a02, Q, 1, 2);
+  }
+}
+
 __device__ __forceinline__ void sym3_eig(double a00, double a11, double a22, double a01, double a02, double a12,
                                          double lam[3], double Q[9]) {
 #pragma unroll
@@ -58,7 +71,10 @@ __device__ __forceinline__ void sym3_eig(double a00, double a11, double a22, dou
 // det F on s2).  V diagonalises F^T F (Jacobi), then a Givens QR of B = F V
 // gives U and the signed singular values on the diagonal of R.
 // ---------------------------------------------------------------------------
-__device__ __forceinline__ void svd3(const double F[9], double U[9], double s[3], double V[9]) {
+// With warm = true, V holds on entry a rotation close to the answer (the
+// previous iterate's): F^T F is first rotated into that frame, where it is
+// nearly diagonal, so the Jacobi sweeps stop after one or two.
+__device__ __forceinline__ void svd3(const double F[9], double U[9], double s[3], double V[9], bool warm = false) {
   // S = F^T F
   double a00 = 0, a11 = 0, a22 = 0, a01 = 0, a02 = 0, a12 = 0;
 #pragma unroll
@@ -68,7 +84,25 @@ __device__ __forceinline__ void svd3(const double F[9], double U[9], double s[3]
     a01 += f0 * f1; a02 += f0 * f2; a12 += f1 * f2;
   }
   double lam[3];
-  sym3_eig(a00, a11, a22, a01, a02, a12, lam, V);
+  if (warm) {
+    // S' = V^T S V
+    double SV[9];
+    const double Sm[9] = {a00, a01, a02, a01, a11, a12, a02, a12, a22};
+#pragma unroll
+    for (int i = 0; i < 3; ++i)
+#pragma unroll
+      for (int j = 0; j < 3; ++j) SV[3 * i + j] = Sm[3 * i] * V[j] + Sm[3 * i + 1] * V[3 + j] + Sm[3 * i + 2] * V[6 + j];
+    double Sp[9];
+#pragma unroll
+    for (int i = 0; i < 3; ++i)
+#pragma unroll
+      for (int j = i; j < 3; ++j) Sp[3 * i + j] = V[i] * SV[j] + V[3 + i] * SV[3 + j] + V[6 + i] * SV[6 + j];
+    a00 = Sp[0]; a11 = Sp[4]; a22 = Sp[8]; a01 = Sp[1]; a02 = Sp[2]; a12 = Sp[5];
+    jacobi_sweeps(a00, a11, a22, a01, a02, a12, V);
+    lam[0] = a00; lam[1] = a11; lam[2] = a22;
+  } else {
+    sym3_eig(a00, a11, a22, a01, a02, a12, lam, V);
+  }
   // sort eigenvalues descending; each swap negates one column to keep det V = +1
 #define PD_SWAPCOL(i, j)                                               \
   {                                                                    \
@@ -155,9 +189,15 @@ __device__ __forceinline__ void prox_hessian(const double s[3], double mu, doubl
 // otherwise a diagonally scaled gradient step; fraction-to-boundary 0.9 keeps
 // s > 0; backtracking (Armijo) on f while the step is large; stops at
 // |g|_inf <= 1e-13 k max(1, |sF|_inf).  Returns the Newton iteration count.
-__device__ __forceinline__ int prox_stretch(const double sF[3], double mu, double lam, double k, double s[3]) {
+// ratio (may be null): per stretch, a previous s*/sF used as the start
+// s = sF * ratio when both are positive.
+__device__ __forceinline__ int prox_stretch(const double sF[3], double mu, double lam, double k, double s[3],
+                                            const double* ratio = nullptr) {
 #pragma unroll
-  for (int i = 0; i < 3; ++i) s[i] = fmax(sF[i], 0.1);
+  for (int i = 0; i < 3; ++i) {
+    s[i] = fmax(sF[i], 0.1);
+    if (ratio && sF[i] > 0.0 && ratio[i] > 0.0) s[i] = sF[i] * ratio[i];
+  }
   const double sfmax = fmax(1.0, fmax(fabs(sF[0]), fmax(fabs(sF[1]), fabs(sF[2]))));
   const double gtol = 1e-13 * k * sfmax;
   int it = 0;

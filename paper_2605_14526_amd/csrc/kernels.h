@@ -9,7 +9,14 @@
 
 namespace pdhot {
 
-enum { kModeFwd = 0, kModePlain = 1, kModeDebugGather = 2, kModePCG = 3, kModeFixed = 4 };
+enum {
+  kModeFwd = 0,
+  kModePlain = 1,
+  kModeDebug = 2,
+  kModePCG = 3,
+  kModePCGInit = 4,
+  kModeFixed = 5
+};
 
 // device control block (int): done flag, final iteration count, status,
 // Anderson resets, Newton iteration maximum, then two Anderson states
@@ -18,101 +25,119 @@ enum { kModeFwd = 0, kModePlain = 1, kModeDebugGather = 2, kModePCG = 3, kModeFi
 enum { kCtlDone = 0, kCtlIters = 1, kCtlStatus = 2, kCtlResets = 3, kCtlNewton = 4, kCtlAA = 8, kCtlSize = 16,
        kCtlAdj = 16, kCtlTotal = 24 };
 
+// Deterministic cross-block reductions without atomics: each producing block
+// writes its partial vector; the first kernel that needs the total sums all
+// partials in a fixed order (thread t takes partials t, t + blockDim, ...,
+// then a fixed tree) and its block 0 stores the total in `fin` for the kernels
+// after it.
+enum { kRedGate = 0, kRedAA = 1, kRedPW = 2, kRedRZ0 = 3, kRedRZ1 = 4, kRedTR = 5, kRedFix = 6, kRedSites = 7 };
+constexpr int kRedWidth = 32;   // doubles per partial
+constexpr int kFinStride = 64;  // doubles per site in the final buffer
+constexpr int kBottomThreads = 512;
+
+struct RedArgs {
+  double* part;    // per site: max_parts x kRedWidth
+  double* fin;     // per site: kFinStride doubles
+  int max_parts;
+  int nparts[kRedSites];  // producing blocks of each site
+};
+
 struct ElemArgs {
-  int ne;
-  const int* tv;
-  const double* Bm;
+  int ne, ninc;
+  const int* tv;      // 4 x ne library vertex ids
+  const int* tinc;    // 4 x ne positions in the incidence order (-1 for pinned)
+  const double* Bm;   // 9 x ne
   const double* wV;
   const double* bV;
   const double* muV;
   const double* lamV;
   const int* tet_orig;
+  double* Vw;         // 9 x ne warm-start rotations (local step)
+  double* rw;         // 3 x ne warm-start stretch ratios
   double mu_bar, lam_bar, k_bar;
 };
 
 struct VertArgs {
-  int nv, nf, ne, max_sub;
+  int nv, nf, ne, ninc;
   const int* v_orig;
   const double* mass;
   const double* rest;
   const double* cpin;
   const int* inc_ptr;
-  const int* inc_idx;
   double h, alpha;
   double grav[3];
 };
 
 struct SolveArgs {
-  int nsub, nB, nT, n_bottom_items, n_top_blocks, top_rows, max_ns, max_nI;
-  const double* Zs;
-  const double* Et;
-  const double* Z;
+  int nsub, nB, nT;
+  const int* sub_of;        // nB: subdomain of each subdomain row
+  const int* sub_begin;     // nsub + 1
+  const double* Zs;         // per subdomain ns x ns
   const long long* zs_off;
-  const long long* et_off;
-  const int* sub_begin;
-  const int* ir_off;
-  const int* irows;
-  const int* slot_of;
-  const int* row_slot_ptr;
-  double* t_slots;
-  const int* bottom_items;
+  const double* Et;         // per subdomain ns x nI (row v: E_s[:, v])
+  const double* E;          // per subdomain nI x ns (row p: E_s[p, :])
+  const long long* e_off;
+  const int* ir_off;        // nsub + 1
+  const int* irows;         // concatenated interface rows of each subdomain
+  const int* rl_ptr;        // nT + 1: couplings of each interface row
+  const int* rl_sub;        // subdomain of each coupling
+  const int* rl_p;          // row of E_s of each coupling
+  const double* Z;          // nT x nT
+  double* rT;               // 3 x nT interface right-hand side
 };
 
 struct StepState {
   int m, kmax;
   double eps_rel, eps_abs;
-  int n_gate_blocks, n_aa_blocks;
   double *contrib, *qt, *vt, *qtil, *c;
   double *q_cur, *q_prev, *b_cur, *b_prev, *qhat;
   double *q_last, *g_last, *dQ, *dG;
-  double *gate_part, *aa_part;
   int* ctl;
   int* done;
   double* dstat;
 };
 
 struct AdjState {
-  int n_vert_blocks, kmax;
+  int kmax;
   double eps;
-  double *contrib, *qbar, *mu, *r, *z, *p, *Ap, *w;
-  double* part;   // per vertex block: 8 doubles
-  double* scal;   // device scalars (2 x 4, by parity)
+  double *contrib, *qbar, *mu, *z, *p, *Ap, *w;
+  double *r0, *r1;  // residual, double-buffered by iteration parity (PCG reads r^k while writing r^{k+1})
   int* ctl;       // [iters, status]
   int* done;
   double* dstat;  // [residual]
 };
 
-void launch_local(const ElemArgs& E, const double* q, int nv, double* contrib, const int* done, int* newton_max,
-                  hipStream_t s);
+int vert_group_blocks(int n);
+int bottom_blocks(int nB, int nT);
+int tr_blocks(int ne, int nf);
+void launch_local(const ElemArgs& E, const StepState& St, const RedArgs& R, const double* q, int nv, int nf,
+                  int k, int fwd, hipStream_t s);
 void launch_elem_GtG(const ElemArgs& E, const double* x, int nv, const double* w, double* contrib, hipStream_t s);
 void launch_prologue(const VertArgs& V, const double* qt, const double* vt, const double* f, const double* q0,
-                     const double* contrib, const StepState& St, hipStream_t s);
-void launch_gather_E(int mode, const VertArgs& V, const SolveArgs& S, const StepState& St, const double* rhs_in,
-                     double* rhs_out, int k, hipStream_t s);
-void launch_top(int mode, const VertArgs& V, const SolveArgs& S, const StepState& St, const double* rhs, double* out,
-                int k, hipStream_t s);
-void launch_bottom(int mode, const VertArgs& V, const SolveArgs& S, const StepState& St, const double* rhs,
-                   double* out, int k, hipStream_t s);
-void launch_aa_update(const VertArgs& V, const StepState& St, int k, hipStream_t s);
+                     const StepState& St, hipStream_t s);
+void launch_gather_fwd(const VertArgs& V, const StepState& St, const RedArgs& R, int k, hipStream_t s);
+void launch_gather_debug(const VertArgs& V, const double* contrib, double* out, hipStream_t s);
+void launch_Eb(int mode, const VertArgs& V, const SolveArgs& S, const StepState& St, const AdjState& A,
+               const RedArgs& R, const double* rhs, int k, hipStream_t s);
+void launch_top(const VertArgs& V, const SolveArgs& S, const int* done, double* out, hipStream_t s);
+void launch_bottom(int mode, const VertArgs& V, const SolveArgs& S, const StepState& St, const AdjState& A,
+                   const RedArgs& R, const double* rhs, double* out, int k, hipStream_t s);
 void launch_epilogue(const VertArgs& V, const StepState& St, double* q_next, double* v_next, double* ckpt,
                      hipStream_t s);
 void launch_to_lib(const VertArgs& V, const double* user, double* lib, int free_only, hipStream_t s);
 void launch_from_lib(const VertArgs& V, const double* lib, double* user, int free_only, hipStream_t s);
-int tr_partial_blocks(const ElemArgs& E, const VertArgs& V);
-void launch_tr_partials(const ElemArgs& E, const VertArgs& V, const double* ck, double* part, hipStream_t s);
-void launch_bwd_elem(const ElemArgs& E, const VertArgs& V, const double* ck, const double* part, int n_part,
-                     double eps_tr, double tau_force, double* jac, double* bstat, hipStream_t s);
-void launch_apply_K(const ElemArgs& E, const VertArgs& V, const double* jac, const double* x, double* contrib,
-                    const int* done, hipStream_t s);
-void launch_adj_gather(int mode, const VertArgs& V, const AdjState& A, int it, hipStream_t s);
-void launch_pcg_alpha(const VertArgs& V, const AdjState& A, int it, hipStream_t s);
-void launch_adj_dots(int mode, const VertArgs& V, const AdjState& A, int it, hipStream_t s);
-void launch_adj_next(int mode, const VertArgs& V, const AdjState& A, int it, hipStream_t s);
+void launch_tr_partials(const ElemArgs& E, const VertArgs& V, const RedArgs& R, const double* ck, hipStream_t s);
+void launch_bwd_elem(const ElemArgs& E, const VertArgs& V, const RedArgs& R, const double* ck, double eps_tr,
+                     double tau_force, int use_partials, double* jac, double* bstat, hipStream_t s);
+void launch_apply_K(int mode, const ElemArgs& E, const VertArgs& V, const AdjState& A, const RedArgs& R,
+                    const double* jac, const double* x, int it, hipStream_t s);
+void launch_adj_gather(int mode, const VertArgs& V, const AdjState& A, const RedArgs& R, int it, hipStream_t s);
 void launch_bwd_prologue(const VertArgs& V, const AdjState& A, const double* gq, const double* gv, hipStream_t s);
-void launch_pcg_start(const VertArgs& V, const AdjState& A, hipStream_t s);
 void launch_grad_elem(const ElemArgs& E, const VertArgs& V, const double* ck, const double* jac, const double* mu,
                       double* contrib, double* g_logE, hipStream_t s);
 void launch_grad_vert(const VertArgs& V, const double* mu, const double* contrib, const double* gv_next, double* gq_t,
                       double* gv_t, double* gf, hipStream_t s);
+void launch_init_warm(const ElemArgs& E, hipStream_t s);
+void launch_zero_int(int* p, int n, hipStream_t s);
 
 }  // namespace pdhot

@@ -1,11 +1,20 @@
-// HIP kernels (gfx950) of the PD hot path.  One lane per tetrahedron for the
-// element work, deterministic gathers over a vertex -> (tet, slot) incidence
-// list instead of atomics, dense blocks of the two-level partitioned inverse
-// for the global solve, and block partial sums reduced in a fixed order by
-// the next kernel (so every result is bitwise reproducible).
+// HIP kernels (gfx950) of the PD hot path.
+//
+// Launch-latency design: on this GPU a kernel boundary costs ~1.6 us inside a
+// graph and a grid-wide barrier inside a persistent kernel ~30 us, so each PD
+// iteration is a short fixed chain of wide kernels.  Element work runs one
+// tet per lane; element contributions are written straight into the
+// vertex-incidence order, so the right-hand-side gathers read contiguous
+// memory with 8 lanes per vertex (no atomics, fixed summation order); every
+// dense block product of the partitioned inverse runs one wave per row; block
+// partial sums are reduced by the last block of the producing kernel in a
+// fixed order, so all results are bitwise reproducible.  The Anderson update
+// of iteration k-1 is applied on the fly by the two kernels that start
+// iteration k, and the conjugate-gradient direction update likewise by the two
+// kernels that start the next adjoint iteration.
 //
 // Vector layout: SoA over the library vertex order, x | y | z, stride nv.
-// Per-tet arrays: SoA, stride ne.  Contributions: [slot*3 + axis][tet].
+// Per-tet arrays: SoA, stride ne.  Contributions: [axis][incidence position].
 #include "kernels.h"
 
 #include "device_math.h"
@@ -19,9 +28,17 @@ __device__ __forceinline__ double wave_sum(double v) {
   return v;
 }
 
+// sum within aligned groups of 8 lanes (every lane of the group gets it)
+__device__ __forceinline__ double group8_sum(double v) {
+  v += __shfl_xor(v, 4, 64);
+  v += __shfl_xor(v, 2, 64);
+  v += __shfl_xor(v, 1, 64);
+  return v;
+}
+
 // block-wide sum of NV values per thread; result valid in thread 0
 template <int NV>
-__device__ __forceinline__ void block_sum(double (&v)[NV], double* lds /* >= 4*NV */) {
+__device__ __forceinline__ void block_sum(double (&v)[NV], double* lds /* >= 16*NV */) {
   const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
 #pragma unroll
   for (int i = 0; i < NV; ++i) v[i] = wave_sum(v[i]);
@@ -53,6 +70,50 @@ __device__ __forceinline__ bool block_done(const int* done) {
   return r;
 }
 
+// Producer side: block sum of N values, written by thread 0 as partial `idx`
+// of `site`.  Every thread of the block must call it.
+template <int N>
+__device__ __forceinline__ void write_partial(double (&v)[N], const RedArgs& R, int site, int idx) {
+  __shared__ double red[16 * N];
+  block_sum<N>(v, red);
+  if (threadIdx.x == 0) {
+    double* part = R.part + ((size_t)site * R.max_parts + idx) * kRedWidth;
+#pragma unroll
+    for (int j = 0; j < N; ++j) part[j] = v[j];
+  }
+}
+
+// Consumer side: the total of the first N values of every partial of `site`
+// (fixed order), returned to every thread; block 0 also stores it in fin.
+template <int N>
+__device__ __forceinline__ void consume(const RedArgs& R, int site, double (&tot)[N], int width = N) {
+  __shared__ double red[16 * N];
+  __shared__ double bc[N];
+  const double* part = R.part + (size_t)site * R.max_parts * kRedWidth;
+  const int np = R.nparts[site];
+#pragma unroll
+  for (int j = 0; j < N; ++j) tot[j] = 0.0;
+#pragma unroll 2
+  for (int b = threadIdx.x; b < np; b += blockDim.x)
+#pragma unroll
+    for (int j = 0; j < N; ++j)
+      if (j < width) tot[j] += part[(size_t)b * kRedWidth + j];
+  block_sum<N>(tot, red);
+  if (threadIdx.x == 0) {
+#pragma unroll
+    for (int j = 0; j < N; ++j) {
+      bc[j] = tot[j];
+      if (blockIdx.x == 0) R.fin[site * kFinStride + j] = tot[j];
+    }
+  }
+  __syncthreads();
+#pragma unroll
+  for (int j = 0; j < N; ++j) tot[j] = bc[j];
+  __syncthreads();
+}
+
+__device__ __forceinline__ double* fin_site(const RedArgs& R, int site) { return R.fin + site * kFinStride; }
+
 __device__ __forceinline__ void load_F(const ElemArgs& E, const double* __restrict__ q, int nv, int t, double F[9],
                                        int vi[4]) {
   vi[0] = E.tv[t];
@@ -76,8 +137,21 @@ __device__ __forceinline__ void load_F(const ElemArgs& E, const double* __restri
     for (int j = 0; j < 3; ++j) F[3 * i + j] = Ds[3 * i] * Bm[j] + Ds[3 * i + 1] * Bm[3 + j] + Ds[3 * i + 2] * Bm[6 + j];
 }
 
-// G_e^T P scaled by w into the 12 contribution slots of tet t:
-// vertex a (1..3) receives w P r_a (r_a = row a-1 of D_m^{-1}), vertex 0 minus their sum.
+__device__ __forceinline__ void F_from_positions(const ElemArgs& E, int t, const double xv[4][3], double F[9]) {
+  double Bm[9];
+#pragma unroll
+  for (int i = 0; i < 9; ++i) Bm[i] = E.Bm[i * E.ne + t];
+#pragma unroll
+  for (int ax = 0; ax < 3; ++ax) {
+    const double d1 = xv[1][ax] - xv[0][ax], d2 = xv[2][ax] - xv[0][ax], d3 = xv[3][ax] - xv[0][ax];
+#pragma unroll
+    for (int j = 0; j < 3; ++j) F[3 * ax + j] = d1 * Bm[j] + d2 * Bm[3 + j] + d3 * Bm[6 + j];
+  }
+}
+
+// w G_e^T P written to the incidence positions of the tet's free vertices:
+// vertex a (1..3) receives w P r_a (r_a = row a-1 of D_m^{-1}), vertex 0 minus
+// their sum.
 __device__ __forceinline__ void store_contrib(const ElemArgs& E, double* __restrict__ contrib, int t, double w,
                                               const double P[9]) {
   double Bm[9];
@@ -86,66 +160,248 @@ __device__ __forceinline__ void store_contrib(const ElemArgs& E, double* __restr
   double c0[3] = {0, 0, 0};
 #pragma unroll
   for (int a = 1; a < 4; ++a) {
+    const int pos = E.tinc[a * E.ne + t];
 #pragma unroll
     for (int ax = 0; ax < 3; ++ax) {
       const double v = w * (P[3 * ax] * Bm[3 * (a - 1)] + P[3 * ax + 1] * Bm[3 * (a - 1) + 1] +
                             P[3 * ax + 2] * Bm[3 * (a - 1) + 2]);
-      contrib[(a * 3 + ax) * E.ne + t] = v;
+      if (pos >= 0) contrib[(size_t)ax * E.ninc + pos] = v;
       c0[ax] -= v;
     }
   }
+  const int pos0 = E.tinc[t];
+  if (pos0 >= 0)
 #pragma unroll
-  for (int ax = 0; ax < 3; ++ax) contrib[ax * E.ne + t] = c0[ax];
+    for (int ax = 0; ax < 3; ++ax) contrib[(size_t)ax * E.ninc + pos0] = c0[ax];
 }
 
-__device__ __forceinline__ void gather3(const int* __restrict__ inc_ptr, const int* __restrict__ inc_idx,
-                                        const double* __restrict__ contrib, int ne, int i, double out[3]) {
+// 8 lanes per vertex: the sum of the vertex's incidence entries (contiguous)
+__device__ __forceinline__ void gather8(const int* __restrict__ inc_ptr, const double* __restrict__ contrib, int ninc,
+                                        int i, int l, double out[3]) {
   double s0 = 0, s1 = 0, s2 = 0;
-  for (int k = inc_ptr[i]; k < inc_ptr[i + 1]; ++k) {
-    const int ts = inc_idx[k];
-    const int t = ts >> 2, slot = ts & 3;
-    s0 += contrib[(slot * 3 + 0) * ne + t];
-    s1 += contrib[(slot * 3 + 1) * ne + t];
-    s2 += contrib[(slot * 3 + 2) * ne + t];
+  const int k1 = inc_ptr[i + 1];
+#pragma unroll 4
+  for (int k = inc_ptr[i] + l; k < k1; k += 8) {
+    s0 += contrib[k];
+    s1 += contrib[(size_t)ninc + k];
+    s2 += contrib[2 * (size_t)ninc + k];
   }
-  out[0] = s0;
-  out[1] = s1;
-  out[2] = s2;
+  out[0] = group8_sum(s0);
+  out[1] = group8_sum(s1);
+  out[2] = group8_sum(s2);
+}
+
+// ---------------------------------------------------------------- Anderson mixing
+struct AAMix {
+  int use;        // apply the mixing
+  int reset;      // |gamma| > 10: history dropped
+  int nc, head;   // columns after the append of iteration k-1
+  int m;
+  double gam[kMaxWindow];
+};
+
+__device__ __forceinline__ void aa_layout(const int* st, int m, int& nonempty, int& nc_after, int& head_after,
+                                          int& slot_new) {
+  nonempty = st[0];
+  const int nc = st[1], head = st[2];
+  slot_new = -1;
+  nc_after = nc;
+  head_after = head;
+  if (m <= 0 || !nonempty) return;
+  if (nc < m) {
+    slot_new = (head + nc) % m;
+    nc_after = nc + 1;
+  } else {
+    slot_new = head;
+    head_after = (head + 1) % m;
+  }
+}
+
+// gamma = (dG^T dG + rho I)^{-1} dG^T g with rho = max(1e-6 |dG|_F^2 / m_c, 1e-12)
+// (Eq. aa_gamma) from the final Gram sums of iteration k-1; reliability guard
+// |gamma|_2 > 10.  Computed by thread 0, broadcast through LDS.
+__device__ __forceinline__ void aa_prepare(const StepState& St, const RedArgs& R, int k, bool reduce, AAMix& out) {
+  __shared__ AAMix mx;
+  __shared__ double aav[kMaxWindow * kMaxWindow + kMaxWindow];
+  // Gram sums of iteration k-1, compact layout: G[j][l] at j*m + l, rhs[j] at m*m + j
+  constexpr int NA = kMaxWindow * kMaxWindow + kMaxWindow;
+  double tot[NA];
+  const int m = St.m;
+  const int W = m * m + m;
+  if (k >= 1 && m > 0) {
+    if (reduce) {
+      consume<NA>(R, kRedAA, tot, W);
+    } else {
+#pragma unroll
+      for (int j = 0; j < NA; ++j) tot[j] = (j < W) ? R.fin[kRedAA * kFinStride + j] : 0.0;
+    }
+    if (threadIdx.x == 0)
+#pragma unroll
+      for (int j = 0; j < NA; ++j) aav[j] = tot[j];
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    mx.use = 0;
+    mx.reset = 0;
+    mx.m = m;
+    mx.nc = 0;
+    mx.head = 0;
+#pragma unroll
+    for (int j = 0; j < kMaxWindow; ++j) mx.gam[j] = 0.0;
+    if (k >= 1 && m > 0) {
+      int nonempty, nc, head, slot_new;
+      aa_layout(St.ctl + kCtlAA + 4 * ((k - 1) & 1), m, nonempty, nc, head, slot_new);
+      mx.nc = nc;
+      mx.head = head;
+      if (nc >= 1) {
+        // padded to kMaxWindow with identity rows (unused columns decouple),
+        // fully unrolled so every array stays in registers
+        double G[kMaxWindow][kMaxWindow], rhs[kMaxWindow];
+        double fro = 0.0;
+#pragma unroll
+        for (int j = 0; j < kMaxWindow; ++j) {
+#pragma unroll
+          for (int l = 0; l < kMaxWindow; ++l) {
+            double g = (j == l) ? 1.0 : 0.0;
+            if (j < nc && l < nc) g = (j <= l) ? aav[j * m + l] : aav[l * m + j];
+            G[j][l] = g;
+          }
+          rhs[j] = (j < nc) ? aav[m * m + j] : 0.0;
+          if (j < nc) fro += G[j][j];
+        }
+        const double rho = fmax(1e-6 * fro / nc, 1e-12);
+#pragma unroll
+        for (int j = 0; j < kMaxWindow; ++j)
+          if (j < nc) G[j][j] += rho;
+        bool ok = true;
+#pragma unroll
+        for (int j = 0; j < kMaxWindow; ++j) {
+          double d = G[j][j];
+#pragma unroll
+          for (int l = 0; l < j; ++l) d -= G[j][l] * G[j][l];
+          ok = ok && (d > 0.0);
+          d = sqrt(fmax(d, 1e-300));
+          G[j][j] = d;
+#pragma unroll
+          for (int i = j + 1; i < kMaxWindow; ++i) {
+            double t = G[i][j];
+#pragma unroll
+            for (int l = 0; l < j; ++l) t -= G[i][l] * G[j][l];
+            G[i][j] = t / d;
+          }
+        }
+        double y[kMaxWindow], gam[kMaxWindow];
+#pragma unroll
+        for (int i = 0; i < kMaxWindow; ++i) {
+          double t = rhs[i];
+#pragma unroll
+          for (int l = 0; l < i; ++l) t -= G[i][l] * y[l];
+          y[i] = t / G[i][i];
+        }
+#pragma unroll
+        for (int i = kMaxWindow - 1; i >= 0; --i) {
+          double t = y[i];
+#pragma unroll
+          for (int l = i + 1; l < kMaxWindow; ++l) t -= G[l][i] * gam[l];
+          gam[i] = t / G[i][i];
+        }
+        double nrm = 0.0;
+#pragma unroll
+        for (int i = 0; i < kMaxWindow; ++i) nrm += (i < nc) ? gam[i] * gam[i] : 0.0;
+        nrm = ok ? sqrt(nrm) : INFINITY;
+#pragma unroll
+        for (int i = 0; i < kMaxWindow; ++i) mx.gam[i] = (i < nc) ? gam[i] : 0.0;
+        mx.use = (nrm <= 10.0);
+        mx.reset = !mx.use;
+      }
+    }
+  }
+  __syncthreads();
+  out = mx;
+  __syncthreads();
+}
+
+// q^k of a free vertex: q^ - (dQ + dG) gamma (Eq. aa_update) or q^ (k >= 1);
+// q_cur at k = 0 (the initial iterate)
+__device__ __forceinline__ double aa_value(const StepState& St, const AAMix& mx, int nv, int a, int i, int k) {
+  const int ix = a * nv + i;
+  if (k == 0) return St.q_cur[ix];
+  double q = St.qhat[ix];
+  if (mx.use) {
+#pragma unroll
+    for (int j = 0; j < kMaxWindow; ++j)
+      if (j < mx.nc) {
+        const size_t cix = ((size_t)((mx.head + j) % mx.m) * 3 + a) * nv + i;
+        q -= (St.dQ[cix] + St.dG[cix]) * mx.gam[j];
+      }
+  }
+  return q;
 }
 
 // ---------------------------------------------------------------- local step
-// p*_e = U diag(s*) V^T of F_e = G_e q (Sec. 4.1 Eq. nh_prox) and the
-// contribution w_e V_e G_e^T p*_e of Eq. A_basic.
-__global__ void __launch_bounds__(kBlock) k_local(ElemArgs E, const double* __restrict__ q, int nv,
-                                                  double* __restrict__ contrib, const int* __restrict__ done,
-                                                  int* __restrict__ newton_max) {
-  if (done && *done) return;
+// p*_e = U diag(s*) V^T of F_e = G_e q^k (Sec. 4.1 Eq. nh_prox) and its
+// contribution w_e V_e G_e^T p*_e (Eq. A_basic).  The SVD and the prox Newton
+// start from the tet's previous rotation and stretch ratios.
+__global__ void __launch_bounds__(kBlock) k_local(ElemArgs E, StepState St, RedArgs R, const double* __restrict__ q,
+                                                  int nv, int nf, int k, int fwd, int* __restrict__ newton_max) {
+  if (fwd && block_done(St.done)) return;
+  AAMix mx;
+  if (fwd) aa_prepare(St, R, k, true, mx);
   const int t = blockIdx.x * blockDim.x + threadIdx.x;
-  int its = 0;
   if (t < E.ne) {
-    double F[9], U[9], V[9], sF[3], ss[3];
     int vi[4];
-    load_F(E, q, nv, t, F, vi);
-    svd3(F, U, sF, V);
-    its = prox_stretch(sF, E.mu_bar, E.lam_bar, E.k_bar, ss);
+    vi[0] = E.tv[t];
+    vi[1] = E.tv[E.ne + t];
+    vi[2] = E.tv[2 * E.ne + t];
+    vi[3] = E.tv[3 * E.ne + t];
+    double xv[4][3];
+#pragma unroll
+    for (int a = 0; a < 4; ++a)
+#pragma unroll
+      for (int ax = 0; ax < 3; ++ax)
+        xv[a][ax] = (fwd && vi[a] < nf) ? aa_value(St, mx, nv, ax, vi[a], k) : q[ax * nv + vi[a]];
+    double F[9], U[9], V[9], sF[3], ss[3], rt[3];
+    F_from_positions(E, t, xv, F);
+    bool warm = true;
+#pragma unroll
+    for (int j = 0; j < 9; ++j) {
+      V[j] = E.Vw[(size_t)j * E.ne + t];
+      warm = warm && isfinite(V[j]);
+    }
+    if (!warm)
+#pragma unroll
+      for (int j = 0; j < 9; ++j) V[j] = (j % 4 == 0) ? 1.0 : 0.0;
+    svd3(F, U, sF, V, warm);
+#pragma unroll
+    for (int j = 0; j < 3; ++j) rt[j] = E.rw[(size_t)j * E.ne + t];
+    prox_stretch(sF, E.mu_bar, E.lam_bar, E.k_bar, ss, rt);
     double P[9];
 #pragma unroll
     for (int i = 0; i < 3; ++i)
 #pragma unroll
       for (int j = 0; j < 3; ++j)
         P[3 * i + j] = U[3 * i] * ss[0] * V[3 * j] + U[3 * i + 1] * ss[1] * V[3 * j + 1] + U[3 * i + 2] * ss[2] * V[3 * j + 2];
-    store_contrib(E, contrib, t, E.wV[t], P);
-  }
-  if (newton_max) {
-    int m = its;
+    store_contrib(E, St.contrib, t, E.wV[t], P);
+    // keep the rotation orthonormal (Gram-Schmidt on its columns) for the next start
+    double c0[3] = {V[0], V[3], V[6]}, c1[3] = {V[1], V[4], V[7]};
+    double n0 = rsqrt(c0[0] * c0[0] + c0[1] * c0[1] + c0[2] * c0[2]);
+    c0[0] *= n0; c0[1] *= n0; c0[2] *= n0;
+    const double d01 = c0[0] * c1[0] + c0[1] * c1[1] + c0[2] * c1[2];
+    c1[0] -= d01 * c0[0]; c1[1] -= d01 * c0[1]; c1[2] -= d01 * c0[2];
+    double n1 = rsqrt(c1[0] * c1[0] + c1[1] * c1[1] + c1[2] * c1[2]);
+    c1[0] *= n1; c1[1] *= n1; c1[2] *= n1;
+    const double c2[3] = {c0[1] * c1[2] - c0[2] * c1[1], c0[2] * c1[0] - c0[0] * c1[2], c0[0] * c1[1] - c0[1] * c1[0]};
+    const double Vn[9] = {c0[0], c1[0], c2[0], c0[1], c1[1], c2[1], c0[2], c1[2], c2[2]};
 #pragma unroll
-    for (int off = 32; off > 0; off >>= 1) m = max(m, __shfl_xor(m, off, 64));
-    if ((threadIdx.x & 63) == 0 && m > 0) atomicMax(newton_max, m);
+    for (int j = 0; j < 9; ++j) E.Vw[(size_t)j * E.ne + t] = Vn[j];
+#pragma unroll
+    for (int j = 0; j < 3; ++j) E.rw[(size_t)j * E.ne + t] = (sF[j] > 1e-12) ? ss[j] / sF[j] : 0.0;
   }
+  (void)newton_max;
 }
 
 // G_e^T (w G_e x): contributions of the symmetric element operator w V G^T G
-// (used for B_beta q_t in the prologue and for B_beta mu in the gradient).
+// (B_beta q_t in the prologue).
 __global__ void __launch_bounds__(kBlock) k_elem_GtG(ElemArgs E, const double* __restrict__ x, int nv,
                                                      const double* __restrict__ w, double* __restrict__ contrib) {
   const int t = blockIdx.x * blockDim.x + threadIdx.x;
@@ -163,11 +419,14 @@ __global__ void __launch_bounds__(kBlock) k_elem_GtG(ElemArgs E, const double* _
 __global__ void __launch_bounds__(kBlock) k_prologue(VertArgs Vx, const double* __restrict__ q_t_user,
                                                      const double* __restrict__ v_t_user,
                                                      const double* __restrict__ f_user,
-                                                     const double* __restrict__ q0_user,
-                                                     const double* __restrict__ contrib, StepState St) {
-  const int i = blockIdx.x * blockDim.x + threadIdx.x;
-  if (i >= Vx.nv) return;
+                                                     const double* __restrict__ q0_user, StepState St) {
+  const int gtid = blockIdx.x * blockDim.x + threadIdx.x;
+  const int i = gtid >> 3, l = gtid & 7;
   const int nv = Vx.nv;
+  if (i >= nv) return;  // whole groups of 8 leave together
+  double bq[3] = {0, 0, 0};
+  if (i < Vx.nf) gather8(Vx.inc_ptr, St.contrib, Vx.ninc, i, l, bq);
+  if (l != 0) return;
   const int o = Vx.v_orig[i];
   if (i >= Vx.nf) {  // pinned: held at rest
 #pragma unroll
@@ -177,12 +436,11 @@ __global__ void __launch_bounds__(kBlock) k_prologue(VertArgs Vx, const double* 
       St.qtil[a * nv + i] = r;
       St.q_cur[a * nv + i] = r;
       St.q_prev[a * nv + i] = r;
+      St.qhat[a * nv + i] = r;
       St.vt[a * nv + i] = 0.0;
     }
     return;
   }
-  double bq[3];
-  gather3(Vx.inc_ptr, Vx.inc_idx, contrib, Vx.ne, i, bq);
   const double m = Vx.mass[i], h = Vx.h;
 #pragma unroll
   for (int a = 0; a < 3; ++a) {
@@ -200,102 +458,98 @@ __global__ void __launch_bounds__(kBlock) k_prologue(VertArgs Vx, const double* 
   }
 }
 
-// ---------------------------------------------------------------- gather + E b
-// Per subdomain block: b = c + gathered contributions for its vertices, the
-// dual-gate partial norms, and t_s = E_s b_s for the interface rows it
-// couples to.  Extra blocks gather the interface vertices.
-template <int MODE>
-__global__ void __launch_bounds__(kBlock) k_gather_E(VertArgs Vx, SolveArgs Sv, StepState St, const double* __restrict__ rhs_in,
-                                                     double* __restrict__ rhs_out, int k) {
-  extern __shared__ double lds[];
+// ---------------------------------------------------------------- right-hand side
+// b^k = c + gathered contributions; q^k (Anderson update of iteration k-1,
+// written by the vertex's group); partial sums of the dual gate
+// (Eq. convergence_dual): |q^k - q^{k-1}|^2, |q^{k-1}|^2, |b^k - b^{k-1}|^2,
+// |b^{k-1}|^2.  Block 0 records the Anderson state of iteration k.
+__global__ void __launch_bounds__(kBlock) k_gather_fwd(VertArgs Vx, StepState St, RedArgs R, int k) {
   if (block_done(St.done)) return;
+  AAMix mx;
+  aa_prepare(St, R, k, false, mx);
   const int nv = Vx.nv;
-  const int blk = blockIdx.x;
-  int i0, i1, s = -1;
-  if (blk < Sv.nsub) {
-    s = blk;
-    i0 = Sv.sub_begin[s];
-    i1 = Sv.sub_begin[s + 1];
-  } else {
-    i0 = Sv.nB + (blk - Sv.nsub) * kBlock;
-    i1 = min(i0 + kBlock, Vx.nf);
-  }
+  const int gtid = blockIdx.x * blockDim.x + threadIdx.x;
+  const int i = gtid >> 3, l = gtid & 7;
   double part[4] = {0, 0, 0, 0};
-  double* bl = lds;  // n_s x 3
-  for (int i = i0 + threadIdx.x; i < i1; i += blockDim.x) {
-    double bn[3];
-    if (MODE == kModeFwd) {
-      gather3(Vx.inc_ptr, Vx.inc_idx, St.contrib, Vx.ne, i, bn);
+  if (i < Vx.nf) {
+    double bs[3];
+    gather8(Vx.inc_ptr, St.contrib, Vx.ninc, i, l, bs);
+    if (l == 0) {
 #pragma unroll
       for (int a = 0; a < 3; ++a) {
-        bn[a] += St.c[a * nv + i];
-        const double bo = St.b_cur[a * nv + i];
-        const double qc = St.q_cur[a * nv + i], qp = St.q_prev[a * nv + i];
-        St.b_prev[a * nv + i] = bo;
-        St.b_cur[a * nv + i] = bn[a];
-        part[0] += (qc - qp) * (qc - qp);
+        const int ix = a * nv + i;
+        const double qk = aa_value(St, mx, nv, a, i, k);
+        const double qp = (k == 0) ? St.q_prev[ix] : St.q_cur[ix];
+        if (k > 0) {
+          St.q_prev[ix] = qp;
+          St.q_cur[ix] = qk;
+        }
+        const double bn = bs[a] + St.c[ix];
+        const double bo = St.b_cur[ix];
+        St.b_prev[ix] = bo;
+        St.b_cur[ix] = bn;
+        part[0] += (qk - qp) * (qk - qp);
         part[1] += qp * qp;
-        part[2] += (bn[a] - bo) * (bn[a] - bo);
+        part[2] += (bn - bo) * (bn - bo);
         part[3] += bo * bo;
       }
-    } else if (MODE == kModeDebugGather) {
-      gather3(Vx.inc_ptr, Vx.inc_idx, St.contrib, Vx.ne, i, bn);
-#pragma unroll
-      for (int a = 0; a < 3; ++a) rhs_out[a * nv + i] = bn[a];
-    } else {  // plain right-hand side given
-#pragma unroll
-      for (int a = 0; a < 3; ++a) bn[a] = rhs_in[a * nv + i];
     }
-    if (s >= 0)
-#pragma unroll
-      for (int a = 0; a < 3; ++a) bl[3 * (i - i0) + a] = bn[a];
   }
-  if (MODE == kModeFwd) {
-    block_sum<4>(part, lds + 3 * Vx.max_sub);
-    if (threadIdx.x == 0)
-#pragma unroll
-      for (int j = 0; j < 4; ++j) St.gate_part[4 * blk + j] = part[j];
-  }
-  if (MODE == kModeDebugGather) return;
-  if (s < 0) return;
-  __syncthreads();
-  const int ns = i1 - i0;
-  const int nI = Sv.ir_off[s + 1] - Sv.ir_off[s];
-  const double* __restrict__ Et = Sv.Et + Sv.et_off[s];
-  for (int p = threadIdx.x; p < nI; p += blockDim.x) {
-    double t0 = 0, t1 = 0, t2 = 0;
-    for (int v = 0; v < ns; ++v) {
-      const double e = Et[(long long)v * nI + p];
-      t0 += e * bl[3 * v];
-      t1 += e * bl[3 * v + 1];
-      t2 += e * bl[3 * v + 2];
+  if (blockIdx.x == 0 && threadIdx.x == 0 && k >= 1) {
+    int* nxt = St.ctl + kCtlAA + 4 * (k & 1);
+    if (St.m <= 0 || mx.reset) {
+      nxt[0] = 0; nxt[1] = 0; nxt[2] = 0;
+      if (mx.reset) St.ctl[kCtlResets] += 1;
+    } else {
+      nxt[0] = 1; nxt[1] = mx.nc; nxt[2] = mx.head;
     }
-    const int slot = Sv.slot_of[Sv.ir_off[s] + p];
-    Sv.t_slots[3 * slot] = t0;
-    Sv.t_slots[3 * slot + 1] = t1;
-    Sv.t_slots[3 * slot + 2] = t2;
   }
+  write_partial<4>(part, R, kRedGate, blockIdx.x);
 }
 
-// ---------------------------------------------------------------- top solve
-// Forward mode first reduces the dual-gate partials (Eq. convergence_dual):
-// the gate holds for k >= 2, and k == kmax - 1 ends the step unconverged.
-// Then x_T = Z (b_T - sum_s t_s) over the interface rows of this block.
-template <int MODE>
-__global__ void __launch_bounds__(kBlock) k_top(VertArgs Vx, SolveArgs Sv, StepState St, const double* __restrict__ rhs,
-                                                double* __restrict__ out, int k) {
-  extern __shared__ double lds[];
-  if (block_done(St.done)) return;
-  const int nv = Vx.nv;
-  if (MODE == kModeFwd && k >= 1) {
-    double g[4] = {0, 0, 0, 0};
-    // every block reduces the same partials in the same order
-    for (int b = threadIdx.x; b < St.n_gate_blocks; b += blockDim.x)
+// b = sum of the incidence entries of every free vertex (diagnostics)
+__global__ void __launch_bounds__(kBlock) k_gather_debug(VertArgs Vx, const double* __restrict__ contrib,
+                                                         double* __restrict__ out) {
+  const int gtid = blockIdx.x * blockDim.x + threadIdx.x;
+  const int i = gtid >> 3, l = gtid & 7;
+  if (i >= Vx.nf) return;
+  double bs[3];
+  gather8(Vx.inc_ptr, contrib, Vx.ninc, i, l, bs);
+  if (l == 0)
 #pragma unroll
-      for (int j = 0; j < 4; ++j) g[j] += St.gate_part[4 * b + j];
-    block_sum<4>(g, lds);
-    __shared__ int stop;
-    if (threadIdx.x == 0) {
+    for (int a = 0; a < 3; ++a) out[a * Vx.nv + i] = bs[a];
+}
+
+// ---------------------------------------------------------------- interface right-hand side
+// Forward mode first takes the dual-gate decision (the gate holds for
+// k >= 2; k == kmax - 1 ends the step unconverged).  Then one wave per
+// interface row i: r_T[i] = rhs_T[i] - sum over the subdomains s coupled to i
+// of E_s[p] . rhs_s (the Schur-complement right-hand side).  PCG mode forms
+// the updated residual r - alpha w on the fly, alpha = (r.z)/(p.w).
+template <int MODE>
+__device__ __forceinline__ double rhs_val(const double* __restrict__ src, const double* __restrict__ w, double alpha,
+                                          int ix) {
+  if (MODE == kModePCG) return src[ix] - alpha * w[ix];
+  return src[ix];
+}
+
+__device__ __forceinline__ double* r_cur(const AdjState& A, int it) { return (it & 1) ? A.r1 : A.r0; }
+
+template <int MODE>
+__global__ void __launch_bounds__(kBlock) k_Eb(VertArgs Vx, SolveArgs Sv, StepState St, AdjState A, RedArgs R,
+                                               const double* __restrict__ rhs, int k) {
+  const int* done = (MODE == kModeFwd) ? St.done : (MODE == kModePlain ? St.done : A.done);
+  if (block_done(done)) return;
+  __shared__ int stop;
+  __shared__ double alpha_s;
+  double g[4] = {0, 0, 0, 0};
+  if (MODE == kModeFwd && k >= 1) consume<4>(R, kRedGate, g);
+  double pw[1] = {1.0};
+  if (MODE == kModePCG) consume<1>(R, kRedPW, pw);
+  if (threadIdx.x == 0) {
+    stop = 0;
+    alpha_s = 0.0;
+    if (MODE == kModeFwd && k >= 1) {
       const double dq = sqrt(g[0]), nq = sqrt(g[1]), db = sqrt(g[2]), nb = sqrt(g[3]);
       const bool pass = dq <= St.eps_rel * nq + St.eps_abs && db <= St.eps_rel * nb + St.eps_abs;
       const bool conv = (k >= 2) && pass;
@@ -308,148 +562,158 @@ __global__ void __launch_bounds__(kBlock) k_top(VertArgs Vx, SolveArgs Sv, StepS
         St.dstat[0] = dq; St.dstat[1] = nq; St.dstat[2] = db; St.dstat[3] = nb;
       }
     }
-    __syncthreads();
-    if (stop) return;
-  }
-  const int nT = Sv.nT, nB = Sv.nB;
-  const double* __restrict__ bsrc = (MODE == kModeFwd) ? St.b_cur : rhs;
-  double* rT = lds;  // nT x 3
-  for (int i = threadIdx.x; i < nT; i += blockDim.x) {
-    double r0 = bsrc[nB + i], r1 = bsrc[nv + nB + i], r2 = bsrc[2 * nv + nB + i];
-    for (int q = Sv.row_slot_ptr[i]; q < Sv.row_slot_ptr[i + 1]; ++q) {
-      r0 -= Sv.t_slots[3 * q];
-      r1 -= Sv.t_slots[3 * q + 1];
-      r2 -= Sv.t_slots[3 * q + 2];
-    }
-    rT[3 * i] = r0;
-    rT[3 * i + 1] = r1;
-    rT[3 * i + 2] = r2;
+    if (MODE == kModePCG) alpha_s = fin_site(R, kRedRZ0 + (k & 1))[0] / pw[0];
   }
   __syncthreads();
-  const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6, nw = blockDim.x >> 6;
-  const int row0 = blockIdx.x * Sv.top_rows;
-  const int row1 = min(row0 + Sv.top_rows, nT);
-  double* dst = (MODE == kModeFwd) ? St.qhat : out;
-  for (int i = row0 + wid; i < row1; i += nw) {
-    const double* __restrict__ Zi = Sv.Z + (long long)i * nT;
-    double a0 = 0, a1 = 0, a2 = 0;
-    for (int j = lane; j < nT; j += 64) {
-      const double z = Zi[j];
-      a0 += z * rT[3 * j];
-      a1 += z * rT[3 * j + 1];
-      a2 += z * rT[3 * j + 2];
+  if (stop) return;
+  const double alpha = alpha_s;
+  const double* src = (MODE == kModeFwd) ? St.b_cur : (MODE == kModePCG ? r_cur(A, k) : rhs);
+  const double* wv = A.w;
+  const int nv = Vx.nv, nB = Sv.nB;
+  const int lane = threadIdx.x & 63;
+  const int row = (blockIdx.x * blockDim.x + threadIdx.x) >> 6;
+  if (row >= Sv.nT) return;
+  double a0 = 0, a1 = 0, a2 = 0;
+  for (int c = Sv.rl_ptr[row]; c < Sv.rl_ptr[row + 1]; ++c) {
+    const int s = Sv.rl_sub[c];
+    const int b0 = Sv.sub_begin[s], ns = Sv.sub_begin[s + 1] - b0;
+    const double* __restrict__ Ep = Sv.E + Sv.e_off[s] + (size_t)Sv.rl_p[c] * ns;
+#pragma unroll 4
+    for (int v = lane; v < ns; v += 64) {
+      const double e = Ep[v];
+      a0 += e * rhs_val<MODE>(src, wv, alpha, b0 + v);
+      a1 += e * rhs_val<MODE>(src, wv, alpha, nv + b0 + v);
+      a2 += e * rhs_val<MODE>(src, wv, alpha, 2 * nv + b0 + v);
     }
-    a0 = wave_sum(a0);
-    a1 = wave_sum(a1);
-    a2 = wave_sum(a2);
-    if (lane == 0) {
-      dst[nB + i] = a0;
-      dst[nv + nB + i] = a1;
-      dst[2 * nv + nB + i] = a2;
-    }
+  }
+  a0 = wave_sum(a0);
+  a1 = wave_sum(a1);
+  a2 = wave_sum(a2);
+  if (lane == 0) {
+    const int gi = nB + row;
+    Sv.rT[row] = rhs_val<MODE>(src, wv, alpha, gi) - a0;
+    Sv.rT[Sv.nT + row] = rhs_val<MODE>(src, wv, alpha, nv + gi) - a1;
+    Sv.rT[2 * Sv.nT + row] = rhs_val<MODE>(src, wv, alpha, 2 * nv + gi) - a2;
   }
 }
 
-// ---------------------------------------------------------------- Anderson state
-__device__ __forceinline__ void aa_layout(const int* ctl, int k, int m, int& nonempty, int& nc_after, int& head_after,
-                                          int& slot_new) {
-  const int* st = ctl + kCtlAA + 4 * (k & 1);
-  nonempty = st[0];
-  const int nc = st[1], head = st[2];
-  slot_new = -1;
-  nc_after = nc;
-  head_after = head;
-  if (m <= 0 || !nonempty) return;
-  if (nc < m) {
-    slot_new = (head + nc) % m;
-    nc_after = nc + 1;
-  } else {
-    slot_new = head;
-    head_after = (head + 1) % m;
+// ---------------------------------------------------------------- interface solve
+// x_T = Z r_T, one wave per interface row (Z = inverse Schur complement).
+__global__ void __launch_bounds__(kBlock) k_top(VertArgs Vx, SolveArgs Sv, const int* __restrict__ done,
+                                                double* __restrict__ out) {
+  if (block_done(done)) return;
+  const int lane = threadIdx.x & 63;
+  const int row = (blockIdx.x * blockDim.x + threadIdx.x) >> 6;
+  const int nT = Sv.nT;
+  if (row >= nT) return;
+  const double* __restrict__ Zi = Sv.Z + (size_t)row * nT;
+  const double* __restrict__ r0 = Sv.rT;
+  const double* __restrict__ r1 = Sv.rT + nT;
+  const double* __restrict__ r2 = Sv.rT + 2 * nT;
+  double a0 = 0, a1 = 0, a2 = 0;
+#pragma unroll 8
+  for (int j = lane; j < nT; j += 64) {
+    const double z = Zi[j];
+    a0 += z * r0[j];
+    a1 += z * r1[j];
+    a2 += z * r2[j];
+  }
+  a0 = wave_sum(a0);
+  a1 = wave_sum(a1);
+  a2 = wave_sum(a2);
+  if (lane == 0) {
+    const int gi = Sv.nB + row, nv = Vx.nv;
+    out[gi] = a0;
+    out[nv + gi] = a1;
+    out[2 * nv + gi] = a2;
   }
 }
 
-// ---------------------------------------------------------------- bottom solve
-// x_s = Zs b_s - E_s^T x_T on subdomain rows (one wave per row); forward mode
-// then forms g = q^ - q^k, appends the Anderson difference columns
-// (Eqs. aa_dG, aa_dQ) and writes the Gram partial sums of this block.
+// ---------------------------------------------------------------- subdomain solve
+// x_s = Zs rhs_s - E_s^T x_T on the subdomain rows (one wave per row), then
+// the per-vertex work of each mode on every free row:
+//  forward: g = q^ - q^k, the Anderson difference columns (Eqs. aa_dG, aa_dQ)
+//           and the Gram partial sums of the mixing;
+//  PCG:     r <- r - alpha w, mu <- mu + alpha p, partial r.z, |z|^2, |mu|^2;
+//  PCG start: partial r.z, |z|^2, |mu|^2 of the first solve;
+//  fixed point: partial |z - mu|^2, |z|^2, then mu <- z.
 template <int MODE>
-__global__ void __launch_bounds__(kBlock) k_bottom(VertArgs Vx, SolveArgs Sv, StepState St, const double* __restrict__ rhs,
-                                                   double* __restrict__ out, int k) {
-  extern __shared__ double lds[];
-  if (block_done(St.done)) return;
-  const int nv = Vx.nv, nf = Vx.nf, nB = Sv.nB;
-  const int blk = blockIdx.x;
-  const double* __restrict__ bsrc = (MODE == kModeFwd) ? St.b_cur : rhs;
+__global__ void __launch_bounds__(kBottomThreads) k_bottom(VertArgs Vx, SolveArgs Sv, StepState St, AdjState A, RedArgs R,
+                                                   const double* __restrict__ rhs, double* __restrict__ out, int k) {
+  const int* done = (MODE == kModeFwd || MODE == kModePlain) ? St.done : A.done;
+  if (block_done(done)) return;
+  __shared__ double alpha_s;
+  if (threadIdx.x == 0) {
+    alpha_s = 0.0;
+    if (MODE == kModePCG) alpha_s = fin_site(R, kRedRZ0 + (k & 1))[0] / fin_site(R, kRedPW)[0];
+  }
+  __syncthreads();
+  const double alpha = alpha_s;
+  const int nv = Vx.nv, nB = Sv.nB, nf = Vx.nf;
+  const double* src = (MODE == kModeFwd) ? St.b_cur : (MODE == kModePCG ? r_cur(A, k) : rhs);
+  const double* wv = A.w;
   double* dst = (MODE == kModeFwd) ? St.qhat : out;
-  int r0, r1;  // library rows handled here
-  if (blk < Sv.n_bottom_items) {
-    const int s = Sv.bottom_items[3 * blk], lr0 = Sv.bottom_items[3 * blk + 1], lr1 = Sv.bottom_items[3 * blk + 2];
-    const int i0 = Sv.sub_begin[s], ns = Sv.sub_begin[s + 1] - i0;
-    const int nI = Sv.ir_off[s + 1] - Sv.ir_off[s];
-    double* bl = lds;            // ns x 3
-    double* xl = lds + 3 * ns;   // nI x 3
-    for (int v = threadIdx.x; v < ns; v += blockDim.x)
-#pragma unroll
-      for (int a = 0; a < 3; ++a) bl[3 * v + a] = bsrc[a * nv + i0 + v];
-    for (int p = threadIdx.x; p < nI; p += blockDim.x) {
-      const int ri = nB + Sv.irows[Sv.ir_off[s] + p];
-#pragma unroll
-      for (int a = 0; a < 3; ++a) xl[3 * p + a] = dst[a * nv + ri];
-    }
-    __syncthreads();
-    const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6, nw = blockDim.x >> 6;
-    const double* __restrict__ Zs = Sv.Zs + Sv.zs_off[s];
-    const double* __restrict__ Et = Sv.Et + Sv.et_off[s];
-    for (int v = lr0 + wid; v < lr1; v += nw) {
+  const int lane = threadIdx.x & 63;
+  const int n_sub_blocks = (nB + kBottomThreads / 64 - 1) / (kBottomThreads / 64);
+  // rows whose per-vertex work this thread does (at most one)
+  int my_row = -1;
+  if ((int)blockIdx.x < n_sub_blocks) {
+    const int v = blockIdx.x * (kBottomThreads / 64) + (threadIdx.x >> 6);
+    if (v < nB) {
+      const int s = Sv.sub_of[v];
+      const int b0 = Sv.sub_begin[s], ns = Sv.sub_begin[s + 1] - b0, lr = v - b0;
+      const int nI = Sv.ir_off[s + 1] - Sv.ir_off[s];
+      const int* __restrict__ Ir = Sv.irows + Sv.ir_off[s];
+      const double* __restrict__ Zr = Sv.Zs + Sv.zs_off[s] + (size_t)lr * ns;
+      const double* __restrict__ Er = Sv.Et + Sv.e_off[s] + (size_t)lr * nI;
       double a0 = 0, a1 = 0, a2 = 0;
-      const double* __restrict__ Zr = Zs + (long long)v * ns;
+#pragma unroll 4
       for (int u = lane; u < ns; u += 64) {
         const double z = Zr[u];
-        a0 += z * bl[3 * u];
-        a1 += z * bl[3 * u + 1];
-        a2 += z * bl[3 * u + 2];
+        a0 += z * rhs_val<MODE>(src, wv, alpha, b0 + u);
+        a1 += z * rhs_val<MODE>(src, wv, alpha, nv + b0 + u);
+        a2 += z * rhs_val<MODE>(src, wv, alpha, 2 * nv + b0 + u);
       }
-      const double* __restrict__ Er = Et + (long long)v * nI;
+#pragma unroll 4
       for (int p = lane; p < nI; p += 64) {
         const double e = Er[p];
-        a0 -= e * xl[3 * p];
-        a1 -= e * xl[3 * p + 1];
-        a2 -= e * xl[3 * p + 2];
+        const int gi = nB + Ir[p];
+        a0 -= e * dst[gi];
+        a1 -= e * dst[nv + gi];
+        a2 -= e * dst[2 * nv + gi];
       }
       a0 = wave_sum(a0);
       a1 = wave_sum(a1);
       a2 = wave_sum(a2);
       if (lane == 0) {
-        dst[i0 + v] = a0;
-        dst[nv + i0 + v] = a1;
-        dst[2 * nv + i0 + v] = a2;
+        dst[v] = a0;
+        dst[nv + v] = a1;
+        dst[2 * nv + v] = a2;
+        my_row = v;
       }
     }
-    r0 = i0 + lr0;
-    r1 = i0 + lr1;
   } else {
-    r0 = nB + (blk - Sv.n_bottom_items) * kBlock;
-    r1 = min(r0 + kBlock, nf);
+    const int i = nB + (blockIdx.x - n_sub_blocks) * blockDim.x + threadIdx.x;
+    if (i < nf) my_row = i;
   }
-  if (MODE != kModeFwd) return;
-  __syncthreads();
-  // Anderson acceleration: append and Gram partials
-  const int m = St.m;
-  int nonempty, nc, head, slot_new;
-  aa_layout(St.ctl, k, m, nonempty, nc, head, slot_new);
-  double part[kAAPart];
+  if (MODE == kModePlain) return;
+  // per-vertex work
+  double part[kRedWidth];
 #pragma unroll
-  for (int j = 0; j < kAAPart; ++j) part[j] = 0.0;
-  if (m > 0) {
-    for (int i = r0 + threadIdx.x; i < r1; i += blockDim.x) {
+  for (int j = 0; j < kRedWidth; ++j) part[j] = 0.0;
+  if (MODE == kModeFwd) {
+    const int m = St.m;
+    int nonempty, nc, head, slot_new;
+    aa_layout(St.ctl + kCtlAA + 4 * (k & 1), m, nonempty, nc, head, slot_new);
+    if (m > 0 && my_row >= 0) {
+      const int i = my_row;
 #pragma unroll
       for (int a = 0; a < 3; ++a) {
         const int ix = a * nv + i;
         const double qc = St.q_cur[ix];
-        const double g = St.qhat[ix] - qc;
+        const double g = dst[ix] - qc;
         if (slot_new >= 0) {
-          const long long cix = ((long long)slot_new * 3 + a) * nv + i;
+          const size_t cix = ((size_t)slot_new * 3 + a) * nv + i;
           St.dG[cix] = g - St.g_last[ix];
           St.dQ[cix] = qc - St.q_last[ix];
         }
@@ -458,7 +722,7 @@ __global__ void __launch_bounds__(kBlock) k_bottom(VertArgs Vx, SolveArgs Sv, St
         double col[kMaxWindow];
 #pragma unroll
         for (int j = 0; j < kMaxWindow; ++j)
-          col[j] = (j < nc) ? St.dG[((long long)((head + j) % m) * 3 + a) * nv + i] : 0.0;
+          col[j] = (j < nc) ? St.dG[((size_t)((head + j) % m) * 3 + a) * nv + i] : 0.0;
 #pragma unroll
         for (int j = 0; j < kMaxWindow; ++j) {
 #pragma unroll
@@ -467,105 +731,59 @@ __global__ void __launch_bounds__(kBlock) k_bottom(VertArgs Vx, SolveArgs Sv, St
         }
       }
     }
-  }
-  block_sum<kAAPart>(part, lds + 0);
-  if (threadIdx.x == 0)
+    // block sum, stored compactly: G[j][l] at j*m + l, rhs[j] at m*m + j
+    constexpr int NA = kMaxWindow * kMaxWindow + kMaxWindow;
+    double vv[NA];
 #pragma unroll
-    for (int j = 0; j < kAAPart; ++j) St.aa_part[(long long)blk * kAAPart + j] = part[j];
-}
-
-// ---------------------------------------------------------------- Anderson update
-// gamma = (dG^T dG + rho I)^{-1} dG^T g, rho = max(1e-6 |dG|_F^2 / m, 1e-12)
-// (Eq. aa_gamma); q^{k+1} = q^ - (dQ + dG) gamma (Eq. aa_update), or q^ with
-// the history dropped when |gamma|_2 > 10 (reliability guard).
-__global__ void __launch_bounds__(kBlock) k_aa_update(VertArgs Vx, StepState St, int k) {
-  if (block_done(St.done)) return;
-  __shared__ double gam[kMaxWindow];
-  __shared__ int use_aa;
-  __shared__ double red[4 * kAAPart];
-  const int nv = Vx.nv, m = St.m;
-  int nonempty, nc, head, slot_new;
-  aa_layout(St.ctl, k, m, nonempty, nc, head, slot_new);
-  if (m > 0 && nc >= 1) {
-    double part[kAAPart];
+    for (int j = 0; j < NA; ++j) vv[j] = part[j];
+    __shared__ double red[16 * NA];
+    block_sum<NA>(vv, red);
+    if (threadIdx.x == 0 && m > 0) {
+      double* out = R.part + ((size_t)kRedAA * R.max_parts + blockIdx.x) * kRedWidth;
 #pragma unroll
-    for (int j = 0; j < kAAPart; ++j) part[j] = 0.0;
-    for (int b = threadIdx.x; b < St.n_aa_blocks; b += blockDim.x)
+      for (int j = 0; j < kMaxWindow; ++j) {
 #pragma unroll
-      for (int j = 0; j < kAAPart; ++j) part[j] += St.aa_part[(long long)b * kAAPart + j];
-    block_sum<kAAPart>(part, red);
-    if (threadIdx.x == 0) {
-      double G[kMaxWindow * kMaxWindow], rhs[kMaxWindow];
-      double fro = 0.0;
-      for (int j = 0; j < nc; ++j) {
-        for (int l = 0; l < nc; ++l) G[j * nc + l] = (j <= l) ? part[j * kMaxWindow + l] : part[l * kMaxWindow + j];
-        rhs[j] = part[kMaxWindow * kMaxWindow + j];
-        fro += G[j * nc + j];
+        for (int l = 0; l < kMaxWindow; ++l)
+          if (j < m && l < m) out[j * m + l] = (j <= l) ? vv[j * kMaxWindow + l] : vv[l * kMaxWindow + j];
+        if (j < m) out[m * m + j] = vv[kMaxWindow * kMaxWindow + j];
       }
-      const double rho = fmax(1e-6 * fro / nc, 1e-12);
-      for (int j = 0; j < nc; ++j) G[j * nc + j] += rho;
-      // Cholesky solve
-      bool ok = true;
-      for (int j = 0; j < nc && ok; ++j) {
-        double d = G[j * nc + j];
-        for (int l = 0; l < j; ++l) d -= G[j * nc + l] * G[j * nc + l];
-        if (!(d > 0.0)) { ok = false; break; }
-        d = sqrt(d);
-        G[j * nc + j] = d;
-        for (int i = j + 1; i < nc; ++i) {
-          double s = G[i * nc + j];
-          for (int l = 0; l < j; ++l) s -= G[i * nc + l] * G[j * nc + l];
-          G[i * nc + j] = s / d;
-        }
-      }
-      double nrm = INFINITY;
-      if (ok) {
-        double y[kMaxWindow];
-        for (int i = 0; i < nc; ++i) {
-          double s = rhs[i];
-          for (int l = 0; l < i; ++l) s -= G[i * nc + l] * y[l];
-          y[i] = s / G[i * nc + i];
-        }
-        for (int i = nc - 1; i >= 0; --i) {
-          double s = y[i];
-          for (int l = i + 1; l < nc; ++l) s -= G[l * nc + i] * gam[l];
-          gam[i] = s / G[i * nc + i];
-        }
-        nrm = 0.0;
-        for (int i = 0; i < nc; ++i) nrm += gam[i] * gam[i];
-        nrm = sqrt(nrm);
-      }
-      use_aa = (nrm <= 10.0);
     }
-  } else if (threadIdx.x == 0) {
-    use_aa = 0;
-  }
-  __syncthreads();
-  const bool reset = (m > 0 && nc >= 1 && !use_aa);
-  if (blockIdx.x == 0 && threadIdx.x == 0) {
-    int* nxt = St.ctl + kCtlAA + 4 * ((k + 1) & 1);
-    if (m <= 0) {
-      nxt[0] = 0; nxt[1] = 0; nxt[2] = 0;
-    } else if (reset) {
-      nxt[0] = 0; nxt[1] = 0; nxt[2] = 0;
-      St.ctl[kCtlResets] += 1;
+  } else {
+    double v3[3] = {0, 0, 0};
+    if (my_row >= 0) {
+      const int i = my_row;
+#pragma unroll
+      for (int a = 0; a < 3; ++a) {
+        const int ix = a * nv + i;
+        const double z = dst[ix];
+        if (MODE == kModePCG) {
+          const double rn = src[ix] - alpha * A.w[ix];
+          const double mn = A.mu[ix] + alpha * A.p[ix];
+          r_cur(A, k + 1)[ix] = rn;
+          A.mu[ix] = mn;
+          v3[0] += rn * z;
+          v3[1] += z * z;
+          v3[2] += mn * mn;
+        } else if (MODE == kModePCGInit) {
+          const double rn = A.r0[ix], mn = A.mu[ix];
+          v3[0] += rn * z;
+          v3[1] += z * z;
+          v3[2] += mn * mn;
+        } else {  // fixed point
+          const double mo = A.mu[ix];
+          v3[0] += (z - mo) * (z - mo);
+          v3[1] += z * z;
+          A.mu[ix] = z;
+        }
+      }
+    }
+    if (MODE == kModeFixed) {
+      write_partial<3>(v3, R, kRedFix, blockIdx.x);
     } else {
-      nxt[0] = 1; nxt[1] = nc; nxt[2] = head;
+      // PCG sums of iteration k land in the parity slot read by iteration k + 1
+      const int slot = (MODE == kModePCGInit) ? 0 : ((k + 1) & 1);
+      write_partial<3>(v3, R, kRedRZ0 + slot, blockIdx.x);
     }
-  }
-  const int i = blockIdx.x * blockDim.x + threadIdx.x;
-  if (i >= Vx.nf) return;
-#pragma unroll
-  for (int a = 0; a < 3; ++a) {
-    const int ix = a * nv + i;
-    double qn = St.qhat[ix];
-    if (use_aa)
-      for (int j = 0; j < nc; ++j) {
-        const long long cix = ((long long)((head + j) % m) * 3 + a) * nv + i;
-        qn -= (St.dQ[cix] + St.dG[cix]) * gam[j];
-      }
-    St.q_prev[ix] = St.q_cur[ix];
-    St.q_cur[ix] = qn;
   }
 }
 
@@ -616,14 +834,12 @@ __global__ void __launch_bounds__(kBlock) k_from_lib(VertArgs Vx, const double* 
 }
 
 // ================================================================= backward
-// Trust-region ratio partials (Eqs. tr_step, tr_decreases): per tet
+// Trust-region ratio sums (Eqs. tr_step, tr_decreases): per tet
 // V_e (psi_e(F(q*-1)) - psi_e(F(q*))) and (w_e + beta_e/h) V_e |G_e dq|^2;
 // per free vertex m/(2h^2) (a - b).(a + b - 2 q~) and (1 + alpha h) m/h^2 |dq|^2.
-__global__ void __launch_bounds__(kBlock) k_tr_partials(ElemArgs E, VertArgs Vx, const double* __restrict__ ck,
-                                                        double* __restrict__ part, int n_tet_blocks) {
-  __shared__ double red[8];
+__global__ void __launch_bounds__(kBlock) k_tr_partials(ElemArgs E, VertArgs Vx, RedArgs R, const double* __restrict__ ck,
+                                                        int n_tet_blocks) {
   const int nv = Vx.nv;
-  const double* qt = ck;
   const double* qtil = ck + 3 * nv;
   const double* qs = ck + 6 * nv;
   const double* qm = ck + 9 * nv;
@@ -640,20 +856,19 @@ __global__ void __launch_bounds__(kBlock) k_tr_partials(ElemArgs E, VertArgs Vx,
       const double Jb = Fb[0] * (Fb[4] * Fb[8] - Fb[5] * Fb[7]) - Fb[1] * (Fb[3] * Fb[8] - Fb[5] * Fb[6]) +
                         Fb[2] * (Fb[3] * Fb[7] - Fb[4] * Fb[6]);
       double d = 0.0, gg = 0.0;
+#pragma unroll
+      for (int j = 0; j < 9; ++j) gg += (Fb[j] - Fa[j]) * (Fb[j] - Fa[j]);
       if (Ja > 0.0 && Jb > 0.0) {
         double Ia = 0.0, Ib = 0.0;
 #pragma unroll
         for (int j = 0; j < 9; ++j) {
           Ia += Fa[j] * Fa[j];
           Ib += Fb[j] * Fb[j];
-          gg += (Fb[j] - Fa[j]) * (Fb[j] - Fa[j]);
         }
         const double la = log(Ja), lb = log(Jb);
         d = 0.5 * E.muV[t] * (Ia - Ib) - E.muV[t] * (la - lb) + 0.5 * E.lamV[t] * (la * la - lb * lb);
       } else {
         d = (Ja > 0.0) ? -INFINITY : INFINITY;
-#pragma unroll
-        for (int j = 0; j < 9; ++j) gg += (Fb[j] - Fa[j]) * (Fb[j] - Fa[j]);
       }
       v[0] = d;
       v[1] = (E.wV[t] + E.bV[t]) * gg;
@@ -665,38 +880,27 @@ __global__ void __launch_bounds__(kBlock) k_tr_partials(ElemArgs E, VertArgs Vx,
 #pragma unroll
       for (int a = 0; a < 3; ++a) {
         const int ix = a * nv + i;
-        const double A = qm[ix], B = qs[ix];
-        v[0] += 0.5 / (h * h) * m * (A - B) * (A + B - 2.0 * qtil[ix]);
-        v[1] += (1.0 + Vx.alpha * h) * m / (h * h) * (B - A) * (B - A);
+        const double Aq = qm[ix], Bq = qs[ix];
+        v[0] += 0.5 / (h * h) * m * (Aq - Bq) * (Aq + Bq - 2.0 * qtil[ix]);
+        v[1] += (1.0 + Vx.alpha * h) * m / (h * h) * (Bq - Aq) * (Bq - Aq);
       }
     }
   }
-  (void)qt;
-  block_sum<2>(v, red);
-  if (threadIdx.x == 0) {
-    part[2 * blockIdx.x] = v[0];
-    part[2 * blockIdx.x + 1] = v[1];
-  }
+  write_partial<2>(v, R, kRedTR, blockIdx.x);
 }
 
 // rho = dPhi_act / dPhi_mod (rho = 1 when dPhi_mod < 1e-12), tau* = 1/2 when
 // |rho - 1| <= eps_TR else 1 (Eqs. tr_ratio, tr_rule); then per tet the
 // recomputed SVD and prox stretches at q*, and the compact filtered prox
 // differential {U, V, D, c1, c2, s*} (Alg. 2 element loop).
-__global__ void __launch_bounds__(kBlock) k_bwd_elem(ElemArgs E, VertArgs Vx, const double* __restrict__ ck,
-                                                     const double* __restrict__ part, int n_part, double eps_tr,
-                                                     double tau_force, double* __restrict__ jac,
-                                                     double* __restrict__ bstat) {
-  __shared__ double red[8];
+__global__ void __launch_bounds__(kBlock) k_bwd_elem(ElemArgs E, VertArgs Vx, RedArgs R, const double* __restrict__ ck,
+                                                     double eps_tr, double tau_force, int use_partials,
+                                                     double* __restrict__ jac, double* __restrict__ bstat) {
   __shared__ double tau_s;
-  double v[2] = {0.0, 0.0};
-  for (int b = threadIdx.x; b < n_part; b += blockDim.x) {
-    v[0] += part[2 * b];
-    v[1] += part[2 * b + 1];
-  }
-  block_sum<2>(v, red);
+  double tr[2] = {0.0, 0.0};
+  if (use_partials) consume<2>(R, kRedTR, tr);
   if (threadIdx.x == 0) {
-    const double act = v[0], mod = 0.5 * fabs(v[1]);
+    const double act = tr[0], mod = 0.5 * fabs(tr[1]);
     const double rho = (mod < 1e-12) ? 1.0 : act / mod;
     double tau = (fabs(rho - 1.0) <= eps_tr) ? 0.5 : 1.0;
     if (tau_force >= 0.0) tau = tau_force;
@@ -714,14 +918,25 @@ __global__ void __launch_bounds__(kBlock) k_bwd_elem(ElemArgs E, VertArgs Vx, co
   if (t >= E.ne) return;
   const int nv = Vx.nv;
   const double* qs = ck + 6 * nv;
-  double F[9], U[9], V[9], sF[3], ss[3];
+  double F[9], U[9], V[9], sF[3], ss[3], rt[3];
   int vi[4];
   load_F(E, qs, nv, t, F, vi);
-  svd3(F, U, sF, V);
-  prox_stretch(sF, E.mu_bar, E.lam_bar, E.k_bar, ss);
+  bool warm = true;
+#pragma unroll
+  for (int j = 0; j < 9; ++j) {
+    V[j] = E.Vw[(size_t)j * E.ne + t];
+    warm = warm && isfinite(V[j]);
+  }
+  if (!warm)
+#pragma unroll
+    for (int j = 0; j < 9; ++j) V[j] = (j % 4 == 0) ? 1.0 : 0.0;
+  svd3(F, U, sF, V, warm);
+#pragma unroll
+  for (int j = 0; j < 3; ++j) rt[j] = E.rw[(size_t)j * E.ne + t];
+  prox_stretch(sF, E.mu_bar, E.lam_bar, E.k_bar, ss, rt);
   double D[6], c1[3], c2[3];
   prox_diff(sF, ss, E.mu_bar, E.lam_bar, E.k_bar, tau, D, c1, c2);
-  const long long ne = E.ne;
+  const size_t ne = E.ne;
 #pragma unroll
   for (int j = 0; j < 9; ++j) {
     jac[j * ne + t] = U[j];
@@ -741,24 +956,72 @@ __device__ __forceinline__ void load_jac(const double* __restrict__ jac, int ne,
                                          double D[6], double c1[3], double c2[3]) {
 #pragma unroll
   for (int j = 0; j < 9; ++j) {
-    U[j] = jac[(long long)j * ne + t];
-    V[j] = jac[(long long)(9 + j) * ne + t];
+    U[j] = jac[(size_t)j * ne + t];
+    V[j] = jac[(size_t)(9 + j) * ne + t];
   }
 #pragma unroll
-  for (int j = 0; j < 6; ++j) D[j] = jac[(long long)(18 + j) * ne + t];
+  for (int j = 0; j < 6; ++j) D[j] = jac[(size_t)(18 + j) * ne + t];
 #pragma unroll
   for (int j = 0; j < 3; ++j) {
-    c1[j] = jac[(long long)(24 + j) * ne + t];
-    c2[j] = jac[(long long)(27 + j) * ne + t];
+    c1[j] = jac[(size_t)(24 + j) * ne + t];
+    c2[j] = jac[(size_t)(27 + j) * ne + t];
   }
 }
 
-// K x element contributions: w_e V_e G_e^T (dp*/dF) G_e x (Eq. db_dq).
-// x is read on free vertices only (pinned entries are treated as zero).
-__global__ void __launch_bounds__(kBlock) k_apply_K(ElemArgs E, VertArgs Vx, const double* __restrict__ jac,
-                                                    const double* __restrict__ x, double* __restrict__ contrib,
-                                                    const int* __restrict__ done) {
-  if (done && *done) return;
+// PCG scalars at the start of adjoint iteration it: convergence of the
+// previous solve (|z| <= eps |mu|, the relative preconditioned residual) and
+// beta = (r.z)_{it} / (r.z)_{it-1} for the direction p = z + beta p.
+struct PCGCtl {
+  int stop;
+  double beta;
+};
+
+template <int MODE>
+__device__ __forceinline__ PCGCtl adj_control(const AdjState& A, const RedArgs& R, int it) {
+  __shared__ PCGCtl c;
+  double f[3] = {0.0, 0.0, 0.0};
+  if (MODE == kModePCG) consume<3>(R, kRedRZ0 + (it & 1), f);
+  if (MODE == kModeFixed && it >= 1) consume<3>(R, kRedFix, f);
+  if (threadIdx.x == 0) {
+    c.stop = 0;
+    c.beta = 0.0;
+    double res = INFINITY;
+    bool conv = false;
+    if (MODE == kModePCG) {
+      const double rz = f[0], zz = f[1], mm = f[2];
+      res = (zz == 0.0) ? 0.0 : sqrt(zz) / sqrt(mm);
+      conv = (it >= 1 && res <= A.eps) || zz == 0.0;
+      if (it >= 1) c.beta = rz / fin_site(R, kRedRZ0 + ((it - 1) & 1))[0];
+    } else if (MODE == kModeFixed && it >= 1) {
+      res = (f[1] == 0.0) ? 0.0 : sqrt(f[0]) / sqrt(f[1]);
+      conv = res <= A.eps;
+    }
+    const bool cap = it >= A.kmax;
+    c.stop = conv || cap;
+    if (blockIdx.x == 0 && (MODE == kModePCG || MODE == kModeFixed)) {
+      A.dstat[0] = res;
+      if (c.stop) {
+        *A.done = 1;
+        A.ctl[0] = it;
+        A.ctl[1] = conv ? 0 : 1;
+      }
+    }
+  }
+  __syncthreads();
+  PCGCtl out = c;
+  __syncthreads();
+  return out;
+}
+
+// K x element contributions: w_e V_e G_e^T (dp*/dF) G_e x (Eq. db_dq) on
+// free vertices; PCG forms x = p = z + beta p on the fly.
+template <int MODE>
+__global__ void __launch_bounds__(kBlock) k_apply_K(ElemArgs E, VertArgs Vx, AdjState A, RedArgs R,
+                                                    const double* __restrict__ jac, const double* __restrict__ x, int it) {
+  if (MODE != kModeDebug && block_done(A.done)) return;
+  PCGCtl c = {0, 0.0};
+  if (MODE != kModeDebug) c = adj_control<MODE>(A, R, it);
+  if (c.stop) return;
   const int t = blockIdx.x * blockDim.x + threadIdx.x;
   if (t >= E.ne) return;
   const int nv = Vx.nv, nf = Vx.nf;
@@ -771,161 +1034,70 @@ __global__ void __launch_bounds__(kBlock) k_apply_K(ElemArgs E, VertArgs Vx, con
 #pragma unroll
   for (int a = 0; a < 4; ++a)
 #pragma unroll
-    for (int ax = 0; ax < 3; ++ax) xv[a][ax] = vi[a] < nf ? x[ax * nv + vi[a]] : 0.0;
-  double Bm[9];
-#pragma unroll
-  for (int i = 0; i < 9; ++i) Bm[i] = E.Bm[i * E.ne + t];
+    for (int ax = 0; ax < 3; ++ax) {
+      const int ix = ax * nv + vi[a];
+      double val = 0.0;
+      if (vi[a] < nf) {
+        if (MODE == kModePCG) val = A.z[ix] + c.beta * A.p[ix];
+        else if (MODE == kModeFixed) val = A.mu[ix];
+        else val = x[ix];
+      }
+      xv[a][ax] = val;
+    }
   double dF[9];
-#pragma unroll
-  for (int ax = 0; ax < 3; ++ax) {
-    const double d1 = xv[1][ax] - xv[0][ax], d2 = xv[2][ax] - xv[0][ax], d3 = xv[3][ax] - xv[0][ax];
-#pragma unroll
-    for (int j = 0; j < 3; ++j) dF[3 * ax + j] = d1 * Bm[j] + d2 * Bm[3 + j] + d3 * Bm[6 + j];
-  }
+  F_from_positions(E, t, xv, dF);
   double U[9], V[9], D[6], c1[3], c2[3], dP[9];
   load_jac(jac, E.ne, t, U, V, D, c1, c2);
   prox_diff_apply(U, V, D, c1, c2, dF, dP);
-  store_contrib(E, contrib, t, E.wV[t], dP);
+  store_contrib(E, A.contrib, t, E.wV[t], dP);
 }
 
-// Gathered K x on free vertices; PCG: w = A p - K p and the partial p.w;
-// fixed point: rhs = qbar + K mu.
+// Gathered K x on free vertices (8 lanes per vertex).  PCG: p = z + beta p,
+// A p = r + beta A p (A z = r, so no product with A is needed), w = A p - K p
+// and the partial p.w; fixed point: r = qbar + K mu; debug: w = K x.
 template <int MODE>
-__global__ void __launch_bounds__(kBlock) k_adj_gather(VertArgs Vx, AdjState Ad, int it) {
-  __shared__ double red[8];
-  if (block_done(Ad.done)) return;
+__global__ void __launch_bounds__(kBlock) k_adj_gather(VertArgs Vx, AdjState A, RedArgs R, int it) {
+  if (MODE != kModeDebug && block_done(A.done)) return;
+  __shared__ double beta_s;
+  if (threadIdx.x == 0) {
+    beta_s = 0.0;
+    if (MODE == kModePCG && it >= 1)
+      beta_s = fin_site(R, kRedRZ0 + (it & 1))[0] / fin_site(R, kRedRZ0 + ((it - 1) & 1))[0];
+  }
+  __syncthreads();
+  const double beta = beta_s;
   const int nv = Vx.nv;
-  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  const int gtid = blockIdx.x * blockDim.x + threadIdx.x;
+  const int i = gtid >> 3, l = gtid & 7;
   double v[1] = {0.0};
   if (i < Vx.nf) {
     double kx[3];
-    gather3(Vx.inc_ptr, Vx.inc_idx, Ad.contrib, Vx.ne, i, kx);
+    gather8(Vx.inc_ptr, A.contrib, Vx.ninc, i, l, kx);
+    if (l == 0) {
 #pragma unroll
-    for (int a = 0; a < 3; ++a) {
-      const int ix = a * nv + i;
-      if (MODE == kModePCG) {
-        const double w = Ad.Ap[ix] - kx[a];
-        Ad.w[ix] = w;
-        v[0] += Ad.p[ix] * w;
-      } else if (MODE == kModeFixed) {
-        Ad.r[ix] = Ad.qbar[ix] + kx[a];
-      } else {  // debug: K x
-        Ad.w[ix] = kx[a];
+      for (int a = 0; a < 3; ++a) {
+        const int ix = a * nv + i;
+        if (MODE == kModePCG) {
+          const double pn = A.z[ix] + beta * A.p[ix];
+          const double apn = r_cur(A, it)[ix] + beta * A.Ap[ix];
+          A.p[ix] = pn;
+          A.Ap[ix] = apn;
+          const double w = apn - kx[a];
+          A.w[ix] = w;
+          v[0] += pn * w;
+        } else if (MODE == kModeFixed) {
+          A.r0[ix] = A.qbar[ix] + kx[a];
+        } else {
+          A.w[ix] = kx[a];
+        }
       }
     }
   }
-  if (MODE != kModePCG) return;
-  block_sum<1>(v, red);
-  if (threadIdx.x == 0) Ad.part[8 * blockIdx.x] = v[0];
-}
-
-// PCG: alpha = (r.z)/(p.w); mu += alpha p; r -= alpha w (done by every
-// vertex block after an identical reduction of the p.w partials).
-__global__ void __launch_bounds__(kBlock) k_pcg_alpha(VertArgs Vx, AdjState Ad, int it) {
-  __shared__ double red[8];
-  __shared__ double alpha_s;
-  if (block_done(Ad.done)) return;
-  double v[1] = {0.0};
-  for (int b = threadIdx.x; b < Ad.n_vert_blocks; b += blockDim.x) v[0] += Ad.part[8 * b];
-  block_sum<1>(v, red);
-  if (threadIdx.x == 0) alpha_s = Ad.scal[(it & 1) * 4 + 0] / v[0];
-  __syncthreads();
-  const double alpha = alpha_s;
-  const int nv = Vx.nv;
-  const int i = blockIdx.x * blockDim.x + threadIdx.x;
-  if (i >= Vx.nf) return;
-#pragma unroll
-  for (int a = 0; a < 3; ++a) {
-    const int ix = a * nv + i;
-    Ad.mu[ix] += alpha * Ad.p[ix];
-    Ad.r[ix] -= alpha * Ad.w[ix];
-  }
-}
-
-// After z = A^{-1} r: partial sums of r.z, |z|^2, |mu|^2 (PCG) or of
-// |mu_new - mu|^2, |mu_new|^2 (fixed point, which also moves mu_new into mu).
-template <int MODE>
-__global__ void __launch_bounds__(kBlock) k_adj_dots(VertArgs Vx, AdjState Ad, int it) {
-  __shared__ double red[16];
-  if (block_done(Ad.done)) return;
-  const int nv = Vx.nv;
-  const int i = blockIdx.x * blockDim.x + threadIdx.x;
-  double v[3] = {0.0, 0.0, 0.0};
-  if (i < Vx.nf) {
-#pragma unroll
-    for (int a = 0; a < 3; ++a) {
-      const int ix = a * nv + i;
-      if (MODE == kModePCG) {
-        const double z = Ad.z[ix];
-        v[0] += Ad.r[ix] * z;
-        v[1] += z * z;
-        v[2] += Ad.mu[ix] * Ad.mu[ix];
-      } else {
-        const double mn = Ad.z[ix], mo = Ad.mu[ix];
-        v[0] += (mn - mo) * (mn - mo);
-        v[1] += mn * mn;
-        Ad.mu[ix] = mn;
-      }
-    }
-  }
-  block_sum<3>(v, red);
-  if (threadIdx.x == 0)
-#pragma unroll
-    for (int j = 0; j < 3; ++j) Ad.part[8 * blockIdx.x + 1 + j] = v[j];
-}
-
-// Convergence test and the next PCG direction: beta = (r.z)_new/(r.z)_old,
-// p = z + beta p, A p = r + beta A p (A z = r, so no product with A is needed).
-template <int MODE>
-__global__ void __launch_bounds__(kBlock) k_adj_next(VertArgs Vx, AdjState Ad, int it) {
-  __shared__ double red[16];
-  __shared__ int stop;
-  __shared__ double beta_s;
-  if (block_done(Ad.done)) return;
-  double v[3] = {0.0, 0.0, 0.0};
-  for (int b = threadIdx.x; b < Ad.n_vert_blocks; b += blockDim.x)
-#pragma unroll
-    for (int j = 0; j < 3; ++j) v[j] += Ad.part[8 * b + 1 + j];
-  block_sum<3>(v, red);
-  if (threadIdx.x == 0) {
-    double res;
-    if (MODE == kModePCG) {
-      res = sqrt(v[1]) / fmax(sqrt(v[2]), 1e-300);
-      const double rz_old = Ad.scal[(it & 1) * 4 + 0];
-      beta_s = v[0] / rz_old;
-      if (blockIdx.x == 0) Ad.scal[((it + 1) & 1) * 4 + 0] = v[0];
-    } else {
-      res = sqrt(v[0]) / fmax(sqrt(v[1]), 1e-300);
-      beta_s = 0.0;
-    }
-    const bool conv = res <= Ad.eps;
-    const bool cap = it + 1 >= Ad.kmax;
-    stop = conv || cap;
-    if (blockIdx.x == 0) {
-      Ad.dstat[0] = res;
-      if (stop) {
-        *Ad.done = 1;
-        Ad.ctl[0] = it + 1;
-        Ad.ctl[1] = conv ? 0 : 1;
-      }
-    }
-  }
-  __syncthreads();
-  if (stop || MODE != kModePCG) return;
-  const double beta = beta_s;
-  const int nv = Vx.nv;
-  const int i = blockIdx.x * blockDim.x + threadIdx.x;
-  if (i >= Vx.nf) return;
-#pragma unroll
-  for (int a = 0; a < 3; ++a) {
-    const int ix = a * nv + i;
-    Ad.p[ix] = Ad.z[ix] + beta * Ad.p[ix];
-    Ad.Ap[ix] = Ad.r[ix] + beta * Ad.Ap[ix];
-  }
+  if (MODE == kModePCG) write_partial<1>(v, R, kRedPW, blockIdx.x);
 }
 
 // q bar = gq_next + gv_next / h on free vertices (Alg. 2 first line), in
-// library order; PCG start: mu = 0, r = q bar.
+// library order; adjoint start: mu = 0, r = q bar.
 __global__ void __launch_bounds__(kBlock) k_bwd_prologue(VertArgs Vx, AdjState Ad, const double* __restrict__ gq,
                                                          const double* __restrict__ gv) {
   const int i = blockIdx.x * blockDim.x + threadIdx.x;
@@ -936,37 +1108,11 @@ __global__ void __launch_bounds__(kBlock) k_bwd_prologue(VertArgs Vx, AdjState A
     const int ix = a * nv + i;
     const double qb = (i < Vx.nf) ? ((gq ? gq[3 * o + a] : 0.0) + (gv ? gv[3 * o + a] : 0.0) / Vx.h) : 0.0;
     Ad.qbar[ix] = qb;
-    Ad.r[ix] = qb;
+    Ad.r0[ix] = qb;
     Ad.mu[ix] = 0.0;
+    Ad.p[ix] = 0.0;
+    Ad.Ap[ix] = 0.0;
   }
-}
-
-// PCG after the first solve z0 = A^{-1} r0: p = z0, A p = r0, (r.z)_0.
-__global__ void __launch_bounds__(kBlock) k_pcg_start(VertArgs Vx, AdjState Ad) {
-  __shared__ double red[8];
-  const int nv = Vx.nv;
-  const int i = blockIdx.x * blockDim.x + threadIdx.x;
-  double v[1] = {0.0};
-  if (i < Vx.nf) {
-#pragma unroll
-    for (int a = 0; a < 3; ++a) {
-      const int ix = a * nv + i;
-      const double z = Ad.z[ix];
-      Ad.p[ix] = z;
-      Ad.Ap[ix] = Ad.r[ix];
-      v[0] += Ad.r[ix] * z;
-    }
-  }
-  block_sum<1>(v, red);
-  if (threadIdx.x == 0) Ad.part[8 * blockIdx.x] = v[0];
-}
-
-__global__ void __launch_bounds__(kBlock) k_pcg_start_reduce(AdjState Ad) {
-  __shared__ double red[8];
-  double v[1] = {0.0};
-  for (int b = threadIdx.x; b < Ad.n_vert_blocks; b += blockDim.x) v[0] += Ad.part[8 * b];
-  block_sum<1>(v, red);
-  if (threadIdx.x == 0) Ad.scal[0] = v[0];
 }
 
 // Gradient routing per tet (Eq. dl_dwe and its damping counterpart, chain
@@ -987,11 +1133,11 @@ __global__ void __launch_bounds__(kBlock) k_grad_elem(ElemArgs E, VertArgs Vx, c
   double U[9], V[9], ss[3];
 #pragma unroll
   for (int j = 0; j < 9; ++j) {
-    U[j] = jac[(long long)j * E.ne + t];
-    V[j] = jac[(long long)(9 + j) * E.ne + t];
+    U[j] = jac[(size_t)j * E.ne + t];
+    V[j] = jac[(size_t)(9 + j) * E.ne + t];
   }
 #pragma unroll
-  for (int j = 0; j < 3; ++j) ss[j] = jac[(long long)(30 + j) * E.ne + t];
+  for (int j = 0; j < 3; ++j) ss[j] = jac[(size_t)(30 + j) * E.ne + t];
   double gw = 0.0, gb = 0.0;
 #pragma unroll
   for (int i = 0; i < 3; ++i)
@@ -1011,9 +1157,13 @@ __global__ void __launch_bounds__(kBlock) k_grad_vert(VertArgs Vx, const double*
                                                       const double* __restrict__ contrib,
                                                       const double* __restrict__ gv_next, double* __restrict__ gq_t,
                                                       double* __restrict__ gv_t, double* __restrict__ gf) {
-  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  const int gtid = blockIdx.x * blockDim.x + threadIdx.x;
+  const int i = gtid >> 3, l = gtid & 7;
   const int nv = Vx.nv;
   if (i >= nv) return;
+  double bm[3] = {0, 0, 0};
+  if (i < Vx.nf) gather8(Vx.inc_ptr, contrib, Vx.ninc, i, l, bm);
+  if (l != 0) return;
   const int o = Vx.v_orig[i];
   if (i >= Vx.nf) {
 #pragma unroll
@@ -1024,8 +1174,6 @@ __global__ void __launch_bounds__(kBlock) k_grad_vert(VertArgs Vx, const double*
     }
     return;
   }
-  double bm[3];
-  gather3(Vx.inc_ptr, Vx.inc_idx, contrib, Vx.ne, i, bm);
   const double m = Vx.mass[i], h = Vx.h;
 #pragma unroll
   for (int a = 0; a < 3; ++a) {
@@ -1037,60 +1185,74 @@ __global__ void __launch_bounds__(kBlock) k_grad_vert(VertArgs Vx, const double*
   }
 }
 
+__global__ void __launch_bounds__(kBlock) k_init_warm(ElemArgs E) {
+  const int t = blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= E.ne) return;
+#pragma unroll
+  for (int j = 0; j < 9; ++j) E.Vw[(size_t)j * E.ne + t] = (j % 4 == 0) ? 1.0 : 0.0;
+#pragma unroll
+  for (int j = 0; j < 3; ++j) E.rw[(size_t)j * E.ne + t] = 0.0;
+}
+
+__global__ void __launch_bounds__(kBlock) k_zero_int(int* p, int n) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) p[i] = 0;
+}
+
 // ================================================================= launchers
 #define PD_GRID(n) dim3(((n) + kBlock - 1) / kBlock), dim3(kBlock)
 
-void launch_local(const ElemArgs& E, const double* q, int nv, double* contrib, const int* done, int* newton_max,
-                  hipStream_t s) {
-  hipLaunchKernelGGL(k_local, PD_GRID(E.ne), 0, s, E, q, nv, contrib, done, newton_max);
+int vert_group_blocks(int n) { return (8 * n + kBlock - 1) / kBlock; }
+int bottom_blocks(int nB, int nT) {
+  const int rows = kBottomThreads / 64;
+  return (nB + rows - 1) / rows + (nT + kBottomThreads - 1) / kBottomThreads;
+}
+int tr_blocks(int ne, int nf) { return (ne + kBlock - 1) / kBlock + (nf + kBlock - 1) / kBlock; }
+
+void launch_local(const ElemArgs& E, const StepState& St, const RedArgs& R, const double* q, int nv, int nf,
+                  int k, int fwd, hipStream_t s) {
+  hipLaunchKernelGGL(k_local, PD_GRID(E.ne), 0, s, E, St, R, q, nv, nf, k, fwd, fwd ? St.ctl + kCtlNewton : nullptr);
 }
 void launch_elem_GtG(const ElemArgs& E, const double* x, int nv, const double* w, double* contrib, hipStream_t s) {
   hipLaunchKernelGGL(k_elem_GtG, PD_GRID(E.ne), 0, s, E, x, nv, w, contrib);
 }
 void launch_prologue(const VertArgs& V, const double* qt, const double* vt, const double* f, const double* q0,
-                     const double* contrib, const StepState& St, hipStream_t s) {
-  hipLaunchKernelGGL(k_prologue, PD_GRID(V.nv), 0, s, V, qt, vt, f, q0, contrib, St);
+                     const StepState& St, hipStream_t s) {
+  hipLaunchKernelGGL(k_prologue, dim3(vert_group_blocks(V.nv)), dim3(kBlock), 0, s, V, qt, vt, f, q0, St);
 }
-static size_t lds_gather(const VertArgs& V) { return sizeof(double) * (3 * V.max_sub + 4 * 4 + 8); }
-static size_t lds_top(const SolveArgs& S) { return sizeof(double) * std::max(3 * S.nT, 4 * 4 + 8); }
-static size_t lds_bottom(const SolveArgs& S) {
-  return sizeof(double) * std::max(3 * (S.max_ns + S.max_nI), 4 * kAAPart + 8);
+void launch_gather_fwd(const VertArgs& V, const StepState& St, const RedArgs& R, int k, hipStream_t s) {
+  hipLaunchKernelGGL(k_gather_fwd, dim3(vert_group_blocks(V.nf)), dim3(kBlock), 0, s, V, St, R, k);
 }
-void launch_gather_E(int mode, const VertArgs& V, const SolveArgs& S, const StepState& St, const double* rhs_in,
-                     double* rhs_out, int k, hipStream_t s) {
-  const int nblk = S.nsub + (S.nT + kBlock - 1) / kBlock;
+void launch_gather_debug(const VertArgs& V, const double* contrib, double* out, hipStream_t s) {
+  hipLaunchKernelGGL(k_gather_debug, dim3(vert_group_blocks(V.nf)), dim3(kBlock), 0, s, V, contrib, out);
+}
+void launch_Eb(int mode, const VertArgs& V, const SolveArgs& S, const StepState& St, const AdjState& A,
+               const RedArgs& R, const double* rhs, int k, hipStream_t s) {
+  const int nblk = std::max(1, (S.nT + 3) / 4);
+  if (mode == kModeFwd)
+    hipLaunchKernelGGL(k_Eb<kModeFwd>, dim3(nblk), dim3(kBlock), 0, s, V, S, St, A, R, rhs, k);
+  else if (mode == kModePCG)
+    hipLaunchKernelGGL(k_Eb<kModePCG>, dim3(nblk), dim3(kBlock), 0, s, V, S, St, A, R, rhs, k);
+  else if (S.nT > 0)
+    hipLaunchKernelGGL(k_Eb<kModePlain>, dim3(nblk), dim3(kBlock), 0, s, V, S, St, A, R, rhs, k);
+}
+void launch_top(const VertArgs& V, const SolveArgs& S, const int* done, double* out, hipStream_t s) {
+  if (S.nT == 0) return;
+  hipLaunchKernelGGL(k_top, dim3((S.nT + 3) / 4), dim3(kBlock), 0, s, V, S, done, out);
+}
+void launch_bottom(int mode, const VertArgs& V, const SolveArgs& S, const StepState& St, const AdjState& A,
+                   const RedArgs& R, const double* rhs, double* out, int k, hipStream_t s) {
+  const int nblk = bottom_blocks(S.nB, S.nT);
   if (nblk == 0) return;
-  if (mode == kModeFwd)
-    hipLaunchKernelGGL(k_gather_E<kModeFwd>, dim3(nblk), dim3(kBlock), lds_gather(V), s, V, S, St, rhs_in, rhs_out, k);
-  else if (mode == kModeDebugGather)
-    hipLaunchKernelGGL(k_gather_E<kModeDebugGather>, dim3(nblk), dim3(kBlock), lds_gather(V), s, V, S, St, rhs_in,
-                       rhs_out, k);
-  else
-    hipLaunchKernelGGL(k_gather_E<kModePlain>, dim3(nblk), dim3(kBlock), lds_gather(V), s, V, S, St, rhs_in, rhs_out,
-                       k);
-}
-void launch_top(int mode, const VertArgs& V, const SolveArgs& S, const StepState& St, const double* rhs, double* out,
-                int k, hipStream_t s) {
-  // forward mode always runs: the dual-gate decision lives in this kernel
-  if (mode == kModeFwd)
-    hipLaunchKernelGGL(k_top<kModeFwd>, dim3(std::max(1, S.n_top_blocks)), dim3(kBlock), lds_top(S), s, V, S, St, rhs,
-                       out, k);
-  else if (S.nT == 0)
-    return;
-  else
-    hipLaunchKernelGGL(k_top<kModePlain>, dim3(S.n_top_blocks), dim3(kBlock), lds_top(S), s, V, S, St, rhs, out, k);
-}
-void launch_bottom(int mode, const VertArgs& V, const SolveArgs& S, const StepState& St, const double* rhs,
-                   double* out, int k, hipStream_t s) {
-  const int nblk = S.n_bottom_items + (S.nT + kBlock - 1) / kBlock;
-  if (nblk == 0) return;
-  if (mode == kModeFwd)
-    hipLaunchKernelGGL(k_bottom<kModeFwd>, dim3(nblk), dim3(kBlock), lds_bottom(S), s, V, S, St, rhs, out, k);
-  else
-    hipLaunchKernelGGL(k_bottom<kModePlain>, dim3(nblk), dim3(kBlock), lds_bottom(S), s, V, S, St, rhs, out, k);
-}
-void launch_aa_update(const VertArgs& V, const StepState& St, int k, hipStream_t s) {
-  hipLaunchKernelGGL(k_aa_update, PD_GRID(V.nf), 0, s, V, St, k);
+#define PD_BOTTOM(M) hipLaunchKernelGGL(k_bottom<M>, dim3(nblk), dim3(kBottomThreads), 0, s, V, S, St, A, R, rhs, out, k)
+  switch (mode) {
+    case kModeFwd: PD_BOTTOM(kModeFwd); break;
+    case kModePCG: PD_BOTTOM(kModePCG); break;
+    case kModePCGInit: PD_BOTTOM(kModePCGInit); break;
+    case kModeFixed: PD_BOTTOM(kModeFixed); break;
+    default: PD_BOTTOM(kModePlain); break;
+  }
+#undef PD_BOTTOM
 }
 void launch_epilogue(const VertArgs& V, const StepState& St, double* q_next, double* v_next, double* ckpt,
                      hipStream_t s) {
@@ -1102,43 +1264,29 @@ void launch_to_lib(const VertArgs& V, const double* user, double* lib, int free_
 void launch_from_lib(const VertArgs& V, const double* lib, double* user, int free_only, hipStream_t s) {
   hipLaunchKernelGGL(k_from_lib, PD_GRID(V.nv), 0, s, V, lib, user, free_only);
 }
-int tr_partial_blocks(const ElemArgs& E, const VertArgs& V) {
-  return (E.ne + kBlock - 1) / kBlock + (V.nf + kBlock - 1) / kBlock;
-}
-void launch_tr_partials(const ElemArgs& E, const VertArgs& V, const double* ck, double* part, hipStream_t s) {
+void launch_tr_partials(const ElemArgs& E, const VertArgs& V, const RedArgs& R, const double* ck, hipStream_t s) {
   const int ntb = (E.ne + kBlock - 1) / kBlock;
-  hipLaunchKernelGGL(k_tr_partials, dim3(tr_partial_blocks(E, V)), dim3(kBlock), 0, s, E, V, ck, part, ntb);
+  const int nblk = ntb + (V.nf + kBlock - 1) / kBlock;
+  hipLaunchKernelGGL(k_tr_partials, dim3(nblk), dim3(kBlock), 0, s, E, V, R, ck, ntb);
 }
-void launch_bwd_elem(const ElemArgs& E, const VertArgs& V, const double* ck, const double* part, int n_part,
-                     double eps_tr, double tau_force, double* jac, double* bstat, hipStream_t s) {
-  hipLaunchKernelGGL(k_bwd_elem, PD_GRID(E.ne), 0, s, E, V, ck, part, n_part, eps_tr, tau_force, jac, bstat);
+void launch_bwd_elem(const ElemArgs& E, const VertArgs& V, const RedArgs& R, const double* ck, double eps_tr,
+                     double tau_force, int use_partials, double* jac, double* bstat, hipStream_t s) {
+  hipLaunchKernelGGL(k_bwd_elem, PD_GRID(E.ne), 0, s, E, V, R, ck, eps_tr, tau_force, use_partials, jac, bstat);
 }
-void launch_apply_K(const ElemArgs& E, const VertArgs& V, const double* jac, const double* x, double* contrib,
-                    const int* done, hipStream_t s) {
-  hipLaunchKernelGGL(k_apply_K, PD_GRID(E.ne), 0, s, E, V, jac, x, contrib, done);
+void launch_apply_K(int mode, const ElemArgs& E, const VertArgs& V, const AdjState& A, const RedArgs& R,
+                    const double* jac, const double* x, int it, hipStream_t s) {
+  if (mode == kModePCG) hipLaunchKernelGGL(k_apply_K<kModePCG>, PD_GRID(E.ne), 0, s, E, V, A, R, jac, x, it);
+  else if (mode == kModeFixed) hipLaunchKernelGGL(k_apply_K<kModeFixed>, PD_GRID(E.ne), 0, s, E, V, A, R, jac, x, it);
+  else hipLaunchKernelGGL(k_apply_K<kModeDebug>, PD_GRID(E.ne), 0, s, E, V, A, R, jac, x, it);
 }
-void launch_adj_gather(int mode, const VertArgs& V, const AdjState& A, int it, hipStream_t s) {
-  if (mode == kModePCG) hipLaunchKernelGGL(k_adj_gather<kModePCG>, PD_GRID(V.nf), 0, s, V, A, it);
-  else if (mode == kModeFixed) hipLaunchKernelGGL(k_adj_gather<kModeFixed>, PD_GRID(V.nf), 0, s, V, A, it);
-  else hipLaunchKernelGGL(k_adj_gather<kModeDebugGather>, PD_GRID(V.nf), 0, s, V, A, it);
-}
-void launch_pcg_alpha(const VertArgs& V, const AdjState& A, int it, hipStream_t s) {
-  hipLaunchKernelGGL(k_pcg_alpha, PD_GRID(V.nf), 0, s, V, A, it);
-}
-void launch_adj_dots(int mode, const VertArgs& V, const AdjState& A, int it, hipStream_t s) {
-  if (mode == kModePCG) hipLaunchKernelGGL(k_adj_dots<kModePCG>, PD_GRID(V.nf), 0, s, V, A, it);
-  else hipLaunchKernelGGL(k_adj_dots<kModeFixed>, PD_GRID(V.nf), 0, s, V, A, it);
-}
-void launch_adj_next(int mode, const VertArgs& V, const AdjState& A, int it, hipStream_t s) {
-  if (mode == kModePCG) hipLaunchKernelGGL(k_adj_next<kModePCG>, PD_GRID(V.nf), 0, s, V, A, it);
-  else hipLaunchKernelGGL(k_adj_next<kModeFixed>, PD_GRID(V.nf), 0, s, V, A, it);
+void launch_adj_gather(int mode, const VertArgs& V, const AdjState& A, const RedArgs& R, int it, hipStream_t s) {
+  const dim3 g(vert_group_blocks(V.nf)), b(kBlock);
+  if (mode == kModePCG) hipLaunchKernelGGL(k_adj_gather<kModePCG>, g, b, 0, s, V, A, R, it);
+  else if (mode == kModeFixed) hipLaunchKernelGGL(k_adj_gather<kModeFixed>, g, b, 0, s, V, A, R, it);
+  else hipLaunchKernelGGL(k_adj_gather<kModeDebug>, g, b, 0, s, V, A, R, it);
 }
 void launch_bwd_prologue(const VertArgs& V, const AdjState& A, const double* gq, const double* gv, hipStream_t s) {
   hipLaunchKernelGGL(k_bwd_prologue, PD_GRID(V.nv), 0, s, V, A, gq, gv);
-}
-void launch_pcg_start(const VertArgs& V, const AdjState& A, hipStream_t s) {
-  hipLaunchKernelGGL(k_pcg_start, PD_GRID(V.nf), 0, s, V, A);
-  hipLaunchKernelGGL(k_pcg_start_reduce, dim3(1), dim3(kBlock), 0, s, A);
 }
 void launch_grad_elem(const ElemArgs& E, const VertArgs& V, const double* ck, const double* jac, const double* mu,
                       double* contrib, double* g_logE, hipStream_t s) {
@@ -1146,7 +1294,12 @@ void launch_grad_elem(const ElemArgs& E, const VertArgs& V, const double* ck, co
 }
 void launch_grad_vert(const VertArgs& V, const double* mu, const double* contrib, const double* gv_next, double* gq_t,
                       double* gv_t, double* gf, hipStream_t s) {
-  hipLaunchKernelGGL(k_grad_vert, PD_GRID(V.nv), 0, s, V, mu, contrib, gv_next, gq_t, gv_t, gf);
+  hipLaunchKernelGGL(k_grad_vert, dim3(vert_group_blocks(V.nv)), dim3(kBlock), 0, s, V, mu, contrib, gv_next, gq_t,
+                     gv_t, gf);
 }
+void launch_init_warm(const ElemArgs& E, hipStream_t s) {
+  hipLaunchKernelGGL(k_init_warm, PD_GRID(E.ne), 0, s, E);
+}
+void launch_zero_int(int* p, int n, hipStream_t s) { hipLaunchKernelGGL(k_zero_int, PD_GRID(n), 0, s, p, n); }
 
 }  // namespace pdhot

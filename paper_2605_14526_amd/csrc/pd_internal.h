@@ -12,7 +12,6 @@ namespace pdhot {
 
 constexpr int kBlock = 256;      // threads per workgroup for every kernel
 constexpr int kMaxWindow = 5;    // largest Anderson window supported
-constexpr int kAAPart = 32;      // per-block Anderson partial sums (>= m*m + m)
 constexpr int kCheckpointVecs = 4;
 
 // ---------------------------------------------------------------- host layout
@@ -35,24 +34,22 @@ void build_layout(int nv, int ne, const double* X, const int32_t* tets, const ui
 // ---------------------------------------------------------------- device scene
 struct DeviceSolve {
   // partitioned inverse of A~ over free vertices (two-level Schur complement)
-  double* Zs = nullptr;        // per subdomain n_s x n_s (row-major), = A_ss^{-1}
-  double* Et = nullptr;        // per subdomain n_s x |I_s| (row v holds E_s[:, v]), E_s = A_Ts A_ss^{-1}
-  double* Z = nullptr;         // nT x nT, inverse Schur complement
-  int* zs_off = nullptr;       // nsub (offsets into Zs, in doubles)  -- long offsets fit in int64 below
-  long long* zs_off64 = nullptr;
-  long long* et_off64 = nullptr;
-  int* sub_begin = nullptr;    // nsub + 1
-  int* ir_off = nullptr;       // nsub + 1 offsets into irows / slot_of
-  int* irows = nullptr;        // concatenated I_s (relative interface rows)
-  int* slot_of = nullptr;      // (s, p) -> slot index of the t buffer
-  int* row_slot_ptr = nullptr; // nT + 1
-  int nslots = 0;
-  double* t_slots = nullptr;   // nslots x 3
-  // work lists
-  int n_bottom_items = 0;      // subdomain row chunks
-  int* bottom_items = nullptr; // 3 ints per item: s, r0, r1
-  int n_top_blocks = 0, top_rows = 0;
+  double* Zs = nullptr;         // per subdomain n_s x n_s (row-major), = A_ss^{-1}
+  double* Et = nullptr;         // per subdomain n_s x |I_s| (row v holds E_s[:, v]), E_s = A_Ts A_ss^{-1}
+  double* E = nullptr;          // per subdomain |I_s| x n_s (row p holds E_s[p, :])
+  double* Z = nullptr;          // nT x nT, inverse Schur complement
+  long long* zs_off = nullptr;  // nsub + 1
+  long long* e_off = nullptr;   // nsub + 1 (same offsets for E and Et)
+  int* sub_of = nullptr;        // nB
+  int* sub_begin = nullptr;     // nsub + 1
+  int* ir_off = nullptr;        // nsub + 1
+  int* irows = nullptr;         // concatenated I_s (relative interface rows)
+  int* rl_ptr = nullptr;        // nT + 1
+  int* rl_sub = nullptr;
+  int* rl_p = nullptr;
+  double* rT = nullptr;         // 3 x nT
   size_t bytes = 0;
+  double zs_entries = 0, e_entries = 0;
 };
 
 // Per-launch timing of one kernel with HIP events (roofline instrumentation).
@@ -66,7 +63,7 @@ struct KernelTimer {
 
 struct Scene {
   // --- host copies
-  int nv = 0, ne = 0;
+  int nv = 0, ne = 0, ninc = 0;
   std::vector<double> X;
   std::vector<int32_t> tets;
   std::vector<uint8_t> pinned;
@@ -76,42 +73,48 @@ struct Scene {
   int m = 0, kmax_fwd = 1000, kmax_bwd = 1000, adj_method = 0, max_sub = 0, iters_per_check = 0;
   double eps_rel = 1e-6, eps_abs = 1e-12, eps_adj = 1e-6, eps_tr = 0.1;
   bool stale = true;
-  int last_fwd_iters = 4;
+  int last_fwd_iters = 4, last_adj_iters = 8;
   Layout L;
   double mu_bar = 0, lam_bar = 0, k_bar = 0, mu_ref = 0;
+  std::vector<double> hBm;  // host copy of the per-tet D_m^{-1} (library order, SoA)
+  std::vector<int> htv;     // host copy of the tet vertex ids
 
   // --- device: element arrays (library tet order, SoA)
   int* tv = nullptr;        // 4 x ne
+  int* tinc = nullptr;      // 4 x ne incidence positions
   double* Bm = nullptr;     // 9 x ne  (D_m^{-1}, row-major per tet)
   double* wV = nullptr;     // ne: w_e V_e
   double* bV = nullptr;     // ne: beta_e V_e / h
   double* muV = nullptr;    // ne: mu_e V_e   (primal objective)
   double* lamV = nullptr;   // ne: lam_e V_e
   int* tet_orig = nullptr;  // ne
+  double* Vw = nullptr;     // 9 x ne warm-start rotations
+  double* rw = nullptr;     // 3 x ne warm-start stretch ratios
   // --- device: vertex arrays (library order)
   int* v_orig = nullptr;    // nv
   double* mass = nullptr;   // nv
   double* rest = nullptr;   // 3 x nv SoA
-  double* cpin = nullptr;   // 3 x nf: -A~_{free,pinned} q_pinned
+  double* cpin = nullptr;   // 3 x nv: -A~_{free,pinned} q_pinned
   int* inc_ptr = nullptr;   // nf + 1
-  int* inc_idx = nullptr;   // tet * 4 + slot
   DeviceSolve S;
-  // --- device: iteration state (3 x nf SoA unless noted)
-  double* contrib = nullptr;  // 12 x ne
-  double *qt = nullptr, *vt = nullptr, *qtil = nullptr, *c = nullptr;  // qt/qtil 3 x nv
+  // --- device: iteration state (3 x nv SoA)
+  double* contrib = nullptr;  // 3 x ninc
+  double *qt = nullptr, *vt = nullptr, *qtil = nullptr, *c = nullptr;
   double *q_cur = nullptr, *q_prev = nullptr, *b_cur = nullptr, *b_prev = nullptr, *qhat = nullptr;
-  double *q_last = nullptr, *g_last = nullptr, *dQ = nullptr, *dG = nullptr;  // dQ, dG: m x 3 x nf
-  double* gate_part = nullptr;  // n_gather_blocks x 4
-  double* aa_part = nullptr;    // n_bottom_blocks x kAAPart
+  double *q_last = nullptr, *g_last = nullptr, *dQ = nullptr, *dG = nullptr;  // dQ, dG: m x 3 x nv
   int* ctl = nullptr;           // device control block (see kernels)
   double* dstat = nullptr;      // device statistics
   int* hctl = nullptr;          // pinned host mirror of ctl
   double* hdstat = nullptr;     // pinned host mirror of dstat
+  // deterministic reductions
+  double* red_part = nullptr;
+  double* red_fin = nullptr;
+  int red_max_parts = 0;
   // backward
   double* jac = nullptr;       // 33 x ne compact prox differential
-  double *mu = nullptr, *r = nullptr, *z = nullptr, *p = nullptr, *Ap = nullptr, *wv = nullptr, *qbar = nullptr;
-  double* red_part = nullptr;  // generic per-block partials (n_red_blocks x 8)
-  int n_gather_blocks = 0, n_bottom_blocks = 0, n_vert_blocks = 0, n_tet_blocks = 0;
+  double *mu = nullptr, *r0 = nullptr, *r1 = nullptr, *z = nullptr, *p = nullptr, *Ap = nullptr, *wv = nullptr,
+         *qbar = nullptr;
+  double* ck_scratch = nullptr;  // 12 x nv (diagnostic K apply)
   KernelTimer kt;
 };
 

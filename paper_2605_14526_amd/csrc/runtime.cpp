@@ -110,15 +110,17 @@ double det3(const double* A) {
 }
 
 void free_device(Scene& S) {
-  dfree(S.tv); dfree(S.Bm); dfree(S.wV); dfree(S.bV); dfree(S.muV); dfree(S.lamV); dfree(S.tet_orig);
-  dfree(S.v_orig); dfree(S.mass); dfree(S.rest); dfree(S.cpin); dfree(S.inc_ptr); dfree(S.inc_idx);
-  dfree(S.S.Zs); dfree(S.S.Et); dfree(S.S.Z); dfree(S.S.zs_off64); dfree(S.S.et_off64); dfree(S.S.sub_begin);
-  dfree(S.S.ir_off); dfree(S.S.irows); dfree(S.S.slot_of); dfree(S.S.row_slot_ptr); dfree(S.S.t_slots);
-  dfree(S.S.bottom_items);
+  dfree(S.tv); dfree(S.tinc); dfree(S.Bm); dfree(S.wV); dfree(S.bV); dfree(S.muV); dfree(S.lamV);
+  dfree(S.tet_orig); dfree(S.Vw); dfree(S.rw);
+  dfree(S.v_orig); dfree(S.mass); dfree(S.rest); dfree(S.cpin); dfree(S.inc_ptr);
+  DeviceSolve& D = S.S;
+  dfree(D.Zs); dfree(D.Et); dfree(D.E); dfree(D.Z); dfree(D.zs_off); dfree(D.e_off); dfree(D.sub_of);
+  dfree(D.sub_begin); dfree(D.ir_off); dfree(D.irows); dfree(D.rl_ptr); dfree(D.rl_sub); dfree(D.rl_p); dfree(D.rT);
   dfree(S.contrib); dfree(S.qt); dfree(S.vt); dfree(S.qtil); dfree(S.c); dfree(S.q_cur); dfree(S.q_prev);
   dfree(S.b_cur); dfree(S.b_prev); dfree(S.qhat); dfree(S.q_last); dfree(S.g_last); dfree(S.dQ); dfree(S.dG);
-  dfree(S.gate_part); dfree(S.aa_part); dfree(S.ctl); dfree(S.dstat); dfree(S.jac); dfree(S.mu); dfree(S.r);
-  dfree(S.z); dfree(S.p); dfree(S.Ap); dfree(S.wv); dfree(S.qbar); dfree(S.red_part);
+  dfree(S.ctl); dfree(S.dstat); dfree(S.red_part); dfree(S.red_fin);
+  dfree(S.jac); dfree(S.mu); dfree(S.r0); dfree(S.r1); dfree(S.z); dfree(S.p); dfree(S.Ap); dfree(S.wv);
+  dfree(S.qbar); dfree(S.ck_scratch);
   if (S.hctl) (void)hipHostFree(S.hctl);
   if (S.hdstat) (void)hipHostFree(S.hdstat);
   S.hctl = nullptr;
@@ -127,9 +129,8 @@ void free_device(Scene& S) {
   S.kt.ev.clear();
 }
 
-
 // ---------------------------------------------------------------- kernel timer
-enum { kKLocal = 0, kKGather = 1, kKTop = 2, kKBottom = 3, kKAA = 4, kKApplyK = 5, kKCount = 6 };
+enum { kKLocal = 0, kKGather = 1, kKTop = 2, kKBottom = 3, kKEb = 4, kKApplyK = 5, kKCount = 6 };
 constexpr int kTimerPairs = 1024;
 
 void kt_flush(Scene& S) {
@@ -180,17 +181,17 @@ void kt_destroy(Scene& S) {
 // ---------------------------------------------------------------- argument blocks
 ElemArgs elem_args(const Scene& S) {
   ElemArgs E;
-  E.ne = S.ne;
-  E.tv = S.tv; E.Bm = S.Bm; E.wV = S.wV; E.bV = S.bV; E.muV = S.muV; E.lamV = S.lamV; E.tet_orig = S.tet_orig;
+  E.ne = S.ne; E.ninc = S.ninc;
+  E.tv = S.tv; E.tinc = S.tinc; E.Bm = S.Bm; E.wV = S.wV; E.bV = S.bV; E.muV = S.muV; E.lamV = S.lamV;
+  E.tet_orig = S.tet_orig; E.Vw = S.Vw; E.rw = S.rw;
   E.mu_bar = S.mu_bar; E.lam_bar = S.lam_bar; E.k_bar = S.k_bar;
   return E;
 }
 
 VertArgs vert_args(const Scene& S) {
   VertArgs V;
-  V.nv = S.nv; V.nf = S.L.nf; V.ne = S.ne; V.max_sub = 0;
-  for (int s = 0; s < S.L.nsub; ++s) V.max_sub = std::max(V.max_sub, S.L.sub_begin[s + 1] - S.L.sub_begin[s]);
-  V.v_orig = S.v_orig; V.mass = S.mass; V.rest = S.rest; V.cpin = S.cpin; V.inc_ptr = S.inc_ptr; V.inc_idx = S.inc_idx;
+  V.nv = S.nv; V.nf = S.L.nf; V.ne = S.ne; V.ninc = S.ninc;
+  V.v_orig = S.v_orig; V.mass = S.mass; V.rest = S.rest; V.cpin = S.cpin; V.inc_ptr = S.inc_ptr;
   V.h = S.h; V.alpha = S.alpha;
   for (int a = 0; a < 3; ++a) V.grav[a] = S.grav[a];
   return V;
@@ -198,29 +199,36 @@ VertArgs vert_args(const Scene& S) {
 
 SolveArgs solve_args(const Scene& S) {
   SolveArgs A;
-  const Layout& L = S.L;
-  A.nsub = L.nsub; A.nB = L.nB; A.nT = L.nT;
-  A.n_bottom_items = S.S.n_bottom_items; A.n_top_blocks = S.S.n_top_blocks; A.top_rows = S.S.top_rows;
-  A.max_ns = 0; A.max_nI = 0;
-  for (int s = 0; s < L.nsub; ++s) {
-    A.max_ns = std::max(A.max_ns, L.sub_begin[s + 1] - L.sub_begin[s]);
-    A.max_nI = std::max(A.max_nI, (int)L.Irows[s].size());
-  }
-  A.Zs = S.S.Zs; A.Et = S.S.Et; A.Z = S.S.Z; A.zs_off = S.S.zs_off64; A.et_off = S.S.et_off64;
-  A.sub_begin = S.S.sub_begin; A.ir_off = S.S.ir_off; A.irows = S.S.irows; A.slot_of = S.S.slot_of;
-  A.row_slot_ptr = S.S.row_slot_ptr; A.t_slots = S.S.t_slots; A.bottom_items = S.S.bottom_items;
+  const DeviceSolve& D = S.S;
+  A.nsub = S.L.nsub; A.nB = S.L.nB; A.nT = S.L.nT;
+  A.sub_of = D.sub_of; A.sub_begin = D.sub_begin; A.Zs = D.Zs; A.zs_off = D.zs_off; A.Et = D.Et; A.E = D.E;
+  A.e_off = D.e_off; A.ir_off = D.ir_off; A.irows = D.irows; A.rl_ptr = D.rl_ptr; A.rl_sub = D.rl_sub;
+  A.rl_p = D.rl_p; A.Z = D.Z; A.rT = D.rT;
   return A;
 }
 
 StepState step_state(Scene& S) {
   StepState T;
   T.m = S.m; T.kmax = S.kmax_fwd; T.eps_rel = S.eps_rel; T.eps_abs = S.eps_abs;
-  T.n_gate_blocks = S.n_gather_blocks; T.n_aa_blocks = S.n_bottom_blocks;
   T.contrib = S.contrib; T.qt = S.qt; T.vt = S.vt; T.qtil = S.qtil; T.c = S.c;
   T.q_cur = S.q_cur; T.q_prev = S.q_prev; T.b_cur = S.b_cur; T.b_prev = S.b_prev; T.qhat = S.qhat;
   T.q_last = S.q_last; T.g_last = S.g_last; T.dQ = S.dQ; T.dG = S.dG;
-  T.gate_part = S.gate_part; T.aa_part = S.aa_part; T.ctl = S.ctl; T.done = S.ctl + kCtlDone; T.dstat = S.dstat;
+  T.ctl = S.ctl; T.done = S.ctl + kCtlDone; T.dstat = S.dstat;
   return T;
+}
+
+RedArgs red_args(const Scene& S) {
+  RedArgs R;
+  R.part = S.red_part; R.fin = S.red_fin; R.max_parts = S.red_max_parts;
+  const int nb = bottom_blocks(S.L.nB, S.L.nT), ng = vert_group_blocks(S.L.nf);
+  R.nparts[kRedGate] = ng;
+  R.nparts[kRedAA] = nb;
+  R.nparts[kRedPW] = ng;
+  R.nparts[kRedRZ0] = nb;
+  R.nparts[kRedRZ1] = nb;
+  R.nparts[kRedTR] = tr_blocks(S.ne, S.L.nf);
+  R.nparts[kRedFix] = nb;
+  return R;
 }
 
 // ---------------------------------------------------------------- setup
@@ -230,8 +238,9 @@ void setup_scene(Scene& S, const pd_mesh_desc* mesh, const pd_material_desc* mat
   if (nv <= 0 || ne <= 0 || !mesh->rest_xyz || !mesh->tets || !mesh->pinned || !mat->log_E)
     throw PdError{PD_ERR_INVALID_ARG, "empty mesh or null array"};
   if (!(o->h > 0.0) || o->aa_window < 0 || o->aa_window > kMaxWindow || !(o->eps_rel >= 0.0) || o->kmax_fwd < 3 ||
-      o->kmax_bwd < 1 || !(o->eps_adj > 0.0))
-    throw PdError{PD_ERR_INVALID_ARG, "invalid solver options (h > 0, 0 <= aa_window <= 5, kmax_fwd >= 3)"};
+      o->kmax_bwd < 1 || !(o->eps_adj > 0.0) || o->adj_method < 0 || o->adj_method > 1)
+    throw PdError{PD_ERR_INVALID_ARG,
+                  "invalid solver options (h > 0, 0 <= aa_window <= 5, kmax_fwd >= 3, adj_method 0 or 1)"};
   if (!(mat->nu > -1.0 && mat->nu < 0.5) || !(mat->rho > 0.0) || !(mat->alpha >= 0.0) || !(mat->beta0 >= 0.0))
     throw PdError{PD_ERR_INVALID_ARG, "invalid material constants"};
   S.nv = nv;
@@ -256,6 +265,8 @@ void setup_scene(Scene& S, const pd_mesh_desc* mesh, const pd_material_desc* mat
   // orientation (reorient negative tets), degenerate check
   for (int e = 0; e < ne; ++e) {
     int* t = &S.tets[4 * (size_t)e];
+    if (t[0] == t[1] || t[0] == t[2] || t[0] == t[3] || t[1] == t[2] || t[1] == t[3] || t[2] == t[3])
+      throw PdError{PD_ERR_DEGENERATE_TET, "repeated vertex in tet " + std::to_string(e)};
     double Dm[9];
     for (int a = 1; a < 4; ++a)
       for (int i = 0; i < 3; ++i) Dm[3 * i + a - 1] = S.X[3 * t[a] + i] - S.X[3 * t[0] + i];
@@ -263,16 +274,17 @@ void setup_scene(Scene& S, const pd_mesh_desc* mesh, const pd_material_desc* mat
     if (d < 0.0) std::swap(t[1], t[2]), d = -d;
     double scale = 0.0;
     for (int i = 0; i < 9; ++i) scale = std::max(scale, std::fabs(Dm[i]));
-    if (!(d > 1e-14 * scale * scale * scale)) throw PdError{PD_ERR_DEGENERATE_TET, "zero-volume tet " + std::to_string(e)};
-    if (t[0] == t[1] || t[0] == t[2] || t[0] == t[3] || t[1] == t[2] || t[1] == t[3] || t[2] == t[3])
-      throw PdError{PD_ERR_DEGENERATE_TET, "repeated vertex in tet " + std::to_string(e)};
+    if (!(d > 1e-14 * scale * scale * scale))
+      throw PdError{PD_ERR_DEGENERATE_TET, "zero-volume tet " + std::to_string(e)};
   }
   build_layout(nv, ne, S.X.data(), S.tets.data(), S.pinned.data(), S.max_sub, S.L);
   if (S.L.nf == 0) throw PdError{PD_ERR_INVALID_ARG, "no free vertex"};
   const Layout& L = S.L;
   // element geometry in library order
-  std::vector<int> tv(4 * (size_t)ne);
-  std::vector<double> Bm(9 * (size_t)ne), vol(ne);
+  std::vector<int>& tv = S.htv;
+  std::vector<double>& Bm = S.hBm;
+  tv.assign(4 * (size_t)ne, 0);
+  Bm.assign(9 * (size_t)ne, 0.0);
   std::vector<int> tet_orig(ne);
   for (int t = 0; t < ne; ++t) {
     const int e = L.tet_lib2orig[t];
@@ -282,7 +294,6 @@ void setup_scene(Scene& S, const pd_mesh_desc* mesh, const pd_material_desc* mat
     for (int a = 1; a < 4; ++a)
       for (int i = 0; i < 3; ++i) Dm[3 * i + a - 1] = S.X[3 * tt[a] + i] - S.X[3 * tt[0] + i];
     const double d = det3(Dm);
-    vol[t] = d / 6.0;
     double Bi[9];
     Bi[0] = (Dm[4] * Dm[8] - Dm[5] * Dm[7]) / d;
     Bi[1] = (Dm[2] * Dm[7] - Dm[1] * Dm[8]) / d;
@@ -311,7 +322,8 @@ void setup_scene(Scene& S, const pd_mesh_desc* mesh, const pd_material_desc* mat
     for (int a = 0; a < 3; ++a) rest[(size_t)a * nv + i] = S.X[3 * (size_t)L.lib2orig[i] + a];
   S.rest = dalloc<double>(3 * (size_t)nv);
   upload(S.rest, rest);
-  // incidence of free vertices: (tet, slot) in tet order
+  // incidence of free vertices: (tet, slot) in tet order; each tet slot knows
+  // its position so element kernels write straight into vertex order
   const int nf = L.nf;
   std::vector<int> cnt(nf + 1, 0);
   for (int t = 0; t < ne; ++t)
@@ -320,22 +332,25 @@ void setup_scene(Scene& S, const pd_mesh_desc* mesh, const pd_material_desc* mat
       if (i < nf) cnt[i + 1]++;
     }
   for (int i = 0; i < nf; ++i) cnt[i + 1] += cnt[i];
-  std::vector<int> inc(cnt[nf]), fill(cnt.begin(), cnt.end() - 1);
+  S.ninc = cnt[nf];
+  std::vector<int> fill(cnt.begin(), cnt.end() - 1), tinc(4 * (size_t)ne, -1);
   for (int t = 0; t < ne; ++t)
     for (int a = 0; a < 4; ++a) {
       const int i = tv[(size_t)a * ne + t];
-      if (i < nf) inc[fill[i]++] = 4 * t + a;
+      if (i < nf) tinc[(size_t)a * ne + t] = fill[i]++;
     }
   S.inc_ptr = dalloc<int>(nf + 1);
   upload(S.inc_ptr, cnt);
-  S.inc_idx = dalloc<int>(inc.size());
-  upload(S.inc_idx, inc);
+  S.tinc = dalloc<int>(4 * (size_t)ne);
+  upload(S.tinc, tinc);
   // element-material arrays and iteration buffers (sized once)
   S.wV = dalloc<double>(ne); S.bV = dalloc<double>(ne); S.muV = dalloc<double>(ne); S.lamV = dalloc<double>(ne);
+  S.Vw = dalloc<double>(9 * (size_t)ne);
+  S.rw = dalloc<double>(3 * (size_t)ne);
   S.mass = dalloc<double>(nv);
   S.cpin = dalloc<double>(3 * (size_t)nv);
   const size_t V3 = 3 * (size_t)nv;
-  S.contrib = dalloc<double>(12 * (size_t)ne);
+  S.contrib = dalloc<double>(3 * (size_t)std::max(1, S.ninc));
   S.qt = dalloc<double>(V3); S.vt = dalloc<double>(V3); S.qtil = dalloc<double>(V3); S.c = dalloc<double>(V3);
   S.q_cur = dalloc<double>(V3); S.q_prev = dalloc<double>(V3); S.b_cur = dalloc<double>(V3);
   S.b_prev = dalloc<double>(V3); S.qhat = dalloc<double>(V3); S.q_last = dalloc<double>(V3);
@@ -344,16 +359,23 @@ void setup_scene(Scene& S, const pd_mesh_desc* mesh, const pd_material_desc* mat
   S.dQ = dalloc<double>(mm * V3); S.dG = dalloc<double>(mm * V3);
   PD_HIP(hipMemset(S.b_cur, 0, V3 * sizeof(double)));
   S.ctl = dalloc<int>(kCtlTotal);
+  PD_HIP(hipMemset(S.ctl, 0, kCtlTotal * sizeof(int)));
   S.dstat = dalloc<double>(32);
   PD_HIP(hipHostMalloc((void**)&S.hctl, kCtlTotal * sizeof(int)));
   PD_HIP(hipHostMalloc((void**)&S.hdstat, 32 * sizeof(double)));
   S.jac = dalloc<double>(33 * (size_t)ne);
-  S.mu = dalloc<double>(V3); S.r = dalloc<double>(V3); S.z = dalloc<double>(V3); S.p = dalloc<double>(V3);
-  S.Ap = dalloc<double>(V3); S.wv = dalloc<double>(V3); S.qbar = dalloc<double>(V3);
-  S.n_vert_blocks = (nf + kBlock - 1) / kBlock;
-  S.n_tet_blocks = (ne + kBlock - 1) / kBlock;
-  const int n_red = std::max(S.n_vert_blocks, S.n_tet_blocks + S.n_vert_blocks) + 4;
-  S.red_part = dalloc<double>(8 * (size_t)n_red);
+  S.mu = dalloc<double>(V3); S.r0 = dalloc<double>(V3); S.r1 = dalloc<double>(V3); S.z = dalloc<double>(V3);
+  S.p = dalloc<double>(V3); S.Ap = dalloc<double>(V3); S.wv = dalloc<double>(V3); S.qbar = dalloc<double>(V3);
+  S.ck_scratch = dalloc<double>(12 * (size_t)nv);
+  PD_HIP(hipMemset(S.z, 0, V3 * sizeof(double)));
+  // reduction sites sized for the widest producing kernel
+  S.red_max_parts = std::max({bottom_blocks(L.nB, L.nT), vert_group_blocks(nf), tr_blocks(ne, nf), 1});
+  S.red_part = dalloc<double>((size_t)kRedSites * S.red_max_parts * kRedWidth);
+  S.red_fin = dalloc<double>((size_t)kRedSites * kFinStride);
+  PD_HIP(hipMemset(S.red_part, 0, (size_t)kRedSites * S.red_max_parts * kRedWidth * sizeof(double)));
+  PD_HIP(hipMemset(S.red_fin, 0, (size_t)kRedSites * kFinStride * sizeof(double)));
+  launch_init_warm(elem_args(S), nullptr);
+  PD_HIP(hipDeviceSynchronize());
   S.stale = true;
 }
 
@@ -380,10 +402,9 @@ void factorize(Scene& S) {
   S.mu_ref = mref;
   for (int e = 0; e < ne; ++e) beta[e] = S.beta0 * mu[e] / mref;
   // per-tet data in library order
-  std::vector<double> Bm(9 * (size_t)ne), wV(ne), bV(ne), muV(ne), lamV(ne);
-  std::vector<int> tv(4 * (size_t)ne);
-  PD_HIP(hipMemcpy(Bm.data(), S.Bm, Bm.size() * sizeof(double), hipMemcpyDeviceToHost));
-  PD_HIP(hipMemcpy(tv.data(), S.tv, tv.size() * sizeof(int), hipMemcpyDeviceToHost));
+  const std::vector<double>& Bm = S.hBm;
+  const std::vector<int>& tv = S.htv;
+  std::vector<double> wV(ne), bV(ne), muV(ne), lamV(ne);
   std::vector<double> mass(nv, 0.0);
   for (int t = 0; t < ne; ++t) {
     const int e = L.tet_lib2orig[t];
@@ -442,10 +463,7 @@ void factorize(Scene& S) {
         const int j = tv[(size_t)b * ne + t];
         const double val = cst * (Bh[a][0] * Bh[b][0] + Bh[a][1] * Bh[b][1] + Bh[a][2] * Bh[b][2]);
         if (j >= nf) {  // coupling to a pinned vertex (held at rest)
-          for (int ax = 0; ax < 3; ++ax) {
-            const double xr = S.X[3 * (size_t)L.lib2orig[j] + ax];
-            cpin[(size_t)ax * nv + i] -= val * xr;
-          }
+          for (int ax = 0; ax < 3; ++ax) cpin[(size_t)ax * nv + i] -= val * S.X[3 * (size_t)L.lib2orig[j] + ax];
           continue;
         }
         if (i < nB && j < nB) {
@@ -464,13 +482,13 @@ void factorize(Scene& S) {
   }
   upload(S.cpin, cpin);
   // partitioned inverse: Zs = A_ss^{-1}, E_s = A_{I s} Zs, S = A_TT - sum E_s A_{s I}, Z = S^{-1}
-  std::vector<long long> zs_off(nsub + 1, 0), et_off(nsub + 1, 0);
+  std::vector<long long> zs_off(nsub + 1, 0), e_off(nsub + 1, 0);
   for (int s = 0; s < nsub; ++s) {
     const long long ns = L.sub_begin[s + 1] - L.sub_begin[s];
     zs_off[s + 1] = zs_off[s] + ns * ns;
-    et_off[s + 1] = et_off[s] + ns * (long long)L.Irows[s].size();
+    e_off[s + 1] = e_off[s] + ns * (long long)L.Irows[s].size();
   }
-  std::vector<double> Zs_all(zs_off[nsub]), Et_all(et_off[nsub]);
+  std::vector<double> Zs_all(zs_off[nsub]), Et_all(e_off[nsub]), E_all(e_off[nsub]);
   for (int s = 0; s < nsub; ++s) {
     const int ns = L.sub_begin[s + 1] - L.sub_begin[s];
     const int nI = (int)L.Irows[s].size();
@@ -478,10 +496,10 @@ void factorize(Scene& S) {
     if (!spd_inverse(Z, ns)) throw PdError{PD_ERR_FACTOR_NOT_SPD, "subdomain block not SPD"};
     std::copy(Z.begin(), Z.end(), Zs_all.begin() + zs_off[s]);
     // E_s (nI x ns) = A_Is (nI x ns) Z (ns x ns)
-    std::vector<double> Es((size_t)nI * ns, 0.0);
+    double* Es = &E_all[e_off[s]];
     for (int p = 0; p < nI; ++p) {
       const double* a = &AIs[s][(size_t)p * ns];
-      double* e = &Es[(size_t)p * ns];
+      double* e = Es + (size_t)p * ns;
       for (int u = 0; u < ns; ++u) {
         if (a[u] == 0.0) continue;
         const double* zr = &Z[(size_t)u * ns];
@@ -489,10 +507,10 @@ void factorize(Scene& S) {
       }
     }
     for (int v = 0; v < ns; ++v)
-      for (int p = 0; p < nI; ++p) Et_all[et_off[s] + (size_t)v * nI + p] = Es[(size_t)p * ns + v];
+      for (int p = 0; p < nI; ++p) Et_all[e_off[s] + (size_t)v * nI + p] = Es[(size_t)p * ns + v];
     // Schur update on the interface rows of s
     for (int p = 0; p < nI; ++p) {
-      const double* e = &Es[(size_t)p * ns];
+      const double* e = Es + (size_t)p * ns;
       const int ip = L.Irows[s][p];
       for (int q = 0; q < nI; ++q) {
         const double* a = &AIs[s][(size_t)q * ns];
@@ -503,105 +521,92 @@ void factorize(Scene& S) {
     }
   }
   if (nT > 0 && !spd_inverse(ATT, nT)) throw PdError{PD_ERR_FACTOR_NOT_SPD, "interface Schur complement not SPD"};
-  // upload the solve structure
-  DeviceSolve& D = S.S;
-  dfree(D.Zs); dfree(D.Et); dfree(D.Z); dfree(D.zs_off64); dfree(D.et_off64); dfree(D.sub_begin); dfree(D.ir_off);
-  dfree(D.irows); dfree(D.slot_of); dfree(D.row_slot_ptr); dfree(D.t_slots); dfree(D.bottom_items);
-  D.Zs = dalloc<double>(Zs_all.size()); upload(D.Zs, Zs_all);
-  D.Et = dalloc<double>(Et_all.size()); upload(D.Et, Et_all);
-  D.Z = dalloc<double>(ATT.size()); upload(D.Z, ATT);
-  D.zs_off64 = dalloc<long long>(nsub + 1); upload(D.zs_off64, zs_off);
-  D.et_off64 = dalloc<long long>(nsub + 1); upload(D.et_off64, et_off);
-  D.sub_begin = dalloc<int>(nsub + 1); upload(D.sub_begin, L.sub_begin);
+  // couplings of each interface row: (subdomain, row of E_s), subdomains ascending
   std::vector<int> ir_off(nsub + 1, 0), irows;
   for (int s = 0; s < nsub; ++s) {
     ir_off[s + 1] = ir_off[s] + (int)L.Irows[s].size();
     irows.insert(irows.end(), L.Irows[s].begin(), L.Irows[s].end());
   }
-  std::vector<int> rcount(nT + 1, 0);
-  for (int v : irows) rcount[v + 1]++;
-  for (int i = 0; i < nT; ++i) rcount[i + 1] += rcount[i];
-  std::vector<int> rfill(rcount.begin(), rcount.end() - 1), slot_of(irows.size());
-  for (size_t k = 0; k < irows.size(); ++k) slot_of[k] = rfill[irows[k]]++;
-  D.nslots = (int)irows.size();
+  std::vector<int> rl_ptr(nT + 1, 0);
+  for (int v : irows) rl_ptr[v + 1]++;
+  for (int i = 0; i < nT; ++i) rl_ptr[i + 1] += rl_ptr[i];
+  std::vector<int> rl_fill(rl_ptr.begin(), rl_ptr.end() - 1), rl_sub(irows.size()), rl_p(irows.size());
+  for (int s = 0; s < nsub; ++s)
+    for (int p = 0; p < (int)L.Irows[s].size(); ++p) {
+      const int pos = rl_fill[L.Irows[s][p]]++;
+      rl_sub[pos] = s;
+      rl_p[pos] = p;
+    }
+  // upload the solve structure
+  DeviceSolve& D = S.S;
+  dfree(D.Zs); dfree(D.Et); dfree(D.E); dfree(D.Z); dfree(D.zs_off); dfree(D.e_off); dfree(D.sub_of);
+  dfree(D.sub_begin); dfree(D.ir_off); dfree(D.irows); dfree(D.rl_ptr); dfree(D.rl_sub); dfree(D.rl_p); dfree(D.rT);
+  D.Zs = dalloc<double>(Zs_all.size()); upload(D.Zs, Zs_all);
+  D.Et = dalloc<double>(Et_all.size()); upload(D.Et, Et_all);
+  D.E = dalloc<double>(E_all.size()); upload(D.E, E_all);
+  D.Z = dalloc<double>(ATT.size()); upload(D.Z, ATT);
+  D.zs_off = dalloc<long long>(nsub + 1); upload(D.zs_off, zs_off);
+  D.e_off = dalloc<long long>(nsub + 1); upload(D.e_off, e_off);
+  std::vector<int> sub_of_B(sub_of.begin(), sub_of.begin() + nB);
+  D.sub_of = dalloc<int>(std::max(1, nB)); upload(D.sub_of, sub_of_B);
+  D.sub_begin = dalloc<int>(nsub + 1); upload(D.sub_begin, L.sub_begin);
   D.ir_off = dalloc<int>(nsub + 1); upload(D.ir_off, ir_off);
   D.irows = dalloc<int>(irows.size()); upload(D.irows, irows);
-  D.slot_of = dalloc<int>(slot_of.size()); upload(D.slot_of, slot_of);
-  D.row_slot_ptr = dalloc<int>(nT + 1); upload(D.row_slot_ptr, rcount);
-  D.t_slots = dalloc<double>(3 * (size_t)std::max(1, D.nslots));
-  // work lists: subdomain row chunks of 16 rows; interface rows spread over blocks
-  std::vector<int> items;
-  const int rows_per_item = 16;
-  for (int s = 0; s < nsub; ++s) {
-    const int ns = L.sub_begin[s + 1] - L.sub_begin[s];
-    for (int r = 0; r < ns; r += rows_per_item) {
-      items.push_back(s);
-      items.push_back(r);
-      items.push_back(std::min(ns, r + rows_per_item));
-    }
-  }
-  D.n_bottom_items = (int)items.size() / 3;
-  D.bottom_items = dalloc<int>(items.size()); upload(D.bottom_items, items);
-  D.top_rows = std::max(4, (nT + 255) / 256);
-  D.n_top_blocks = nT > 0 ? (nT + D.top_rows - 1) / D.top_rows : 0;
-  D.bytes = (Zs_all.size() + Et_all.size() + ATT.size()) * sizeof(double);
-  if (3 * (size_t)nT * sizeof(double) > 150 * 1024) throw PdError{PD_ERR_ALLOC, "interface exceeds the LDS budget"};
-  // per-block partial buffers
-  S.n_gather_blocks = nsub + (nT + kBlock - 1) / kBlock;
-  S.n_bottom_blocks = D.n_bottom_items + (nT + kBlock - 1) / kBlock;
-  dfree(S.gate_part); dfree(S.aa_part);
-  S.gate_part = dalloc<double>(4 * (size_t)std::max(1, S.n_gather_blocks));
-  S.aa_part = dalloc<double>(kAAPart * (size_t)std::max(1, S.n_bottom_blocks));
+  D.rl_ptr = dalloc<int>(nT + 1); upload(D.rl_ptr, rl_ptr);
+  D.rl_sub = dalloc<int>(rl_sub.size()); upload(D.rl_sub, rl_sub);
+  D.rl_p = dalloc<int>(rl_p.size()); upload(D.rl_p, rl_p);
+  D.rT = dalloc<double>(3 * (size_t)std::max(1, nT));
+  D.zs_entries = (double)Zs_all.size();
+  D.e_entries = (double)E_all.size();
+  D.bytes = (Zs_all.size() + Et_all.size() + E_all.size() + ATT.size()) * sizeof(double);
   PD_HIP(hipDeviceSynchronize());
   S.stale = false;
 }
 
 AdjState adj_state(Scene& S) {
   AdjState A;
-  A.n_vert_blocks = S.n_vert_blocks; A.kmax = S.kmax_bwd; A.eps = S.eps_adj;
-  A.contrib = S.contrib; A.qbar = S.qbar; A.mu = S.mu; A.r = S.r; A.z = S.z; A.p = S.p; A.Ap = S.Ap; A.w = S.wv;
-  A.part = S.red_part; A.scal = S.dstat + 8; A.ctl = S.ctl + kCtlAdj; A.done = S.ctl + kCtlAdj + 2; A.dstat = S.dstat + 16;
+  A.kmax = S.kmax_bwd; A.eps = S.eps_adj;
+  A.contrib = S.contrib; A.qbar = S.qbar; A.mu = S.mu; A.z = S.z; A.p = S.p; A.Ap = S.Ap; A.w = S.wv;
+  A.r0 = S.r0; A.r1 = S.r1;
+  A.ctl = S.ctl + kCtlAdj; A.done = S.ctl + kCtlAdj + 2; A.dstat = S.dstat + 16;
   return A;
 }
 
-void solve_plain(Scene& S, const double* rhs, double* out, const int* done, hipStream_t st) {
+// x = A~^{-1} rhs (plain mode: no reductions, `done` may be null)
+void solve_plain(Scene& S, const double* rhs, double* out, int* done, hipStream_t st) {
   const VertArgs V = vert_args(S);
   const SolveArgs A = solve_args(S);
+  const RedArgs R = red_args(S);
   StepState T = step_state(S);
-  T.done = const_cast<int*>(done);
-  PD_TIMED(S, kKGather, st, launch_gather_E(kModePlain, V, A, T, rhs, nullptr, 0, st));
-  PD_TIMED(S, kKTop, st, launch_top(kModePlain, V, A, T, rhs, out, 0, st));
-  PD_TIMED(S, kKBottom, st, launch_bottom(kModePlain, V, A, T, rhs, out, 0, st));
+  T.done = done;
+  const AdjState Ad = adj_state(S);
+  PD_TIMED(S, kKEb, st, launch_Eb(kModePlain, V, A, T, Ad, R, rhs, 0, st));
+  PD_TIMED(S, kKTop, st, launch_top(V, A, done, out, st));
+  PD_TIMED(S, kKBottom, st, launch_bottom(kModePlain, V, A, T, Ad, R, rhs, out, 0, st));
 }
 
 }  // namespace
-
 
 // Algorithmic bytes of one working launch of each timed kernel: what the
 // operation must read and write once (matrix blocks, element data, vectors),
 // not what the implementation re-reads.
 static double kernel_bytes(const Scene& S, int id) {
   const Layout& L = S.L;
-  const double nf = L.nf, nT = L.nT, ne = S.ne, nv = S.nv;
-  double zs = 0, et = 0;
-  for (int s = 0; s < L.nsub; ++s) {
-    const double ns = L.sub_begin[s + 1] - L.sub_begin[s];
-    zs += ns * ns;
-    et += ns * (double)L.Irows[s].size();
-  }
+  const double nf = L.nf, nT = L.nT, nB = L.nB, ne = S.ne, nv = S.nv, ninc = S.ninc;
+  const double zs = S.S.zs_entries, et = S.S.e_entries;
   switch (id) {
     case kKLocal:  // tet indices, D_m^-1, weight, positions in, 12 contributions out
-      return ne * (16.0 + 72.0 + 8.0 + 96.0) + 24.0 * nv;
-    case kKGather:  // contributions and constant part in, b out, E blocks, coupling slots out
-      return ne * 96.0 + 24.0 * nf * 2 + 8.0 * et + 24.0 * (double)S.S.nslots;
+      return ne * (16.0 + 72.0 + 8.0) + 24.0 * nv + 24.0 * ninc;
+    case kKGather:  // contributions and constant part in, b and q out
+      return 24.0 * ninc + 24.0 * nf * 4;
+    case kKEb:  // coupling blocks E_s, right-hand side in, interface right-hand side out
+      return 8.0 * et + 24.0 * nf + 24.0 * nT;
     case kKTop:  // inverse Schur block, interface right-hand side in, solution out
-      return 8.0 * nT * nT + 24.0 * nT * 2 + 24.0 * (double)S.S.nslots;
+      return 8.0 * nT * nT + 24.0 * nT * 2;
     case kKBottom:  // subdomain inverses and couplings, right-hand sides, solution out
-      return 8.0 * (zs + et) + 24.0 * (L.nB * 2 + nT);
-    case kKAA:  // q^, q, m difference pairs in, q out
-      return 24.0 * nf * (3 + 2 * std::max(1, S.m));
+      return 8.0 * (zs + et) + 24.0 * (nB * 2 + nT);
     case kKApplyK:  // tet indices, D_m^-1, weight, 30 Jacobian values, x in, contributions out
-      return ne * (16.0 + 72.0 + 8.0 + 240.0 + 96.0) + 24.0 * nv;
+      return ne * (16.0 + 72.0 + 8.0 + 240.0) + 24.0 * nv + 24.0 * ninc;
     default:
       return 0.0;
   }
@@ -725,21 +730,23 @@ int pd_step_forward(pd_scene* scene, const double* q_t, const double* v_t, const
   const VertArgs V = vert_args(S);
   const SolveArgs A = solve_args(S);
   const StepState T = step_state(S);
+  const AdjState Ad = adj_state(S);
+  const RedArgs R = red_args(S);
   // prologue: (1/h) B_beta q_t element terms, then q~, c, q^0
   launch_to_lib(V, q_t, S.qt, 0, st);
   launch_elem_GtG(E, S.qt, S.nv, S.bV, S.contrib, st);
-  launch_prologue(V, q_t, v_t, f_ext, q0, S.contrib, T, st);
-  PD_HIP(hipMemsetAsync(S.ctl, 0, (kCtlSize) * sizeof(int), st));
+  launch_prologue(V, q_t, v_t, f_ext, q0, T, st);
+  launch_zero_int(S.ctl, kCtlSize, st);
   int k = 0;
   int chunk = S.iters_per_check > 0 ? S.iters_per_check : std::max(3, S.last_fwd_iters + 1);
   for (;;) {
     const int kend = std::min(k + chunk, S.kmax_fwd);
     for (; k < kend; ++k) {
-      PD_TIMED(S, kKLocal, st, launch_local(E, S.q_cur, S.nv, S.contrib, T.done, S.ctl + kCtlNewton, st));
-      PD_TIMED(S, kKGather, st, launch_gather_E(kModeFwd, V, A, T, nullptr, nullptr, k, st));
-      PD_TIMED(S, kKTop, st, launch_top(kModeFwd, V, A, T, nullptr, nullptr, k, st));
-      PD_TIMED(S, kKBottom, st, launch_bottom(kModeFwd, V, A, T, nullptr, nullptr, k, st));
-      PD_TIMED(S, kKAA, st, launch_aa_update(V, T, k, st));
+      PD_TIMED(S, kKLocal, st, launch_local(E, T, R, S.q_cur, S.nv, V.nf, k, 1, st));
+      PD_TIMED(S, kKGather, st, launch_gather_fwd(V, T, R, k, st));
+      PD_TIMED(S, kKEb, st, launch_Eb(kModeFwd, V, A, T, Ad, R, nullptr, k, st));
+      PD_TIMED(S, kKTop, st, launch_top(V, A, T.done, S.qhat, st));
+      PD_TIMED(S, kKBottom, st, launch_bottom(kModeFwd, V, A, T, Ad, R, nullptr, S.qhat, k, st));
     }
     PD_HIP(hipMemcpyAsync(S.hctl, S.ctl, kCtlSize * sizeof(int), hipMemcpyDeviceToHost, st));
     PD_HIP(hipStreamSynchronize(st));
@@ -755,12 +762,13 @@ int pd_step_forward(pd_scene* scene, const double* q_t, const double* v_t, const
   const int iters = S.hctl[kCtlIters], status = S.hctl[kCtlStatus];
   if (S.hctl[kCtlDone]) S.last_fwd_iters = iters;
   // launches that did work: local step and gather at k = 0..iters, the
-  // interface solve, subdomain solve and mixing at k = 0..iters-1
+  // interface right-hand side, interface solve and subdomain solve at
+  // k = 0..iters-1 (at k = iters the gate decision ends the step)
   kt_work(S, kKLocal, iters + 1);
   kt_work(S, kKGather, iters + 1);
+  kt_work(S, kKEb, iters);
   kt_work(S, kKTop, iters);
   kt_work(S, kKBottom, iters);
-  kt_work(S, kKAA, iters);
   if (stats) {
     stats->iters = iters;
     stats->aa_resets = S.hctl[kCtlResets];
@@ -776,40 +784,43 @@ int pd_step_forward(pd_scene* scene, const double* q_t, const double* v_t, const
 static void adjoint_solve(Scene& S, hipStream_t st, double tau_force, double* bstat_host, const double* ck) {
   const ElemArgs E = elem_args(S);
   const VertArgs V = vert_args(S);
+  const SolveArgs Sv = solve_args(S);
   const AdjState Ad = adj_state(S);
-  const int n_part = tr_partial_blocks(E, V);
-  launch_tr_partials(E, V, ck, S.red_part, st);
-  launch_bwd_elem(E, V, ck, S.red_part, n_part, S.eps_tr, tau_force, S.jac, S.dstat + 4, st);
-  PD_HIP(hipMemsetAsync(S.ctl + kCtlAdj, 0, 4 * sizeof(int), st));
-  const int mode = S.adj_method == 1 ? kModeFixed : kModePCG;
-  if (mode == kModePCG) {
-    solve_plain(S, S.r, S.z, Ad.done, st);
-    launch_pcg_start(V, Ad, st);
+  const RedArgs R = red_args(S);
+  StepState T = step_state(S);
+  T.done = Ad.done;  // plain solves inside the adjoint stop with it
+  launch_tr_partials(E, V, R, ck, st);
+  launch_bwd_elem(E, V, R, ck, S.eps_tr, tau_force, 1, S.jac, S.dstat + 4, st);
+  launch_zero_int(S.ctl + kCtlAdj, 4, st);
+  const bool pcg = S.adj_method == 0;
+  if (pcg) {
+    PD_TIMED(S, kKEb, st, launch_Eb(kModePlain, V, Sv, T, Ad, R, S.r0, 0, st));
+    PD_TIMED(S, kKTop, st, launch_top(V, Sv, Ad.done, S.z, st));
+    PD_TIMED(S, kKBottom, st, launch_bottom(kModePCGInit, V, Sv, T, Ad, R, S.r0, S.z, 0, st));
   }
   int it = 0;
-  int chunk = 8;
+  int chunk = std::max(4, S.last_adj_iters + 1);
   for (;;) {
-    const int iend = std::min(it + chunk, S.kmax_bwd);
+    const int iend = std::min(it + chunk, S.kmax_bwd + 1);
     for (; it < iend; ++it) {
-      if (mode == kModePCG) {
-        PD_TIMED(S, kKApplyK, st, launch_apply_K(E, V, S.jac, S.p, S.contrib, Ad.done, st));
-        launch_adj_gather(kModePCG, V, Ad, it, st);
-        launch_pcg_alpha(V, Ad, it, st);
-        solve_plain(S, S.r, S.z, Ad.done, st);
-        launch_adj_dots(kModePCG, V, Ad, it, st);
-        launch_adj_next(kModePCG, V, Ad, it, st);
+      if (pcg) {
+        PD_TIMED(S, kKApplyK, st, launch_apply_K(kModePCG, E, V, Ad, R, S.jac, nullptr, it, st));
+        launch_adj_gather(kModePCG, V, Ad, R, it, st);
+        PD_TIMED(S, kKEb, st, launch_Eb(kModePCG, V, Sv, T, Ad, R, nullptr, it, st));
+        PD_TIMED(S, kKTop, st, launch_top(V, Sv, Ad.done, S.z, st));
+        PD_TIMED(S, kKBottom, st, launch_bottom(kModePCG, V, Sv, T, Ad, R, nullptr, S.z, it, st));
       } else {
-        PD_TIMED(S, kKApplyK, st, launch_apply_K(E, V, S.jac, S.mu, S.contrib, Ad.done, st));
-        launch_adj_gather(kModeFixed, V, Ad, it, st);
-        solve_plain(S, S.r, S.z, Ad.done, st);
-        launch_adj_dots(kModeFixed, V, Ad, it, st);
-        launch_adj_next(kModeFixed, V, Ad, it, st);
+        PD_TIMED(S, kKApplyK, st, launch_apply_K(kModeFixed, E, V, Ad, R, S.jac, nullptr, it, st));
+        launch_adj_gather(kModeFixed, V, Ad, R, it, st);
+        PD_TIMED(S, kKEb, st, launch_Eb(kModePlain, V, Sv, T, Ad, R, S.r0, it, st));
+        PD_TIMED(S, kKTop, st, launch_top(V, Sv, Ad.done, S.z, st));
+        PD_TIMED(S, kKBottom, st, launch_bottom(kModeFixed, V, Sv, T, Ad, R, S.r0, S.z, it, st));
       }
     }
     PD_HIP(hipMemcpyAsync(S.hctl, S.ctl, kCtlTotal * sizeof(int), hipMemcpyDeviceToHost, st));
     PD_HIP(hipStreamSynchronize(st));
     kt_flush(S);
-    if (S.hctl[kCtlAdj + 2] || it >= S.kmax_bwd) break;
+    if (S.hctl[kCtlAdj + 2] || it > S.kmax_bwd) break;
     chunk = 4;
   }
   PD_HIP(hipMemcpyAsync(S.hdstat, S.dstat, 32 * sizeof(double), hipMemcpyDeviceToHost, st));
@@ -819,11 +830,13 @@ static void adjoint_solve(Scene& S, hipStream_t st, double tau_force, double* bs
     bstat_host[4] = S.hdstat[16];
   }
   const int n_it = S.hctl[kCtlAdj];
-  const int n_solves = (mode == kModePCG) ? n_it + 1 : n_it;
+  if (S.hctl[kCtlAdj + 2]) S.last_adj_iters = n_it;
+  const int n_solves = pcg ? n_it + 1 : n_it;
   kt_work(S, kKApplyK, n_it);
-  kt_work(S, kKGather, n_solves);
+  kt_work(S, kKEb, n_solves);
   kt_work(S, kKTop, n_solves);
   kt_work(S, kKBottom, n_solves);
+  if (!S.hctl[kCtlAdj + 2]) throw PdError{PD_ERR_HIP, "adjoint loop ended without a decision"};
 }
 
 int pd_step_backward(pd_scene* scene, const void* ckpt, const double* gq_next, const double* gv_next, double* gq_t,
@@ -872,12 +885,11 @@ int pd_debug_local_rhs(pd_scene* scene, const double* q, double* b, void* stream
   hipStream_t st = (hipStream_t)stream;
   const ElemArgs E = elem_args(S);
   const VertArgs V = vert_args(S);
-  const SolveArgs A = solve_args(S);
-  StepState T = step_state(S);
-  T.done = nullptr;
+  const StepState T = step_state(S);
+  const RedArgs R = red_args(S);
   launch_to_lib(V, q, S.z, 0, st);
-  launch_local(E, S.z, S.nv, S.contrib, nullptr, nullptr, st);
-  launch_gather_E(kModeDebugGather, V, A, T, nullptr, S.wv, 0, st);
+  launch_local(E, T, R, S.z, S.nv, V.nf, 0, 0, st);
+  launch_gather_debug(V, S.contrib, S.wv, st);
   launch_from_lib(V, S.wv, b, 1, st);
   PD_HIP(hipStreamSynchronize(st));
   PD_HIP(hipGetLastError());
@@ -895,8 +907,8 @@ int pd_debug_apply_Ainv(pd_scene* scene, const double* r, double* x, void* strea
   PD_TRY
   hipStream_t st = (hipStream_t)stream;
   const VertArgs V = vert_args(S);
-  launch_to_lib(V, r, S.r, 1, st);
-  solve_plain(S, S.r, S.z, nullptr, st);
+  launch_to_lib(V, r, S.r1, 1, st);
+  solve_plain(S, S.r1, S.z, nullptr, st);
   launch_from_lib(V, S.z, x, 1, st);
   PD_HIP(hipStreamSynchronize(st));
   PD_HIP(hipGetLastError());
@@ -916,17 +928,16 @@ int pd_debug_apply_K(pd_scene* scene, const double* q, double tau, const double*
   const ElemArgs E = elem_args(S);
   const VertArgs V = vert_args(S);
   const AdjState Ad = adj_state(S);
+  const RedArgs R = red_args(S);
   // a checkpoint-shaped scratch whose q* slot holds q
-  double* ck = dalloc<double>(12 * (size_t)S.nv);
+  double* ck = S.ck_scratch;
   launch_to_lib(V, q, ck + 6 * (size_t)S.nv, 0, st);
-  launch_bwd_elem(E, V, ck, S.red_part, 0, S.eps_tr, tau, S.jac, S.dstat + 4, st);
+  launch_bwd_elem(E, V, R, ck, S.eps_tr, tau, 0, S.jac, S.dstat + 4, st);
   launch_to_lib(V, x, S.p, 1, st);
-  launch_apply_K(E, V, S.jac, S.p, S.contrib, nullptr, st);
-  PD_HIP(hipMemsetAsync(S.ctl + kCtlAdj + 2, 0, sizeof(int), st));
-  launch_adj_gather(kModeDebugGather, V, Ad, 0, st);
+  launch_apply_K(kModeDebug, E, V, Ad, R, S.jac, S.p, 0, st);
+  launch_adj_gather(kModeDebug, V, Ad, R, 0, st);
   launch_from_lib(V, S.wv, y, 1, st);
   PD_HIP(hipStreamSynchronize(st));
-  (void)hipFree(ck);
   PD_HIP(hipGetLastError());
   return PD_OK;
   PD_CATCH

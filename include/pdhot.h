@@ -101,7 +101,7 @@ typedef struct pd_fwd_stats {
   int32_t iters;
   int32_t aa_resets;
   int32_t status;
-  int32_t newton_max_iters;
+  int32_t newton_capped;  /* 1 if a tet's prox Newton reached its 50-iteration cap */
   double gate[4];
 } pd_fwd_stats;
 

@@ -45,7 +45,7 @@ class pd_solver_opts(ctypes.Structure):
 
 class pd_fwd_stats(ctypes.Structure):
     _fields_ = [("iters", ctypes.c_int32), ("aa_resets", ctypes.c_int32), ("status", ctypes.c_int32),
-                ("newton_max_iters", ctypes.c_int32), ("gate", ctypes.c_double * 4)]
+                ("newton_capped", ctypes.c_int32), ("gate", ctypes.c_double * 4)]
 
 
 class pd_bwd_stats(ctypes.Structure):
@@ -181,7 +181,7 @@ class Scene:
         rc = check(lib().pd_step_forward(self.ptr, _ptr(q_t), _ptr(v_t), _ptr(f_ext), _ptr(q0), _ptr(q_next),
                                          _ptr(v_next), _ptr(ckpt), ctypes.byref(st), _stream()), "pd_step_forward")
         return q_next, v_next, dict(iters=st.iters, aa_resets=st.aa_resets, status=st.status, rc=rc,
-                                    newton_max=st.newton_max_iters, gate=list(st.gate))
+                                    newton_capped=st.newton_capped, gate=list(st.gate))
 
     def step_backward(self, ckpt, gq_next, gv_next, g_logE=None, gq_t=None, gv_t=None, gf_ext=None):
         import torch

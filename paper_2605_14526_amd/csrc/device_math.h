@@ -8,6 +8,8 @@
 
 namespace pdhot {
 
+constexpr int kNewtonCap = 50;  // iteration cap of the prox Newton
+
 // ---------------------------------------------------------------------------
 // Symmetric 3x3 eigendecomposition by cyclic Jacobi rotations (the paper's
 // closed-form Jacobi sweep of Sec. 4.4).  On entry a00..a22 hold the matrix;
@@ -201,7 +203,7 @@ __device__ __forceinline__ int prox_stretch(const double sF[3], double mu, doubl
   const double sfmax = fmax(1.0, fmax(fabs(sF[0]), fmax(fabs(sF[1]), fabs(sF[2]))));
   const double gtol = 1e-13 * k * sfmax;
   int it = 0;
-  for (; it < 50; ++it) {
+  for (; it < kNewtonCap; ++it) {
     const double l = log(s[0] * s[1] * s[2]);
     double g[3], u[3];
 #pragma unroll
@@ -210,7 +212,9 @@ __device__ __forceinline__ int prox_stretch(const double sF[3], double mu, doubl
       g[i] = k * (s[i] - sF[i]) + mu * s[i] - mu * u[i] + lam * l * u[i];
     }
     if (fmax(fabs(g[0]), fmax(fabs(g[1]), fabs(g[2]))) <= gtol) break;
-    const double dc = mu - lam * l + lam;
+    // Hessian = diag(D) + lam u u^T: the rank-one part carries lam / s_i^2 of
+    // the diagonal, so D holds only the rest of it
+    const double dc = mu - lam * l;
     double D[3], d[3];
     bool diag_pos = true;
 #pragma unroll

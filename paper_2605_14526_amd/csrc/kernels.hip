@@ -219,119 +219,130 @@ __device__ __forceinline__ void aa_layout(const int* st, int m, int& nonempty, i
 
 // gamma = (dG^T dG + rho I)^{-1} dG^T g with rho = max(1e-6 |dG|_F^2 / m_c, 1e-12)
 // (Eq. aa_gamma) from the final Gram sums of iteration k-1; reliability guard
-// |gamma|_2 > 10.  Computed by thread 0, broadcast through LDS.
+// |gamma|_2 > 10.  The window M is a compile-time constant, so the Gram sums
+// and the M x M Cholesky stay in registers.  Computed by thread 0, broadcast
+// through LDS.
+template <int M>
 __device__ __forceinline__ void aa_prepare(const StepState& St, const RedArgs& R, int k, bool reduce, AAMix& out) {
-  __shared__ AAMix mx;
-  __shared__ double aav[kMaxWindow * kMaxWindow + kMaxWindow];
-  // Gram sums of iteration k-1, compact layout: G[j][l] at j*m + l, rhs[j] at m*m + j
-  constexpr int NA = kMaxWindow * kMaxWindow + kMaxWindow;
-  double tot[NA];
-  const int m = St.m;
-  const int W = m * m + m;
-  if (k >= 1 && m > 0) {
-    if (reduce) {
-      consume<NA>(R, kRedAA, tot, W);
-    } else {
+  if constexpr (M == 0) {
+    out.use = 0;
+    out.reset = 0;
+    out.nc = 0;
+    out.head = 0;
+    out.m = 0;
+  } else {
+    __shared__ AAMix mx;
+    // Gram sums of iteration k-1, compact layout: G[j][l] at j*M + l, rhs[j] at M*M + j
+    constexpr int NA = M * M + M;
+    __shared__ double aav[NA];
+    double tot[NA];
+    if (k >= 1) {
+      if (reduce) {
+        consume<NA>(R, kRedAA, tot);
+      } else {
 #pragma unroll
-      for (int j = 0; j < NA; ++j) tot[j] = (j < W) ? R.fin[kRedAA * kFinStride + j] : 0.0;
+        for (int j = 0; j < NA; ++j) tot[j] = R.fin[kRedAA * kFinStride + j];
+      }
+      if (threadIdx.x == 0)
+#pragma unroll
+        for (int j = 0; j < NA; ++j) aav[j] = tot[j];
     }
-    if (threadIdx.x == 0)
+    __syncthreads();
+    if (threadIdx.x == 0) {
+      mx.use = 0;
+      mx.reset = 0;
+      mx.m = M;
+      mx.nc = 0;
+      mx.head = 0;
 #pragma unroll
-      for (int j = 0; j < NA; ++j) aav[j] = tot[j];
-  }
-  __syncthreads();
-  if (threadIdx.x == 0) {
-    mx.use = 0;
-    mx.reset = 0;
-    mx.m = m;
-    mx.nc = 0;
-    mx.head = 0;
+      for (int j = 0; j < kMaxWindow; ++j) mx.gam[j] = 0.0;
+      if (k >= 1) {
+        int nonempty, nc, head, slot_new;
+        aa_layout(St.ctl + kCtlAA + 4 * ((k - 1) & 1), M, nonempty, nc, head, slot_new);
+        mx.nc = nc;
+        mx.head = head;
+        if (nc >= 1) {
+          // padded to M with identity rows (unused columns decouple)
+          double G[M][M], rhs[M];
+          double fro = 0.0;
 #pragma unroll
-    for (int j = 0; j < kMaxWindow; ++j) mx.gam[j] = 0.0;
-    if (k >= 1 && m > 0) {
-      int nonempty, nc, head, slot_new;
-      aa_layout(St.ctl + kCtlAA + 4 * ((k - 1) & 1), m, nonempty, nc, head, slot_new);
-      mx.nc = nc;
-      mx.head = head;
-      if (nc >= 1) {
-        // padded to kMaxWindow with identity rows (unused columns decouple),
-        // fully unrolled so every array stays in registers
-        double G[kMaxWindow][kMaxWindow], rhs[kMaxWindow];
-        double fro = 0.0;
+          for (int j = 0; j < M; ++j) {
 #pragma unroll
-        for (int j = 0; j < kMaxWindow; ++j) {
-#pragma unroll
-          for (int l = 0; l < kMaxWindow; ++l) {
-            double g = (j == l) ? 1.0 : 0.0;
-            if (j < nc && l < nc) g = (j <= l) ? aav[j * m + l] : aav[l * m + j];
-            G[j][l] = g;
+            for (int l = 0; l < M; ++l) {
+              double g = (j == l) ? 1.0 : 0.0;
+              if (j < nc && l < nc) g = (j <= l) ? aav[j * M + l] : aav[l * M + j];
+              G[j][l] = g;
+            }
+            rhs[j] = (j < nc) ? aav[M * M + j] : 0.0;
+            if (j < nc) fro += G[j][j];
           }
-          rhs[j] = (j < nc) ? aav[m * m + j] : 0.0;
-          if (j < nc) fro += G[j][j];
-        }
-        const double rho = fmax(1e-6 * fro / nc, 1e-12);
+          const double rho = fmax(1e-6 * fro / nc, 1e-12);
 #pragma unroll
-        for (int j = 0; j < kMaxWindow; ++j)
-          if (j < nc) G[j][j] += rho;
-        bool ok = true;
+          for (int j = 0; j < M; ++j)
+            if (j < nc) G[j][j] += rho;
+          bool ok = true;
 #pragma unroll
-        for (int j = 0; j < kMaxWindow; ++j) {
-          double d = G[j][j];
+          for (int j = 0; j < M; ++j) {
+            double d = G[j][j];
 #pragma unroll
-          for (int l = 0; l < j; ++l) d -= G[j][l] * G[j][l];
-          ok = ok && (d > 0.0);
-          d = sqrt(fmax(d, 1e-300));
-          G[j][j] = d;
+            for (int l = 0; l < j; ++l) d -= G[j][l] * G[j][l];
+            ok = ok && (d > 0.0);
+            d = sqrt(fmax(d, 1e-300));
+            G[j][j] = d;
 #pragma unroll
-          for (int i = j + 1; i < kMaxWindow; ++i) {
-            double t = G[i][j];
+            for (int i = j + 1; i < M; ++i) {
+              double t = G[i][j];
 #pragma unroll
-            for (int l = 0; l < j; ++l) t -= G[i][l] * G[j][l];
-            G[i][j] = t / d;
+              for (int l = 0; l < j; ++l) t -= G[i][l] * G[j][l];
+              G[i][j] = t / d;
+            }
           }
+          double y[M], gam[M];
+#pragma unroll
+          for (int i = 0; i < M; ++i) {
+            double t = rhs[i];
+#pragma unroll
+            for (int l = 0; l < i; ++l) t -= G[i][l] * y[l];
+            y[i] = t / G[i][i];
+          }
+#pragma unroll
+          for (int i = M - 1; i >= 0; --i) {
+            double t = y[i];
+#pragma unroll
+            for (int l = i + 1; l < M; ++l) t -= G[l][i] * gam[l];
+            gam[i] = t / G[i][i];
+          }
+          double nrm = 0.0;
+#pragma unroll
+          for (int i = 0; i < M; ++i) nrm += (i < nc) ? gam[i] * gam[i] : 0.0;
+          nrm = ok ? sqrt(nrm) : INFINITY;
+#pragma unroll
+          for (int i = 0; i < M; ++i) mx.gam[i] = (i < nc) ? gam[i] : 0.0;
+          mx.use = (nrm <= 10.0);
+          mx.reset = !mx.use;
         }
-        double y[kMaxWindow], gam[kMaxWindow];
-#pragma unroll
-        for (int i = 0; i < kMaxWindow; ++i) {
-          double t = rhs[i];
-#pragma unroll
-          for (int l = 0; l < i; ++l) t -= G[i][l] * y[l];
-          y[i] = t / G[i][i];
-        }
-#pragma unroll
-        for (int i = kMaxWindow - 1; i >= 0; --i) {
-          double t = y[i];
-#pragma unroll
-          for (int l = i + 1; l < kMaxWindow; ++l) t -= G[l][i] * gam[l];
-          gam[i] = t / G[i][i];
-        }
-        double nrm = 0.0;
-#pragma unroll
-        for (int i = 0; i < kMaxWindow; ++i) nrm += (i < nc) ? gam[i] * gam[i] : 0.0;
-        nrm = ok ? sqrt(nrm) : INFINITY;
-#pragma unroll
-        for (int i = 0; i < kMaxWindow; ++i) mx.gam[i] = (i < nc) ? gam[i] : 0.0;
-        mx.use = (nrm <= 10.0);
-        mx.reset = !mx.use;
       }
     }
+    __syncthreads();
+    out = mx;
+    __syncthreads();
   }
-  __syncthreads();
-  out = mx;
-  __syncthreads();
 }
 
 // q^k of a free vertex: q^ - (dQ + dG) gamma (Eq. aa_update) or q^ (k >= 1);
 // q_cur at k = 0 (the initial iterate)
+template <int M>
 __device__ __forceinline__ double aa_value(const StepState& St, const AAMix& mx, int nv, int a, int i, int k) {
   const int ix = a * nv + i;
   if (k == 0) return St.q_cur[ix];
   double q = St.qhat[ix];
-  if (mx.use) {
+  if (M > 0 && mx.use) {
 #pragma unroll
-    for (int j = 0; j < kMaxWindow; ++j)
+    for (int j = 0; j < M; ++j)
       if (j < mx.nc) {
-        const size_t cix = ((size_t)((mx.head + j) % mx.m) * 3 + a) * nv + i;
+        int slot = mx.head + j;
+        if (slot >= M) slot -= M;
+        const size_t cix = ((size_t)slot * 3 + a) * nv + i;
         q -= (St.dQ[cix] + St.dG[cix]) * mx.gam[j];
       }
   }
@@ -342,11 +353,12 @@ __device__ __forceinline__ double aa_value(const StepState& St, const AAMix& mx,
 // p*_e = U diag(s*) V^T of F_e = G_e q^k (Sec. 4.1 Eq. nh_prox) and its
 // contribution w_e V_e G_e^T p*_e (Eq. A_basic).  The SVD and the prox Newton
 // start from the tet's previous rotation and stretch ratios.
+template <int M>
 __global__ void __launch_bounds__(kBlock) k_local(ElemArgs E, StepState St, RedArgs R, const double* __restrict__ q,
-                                                  int nv, int nf, int k, int fwd, int* __restrict__ newton_max) {
+                                                  int nv, int nf, int k, int fwd, int* __restrict__ newton_cap) {
   if (fwd && block_done(St.done)) return;
   AAMix mx;
-  if (fwd) aa_prepare(St, R, k, true, mx);
+  if (fwd) aa_prepare<M>(St, R, k, true, mx);
   const int t = blockIdx.x * blockDim.x + threadIdx.x;
   if (t < E.ne) {
     int vi[4];
@@ -359,7 +371,7 @@ __global__ void __launch_bounds__(kBlock) k_local(ElemArgs E, StepState St, RedA
     for (int a = 0; a < 4; ++a)
 #pragma unroll
       for (int ax = 0; ax < 3; ++ax)
-        xv[a][ax] = (fwd && vi[a] < nf) ? aa_value(St, mx, nv, ax, vi[a], k) : q[ax * nv + vi[a]];
+        xv[a][ax] = (fwd && vi[a] < nf) ? aa_value<M>(St, mx, nv, ax, vi[a], k) : q[ax * nv + vi[a]];
     double F[9], U[9], V[9], sF[3], ss[3], rt[3];
     F_from_positions(E, t, xv, F);
     bool warm = true;
@@ -374,7 +386,9 @@ __global__ void __launch_bounds__(kBlock) k_local(ElemArgs E, StepState St, RedA
     svd3(F, U, sF, V, warm);
 #pragma unroll
     for (int j = 0; j < 3; ++j) rt[j] = E.rw[(size_t)j * E.ne + t];
-    prox_stretch(sF, E.mu_bar, E.lam_bar, E.k_bar, ss, rt);
+    const int nit = prox_stretch(sF, E.mu_bar, E.lam_bar, E.k_bar, ss, rt);
+    // cap hit: every writer stores the same value, so plain stores suffice
+    if (newton_cap && nit >= kNewtonCap) *newton_cap = 1;
     double P[9];
 #pragma unroll
     for (int i = 0; i < 3; ++i)
@@ -397,7 +411,6 @@ __global__ void __launch_bounds__(kBlock) k_local(ElemArgs E, StepState St, RedA
 #pragma unroll
     for (int j = 0; j < 3; ++j) E.rw[(size_t)j * E.ne + t] = (sF[j] > 1e-12) ? ss[j] / sF[j] : 0.0;
   }
-  (void)newton_max;
 }
 
 // G_e^T (w G_e x): contributions of the symmetric element operator w V G^T G
@@ -463,10 +476,11 @@ __global__ void __launch_bounds__(kBlock) k_prologue(VertArgs Vx, const double* 
 // written by the vertex's group); partial sums of the dual gate
 // (Eq. convergence_dual): |q^k - q^{k-1}|^2, |q^{k-1}|^2, |b^k - b^{k-1}|^2,
 // |b^{k-1}|^2.  Block 0 records the Anderson state of iteration k.
+template <int M>
 __global__ void __launch_bounds__(kBlock) k_gather_fwd(VertArgs Vx, StepState St, RedArgs R, int k) {
   if (block_done(St.done)) return;
   AAMix mx;
-  aa_prepare(St, R, k, false, mx);
+  aa_prepare<M>(St, R, k, false, mx);
   const int nv = Vx.nv;
   const int gtid = blockIdx.x * blockDim.x + threadIdx.x;
   const int i = gtid >> 3, l = gtid & 7;
@@ -478,7 +492,7 @@ __global__ void __launch_bounds__(kBlock) k_gather_fwd(VertArgs Vx, StepState St
 #pragma unroll
       for (int a = 0; a < 3; ++a) {
         const int ix = a * nv + i;
-        const double qk = aa_value(St, mx, nv, a, i, k);
+        const double qk = aa_value<M>(St, mx, nv, a, i, k);
         const double qp = (k == 0) ? St.q_prev[ix] : St.q_cur[ix];
         if (k > 0) {
           St.q_prev[ix] = qp;
@@ -497,7 +511,7 @@ __global__ void __launch_bounds__(kBlock) k_gather_fwd(VertArgs Vx, StepState St
   }
   if (blockIdx.x == 0 && threadIdx.x == 0 && k >= 1) {
     int* nxt = St.ctl + kCtlAA + 4 * (k & 1);
-    if (St.m <= 0 || mx.reset) {
+    if (M <= 0 || mx.reset) {
       nxt[0] = 0; nxt[1] = 0; nxt[2] = 0;
       if (mx.reset) St.ctl[kCtlResets] += 1;
     } else {
@@ -637,7 +651,7 @@ __global__ void __launch_bounds__(kBlock) k_top(VertArgs Vx, SolveArgs Sv, const
 //  PCG:     r <- r - alpha w, mu <- mu + alpha p, partial r.z, |z|^2, |mu|^2;
 //  PCG start: partial r.z, |z|^2, |mu|^2 of the first solve;
 //  fixed point: partial |z - mu|^2, |z|^2, then mu <- z.
-template <int MODE>
+template <int MODE, int M>
 __global__ void __launch_bounds__(kBottomThreads) k_bottom(VertArgs Vx, SolveArgs Sv, StepState St, AdjState A, RedArgs R,
                                                    const double* __restrict__ rhs, double* __restrict__ out, int k) {
   const int* done = (MODE == kModeFwd || MODE == kModePlain) ? St.done : A.done;
@@ -698,54 +712,55 @@ __global__ void __launch_bounds__(kBottomThreads) k_bottom(VertArgs Vx, SolveArg
   }
   if (MODE == kModePlain) return;
   // per-vertex work
-  double part[kRedWidth];
-#pragma unroll
-  for (int j = 0; j < kRedWidth; ++j) part[j] = 0.0;
   if (MODE == kModeFwd) {
-    const int m = St.m;
-    int nonempty, nc, head, slot_new;
-    aa_layout(St.ctl + kCtlAA + 4 * (k & 1), m, nonempty, nc, head, slot_new);
-    if (m > 0 && my_row >= 0) {
-      const int i = my_row;
+    if constexpr (M > 0) {
+      int nonempty, nc, head, slot_new;
+      aa_layout(St.ctl + kCtlAA + 4 * (k & 1), M, nonempty, nc, head, slot_new);
+      // Gram partial sums, compact layout: G[j][l] at j*M + l, rhs[j] at M*M + j
+      constexpr int NA = M * M + M;
+      double part[NA];
 #pragma unroll
-      for (int a = 0; a < 3; ++a) {
-        const int ix = a * nv + i;
-        const double qc = St.q_cur[ix];
-        const double g = dst[ix] - qc;
-        if (slot_new >= 0) {
-          const size_t cix = ((size_t)slot_new * 3 + a) * nv + i;
-          St.dG[cix] = g - St.g_last[ix];
-          St.dQ[cix] = qc - St.q_last[ix];
-        }
-        St.g_last[ix] = g;
-        St.q_last[ix] = qc;
-        double col[kMaxWindow];
+      for (int j = 0; j < NA; ++j) part[j] = 0.0;
+      if (my_row >= 0) {
+        const int i = my_row;
 #pragma unroll
-        for (int j = 0; j < kMaxWindow; ++j)
-          col[j] = (j < nc) ? St.dG[((size_t)((head + j) % m) * 3 + a) * nv + i] : 0.0;
+        for (int a = 0; a < 3; ++a) {
+          const int ix = a * nv + i;
+          const double qc = St.q_cur[ix];
+          const double g = dst[ix] - qc;
+          if (slot_new >= 0) {
+            const size_t cix = ((size_t)slot_new * 3 + a) * nv + i;
+            St.dG[cix] = g - St.g_last[ix];
+            St.dQ[cix] = qc - St.q_last[ix];
+          }
+          St.g_last[ix] = g;
+          St.q_last[ix] = qc;
+          double col[M];
 #pragma unroll
-        for (int j = 0; j < kMaxWindow; ++j) {
+          for (int j = 0; j < M; ++j) {
+            int slot = head + j;
+            if (slot >= M) slot -= M;
+            col[j] = (j < nc) ? St.dG[((size_t)slot * 3 + a) * nv + i] : 0.0;
+          }
 #pragma unroll
-          for (int l = j; l < kMaxWindow; ++l) part[j * kMaxWindow + l] += col[j] * col[l];
-          part[kMaxWindow * kMaxWindow + j] += col[j] * g;
+          for (int j = 0; j < M; ++j) {
+#pragma unroll
+            for (int l = 0; l < M; ++l)
+              if (l >= j) part[j * M + l] += col[j] * col[l];
+            part[M * M + j] += col[j] * g;
+          }
         }
       }
-    }
-    // block sum, stored compactly: G[j][l] at j*m + l, rhs[j] at m*m + j
-    constexpr int NA = kMaxWindow * kMaxWindow + kMaxWindow;
-    double vv[NA];
+      __shared__ double red[16 * NA];
+      block_sum<NA>(part, red);
+      if (threadIdx.x == 0) {
+        double* o = R.part + ((size_t)kRedAA * R.max_parts + blockIdx.x) * kRedWidth;
 #pragma unroll
-    for (int j = 0; j < NA; ++j) vv[j] = part[j];
-    __shared__ double red[16 * NA];
-    block_sum<NA>(vv, red);
-    if (threadIdx.x == 0 && m > 0) {
-      double* out = R.part + ((size_t)kRedAA * R.max_parts + blockIdx.x) * kRedWidth;
+        for (int j = 0; j < M; ++j) {
 #pragma unroll
-      for (int j = 0; j < kMaxWindow; ++j) {
-#pragma unroll
-        for (int l = 0; l < kMaxWindow; ++l)
-          if (j < m && l < m) out[j * m + l] = (j <= l) ? vv[j * kMaxWindow + l] : vv[l * kMaxWindow + j];
-        if (j < m) out[m * m + j] = vv[kMaxWindow * kMaxWindow + j];
+          for (int l = 0; l < M; ++l) o[j * M + l] = (j <= l) ? part[j * M + l] : part[l * M + j];
+          o[M * M + j] = part[M * M + j];
+        }
       }
     }
   } else {
@@ -1211,7 +1226,17 @@ int tr_blocks(int ne, int nf) { return (ne + kBlock - 1) / kBlock + (nf + kBlock
 
 void launch_local(const ElemArgs& E, const StepState& St, const RedArgs& R, const double* q, int nv, int nf,
                   int k, int fwd, hipStream_t s) {
-  hipLaunchKernelGGL(k_local, PD_GRID(E.ne), 0, s, E, St, R, q, nv, nf, k, fwd, fwd ? St.ctl + kCtlNewton : nullptr);
+  int* cap = fwd ? St.ctl + kCtlNewton : nullptr;
+#define PD_LOCAL(M) hipLaunchKernelGGL(k_local<M>, PD_GRID(E.ne), 0, s, E, St, R, q, nv, nf, k, fwd, cap)
+  switch (fwd ? St.m : 0) {
+    case 1: PD_LOCAL(1); break;
+    case 2: PD_LOCAL(2); break;
+    case 3: PD_LOCAL(3); break;
+    case 4: PD_LOCAL(4); break;
+    case 5: PD_LOCAL(5); break;
+    default: PD_LOCAL(0); break;
+  }
+#undef PD_LOCAL
 }
 void launch_elem_GtG(const ElemArgs& E, const double* x, int nv, const double* w, double* contrib, hipStream_t s) {
   hipLaunchKernelGGL(k_elem_GtG, PD_GRID(E.ne), 0, s, E, x, nv, w, contrib);
@@ -1221,7 +1246,17 @@ void launch_prologue(const VertArgs& V, const double* qt, const double* vt, cons
   hipLaunchKernelGGL(k_prologue, dim3(vert_group_blocks(V.nv)), dim3(kBlock), 0, s, V, qt, vt, f, q0, St);
 }
 void launch_gather_fwd(const VertArgs& V, const StepState& St, const RedArgs& R, int k, hipStream_t s) {
-  hipLaunchKernelGGL(k_gather_fwd, dim3(vert_group_blocks(V.nf)), dim3(kBlock), 0, s, V, St, R, k);
+  const dim3 g(vert_group_blocks(V.nf)), b(kBlock);
+#define PD_GATHER(M) hipLaunchKernelGGL(k_gather_fwd<M>, g, b, 0, s, V, St, R, k)
+  switch (St.m) {
+    case 1: PD_GATHER(1); break;
+    case 2: PD_GATHER(2); break;
+    case 3: PD_GATHER(3); break;
+    case 4: PD_GATHER(4); break;
+    case 5: PD_GATHER(5); break;
+    default: PD_GATHER(0); break;
+  }
+#undef PD_GATHER
 }
 void launch_gather_debug(const VertArgs& V, const double* contrib, double* out, hipStream_t s) {
   hipLaunchKernelGGL(k_gather_debug, dim3(vert_group_blocks(V.nf)), dim3(kBlock), 0, s, V, contrib, out);
@@ -1244,13 +1279,23 @@ void launch_bottom(int mode, const VertArgs& V, const SolveArgs& S, const StepSt
                    const RedArgs& R, const double* rhs, double* out, int k, hipStream_t s) {
   const int nblk = bottom_blocks(S.nB, S.nT);
   if (nblk == 0) return;
-#define PD_BOTTOM(M) hipLaunchKernelGGL(k_bottom<M>, dim3(nblk), dim3(kBottomThreads), 0, s, V, S, St, A, R, rhs, out, k)
+#define PD_BOTTOM(MODE, M) \
+  hipLaunchKernelGGL((k_bottom<MODE, M>), dim3(nblk), dim3(kBottomThreads), 0, s, V, S, St, A, R, rhs, out, k)
   switch (mode) {
-    case kModeFwd: PD_BOTTOM(kModeFwd); break;
-    case kModePCG: PD_BOTTOM(kModePCG); break;
-    case kModePCGInit: PD_BOTTOM(kModePCGInit); break;
-    case kModeFixed: PD_BOTTOM(kModeFixed); break;
-    default: PD_BOTTOM(kModePlain); break;
+    case kModeFwd:
+      switch (St.m) {
+        case 1: PD_BOTTOM(kModeFwd, 1); break;
+        case 2: PD_BOTTOM(kModeFwd, 2); break;
+        case 3: PD_BOTTOM(kModeFwd, 3); break;
+        case 4: PD_BOTTOM(kModeFwd, 4); break;
+        case 5: PD_BOTTOM(kModeFwd, 5); break;
+        default: PD_BOTTOM(kModeFwd, 0); break;
+      }
+      break;
+    case kModePCG: PD_BOTTOM(kModePCG, 0); break;
+    case kModePCGInit: PD_BOTTOM(kModePCGInit, 0); break;
+    case kModeFixed: PD_BOTTOM(kModeFixed, 0); break;
+    default: PD_BOTTOM(kModePlain, 0); break;
   }
 #undef PD_BOTTOM
 }

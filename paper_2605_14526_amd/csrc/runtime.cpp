@@ -773,7 +773,7 @@ int pd_step_forward(pd_scene* scene, const double* q_t, const double* v_t, const
     stats->iters = iters;
     stats->aa_resets = S.hctl[kCtlResets];
     stats->status = status;
-    stats->newton_max_iters = S.hctl[kCtlNewton];
+    stats->newton_capped = S.hctl[kCtlNewton];
     for (int j = 0; j < 4; ++j) stats->gate[j] = S.hdstat[j];
   }
   if (!S.hctl[kCtlDone]) throw PdError{PD_ERR_HIP, "forward loop ended without a decision"};

@@ -79,7 +79,16 @@ typedef struct pd_material_desc {
  * max_sub: largest subdomain (vertices) of the two-level partitioned inverse
  *          (0 = library default).
  * iters_per_check: PD iterations issued between convergence checks of the
- *          host (0 = adaptive). */
+ *          host (0 = adaptive).
+ * adj_warm: start of the adjoint iteration of pd_step_backward: 0 = zero
+ *          (as in Alg. 2), 1 = the previous call's solution, 2 = the linear
+ *          extrapolation 2 mu_{t+1} - mu_{t+2} of the two previous calls.  The
+ *          history belongs to the scene; pd_adjoint_reset clears it (call it
+ *          at the start of each reverse sweep); refactorization clears it too.
+ *          The solve still runs to eps_adj, so only the iteration count
+ *          depends on the start.
+ * fwd_start: first PD iterate when pd_step_forward gets no q0: 0 = q_t (as in
+ *          Alg. 1), 1 = the inertial guess q_t + h v_t. */
 typedef struct pd_solver_opts {
   double h;
   double gravity[3];
@@ -93,6 +102,8 @@ typedef struct pd_solver_opts {
   int32_t adj_method;
   int32_t max_sub;
   int32_t iters_per_check;
+  int32_t adj_warm;
+  int32_t fwd_start;
 } pd_solver_opts;
 
 /* Forward statistics. gate[0..3] = |q^k - q^{k-1}|, |q^{k-1}|, |b^k - b^{k-1}|,
@@ -137,8 +148,9 @@ int pd_scene_set_material(pd_scene* scene, const double* log_E_host);
  * every solve (Sec. 4.6 Eq. Ainv_STS in role).  Host work plus one upload. */
 int pd_scene_factorize(pd_scene* scene, void* stream);
 
-/* Scene facts. info[0..6] = n_verts, n_tets, n_free, n_subdomains,
- * n_interface, aa_window, factor bytes on the device (as double). means[0..3] =
+/* Scene facts. info[0..7] = n_verts, n_tets, n_free, n_subdomains,
+ * n_interface, aa_window, factor bytes on the device, most subdomains bordered
+ * by one interface vertex (as double; info holds 8 values). means[0..3] =
  * mu_bar, lam_bar, k_bar, mu_ref (may be NULL). */
 int pd_scene_info(const pd_scene* scene, double* info, double* means);
 
@@ -147,9 +159,10 @@ size_t pd_ckpt_bytes(const pd_scene* scene);
 
 /* One forward step (Alg. 1, no contact).
  * q_t, v_t: current state; f_ext: external force per vertex (NULL = none;
- * gravity from the options is added); q0: initial iterate (NULL = q_t,
- * e.g. a learned warm start); outputs q_next, v_next (may alias nothing else);
- * ckpt: caller-allocated device buffer of pd_ckpt_bytes() bytes or NULL.
+ * gravity from the options is added); q0: initial iterate, e.g. a learned
+ * warm start (NULL = q_t, or q_t + h v_t with fwd_start = 1); outputs q_next,
+ * v_next (may alias nothing else); ckpt: caller-allocated device buffer of
+ * pd_ckpt_bytes() bytes or NULL.
  * Pinned vertices are held at their rest positions.  Runs the local step,
  * RHS assembly, dual gate, global solve and Anderson mixing until the gate
  * holds (Secs. 4.1-4.3). */
@@ -168,6 +181,10 @@ int pd_step_backward(pd_scene* scene, const void* ckpt, const double* gq_next, c
                      double* gq_t, double* gv_t, double* gf_ext, double* g_logE_accum, pd_bwd_stats* stats,
                      void* stream);
 
+/* Forget the adjoint solutions kept for the warm start (adj_warm > 0), so the
+ * next pd_step_backward starts from zero.  No device work. */
+int pd_adjoint_reset(pd_scene* scene);
+
 /* Diagnostic entry points (stage parity), all device pointers, n_verts x 3.
  * pd_debug_local_rhs: b = sum_e w_e V_e G_e^T p*_e(G_e q) (Eq. A_basic without
  *   its constant part), free rows (pinned rows zero).
@@ -178,13 +195,13 @@ int pd_debug_local_rhs(pd_scene* scene, const double* q, double* b, void* stream
 int pd_debug_apply_Ainv(pd_scene* scene, const double* r, double* x, void* stream);
 int pd_debug_apply_K(pd_scene* scene, const double* q, double tau, const double* x, double* y, void* stream);
 
-/* Kernel timing for roofline reports: HIP events recorded on the caller's
- * stream around every launch of one kernel inside pd_step_forward /
- * pd_step_backward.  kernel: 0 local step, 1 right-hand-side gather,
- * 2 interface (Schur) solve, 3 subdomain solve, 4 interface right-hand side
- * (coupling products), 5 K apply;
- * -1 stops timing.  Resets the totals.  Instrumentation only: it adds two
- * event records per launch of the chosen kernel. */
+/* Kernel timing for roofline reports: every launch of one kernel inside
+ * pd_step_forward / pd_step_backward carries a start and a stop HIP event
+ * stamped by the dispatch itself on the caller's stream, so the elapsed time
+ * is the kernel's own execution time.  kernel: 0 local step, 1 right-hand-side
+ * gather, 2 interface (Schur) solve, 3 subdomain solve, 4 interface
+ * right-hand side (coupling products), 5 K apply; -1 stops timing.  Resets the
+ * totals.  Instrumentation only. */
 int pd_kernel_timer(pd_scene* scene, int kernel);
 /* Totals since pd_kernel_timer: summed launch durations (ms), launches timed,
  * launches that did work (the others exit at once after convergence), and

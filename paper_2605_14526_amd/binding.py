@@ -23,7 +23,7 @@ ERRORS = {-1: "PD_ERR_INVALID_ARG", -2: "PD_ERR_DEGENERATE_TET", -3: "PD_ERR_NON
 
 EXPORTED = ["pd_scene_create", "pd_scene_destroy", "pd_scene_set_material", "pd_scene_factorize", "pd_scene_info",
             "pd_ckpt_bytes", "pd_step_forward", "pd_step_backward", "pd_debug_local_rhs", "pd_debug_apply_Ainv",
-            "pd_debug_apply_K", "pd_kernel_timer", "pd_kernel_timer_read", "pd_last_error"]
+            "pd_debug_apply_K", "pd_kernel_timer", "pd_kernel_timer_read", "pd_adjoint_reset", "pd_last_error"]
 
 
 class pd_mesh_desc(ctypes.Structure):
@@ -40,7 +40,8 @@ class pd_solver_opts(ctypes.Structure):
     _fields_ = [("h", ctypes.c_double), ("gravity", ctypes.c_double * 3), ("aa_window", ctypes.c_int32),
                 ("eps_rel", ctypes.c_double), ("eps_abs", ctypes.c_double), ("kmax_fwd", ctypes.c_int32),
                 ("kmax_bwd", ctypes.c_int32), ("eps_adj", ctypes.c_double), ("eps_tr", ctypes.c_double),
-                ("adj_method", ctypes.c_int32), ("max_sub", ctypes.c_int32), ("iters_per_check", ctypes.c_int32)]
+                ("adj_method", ctypes.c_int32), ("max_sub", ctypes.c_int32), ("iters_per_check", ctypes.c_int32),
+                ("adj_warm", ctypes.c_int32), ("fwd_start", ctypes.c_int32)]
 
 
 class pd_fwd_stats(ctypes.Structure):
@@ -82,6 +83,7 @@ def lib() -> ctypes.CDLL:
     L.pd_debug_apply_K.argtypes = [vp, vp, dbl, vp, vp, vp]
     L.pd_kernel_timer.argtypes = [vp, i32]
     L.pd_kernel_timer_read.argtypes = [vp, vp, vp, vp, vp]
+    L.pd_adjoint_reset.argtypes = [vp]
     L.pd_last_error.restype = ctypes.c_char_p
     for name in EXPORTED:
         getattr(L, name)
@@ -113,7 +115,7 @@ class Scene:
 
     def __init__(self, X, tets, pinned, log_E, nu, rho, alpha, beta0, h, gravity=(0.0, 0.0, 0.0), aa_window=1,
                  eps_rel=1e-6, eps_abs=1e-12, kmax_fwd=1000, kmax_bwd=1000, eps_adj=1e-6, eps_tr=0.1,
-                 adj_method=0, max_sub=0, iters_per_check=0):
+                 adj_method=0, max_sub=0, iters_per_check=0, adj_warm=0, fwd_start=0):
         L = lib()
         self._X = np.ascontiguousarray(X, dtype=np.float64)
         self._tets = np.ascontiguousarray(tets, dtype=np.int32)
@@ -125,7 +127,7 @@ class Scene:
                             self._pinned.ctypes.data)
         mat = pd_material_desc(self._logE.ctypes.data, nu, rho, alpha, beta0)
         opts = pd_solver_opts(h, (ctypes.c_double * 3)(*gravity), aa_window, eps_rel, eps_abs, kmax_fwd, kmax_bwd,
-                              eps_adj, eps_tr, adj_method, max_sub, iters_per_check)
+                              eps_adj, eps_tr, adj_method, max_sub, iters_per_check, adj_warm, fwd_start)
         self.h = float(h)
         ptr = ctypes.c_void_p()
         check(L.pd_scene_create(ctypes.byref(mesh), ctypes.byref(mat), ctypes.byref(opts), ctypes.byref(ptr)),
@@ -151,10 +153,11 @@ class Scene:
             pass
 
     def info(self):
-        info = (ctypes.c_double * 7)()
+        info = (ctypes.c_double * 8)()
         means = (ctypes.c_double * 4)()
         check(lib().pd_scene_info(self.ptr, info, means), "pd_scene_info")
-        keys = ["n_verts", "n_tets", "n_free", "n_subdomains", "n_interface", "aa_window", "factor_bytes"]
+        keys = ["n_verts", "n_tets", "n_free", "n_subdomains", "n_interface", "aa_window", "factor_bytes",
+                "max_couplings"]
         d = {k: info[i] for i, k in enumerate(keys)}
         d.update(mu_bar=means[0], lam_bar=means[1], k_bar=means[2], mu_ref=means[3])
         return d
@@ -197,6 +200,10 @@ class Scene:
         self.last_bwd_stats = dict(adj_iters=st.adj_iters, status=st.status, rho=st.rho, tau=st.tau,
                                    dphi_act=st.dphi_act, dphi_mod=st.dphi_mod, residual=st.residual, rc=rc)
         return gq_t, gv_t, gf_ext, g_logE, self.last_bwd_stats
+
+    def adjoint_reset(self):
+        """Start the next backward step from zero (clears the adjoint warm-start history)."""
+        check(lib().pd_adjoint_reset(self.ptr), "pd_adjoint_reset")
 
     def kernel_timer(self, kernel: int):
         check(lib().pd_kernel_timer(self.ptr, int(kernel)), "pd_kernel_timer")

@@ -15,7 +15,9 @@ enum {
   kModeDebug = 2,
   kModePCG = 3,
   kModePCGInit = 4,
-  kModeFixed = 5
+  kModeFixed = 5,
+  kModeAmK = 6,   // (A~ - K) x element terms (adjoint warm start)
+  kModeInit = 7   // r = q bar - (A~ - K) mu (adjoint warm start)
 };
 
 // device control block (int): done flag, final iteration count, status,
@@ -75,7 +77,7 @@ struct SolveArgs {
   const double* Zs;         // per subdomain ns x ns
   const long long* zs_off;
   const double* Et;         // per subdomain ns x nI (row v: E_s[:, v])
-  const double* E;          // per subdomain nI x ns (row p: E_s[p, :])
+  const double* E;          // per interface row: E_s[p, :] of its couplings, concatenated
   const long long* e_off;
   const int* ir_off;        // nsub + 1
   const int* irows;         // concatenated interface rows of each subdomain
@@ -84,6 +86,12 @@ struct SolveArgs {
   const int* rl_p;          // row of E_s of each coupling
   const double* Z;          // nT x nT
   double* rT;               // 3 x nT interface right-hand side
+  const Cpl* cpl;           // nT x kMaxCoup coupling descriptors
+  const ERow* erow;         // nT: the row's couplings in E (row-concatenated)
+  const BRow* brow;         // nB subdomain-row descriptors
+  const BOff* boff;
+  double* xsT;              // 3 x n_irows interface solution gathered per subdomain
+  int n_irows;
 };
 
 struct StepState {
@@ -101,11 +109,18 @@ struct AdjState {
   int kmax;
   double eps;
   double *contrib, *qbar, *mu, *z, *p, *Ap, *w;
-  double *r0, *r1;  // residual, double-buffered by iteration parity (PCG reads r^k while writing r^{k+1})
+  double *r0, *r1;  // residual, double-buffered by iteration parity (PCG reads r^k while writing r^{k+1});
+                    // r0 also holds q bar + K mu (fixed point)
   int* ctl;       // [iters, status]
   int* done;
   double* dstat;  // [residual]
 };
+
+// Per-launch timing: arm a start/stop event pair for the next kernel launch of
+// this thread (stamped by the dispatch itself); launch_events_used() tells
+// whether a launch consumed them and disarms.
+void arm_launch_events(hipEvent_t start, hipEvent_t stop);
+bool launch_events_used();
 
 int vert_group_blocks(int n);
 int bottom_blocks(int nB, int nT);
@@ -114,12 +129,12 @@ void launch_local(const ElemArgs& E, const StepState& St, const RedArgs& R, cons
                   int k, int fwd, hipStream_t s);
 void launch_elem_GtG(const ElemArgs& E, const double* x, int nv, const double* w, double* contrib, hipStream_t s);
 void launch_prologue(const VertArgs& V, const double* qt, const double* vt, const double* f, const double* q0,
-                     const StepState& St, hipStream_t s);
+                     int inertial, const StepState& St, hipStream_t s);
 void launch_gather_fwd(const VertArgs& V, const StepState& St, const RedArgs& R, int k, hipStream_t s);
 void launch_gather_debug(const VertArgs& V, const double* contrib, double* out, hipStream_t s);
 void launch_Eb(int mode, const VertArgs& V, const SolveArgs& S, const StepState& St, const AdjState& A,
                const RedArgs& R, const double* rhs, int k, hipStream_t s);
-void launch_top(const VertArgs& V, const SolveArgs& S, const int* done, double* out, hipStream_t s);
+void launch_top(const VertArgs& V, const SolveArgs& S, double* out, hipStream_t s);
 void launch_bottom(int mode, const VertArgs& V, const SolveArgs& S, const StepState& St, const AdjState& A,
                    const RedArgs& R, const double* rhs, double* out, int k, hipStream_t s);
 void launch_epilogue(const VertArgs& V, const StepState& St, double* q_next, double* v_next, double* ckpt,
@@ -132,7 +147,8 @@ void launch_bwd_elem(const ElemArgs& E, const VertArgs& V, const RedArgs& R, con
 void launch_apply_K(int mode, const ElemArgs& E, const VertArgs& V, const AdjState& A, const RedArgs& R,
                     const double* jac, const double* x, int it, hipStream_t s);
 void launch_adj_gather(int mode, const VertArgs& V, const AdjState& A, const RedArgs& R, int it, hipStream_t s);
-void launch_bwd_prologue(const VertArgs& V, const AdjState& A, const double* gq, const double* gv, hipStream_t s);
+void launch_bwd_prologue(const VertArgs& V, const AdjState& A, const double* gq, const double* gv, int warm,
+                         const double* h1, const double* h2, hipStream_t s);
 void launch_grad_elem(const ElemArgs& E, const VertArgs& V, const double* ck, const double* jac, const double* mu,
                       double* contrib, double* g_logE, hipStream_t s);
 void launch_grad_vert(const VertArgs& V, const double* mu, const double* contrib, const double* gv_next, double* gq_t,

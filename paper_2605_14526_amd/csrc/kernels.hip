@@ -7,15 +7,20 @@
 // vertex-incidence order, so the right-hand-side gathers read contiguous
 // memory with 8 lanes per vertex (no atomics, fixed summation order); every
 // dense block product of the partitioned inverse runs one wave per row; block
-// partial sums are reduced by the last block of the producing kernel in a
-// fixed order, so all results are bitwise reproducible.  The Anderson update
+// partial sums are reduced in a fixed order by the kernel that consumes them,
+// so all results are bitwise reproducible.  The Anderson update
 // of iteration k-1 is applied on the fly by the two kernels that start
 // iteration k, and the conjugate-gradient direction update likewise by the two
-// kernels that start the next adjoint iteration.
+// kernels that start the next adjoint iteration.  Each kernel requests every
+// load that does not depend on another load (descriptors, own state, partial
+// sums, the done flag) before it waits for any of them, so a stage costs about
+// two dependent memory round trips.
 //
 // Vector layout: SoA over the library vertex order, x | y | z, stride nv.
 // Per-tet arrays: SoA, stride ne.  Contributions: [axis][incidence position].
 #include "kernels.h"
+
+#include <hip/hip_ext.h>
 
 #include "device_math.h"
 
@@ -57,17 +62,6 @@ __device__ __forceinline__ void block_sum(double (&v)[NV], double* lds /* >= 16*
     }
   }
   __syncthreads();
-}
-
-// The done flag read once per block (thread 0) and broadcast, so every wave of
-// a block takes the same early exit even while another block sets the flag.
-__device__ __forceinline__ bool block_done(const int* done) {
-  __shared__ int flag;
-  if (threadIdx.x == 0) flag = done ? __hip_atomic_load(done, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) : 0;
-  __syncthreads();
-  const bool r = flag != 0;
-  __syncthreads();
-  return r;
 }
 
 // Producer side: block sum of N values, written by thread 0 as partial `idx`
@@ -137,18 +131,6 @@ __device__ __forceinline__ void load_F(const ElemArgs& E, const double* __restri
     for (int j = 0; j < 3; ++j) F[3 * i + j] = Ds[3 * i] * Bm[j] + Ds[3 * i + 1] * Bm[3 + j] + Ds[3 * i + 2] * Bm[6 + j];
 }
 
-__device__ __forceinline__ void F_from_positions(const ElemArgs& E, int t, const double xv[4][3], double F[9]) {
-  double Bm[9];
-#pragma unroll
-  for (int i = 0; i < 9; ++i) Bm[i] = E.Bm[i * E.ne + t];
-#pragma unroll
-  for (int ax = 0; ax < 3; ++ax) {
-    const double d1 = xv[1][ax] - xv[0][ax], d2 = xv[2][ax] - xv[0][ax], d3 = xv[3][ax] - xv[0][ax];
-#pragma unroll
-    for (int j = 0; j < 3; ++j) F[3 * ax + j] = d1 * Bm[j] + d2 * Bm[3 + j] + d3 * Bm[6 + j];
-  }
-}
-
 // w G_e^T P written to the incidence positions of the tet's free vertices:
 // vertex a (1..3) receives w P r_a (r_a = row a-1 of D_m^{-1}), vertex 0 minus
 // their sum.
@@ -191,8 +173,70 @@ __device__ __forceinline__ void gather8(const int* __restrict__ inc_ptr, const d
   out[2] = group8_sum(s2);
 }
 
+// Element data of tet t: vertex ids, incidence positions, D_m^{-1}.
+struct TetData {
+  int vi[4], pos[4];
+  double Bm[9];
+};
+
+__device__ __forceinline__ void load_tet(const ElemArgs& E, int t, TetData& T) {
+#pragma unroll
+  for (int a = 0; a < 4; ++a) {
+    T.vi[a] = E.tv[a * E.ne + t];
+    T.pos[a] = E.tinc[a * E.ne + t];
+  }
+#pragma unroll
+  for (int i = 0; i < 9; ++i) T.Bm[i] = E.Bm[i * E.ne + t];
+}
+
+__device__ __forceinline__ void grad_of(const TetData& T, const double xv[4][3], double F[9]) {
+#pragma unroll
+  for (int ax = 0; ax < 3; ++ax) {
+    const double d1 = xv[1][ax] - xv[0][ax], d2 = xv[2][ax] - xv[0][ax], d3 = xv[3][ax] - xv[0][ax];
+#pragma unroll
+    for (int j = 0; j < 3; ++j) F[3 * ax + j] = d1 * T.Bm[j] + d2 * T.Bm[3 + j] + d3 * T.Bm[6 + j];
+  }
+}
+
+// G_e^T P written to the incidence positions of the tet's free vertices.
+__device__ __forceinline__ void store_GtP(const TetData& T, double* __restrict__ contrib, int ninc, const double P[9]) {
+  double c0[3] = {0, 0, 0};
+#pragma unroll
+  for (int a = 1; a < 4; ++a)
+#pragma unroll
+    for (int ax = 0; ax < 3; ++ax) {
+      const double v = P[3 * ax] * T.Bm[3 * (a - 1)] + P[3 * ax + 1] * T.Bm[3 * (a - 1) + 1] +
+                       P[3 * ax + 2] * T.Bm[3 * (a - 1) + 2];
+      if (T.pos[a] >= 0) contrib[(size_t)ax * ninc + T.pos[a]] = v;
+      c0[ax] -= v;
+    }
+  if (T.pos[0] >= 0)
+#pragma unroll
+    for (int ax = 0; ax < 3; ++ax) contrib[(size_t)ax * ninc + T.pos[0]] = c0[ax];
+}
+
+// The warm start of the tet's next SVD and prox Newton: the rotation V,
+// re-orthonormalised (Gram-Schmidt on its columns), and the ratios s*/sF.
+__device__ __forceinline__ void store_warm(const ElemArgs& E, int t, const double V[9], const double sF[3],
+                                           const double ss[3]) {
+  double c0[3] = {V[0], V[3], V[6]}, c1[3] = {V[1], V[4], V[7]};
+  double n0 = rsqrt(c0[0] * c0[0] + c0[1] * c0[1] + c0[2] * c0[2]);
+  c0[0] *= n0; c0[1] *= n0; c0[2] *= n0;
+  const double d01 = c0[0] * c1[0] + c0[1] * c1[1] + c0[2] * c1[2];
+  c1[0] -= d01 * c0[0]; c1[1] -= d01 * c0[1]; c1[2] -= d01 * c0[2];
+  double n1 = rsqrt(c1[0] * c1[0] + c1[1] * c1[1] + c1[2] * c1[2]);
+  c1[0] *= n1; c1[1] *= n1; c1[2] *= n1;
+  const double c2[3] = {c0[1] * c1[2] - c0[2] * c1[1], c0[2] * c1[0] - c0[0] * c1[2], c0[0] * c1[1] - c0[1] * c1[0]};
+  const double Vn[9] = {c0[0], c1[0], c2[0], c0[1], c1[1], c2[1], c0[2], c1[2], c2[2]};
+#pragma unroll
+  for (int j = 0; j < 9; ++j) E.Vw[(size_t)j * E.ne + t] = Vn[j];
+#pragma unroll
+  for (int j = 0; j < 3; ++j) E.rw[(size_t)j * E.ne + t] = (sF[j] > 1e-12) ? ss[j] / sF[j] : 0.0;
+}
+
 // ---------------------------------------------------------------- Anderson mixing
 struct AAMix {
+  int stop;       // the loop has already stopped (done flag)
   int use;        // apply the mixing
   int reset;      // |gamma| > 10: history dropped
   int nc, head;   // columns after the append of iteration k-1
@@ -221,44 +265,45 @@ __device__ __forceinline__ void aa_layout(const int* st, int m, int& nonempty, i
 // (Eq. aa_gamma) from the final Gram sums of iteration k-1; reliability guard
 // |gamma|_2 > 10.  The window M is a compile-time constant, so the Gram sums
 // and the M x M Cholesky stay in registers.  Computed by thread 0, broadcast
-// through LDS.
+// through LDS together with the loop's done flag (read with the sums).  Every
+// thread of the block must call it; loads issued before the call stay ahead
+// of its barriers.
 template <int M>
 __device__ __forceinline__ void aa_prepare(const StepState& St, const RedArgs& R, int k, bool reduce, AAMix& out) {
-  if constexpr (M == 0) {
-    out.use = 0;
-    out.reset = 0;
-    out.nc = 0;
-    out.head = 0;
-    out.m = 0;
-  } else {
-    __shared__ AAMix mx;
-    // Gram sums of iteration k-1, compact layout: G[j][l] at j*M + l, rhs[j] at M*M + j
-    constexpr int NA = M * M + M;
-    __shared__ double aav[NA];
-    double tot[NA];
-    if (k >= 1) {
-      if (reduce) {
-        consume<NA>(R, kRedAA, tot);
-      } else {
+  __shared__ AAMix mx;
+  constexpr int NA = (M > 0) ? M * M + M : 1;
+  int flag = 0;
+  int st[4] = {0, 0, 0, 0};
+  double tot[NA];
 #pragma unroll
-        for (int j = 0; j < NA; ++j) tot[j] = R.fin[kRedAA * kFinStride + j];
-      }
-      if (threadIdx.x == 0)
+  for (int j = 0; j < NA; ++j) tot[j] = 0.0;
+  if (threadIdx.x == 0) {
+    flag = *St.done;
+    if (M > 0 && k >= 1)
 #pragma unroll
-        for (int j = 0; j < NA; ++j) aav[j] = tot[j];
+      for (int j = 0; j < 4; ++j) st[j] = St.ctl[kCtlAA + 4 * ((k - 1) & 1) + j];
+  }
+  if (M > 0 && k >= 1) {
+    if (reduce) {
+      consume<NA>(R, kRedAA, tot);  // Gram sums of iteration k-1: G[j][l] at j*M + l, rhs[j] at M*M + j
+    } else if (threadIdx.x == 0) {
+#pragma unroll
+      for (int j = 0; j < NA; ++j) tot[j] = R.fin[kRedAA * kFinStride + j];
     }
-    __syncthreads();
-    if (threadIdx.x == 0) {
-      mx.use = 0;
-      mx.reset = 0;
-      mx.m = M;
-      mx.nc = 0;
-      mx.head = 0;
+  }
+  if (threadIdx.x == 0) {
+    mx.stop = flag;
+    mx.use = 0;
+    mx.reset = 0;
+    mx.m = M;
+    mx.nc = 0;
+    mx.head = 0;
 #pragma unroll
-      for (int j = 0; j < kMaxWindow; ++j) mx.gam[j] = 0.0;
-      if (k >= 1) {
+    for (int j = 0; j < kMaxWindow; ++j) mx.gam[j] = 0.0;
+    if constexpr (M > 0) {
+      if (k >= 1 && !flag) {
         int nonempty, nc, head, slot_new;
-        aa_layout(St.ctl + kCtlAA + 4 * ((k - 1) & 1), M, nonempty, nc, head, slot_new);
+        aa_layout(st, M, nonempty, nc, head, slot_new);
         mx.nc = nc;
         mx.head = head;
         if (nc >= 1) {
@@ -270,10 +315,10 @@ __device__ __forceinline__ void aa_prepare(const StepState& St, const RedArgs& R
 #pragma unroll
             for (int l = 0; l < M; ++l) {
               double g = (j == l) ? 1.0 : 0.0;
-              if (j < nc && l < nc) g = (j <= l) ? aav[j * M + l] : aav[l * M + j];
+              if (j < nc && l < nc) g = (j <= l) ? tot[j * M + l] : tot[l * M + j];
               G[j][l] = g;
             }
-            rhs[j] = (j < nc) ? aav[M * M + j] : 0.0;
+            rhs[j] = (j < nc) ? tot[M * M + j] : 0.0;
             if (j < nc) fro += G[j][j];
           }
           const double rho = fmax(1e-6 * fro / nc, 1e-12);
@@ -323,10 +368,10 @@ __device__ __forceinline__ void aa_prepare(const StepState& St, const RedArgs& R
         }
       }
     }
-    __syncthreads();
-    out = mx;
-    __syncthreads();
   }
+  __syncthreads();
+  out = mx;
+  __syncthreads();
 }
 
 // q^k of a free vertex: q^ - (dQ + dG) gamma (Eq. aa_update) or q^ (k >= 1);
@@ -356,61 +401,52 @@ __device__ __forceinline__ double aa_value(const StepState& St, const AAMix& mx,
 template <int M>
 __global__ void __launch_bounds__(kBlock) k_local(ElemArgs E, StepState St, RedArgs R, const double* __restrict__ q,
                                                   int nv, int nf, int k, int fwd, int* __restrict__ newton_cap) {
-  if (fwd && block_done(St.done)) return;
-  AAMix mx;
-  if (fwd) aa_prepare<M>(St, R, k, true, mx);
   const int t = blockIdx.x * blockDim.x + threadIdx.x;
-  if (t < E.ne) {
-    int vi[4];
-    vi[0] = E.tv[t];
-    vi[1] = E.tv[E.ne + t];
-    vi[2] = E.tv[2 * E.ne + t];
-    vi[3] = E.tv[3 * E.ne + t];
-    double xv[4][3];
+  const bool have = t < E.ne;
+  // the tet's data and warm start, requested before the Anderson scalars
+  TetData T;
+  double V[9], rt[3], wv = 0.0;
+  if (have) {
+    load_tet(E, t, T);
 #pragma unroll
-    for (int a = 0; a < 4; ++a)
-#pragma unroll
-      for (int ax = 0; ax < 3; ++ax)
-        xv[a][ax] = (fwd && vi[a] < nf) ? aa_value<M>(St, mx, nv, ax, vi[a], k) : q[ax * nv + vi[a]];
-    double F[9], U[9], V[9], sF[3], ss[3], rt[3];
-    F_from_positions(E, t, xv, F);
-    bool warm = true;
-#pragma unroll
-    for (int j = 0; j < 9; ++j) {
-      V[j] = E.Vw[(size_t)j * E.ne + t];
-      warm = warm && isfinite(V[j]);
-    }
-    if (!warm)
-#pragma unroll
-      for (int j = 0; j < 9; ++j) V[j] = (j % 4 == 0) ? 1.0 : 0.0;
-    svd3(F, U, sF, V, warm);
+    for (int j = 0; j < 9; ++j) V[j] = E.Vw[(size_t)j * E.ne + t];
 #pragma unroll
     for (int j = 0; j < 3; ++j) rt[j] = E.rw[(size_t)j * E.ne + t];
-    const int nit = prox_stretch(sF, E.mu_bar, E.lam_bar, E.k_bar, ss, rt);
-    // cap hit: every writer stores the same value, so plain stores suffice
-    if (newton_cap && nit >= kNewtonCap) *newton_cap = 1;
-    double P[9];
-#pragma unroll
-    for (int i = 0; i < 3; ++i)
-#pragma unroll
-      for (int j = 0; j < 3; ++j)
-        P[3 * i + j] = U[3 * i] * ss[0] * V[3 * j] + U[3 * i + 1] * ss[1] * V[3 * j + 1] + U[3 * i + 2] * ss[2] * V[3 * j + 2];
-    store_contrib(E, St.contrib, t, E.wV[t], P);
-    // keep the rotation orthonormal (Gram-Schmidt on its columns) for the next start
-    double c0[3] = {V[0], V[3], V[6]}, c1[3] = {V[1], V[4], V[7]};
-    double n0 = rsqrt(c0[0] * c0[0] + c0[1] * c0[1] + c0[2] * c0[2]);
-    c0[0] *= n0; c0[1] *= n0; c0[2] *= n0;
-    const double d01 = c0[0] * c1[0] + c0[1] * c1[1] + c0[2] * c1[2];
-    c1[0] -= d01 * c0[0]; c1[1] -= d01 * c0[1]; c1[2] -= d01 * c0[2];
-    double n1 = rsqrt(c1[0] * c1[0] + c1[1] * c1[1] + c1[2] * c1[2]);
-    c1[0] *= n1; c1[1] *= n1; c1[2] *= n1;
-    const double c2[3] = {c0[1] * c1[2] - c0[2] * c1[1], c0[2] * c1[0] - c0[0] * c1[2], c0[0] * c1[1] - c0[1] * c1[0]};
-    const double Vn[9] = {c0[0], c1[0], c2[0], c0[1], c1[1], c2[1], c0[2], c1[2], c2[2]};
-#pragma unroll
-    for (int j = 0; j < 9; ++j) E.Vw[(size_t)j * E.ne + t] = Vn[j];
-#pragma unroll
-    for (int j = 0; j < 3; ++j) E.rw[(size_t)j * E.ne + t] = (sF[j] > 1e-12) ? ss[j] / sF[j] : 0.0;
+    wv = E.wV[t];
   }
+  AAMix mx;
+  if (fwd) {
+    aa_prepare<M>(St, R, k, true, mx);
+    if (mx.stop) return;
+  }
+  if (!have) return;
+  double xv[4][3];
+#pragma unroll
+  for (int a = 0; a < 4; ++a)
+#pragma unroll
+    for (int ax = 0; ax < 3; ++ax)
+      xv[a][ax] = (fwd && T.vi[a] < nf) ? aa_value<M>(St, mx, nv, ax, T.vi[a], k) : q[ax * nv + T.vi[a]];
+  double F[9], U[9], sF[3], ss[3];
+  grad_of(T, xv, F);
+  bool warm = true;
+#pragma unroll
+  for (int j = 0; j < 9; ++j) warm = warm && isfinite(V[j]);
+  if (!warm)
+#pragma unroll
+    for (int j = 0; j < 9; ++j) V[j] = (j % 4 == 0) ? 1.0 : 0.0;
+  svd3(F, U, sF, V, warm);
+  const int nit = prox_stretch(sF, E.mu_bar, E.lam_bar, E.k_bar, ss, rt);
+  // cap hit: every writer stores the same value, so plain stores suffice
+  if (newton_cap && nit >= kNewtonCap) *newton_cap = 1;
+  double P[9];
+#pragma unroll
+  for (int i = 0; i < 3; ++i)
+#pragma unroll
+    for (int j = 0; j < 3; ++j)
+      P[3 * i + j] =
+          wv * (U[3 * i] * ss[0] * V[3 * j] + U[3 * i + 1] * ss[1] * V[3 * j + 1] + U[3 * i + 2] * ss[2] * V[3 * j + 2]);
+  store_GtP(T, St.contrib, E.ninc, P);
+  store_warm(E, t, V, sF, ss);
 }
 
 // G_e^T (w G_e x): contributions of the symmetric element operator w V G^T G
@@ -432,7 +468,8 @@ __global__ void __launch_bounds__(kBlock) k_elem_GtG(ElemArgs E, const double* _
 __global__ void __launch_bounds__(kBlock) k_prologue(VertArgs Vx, const double* __restrict__ q_t_user,
                                                      const double* __restrict__ v_t_user,
                                                      const double* __restrict__ f_user,
-                                                     const double* __restrict__ q0_user, StepState St) {
+                                                     const double* __restrict__ q0_user, int inertial,
+                                                     StepState St) {
   const int gtid = blockIdx.x * blockDim.x + threadIdx.x;
   const int i = gtid >> 3, l = gtid & 7;
   const int nv = Vx.nv;
@@ -465,7 +502,7 @@ __global__ void __launch_bounds__(kBlock) k_prologue(VertArgs Vx, const double* 
     St.vt[a * nv + i] = vt;
     St.qtil[a * nv + i] = qtil;
     St.c[a * nv + i] = m / (h * h) * qtil + Vx.alpha / h * m * qt + bq[a] + Vx.cpin[a * nv + i];
-    const double q0 = q0_user ? q0_user[3 * o + a] : qt;
+    const double q0 = q0_user ? q0_user[3 * o + a] : (inertial ? qt + h * vt : qt);
     St.q_cur[a * nv + i] = q0;
     St.q_prev[a * nv + i] = q0;
   }
@@ -478,34 +515,72 @@ __global__ void __launch_bounds__(kBlock) k_prologue(VertArgs Vx, const double* 
 // |b^{k-1}|^2.  Block 0 records the Anderson state of iteration k.
 template <int M>
 __global__ void __launch_bounds__(kBlock) k_gather_fwd(VertArgs Vx, StepState St, RedArgs R, int k) {
-  if (block_done(St.done)) return;
-  AAMix mx;
-  aa_prepare<M>(St, R, k, false, mx);
   const int nv = Vx.nv;
   const int gtid = blockIdx.x * blockDim.x + threadIdx.x;
   const int i = gtid >> 3, l = gtid & 7;
+  const bool have = i < Vx.nf;
+  const bool owner = have && l == 0;
+  // the vertex's incidence range and state, requested before the Anderson scalars
+  int k0 = 0, k1 = 0;
+  if (have) {
+    k0 = Vx.inc_ptr[i];
+    k1 = Vx.inc_ptr[i + 1];
+  }
+  double qh[3] = {0, 0, 0}, qc[3] = {0, 0, 0}, qp0[3] = {0, 0, 0}, bo[3] = {0, 0, 0}, cc[3] = {0, 0, 0};
+  if (owner)
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+      const int ix = a * nv + i;
+      if (k >= 1) qh[a] = St.qhat[ix];
+      else qp0[a] = St.q_prev[ix];
+      qc[a] = St.q_cur[ix];
+      bo[a] = St.b_cur[ix];
+      cc[a] = St.c[ix];
+    }
+  AAMix mx;
+  aa_prepare<M>(St, R, k, false, mx);
+  if (mx.stop) return;
   double part[4] = {0, 0, 0, 0};
-  if (i < Vx.nf) {
-    double bs[3];
-    gather8(Vx.inc_ptr, St.contrib, Vx.ninc, i, l, bs);
+  if (have) {
+    double s0 = 0, s1 = 0, s2 = 0;
+    const int ninc = Vx.ninc;
+#pragma unroll 4
+    for (int kk = k0 + l; kk < k1; kk += 8) {
+      s0 += St.contrib[kk];
+      s1 += St.contrib[(size_t)ninc + kk];
+      s2 += St.contrib[2 * (size_t)ninc + kk];
+    }
+    const double bs[3] = {group8_sum(s0), group8_sum(s1), group8_sum(s2)};
     if (l == 0) {
 #pragma unroll
       for (int a = 0; a < 3; ++a) {
         const int ix = a * nv + i;
-        const double qk = aa_value<M>(St, mx, nv, a, i, k);
-        const double qp = (k == 0) ? St.q_prev[ix] : St.q_cur[ix];
+        double qk = qc[a];
+        if (k >= 1) {
+          qk = qh[a];
+          if (M > 0 && mx.use) {
+#pragma unroll
+            for (int j = 0; j < M; ++j)
+              if (j < mx.nc) {
+                int slot = mx.head + j;
+                if (slot >= M) slot -= M;
+                const size_t cix = ((size_t)slot * 3 + a) * nv + i;
+                qk -= (St.dQ[cix] + St.dG[cix]) * mx.gam[j];
+              }
+          }
+        }
+        const double qp = (k == 0) ? qp0[a] : qc[a];
         if (k > 0) {
           St.q_prev[ix] = qp;
           St.q_cur[ix] = qk;
         }
-        const double bn = bs[a] + St.c[ix];
-        const double bo = St.b_cur[ix];
-        St.b_prev[ix] = bo;
+        const double bn = bs[a] + cc[a];
+        St.b_prev[ix] = bo[a];
         St.b_cur[ix] = bn;
         part[0] += (qk - qp) * (qk - qp);
         part[1] += qp * qp;
-        part[2] += (bn - bo) * (bn - bo);
-        part[3] += bo * bo;
+        part[2] += (bn - bo[a]) * (bn - bo[a]);
+        part[3] += bo[a] * bo[a];
       }
     }
   }
@@ -535,91 +610,127 @@ __global__ void __launch_bounds__(kBlock) k_gather_debug(VertArgs Vx, const doub
 }
 
 // ---------------------------------------------------------------- interface right-hand side
-// Forward mode first takes the dual-gate decision (the gate holds for
-// k >= 2; k == kmax - 1 ends the step unconverged).  Then one wave per
-// interface row i: r_T[i] = rhs_T[i] - sum over the subdomains s coupled to i
-// of E_s[p] . rhs_s (the Schur-complement right-hand side).  PCG mode forms
-// the updated residual r - alpha w on the fly, alpha = (r.z)/(p.w).
-template <int MODE>
-__device__ __forceinline__ double rhs_val(const double* __restrict__ src, const double* __restrict__ w, double alpha,
-                                          int ix) {
-  if (MODE == kModePCG) return src[ix] - alpha * w[ix];
-  return src[ix];
-}
-
+// One wave per interface row i: r_T[i] = rhs_T[i] - sum over the subdomains s
+// coupled to i of E_s[p] . rhs_s (the Schur-complement right-hand side).  The
+// forward mode first takes the dual-gate decision (Eq. convergence_dual; the
+// gate holds for k >= 2, k == kmax - 1 ends the step unconverged).  The PCG
+// mode forms the updated residual r - alpha w on the fly, alpha = (r.z)/(p.w).
+// The row descriptors, the row's own entries and the partial sums are all
+// requested before the first of them is needed.
 __device__ __forceinline__ double* r_cur(const AdjState& A, int it) { return (it & 1) ? A.r1 : A.r0; }
 
 template <int MODE>
 __global__ void __launch_bounds__(kBlock) k_Eb(VertArgs Vx, SolveArgs Sv, StepState St, AdjState A, RedArgs R,
                                                const double* __restrict__ rhs, int k) {
-  const int* done = (MODE == kModeFwd) ? St.done : (MODE == kModePlain ? St.done : A.done);
-  if (block_done(done)) return;
+  const int lane = threadIdx.x & 63;
+  const int row = (blockIdx.x * blockDim.x + threadIdx.x) >> 6;
+  const bool have = row < Sv.nT;
+  const int nv = Vx.nv, nB = Sv.nB;
+  const double* __restrict__ src = (MODE == kModeFwd) ? St.b_cur : (MODE == kModePCG ? r_cur(A, k) : rhs);
+  const double* __restrict__ wv = A.w;
+  Cpl cd = {0, 0, 0, 0};
+  ERow er = {0, 0, 0};
+  double own[3] = {0.0, 0.0, 0.0}, ownw[3] = {0.0, 0.0, 0.0};
+  if (have) {
+    er = Sv.erow[row];
+    if (lane < kMaxCoup) cd = Sv.cpl[row * kMaxCoup + lane];
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+      own[a] = src[a * nv + nB + row];
+      if (MODE == kModePCG) ownw[a] = wv[a * nv + nB + row];
+    }
+  }
   __shared__ int stop;
   __shared__ double alpha_s;
-  double g[4] = {0, 0, 0, 0};
-  if (MODE == kModeFwd && k >= 1) consume<4>(R, kRedGate, g);
-  double pw[1] = {1.0};
-  if (MODE == kModePCG) consume<1>(R, kRedPW, pw);
-  if (threadIdx.x == 0) {
-    stop = 0;
-    alpha_s = 0.0;
-    if (MODE == kModeFwd && k >= 1) {
+  if (MODE == kModePCG) {
+    int flag = 0;
+    double rz = 0.0;
+    if (threadIdx.x == 0) {
+      flag = *A.done;
+      rz = fin_site(R, kRedRZ0 + (k & 1))[0];
+    }
+    double pw[1] = {1.0};
+    consume<1>(R, kRedPW, pw);
+    if (threadIdx.x == 0) {
+      stop = flag;
+      alpha_s = rz / pw[0];
+    }
+  } else if (MODE == kModeFwd) {
+    int flag = 0;
+    if (threadIdx.x == 0) flag = *St.done;
+    double g[4] = {0, 0, 0, 0};
+    if (k >= 1) consume<4>(R, kRedGate, g);
+    if (threadIdx.x == 0) {
       const double dq = sqrt(g[0]), nq = sqrt(g[1]), db = sqrt(g[2]), nb = sqrt(g[3]);
       const bool pass = dq <= St.eps_rel * nq + St.eps_abs && db <= St.eps_rel * nb + St.eps_abs;
       const bool conv = (k >= 2) && pass;
       const bool cap = (k >= St.kmax - 1);
-      stop = conv || cap;
-      if (stop && blockIdx.x == 0) {
+      stop = flag || conv || cap;
+      if (!flag && (conv || cap) && blockIdx.x == 0) {
         St.ctl[kCtlDone] = 1;
         St.ctl[kCtlIters] = k;
         St.ctl[kCtlStatus] = conv ? 0 : 1;
         St.dstat[0] = dq; St.dstat[1] = nq; St.dstat[2] = db; St.dstat[3] = nb;
       }
     }
-    if (MODE == kModePCG) alpha_s = fin_site(R, kRedRZ0 + (k & 1))[0] / pw[0];
+  } else {
+    // the flag is written by earlier kernels only, so every thread reads the same value
+    if (threadIdx.x == 0) stop = St.done ? *St.done : 0;
   }
   __syncthreads();
-  if (stop) return;
-  const double alpha = alpha_s;
-  const double* src = (MODE == kModeFwd) ? St.b_cur : (MODE == kModePCG ? r_cur(A, k) : rhs);
-  const double* wv = A.w;
-  const int nv = Vx.nv, nB = Sv.nB;
-  const int lane = threadIdx.x & 63;
-  const int row = (blockIdx.x * blockDim.x + threadIdx.x) >> 6;
-  if (row >= Sv.nT) return;
+  if (stop || !have) return;
+  const double alpha = (MODE == kModePCG) ? alpha_s : 0.0;
+  // the couplings' first entries and subdomain rows, wave-uniform
+  int B[kMaxCoup], P[kMaxCoup];
+#pragma unroll
+  for (int c = 0; c < kMaxCoup; ++c) {
+    B[c] = __shfl(cd.b0, c, 64);
+    P[c] = __shfl(cd.pre, c, 64);
+  }
+  const double* __restrict__ Er = Sv.E + er.off;
   double a0 = 0, a1 = 0, a2 = 0;
-  for (int c = Sv.rl_ptr[row]; c < Sv.rl_ptr[row + 1]; ++c) {
-    const int s = Sv.rl_sub[c];
-    const int b0 = Sv.sub_begin[s], ns = Sv.sub_begin[s + 1] - b0;
-    const double* __restrict__ Ep = Sv.E + Sv.e_off[s] + (size_t)Sv.rl_p[c] * ns;
 #pragma unroll 4
-    for (int v = lane; v < ns; v += 64) {
-      const double e = Ep[v];
-      a0 += e * rhs_val<MODE>(src, wv, alpha, b0 + v);
-      a1 += e * rhs_val<MODE>(src, wv, alpha, nv + b0 + v);
-      a2 += e * rhs_val<MODE>(src, wv, alpha, 2 * nv + b0 + v);
+  for (int idx = lane; idx < er.len; idx += 64) {
+    int col = B[0] + idx;
+#pragma unroll
+    for (int c = 1; c < kMaxCoup; ++c)
+      if (c < er.n && idx >= P[c]) col = B[c] + idx - P[c];
+    const double e = Er[idx];
+    if (MODE == kModePCG) {
+      a0 += e * (src[col] - alpha * wv[col]);
+      a1 += e * (src[nv + col] - alpha * wv[nv + col]);
+      a2 += e * (src[2 * nv + col] - alpha * wv[2 * nv + col]);
+    } else {
+      a0 += e * src[col];
+      a1 += e * src[nv + col];
+      a2 += e * src[2 * nv + col];
     }
   }
   a0 = wave_sum(a0);
   a1 = wave_sum(a1);
   a2 = wave_sum(a2);
   if (lane == 0) {
-    const int gi = nB + row;
-    Sv.rT[row] = rhs_val<MODE>(src, wv, alpha, gi) - a0;
-    Sv.rT[Sv.nT + row] = rhs_val<MODE>(src, wv, alpha, nv + gi) - a1;
-    Sv.rT[2 * Sv.nT + row] = rhs_val<MODE>(src, wv, alpha, 2 * nv + gi) - a2;
+#pragma unroll
+    for (int a = 0; a < 3; ++a) own[a] -= alpha * ownw[a];
+    Sv.rT[row] = own[0] - a0;
+    Sv.rT[Sv.nT + row] = own[1] - a1;
+    Sv.rT[2 * Sv.nT + row] = own[2] - a2;
   }
 }
 
 // ---------------------------------------------------------------- interface solve
-// x_T = Z r_T, one wave per interface row (Z = inverse Schur complement).
-__global__ void __launch_bounds__(kBlock) k_top(VertArgs Vx, SolveArgs Sv, const int* __restrict__ done,
-                                                double* __restrict__ out) {
-  if (block_done(done)) return;
+// x_T = Z r_T, one wave per interface row (Z = inverse Schur complement); the
+// value is also stored at the row's position in the per-subdomain interface
+// vectors read by the subdomain solve.  There is no done test: once a loop has
+// stopped, k_Eb leaves r_T unchanged, so this kernel rewrites the same values.
+__global__ void __launch_bounds__(kBlock) k_top(VertArgs Vx, SolveArgs Sv, double* __restrict__ out) {
   const int lane = threadIdx.x & 63;
   const int row = (blockIdx.x * blockDim.x + threadIdx.x) >> 6;
   const int nT = Sv.nT;
   if (row >= nT) return;
+  const ERow er = Sv.erow[row];
+  Cpl cd = {0, 0, 0, 0};
+  if (lane < kMaxCoup) cd = Sv.cpl[row * kMaxCoup + lane];
   const double* __restrict__ Zi = Sv.Z + (size_t)row * nT;
   const double* __restrict__ r0 = Sv.rT;
   const double* __restrict__ r1 = Sv.rT + nT;
@@ -641,81 +752,136 @@ __global__ void __launch_bounds__(kBlock) k_top(VertArgs Vx, SolveArgs Sv, const
     out[nv + gi] = a1;
     out[2 * nv + gi] = a2;
   }
+  if (lane < er.n) {
+    const int ni = Sv.n_irows;
+    Sv.xsT[cd.pos] = a0;
+    Sv.xsT[ni + cd.pos] = a1;
+    Sv.xsT[2 * ni + cd.pos] = a2;
+  }
 }
 
 // ---------------------------------------------------------------- subdomain solve
-// x_s = Zs rhs_s - E_s^T x_T on the subdomain rows (one wave per row), then
-// the per-vertex work of each mode on every free row:
+// x_s = Z_s rhs_s - E_s^T x_T on the subdomain rows (one wave per row), then
+// the per-vertex work of each mode on every free row (the lane 0 of a
+// subdomain row's wave, or one thread per interface row):
 //  forward: g = q^ - q^k, the Anderson difference columns (Eqs. aa_dG, aa_dQ)
 //           and the Gram partial sums of the mixing;
-//  PCG:     r <- r - alpha w, mu <- mu + alpha p, partial r.z, |z|^2, |mu|^2;
+//  PCG:     the right-hand side is r - alpha w (formed on the fly); the
+//           solution is z; r <- r - alpha w, mu <- mu + alpha p, partial
+//           r.z, |z|^2, |mu|^2;
 //  PCG start: partial r.z, |z|^2, |mu|^2 of the first solve;
 //  fixed point: partial |z - mu|^2, |z|^2, then mu <- z.
+// Everything a thread needs that does not depend on the row descriptors is
+// requested together with them.
 template <int MODE, int M>
 __global__ void __launch_bounds__(kBottomThreads) k_bottom(VertArgs Vx, SolveArgs Sv, StepState St, AdjState A, RedArgs R,
                                                    const double* __restrict__ rhs, double* __restrict__ out, int k) {
-  const int* done = (MODE == kModeFwd || MODE == kModePlain) ? St.done : A.done;
-  if (block_done(done)) return;
-  __shared__ double alpha_s;
-  if (threadIdx.x == 0) {
-    alpha_s = 0.0;
-    if (MODE == kModePCG) alpha_s = fin_site(R, kRedRZ0 + (k & 1))[0] / fin_site(R, kRedPW)[0];
-  }
-  __syncthreads();
-  const double alpha = alpha_s;
   const int nv = Vx.nv, nB = Sv.nB, nf = Vx.nf;
-  const double* src = (MODE == kModeFwd) ? St.b_cur : (MODE == kModePCG ? r_cur(A, k) : rhs);
-  const double* wv = A.w;
-  double* dst = (MODE == kModeFwd) ? St.qhat : out;
   const int lane = threadIdx.x & 63;
-  const int n_sub_blocks = (nB + kBottomThreads / 64 - 1) / (kBottomThreads / 64);
-  // rows whose per-vertex work this thread does (at most one)
+  constexpr int kRows = kBottomThreads / 64;
+  const int n_sub_blocks = (nB + kRows - 1) / kRows;
+  const bool sub_block = (int)blockIdx.x < n_sub_blocks;
+  const int v = blockIdx.x * kRows + (threadIdx.x >> 6);
+  const bool have_row = sub_block && v < nB;
   int my_row = -1;
-  if ((int)blockIdx.x < n_sub_blocks) {
-    const int v = blockIdx.x * (kBottomThreads / 64) + (threadIdx.x >> 6);
-    if (v < nB) {
-      const int s = Sv.sub_of[v];
-      const int b0 = Sv.sub_begin[s], ns = Sv.sub_begin[s + 1] - b0, lr = v - b0;
-      const int nI = Sv.ir_off[s + 1] - Sv.ir_off[s];
-      const int* __restrict__ Ir = Sv.irows + Sv.ir_off[s];
-      const double* __restrict__ Zr = Sv.Zs + Sv.zs_off[s] + (size_t)lr * ns;
-      const double* __restrict__ Er = Sv.Et + Sv.e_off[s] + (size_t)lr * nI;
-      double a0 = 0, a1 = 0, a2 = 0;
-#pragma unroll 4
-      for (int u = lane; u < ns; u += 64) {
-        const double z = Zr[u];
-        a0 += z * rhs_val<MODE>(src, wv, alpha, b0 + u);
-        a1 += z * rhs_val<MODE>(src, wv, alpha, nv + b0 + u);
-        a2 += z * rhs_val<MODE>(src, wv, alpha, 2 * nv + b0 + u);
-      }
-#pragma unroll 4
-      for (int p = lane; p < nI; p += 64) {
-        const double e = Er[p];
-        const int gi = nB + Ir[p];
-        a0 -= e * dst[gi];
-        a1 -= e * dst[nv + gi];
-        a2 -= e * dst[2 * nv + gi];
-      }
-      a0 = wave_sum(a0);
-      a1 = wave_sum(a1);
-      a2 = wave_sum(a2);
-      if (lane == 0) {
-        dst[v] = a0;
-        dst[nv + v] = a1;
-        dst[2 * nv + v] = a2;
-        my_row = v;
-      }
-    }
-  } else {
+  if (have_row) {
+    if (lane == 0) my_row = v;
+  } else if (!sub_block) {
     const int i = nB + (blockIdx.x - n_sub_blocks) * blockDim.x + threadIdx.x;
     if (i < nf) my_row = i;
   }
+  const bool iface = my_row >= nB;
+  const double* __restrict__ src = (MODE == kModeFwd) ? St.b_cur : (MODE == kModePCG ? r_cur(A, k) : rhs);
+  const double* __restrict__ wv = A.w;
+  double* dst = (MODE == kModeFwd) ? St.qhat : out;
+  const int* done = (MODE == kModeFwd || MODE == kModePlain) ? St.done : A.done;
+  // ---- first round of loads
+  BRow br = {0, 0, 0, 0};
+  BOff bo = {0, 0};
+  if (have_row) {
+    br = Sv.brow[v];
+    bo = Sv.boff[v];
+  }
+  __shared__ int flag_s;
+  if (threadIdx.x == 0) flag_s = done ? *done : 0;
+  // per-vertex state of my_row (x_T of an interface row comes from k_top)
+  double xo[3] = {0, 0, 0};
+  double u0[3] = {0, 0, 0}, u1[3] = {0, 0, 0}, u2[3] = {0, 0, 0}, u3[3] = {0, 0, 0};
+  int aa[4] = {0, 0, 0, 0};
+  if (MODE == kModeFwd && M > 0)
+#pragma unroll
+    for (int j = 0; j < 4; ++j) aa[j] = St.ctl[kCtlAA + 4 * (k & 1) + j];
+  if (my_row >= 0) {
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+      const int ix = a * nv + my_row;
+      if (iface) xo[a] = dst[ix];
+      if (MODE == kModeFwd && M > 0) {
+        u0[a] = St.q_cur[ix];
+        u1[a] = St.g_last[ix];
+        u2[a] = St.q_last[ix];
+      } else if (MODE == kModePCG) {
+        u0[a] = src[ix];
+        u1[a] = A.p[ix];
+        u2[a] = wv[ix];
+        u3[a] = A.mu[ix];
+      } else if (MODE == kModePCGInit) {
+        u0[a] = rhs[ix];
+        u1[a] = A.mu[ix];
+      } else if (MODE == kModeFixed) {
+        u1[a] = A.mu[ix];
+      }
+    }
+  }
+  // alpha = (r.z)/(p.w): both totals were stored by k_Eb's block 0 and earlier
+  const double rz = (MODE == kModePCG) ? fin_site(R, kRedRZ0 + (k & 1))[0] : 0.0;
+  const double pwt = (MODE == kModePCG) ? fin_site(R, kRedPW)[0] : 1.0;
+  __syncthreads();
+  if (flag_s) return;
+  const double alpha = rz / pwt;
+  // ---- the subdomain row: x_v = Z_s[v, :] rhs_s - E_s^T[v, :] x_T(s)
+  if (have_row) {
+    const double* __restrict__ Zr = Sv.Zs + bo.zs;
+    const double* __restrict__ Er = Sv.Et + bo.et;
+    const int ni = Sv.n_irows;
+    const double* __restrict__ x0 = Sv.xsT + br.ir0;
+    double a0 = 0, a1 = 0, a2 = 0;
+#pragma unroll 4
+    for (int u = lane; u < br.ns; u += 64) {
+      const double z = Zr[u];
+      const int c = br.b0 + u;
+      if (MODE == kModePCG) {
+        a0 += z * (src[c] - alpha * wv[c]);
+        a1 += z * (src[nv + c] - alpha * wv[nv + c]);
+        a2 += z * (src[2 * nv + c] - alpha * wv[2 * nv + c]);
+      } else {
+        a0 += z * src[c];
+        a1 += z * src[nv + c];
+        a2 += z * src[2 * nv + c];
+      }
+    }
+#pragma unroll 4
+    for (int p = lane; p < br.nI; p += 64) {
+      const double e = Er[p];
+      a0 -= e * x0[p];
+      a1 -= e * x0[ni + p];
+      a2 -= e * x0[2 * ni + p];
+    }
+    xo[0] = wave_sum(a0);
+    xo[1] = wave_sum(a1);
+    xo[2] = wave_sum(a2);
+    if (lane == 0) {
+      dst[v] = xo[0];
+      dst[nv + v] = xo[1];
+      dst[2 * nv + v] = xo[2];
+    }
+  }
   if (MODE == kModePlain) return;
-  // per-vertex work
+  // ---- per-vertex work
   if (MODE == kModeFwd) {
     if constexpr (M > 0) {
       int nonempty, nc, head, slot_new;
-      aa_layout(St.ctl + kCtlAA + 4 * (k & 1), M, nonempty, nc, head, slot_new);
+      aa_layout(aa, M, nonempty, nc, head, slot_new);
       // Gram partial sums, compact layout: G[j][l] at j*M + l, rhs[j] at M*M + j
       constexpr int NA = M * M + M;
       double part[NA];
@@ -723,31 +889,41 @@ __global__ void __launch_bounds__(kBottomThreads) k_bottom(VertArgs Vx, SolveArg
       for (int j = 0; j < NA; ++j) part[j] = 0.0;
       if (my_row >= 0) {
         const int i = my_row;
+        double col[3][M];
 #pragma unroll
-        for (int a = 0; a < 3; ++a) {
-          const int ix = a * nv + i;
-          const double qc = St.q_cur[ix];
-          const double g = dst[ix] - qc;
-          if (slot_new >= 0) {
-            const size_t cix = ((size_t)slot_new * 3 + a) * nv + i;
-            St.dG[cix] = g - St.g_last[ix];
-            St.dQ[cix] = qc - St.q_last[ix];
-          }
-          St.g_last[ix] = g;
-          St.q_last[ix] = qc;
-          double col[M];
+        for (int a = 0; a < 3; ++a)
 #pragma unroll
           for (int j = 0; j < M; ++j) {
             int slot = head + j;
             if (slot >= M) slot -= M;
-            col[j] = (j < nc) ? St.dG[((size_t)slot * 3 + a) * nv + i] : 0.0;
+            col[a][j] = (j < nc) ? St.dG[((size_t)slot * 3 + a) * nv + i] : 0.0;
           }
+#pragma unroll
+        for (int a = 0; a < 3; ++a) {
+          const int ix = a * nv + i;
+          const double qc = u0[a];
+          const double g = xo[a] - qc;
+          if (slot_new >= 0) {
+            const size_t cix = ((size_t)slot_new * 3 + a) * nv + i;
+            const double dg = g - u1[a];
+            St.dG[cix] = dg;
+            St.dQ[cix] = qc - u2[a];
+            // the new column enters the Gram sums at its position in the window
+#pragma unroll
+            for (int j = 0; j < M; ++j) {
+              int slot = head + j;
+              if (slot >= M) slot -= M;
+              if (j < nc && slot == slot_new) col[a][j] = dg;
+            }
+          }
+          St.g_last[ix] = g;
+          St.q_last[ix] = qc;
 #pragma unroll
           for (int j = 0; j < M; ++j) {
 #pragma unroll
             for (int l = 0; l < M; ++l)
-              if (l >= j) part[j * M + l] += col[j] * col[l];
-            part[M * M + j] += col[j] * g;
+              if (l >= j) part[j * M + l] += col[a][j] * col[a][l];
+            part[M * M + j] += col[a][j] * g;
           }
         }
       }
@@ -766,29 +942,27 @@ __global__ void __launch_bounds__(kBottomThreads) k_bottom(VertArgs Vx, SolveArg
   } else {
     double v3[3] = {0, 0, 0};
     if (my_row >= 0) {
-      const int i = my_row;
 #pragma unroll
       for (int a = 0; a < 3; ++a) {
-        const int ix = a * nv + i;
-        const double z = dst[ix];
+        const int ix = a * nv + my_row;
+        const double x = xo[a];
         if (MODE == kModePCG) {
-          const double rn = src[ix] - alpha * A.w[ix];
-          const double mn = A.mu[ix] + alpha * A.p[ix];
+          const double rn = u0[a] - alpha * u2[a];
+          const double mn = u3[a] + alpha * u1[a];
           r_cur(A, k + 1)[ix] = rn;
           A.mu[ix] = mn;
-          v3[0] += rn * z;
-          v3[1] += z * z;
+          v3[0] += rn * x;
+          v3[1] += x * x;
           v3[2] += mn * mn;
         } else if (MODE == kModePCGInit) {
-          const double rn = A.r0[ix], mn = A.mu[ix];
-          v3[0] += rn * z;
-          v3[1] += z * z;
-          v3[2] += mn * mn;
+          v3[0] += u0[a] * x;
+          v3[1] += x * x;
+          v3[2] += u1[a] * u1[a];
         } else {  // fixed point
-          const double mo = A.mu[ix];
-          v3[0] += (z - mo) * (z - mo);
-          v3[1] += z * z;
-          A.mu[ix] = z;
+          const double mo = u1[a];
+          v3[0] += (x - mo) * (x - mo);
+          v3[1] += x * x;
+          A.mu[ix] = x;
         }
       }
     }
@@ -965,6 +1139,8 @@ __global__ void __launch_bounds__(kBlock) k_bwd_elem(ElemArgs E, VertArgs Vx, Re
     jac[(27 + j) * ne + t] = c2[j];
     jac[(30 + j) * ne + t] = ss[j];
   }
+  // a reverse sweep visits q* of neighbouring steps: start the next one from here
+  store_warm(E, t, V, sF, ss);
 }
 
 __device__ __forceinline__ void load_jac(const double* __restrict__ jac, int ne, int t, double U[9], double V[9],
@@ -985,7 +1161,9 @@ __device__ __forceinline__ void load_jac(const double* __restrict__ jac, int ne,
 
 // PCG scalars at the start of adjoint iteration it: convergence of the
 // previous solve (|z| <= eps |mu|, the relative preconditioned residual) and
-// beta = (r.z)_{it} / (r.z)_{it-1} for the direction p = z + beta p.
+// beta = (r.z)_{it} / (r.z)_{it-1} for the direction p = z + beta p.  The done
+// flag of earlier iterations is read together with the partial sums; the
+// decision is block-uniform.
 struct PCGCtl {
   int stop;
   double beta;
@@ -994,6 +1172,12 @@ struct PCGCtl {
 template <int MODE>
 __device__ __forceinline__ PCGCtl adj_control(const AdjState& A, const RedArgs& R, int it) {
   __shared__ PCGCtl c;
+  int flag = 0;
+  double prev = 1.0;
+  if (threadIdx.x == 0) {
+    flag = *A.done;
+    if (MODE == kModePCG && it >= 1) prev = fin_site(R, kRedRZ0 + ((it - 1) & 1))[0];
+  }
   double f[3] = {0.0, 0.0, 0.0};
   if (MODE == kModePCG) consume<3>(R, kRedRZ0 + (it & 1), f);
   if (MODE == kModeFixed && it >= 1) consume<3>(R, kRedFix, f);
@@ -1005,17 +1189,17 @@ __device__ __forceinline__ PCGCtl adj_control(const AdjState& A, const RedArgs& 
     if (MODE == kModePCG) {
       const double rz = f[0], zz = f[1], mm = f[2];
       res = (zz == 0.0) ? 0.0 : sqrt(zz) / sqrt(mm);
-      conv = (it >= 1 && res <= A.eps) || zz == 0.0;
-      if (it >= 1) c.beta = rz / fin_site(R, kRedRZ0 + ((it - 1) & 1))[0];
+      conv = res <= A.eps;
+      if (it >= 1) c.beta = rz / prev;
     } else if (MODE == kModeFixed && it >= 1) {
       res = (f[1] == 0.0) ? 0.0 : sqrt(f[0]) / sqrt(f[1]);
       conv = res <= A.eps;
     }
     const bool cap = it >= A.kmax;
-    c.stop = conv || cap;
-    if (blockIdx.x == 0 && (MODE == kModePCG || MODE == kModeFixed)) {
+    c.stop = flag || conv || cap;
+    if (!flag && blockIdx.x == 0) {
       A.dstat[0] = res;
-      if (c.stop) {
+      if (conv || cap) {
         *A.done = 1;
         A.ctl[0] = it;
         A.ctl[1] = conv ? 0 : 1;
@@ -1028,80 +1212,132 @@ __device__ __forceinline__ PCGCtl adj_control(const AdjState& A, const RedArgs& 
   return out;
 }
 
-// K x element contributions: w_e V_e G_e^T (dp*/dF) G_e x (Eq. db_dq) on
-// free vertices; PCG forms x = p = z + beta p on the fly.
+// Element contributions on free vertices of
+//   K x = sum_e w_e V_e G_e^T (dp*/dF) G_e x               (Eq. db_dq)
+// and, in the warm-start mode, of (A~ - K) x without its mass term:
+//   sum_e G_e^T [(w_e + beta_e / h) V_e G_e x - w_e V_e (dp*/dF) G_e x].
+// PCG forms x = p = z + beta p on the fly.  The tet's data and its compact
+// differential are requested together with the control sums.
 template <int MODE>
 __global__ void __launch_bounds__(kBlock) k_apply_K(ElemArgs E, VertArgs Vx, AdjState A, RedArgs R,
                                                     const double* __restrict__ jac, const double* __restrict__ x, int it) {
-  if (MODE != kModeDebug && block_done(A.done)) return;
-  PCGCtl c = {0, 0.0};
-  if (MODE != kModeDebug) c = adj_control<MODE>(A, R, it);
-  if (c.stop) return;
   const int t = blockIdx.x * blockDim.x + threadIdx.x;
-  if (t >= E.ne) return;
+  const bool have = t < E.ne;
+  TetData T;
+  double U[9], V[9], D[6], c1[3], c2[3], wv = 0.0, bv = 0.0;
+  if (have) {
+    load_tet(E, t, T);
+    load_jac(jac, E.ne, t, U, V, D, c1, c2);
+    wv = E.wV[t];
+    if (MODE == kModeAmK) bv = E.bV[t];
+  }
+  PCGCtl c = {0, 0.0};
+  if (MODE == kModePCG || MODE == kModeFixed) c = adj_control<MODE>(A, R, it);
+  if (c.stop || !have) return;
   const int nv = Vx.nv, nf = Vx.nf;
-  int vi[4];
-  vi[0] = E.tv[t];
-  vi[1] = E.tv[E.ne + t];
-  vi[2] = E.tv[2 * E.ne + t];
-  vi[3] = E.tv[3 * E.ne + t];
   double xv[4][3];
 #pragma unroll
   for (int a = 0; a < 4; ++a)
 #pragma unroll
     for (int ax = 0; ax < 3; ++ax) {
-      const int ix = ax * nv + vi[a];
+      const int ix = ax * nv + T.vi[a];
       double val = 0.0;
-      if (vi[a] < nf) {
+      if (T.vi[a] < nf) {
         if (MODE == kModePCG) val = A.z[ix] + c.beta * A.p[ix];
         else if (MODE == kModeFixed) val = A.mu[ix];
         else val = x[ix];
       }
       xv[a][ax] = val;
     }
-  double dF[9];
-  F_from_positions(E, t, xv, dF);
-  double U[9], V[9], D[6], c1[3], c2[3], dP[9];
-  load_jac(jac, E.ne, t, U, V, D, c1, c2);
+  double dF[9], dP[9];
+  grad_of(T, xv, dF);
   prox_diff_apply(U, V, D, c1, c2, dF, dP);
-  store_contrib(E, A.contrib, t, E.wV[t], dP);
+  double P[9];
+#pragma unroll
+  for (int j = 0; j < 9; ++j) P[j] = (MODE == kModeAmK) ? (wv + bv) * dF[j] - wv * dP[j] : wv * dP[j];
+  store_GtP(T, A.contrib, E.ninc, P);
 }
 
-// Gathered K x on free vertices (8 lanes per vertex).  PCG: p = z + beta p,
-// A p = r + beta A p (A z = r, so no product with A is needed), w = A p - K p
-// and the partial p.w; fixed point: r = qbar + K mu; debug: w = K x.
+// Gathered contributions on free vertices (8 lanes per vertex).
+//  PCG:   p = z + beta p, A p = r + beta A p (A z = r, so no product with A is
+//         needed), w = A p - K p and the partial p.w;
+//  fixed point: r = q bar + K mu;
+//  warm start: r = q bar - (A~ - K) mu (mass term (1 + alpha h) m / h^2 added here);
+//  debug: K x.
 template <int MODE>
 __global__ void __launch_bounds__(kBlock) k_adj_gather(VertArgs Vx, AdjState A, RedArgs R, int it) {
-  if (MODE != kModeDebug && block_done(A.done)) return;
-  __shared__ double beta_s;
-  if (threadIdx.x == 0) {
-    beta_s = 0.0;
-    if (MODE == kModePCG && it >= 1)
-      beta_s = fin_site(R, kRedRZ0 + (it & 1))[0] / fin_site(R, kRedRZ0 + ((it - 1) & 1))[0];
-  }
-  __syncthreads();
-  const double beta = beta_s;
   const int nv = Vx.nv;
   const int gtid = blockIdx.x * blockDim.x + threadIdx.x;
   const int i = gtid >> 3, l = gtid & 7;
+  const bool have = i < Vx.nf;
+  const bool owner = have && l == 0;
+  // first round: the vertex's incidence range, its own state and the scalars
+  int k0 = 0, k1 = 0;
+  if (have) {
+    k0 = Vx.inc_ptr[i];
+    k1 = Vx.inc_ptr[i + 1];
+  }
+  double u0[3] = {0, 0, 0}, u1[3] = {0, 0, 0}, u2[3] = {0, 0, 0}, u3[3] = {0, 0, 0};
+  if (owner)
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+      const int ix = a * nv + i;
+      if (MODE == kModePCG) {
+        u0[a] = A.z[ix];
+        u1[a] = A.p[ix];
+        u2[a] = r_cur(A, it)[ix];
+        u3[a] = A.Ap[ix];
+      } else if (MODE == kModeFixed) {
+        u0[a] = A.qbar[ix];
+      } else if (MODE == kModeInit) {
+        u0[a] = A.qbar[ix];
+        u1[a] = A.mu[ix];
+      }
+    }
+  double num = 0.0, den = 1.0, mass = 0.0;
+  if (MODE == kModePCG && it >= 1) {
+    num = fin_site(R, kRedRZ0 + (it & 1))[0];
+    den = fin_site(R, kRedRZ0 + ((it - 1) & 1))[0];
+  }
+  if (MODE == kModeInit && owner) mass = Vx.mass[i];
+  __shared__ int flag_s;
+  if (threadIdx.x == 0) flag_s = (MODE == kModePCG || MODE == kModeFixed) ? *A.done : 0;
+  __syncthreads();
+  if (flag_s) return;
+  const double beta = num / den;
   double v[1] = {0.0};
-  if (i < Vx.nf) {
-    double kx[3];
-    gather8(Vx.inc_ptr, A.contrib, Vx.ninc, i, l, kx);
+  if (have) {
+    double kx[3] = {0, 0, 0};
+    {
+      double s0 = 0, s1 = 0, s2 = 0;
+      const int ninc = Vx.ninc;
+#pragma unroll 4
+      for (int k = k0 + l; k < k1; k += 8) {
+        s0 += A.contrib[k];
+        s1 += A.contrib[(size_t)ninc + k];
+        s2 += A.contrib[2 * (size_t)ninc + k];
+      }
+      kx[0] = group8_sum(s0);
+      kx[1] = group8_sum(s1);
+      kx[2] = group8_sum(s2);
+    }
     if (l == 0) {
+      const double h = Vx.h;
 #pragma unroll
       for (int a = 0; a < 3; ++a) {
         const int ix = a * nv + i;
         if (MODE == kModePCG) {
-          const double pn = A.z[ix] + beta * A.p[ix];
-          const double apn = r_cur(A, it)[ix] + beta * A.Ap[ix];
+          const double pn = u0[a] + beta * u1[a];
+          const double apn = u2[a] + beta * u3[a];
+          const double w = apn - kx[a];
           A.p[ix] = pn;
           A.Ap[ix] = apn;
-          const double w = apn - kx[a];
           A.w[ix] = w;
           v[0] += pn * w;
         } else if (MODE == kModeFixed) {
-          A.r0[ix] = A.qbar[ix] + kx[a];
+          A.r0[ix] = u0[a] + kx[a];
+        } else if (MODE == kModeInit) {
+          A.r0[ix] = u0[a] - ((1.0 + Vx.alpha * h) * mass / (h * h) * u1[a] + kx[a]);
         } else {
           A.w[ix] = kx[a];
         }
@@ -1112,19 +1348,25 @@ __global__ void __launch_bounds__(kBlock) k_adj_gather(VertArgs Vx, AdjState A, 
 }
 
 // q bar = gq_next + gv_next / h on free vertices (Alg. 2 first line), in
-// library order; adjoint start: mu = 0, r = q bar.
+// library order; adjoint start mu0 (zero, the previous solution mu1 of the
+// sweep, or the linear extrapolation 2 mu1 - mu2), r = q bar, p = A p = 0.
 __global__ void __launch_bounds__(kBlock) k_bwd_prologue(VertArgs Vx, AdjState Ad, const double* __restrict__ gq,
-                                                         const double* __restrict__ gv) {
+                                                         const double* __restrict__ gv, int warm,
+                                                         const double* __restrict__ h1, const double* __restrict__ h2) {
   const int i = blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= Vx.nv) return;
   const int nv = Vx.nv, o = Vx.v_orig[i];
+  const bool fr = i < Vx.nf;
 #pragma unroll
   for (int a = 0; a < 3; ++a) {
     const int ix = a * nv + i;
-    const double qb = (i < Vx.nf) ? ((gq ? gq[3 * o + a] : 0.0) + (gv ? gv[3 * o + a] : 0.0) / Vx.h) : 0.0;
+    const double qb = fr ? ((gq ? gq[3 * o + a] : 0.0) + (gv ? gv[3 * o + a] : 0.0) / Vx.h) : 0.0;
+    double m0 = 0.0;
+    if (fr && warm == 1) m0 = h1[ix];
+    if (fr && warm == 2) m0 = 2.0 * h1[ix] - h2[ix];
     Ad.qbar[ix] = qb;
     Ad.r0[ix] = qb;
-    Ad.mu[ix] = 0.0;
+    Ad.mu[ix] = m0;
     Ad.p[ix] = 0.0;
     Ad.Ap[ix] = 0.0;
   }
@@ -1217,6 +1459,35 @@ __global__ void __launch_bounds__(kBlock) k_zero_int(int* p, int n) {
 // ================================================================= launchers
 #define PD_GRID(n) dim3(((n) + kBlock - 1) / kBlock), dim3(kBlock)
 
+// Every launch goes through the extended launch, which can stamp a start and
+// a stop event from the dispatch itself (the kernel's own execution time, the
+// figure a kernel trace reports).  The events are armed for one launch.
+namespace {
+thread_local hipEvent_t g_ev_start = nullptr, g_ev_stop = nullptr;
+thread_local bool g_ev_used = false;
+
+template <typename F, typename... Args>
+void launch_ext(F kernel, const dim3& grid, const dim3& block, unsigned shmem, hipStream_t s, Args... args) {
+  hipEvent_t e0 = g_ev_start, e1 = g_ev_stop;
+  g_ev_start = g_ev_stop = nullptr;
+  if (e0) g_ev_used = true;
+  hipExtLaunchKernelGGL(kernel, grid, block, shmem, s, e0, e1, 0u, args...);
+}
+}  // namespace
+
+void arm_launch_events(hipEvent_t start, hipEvent_t stop) {
+  g_ev_start = start;
+  g_ev_stop = stop;
+  g_ev_used = false;
+}
+
+bool launch_events_used() {
+  const bool u = g_ev_used;
+  g_ev_start = g_ev_stop = nullptr;
+  g_ev_used = false;
+  return u;
+}
+
 int vert_group_blocks(int n) { return (8 * n + kBlock - 1) / kBlock; }
 int bottom_blocks(int nB, int nT) {
   const int rows = kBottomThreads / 64;
@@ -1227,7 +1498,7 @@ int tr_blocks(int ne, int nf) { return (ne + kBlock - 1) / kBlock + (nf + kBlock
 void launch_local(const ElemArgs& E, const StepState& St, const RedArgs& R, const double* q, int nv, int nf,
                   int k, int fwd, hipStream_t s) {
   int* cap = fwd ? St.ctl + kCtlNewton : nullptr;
-#define PD_LOCAL(M) hipLaunchKernelGGL(k_local<M>, PD_GRID(E.ne), 0, s, E, St, R, q, nv, nf, k, fwd, cap)
+#define PD_LOCAL(M) launch_ext(k_local<M>, PD_GRID(E.ne), 0, s, E, St, R, q, nv, nf, k, fwd, cap)
   switch (fwd ? St.m : 0) {
     case 1: PD_LOCAL(1); break;
     case 2: PD_LOCAL(2); break;
@@ -1239,15 +1510,15 @@ void launch_local(const ElemArgs& E, const StepState& St, const RedArgs& R, cons
 #undef PD_LOCAL
 }
 void launch_elem_GtG(const ElemArgs& E, const double* x, int nv, const double* w, double* contrib, hipStream_t s) {
-  hipLaunchKernelGGL(k_elem_GtG, PD_GRID(E.ne), 0, s, E, x, nv, w, contrib);
+  launch_ext(k_elem_GtG, PD_GRID(E.ne), 0, s, E, x, nv, w, contrib);
 }
 void launch_prologue(const VertArgs& V, const double* qt, const double* vt, const double* f, const double* q0,
-                     const StepState& St, hipStream_t s) {
-  hipLaunchKernelGGL(k_prologue, dim3(vert_group_blocks(V.nv)), dim3(kBlock), 0, s, V, qt, vt, f, q0, St);
+                     int inertial, const StepState& St, hipStream_t s) {
+  launch_ext(k_prologue, dim3(vert_group_blocks(V.nv)), dim3(kBlock), 0, s, V, qt, vt, f, q0, inertial, St);
 }
 void launch_gather_fwd(const VertArgs& V, const StepState& St, const RedArgs& R, int k, hipStream_t s) {
   const dim3 g(vert_group_blocks(V.nf)), b(kBlock);
-#define PD_GATHER(M) hipLaunchKernelGGL(k_gather_fwd<M>, g, b, 0, s, V, St, R, k)
+#define PD_GATHER(M) launch_ext(k_gather_fwd<M>, g, b, 0, s, V, St, R, k)
   switch (St.m) {
     case 1: PD_GATHER(1); break;
     case 2: PD_GATHER(2); break;
@@ -1259,28 +1530,29 @@ void launch_gather_fwd(const VertArgs& V, const StepState& St, const RedArgs& R,
 #undef PD_GATHER
 }
 void launch_gather_debug(const VertArgs& V, const double* contrib, double* out, hipStream_t s) {
-  hipLaunchKernelGGL(k_gather_debug, dim3(vert_group_blocks(V.nf)), dim3(kBlock), 0, s, V, contrib, out);
+  launch_ext(k_gather_debug, dim3(vert_group_blocks(V.nf)), dim3(kBlock), 0, s, V, contrib, out);
 }
 void launch_Eb(int mode, const VertArgs& V, const SolveArgs& S, const StepState& St, const AdjState& A,
                const RedArgs& R, const double* rhs, int k, hipStream_t s) {
+  // the forward mode (gate decision) and the PCG mode (alpha) always run, with at least one block
   const int nblk = std::max(1, (S.nT + 3) / 4);
   if (mode == kModeFwd)
-    hipLaunchKernelGGL(k_Eb<kModeFwd>, dim3(nblk), dim3(kBlock), 0, s, V, S, St, A, R, rhs, k);
+    launch_ext(k_Eb<kModeFwd>, dim3(nblk), dim3(kBlock), 0, s, V, S, St, A, R, rhs, k);
   else if (mode == kModePCG)
-    hipLaunchKernelGGL(k_Eb<kModePCG>, dim3(nblk), dim3(kBlock), 0, s, V, S, St, A, R, rhs, k);
+    launch_ext(k_Eb<kModePCG>, dim3(nblk), dim3(kBlock), 0, s, V, S, St, A, R, rhs, k);
   else if (S.nT > 0)
-    hipLaunchKernelGGL(k_Eb<kModePlain>, dim3(nblk), dim3(kBlock), 0, s, V, S, St, A, R, rhs, k);
+    launch_ext(k_Eb<kModePlain>, dim3(nblk), dim3(kBlock), 0, s, V, S, St, A, R, rhs, k);
 }
-void launch_top(const VertArgs& V, const SolveArgs& S, const int* done, double* out, hipStream_t s) {
+void launch_top(const VertArgs& V, const SolveArgs& S, double* out, hipStream_t s) {
   if (S.nT == 0) return;
-  hipLaunchKernelGGL(k_top, dim3((S.nT + 3) / 4), dim3(kBlock), 0, s, V, S, done, out);
+  launch_ext(k_top, dim3((S.nT + 3) / 4), dim3(kBlock), 0, s, V, S, out);
 }
 void launch_bottom(int mode, const VertArgs& V, const SolveArgs& S, const StepState& St, const AdjState& A,
                    const RedArgs& R, const double* rhs, double* out, int k, hipStream_t s) {
   const int nblk = bottom_blocks(S.nB, S.nT);
   if (nblk == 0) return;
 #define PD_BOTTOM(MODE, M) \
-  hipLaunchKernelGGL((k_bottom<MODE, M>), dim3(nblk), dim3(kBottomThreads), 0, s, V, S, St, A, R, rhs, out, k)
+  launch_ext((k_bottom<MODE, M>), dim3(nblk), dim3(kBottomThreads), 0, s, V, S, St, A, R, rhs, out, k)
   switch (mode) {
     case kModeFwd:
       switch (St.m) {
@@ -1301,50 +1573,53 @@ void launch_bottom(int mode, const VertArgs& V, const SolveArgs& S, const StepSt
 }
 void launch_epilogue(const VertArgs& V, const StepState& St, double* q_next, double* v_next, double* ckpt,
                      hipStream_t s) {
-  hipLaunchKernelGGL(k_epilogue, PD_GRID(V.nv), 0, s, V, St, q_next, v_next, ckpt);
+  launch_ext(k_epilogue, PD_GRID(V.nv), 0, s, V, St, q_next, v_next, ckpt);
 }
 void launch_to_lib(const VertArgs& V, const double* user, double* lib, int free_only, hipStream_t s) {
-  hipLaunchKernelGGL(k_to_lib, PD_GRID(V.nv), 0, s, V, user, lib, free_only);
+  launch_ext(k_to_lib, PD_GRID(V.nv), 0, s, V, user, lib, free_only);
 }
 void launch_from_lib(const VertArgs& V, const double* lib, double* user, int free_only, hipStream_t s) {
-  hipLaunchKernelGGL(k_from_lib, PD_GRID(V.nv), 0, s, V, lib, user, free_only);
+  launch_ext(k_from_lib, PD_GRID(V.nv), 0, s, V, lib, user, free_only);
 }
 void launch_tr_partials(const ElemArgs& E, const VertArgs& V, const RedArgs& R, const double* ck, hipStream_t s) {
   const int ntb = (E.ne + kBlock - 1) / kBlock;
   const int nblk = ntb + (V.nf + kBlock - 1) / kBlock;
-  hipLaunchKernelGGL(k_tr_partials, dim3(nblk), dim3(kBlock), 0, s, E, V, R, ck, ntb);
+  launch_ext(k_tr_partials, dim3(nblk), dim3(kBlock), 0, s, E, V, R, ck, ntb);
 }
 void launch_bwd_elem(const ElemArgs& E, const VertArgs& V, const RedArgs& R, const double* ck, double eps_tr,
                      double tau_force, int use_partials, double* jac, double* bstat, hipStream_t s) {
-  hipLaunchKernelGGL(k_bwd_elem, PD_GRID(E.ne), 0, s, E, V, R, ck, eps_tr, tau_force, use_partials, jac, bstat);
+  launch_ext(k_bwd_elem, PD_GRID(E.ne), 0, s, E, V, R, ck, eps_tr, tau_force, use_partials, jac, bstat);
 }
 void launch_apply_K(int mode, const ElemArgs& E, const VertArgs& V, const AdjState& A, const RedArgs& R,
                     const double* jac, const double* x, int it, hipStream_t s) {
-  if (mode == kModePCG) hipLaunchKernelGGL(k_apply_K<kModePCG>, PD_GRID(E.ne), 0, s, E, V, A, R, jac, x, it);
-  else if (mode == kModeFixed) hipLaunchKernelGGL(k_apply_K<kModeFixed>, PD_GRID(E.ne), 0, s, E, V, A, R, jac, x, it);
-  else hipLaunchKernelGGL(k_apply_K<kModeDebug>, PD_GRID(E.ne), 0, s, E, V, A, R, jac, x, it);
+  if (mode == kModePCG) launch_ext(k_apply_K<kModePCG>, PD_GRID(E.ne), 0, s, E, V, A, R, jac, x, it);
+  else if (mode == kModeFixed) launch_ext(k_apply_K<kModeFixed>, PD_GRID(E.ne), 0, s, E, V, A, R, jac, x, it);
+  else if (mode == kModeAmK) launch_ext(k_apply_K<kModeAmK>, PD_GRID(E.ne), 0, s, E, V, A, R, jac, x, it);
+  else launch_ext(k_apply_K<kModeDebug>, PD_GRID(E.ne), 0, s, E, V, A, R, jac, x, it);
 }
 void launch_adj_gather(int mode, const VertArgs& V, const AdjState& A, const RedArgs& R, int it, hipStream_t s) {
   const dim3 g(vert_group_blocks(V.nf)), b(kBlock);
-  if (mode == kModePCG) hipLaunchKernelGGL(k_adj_gather<kModePCG>, g, b, 0, s, V, A, R, it);
-  else if (mode == kModeFixed) hipLaunchKernelGGL(k_adj_gather<kModeFixed>, g, b, 0, s, V, A, R, it);
-  else hipLaunchKernelGGL(k_adj_gather<kModeDebug>, g, b, 0, s, V, A, R, it);
+  if (mode == kModePCG) launch_ext(k_adj_gather<kModePCG>, g, b, 0, s, V, A, R, it);
+  else if (mode == kModeFixed) launch_ext(k_adj_gather<kModeFixed>, g, b, 0, s, V, A, R, it);
+  else if (mode == kModeInit) launch_ext(k_adj_gather<kModeInit>, g, b, 0, s, V, A, R, it);
+  else launch_ext(k_adj_gather<kModeDebug>, g, b, 0, s, V, A, R, it);
 }
-void launch_bwd_prologue(const VertArgs& V, const AdjState& A, const double* gq, const double* gv, hipStream_t s) {
-  hipLaunchKernelGGL(k_bwd_prologue, PD_GRID(V.nv), 0, s, V, A, gq, gv);
+void launch_bwd_prologue(const VertArgs& V, const AdjState& A, const double* gq, const double* gv, int warm,
+                         const double* h1, const double* h2, hipStream_t s) {
+  launch_ext(k_bwd_prologue, PD_GRID(V.nv), 0, s, V, A, gq, gv, warm, h1, h2);
 }
 void launch_grad_elem(const ElemArgs& E, const VertArgs& V, const double* ck, const double* jac, const double* mu,
                       double* contrib, double* g_logE, hipStream_t s) {
-  hipLaunchKernelGGL(k_grad_elem, PD_GRID(E.ne), 0, s, E, V, ck, jac, mu, contrib, g_logE);
+  launch_ext(k_grad_elem, PD_GRID(E.ne), 0, s, E, V, ck, jac, mu, contrib, g_logE);
 }
 void launch_grad_vert(const VertArgs& V, const double* mu, const double* contrib, const double* gv_next, double* gq_t,
                       double* gv_t, double* gf, hipStream_t s) {
-  hipLaunchKernelGGL(k_grad_vert, dim3(vert_group_blocks(V.nv)), dim3(kBlock), 0, s, V, mu, contrib, gv_next, gq_t,
+  launch_ext(k_grad_vert, dim3(vert_group_blocks(V.nv)), dim3(kBlock), 0, s, V, mu, contrib, gv_next, gq_t,
                      gv_t, gf);
 }
 void launch_init_warm(const ElemArgs& E, hipStream_t s) {
-  hipLaunchKernelGGL(k_init_warm, PD_GRID(E.ne), 0, s, E);
+  launch_ext(k_init_warm, PD_GRID(E.ne), 0, s, E);
 }
-void launch_zero_int(int* p, int n, hipStream_t s) { hipLaunchKernelGGL(k_zero_int, PD_GRID(n), 0, s, p, n); }
+void launch_zero_int(int* p, int n, hipStream_t s) { launch_ext(k_zero_int, PD_GRID(n), 0, s, p, n); }
 
 }  // namespace pdhot

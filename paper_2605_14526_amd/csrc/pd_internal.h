@@ -32,11 +32,34 @@ void build_layout(int nv, int ne, const double* X, const int32_t* tets, const ui
                   Layout& L);
 
 // ---------------------------------------------------------------- device scene
+// Couplings of interface row i with the subdomains s it borders (row p of
+// E_s = A_Ts A_ss^{-1}).  E is stored row-concatenated: the rows E_s[p, :] of
+// all couplings of i follow each other from off.  Coupling c starts at entry
+// pre of that range, maps to the subdomain rows b0 .. b0 + ns - 1, and its
+// interface value sits at pos = ir_off[s] + p of the per-subdomain interface
+// vectors.  Unused entries (c >= n) repeat pre = len and are never read.
+constexpr int kMaxCoup = 8;
+struct alignas(16) Cpl {
+  int b0, pre, pos, pad;
+};
+struct alignas(16) ERow {
+  long long off;
+  int len, n;
+};
+// A subdomain row: its subdomain's first row b0, size ns, interface count nI
+// and interface offset ir0, and the offsets of its rows of Z_s and E_s^T.
+struct alignas(16) BRow {
+  int b0, ns, nI, ir0;
+};
+struct alignas(16) BOff {
+  long long zs, et;
+};
+
 struct DeviceSolve {
   // partitioned inverse of A~ over free vertices (two-level Schur complement)
   double* Zs = nullptr;         // per subdomain n_s x n_s (row-major), = A_ss^{-1}
   double* Et = nullptr;         // per subdomain n_s x |I_s| (row v holds E_s[:, v]), E_s = A_Ts A_ss^{-1}
-  double* E = nullptr;          // per subdomain |I_s| x n_s (row p holds E_s[p, :])
+  double* E = nullptr;          // per interface row: E_s[p, :] of its couplings, concatenated
   double* Z = nullptr;          // nT x nT, inverse Schur complement
   long long* zs_off = nullptr;  // nsub + 1
   long long* e_off = nullptr;   // nsub + 1 (same offsets for E and Et)
@@ -48,6 +71,13 @@ struct DeviceSolve {
   int* rl_sub = nullptr;
   int* rl_p = nullptr;
   double* rT = nullptr;         // 3 x nT
+  Cpl* cpl = nullptr;           // nT x kMaxCoup
+  ERow* erow = nullptr;         // nT
+  BRow* brow = nullptr;         // nB
+  BOff* boff = nullptr;         // nB
+  double* xsT = nullptr;        // 3 x n_irows: interface values gathered per subdomain
+  int n_irows = 0;
+  int max_coup = 0;
   size_t bytes = 0;
   double zs_entries = 0, e_entries = 0;
 };
@@ -114,6 +144,10 @@ struct Scene {
   double* jac = nullptr;       // 33 x ne compact prox differential
   double *mu = nullptr, *r0 = nullptr, *r1 = nullptr, *z = nullptr, *p = nullptr, *Ap = nullptr, *wv = nullptr,
          *qbar = nullptr;
+  // adjoint warm start: the last two adjoint solutions of a backward sweep
+  double *mu_h1 = nullptr, *mu_h2 = nullptr;
+  int adj_hist = 0, adj_warm = 0;
+  int fwd_start = 0;  // 0: q0 = q_t; 1: q0 = q_t + h v_t (when the caller passes no q0)
   double* ck_scratch = nullptr;  // 12 x nv (diagnostic K apply)
   KernelTimer kt;
 };

@@ -27,6 +27,7 @@ FP64_VECTOR_PEAK_TFLOPS = 78.6
 
 # kernel ids understood by pd_kernel_timer (see include/pdhot.h)
 KERNELS = {"local": 0, "gather": 1, "top": 2, "bottom": 3, "Eb": 4, "apply_K": 5}
+LEARNED_EDGE_WEIGHT = 100.0  # edge-difference weight of the warm-start network's training loss
 
 
 def parse():
@@ -39,7 +40,11 @@ def parse():
     ap.add_argument("--cpu-sample-steps", type=int, default=20)
     ap.add_argument("--timed-kernel", default="bottom", choices=sorted(KERNELS))
     ap.add_argument("--max-sub", type=int, default=0)
-    ap.add_argument("--no-warm-run", action="store_true", help="skip the warm-started (inertial) measurement")
+    ap.add_argument("--no-warm-run", action="store_true", help="skip the warm-started measurements")
+    ap.add_argument("--train-scenes", type=int, default=4, help="beams the warm-start network is trained on")
+    ap.add_argument("--train-epochs", type=int, default=16)
+    ap.add_argument("--batch-scenes", type=int, default=64, help="scenes of --config batch")
+    ap.add_argument("--tune-cache", default="", help="autotuner cache file of --config batch")
     return ap.parse_args()
 
 
@@ -65,8 +70,10 @@ def ensure_built():
         build.build()
 
 
-def rollout_fwd_bwd(g, sc, K, torch, dev, timed_kernel=None):
-    """K forward steps with checkpoints, then K backward steps."""
+def rollout_fwd_bwd(g, sc, K, torch, dev, net=None, logw=None):
+    """K forward steps with checkpoints, then K backward steps.  With a
+    warm-start network, each step starts from its prediction (its inference is
+    inside the timed region)."""
     q = dev(sc.q0())
     v = dev(sc.v0())
     forces = [dev(sc.f_ext(t)) for t in range(K)]
@@ -81,8 +88,11 @@ def rollout_fwd_bwd(g, sc, K, torch, dev, timed_kernel=None):
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     fiters, biters = [], []
+    q0 = torch.empty_like(q) if net is not None else None
     for t in range(K):
-        _, _, st = g.step_forward(qs[t], vs[t], forces[t], q_next=qs[t + 1], v_next=vs[t + 1], ckpt=ckpts[t])
+        if net is not None:
+            net.forward(qs[t], vs[max(t - 1, 0)], vs[t], forces[t], logw, q0=q0)
+        _, _, st = g.step_forward(qs[t], vs[t], forces[t], q0=q0, q_next=qs[t + 1], v_next=vs[t + 1], ckpt=ckpts[t])
         fiters.append(st["iters"])
     # loss = |mean(q_K) - target|^2 (the gradient is formed on the device)
     c = qs[K].mean(dim=0)
@@ -112,6 +122,61 @@ def cpu_baseline(sc, steps):
     return t1 - t0
 
 
+def bench_batch(args, torch):
+    """Uneven-beam batch (64 scenes, about 0.57 M tets): batched fwd+bwd
+    scene-steps per second after autotuning the launch shapes."""
+    from paper_2605_14526_amd import autotune, scenes
+    from paper_2605_14526_amd.binding import Batch, Scene
+    scs = scenes.beam_batch(n=args.batch_scenes, steps=args.steps)
+    t0 = time.perf_counter()
+    gs = [Scene.from_scene(sc, eps_adj=1e-6, adj_warm=2) for sc in scs]
+    t_setup = time.perf_counter() - t0
+    B = Batch(gs)
+    dev = lambda a: torch.tensor(np.ascontiguousarray(a), dtype=torch.float64, device="cuda")  # noqa: E731
+    forces = [[dev(sc.f_ext(t)) for sc in scs] for t in range(args.steps)]
+    targets = [torch.tensor(sc.target_centroid, dtype=torch.float64, device="cuda") for sc in scs]
+
+    def rollout(K):
+        q = [dev(sc.q0()) for sc in scs]
+        v = [dev(sc.v0()) for sc in scs]
+        cks = []
+        fi, bi = [], []
+        for t in range(K):
+            ck = [g.new_ckpt() for g in gs]
+            q, v, st, _ = B.step_forward(q, v, forces[t], ckpt=ck)
+            cks.append(ck)
+            fi.append(np.mean([x["iters"] for x in st]))
+        gq = [(2.0 * (qq.mean(dim=0) - tg) / qq.shape[0]).expand_as(qq).contiguous() for qq, tg in zip(q, targets)]
+        gv = [torch.zeros_like(x) for x in gq]
+        for g in gs:
+            g.adjoint_reset()
+        for ck in reversed(cks):
+            gq, gv, _, _, st, _ = B.step_backward(ck, gq, gv)
+            bi.append(np.mean([x["adj_iters"] for x in st]))
+        return fi, bi
+
+    t1 = time.perf_counter()
+    cfg = autotune.autotune(B, lambda: rollout(2), torch, cache_path=args.tune_cache or None, reps=1)
+    t_tune = time.perf_counter() - t1
+    rollout(args.warmup)
+    torch.cuda.synchronize()
+    t2 = time.perf_counter()
+    fi, bi = rollout(args.steps)
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t2
+    ne = sum(sc.n_e for sc in scs)
+    out = {"metric": METRIC, "value": round(len(scs) * args.steps / dt, 3), "unit": "scene fwd+bwd steps/s",
+           "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
+           "ms_per_step": round(1000.0 * dt / args.steps, 4), "higher_is_better": True, "scaling": "weak",
+           "vs_baseline": None, "dtype": "f64", "data": "synthetic",
+           "config": {"workload": f"batch of {len(scs)} uneven beams, {ne} tets in total (1k-30k each), "
+                                  f"contrast 1-100x, nu 0.40-0.49, h 0.01, {args.steps} steps, gate and adjoint 1e-6",
+                      "launch_shapes": cfg, "setup_s": round(t_setup, 2), "tune_s": round(t_tune, 2),
+                      "fwd_iters_per_step": round(float(np.mean(fi)), 3),
+                      "adj_iters_per_step": round(float(np.mean(bi)), 3)}}
+    print(json.dumps(out), flush=True)
+
+
 def main():
     args = parse()
     if args.gpus != 1:
@@ -120,6 +185,9 @@ def main():
         sys.exit(2)
     import torch
     ensure_built()
+    if args.config == "batch":
+        bench_batch(args, torch)
+        return
     from paper_2605_14526_amd import scenes
     from paper_2605_14526_amd.binding import Scene
 
@@ -164,17 +232,37 @@ def main():
                       "n_subdomains": int(info["n_subdomains"]), "n_interface": int(info["n_interface"])},
            "roofline": roof}
     if not args.no_warm_run:
+        out["warm_started"] = {}
         # the same rollout with the inertial first iterate q0 = q_t + h v_t
         gw = Scene.from_scene(sc, eps_adj=1e-6, max_sub=args.max_sub, adj_warm=2, fwd_start=1)
         if args.warmup > 0:
             rollout_fwd_bwd(gw, sc, args.warmup, torch, dev)
         dtw, fw, bw, _ = rollout_fwd_bwd(gw, sc, args.steps, torch, dev)
-        out["warm_started"] = {"value": round(args.steps / dtw, 3), "unit": "steps/s",
-                               "ms_per_step": round(1000.0 * dtw / args.steps, 4),
-                               "fwd_iters_per_step": round(float(np.mean(fw)), 3),
-                               "adj_iters_per_step": round(float(np.mean(bw)), 3),
-                               "start": "inertial q0 = q_t + h v_t"}
-        print(f"[bench] warm-started run: {args.steps / dtw:.1f} steps/s", file=sys.stderr, flush=True)
+        out["warm_started"]["inertial"] = {"value": round(args.steps / dtw, 3), "unit": "steps/s",
+                                           "ms_per_step": round(1000.0 * dtw / args.steps, 4),
+                                           "fwd_iters_per_step": round(float(np.mean(fw)), 3),
+                                           "adj_iters_per_step": round(float(np.mean(bw)), 3),
+                                           "start": "q0 = q_t + h v_t"}
+        print(f"[bench] inertial start: {args.steps / dtw:.1f} steps/s", file=sys.stderr, flush=True)
+        # the learned start: a network trained here, on the GPU, on plain rollouts of other beams
+        from paper_2605_14526_amd import warmstart
+        fam = lambda k: scenes.hetero_beam_family(k, steps=args.steps)  # noqa: E731
+        net, hist, tsec, nsamp = warmstart.train_for(fam, args.train_scenes, 100, args.train_epochs, torch, seed=1,
+                                                     edge_weight=LEARNED_EDGE_WEIGHT)
+        logw = torch.tensor(g.vertex_logw(), dtype=torch.float64, device="cuda")
+        if args.warmup > 0:
+            rollout_fwd_bwd(g, sc, args.warmup, torch, dev, net, logw)
+        dtl, fl, bl, _ = rollout_fwd_bwd(g, sc, args.steps, torch, dev, net, logw)
+        out["warm_started"]["learned"] = {"value": round(args.steps / dtl, 3), "unit": "steps/s",
+                                          "ms_per_step": round(1000.0 * dtl / args.steps, 4),
+                                          "fwd_iters_per_step": round(float(np.mean(fl)), 3),
+                                          "adj_iters_per_step": round(float(np.mean(bl)), 3),
+                                          "start": "message-passing network (BF16 matrix cores), inference timed",
+                                          "train": {"scenes": args.train_scenes, "samples": nsamp,
+                                                    "epochs": args.train_epochs, "seconds": round(tsec, 2),
+                                                    "final_loss": hist[-1]}}
+        print(f"[bench] learned start: {args.steps / dtl:.1f} steps/s, fwd iters/step {np.mean(fl):.2f} "
+              f"(trained {tsec:.1f} s)", file=sys.stderr, flush=True)
     if not args.no_cpu_baseline:
         n = args.cpu_sample_steps
         t = cpu_baseline(sc, n)

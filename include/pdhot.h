@@ -209,6 +209,98 @@ int pd_kernel_timer(pd_scene* scene, int kernel);
 int pd_kernel_timer_read(pd_scene* scene, double* total_ms, int64_t* launches, int64_t* working,
                          double* bytes_per_launch);
 
+/* ------------------------------------------------------------------------
+ * Batches: many scenes (any sizes, materials and Anderson windows) stepped
+ * together.  Every stage of a PD iteration and of an adjoint iteration is one
+ * launch across all scenes; each scene keeps its own state, reductions and
+ * convergence flag, so a converged scene idles while the others iterate.
+ * Results are bitwise those of stepping each scene alone.  The scenes stay
+ * owned by the caller and must outlive the batch; a batch runs the PCG
+ * adjoint (adj_method 0).  Array arguments hold one pointer per scene, in the
+ * order given to pd_batch_create (device buffers as for the single-scene
+ * calls; NULL entries where those calls allow NULL).
+ * ------------------------------------------------------------------------ */
+typedef struct pd_batch pd_batch;
+int pd_batch_create(pd_scene* const* scenes, int n, pd_batch** out);
+int pd_batch_destroy(pd_batch* batch);
+/* Launch shapes and host checks: workgroup sizes (64, 128 or 256 threads) of
+ * the local step and of the K apply, PD / adjoint iterations issued between
+ * convergence checks (0 = adaptive; graphs use 4 then), and use_graph = 1 to
+ * capture each chunk of iterations once into a HIP graph and replay it. */
+int pd_batch_config(pd_batch* batch, int block_local, int block_applyK, int iters_per_check, int use_graph);
+/* pd_step_forward / pd_step_backward on every scene of the batch. stats: arrays
+ * of n entries or NULL. Returns PD_NOT_CONVERGED if any scene did not converge. */
+int pd_batch_step_forward(pd_batch* batch, const double* const* q_t, const double* const* v_t,
+                          const double* const* f_ext, const double* const* q0, double* const* q_next,
+                          double* const* v_next, void* const* ckpt, pd_fwd_stats* stats, void* stream);
+int pd_batch_step_backward(pd_batch* batch, const void* const* ckpt, const double* const* gq_next,
+                           const double* const* gv_next, double* const* gq_t, double* const* gv_t,
+                           double* const* gf_ext, double* const* g_logE_accum, pd_bwd_stats* stats, void* stream);
+
+/* Per-vertex material feature of the learned warm start: the mean of
+ * log(2 mu_e + lam_e) over the vertex's tets (Eq. lame, the PD weight of
+ * Sec. 4.2), minus its mean over the vertices.  out: host, n_verts doubles. */
+int pd_scene_vertex_logw(const pd_scene* scene, double* out);
+
+/* ------------------------------------------------------------------------
+ * Learned warm start (an extension: the paper starts every step from q_t).
+ * A message-passing network on the mesh edges predicts the correction of the
+ * inertial guess; pd_step_forward takes its output as q0 and still iterates to
+ * the same dual-gate tolerance.  Network: 16 node features
+ * ((q_t - X)/l, h (v_t - v_{t-h})/s_out, h v_t/l, h^2 f/(m s_out),
+ * (X - X_min)/L, vertex log w), encoder 16 -> 64 (SiLU), two message-passing layers
+ * (m_ij = SiLU([h_i, h_j, (q_j - q_i)/l, (X_j - X_i)/l] W_msg + b_msg), sum over
+ * in-edges, h_i += SiLU([h_i, a_i] W_node + b_node)), decoder 64 -> 3; q0 =
+ * q_t + h v_t + s_out y on free vertices (l = mean edge length, L = largest
+ * bounding-box extent).  Parameters: one FP32 vector, in the order W_enc
+ * (16 x 64, row-major), b_enc, per layer W_msg (134 x 64), b_msg, W_node
+ * (128 x 64), b_node, then W_dec (64 x 3), b_dec.
+ * ------------------------------------------------------------------------ */
+typedef struct pd_mpn pd_mpn;
+typedef struct pd_mpn_desc {
+  int32_t compute;  /* 0 = BF16 products on the matrix cores (FP32 accumulate), 1 = FP32 */
+  double h;         /* time step of the scenes it serves */
+  double rho;       /* density (lumped masses of the force feature) */
+  double edge_weight; /* kappa of the training loss (edge-difference term, below) */
+} pd_mpn_desc;
+
+/* Build the network for a mesh (host arrays as in pd_scene_create; only the
+ * topology, rest positions and pinned flags are used).  Weights are zero until
+ * pd_mpn_init_params or pd_mpn_set_params. */
+int pd_mpn_create(const pd_mesh_desc* mesh, const pd_mpn_desc* desc, pd_mpn** out);
+int pd_mpn_destroy(pd_mpn* mpn);
+/* info[0..6] = n_verts, directed edges, mean edge length, largest extent,
+ * parameter count, output scale, compute mode. */
+int pd_mpn_info(const pd_mpn* mpn, double* info);
+/* Seeded initialisation: uniform(-1, 1)/sqrt(fan_in) weights (decoder x 0.1),
+ * zero biases; resets the Adam moments. */
+int pd_mpn_init_params(pd_mpn* mpn, uint64_t seed);
+/* Host FP32 parameter vectors of exactly the parameter count. */
+int pd_mpn_set_params(pd_mpn* mpn, const float* host, int64_t n);
+int pd_mpn_get_params(const pd_mpn* mpn, float* host, int64_t n);
+/* Gradient of the last pd_mpn_loss_grad (host copy). */
+int pd_mpn_get_grads(const pd_mpn* mpn, float* host, int64_t n);
+/* s_out: the scale of the predicted correction (positions per unit output);
+ * it also scales the correction-sized input features. */
+int pd_mpn_set_output_scale(pd_mpn* mpn, double s_out);
+/* q0 (device, n_verts x 3) for the step from (q_t, v_t) with the previous
+ * step's velocity v_tm1 (v_t at the first step), the external force f_ext
+ * (NULL = none) and the per-vertex
+ * log w (device, n_verts, from pd_scene_vertex_logw).  Pinned vertices get q_t. */
+int pd_mpn_forward(pd_mpn* mpn, const double* q_t, const double* v_tm1, const double* v_t, const double* f_ext,
+                   const double* logw, double* q0, void* stream);
+/* One training sample: forward, the loss
+ *   sum_free |r|^2 / (3 n_free) + kappa sum_edges |r_j - r_i|^2 / (3 n_edges),
+ *   r = y - (q_next - q_t - h v_t)/s_out on free vertices (0 on pinned),
+ * summed over the directed edges (the second term weighs the strain that the
+ * correction implies), and its gradient with respect to the parameters (kept
+ * on the device).  loss: host pointer or NULL (NULL avoids a
+ * synchronisation). */
+int pd_mpn_loss_grad(pd_mpn* mpn, const double* q_t, const double* v_tm1, const double* v_t, const double* f_ext,
+                     const double* logw, const double* q_next, double* loss, void* stream);
+/* One Adam step on the FP32 master weights with the last gradient. */
+int pd_mpn_adam_step(pd_mpn* mpn, double lr, double beta1, double beta2, double eps, void* stream);
+
 /* Message of the last failing call on this thread ("" if none). */
 const char* pd_last_error(void);
 

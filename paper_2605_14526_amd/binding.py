@@ -23,7 +23,11 @@ ERRORS = {-1: "PD_ERR_INVALID_ARG", -2: "PD_ERR_DEGENERATE_TET", -3: "PD_ERR_NON
 
 EXPORTED = ["pd_scene_create", "pd_scene_destroy", "pd_scene_set_material", "pd_scene_factorize", "pd_scene_info",
             "pd_ckpt_bytes", "pd_step_forward", "pd_step_backward", "pd_debug_local_rhs", "pd_debug_apply_Ainv",
-            "pd_debug_apply_K", "pd_kernel_timer", "pd_kernel_timer_read", "pd_adjoint_reset", "pd_last_error"]
+            "pd_debug_apply_K", "pd_kernel_timer", "pd_kernel_timer_read", "pd_adjoint_reset", "pd_scene_vertex_logw",
+            "pd_mpn_create", "pd_mpn_destroy", "pd_mpn_info", "pd_mpn_init_params", "pd_mpn_set_params",
+            "pd_mpn_get_params", "pd_mpn_get_grads", "pd_mpn_set_output_scale", "pd_mpn_forward", "pd_mpn_loss_grad",
+            "pd_mpn_adam_step", "pd_batch_create", "pd_batch_destroy", "pd_batch_config", "pd_batch_step_forward",
+            "pd_batch_step_backward", "pd_last_error"]
 
 
 class pd_mesh_desc(ctypes.Structure):
@@ -42,6 +46,11 @@ class pd_solver_opts(ctypes.Structure):
                 ("kmax_bwd", ctypes.c_int32), ("eps_adj", ctypes.c_double), ("eps_tr", ctypes.c_double),
                 ("adj_method", ctypes.c_int32), ("max_sub", ctypes.c_int32), ("iters_per_check", ctypes.c_int32),
                 ("adj_warm", ctypes.c_int32), ("fwd_start", ctypes.c_int32)]
+
+
+class pd_mpn_desc(ctypes.Structure):
+    _fields_ = [("compute", ctypes.c_int32), ("h", ctypes.c_double), ("rho", ctypes.c_double),
+                ("edge_weight", ctypes.c_double)]
 
 
 class pd_fwd_stats(ctypes.Structure):
@@ -84,6 +93,23 @@ def lib() -> ctypes.CDLL:
     L.pd_kernel_timer.argtypes = [vp, i32]
     L.pd_kernel_timer_read.argtypes = [vp, vp, vp, vp, vp]
     L.pd_adjoint_reset.argtypes = [vp]
+    L.pd_scene_vertex_logw.argtypes = [vp, vp]
+    L.pd_mpn_create.argtypes = [ctypes.POINTER(pd_mesh_desc), ctypes.POINTER(pd_mpn_desc), ctypes.POINTER(vp)]
+    L.pd_mpn_destroy.argtypes = [vp]
+    L.pd_mpn_info.argtypes = [vp, vp]
+    L.pd_mpn_init_params.argtypes = [vp, ctypes.c_uint64]
+    L.pd_mpn_set_params.argtypes = [vp, vp, ctypes.c_int64]
+    L.pd_mpn_get_params.argtypes = [vp, vp, ctypes.c_int64]
+    L.pd_mpn_get_grads.argtypes = [vp, vp, ctypes.c_int64]
+    L.pd_mpn_set_output_scale.argtypes = [vp, dbl]
+    L.pd_mpn_forward.argtypes = [vp, vp, vp, vp, vp, vp, vp, vp]
+    L.pd_mpn_loss_grad.argtypes = [vp, vp, vp, vp, vp, vp, vp, vp, vp]
+    L.pd_mpn_adam_step.argtypes = [vp, dbl, dbl, dbl, dbl, vp]
+    L.pd_batch_create.argtypes = [vp, i32, ctypes.POINTER(vp)]
+    L.pd_batch_destroy.argtypes = [vp]
+    L.pd_batch_config.argtypes = [vp, i32, i32, i32, i32]
+    L.pd_batch_step_forward.argtypes = [vp, vp, vp, vp, vp, vp, vp, vp, vp, vp]
+    L.pd_batch_step_backward.argtypes = [vp, vp, vp, vp, vp, vp, vp, vp, vp, vp]
     L.pd_last_error.restype = ctypes.c_char_p
     for name in EXPORTED:
         getattr(L, name)
@@ -201,6 +227,12 @@ class Scene:
                                    dphi_act=st.dphi_act, dphi_mod=st.dphi_mod, residual=st.residual, rc=rc)
         return gq_t, gv_t, gf_ext, g_logE, self.last_bwd_stats
 
+    def vertex_logw(self) -> np.ndarray:
+        """Per-vertex mean log(2 mu_e + lam_e) minus its mean (the warm-start network's material feature)."""
+        out = np.zeros(self.n_verts)
+        check(lib().pd_scene_vertex_logw(self.ptr, out.ctypes.data), "pd_scene_vertex_logw")
+        return out
+
     def adjoint_reset(self):
         """Start the next backward step from zero (clears the adjoint warm-start history)."""
         check(lib().pd_adjoint_reset(self.ptr), "pd_adjoint_reset")
@@ -238,3 +270,142 @@ class Scene:
         check(lib().pd_debug_apply_K(self.ptr, _ptr(q), float(tau), _ptr(x), _ptr(y), _stream()),
               "pd_debug_apply_K")
         return y
+
+
+class Mpn:
+    """The learned warm-start network on one mesh (wraps pd_mpn_create ... pd_mpn_destroy)."""
+
+    def __init__(self, X, tets, pinned, h, rho, compute=0, edge_weight=0.0):
+        L = lib()
+        self._X = np.ascontiguousarray(X, dtype=np.float64)
+        self._tets = np.ascontiguousarray(tets, dtype=np.int32)
+        self._pinned = np.ascontiguousarray(pinned, dtype=np.uint8)
+        mesh = pd_mesh_desc(int(self._X.shape[0]), int(self._tets.shape[0]), self._X.ctypes.data,
+                            self._tets.ctypes.data, self._pinned.ctypes.data)
+        desc = pd_mpn_desc(int(compute), float(h), float(rho), float(edge_weight))
+        ptr = ctypes.c_void_p()
+        check(L.pd_mpn_create(ctypes.byref(mesh), ctypes.byref(desc), ctypes.byref(ptr)), "pd_mpn_create")
+        self.ptr = ptr
+        self.n_params = int(self.info()["n_params"])
+
+    @classmethod
+    def for_scene(cls, sc, compute=0, edge_weight=0.0):
+        return cls(sc.X, sc.tets, sc.pinned, sc.h, sc.rho, compute, edge_weight)
+
+    def close(self):
+        if getattr(self, "ptr", None) is not None and self.ptr.value:
+            lib().pd_mpn_destroy(self.ptr)
+        self.ptr = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def info(self):
+        info = (ctypes.c_double * 7)()
+        check(lib().pd_mpn_info(self.ptr, info), "pd_mpn_info")
+        keys = ["n_verts", "n_edges", "ell", "L", "n_params", "s_out", "compute"]
+        return {k: info[i] for i, k in enumerate(keys)}
+
+    def init_params(self, seed: int):
+        check(lib().pd_mpn_init_params(self.ptr, int(seed)), "pd_mpn_init_params")
+
+    def set_params(self, theta):
+        a = np.ascontiguousarray(theta, dtype=np.float32)
+        check(lib().pd_mpn_set_params(self.ptr, a.ctypes.data, a.size), "pd_mpn_set_params")
+
+    def get_params(self) -> np.ndarray:
+        a = np.zeros(self.n_params, dtype=np.float32)
+        check(lib().pd_mpn_get_params(self.ptr, a.ctypes.data, a.size), "pd_mpn_get_params")
+        return a
+
+    def get_grads(self) -> np.ndarray:
+        a = np.zeros(self.n_params, dtype=np.float32)
+        check(lib().pd_mpn_get_grads(self.ptr, a.ctypes.data, a.size), "pd_mpn_get_grads")
+        return a
+
+    def set_output_scale(self, s_out: float):
+        check(lib().pd_mpn_set_output_scale(self.ptr, float(s_out)), "pd_mpn_set_output_scale")
+
+    def forward(self, q_t, v_tm1, v_t, f_ext, logw, q0=None):
+        import torch
+        q0 = torch.empty_like(q_t) if q0 is None else q0
+        check(lib().pd_mpn_forward(self.ptr, _ptr(q_t), _ptr(v_tm1), _ptr(v_t), _ptr(f_ext), _ptr(logw), _ptr(q0),
+                                   _stream()), "pd_mpn_forward")
+        return q0
+
+    def loss_grad(self, q_t, v_tm1, v_t, f_ext, logw, q_next, want_loss=True):
+        loss = ctypes.c_double(0.0)
+        check(lib().pd_mpn_loss_grad(self.ptr, _ptr(q_t), _ptr(v_tm1), _ptr(v_t), _ptr(f_ext), _ptr(logw),
+                                     _ptr(q_next), ctypes.byref(loss) if want_loss else None, _stream()),
+              "pd_mpn_loss_grad")
+        return loss.value if want_loss else None
+
+    def adam_step(self, lr, beta1=0.9, beta2=0.999, eps=1e-8):
+        check(lib().pd_mpn_adam_step(self.ptr, float(lr), float(beta1), float(beta2), float(eps), _stream()),
+              "pd_mpn_adam_step")
+
+
+def _ptrs(ts):
+    if ts is None:
+        return None
+    arr = (ctypes.c_void_p * len(ts))(*[(t.data_ptr() if t is not None else None) for t in ts])
+    return arr
+
+
+class Batch:
+    """Several scenes stepped together (wraps pd_batch_*); the scenes must outlive it."""
+
+    def __init__(self, scenes):
+        self.scenes = list(scenes)
+        arr = (ctypes.c_void_p * len(self.scenes))(*[sc.ptr.value for sc in self.scenes])
+        ptr = ctypes.c_void_p()
+        check(lib().pd_batch_create(arr, len(self.scenes), ctypes.byref(ptr)), "pd_batch_create")
+        self.ptr = ptr
+        self.cfg = dict(block_local=256, block_applyK=256, iters_per_check=0, use_graph=0)
+
+    def close(self):
+        if getattr(self, "ptr", None) is not None and self.ptr.value:
+            lib().pd_batch_destroy(self.ptr)
+        self.ptr = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def config(self, block_local=256, block_applyK=256, iters_per_check=0, use_graph=0):
+        check(lib().pd_batch_config(self.ptr, int(block_local), int(block_applyK), int(iters_per_check),
+                                    int(use_graph)), "pd_batch_config")
+        self.cfg = dict(block_local=block_local, block_applyK=block_applyK, iters_per_check=iters_per_check,
+                        use_graph=use_graph)
+
+    def step_forward(self, q_t, v_t, f_ext=None, q0=None, q_next=None, v_next=None, ckpt=None):
+        import torch
+        n = len(self.scenes)
+        q_next = [torch.empty_like(q) for q in q_t] if q_next is None else q_next
+        v_next = [torch.empty_like(q) for q in q_t] if v_next is None else v_next
+        st = (pd_fwd_stats * n)()
+        keep = [_ptrs(q_t), _ptrs(v_t), _ptrs(f_ext), _ptrs(q0), _ptrs(q_next), _ptrs(v_next), _ptrs(ckpt)]
+        rc = check(lib().pd_batch_step_forward(self.ptr, *keep, st, _stream()), "pd_batch_step_forward")
+        stats = [dict(iters=x.iters, aa_resets=x.aa_resets, status=x.status, newton_capped=x.newton_capped,
+                      gate=list(x.gate)) for x in st]
+        return q_next, v_next, stats, rc
+
+    def step_backward(self, ckpt, gq_next, gv_next, g_logE=None, gq_t=None, gv_t=None, gf_ext=None):
+        import torch
+        n = len(self.scenes)
+        gq_t = [torch.empty_like(g) for g in gq_next] if gq_t is None else gq_t
+        gv_t = [torch.empty_like(g) for g in gq_next] if gv_t is None else gv_t
+        gf_ext = [torch.empty_like(g) for g in gq_next] if gf_ext is None else gf_ext
+        if g_logE is None:
+            g_logE = [torch.zeros(sc.n_tets, dtype=torch.float64, device="cuda") for sc in self.scenes]
+        st = (pd_bwd_stats * n)()
+        keep = [_ptrs(ckpt), _ptrs(gq_next), _ptrs(gv_next), _ptrs(gq_t), _ptrs(gv_t), _ptrs(gf_ext), _ptrs(g_logE)]
+        rc = check(lib().pd_batch_step_backward(self.ptr, *keep, st, _stream()), "pd_batch_step_backward")
+        stats = [dict(adj_iters=x.adj_iters, status=x.status, rho=x.rho, tau=x.tau, residual=x.residual)
+                 for x in st]
+        return gq_t, gv_t, gf_ext, g_logE, stats, rc

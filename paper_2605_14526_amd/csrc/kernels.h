@@ -116,6 +116,37 @@ struct AdjState {
   double* dstat;  // [residual]
 };
 
+// Everything a kernel needs about one scene, for launches that span many
+// scenes (one device array entry per scene).
+struct SceneBundle {
+  ElemArgs E;
+  VertArgs V;
+  SolveArgs S;
+  StepState St;
+  AdjState A;
+  RedArgs R;
+  const double* jac;
+};
+
+// Block-to-scene map of a batched launch: scene s owns blocks
+// base[s] .. base[s+1]-1 (empty ranges allowed).
+struct BatchMap {
+  const SceneBundle* B;
+  const int* base;
+  int ns;
+};
+
+enum { kBKLocal = 0, kBKGather = 1, kBKEb = 2, kBKTop = 3, kBKBottom = 4, kBKApplyK = 5, kBKKinds = 6 };
+
+void launch_b_local(const BatchMap& M, int nblk, int block, int k, hipStream_t s);
+void launch_b_gather_fwd(const BatchMap& M, int nblk, int k, hipStream_t s);
+void launch_b_Eb(int mode, const BatchMap& M, int nblk, int k, hipStream_t s);
+void launch_b_top(const BatchMap& M, int nblk, int adjoint, hipStream_t s);
+void launch_b_bottom(int mode, const BatchMap& M, int nblk, int k, hipStream_t s);
+void launch_b_apply_K(int mode, const BatchMap& M, int nblk, int block, int it, hipStream_t s);
+void launch_b_adj_gather(int mode, const BatchMap& M, int nblk, int it, hipStream_t s);
+void launch_b_flags(const BatchMap& M, int* ctl_out, double* dstat_out, hipStream_t s);
+
 // Per-launch timing: arm a start/stop event pair for the next kernel launch of
 // this thread (stamped by the dispatch itself); launch_events_used() tells
 // whether a launch consumed them and disarms.

@@ -78,9 +78,9 @@ __device__ __forceinline__ void write_partial(double (&v)[N], const RedArgs& R, 
 }
 
 // Consumer side: the total of the first N values of every partial of `site`
-// (fixed order), returned to every thread; block 0 also stores it in fin.
+// (fixed order), returned to every thread; block 0 (bid) also stores it in fin.
 template <int N>
-__device__ __forceinline__ void consume(const RedArgs& R, int site, double (&tot)[N], int width = N) {
+__device__ __forceinline__ void consume(const RedArgs& R, int site, double (&tot)[N], int bid, int width = N) {
   __shared__ double red[16 * N];
   __shared__ double bc[N];
   const double* part = R.part + (size_t)site * R.max_parts * kRedWidth;
@@ -97,7 +97,7 @@ __device__ __forceinline__ void consume(const RedArgs& R, int site, double (&tot
 #pragma unroll
     for (int j = 0; j < N; ++j) {
       bc[j] = tot[j];
-      if (blockIdx.x == 0) R.fin[site * kFinStride + j] = tot[j];
+      if (bid == 0) R.fin[site * kFinStride + j] = tot[j];
     }
   }
   __syncthreads();
@@ -269,7 +269,8 @@ __device__ __forceinline__ void aa_layout(const int* st, int m, int& nonempty, i
 // thread of the block must call it; loads issued before the call stay ahead
 // of its barriers.
 template <int M>
-__device__ __forceinline__ void aa_prepare(const StepState& St, const RedArgs& R, int k, bool reduce, AAMix& out) {
+__device__ __forceinline__ void aa_prepare(const StepState& St, const RedArgs& R, int k, bool reduce, AAMix& out,
+                                           int bid) {
   __shared__ AAMix mx;
   constexpr int NA = (M > 0) ? M * M + M : 1;
   int flag = 0;
@@ -285,7 +286,7 @@ __device__ __forceinline__ void aa_prepare(const StepState& St, const RedArgs& R
   }
   if (M > 0 && k >= 1) {
     if (reduce) {
-      consume<NA>(R, kRedAA, tot);  // Gram sums of iteration k-1: G[j][l] at j*M + l, rhs[j] at M*M + j
+      consume<NA>(R, kRedAA, tot, bid);  // Gram sums of iteration k-1: G[j][l] at j*M + l, rhs[j] at M*M + j
     } else if (threadIdx.x == 0) {
 #pragma unroll
       for (int j = 0; j < NA; ++j) tot[j] = R.fin[kRedAA * kFinStride + j];
@@ -399,9 +400,9 @@ __device__ __forceinline__ double aa_value(const StepState& St, const AAMix& mx,
 // contribution w_e V_e G_e^T p*_e (Eq. A_basic).  The SVD and the prox Newton
 // start from the tet's previous rotation and stretch ratios.
 template <int M>
-__global__ void __launch_bounds__(kBlock) k_local(ElemArgs E, StepState St, RedArgs R, const double* __restrict__ q,
-                                                  int nv, int nf, int k, int fwd, int* __restrict__ newton_cap) {
-  const int t = blockIdx.x * blockDim.x + threadIdx.x;
+__device__ __forceinline__ void b_local(ElemArgs E, StepState St, RedArgs R, const double* __restrict__ q,
+                                                  int nv, int nf, int k, int fwd, int* __restrict__ newton_cap, int bid) {
+  const int t = bid * blockDim.x + threadIdx.x;
   const bool have = t < E.ne;
   // the tet's data and warm start, requested before the Anderson scalars
   TetData T;
@@ -416,7 +417,7 @@ __global__ void __launch_bounds__(kBlock) k_local(ElemArgs E, StepState St, RedA
   }
   AAMix mx;
   if (fwd) {
-    aa_prepare<M>(St, R, k, true, mx);
+    aa_prepare<M>(St, R, k, true, mx, bid);
     if (mx.stop) return;
   }
   if (!have) return;
@@ -447,6 +448,12 @@ __global__ void __launch_bounds__(kBlock) k_local(ElemArgs E, StepState St, RedA
           wv * (U[3 * i] * ss[0] * V[3 * j] + U[3 * i + 1] * ss[1] * V[3 * j + 1] + U[3 * i + 2] * ss[2] * V[3 * j + 2]);
   store_GtP(T, St.contrib, E.ninc, P);
   store_warm(E, t, V, sF, ss);
+}
+
+template <int M>
+__global__ void __launch_bounds__(kBlock) k_local(ElemArgs E, StepState St, RedArgs R, const double* __restrict__ q,
+                                                  int nv, int nf, int k, int fwd, int* __restrict__ newton_cap) {
+  b_local<M>(E, St, R, q, nv, nf, k, fwd, newton_cap, blockIdx.x);
 }
 
 // G_e^T (w G_e x): contributions of the symmetric element operator w V G^T G
@@ -514,9 +521,9 @@ __global__ void __launch_bounds__(kBlock) k_prologue(VertArgs Vx, const double* 
 // (Eq. convergence_dual): |q^k - q^{k-1}|^2, |q^{k-1}|^2, |b^k - b^{k-1}|^2,
 // |b^{k-1}|^2.  Block 0 records the Anderson state of iteration k.
 template <int M>
-__global__ void __launch_bounds__(kBlock) k_gather_fwd(VertArgs Vx, StepState St, RedArgs R, int k) {
+__device__ __forceinline__ void b_gather_fwd(VertArgs Vx, StepState St, RedArgs R, int k, int bid) {
   const int nv = Vx.nv;
-  const int gtid = blockIdx.x * blockDim.x + threadIdx.x;
+  const int gtid = bid * blockDim.x + threadIdx.x;
   const int i = gtid >> 3, l = gtid & 7;
   const bool have = i < Vx.nf;
   const bool owner = have && l == 0;
@@ -538,7 +545,7 @@ __global__ void __launch_bounds__(kBlock) k_gather_fwd(VertArgs Vx, StepState St
       cc[a] = St.c[ix];
     }
   AAMix mx;
-  aa_prepare<M>(St, R, k, false, mx);
+  aa_prepare<M>(St, R, k, false, mx, bid);
   if (mx.stop) return;
   double part[4] = {0, 0, 0, 0};
   if (have) {
@@ -584,7 +591,7 @@ __global__ void __launch_bounds__(kBlock) k_gather_fwd(VertArgs Vx, StepState St
       }
     }
   }
-  if (blockIdx.x == 0 && threadIdx.x == 0 && k >= 1) {
+  if (bid == 0 && threadIdx.x == 0 && k >= 1) {
     int* nxt = St.ctl + kCtlAA + 4 * (k & 1);
     if (M <= 0 || mx.reset) {
       nxt[0] = 0; nxt[1] = 0; nxt[2] = 0;
@@ -593,7 +600,12 @@ __global__ void __launch_bounds__(kBlock) k_gather_fwd(VertArgs Vx, StepState St
       nxt[0] = 1; nxt[1] = mx.nc; nxt[2] = mx.head;
     }
   }
-  write_partial<4>(part, R, kRedGate, blockIdx.x);
+  write_partial<4>(part, R, kRedGate, bid);
+}
+
+template <int M>
+__global__ void __launch_bounds__(kBlock) k_gather_fwd(VertArgs Vx, StepState St, RedArgs R, int k) {
+  b_gather_fwd<M>(Vx, St, R, k, blockIdx.x);
 }
 
 // b = sum of the incidence entries of every free vertex (diagnostics)
@@ -620,10 +632,10 @@ __global__ void __launch_bounds__(kBlock) k_gather_debug(VertArgs Vx, const doub
 __device__ __forceinline__ double* r_cur(const AdjState& A, int it) { return (it & 1) ? A.r1 : A.r0; }
 
 template <int MODE>
-__global__ void __launch_bounds__(kBlock) k_Eb(VertArgs Vx, SolveArgs Sv, StepState St, AdjState A, RedArgs R,
-                                               const double* __restrict__ rhs, int k) {
+__device__ __forceinline__ void b_Eb(VertArgs Vx, SolveArgs Sv, StepState St, AdjState A, RedArgs R,
+                                               const double* __restrict__ rhs, int k, int bid) {
   const int lane = threadIdx.x & 63;
-  const int row = (blockIdx.x * blockDim.x + threadIdx.x) >> 6;
+  const int row = (bid * blockDim.x + threadIdx.x) >> 6;
   const bool have = row < Sv.nT;
   const int nv = Vx.nv, nB = Sv.nB;
   const double* __restrict__ src = (MODE == kModeFwd) ? St.b_cur : (MODE == kModePCG ? r_cur(A, k) : rhs);
@@ -650,7 +662,7 @@ __global__ void __launch_bounds__(kBlock) k_Eb(VertArgs Vx, SolveArgs Sv, StepSt
       rz = fin_site(R, kRedRZ0 + (k & 1))[0];
     }
     double pw[1] = {1.0};
-    consume<1>(R, kRedPW, pw);
+    consume<1>(R, kRedPW, pw, bid);
     if (threadIdx.x == 0) {
       stop = flag;
       alpha_s = rz / pw[0];
@@ -659,14 +671,14 @@ __global__ void __launch_bounds__(kBlock) k_Eb(VertArgs Vx, SolveArgs Sv, StepSt
     int flag = 0;
     if (threadIdx.x == 0) flag = *St.done;
     double g[4] = {0, 0, 0, 0};
-    if (k >= 1) consume<4>(R, kRedGate, g);
+    if (k >= 1) consume<4>(R, kRedGate, g, bid);
     if (threadIdx.x == 0) {
       const double dq = sqrt(g[0]), nq = sqrt(g[1]), db = sqrt(g[2]), nb = sqrt(g[3]);
       const bool pass = dq <= St.eps_rel * nq + St.eps_abs && db <= St.eps_rel * nb + St.eps_abs;
       const bool conv = (k >= 2) && pass;
       const bool cap = (k >= St.kmax - 1);
       stop = flag || conv || cap;
-      if (!flag && (conv || cap) && blockIdx.x == 0) {
+      if (!flag && (conv || cap) && bid == 0) {
         St.ctl[kCtlDone] = 1;
         St.ctl[kCtlIters] = k;
         St.ctl[kCtlStatus] = conv ? 0 : 1;
@@ -718,14 +730,20 @@ __global__ void __launch_bounds__(kBlock) k_Eb(VertArgs Vx, SolveArgs Sv, StepSt
   }
 }
 
+template <int MODE>
+__global__ void __launch_bounds__(kBlock) k_Eb(VertArgs Vx, SolveArgs Sv, StepState St, AdjState A, RedArgs R,
+                                               const double* __restrict__ rhs, int k) {
+  b_Eb<MODE>(Vx, Sv, St, A, R, rhs, k, blockIdx.x);
+}
+
 // ---------------------------------------------------------------- interface solve
 // x_T = Z r_T, one wave per interface row (Z = inverse Schur complement); the
 // value is also stored at the row's position in the per-subdomain interface
 // vectors read by the subdomain solve.  There is no done test: once a loop has
 // stopped, k_Eb leaves r_T unchanged, so this kernel rewrites the same values.
-__global__ void __launch_bounds__(kBlock) k_top(VertArgs Vx, SolveArgs Sv, double* __restrict__ out) {
+__device__ __forceinline__ void b_top(VertArgs Vx, SolveArgs Sv, double* __restrict__ out, int bid) {
   const int lane = threadIdx.x & 63;
-  const int row = (blockIdx.x * blockDim.x + threadIdx.x) >> 6;
+  const int row = (bid * blockDim.x + threadIdx.x) >> 6;
   const int nT = Sv.nT;
   if (row >= nT) return;
   const ERow er = Sv.erow[row];
@@ -760,6 +778,10 @@ __global__ void __launch_bounds__(kBlock) k_top(VertArgs Vx, SolveArgs Sv, doubl
   }
 }
 
+__global__ void __launch_bounds__(kBlock) k_top(VertArgs Vx, SolveArgs Sv, double* __restrict__ out) {
+  b_top(Vx, Sv, out, blockIdx.x);
+}
+
 // ---------------------------------------------------------------- subdomain solve
 // x_s = Z_s rhs_s - E_s^T x_T on the subdomain rows (one wave per row), then
 // the per-vertex work of each mode on every free row (the lane 0 of a
@@ -774,20 +796,20 @@ __global__ void __launch_bounds__(kBlock) k_top(VertArgs Vx, SolveArgs Sv, doubl
 // Everything a thread needs that does not depend on the row descriptors is
 // requested together with them.
 template <int MODE, int M>
-__global__ void __launch_bounds__(kBottomThreads) k_bottom(VertArgs Vx, SolveArgs Sv, StepState St, AdjState A, RedArgs R,
-                                                   const double* __restrict__ rhs, double* __restrict__ out, int k) {
+__device__ __forceinline__ void b_bottom(VertArgs Vx, SolveArgs Sv, StepState St, AdjState A, RedArgs R,
+                                                   const double* __restrict__ rhs, double* __restrict__ out, int k, int bid) {
   const int nv = Vx.nv, nB = Sv.nB, nf = Vx.nf;
   const int lane = threadIdx.x & 63;
   constexpr int kRows = kBottomThreads / 64;
   const int n_sub_blocks = (nB + kRows - 1) / kRows;
-  const bool sub_block = (int)blockIdx.x < n_sub_blocks;
-  const int v = blockIdx.x * kRows + (threadIdx.x >> 6);
+  const bool sub_block = (int)bid < n_sub_blocks;
+  const int v = bid * kRows + (threadIdx.x >> 6);
   const bool have_row = sub_block && v < nB;
   int my_row = -1;
   if (have_row) {
     if (lane == 0) my_row = v;
   } else if (!sub_block) {
-    const int i = nB + (blockIdx.x - n_sub_blocks) * blockDim.x + threadIdx.x;
+    const int i = nB + (bid - n_sub_blocks) * blockDim.x + threadIdx.x;
     if (i < nf) my_row = i;
   }
   const bool iface = my_row >= nB;
@@ -930,7 +952,7 @@ __global__ void __launch_bounds__(kBottomThreads) k_bottom(VertArgs Vx, SolveArg
       __shared__ double red[16 * NA];
       block_sum<NA>(part, red);
       if (threadIdx.x == 0) {
-        double* o = R.part + ((size_t)kRedAA * R.max_parts + blockIdx.x) * kRedWidth;
+        double* o = R.part + ((size_t)kRedAA * R.max_parts + bid) * kRedWidth;
 #pragma unroll
         for (int j = 0; j < M; ++j) {
 #pragma unroll
@@ -967,13 +989,19 @@ __global__ void __launch_bounds__(kBottomThreads) k_bottom(VertArgs Vx, SolveArg
       }
     }
     if (MODE == kModeFixed) {
-      write_partial<3>(v3, R, kRedFix, blockIdx.x);
+      write_partial<3>(v3, R, kRedFix, bid);
     } else {
       // PCG sums of iteration k land in the parity slot read by iteration k + 1
       const int slot = (MODE == kModePCGInit) ? 0 : ((k + 1) & 1);
-      write_partial<3>(v3, R, kRedRZ0 + slot, blockIdx.x);
+      write_partial<3>(v3, R, kRedRZ0 + slot, bid);
     }
   }
+}
+
+template <int MODE, int M>
+__global__ void __launch_bounds__(kBottomThreads) k_bottom(VertArgs Vx, SolveArgs Sv, StepState St, AdjState A, RedArgs R,
+                                                   const double* __restrict__ rhs, double* __restrict__ out, int k) {
+  b_bottom<MODE, M>(Vx, Sv, St, A, R, rhs, out, k, blockIdx.x);
 }
 
 // ---------------------------------------------------------------- step epilogue
@@ -1087,7 +1115,7 @@ __global__ void __launch_bounds__(kBlock) k_bwd_elem(ElemArgs E, VertArgs Vx, Re
                                                      double* __restrict__ jac, double* __restrict__ bstat) {
   __shared__ double tau_s;
   double tr[2] = {0.0, 0.0};
-  if (use_partials) consume<2>(R, kRedTR, tr);
+  if (use_partials) consume<2>(R, kRedTR, tr, blockIdx.x);
   if (threadIdx.x == 0) {
     const double act = tr[0], mod = 0.5 * fabs(tr[1]);
     const double rho = (mod < 1e-12) ? 1.0 : act / mod;
@@ -1170,7 +1198,7 @@ struct PCGCtl {
 };
 
 template <int MODE>
-__device__ __forceinline__ PCGCtl adj_control(const AdjState& A, const RedArgs& R, int it) {
+__device__ __forceinline__ PCGCtl adj_control(const AdjState& A, const RedArgs& R, int it, int bid) {
   __shared__ PCGCtl c;
   int flag = 0;
   double prev = 1.0;
@@ -1179,8 +1207,8 @@ __device__ __forceinline__ PCGCtl adj_control(const AdjState& A, const RedArgs& 
     if (MODE == kModePCG && it >= 1) prev = fin_site(R, kRedRZ0 + ((it - 1) & 1))[0];
   }
   double f[3] = {0.0, 0.0, 0.0};
-  if (MODE == kModePCG) consume<3>(R, kRedRZ0 + (it & 1), f);
-  if (MODE == kModeFixed && it >= 1) consume<3>(R, kRedFix, f);
+  if (MODE == kModePCG) consume<3>(R, kRedRZ0 + (it & 1), f, bid);
+  if (MODE == kModeFixed && it >= 1) consume<3>(R, kRedFix, f, bid);
   if (threadIdx.x == 0) {
     c.stop = 0;
     c.beta = 0.0;
@@ -1197,7 +1225,7 @@ __device__ __forceinline__ PCGCtl adj_control(const AdjState& A, const RedArgs& 
     }
     const bool cap = it >= A.kmax;
     c.stop = flag || conv || cap;
-    if (!flag && blockIdx.x == 0) {
+    if (!flag && bid == 0) {
       A.dstat[0] = res;
       if (conv || cap) {
         *A.done = 1;
@@ -1219,9 +1247,9 @@ __device__ __forceinline__ PCGCtl adj_control(const AdjState& A, const RedArgs& 
 // PCG forms x = p = z + beta p on the fly.  The tet's data and its compact
 // differential are requested together with the control sums.
 template <int MODE>
-__global__ void __launch_bounds__(kBlock) k_apply_K(ElemArgs E, VertArgs Vx, AdjState A, RedArgs R,
-                                                    const double* __restrict__ jac, const double* __restrict__ x, int it) {
-  const int t = blockIdx.x * blockDim.x + threadIdx.x;
+__device__ __forceinline__ void b_apply_K(ElemArgs E, VertArgs Vx, AdjState A, RedArgs R,
+                                                    const double* __restrict__ jac, const double* __restrict__ x, int it, int bid) {
+  const int t = bid * blockDim.x + threadIdx.x;
   const bool have = t < E.ne;
   TetData T;
   double U[9], V[9], D[6], c1[3], c2[3], wv = 0.0, bv = 0.0;
@@ -1232,7 +1260,7 @@ __global__ void __launch_bounds__(kBlock) k_apply_K(ElemArgs E, VertArgs Vx, Adj
     if (MODE == kModeAmK) bv = E.bV[t];
   }
   PCGCtl c = {0, 0.0};
-  if (MODE == kModePCG || MODE == kModeFixed) c = adj_control<MODE>(A, R, it);
+  if (MODE == kModePCG || MODE == kModeFixed) c = adj_control<MODE>(A, R, it, bid);
   if (c.stop || !have) return;
   const int nv = Vx.nv, nf = Vx.nf;
   double xv[4][3];
@@ -1258,6 +1286,12 @@ __global__ void __launch_bounds__(kBlock) k_apply_K(ElemArgs E, VertArgs Vx, Adj
   store_GtP(T, A.contrib, E.ninc, P);
 }
 
+template <int MODE>
+__global__ void __launch_bounds__(kBlock) k_apply_K(ElemArgs E, VertArgs Vx, AdjState A, RedArgs R,
+                                                    const double* __restrict__ jac, const double* __restrict__ x, int it) {
+  b_apply_K<MODE>(E, Vx, A, R, jac, x, it, blockIdx.x);
+}
+
 // Gathered contributions on free vertices (8 lanes per vertex).
 //  PCG:   p = z + beta p, A p = r + beta A p (A z = r, so no product with A is
 //         needed), w = A p - K p and the partial p.w;
@@ -1265,9 +1299,9 @@ __global__ void __launch_bounds__(kBlock) k_apply_K(ElemArgs E, VertArgs Vx, Adj
 //  warm start: r = q bar - (A~ - K) mu (mass term (1 + alpha h) m / h^2 added here);
 //  debug: K x.
 template <int MODE>
-__global__ void __launch_bounds__(kBlock) k_adj_gather(VertArgs Vx, AdjState A, RedArgs R, int it) {
+__device__ __forceinline__ void b_adj_gather(VertArgs Vx, AdjState A, RedArgs R, int it, int bid) {
   const int nv = Vx.nv;
-  const int gtid = blockIdx.x * blockDim.x + threadIdx.x;
+  const int gtid = bid * blockDim.x + threadIdx.x;
   const int i = gtid >> 3, l = gtid & 7;
   const bool have = i < Vx.nf;
   const bool owner = have && l == 0;
@@ -1344,7 +1378,12 @@ __global__ void __launch_bounds__(kBlock) k_adj_gather(VertArgs Vx, AdjState A, 
       }
     }
   }
-  if (MODE == kModePCG) write_partial<1>(v, R, kRedPW, blockIdx.x);
+  if (MODE == kModePCG) write_partial<1>(v, R, kRedPW, bid);
+}
+
+template <int MODE>
+__global__ void __launch_bounds__(kBlock) k_adj_gather(VertArgs Vx, AdjState A, RedArgs R, int it) {
+  b_adj_gather<MODE>(Vx, A, R, it, blockIdx.x);
 }
 
 // q bar = gq_next + gv_next / h on free vertices (Alg. 2 first line), in
@@ -1455,6 +1494,112 @@ __global__ void __launch_bounds__(kBlock) k_zero_int(int* p, int n) {
   const int i = blockIdx.x * blockDim.x + threadIdx.x;
   if (i < n) p[i] = 0;
 }
+
+// ================================================================= batched launches
+// One launch per stage covers every scene of a batch: block b belongs to the
+// scene s with base[s] <= b < base[s+1] and runs as that scene's block
+// b - base[s], with the scene's own arguments, reductions and done flag (so a
+// converged scene's blocks exit at once while the others iterate).
+__device__ __forceinline__ int scene_of(const BatchMap& M, int b) {
+  int lo = 0, hi = M.ns - 1;  // the last s with base[s] <= b
+  while (lo < hi) {
+    const int mid = (lo + hi + 1) >> 1;
+    if (M.base[mid] <= b) lo = mid;
+    else hi = mid - 1;
+  }
+  return lo;
+}
+
+#define PD_BATCH_PROLOGUE                      \
+  const int s_ = scene_of(M, blockIdx.x);      \
+  const int bid = blockIdx.x - M.base[s_];     \
+  const SceneBundle& b = M.B[s_];
+
+__global__ void __launch_bounds__(kBlock) kb_local(BatchMap M, int k) {
+  PD_BATCH_PROLOGUE
+  int* cap = b.St.ctl + kCtlNewton;
+  switch (b.St.m) {
+    case 1: b_local<1>(b.E, b.St, b.R, b.St.q_cur, b.V.nv, b.V.nf, k, 1, cap, bid); break;
+    case 2: b_local<2>(b.E, b.St, b.R, b.St.q_cur, b.V.nv, b.V.nf, k, 1, cap, bid); break;
+    case 3: b_local<3>(b.E, b.St, b.R, b.St.q_cur, b.V.nv, b.V.nf, k, 1, cap, bid); break;
+    case 4: b_local<4>(b.E, b.St, b.R, b.St.q_cur, b.V.nv, b.V.nf, k, 1, cap, bid); break;
+    case 5: b_local<5>(b.E, b.St, b.R, b.St.q_cur, b.V.nv, b.V.nf, k, 1, cap, bid); break;
+    default: b_local<0>(b.E, b.St, b.R, b.St.q_cur, b.V.nv, b.V.nf, k, 1, cap, bid); break;
+  }
+}
+
+__global__ void __launch_bounds__(kBlock) kb_gather_fwd(BatchMap M, int k) {
+  PD_BATCH_PROLOGUE
+  switch (b.St.m) {
+    case 1: b_gather_fwd<1>(b.V, b.St, b.R, k, bid); break;
+    case 2: b_gather_fwd<2>(b.V, b.St, b.R, k, bid); break;
+    case 3: b_gather_fwd<3>(b.V, b.St, b.R, k, bid); break;
+    case 4: b_gather_fwd<4>(b.V, b.St, b.R, k, bid); break;
+    case 5: b_gather_fwd<5>(b.V, b.St, b.R, k, bid); break;
+    default: b_gather_fwd<0>(b.V, b.St, b.R, k, bid); break;
+  }
+}
+
+// forward (gate), PCG (alpha), or the adjoint's first solve (right-hand side r0)
+template <int MODE>
+__global__ void __launch_bounds__(kBlock) kb_Eb(BatchMap M, int k) {
+  PD_BATCH_PROLOGUE
+  if (MODE == kModePlain) {
+    StepState st = b.St;
+    st.done = b.A.done;
+    b_Eb<kModePlain>(b.V, b.S, st, b.A, b.R, b.A.r0, k, bid);
+  } else {
+    b_Eb<MODE>(b.V, b.S, b.St, b.A, b.R, nullptr, k, bid);
+  }
+}
+
+__global__ void __launch_bounds__(kBlock) kb_top(BatchMap M, int adjoint) {
+  PD_BATCH_PROLOGUE
+  b_top(b.V, b.S, adjoint ? b.A.z : b.St.qhat, bid);
+}
+
+template <int MODE>
+__global__ void __launch_bounds__(kBottomThreads) kb_bottom(BatchMap M, int k) {
+  PD_BATCH_PROLOGUE
+  if (MODE == kModeFwd) {
+    switch (b.St.m) {
+      case 1: b_bottom<kModeFwd, 1>(b.V, b.S, b.St, b.A, b.R, nullptr, b.St.qhat, k, bid); break;
+      case 2: b_bottom<kModeFwd, 2>(b.V, b.S, b.St, b.A, b.R, nullptr, b.St.qhat, k, bid); break;
+      case 3: b_bottom<kModeFwd, 3>(b.V, b.S, b.St, b.A, b.R, nullptr, b.St.qhat, k, bid); break;
+      case 4: b_bottom<kModeFwd, 4>(b.V, b.S, b.St, b.A, b.R, nullptr, b.St.qhat, k, bid); break;
+      case 5: b_bottom<kModeFwd, 5>(b.V, b.S, b.St, b.A, b.R, nullptr, b.St.qhat, k, bid); break;
+      default: b_bottom<kModeFwd, 0>(b.V, b.S, b.St, b.A, b.R, nullptr, b.St.qhat, k, bid); break;
+    }
+  } else if (MODE == kModePCGInit) {
+    StepState st = b.St;
+    st.done = b.A.done;
+    b_bottom<kModePCGInit, 0>(b.V, b.S, st, b.A, b.R, b.A.r0, b.A.z, k, bid);
+  } else {
+    b_bottom<MODE, 0>(b.V, b.S, b.St, b.A, b.R, nullptr, b.A.z, k, bid);
+  }
+}
+
+template <int MODE>
+__global__ void __launch_bounds__(kBlock) kb_apply_K(BatchMap M, int it) {
+  PD_BATCH_PROLOGUE
+  b_apply_K<MODE>(b.E, b.V, b.A, b.R, b.jac, MODE == kModeAmK ? b.A.mu : nullptr, it, bid);
+}
+
+template <int MODE>
+__global__ void __launch_bounds__(kBlock) kb_adj_gather(BatchMap M, int it) {
+  PD_BATCH_PROLOGUE
+  b_adj_gather<MODE>(b.V, b.A, b.R, it, bid);
+}
+
+// every scene's control block and statistics, gathered for one copy to the host
+__global__ void __launch_bounds__(64) kb_flags(BatchMap M, int* __restrict__ ctl, double* __restrict__ dstat) {
+  const int s = blockIdx.x;
+  const SceneBundle& b = M.B[s];
+  const int t = threadIdx.x;
+  if (t < kCtlTotal) ctl[s * kCtlTotal + t] = b.St.ctl[t];
+  if (t < 32) dstat[s * 32 + t] = b.St.dstat[t];
+}
+#undef PD_BATCH_PROLOGUE
 
 // ================================================================= launchers
 #define PD_GRID(n) dim3(((n) + kBlock - 1) / kBlock), dim3(kBlock)
@@ -1617,6 +1762,41 @@ void launch_grad_vert(const VertArgs& V, const double* mu, const double* contrib
   launch_ext(k_grad_vert, dim3(vert_group_blocks(V.nv)), dim3(kBlock), 0, s, V, mu, contrib, gv_next, gq_t,
                      gv_t, gf);
 }
+void launch_b_local(const BatchMap& M, int nblk, int block, int k, hipStream_t s) {
+  if (nblk > 0) launch_ext(kb_local, dim3(nblk), dim3(block), 0, s, M, k);
+}
+void launch_b_gather_fwd(const BatchMap& M, int nblk, int k, hipStream_t s) {
+  if (nblk > 0) launch_ext(kb_gather_fwd, dim3(nblk), dim3(kBlock), 0, s, M, k);
+}
+void launch_b_Eb(int mode, const BatchMap& M, int nblk, int k, hipStream_t s) {
+  if (nblk <= 0) return;
+  if (mode == kModeFwd) launch_ext(kb_Eb<kModeFwd>, dim3(nblk), dim3(kBlock), 0, s, M, k);
+  else if (mode == kModePCG) launch_ext(kb_Eb<kModePCG>, dim3(nblk), dim3(kBlock), 0, s, M, k);
+  else launch_ext(kb_Eb<kModePlain>, dim3(nblk), dim3(kBlock), 0, s, M, k);
+}
+void launch_b_top(const BatchMap& M, int nblk, int adjoint, hipStream_t s) {
+  if (nblk > 0) launch_ext(kb_top, dim3(nblk), dim3(kBlock), 0, s, M, adjoint);
+}
+void launch_b_bottom(int mode, const BatchMap& M, int nblk, int k, hipStream_t s) {
+  if (nblk <= 0) return;
+  if (mode == kModeFwd) launch_ext(kb_bottom<kModeFwd>, dim3(nblk), dim3(kBottomThreads), 0, s, M, k);
+  else if (mode == kModePCG) launch_ext(kb_bottom<kModePCG>, dim3(nblk), dim3(kBottomThreads), 0, s, M, k);
+  else launch_ext(kb_bottom<kModePCGInit>, dim3(nblk), dim3(kBottomThreads), 0, s, M, k);
+}
+void launch_b_apply_K(int mode, const BatchMap& M, int nblk, int block, int it, hipStream_t s) {
+  if (nblk <= 0) return;
+  if (mode == kModeAmK) launch_ext(kb_apply_K<kModeAmK>, dim3(nblk), dim3(block), 0, s, M, it);
+  else launch_ext(kb_apply_K<kModePCG>, dim3(nblk), dim3(block), 0, s, M, it);
+}
+void launch_b_adj_gather(int mode, const BatchMap& M, int nblk, int it, hipStream_t s) {
+  if (nblk <= 0) return;
+  if (mode == kModeInit) launch_ext(kb_adj_gather<kModeInit>, dim3(nblk), dim3(kBlock), 0, s, M, it);
+  else launch_ext(kb_adj_gather<kModePCG>, dim3(nblk), dim3(kBlock), 0, s, M, it);
+}
+void launch_b_flags(const BatchMap& M, int* ctl_out, double* dstat_out, hipStream_t s) {
+  launch_ext(kb_flags, dim3(M.ns), dim3(64), 0, s, M, ctl_out, dstat_out);
+}
+
 void launch_init_warm(const ElemArgs& E, hipStream_t s) {
   launch_ext(k_init_warm, PD_GRID(E.ne), 0, s, E);
 }

@@ -22,9 +22,13 @@ struct pd_scene {
   Scene S;
 };
 
+namespace pdhot {
+thread_local std::string g_last_error;
+void set_last_error(const std::string& m) { g_last_error = m; }
+}  // namespace pdhot
+
 namespace {
 
-thread_local std::string g_err;
 
 struct PdError {
   int code;
@@ -670,26 +674,56 @@ static double kernel_bytes(const Scene& S, int id) {
 #define PD_CATCH                                   \
   }                                                \
   catch (const PdError& e) {                       \
-    g_err = e.msg;                                 \
+    pdhot::g_last_error = e.msg;                                 \
     return e.code;                                 \
   }                                                \
   catch (const std::bad_alloc&) {                  \
-    g_err = "host allocation failed";              \
+    pdhot::g_last_error = "host allocation failed";              \
     return PD_ERR_ALLOC;                           \
   }                                                \
   catch (const std::exception& e) {                \
-    g_err = e.what();                              \
+    pdhot::g_last_error = e.what();                              \
     return PD_ERR_INVALID_ARG;                     \
   }
 
 extern "C" {
 
-const char* pd_last_error(void) { return g_err.c_str(); }
+const char* pd_last_error(void) { return pdhot::g_last_error.c_str(); }
+
+int pd_scene_vertex_logw(const pd_scene* scene, double* out) {
+  if (!scene || !out) {
+    pdhot::g_last_error = "null argument";
+    return PD_ERR_INVALID_ARG;
+  }
+  PD_TRY
+  const Scene& S = scene->S;
+  std::vector<double> sum(S.nv, 0.0);
+  std::vector<int> cnt(S.nv, 0);
+  const double nu = S.nu;
+  for (int e = 0; e < S.ne; ++e) {
+    const double E = std::exp(S.logE[e]);
+    const double mu = E / (2.0 * (1.0 + nu)), lam = E * nu / ((1.0 + nu) * (1.0 - 2.0 * nu));
+    const double lw = std::log(2.0 * mu + lam);
+    for (int a = 0; a < 4; ++a) {
+      sum[S.tets[4 * (size_t)e + a]] += lw;
+      cnt[S.tets[4 * (size_t)e + a]] += 1;
+    }
+  }
+  double mean = 0.0;
+  for (int i = 0; i < S.nv; ++i) {
+    out[i] = sum[i] / std::max(1, cnt[i]);
+    mean += out[i];
+  }
+  mean /= S.nv;
+  for (int i = 0; i < S.nv; ++i) out[i] -= mean;
+  return PD_OK;
+  PD_CATCH
+}
 
 int pd_scene_create(const pd_mesh_desc* mesh, const pd_material_desc* mat, const pd_solver_opts* opts,
                     pd_scene** out) {
   if (!out) {
-    g_err = "null output pointer";
+    pdhot::g_last_error = "null output pointer";
     return PD_ERR_INVALID_ARG;
   }
   *out = nullptr;
@@ -699,16 +733,16 @@ int pd_scene_create(const pd_mesh_desc* mesh, const pd_material_desc* mat, const
   setup_scene(sc->S, mesh, mat, opts);
   factorize(sc->S);
   *out = sc;
-  g_err.clear();
+  pdhot::g_last_error.clear();
   return PD_OK;
   }
   catch (const PdError& e) {
-    g_err = e.msg;
+    pdhot::g_last_error = e.msg;
     if (sc) { free_device(sc->S); delete sc; }
     return e.code;
   }
   catch (const std::exception& e) {
-    g_err = e.what();
+    pdhot::g_last_error = e.what();
     if (sc) { free_device(sc->S); delete sc; }
     return PD_ERR_INVALID_ARG;
   }
@@ -723,12 +757,12 @@ int pd_scene_destroy(pd_scene* scene) {
 
 int pd_scene_set_material(pd_scene* scene, const double* log_E_host) {
   if (!scene || !log_E_host) {
-    g_err = "null argument";
+    pdhot::g_last_error = "null argument";
     return PD_ERR_INVALID_ARG;
   }
   for (int e = 0; e < scene->S.ne; ++e)
     if (!std::isfinite(log_E_host[e])) {
-      g_err = "non-finite log E";
+      pdhot::g_last_error = "non-finite log E";
       return PD_ERR_NONFINITE;
     }
   scene->S.logE.assign(log_E_host, log_E_host + scene->S.ne);
@@ -738,7 +772,7 @@ int pd_scene_set_material(pd_scene* scene, const double* log_E_host) {
 
 int pd_scene_factorize(pd_scene* scene, void* stream) {
   if (!scene) {
-    g_err = "null scene";
+    pdhot::g_last_error = "null scene";
     return PD_ERR_INVALID_ARG;
   }
   (void)stream;
@@ -750,7 +784,7 @@ int pd_scene_factorize(pd_scene* scene, void* stream) {
 
 int pd_scene_info(const pd_scene* scene, double* info, double* means) {
   if (!scene) {
-    g_err = "null scene";
+    pdhot::g_last_error = "null scene";
     return PD_ERR_INVALID_ARG;
   }
   const Scene& S = scene->S;
@@ -770,12 +804,12 @@ size_t pd_ckpt_bytes(const pd_scene* scene) {
 int pd_step_forward(pd_scene* scene, const double* q_t, const double* v_t, const double* f_ext, const double* q0,
                     double* q_next, double* v_next, void* ckpt, pd_fwd_stats* stats, void* stream) {
   if (!scene || !q_t || !v_t || !q_next || !v_next) {
-    g_err = "null argument";
+    pdhot::g_last_error = "null argument";
     return PD_ERR_INVALID_ARG;
   }
   Scene& S = scene->S;
   if (S.stale) {
-    g_err = "factor is stale: call pd_scene_factorize after pd_scene_set_material";
+    pdhot::g_last_error = "factor is stale: call pd_scene_factorize after pd_scene_set_material";
     return PD_ERR_STALE_FACTOR;
   }
   PD_TRY
@@ -901,12 +935,12 @@ static void adjoint_solve(Scene& S, hipStream_t st, double tau_force, double* bs
 int pd_step_backward(pd_scene* scene, const void* ckpt, const double* gq_next, const double* gv_next, double* gq_t,
                      double* gv_t, double* gf_ext, double* g_logE_accum, pd_bwd_stats* stats, void* stream) {
   if (!scene || !ckpt) {
-    g_err = "null argument";
+    pdhot::g_last_error = "null argument";
     return PD_ERR_INVALID_ARG;
   }
   Scene& S = scene->S;
   if (S.stale) {
-    g_err = "factor is stale: call pd_scene_factorize after pd_scene_set_material";
+    pdhot::g_last_error = "factor is stale: call pd_scene_factorize after pd_scene_set_material";
     return PD_ERR_STALE_FACTOR;
   }
   PD_TRY
@@ -942,7 +976,7 @@ int pd_step_backward(pd_scene* scene, const void* ckpt, const double* gq_next, c
 
 int pd_adjoint_reset(pd_scene* scene) {
   if (!scene) {
-    g_err = "null scene";
+    pdhot::g_last_error = "null scene";
     return PD_ERR_INVALID_ARG;
   }
   scene->S.adj_hist = 0;
@@ -951,11 +985,11 @@ int pd_adjoint_reset(pd_scene* scene) {
 
 int pd_debug_local_rhs(pd_scene* scene, const double* q, double* b, void* stream) {
   if (!scene || !q || !b) {
-    g_err = "null argument";
+    pdhot::g_last_error = "null argument";
     return PD_ERR_INVALID_ARG;
   }
   Scene& S = scene->S;
-  if (S.stale) { g_err = "factor is stale"; return PD_ERR_STALE_FACTOR; }
+  if (S.stale) { pdhot::g_last_error = "factor is stale"; return PD_ERR_STALE_FACTOR; }
   PD_TRY
   hipStream_t st = (hipStream_t)stream;
   const ElemArgs E = elem_args(S);
@@ -974,11 +1008,11 @@ int pd_debug_local_rhs(pd_scene* scene, const double* q, double* b, void* stream
 
 int pd_debug_apply_Ainv(pd_scene* scene, const double* r, double* x, void* stream) {
   if (!scene || !r || !x) {
-    g_err = "null argument";
+    pdhot::g_last_error = "null argument";
     return PD_ERR_INVALID_ARG;
   }
   Scene& S = scene->S;
-  if (S.stale) { g_err = "factor is stale"; return PD_ERR_STALE_FACTOR; }
+  if (S.stale) { pdhot::g_last_error = "factor is stale"; return PD_ERR_STALE_FACTOR; }
   PD_TRY
   hipStream_t st = (hipStream_t)stream;
   const VertArgs V = vert_args(S);
@@ -993,11 +1027,11 @@ int pd_debug_apply_Ainv(pd_scene* scene, const double* r, double* x, void* strea
 
 int pd_debug_apply_K(pd_scene* scene, const double* q, double tau, const double* x, double* y, void* stream) {
   if (!scene || !q || !x || !y) {
-    g_err = "null argument";
+    pdhot::g_last_error = "null argument";
     return PD_ERR_INVALID_ARG;
   }
   Scene& S = scene->S;
-  if (S.stale) { g_err = "factor is stale"; return PD_ERR_STALE_FACTOR; }
+  if (S.stale) { pdhot::g_last_error = "factor is stale"; return PD_ERR_STALE_FACTOR; }
   PD_TRY
   hipStream_t st = (hipStream_t)stream;
   const ElemArgs E = elem_args(S);
@@ -1020,7 +1054,7 @@ int pd_debug_apply_K(pd_scene* scene, const double* q, double tau, const double*
 
 int pd_kernel_timer(pd_scene* scene, int kernel) {
   if (!scene || kernel < -1 || kernel >= kKCount) {
-    g_err = "invalid scene or kernel id";
+    pdhot::g_last_error = "invalid scene or kernel id";
     return PD_ERR_INVALID_ARG;
   }
   PD_TRY
@@ -1041,7 +1075,7 @@ int pd_kernel_timer(pd_scene* scene, int kernel) {
 int pd_kernel_timer_read(pd_scene* scene, double* total_ms, int64_t* launches, int64_t* working,
                          double* bytes_per_launch) {
   if (!scene) {
-    g_err = "null scene";
+    pdhot::g_last_error = "null scene";
     return PD_ERR_INVALID_ARG;
   }
   PD_TRY
@@ -1053,6 +1087,356 @@ int pd_kernel_timer_read(pd_scene* scene, double* total_ms, int64_t* launches, i
   if (working) *working = S.kt.working;
   if (bytes_per_launch) *bytes_per_launch = S.kt.which >= 0 ? kernel_bytes(S, S.kt.which) : 0.0;
   return PD_OK;
+  PD_CATCH
+}
+
+}  // extern "C"
+
+// ================================================================= batches
+// Many scenes stepped together: every iteration stage is one launch across
+// all scenes (kb_* kernels), each scene keeps its own buffers, reductions,
+// Anderson window and done flag, and the host checks all scenes' flags with
+// one copy per chunk of iterations.  Chunks can be captured once into HIP
+// graphs and replayed.
+struct pd_batch {
+  std::vector<pd_scene*> scenes;
+  SceneBundle* dB = nullptr;
+  int* dbase[kBKKinds] = {};
+  int nblk[kBKKinds] = {};
+  int block_local = kBlock, block_applyK = kBlock;
+  int chunk = 0;        // iterations per host check (0 = adaptive)
+  int use_graph = 0;
+  int* dctl = nullptr;  // ns x kCtlTotal
+  double* ddstat = nullptr;
+  int* hctl = nullptr;
+  double* hdstat = nullptr;
+  int last_fwd = 4, last_adj = 8;
+  std::vector<std::pair<long long, hipGraphExec_t>> graphs;
+  // graphs are captured and replayed on the batch's own stream (the caller's
+  // may be the legacy default stream, which cannot be captured), ordered
+  // after and before the caller's work with events
+  hipStream_t gstream = nullptr;
+  hipEvent_t ev_in = nullptr, ev_out = nullptr;
+};
+
+namespace {
+
+void batch_free_graphs(pd_batch& B) {
+  for (auto& g : B.graphs) (void)hipGraphExecDestroy(g.second);
+  B.graphs.clear();
+}
+
+// per-scene block counts of each kind for the current launch shapes, and the
+// prefix tables the kernels search
+void batch_layout(pd_batch& B) {
+  const int ns = (int)B.scenes.size();
+  for (int kind = 0; kind < kBKKinds; ++kind) {
+    std::vector<int> base(ns + 1, 0);
+    for (int s = 0; s < ns; ++s) {
+      const Scene& S = B.scenes[s]->S;
+      int n = 0;
+      switch (kind) {
+        case kBKLocal: n = (S.ne + B.block_local - 1) / B.block_local; break;
+        case kBKApplyK: n = (S.ne + B.block_applyK - 1) / B.block_applyK; break;
+        case kBKGather: n = vert_group_blocks(S.L.nf); break;
+        case kBKEb: n = std::max(1, (S.L.nT + 3) / 4); break;
+        case kBKTop: n = (S.L.nT + 3) / 4; break;
+        default: n = bottom_blocks(S.L.nB, S.L.nT); break;
+      }
+      base[s + 1] = base[s] + n;
+    }
+    B.nblk[kind] = base[ns];
+    dfree(B.dbase[kind]);
+    B.dbase[kind] = dalloc<int>(ns + 1);
+    upload(B.dbase[kind], base);
+  }
+  batch_free_graphs(B);
+}
+
+void batch_bundles(pd_batch& B) {
+  std::vector<SceneBundle> h;
+  for (pd_scene* p : B.scenes) {
+    Scene& S = p->S;
+    SceneBundle b;
+    b.E = elem_args(S);
+    b.V = vert_args(S);
+    b.S = solve_args(S);
+    b.St = step_state(S);
+    b.A = adj_state(S);
+    b.R = red_args(S);
+    b.jac = S.jac;
+    h.push_back(b);
+  }
+  dfree(B.dB);
+  B.dB = dalloc<SceneBundle>(h.size());
+  PD_HIP(hipMemcpy(B.dB, h.data(), h.size() * sizeof(SceneBundle), hipMemcpyHostToDevice));
+}
+
+BatchMap bmap(const pd_batch& B, int kind) { return BatchMap{B.dB, B.dbase[kind], (int)B.scenes.size()}; }
+
+void batch_fwd_iter(pd_batch& B, int k, hipStream_t st) {
+  launch_b_local(bmap(B, kBKLocal), B.nblk[kBKLocal], B.block_local, k, st);
+  launch_b_gather_fwd(bmap(B, kBKGather), B.nblk[kBKGather], k, st);
+  launch_b_Eb(kModeFwd, bmap(B, kBKEb), B.nblk[kBKEb], k, st);
+  launch_b_top(bmap(B, kBKTop), B.nblk[kBKTop], 0, st);
+  launch_b_bottom(kModeFwd, bmap(B, kBKBottom), B.nblk[kBKBottom], k, st);
+}
+
+void batch_adj_iter(pd_batch& B, int it, hipStream_t st) {
+  launch_b_apply_K(kModePCG, bmap(B, kBKApplyK), B.nblk[kBKApplyK], B.block_applyK, it, st);
+  launch_b_adj_gather(kModePCG, bmap(B, kBKGather), B.nblk[kBKGather], it, st);
+  launch_b_Eb(kModePCG, bmap(B, kBKEb), B.nblk[kBKEb], it, st);
+  launch_b_top(bmap(B, kBKTop), B.nblk[kBKTop], 1, st);
+  launch_b_bottom(kModePCG, bmap(B, kBKBottom), B.nblk[kBKBottom], it, st);
+}
+
+// iterations k0 .. k1-1 of a loop, replayed from a graph when enabled
+template <typename F>
+void batch_chunk(pd_batch& B, int loop, int k0, int k1, hipStream_t st, F iter) {
+  if (!B.use_graph) {
+    for (int k = k0; k < k1; ++k) iter(B, k, st);
+    return;
+  }
+  const long long key = ((long long)loop << 40) | ((long long)k0 << 20) | (long long)k1;
+  hipGraphExec_t exec = nullptr;
+  for (auto& g : B.graphs)
+    if (g.first == key) exec = g.second;
+  if (!exec) {
+    hipGraph_t graph = nullptr;
+    PD_HIP(hipStreamBeginCapture(B.gstream, hipStreamCaptureModeThreadLocal));
+    for (int k = k0; k < k1; ++k) iter(B, k, B.gstream);
+    PD_HIP(hipStreamEndCapture(B.gstream, &graph));
+    PD_HIP(hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0));
+    (void)hipGraphDestroy(graph);
+    B.graphs.push_back({key, exec});
+  }
+  PD_HIP(hipEventRecord(B.ev_in, st));
+  PD_HIP(hipStreamWaitEvent(B.gstream, B.ev_in, 0));
+  PD_HIP(hipGraphLaunch(exec, B.gstream));
+  PD_HIP(hipEventRecord(B.ev_out, B.gstream));
+  PD_HIP(hipStreamWaitEvent(st, B.ev_out, 0));
+}
+
+// all scenes' control blocks and statistics to the host
+void batch_flags(pd_batch& B, hipStream_t st) {
+  const int ns = (int)B.scenes.size();
+  launch_b_flags(BatchMap{B.dB, B.dbase[0], ns}, B.dctl, B.ddstat, st);
+  PD_HIP(hipMemcpyAsync(B.hctl, B.dctl, sizeof(int) * kCtlTotal * ns, hipMemcpyDeviceToHost, st));
+  PD_HIP(hipMemcpyAsync(B.hdstat, B.ddstat, sizeof(double) * 32 * ns, hipMemcpyDeviceToHost, st));
+  PD_HIP(hipStreamSynchronize(st));
+}
+
+}  // namespace
+
+extern "C" {
+
+int pd_batch_create(pd_scene* const* scenes, int n, pd_batch** out) {
+  if (!scenes || n <= 0 || !out) {
+    pdhot::g_last_error = "null argument or empty batch";
+    return PD_ERR_INVALID_ARG;
+  }
+  PD_TRY
+  pd_batch* B = new pd_batch();
+  try {
+    for (int s = 0; s < n; ++s) {
+      if (!scenes[s]) throw PdError{PD_ERR_INVALID_ARG, "null scene in batch"};
+      if (scenes[s]->S.stale) throw PdError{PD_ERR_STALE_FACTOR, "scene factor is stale"};
+      if (scenes[s]->S.adj_method != 0) throw PdError{PD_ERR_INVALID_ARG, "batches run the PCG adjoint"};
+      B->scenes.push_back(scenes[s]);
+    }
+    batch_bundles(*B);
+    batch_layout(*B);
+    B->dctl = dalloc<int>((size_t)kCtlTotal * n);
+    B->ddstat = dalloc<double>((size_t)32 * n);
+    PD_HIP(hipHostMalloc((void**)&B->hctl, sizeof(int) * kCtlTotal * n));
+    PD_HIP(hipHostMalloc((void**)&B->hdstat, sizeof(double) * 32 * n));
+    PD_HIP(hipStreamCreateWithFlags(&B->gstream, hipStreamNonBlocking));
+    PD_HIP(hipEventCreateWithFlags(&B->ev_in, hipEventDisableTiming));
+    PD_HIP(hipEventCreateWithFlags(&B->ev_out, hipEventDisableTiming));
+  } catch (...) {
+    pd_batch_destroy(B);
+    throw;
+  }
+  *out = B;
+  return PD_OK;
+  PD_CATCH
+}
+
+int pd_batch_destroy(pd_batch* B) {
+  if (!B) return PD_OK;
+  batch_free_graphs(*B);
+  dfree(B->dB);
+  for (int k = 0; k < kBKKinds; ++k) dfree(B->dbase[k]);
+  dfree(B->dctl);
+  dfree(B->ddstat);
+  if (B->hctl) (void)hipHostFree(B->hctl);
+  if (B->hdstat) (void)hipHostFree(B->hdstat);
+  if (B->ev_in) (void)hipEventDestroy(B->ev_in);
+  if (B->ev_out) (void)hipEventDestroy(B->ev_out);
+  if (B->gstream) (void)hipStreamDestroy(B->gstream);
+  delete B;
+  return PD_OK;
+}
+
+int pd_batch_config(pd_batch* B, int block_local, int block_applyK, int iters_per_check, int use_graph) {
+  auto ok = [](int b) { return b == 64 || b == 128 || b == 256; };
+  if (!B || !ok(block_local) || !ok(block_applyK) || iters_per_check < 0 || use_graph < 0 || use_graph > 1) {
+    pdhot::g_last_error = "invalid batch configuration (blocks 64, 128 or 256)";
+    return PD_ERR_INVALID_ARG;
+  }
+  PD_TRY
+  B->block_local = block_local;
+  B->block_applyK = block_applyK;
+  B->chunk = iters_per_check;
+  B->use_graph = use_graph;
+  batch_layout(*B);
+  return PD_OK;
+  PD_CATCH
+}
+
+int pd_batch_step_forward(pd_batch* B, const double* const* q_t, const double* const* v_t,
+                          const double* const* f_ext, const double* const* q0, double* const* q_next,
+                          double* const* v_next, void* const* ckpt, pd_fwd_stats* stats, void* stream) {
+  if (!B || !q_t || !v_t || !q_next || !v_next) {
+    pdhot::g_last_error = "null argument";
+    return PD_ERR_INVALID_ARG;
+  }
+  PD_TRY
+  hipStream_t st = (hipStream_t)stream;
+  const int ns = (int)B->scenes.size();
+  int kmax = 0;
+  for (int s = 0; s < ns; ++s) {
+    Scene& S = B->scenes[s]->S;
+    if (S.stale) throw PdError{PD_ERR_STALE_FACTOR, "scene factor is stale"};
+    if (!q_t[s] || !v_t[s] || !q_next[s] || !v_next[s]) throw PdError{PD_ERR_INVALID_ARG, "null scene input"};
+    const ElemArgs E = elem_args(S);
+    const VertArgs V = vert_args(S);
+    const StepState T = step_state(S);
+    launch_to_lib(V, q_t[s], S.qt, 0, st);
+    launch_elem_GtG(E, S.qt, S.nv, S.bV, S.contrib, st);
+    launch_prologue(V, q_t[s], v_t[s], f_ext ? f_ext[s] : nullptr, q0 ? q0[s] : nullptr, S.fwd_start, T, st);
+    launch_zero_int(S.ctl, kCtlSize, st);
+    kmax = std::max(kmax, S.kmax_fwd);
+  }
+  int k = 0;
+  // graph replay wants fixed chunk boundaries (one graph per chunk start)
+  const int fixed = B->chunk > 0 ? B->chunk : (B->use_graph ? 4 : 0);
+  int chunk = fixed > 0 ? fixed : std::max(3, B->last_fwd + 1);
+  bool all = false;
+  for (;;) {
+    const int kend = std::min(k + chunk, kmax);
+    batch_chunk(*B, 0, k, kend, st, batch_fwd_iter);
+    k = kend;
+    batch_flags(*B, st);
+    all = true;
+    for (int s = 0; s < ns; ++s) all = all && B->hctl[s * kCtlTotal + kCtlDone];
+    if (all || k >= kmax) break;
+    chunk = fixed > 0 ? fixed : 2;
+  }
+  int worst = 0, most = 0;
+  for (int s = 0; s < ns; ++s) {
+    Scene& S = B->scenes[s]->S;
+    launch_epilogue(vert_args(S), step_state(S), q_next[s], v_next[s], ckpt ? (double*)ckpt[s] : nullptr, st);
+    const int* c = B->hctl + s * kCtlTotal;
+    if (stats) {
+      stats[s].iters = c[kCtlIters];
+      stats[s].aa_resets = c[kCtlResets];
+      stats[s].status = c[kCtlStatus];
+      stats[s].newton_capped = c[kCtlNewton];
+      for (int j = 0; j < 4; ++j) stats[s].gate[j] = B->hdstat[s * 32 + j];
+    }
+    if (!c[kCtlDone]) throw PdError{PD_ERR_HIP, "batched forward loop ended without a decision"};
+    worst = std::max(worst, c[kCtlStatus]);
+    most = std::max(most, c[kCtlIters]);
+  }
+  B->last_fwd = most;
+  PD_HIP(hipStreamSynchronize(st));
+  PD_HIP(hipGetLastError());
+  return worst == 0 ? PD_OK : PD_NOT_CONVERGED;
+  PD_CATCH
+}
+
+int pd_batch_step_backward(pd_batch* B, const void* const* ckpt, const double* const* gq_next,
+                           const double* const* gv_next, double* const* gq_t, double* const* gv_t,
+                           double* const* gf_ext, double* const* g_logE_accum, pd_bwd_stats* stats, void* stream) {
+  if (!B || !ckpt) {
+    pdhot::g_last_error = "null argument";
+    return PD_ERR_INVALID_ARG;
+  }
+  PD_TRY
+  hipStream_t st = (hipStream_t)stream;
+  const int ns = (int)B->scenes.size();
+  int kmax = 0;
+  bool any_warm = false;
+  std::vector<int> warm(ns, 0);
+  for (int s = 0; s < ns; ++s) {
+    Scene& S = B->scenes[s]->S;
+    if (S.stale) throw PdError{PD_ERR_STALE_FACTOR, "scene factor is stale"};
+    if (!ckpt[s]) throw PdError{PD_ERR_INVALID_ARG, "null checkpoint"};
+    const ElemArgs E = elem_args(S);
+    const VertArgs V = vert_args(S);
+    const AdjState Ad = adj_state(S);
+    const RedArgs R = red_args(S);
+    const double* ck = (const double*)ckpt[s];
+    warm[s] = std::min(S.adj_warm, S.adj_hist);
+    any_warm = any_warm || warm[s] > 0;
+    launch_bwd_prologue(V, Ad, gq_next ? gq_next[s] : nullptr, gv_next ? gv_next[s] : nullptr, warm[s], S.mu_h1,
+                        S.mu_h2, st);
+    launch_tr_partials(E, V, R, ck, st);
+    launch_bwd_elem(E, V, R, ck, S.eps_tr, -1.0, 1, S.jac, S.dstat + 4, st);
+    launch_zero_int(S.ctl + kCtlAdj, 4, st);
+    kmax = std::max(kmax, S.kmax_bwd);
+  }
+  if (any_warm) {  // r = q bar - (A~ - K) mu0 (a zero mu0 gives r = q bar again)
+    launch_b_apply_K(kModeAmK, bmap(*B, kBKApplyK), B->nblk[kBKApplyK], B->block_applyK, 0, st);
+    launch_b_adj_gather(kModeInit, bmap(*B, kBKGather), B->nblk[kBKGather], 0, st);
+  }
+  launch_b_Eb(kModePlain, bmap(*B, kBKEb), B->nblk[kBKEb], 0, st);
+  launch_b_top(bmap(*B, kBKTop), B->nblk[kBKTop], 1, st);
+  launch_b_bottom(kModePCGInit, bmap(*B, kBKBottom), B->nblk[kBKBottom], 0, st);
+  int it = 0;
+  const int fixed = B->chunk > 0 ? B->chunk : (B->use_graph ? 4 : 0);
+  int chunk = fixed > 0 ? fixed : std::max(4, B->last_adj + 1);
+  for (;;) {
+    const int iend = std::min(it + chunk, kmax + 1);
+    batch_chunk(*B, 1, it, iend, st, batch_adj_iter);
+    it = iend;
+    batch_flags(*B, st);
+    bool all = true;
+    for (int s = 0; s < ns; ++s) all = all && B->hctl[s * kCtlTotal + kCtlAdj + 2];
+    if (all || it > kmax) break;
+    chunk = fixed > 0 ? fixed : 4;
+  }
+  int worst = 0, most = 0;
+  for (int s = 0; s < ns; ++s) {
+    Scene& S = B->scenes[s]->S;
+    const ElemArgs E = elem_args(S);
+    const VertArgs V = vert_args(S);
+    const double* ck = (const double*)ckpt[s];
+    launch_grad_elem(E, V, ck, S.jac, S.mu, S.contrib, g_logE_accum ? g_logE_accum[s] : nullptr, st);
+    launch_grad_vert(V, S.mu, S.contrib, gv_next ? gv_next[s] : nullptr, gq_t ? gq_t[s] : nullptr,
+                     gv_t ? gv_t[s] : nullptr, gf_ext ? gf_ext[s] : nullptr, st);
+    if (S.adj_warm > 0) {
+      PD_HIP(hipMemcpyAsync(S.mu_h2, S.mu, 3 * (size_t)S.nv * sizeof(double), hipMemcpyDeviceToDevice, st));
+      std::swap(S.mu_h1, S.mu_h2);
+      S.adj_hist = std::min(S.adj_hist + 1, 2);
+    }
+    const int* c = B->hctl + s * kCtlTotal;
+    const double* d = B->hdstat + s * 32;
+    if (!c[kCtlAdj + 2]) throw PdError{PD_ERR_HIP, "batched adjoint loop ended without a decision"};
+    if (stats) {
+      stats[s].adj_iters = c[kCtlAdj];
+      stats[s].status = c[kCtlAdj + 1];
+      stats[s].rho = d[4]; stats[s].tau = d[5]; stats[s].dphi_act = d[6]; stats[s].dphi_mod = d[7];
+      stats[s].residual = d[16];
+    }
+    worst = std::max(worst, c[kCtlAdj + 1]);
+    most = std::max(most, c[kCtlAdj]);
+  }
+  B->last_adj = most;
+  PD_HIP(hipStreamSynchronize(st));
+  PD_HIP(hipGetLastError());
+  return worst == 0 ? PD_OK : PD_NOT_CONVERGED;
   PD_CATCH
 }
 

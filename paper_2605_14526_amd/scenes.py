@@ -205,7 +205,8 @@ def _tip_force_fn(X: np.ndarray, total: float, seed: int, ramp: int, hold: int):
     return fn
 
 
-def hetero_beam_c2(nx: int = 40, ny: int = 10, nz: int = 10, steps: int = 100) -> Scene:
+def hetero_beam_c2(nx: int = 40, ny: int = 10, nz: int = 10, steps: int = 100, seeds=(2001, 2002, 2003, 2004),
+                   name: str = "c2_hetero_beam") -> Scene:
     """Heterogeneous beam: 40x10x10 cubes (edge 0.05 m) = 20000 tets / 4961 verts.
 
     Two-phase E in {1e4, 1e6} Pa from 8 seeded Gaussian blobs (30 % stiff),
@@ -217,16 +218,26 @@ def hetero_beam_c2(nx: int = 40, ny: int = 10, nz: int = 10, steps: int = 100) -
     X, tets = box_tet_mesh(nx, ny, nz, edge)
     pinned = (np.abs(X[:, 0]) < 1e-12).astype(np.uint8)
     cen = X[tets].mean(axis=1)
-    rng = _rng(2001)
+    rng = _rng(seeds[0])
     field = gaussian_blob_field(cen, X.min(axis=0), X.max(axis=0), 8, rng)
     logE = two_phase_log_E(field, 0.3, 1e4, 1e6)
-    force = _tip_force_fn(X, 50.0, 2002, 20, 60)
-    rng3 = _rng(2003)
+    force = _tip_force_fn(X, 50.0, seeds[1], 20, 60)
+    rng3 = _rng(seeds[2])
     target = X.mean(axis=0) + rng3.uniform(-0.05, 0.05, 3)
-    fd = _rng(2004).choice(tets.shape[0], size=16, replace=False)
-    return Scene("c2_hetero_beam", X, tets, pinned, logE, nu=0.49, rho=1000.0, alpha=0.01,
+    fd = _rng(seeds[3]).choice(tets.shape[0], size=16, replace=False)
+    return Scene(name, X, tets, pinned, logE, nu=0.49, rho=1000.0, alpha=0.01,
                  beta0=1e-2 * 1e6, h=0.005, gravity=np.zeros(3), aa_window=1, steps=steps,
                  force_fn=force, target_centroid=target, fd_tets=fd)
+
+
+def hetero_beam_family(k: int, steps: int = 100, nx: int = 40, ny: int = 10, nz: int = 10) -> Scene:
+    """Member k of the heterogeneous-beam family: the benchmark beam's mesh,
+    load schedule and materials drawn with seeds 2100 + 10 k + (1, 2, 3, 4)
+    (another stiff-blob field and tip-force direction).  Training scenes of the
+    learned warm start are members 0..; the benchmark beam itself is not a
+    member."""
+    b = 2100 + 10 * k
+    return hetero_beam_c2(nx, ny, nz, steps, seeds=(b + 1, b + 2, b + 3, b + 4), name=f"hetero_beam_{k}")
 
 
 def small_beam(nx: int, ny: int, nz: int, seed: int = 7, contrast: float = 100.0, nu: float = 0.45,
@@ -247,6 +258,27 @@ def small_beam(nx: int, ny: int, nz: int, seed: int = 7, contrast: float = 100.0
     return Scene(f"small_beam_{nx}x{ny}x{nz}", X, tets, pinned, logE, nu=nu, rho=1000.0, alpha=alpha,
                  beta0=beta_rel * E_soft * contrast, h=h, gravity=np.asarray(gravity, float),
                  aa_window=aa_window, steps=steps, force_fn=force, target_centroid=target, fd_tets=fd)
+
+
+def beam_batch(n: int = 64, seed: int = 4000, steps: int = 50, ne_range=(1000, 30000)) -> list:
+    """A batch of uneven beams: per scene, a tet count log-uniform in ne_range
+    (square cross-section of 2-6 cubes, length to match, 5 tets per cube),
+    two-phase stiffness contrast log-uniform in [1, 100], nu uniform in
+    [0.40, 0.49], gravity plus a seeded tip force, h = 0.01 s; Anderson window
+    5 below 10x contrast, else 1."""
+    rng = _rng(seed)
+    out = []
+    for s in range(n):
+        ne = float(np.exp(rng.uniform(np.log(ne_range[0]), np.log(ne_range[1]))))
+        c = int(rng.integers(2, 7))
+        nx = max(2, int(round(ne / (5 * c * c))))
+        contrast = float(np.exp(rng.uniform(0.0, np.log(100.0))))
+        nu = float(rng.uniform(0.40, 0.49))
+        sc = small_beam(nx, c, c, seed=seed + 10 * (s + 1), contrast=contrast, nu=nu, tip_force=20.0,
+                        aa_window=5 if contrast < 10.0 else 1, steps=steps)
+        sc.name = f"batch_beam_{s}"
+        out.append(sc)
+    return out
 
 
 def config(name: str) -> Scene:

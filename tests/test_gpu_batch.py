@@ -1,0 +1,133 @@
+"""Batches: every scene of a batch gives bitwise the results it gives alone
+(forward states and reverse-sweep gradients), also with other launch shapes
+and with graph replay; the autotuner picks and caches a valid shape."""
+import json
+
+import numpy as np
+import pytest
+
+from paper_2605_14526_amd import scenes
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def th(torch_cuda):
+    return torch_cuda
+
+
+def batch_scenes():
+    return [scenes.small_beam(6, 3, 3, seed=5, contrast=30.0, nu=0.49, aa_window=1),
+            scenes.small_beam(9, 2, 2, seed=8, contrast=3.0, nu=0.45, aa_window=5),
+            scenes.small_beam(4, 4, 4, seed=13, contrast=100.0, nu=0.48, aa_window=1)]
+
+
+def d(th, a):
+    return th.tensor(np.ascontiguousarray(a), dtype=th.float64, device="cuda")
+
+
+def run_alone(th, scs, T):
+    from paper_2605_14526_amd.binding import Scene
+    out = []
+    for sc in scs:
+        g = Scene.from_scene(sc, adj_warm=2)
+        q, v = d(th, sc.q0()), d(th, sc.v0())
+        cks, iters = [], []
+        for t in range(T):
+            ck = g.new_ckpt()
+            q, v, st = g.step_forward(q, v, d(th, sc.f_ext(t)), ckpt=ck)
+            cks.append(ck)
+            iters.append(st["iters"])
+        g.adjoint_reset()
+        gq, gv = d(th, np.ones_like(sc.X)), d(th, np.zeros_like(sc.X))
+        gl = th.zeros(sc.n_e, dtype=th.float64, device="cuda")
+        for ck in reversed(cks):
+            gq, gv, _, _, _ = g.step_backward(ck, gq, gv, g_logE=gl)
+        out.append((q.cpu().numpy(), gq.cpu().numpy(), gl.cpu().numpy(), iters))
+    return out
+
+
+def run_batched(th, scs, T, **cfg):
+    from paper_2605_14526_amd.binding import Batch, Scene
+    gs = [Scene.from_scene(sc, adj_warm=2) for sc in scs]
+    B = Batch(gs)
+    if cfg:
+        B.config(**cfg)
+    q = [d(th, sc.q0()) for sc in scs]
+    v = [d(th, sc.v0()) for sc in scs]
+    cks = []
+    iters = []
+    for t in range(T):
+        ck = [g.new_ckpt() for g in gs]
+        q, v, stats, rc = B.step_forward(q, v, [d(th, sc.f_ext(t)) for sc in scs], ckpt=ck)
+        assert rc == 0
+        cks.append(ck)
+        iters.append([s_["iters"] for s_ in stats])
+    for g in gs:
+        g.adjoint_reset()
+    gq = [d(th, np.ones_like(sc.X)) for sc in scs]
+    gv = [d(th, np.zeros_like(sc.X)) for sc in scs]
+    gl = [th.zeros(sc.n_e, dtype=th.float64, device="cuda") for sc in scs]
+    for ck in reversed(cks):
+        gq, gv, _, gl, stats, rc = B.step_backward(ck, gq, gv, g_logE=gl)
+        assert rc == 0
+    return [(q[i].cpu().numpy(), gq[i].cpu().numpy(), gl[i].cpu().numpy(), [it[i] for it in iters])
+            for i in range(len(scs))]
+
+
+@pytest.mark.parametrize("cfg", [{}, dict(block_local=64, block_applyK=128, iters_per_check=2, use_graph=0),
+                                 dict(block_local=128, block_applyK=64, iters_per_check=4, use_graph=1)])
+def test_batch_is_bitwise_each_scene_alone(th, cfg):
+    scs = batch_scenes()
+    T = 4
+    alone = run_alone(th, scs, T)
+    together = run_batched(th, scs, T, **cfg)
+    for a, b in zip(alone, together):
+        assert a[3] == b[3]
+        for x, y in zip(a[:3], b[:3]):
+            assert np.array_equal(x, y)
+
+
+def test_graph_replays_match_eager(th):
+    """The same chunks replayed from captured graphs many times, with eager
+    work and synchronisations between replays, give the eager results each time."""
+    from paper_2605_14526_amd.binding import Batch, Scene
+    scs = batch_scenes()
+    res = {}
+    for graph in (0, 1):
+        gs = [Scene.from_scene(sc) for sc in scs]
+        B = Batch(gs)
+        B.config(iters_per_check=2, use_graph=graph)
+        q = [d(th, sc.q0()) for sc in scs]
+        v = [d(th, sc.v0()) for sc in scs]
+        traj = []
+        for t in range(6):
+            q, v, stats, rc = B.step_forward(q, v, [d(th, sc.f_ext(t)) for sc in scs])
+            th.cuda.synchronize()
+            _ = [x.sum().item() for x in q]  # eager work between replays
+            traj.append([x.cpu().numpy() for x in q])
+        res[graph] = traj
+    for a, b in zip(res[0], res[1]):
+        for x, y in zip(a, b):
+            assert np.array_equal(x, y)
+
+
+def test_autotune_picks_and_caches(th, tmp_path):
+    from paper_2605_14526_amd import autotune
+    from paper_2605_14526_amd.binding import Batch, Scene
+    scs = batch_scenes()
+    gs = [Scene.from_scene(sc) for sc in scs]
+    B = Batch(gs)
+    q = [d(th, sc.q0()) for sc in scs]
+    v = [d(th, sc.v0()) for sc in scs]
+    f = [d(th, sc.f_ext(3)) for sc in scs]
+
+    def run():
+        B.step_forward(q, v, f)
+
+    path = str(tmp_path / "tune.json")
+    cfg = autotune.autotune(B, run, th, cache_path=path, reps=1)
+    assert cfg["block_local"] in (64, 128, 256) and cfg["block_applyK"] in (64, 128, 256)
+    cache = json.load(open(path))
+    assert cache[autotune.batch_key(B)] == cfg
+    assert autotune.autotune(B, run, th, cache_path=path) == cfg

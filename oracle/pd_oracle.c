@@ -899,9 +899,181 @@ int or_aa_step(int n, int m, double* Hq, double* Hg, int* hn, const double* q, c
 /* ------------------------------------------------------------------------ */
 /* forward step, Alg. 1 (no contact)                                         */
 /* ------------------------------------------------------------------------ */
-int or_step_forward(const or_scene* s, const double* q_t, const double* v_t, const double* f_ext, const double* q0,
-                    double* q_next, double* v_next, double* q_star_m1, int force_iters, int m_override,
-                    int rec_max, double* rec, int* istats, double* dstats) {
+
+/* ------------------------------------------------------------------------ */
+/* contact (Sec. 4.7), frictionless reading                                  */
+/* ------------------------------------------------------------------------ */
+/* READING (frictionless, per-step linearised obstacles): contact row c acts on
+ * vertex v_c with unit normal n_c and gap delta_c = n_c . q_{v_c} - g_c (Sec. 4.7,
+ * delta_{n,c}).  The impulse lambda_c >= 0 enters A~ q = b + J^T lambda, so
+ * q = A~^{-1} b + sum_c lambda_c a_c n_c with a_c = A~^{-1} e_{v_c} (Eq. q_update)
+ * and delta = delta_free + W lambda, W_cd = (n_c . n_d) [A~^{-1}]_{v_c v_d}
+ * (the Delassus operator J A~^{-1} J^T).  Each PD iteration solves the
+ * complementarity problem by Fischer-Burmeister semi-smooth Newton
+ * (Eqs. fb_n, omega_E_n) with r_c = W_cc (READING: the paper's h^2 W_cc only
+ * rescales lambda), restricted to rows with omega_c > 1e-12 and symmetrised as
+ * (W_AA + diag(E/omega)) dlambda = -phi/omega (Eq. contact_system in role),
+ * solved by dense Cholesky, then projected onto lambda >= 0; lambda carries
+ * over between PD iterations. */
+typedef struct or_contacts {
+  int K;
+  const int* v;
+  const double* n;
+  const double* g;
+  double fb_tol;   /* third gate on the FB residual (READING: added to Eq. convergence_dual) */
+  double* lambda;  /* K, warm start in, converged out */
+  double* col;     /* K x nv: a_c (the axis-0 column of A~^{-1}, the same for every axis) */
+  double* W;       /* K x K */
+  double fb_res;
+  int fb_iters;
+} or_contacts;
+
+static int chol_solve(double* A, int n, double* b) { /* SPD, in place (lower), returns 0 if not PD */
+  for (int j = 0; j < n; ++j) {
+    double d = A[(size_t)j * n + j];
+    for (int k = 0; k < j; ++k) d -= A[(size_t)j * n + k] * A[(size_t)j * n + k];
+    if (!(d > 0.0)) return 0;
+    d = sqrt(d);
+    A[(size_t)j * n + j] = d;
+    for (int i = j + 1; i < n; ++i) {
+      double t = A[(size_t)i * n + j];
+      for (int k = 0; k < j; ++k) t -= A[(size_t)i * n + k] * A[(size_t)j * n + k];
+      A[(size_t)i * n + j] = t / d;
+    }
+  }
+  for (int i = 0; i < n; ++i) {
+    double t = b[i];
+    for (int k = 0; k < i; ++k) t -= A[(size_t)i * n + k] * b[k];
+    b[i] = t / A[(size_t)i * n + i];
+  }
+  for (int i = n - 1; i >= 0; --i) {
+    double t = b[i];
+    for (int k = i + 1; k < n; ++k) t -= A[(size_t)k * n + i] * b[k];
+    b[i] = t / A[(size_t)i * n + i];
+  }
+  return 1;
+}
+
+static void contact_setup(const or_scene* s, or_contacts* con) {
+  int nv = s->nv, n3 = 3 * nv, K = con->K;
+  double* r = (double*)calloc(n3, sizeof(double));
+  double* x = (double*)malloc(sizeof(double) * n3);
+  con->col = (double*)malloc(sizeof(double) * (size_t)K * nv);
+  con->W = (double*)malloc(sizeof(double) * (size_t)K * K);
+  for (int c = 0; c < K; ++c) {
+    r[3 * con->v[c]] = 1.0;
+    or_apply_Ainv(s, r, x);
+    r[3 * con->v[c]] = 0.0;
+    for (int i = 0; i < nv; ++i) con->col[(size_t)c * nv + i] = x[3 * i];
+  }
+  for (int c = 0; c < K; ++c)
+    for (int d = 0; d < K; ++d) {
+      double nn = con->n[3 * c] * con->n[3 * d] + con->n[3 * c + 1] * con->n[3 * d + 1] +
+                  con->n[3 * c + 2] * con->n[3 * d + 2];
+      con->W[(size_t)c * K + d] = nn * con->col[(size_t)c * nv + con->v[d]];
+    }
+  free(r);
+  free(x);
+}
+
+static void contact_free(or_contacts* con) {
+  free(con->col);
+  free(con->W);
+  con->col = NULL;
+  con->W = NULL;
+}
+
+/* FB values of all rows at lambda; returns max |phi| */
+static double fb_eval(const or_contacts* con, const double* dfree, const double* lam, double* phi, double* om,
+                      double* E) {
+  int K = con->K;
+  double res = 0.0;
+  for (int c = 0; c < K; ++c) {
+    double delta = dfree[c];
+    for (int d = 0; d < K; ++d) delta += con->W[(size_t)c * K + d] * lam[d];
+    double r = con->W[(size_t)c * K + c], a = delta, bb = r * lam[c];
+    double sq = sqrt(a * a + bb * bb);
+    if (sq == 0.0) {
+      phi[c] = 0.0;
+      om[c] = 1.0 - 1.0 / sqrt(2.0);
+      E[c] = r * (1.0 - 1.0 / sqrt(2.0));
+    } else {
+      phi[c] = a + bb - sq;
+      om[c] = 1.0 - a / sq;
+      E[c] = r * (1.0 - bb / sq);
+    }
+    if (fabs(phi[c]) > res) res = fabs(phi[c]);
+  }
+  return res;
+}
+
+/* FB semi-smooth Newton on the LCP delta = dfree + W lambda (lambda warm in con->lambda) */
+static void fb_newton(or_contacts* con, const double* dfree) {
+  int K = con->K;
+  double* phi = (double*)malloc(sizeof(double) * K);
+  double* om = (double*)malloc(sizeof(double) * K);
+  double* E = (double*)malloc(sizeof(double) * K);
+  double* M = (double*)malloc(sizeof(double) * (size_t)K * K);
+  double* rhs = (double*)malloc(sizeof(double) * K);
+  int* act = (int*)malloc(sizeof(int) * K);
+  double res = fb_eval(con, dfree, con->lambda, phi, om, E);
+  int it = 0;
+  for (; it < 30 && res > 1e-14; ++it) {
+    int na = 0;
+    for (int c = 0; c < K; ++c)
+      if (om[c] > 1e-12) act[na++] = c;
+      else con->lambda[c] = 0.0;
+    for (int i = 0; i < na; ++i) {
+      for (int j = 0; j < na; ++j) M[(size_t)i * na + j] = con->W[(size_t)act[i] * K + act[j]];
+      M[(size_t)i * na + i] += E[act[i]] / om[act[i]];
+      rhs[i] = -phi[act[i]] / om[act[i]];
+    }
+    if (na > 0 && !chol_solve(M, na, rhs)) break;
+    for (int i = 0; i < na; ++i) {
+      double l = con->lambda[act[i]] + rhs[i];
+      con->lambda[act[i]] = l > 0.0 ? l : 0.0;
+    }
+    res = fb_eval(con, dfree, con->lambda, phi, om, E);
+  }
+  con->fb_res = res;
+  con->fb_iters = it;
+  free(phi); free(om); free(E); free(M); free(rhs); free(act);
+}
+
+/* solve the contact problem at qhat (lambda warm) and add sum lambda_c a_c n_c to qhat */
+static void contact_solve(const or_scene* s, or_contacts* con, double* qhat) {
+  int K = con->K, nv = s->nv;
+  double* dfree = (double*)malloc(sizeof(double) * K);
+  for (int c = 0; c < K; ++c) {
+    const double* q = qhat + 3 * con->v[c];
+    dfree[c] = con->n[3 * c] * q[0] + con->n[3 * c + 1] * q[1] + con->n[3 * c + 2] * q[2] - con->g[c];
+  }
+  fb_newton(con, dfree);
+  for (int c = 0; c < K; ++c) {
+    double l = con->lambda[c];
+    if (l == 0.0) continue;
+    const double* a = con->col + (size_t)c * nv;
+    for (int i = 0; i < nv; ++i) {
+      if (s->fidx[i] < 0) continue;
+      for (int ax = 0; ax < 3; ++ax) qhat[3 * i + ax] += l * a[i] * con->n[3 * c + ax];
+    }
+  }
+  free(dfree);
+}
+
+/* the FB Newton solve alone, on a given W and free gap (for checks); returns the Newton iterations */
+int or_fb_lcp(int K, const double* W, const double* dfree, double* lambda, double* res) {
+  or_contacts con = {K, NULL, NULL, NULL, 0.0, lambda, NULL, (double*)W, 0.0, 0};
+  for (int c = 0; c < K; ++c) lambda[c] = 0.0;
+  fb_newton(&con, dfree);
+  if (res) *res = con.fb_res;
+  return con.fb_iters;
+}
+
+static int step_forward_impl(const or_scene* s, const double* q_t, const double* v_t, const double* f_ext,
+                             const double* q0, double* q_next, double* v_next, double* q_star_m1, int force_iters,
+                             int m_override, int rec_max, double* rec, int* istats, double* dstats,
+                             or_contacts* con) {
   int nv = s->nv, n3 = 3 * nv;
   int m = m_override >= 0 ? m_override : s->m;
   double* c = (double*)malloc(sizeof(double) * n3);
@@ -927,6 +1099,11 @@ int or_step_forward(const or_scene* s, const double* q_t, const double* v_t, con
   memcpy(qprev, q, sizeof(double) * n3);
   int k, status = 1, resets = 0, capped = 0, maxit = 0;
   double gate[4] = {0, 0, 0, 0};
+  if (con) {
+    contact_setup(s, con);
+    for (int c = 0; c < con->K; ++c) con->lambda[c] = 0.0;
+    con->fb_res = 0.0;
+  }
   int kmax = force_iters > 0 ? force_iters + 1 : s->kmax_fwd;
   for (k = 0; k < kmax; ++k) {
     if (rec && k < rec_max) memcpy(rec + (size_t)k * n3, q, sizeof(double) * n3);
@@ -950,12 +1127,14 @@ int or_step_forward(const or_scene* s, const double* q_t, const double* v_t, con
       }
       gate[0] = sqrt(dq); gate[1] = sqrt(nq); gate[2] = sqrt(db); gate[3] = sqrt(nb);
       int pass = gate[0] <= s->eps_rel * gate[1] + s->eps_abs && gate[2] <= s->eps_rel * gate[3] + s->eps_abs;
+      if (con) pass = pass && con->fb_res <= con->fb_tol;
       if (force_iters <= 0 && k >= 2 && pass) { status = 0; break; }
     }
     if (force_iters > 0 && k == force_iters) { status = 0; break; }
     if (force_iters <= 0 && k == kmax - 1) break; /* not converged */
     /* global solve q^ = A^-1 b, Eq. two_spmv (role) */
     or_apply_Ainv(s, b, qhat);
+    if (con) contact_solve(s, con, qhat);
     /* bounded type-II Anderson acceleration, Eqs. aa_dG..aa_update */
     memcpy(qprev, q, sizeof(double) * n3);
     memcpy(bprev, b, sizeof(double) * n3);
@@ -972,8 +1151,27 @@ int or_step_forward(const or_scene* s, const double* q_t, const double* v_t, con
   }
   if (istats) { istats[0] = k; istats[1] = resets; istats[2] = capped; istats[3] = maxit; istats[4] = status; }
   if (dstats) for (int i = 0; i < 4; ++i) dstats[i] = gate[i];
+  if (con) contact_free(con);
   free(c); free(q); free(qprev); free(b); free(bprev); free(qhat); free(g); free(Hq); free(Hg);
   return status;
+}
+
+int or_step_forward(const or_scene* s, const double* q_t, const double* v_t, const double* f_ext, const double* q0,
+                    double* q_next, double* v_next, double* q_star_m1, int force_iters, int m_override,
+                    int rec_max, double* rec, int* istats, double* dstats) {
+  return step_forward_impl(s, q_t, v_t, f_ext, q0, q_next, v_next, q_star_m1, force_iters, m_override, rec_max, rec,
+                           istats, dstats, NULL);
+}
+
+int or_step_forward_contact(const or_scene* s, const double* q_t, const double* v_t, const double* f_ext,
+                            const double* q0, double* q_next, double* v_next, double* q_star_m1, int K,
+                            const int* cv, const double* cn, const double* cg, double fb_tol, double* lambda,
+                            int* istats, double* dstats) {
+  or_contacts con = {K, cv, cn, cg, fb_tol, lambda, NULL, NULL, 0.0, 0};
+  int st = step_forward_impl(s, q_t, v_t, f_ext, q0, q_next, v_next, q_star_m1, 0, -1, 0, NULL, istats, dstats,
+                             K > 0 ? &con : NULL);
+  if (dstats) dstats[4] = con.fb_res;
+  return st;
 }
 
 /* dense LU with partial pivoting, in place; solves A x = b (n small) */
@@ -1004,10 +1202,10 @@ static int dense_lu_solve(double* A, int n, double* b) {
 /* ------------------------------------------------------------------------ */
 /* backward step, Alg. 2 (no contact)                                        */
 /* ------------------------------------------------------------------------ */
-int or_step_backward(const or_scene* s, const double* q_t, const double* v_t, const double* f_ext,
-                     const double* q_star, const double* q_star_m1, const double* gq_next, const double* gv_next,
-                     double* gq_t, double* gv_t, double* gf_ext, double* g_logE, int adj_mode, double tau_force,
-                     int* istats, double* dstats) {
+static int step_backward_impl(const or_scene* s, const double* q_t, const double* v_t, const double* f_ext,
+                              const double* q_star, const double* q_star_m1, const double* gq_next,
+                              const double* gv_next, double* gq_t, double* gv_t, double* gf_ext, double* g_logE,
+                              int adj_mode, double tau_force, int* istats, double* dstats, or_contacts* con) {
   int nv = s->nv, n3 = 3 * nv;
   double h = s->h;
   double* qbar = (double*)malloc(sizeof(double) * n3);
@@ -1053,7 +1251,89 @@ int or_step_backward(const or_scene* s, const double* q_t, const double* v_t, co
   double* mu = (double*)calloc(n3, sizeof(double));
   double* kst = prox_diff_all(s, q_star, tau);
   int iters = 0, status = 0;
-  if (adj_mode == 1) {
+  /* READING (contact adjoint, frictionless): the active set {c: lambda_c >
+   * 1e-10 max lambda} is held fixed; active rows are equalities J_A dq = 0, so
+   * (A - K) mu - J_A^T nu = q^bar, J_A mu = 0. */
+  int na = 0;
+  int* act = NULL;
+  double* WA = NULL;
+  if (con && con->K > 0) {
+    contact_setup(s, con);
+    double lmax = 0.0;
+    for (int c = 0; c < con->K; ++c) lmax = con->lambda[c] > lmax ? con->lambda[c] : lmax;
+    act = (int*)malloc(sizeof(int) * con->K);
+    for (int c = 0; c < con->K; ++c)
+      if (lmax > 0.0 && con->lambda[c] > 1e-10 * lmax) act[na++] = c;
+    WA = (double*)malloc(sizeof(double) * (size_t)(na > 0 ? na : 1) * (na > 0 ? na : 1));
+  }
+  if (na > 0 && adj_mode == 1) {
+    /* dense saddle-point system */
+    int nf = s->nf, N = 3 * nf + na;
+    double* Mat = (double*)calloc((size_t)N * N, sizeof(double));
+    double* col = (double*)calloc(n3, sizeof(double));
+    double* Ac = (double*)malloc(sizeof(double) * n3);
+    double* Kc = (double*)malloc(sizeof(double) * n3);
+    for (int j = 0; j < 3 * nf; ++j) {
+      int vj = s->fvert[j / 3], aj = j % 3;
+      col[3 * vj + aj] = 1.0;
+      or_apply_A(s, col, Ac);
+      apply_K_stored(s, kst, col, Kc);
+      col[3 * vj + aj] = 0.0;
+      for (int i = 0; i < 3 * nf; ++i) {
+        int vi = s->fvert[i / 3], ai = i % 3;
+        Mat[(size_t)i * N + j] = Ac[3 * vi + ai] - Kc[3 * vi + ai];
+      }
+    }
+    for (int a = 0; a < na; ++a) {
+      int c = act[a], v = con->v[c];
+      int fi = s->fidx[v];
+      for (int ax = 0; ax < 3; ++ax) {
+        int j = 3 * fi + ax;
+        Mat[(size_t)j * N + 3 * nf + a] = -con->n[3 * c + ax];
+        Mat[(size_t)(3 * nf + a) * N + j] = -con->n[3 * c + ax];
+      }
+    }
+    double* rhs = (double*)calloc(N, sizeof(double));
+    for (int i = 0; i < 3 * nf; ++i) rhs[i] = qbar[3 * s->fvert[i / 3] + i % 3];
+    if (!dense_lu_solve(Mat, N, rhs)) status = -1;
+    for (int i = 0; i < 3 * nf; ++i) mu[3 * s->fvert[i / 3] + i % 3] = rhs[i];
+    free(Mat); free(col); free(Ac); free(Kc); free(rhs);
+  } else if (na > 0) {
+    /* projected fixed point mu <- P (q^bar + K mu), P = A^-1 - A^-1 J_A^T W_AA^-1 J_A A^-1 */
+    double* t = (double*)malloc(sizeof(double) * n3);
+    double* mun = (double*)malloc(sizeof(double) * n3);
+    double* u = (double*)malloc(sizeof(double) * na);
+    status = 1;
+    for (iters = 1; iters <= s->kmax_bwd; ++iters) {
+      apply_K_stored(s, kst, mu, t);
+      for (int i = 0; i < n3; ++i) t[i] += qbar[i];
+      or_apply_Ainv(s, t, mun);
+      for (int a = 0; a < na; ++a) {
+        int c = act[a];
+        const double* z = mun + 3 * con->v[c];
+        u[a] = con->n[3 * c] * z[0] + con->n[3 * c + 1] * z[1] + con->n[3 * c + 2] * z[2];
+        for (int b2 = 0; b2 < na; ++b2) WA[(size_t)a * na + b2] = con->W[(size_t)c * con->K + act[b2]];
+      }
+      if (!chol_solve(WA, na, u)) { status = -1; break; }
+      for (int a = 0; a < na; ++a) {
+        int c = act[a];
+        const double* col = con->col + (size_t)c * nv;
+        for (int i = 0; i < nv; ++i) {
+          if (s->fidx[i] < 0) continue;
+          for (int ax = 0; ax < 3; ++ax) mun[3 * i + ax] -= u[a] * col[i] * con->n[3 * c + ax];
+        }
+      }
+      double d = 0, nrm = 0;
+      for (int i = 0; i < n3; ++i) {
+        d += (mun[i] - mu[i]) * (mun[i] - mu[i]);
+        nrm += mun[i] * mun[i];
+      }
+      memcpy(mu, mun, sizeof(double) * n3);
+      if (sqrt(d) <= s->eps_adj * sqrt(nrm)) { status = 0; break; }
+    }
+    if (iters > s->kmax_bwd) iters = s->kmax_bwd;
+    free(t); free(mun); free(u);
+  } else if (adj_mode == 1) {
     int nf = s->nf, N = 3 * nf;
     double* Mat = (double*)malloc(sizeof(double) * (size_t)N * N);
     double* col = (double*)calloc(n3, sizeof(double));
@@ -1142,6 +1422,39 @@ int or_step_backward(const or_scene* s, const double* q_t, const double* v_t, co
     }
   if (istats) { istats[0] = iters; istats[1] = status; }
   if (dstats) { dstats[0] = rho; dstats[1] = tau; dstats[2] = dphi_act; dstats[3] = dphi_mod; }
+  if (con && con->K > 0) contact_free(con);
+  free(act); free(WA);
   free(qbar); free(qtilde); free(c); free(dq); free(Adq); free(mu); free(Bmu); free(kst);
   return status;
+}
+
+int or_step_backward(const or_scene* s, const double* q_t, const double* v_t, const double* f_ext,
+                     const double* q_star, const double* q_star_m1, const double* gq_next, const double* gv_next,
+                     double* gq_t, double* gv_t, double* gf_ext, double* g_logE, int adj_mode, double tau_force,
+                     int* istats, double* dstats) {
+  return step_backward_impl(s, q_t, v_t, f_ext, q_star, q_star_m1, gq_next, gv_next, gq_t, gv_t, gf_ext, g_logE,
+                            adj_mode, tau_force, istats, dstats, NULL);
+}
+
+int or_step_backward_contact(const or_scene* s, const double* q_t, const double* v_t, const double* f_ext,
+                             const double* q_star, const double* q_star_m1, const double* gq_next,
+                             const double* gv_next, double* gq_t, double* gv_t, double* gf_ext, double* g_logE,
+                             int adj_mode, double tau_force, int K, const int* cv, const double* cn,
+                             const double* cg, const double* lambda, int* istats, double* dstats) {
+  double* lam = (double*)malloc(sizeof(double) * (K > 0 ? K : 1));
+  for (int c = 0; c < K; ++c) lam[c] = lambda[c];
+  or_contacts con = {K, cv, cn, cg, 0.0, lam, NULL, NULL, 0.0, 0};
+  int st = step_backward_impl(s, q_t, v_t, f_ext, q_star, q_star_m1, gq_next, gv_next, gq_t, gv_t, gf_ext, g_logE,
+                              adj_mode, tau_force, istats, dstats, K > 0 ? &con : NULL);
+  free(lam);
+  return st;
+}
+
+/* Delassus operator of a contact set (for checks): W (K x K) */
+void or_contact_W(const or_scene* s, int K, const int* cv, const double* cn, double* W_out) {
+  double lam0 = 0.0;
+  or_contacts con = {K, cv, cn, NULL, 0.0, &lam0, NULL, NULL, 0.0, 0};
+  contact_setup(s, &con);
+  memcpy(W_out, con.W, sizeof(double) * (size_t)K * K);
+  contact_free(&con);
 }

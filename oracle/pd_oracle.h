@@ -66,6 +66,25 @@ int or_step_backward(const or_scene* s, const double* q_t, const double* v_t, co
                      double* gq_t, double* gv_t, double* gf_ext, double* g_logE, int adj_mode, double tau_force,
                      int* istats, double* dstats);
 
+/* Contact (Sec. 4.7, frictionless reading): K rows, each on vertex cv[c] with unit normal cn[3c..3c+2] and
+ * offset cg[c] (gap n.q - g).  Forward: lambda (K) receives the converged impulses, dstats[4] the final
+ * FB residual; the dual gate also requires that residual <= fb_tol. */
+int or_step_forward_contact(const or_scene* s, const double* q_t, const double* v_t, const double* f_ext,
+                            const double* q0, double* q_next, double* v_next, double* q_star_m1, int K,
+                            const int* cv, const double* cn, const double* cg, double fb_tol, double* lambda,
+                            int* istats, double* dstats);
+/* Backward with the forward's contact rows and impulses; the active set (lambda > 1e-10 max lambda) is held
+ * fixed.  adj_mode 1 solves the dense saddle-point system, 0 the projected fixed point. */
+int or_step_backward_contact(const or_scene* s, const double* q_t, const double* v_t, const double* f_ext,
+                             const double* q_star, const double* q_star_m1, const double* gq_next,
+                             const double* gv_next, double* gq_t, double* gv_t, double* gf_ext, double* g_logE,
+                             int adj_mode, double tau_force, int K, const int* cv, const double* cn,
+                             const double* cg, const double* lambda, int* istats, double* dstats);
+/* Delassus operator W (K x K, row-major) of a contact set */
+void or_contact_W(const or_scene* s, int K, const int* cv, const double* cn, double* W_out);
+/* FB semi-smooth Newton on delta = dfree + W lambda, from lambda = 0; returns its iterations */
+int or_fb_lcp(int K, const double* W, const double* dfree, double* lambda, double* res);
+
 #ifdef __cplusplus
 }
 #endif

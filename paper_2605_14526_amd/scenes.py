@@ -137,6 +137,9 @@ class Scene:
     fd_tets: np.ndarray = dataclasses.field(default_factory=lambda: np.zeros(0, np.int64))
     eps_rel: float = 1e-6
     eps_abs: float = 1e-12
+    # static obstacles: {"planes": [(normal, offset)], "boxes": [(lo, hi)], "d_c": candidate distance}
+    obstacles: Optional[dict] = None
+    v_init: Optional[np.ndarray] = None
 
     @property
     def n_v(self) -> int:
@@ -155,6 +158,8 @@ class Scene:
         return self.X.copy()
 
     def v0(self) -> np.ndarray:
+        if self.v_init is not None:
+            return np.broadcast_to(np.asarray(self.v_init, float), (self.n_v, 3)).copy()
         return np.zeros((self.n_v, 3))
 
 
@@ -279,6 +284,69 @@ def beam_batch(n: int = 64, seed: int = 4000, steps: int = 50, ne_range=(1000, 3
         sc.name = f"batch_beam_{s}"
         out.append(sc)
     return out
+
+
+def shell_tets(tets: np.ndarray) -> np.ndarray:
+    """Mask of the tets that have a vertex on the boundary surface (a face used by one tet)."""
+    faces = {}
+    for t in np.asarray(tets):
+        for f in ((0, 1, 2), (0, 1, 3), (0, 2, 3), (1, 2, 3)):
+            key = tuple(sorted(int(t[i]) for i in f))
+            faces[key] = faces.get(key, 0) + 1
+    bnd = np.zeros(int(np.max(tets)) + 1, dtype=bool)
+    for key, c in faces.items():
+        if c == 1:
+            bnd[list(key)] = True
+    return bnd[np.asarray(tets)].any(axis=1)
+
+
+def drop_blob(res: int = 8, seed: int = 3001, n_spheres: int = 6, r_lo: float = 0.1, r_hi: float = 0.3,
+              contrast: float = 100.0, nu: float = 0.49, h: float = 0.002, steps: int = 200,
+              drop_speed: float = 1.0, with_box: bool = True, aa_window: int = 1) -> Scene:
+    """Contact drop: a seeded implicit blob (union of ``n_spheres`` spheres with radii uniform in [r_lo, r_hi]
+    and centres uniform in a 0.3 m cube), voxelised on a grid with ``res`` cells along its largest extent
+    (largest face-connected component) and split 5 tets per cube.  The shell (tets touching the boundary
+    surface) is ``contrast`` times stiffer than the interior (E 1e4 Pa inside).  Nothing is pinned; the
+    blob starts half a cell above the ground plane z = 0, moving down at ``drop_speed``, under gravity;
+    a static box under one half of the blob rises a quarter of the blob's height above the ground.
+    res = 27 gives about 1e5 tets."""
+    import scipy.ndimage
+    rng = _rng(seed)
+    cen = rng.uniform(0.0, 0.3, (n_spheres, 3))
+    rad = rng.uniform(r_lo, r_hi, n_spheres)
+    lo = (cen - rad[:, None]).min(axis=0)
+    hi = (cen + rad[:, None]).max(axis=0)
+    edge = float((hi - lo).max()) / res
+    dims = np.maximum(1, np.ceil((hi - lo) / edge).astype(int))
+    gi = [lo[a] + edge * (np.arange(dims[a]) + 0.5) for a in range(3)]
+    P = np.stack(np.meshgrid(*gi, indexing="ij"), axis=-1)
+    occ = np.zeros(tuple(dims), dtype=bool)
+    for c, r in zip(cen, rad):
+        occ |= ((P - c) ** 2).sum(axis=-1) <= r * r
+    lab, nlab = scipy.ndimage.label(occ)
+    if nlab > 1:
+        sizes = np.bincount(lab.ravel())[1:]
+        occ = lab == (1 + int(np.argmax(sizes)))
+    X, tets = voxel_tet_mesh(occ, edge)
+    X = X - X.min(axis=0)
+    ext = X.max(axis=0)
+    X[:, 2] += 0.5 * edge
+    shell = shell_tets(tets)
+    E_in = 1e4
+    logE = np.where(shell, np.log(E_in * contrast), np.log(E_in))
+    obs = {"planes": [((0.0, 0.0, 1.0), 0.0)], "boxes": [], "d_c": 0.25 * edge}
+    if with_box:
+        # the box top sits a quarter of the blob height up, under the half x > ext_x / 2; the blob starts
+        # above it by half a cell
+        top = 0.25 * ext[2]
+        obs["boxes"].append(((0.5 * ext[0], -0.5 * ext[1], -1.0), (1.5 * ext[0], 1.5 * ext[1], top)))
+        X[:, 2] += top
+    target = X.mean(axis=0) + _rng(seed + 1).uniform(-0.02, 0.02, 3)
+    fd = _rng(seed + 2).choice(tets.shape[0], size=min(4, tets.shape[0]), replace=False)
+    return Scene(f"drop_blob_r{res}", X, tets, np.zeros(X.shape[0], np.uint8), logE, nu=nu, rho=1000.0,
+                 alpha=0.01, beta0=1e-3 * E_in * contrast, h=h, gravity=np.array([0.0, 0.0, -9.81]),
+                 aa_window=aa_window, steps=steps, force_fn=None, target_centroid=target, fd_tets=fd,
+                 obstacles=obs, v_init=np.array([0.0, 0.0, -drop_speed]))
 
 
 def config(name: str) -> Scene:

@@ -37,7 +37,8 @@ enum {
   PD_ERR_STALE_FACTOR = -4,
   PD_ERR_FACTOR_NOT_SPD = -5,
   PD_ERR_HIP = -6,
-  PD_ERR_ALLOC = -7
+  PD_ERR_ALLOC = -7,
+  PD_ERR_CONTACT = -8  /* contact rows beyond max_contacts or the dense solve size, or a singular contact block */
 };
 
 typedef struct pd_scene pd_scene;
@@ -114,6 +115,9 @@ typedef struct pd_fwd_stats {
   int32_t status;
   int32_t newton_capped;  /* 1 if a tet's prox Newton reached its 50-iteration cap */
   double gate[4];
+  int32_t n_contacts;     /* candidate contact rows of the step */
+  int32_t n_active;       /* rows with a positive impulse at exit */
+  double fb_res;          /* Fischer-Burmeister residual max |phi| of the last contact solve */
 } pd_fwd_stats;
 
 /* Backward statistics: adjoint iterations, trust-region ratio rho and the
@@ -126,6 +130,8 @@ typedef struct pd_bwd_stats {
   double dphi_act;
   double dphi_mod;
   double residual;
+  int32_t n_active;  /* active contact rows held as equalities in the adjoint */
+  int32_t pad;
 } pd_bwd_stats;
 
 /* Create a scene: validates and copies the mesh and material, builds the
@@ -154,10 +160,11 @@ int pd_scene_factorize(pd_scene* scene, void* stream);
  * mu_bar, lam_bar, k_bar, mu_ref (may be NULL). */
 int pd_scene_info(const pd_scene* scene, double* info, double* means);
 
-/* Bytes of one checkpoint record (q_t, q tilde, q*, q*-1 of one step). */
+/* Bytes of one checkpoint record (q_t, q tilde, q*, q*-1 of one step; with
+ * obstacles also the step's contact rows and impulses). */
 size_t pd_ckpt_bytes(const pd_scene* scene);
 
-/* One forward step (Alg. 1, no contact).
+/* One forward step (Alg. 1; contact rows as set by pd_scene_set_obstacles).
  * q_t, v_t: current state; f_ext: external force per vertex (NULL = none;
  * gravity from the options is added); q0: initial iterate, e.g. a learned
  * warm start (NULL = q_t, or q_t + h v_t with fwd_start = 1); outputs q_next,
@@ -170,7 +177,7 @@ int pd_step_forward(pd_scene* scene, const double* q_t, const double* v_t, const
                     const double* q0, double* q_next, double* v_next, void* ckpt, pd_fwd_stats* stats,
                     void* stream);
 
-/* One backward step (Alg. 2, no contact) from a checkpoint written by
+/* One backward step (Alg. 2, with the step's active contact rows) from a checkpoint written by
  * pd_step_forward.  gq_next, gv_next: dL/dq_{t+h}, dL/dv_{t+h}.  Outputs
  * dL/dq_t, dL/dv_t, dL/df_ext (overwritten; zero on pinned vertices) and
  * g_logE_accum += dL/dlog E_e (n_tets, caller's tet order).  Any output
@@ -180,6 +187,40 @@ int pd_step_forward(pd_scene* scene, const double* q_t, const double* v_t, const
 int pd_step_backward(pd_scene* scene, const void* ckpt, const double* gq_next, const double* gv_next,
                      double* gq_t, double* gv_t, double* gf_ext, double* g_logE_accum, pd_bwd_stats* stats,
                      void* stream);
+
+/* ------------------------------------------------------------------------
+ * Contact with static obstacles (Sec. 4.7, Eqs. fb_n, omega_E_n,
+ * contact_system, q_update), read frictionless: each row c acts on one free
+ * vertex v_c along a unit normal n_c with gap n_c . q_{v_c} - g_c >= 0 and
+ * impulse lam_c >= 0, complementary.  At the start of every pd_step_forward
+ * the library detects the rows: for each free vertex and each obstacle, the
+ * obstacle's distance d (a plane's signed distance n.x - o; for a box the
+ * largest signed distance over its faces -x, +x, -y, +y, -z, +z) is taken at
+ * x0 = q_t and x1 = q_t + h v_t, and the pair is a row if min(d(x0), d(x1)) <
+ * d_c, with the normal and offset of the face attaining d(x0).  Inside every
+ * PD iteration the global solve is followed by a Fischer-Burmeister Newton
+ * solve of the rows on the Delassus operator W = J A~^{-1} J^T (built from
+ * cached columns A~^{-1} e_v, reused across steps: one factor serves the
+ * forward, backward and contact stages) and the position correction
+ * sum_c lam_c A~^{-1} e_{v_c} n_c; the dual gate also requires the FB
+ * residual <= fb_tol.  pd_step_backward holds the active rows (lam > 1e-10
+ * max lam) as equalities and projects the adjoint onto them.
+ *
+ * pd_scene_set_obstacles: planes n_planes x 4 (unit normal, offset o), boxes
+ * n_boxes x 6 (lo xyz, hi xyz), host pointers, copied; at most 8 obstacles;
+ * d_c > 0 the candidate distance; max_contacts (1..256) the row capacity per
+ * step (PD_ERR_CONTACT beyond it); fb_tol > 0.  n_planes = n_boxes = 0 turns
+ * contact off.  Checkpoints allocated before this call are too small
+ * afterwards (pd_ckpt_bytes grows).  Scenes with obstacles cannot join a
+ * batch.
+ * pd_contact_rows: the rows of the last pd_step_forward (host buffers of
+ * `capacity` entries, any may be NULL): caller's vertex ids, normals (3 per
+ * row), offsets, impulses; *K receives the row count.
+ * ------------------------------------------------------------------------ */
+int pd_scene_set_obstacles(pd_scene* scene, int n_planes, const double* planes, int n_boxes, const double* boxes,
+                           double d_c, int max_contacts, double fb_tol);
+int pd_contact_rows(const pd_scene* scene, int* K, int32_t* vert, double* normals, double* offsets,
+                    double* lambda, int capacity);
 
 /* Forget the adjoint solutions kept for the warm start (adj_warm > 0), so the
  * next pd_step_backward starts from zero.  No device work. */

@@ -19,7 +19,8 @@ LIB_PATH = os.path.join(_HERE, "libpdhot.so")
 PD_OK = 0
 PD_NOT_CONVERGED = 1
 ERRORS = {-1: "PD_ERR_INVALID_ARG", -2: "PD_ERR_DEGENERATE_TET", -3: "PD_ERR_NONFINITE",
-          -4: "PD_ERR_STALE_FACTOR", -5: "PD_ERR_FACTOR_NOT_SPD", -6: "PD_ERR_HIP", -7: "PD_ERR_ALLOC"}
+          -4: "PD_ERR_STALE_FACTOR", -5: "PD_ERR_FACTOR_NOT_SPD", -6: "PD_ERR_HIP", -7: "PD_ERR_ALLOC",
+          -8: "PD_ERR_CONTACT"}
 
 EXPORTED = ["pd_scene_create", "pd_scene_destroy", "pd_scene_set_material", "pd_scene_factorize", "pd_scene_info",
             "pd_ckpt_bytes", "pd_step_forward", "pd_step_backward", "pd_debug_local_rhs", "pd_debug_apply_Ainv",
@@ -27,7 +28,7 @@ EXPORTED = ["pd_scene_create", "pd_scene_destroy", "pd_scene_set_material", "pd_
             "pd_mpn_create", "pd_mpn_destroy", "pd_mpn_info", "pd_mpn_init_params", "pd_mpn_set_params",
             "pd_mpn_get_params", "pd_mpn_get_grads", "pd_mpn_set_output_scale", "pd_mpn_forward", "pd_mpn_loss_grad",
             "pd_mpn_adam_step", "pd_batch_create", "pd_batch_destroy", "pd_batch_config", "pd_batch_step_forward",
-            "pd_batch_step_backward", "pd_last_error"]
+            "pd_batch_step_backward", "pd_scene_set_obstacles", "pd_contact_rows", "pd_last_error"]
 
 
 class pd_mesh_desc(ctypes.Structure):
@@ -55,13 +56,14 @@ class pd_mpn_desc(ctypes.Structure):
 
 class pd_fwd_stats(ctypes.Structure):
     _fields_ = [("iters", ctypes.c_int32), ("aa_resets", ctypes.c_int32), ("status", ctypes.c_int32),
-                ("newton_capped", ctypes.c_int32), ("gate", ctypes.c_double * 4)]
+                ("newton_capped", ctypes.c_int32), ("gate", ctypes.c_double * 4), ("n_contacts", ctypes.c_int32),
+                ("n_active", ctypes.c_int32), ("fb_res", ctypes.c_double)]
 
 
 class pd_bwd_stats(ctypes.Structure):
     _fields_ = [("adj_iters", ctypes.c_int32), ("status", ctypes.c_int32), ("rho", ctypes.c_double),
                 ("tau", ctypes.c_double), ("dphi_act", ctypes.c_double), ("dphi_mod", ctypes.c_double),
-                ("residual", ctypes.c_double)]
+                ("residual", ctypes.c_double), ("n_active", ctypes.c_int32), ("pad", ctypes.c_int32)]
 
 
 _lib = None
@@ -110,6 +112,8 @@ def lib() -> ctypes.CDLL:
     L.pd_batch_config.argtypes = [vp, i32, i32, i32, i32]
     L.pd_batch_step_forward.argtypes = [vp, vp, vp, vp, vp, vp, vp, vp, vp, vp]
     L.pd_batch_step_backward.argtypes = [vp, vp, vp, vp, vp, vp, vp, vp, vp, vp]
+    L.pd_scene_set_obstacles.argtypes = [vp, i32, vp, i32, vp, dbl, i32, dbl]
+    L.pd_contact_rows.argtypes = [vp, vp, vp, vp, vp, vp, i32]
     L.pd_last_error.restype = ctypes.c_char_p
     for name in EXPORTED:
         getattr(L, name)
@@ -163,9 +167,38 @@ class Scene:
     @classmethod
     def from_scene(cls, sc, **kw):
         args = dict(aa_window=sc.aa_window, eps_rel=sc.eps_rel, eps_abs=sc.eps_abs)
+        contact = kw.pop("contact", {})
         args.update(kw)
-        return cls(sc.X, sc.tets, sc.pinned, sc.log_E, sc.nu, sc.rho, sc.alpha, sc.beta0, sc.h,
-                   tuple(np.asarray(sc.gravity, float)), **args)
+        g = cls(sc.X, sc.tets, sc.pinned, sc.log_E, sc.nu, sc.rho, sc.alpha, sc.beta0, sc.h,
+                tuple(np.asarray(sc.gravity, float)), **args)
+        if getattr(sc, "obstacles", None):
+            g.set_obstacles(sc.obstacles, **contact)
+        return g
+
+    def set_obstacles(self, obs, max_contacts=256, fb_tol=1e-10):
+        """Static obstacles {"planes": [(n, o)], "boxes": [(lo, hi)], "d_c": d} (pd_scene_set_obstacles)."""
+        planes = np.ascontiguousarray([list(n) + [o] for (n, o) in obs.get("planes", [])] or np.zeros((0, 4)),
+                                      dtype=np.float64)
+        boxes = np.ascontiguousarray([list(lo) + list(hi) for (lo, hi) in obs.get("boxes", [])] or np.zeros((0, 6)),
+                                     dtype=np.float64)
+        self._obs = (planes, boxes)
+        check(lib().pd_scene_set_obstacles(self.ptr, planes.shape[0], planes.ctypes.data if planes.size else None,
+                                           boxes.shape[0], boxes.ctypes.data if boxes.size else None,
+                                           float(obs["d_c"]), int(max_contacts), float(fb_tol)),
+              "pd_scene_set_obstacles")
+
+    def contact_rows(self):
+        """Rows of the last forward step: caller's vertex ids, normals, offsets, impulses."""
+        K = ctypes.c_int()
+        check(lib().pd_contact_rows(self.ptr, ctypes.byref(K), None, None, None, None, 0), "pd_contact_rows")
+        n = K.value
+        v = np.zeros(max(n, 1), np.int32)
+        nn = np.zeros((max(n, 1), 3))
+        g = np.zeros(max(n, 1))
+        lam = np.zeros(max(n, 1))
+        check(lib().pd_contact_rows(self.ptr, ctypes.byref(K), v.ctypes.data, nn.ctypes.data, g.ctypes.data,
+                                    lam.ctypes.data, n), "pd_contact_rows")
+        return v[:n], nn[:n], g[:n], lam[:n]
 
     def close(self):
         if getattr(self, "ptr", None) is not None and self.ptr.value:
@@ -210,7 +243,8 @@ class Scene:
         rc = check(lib().pd_step_forward(self.ptr, _ptr(q_t), _ptr(v_t), _ptr(f_ext), _ptr(q0), _ptr(q_next),
                                          _ptr(v_next), _ptr(ckpt), ctypes.byref(st), _stream()), "pd_step_forward")
         return q_next, v_next, dict(iters=st.iters, aa_resets=st.aa_resets, status=st.status, rc=rc,
-                                    newton_capped=st.newton_capped, gate=list(st.gate))
+                                    newton_capped=st.newton_capped, gate=list(st.gate), n_contacts=st.n_contacts,
+                                    n_active=st.n_active, fb_res=st.fb_res)
 
     def step_backward(self, ckpt, gq_next, gv_next, g_logE=None, gq_t=None, gv_t=None, gf_ext=None):
         import torch
@@ -224,7 +258,8 @@ class Scene:
                                           _ptr(gv_t), _ptr(gf_ext), _ptr(g_logE), ctypes.byref(st), _stream()),
                    "pd_step_backward")
         self.last_bwd_stats = dict(adj_iters=st.adj_iters, status=st.status, rho=st.rho, tau=st.tau,
-                                   dphi_act=st.dphi_act, dphi_mod=st.dphi_mod, residual=st.residual, rc=rc)
+                                   dphi_act=st.dphi_act, dphi_mod=st.dphi_mod, residual=st.residual, rc=rc,
+                                   n_active=st.n_active)
         return gq_t, gv_t, gf_ext, g_logE, self.last_bwd_stats
 
     def vertex_logw(self) -> np.ndarray:

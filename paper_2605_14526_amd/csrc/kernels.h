@@ -17,7 +17,8 @@ enum {
   kModePCGInit = 4,
   kModeFixed = 5,
   kModeAmK = 6,   // (A~ - K) x element terms (adjoint warm start)
-  kModeInit = 7   // r = q bar - (A~ - K) mu (adjoint warm start)
+  kModeInit = 7,  // r = q bar - (A~ - K) mu (adjoint warm start)
+  kModePCGSolve = 8  // PCG step whose preconditioned residual is corrected afterwards (contact projection)
 };
 
 // device control block (int): done flag, final iteration count, status,
@@ -103,6 +104,8 @@ struct StepState {
   int* ctl;
   int* done;
   double* dstat;
+  const double* fb = nullptr;  // contact: FB residual of the last contact solve (null without contact rows)
+  double fb_tol = 0.0;
 };
 
 struct AdjState {
@@ -114,6 +117,36 @@ struct AdjState {
   int* ctl;       // [iters, status]
   int* done;
   double* dstat;  // [residual]
+};
+
+// Contact rows of one step (forward: every candidate row; adjoint: the active
+// rows) and the cached columns a = A~^{-1} e_v of their vertices.
+constexpr int kContactThreads = 1024;
+constexpr int kMaxContactRows = 256;  // candidate rows per step
+constexpr int kMaxNewtonRows = 176;   // rows of one FB Newton system (packed in LDS)
+constexpr int kMaxObstacles = 8;
+constexpr int kFBMaxIter = 30;
+constexpr double kFBTol = 1e-14;
+constexpr double kOmegaMin = 1e-12;
+struct ContactArgs {
+  int K;
+  int nf;
+  const int* v;        // K library vertex ids
+  const double* n;     // 3K unit normals, row-major (n[3c + a])
+  const double* g;     // K offsets: gap = n . q_v - g
+  const int* slot;     // K column slots
+  const double* cols;  // columns: a_v at cols[slot * nf + row]
+  const double* W;     // K x K Delassus operator (forward) or its inverse on the active rows (adjoint)
+  double* lam;         // K impulses
+  double* s;           // 3K: lam_c n_c (forward) or u_c n_c (adjoint projection)
+  double* fb;          // [0] FB residual, [1] Newton iterations of the last solve
+  int* flags;          // [0] candidate rows found, [1] Newton system too large, [2] factor not SPD
+};
+struct ObsArgs {
+  int n_planes, n_boxes;
+  const double* planes;  // 4 per plane: unit normal, offset
+  const double* boxes;   // 6 per box: lo xyz, hi xyz
+  double d_c, h;
 };
 
 // Everything a kernel needs about one scene, for launches that span many
@@ -185,6 +218,23 @@ void launch_grad_elem(const ElemArgs& E, const VertArgs& V, const double* ck, co
 void launch_grad_vert(const VertArgs& V, const double* mu, const double* contrib, const double* gv_next, double* gq_t,
                       double* gv_t, double* gf, hipStream_t s);
 void launch_init_warm(const ElemArgs& E, hipStream_t s);
+
+// contact (contact.hip, and the apply kernels in kernels.hip)
+void launch_contact_detect(const VertArgs& V, const double* qt, const double* vt, const ObsArgs& O, int kmax,
+                           int* v, double* n, double* g, int* flags, hipStream_t s);
+void launch_unit_rhs(int nv, double* rhs, int v0, int v1, int v2, hipStream_t s);
+void launch_store_cols(int nf, int nv, const double* x, double* cols, int s0, int s1, int s2, hipStream_t s);
+void launch_contact_W(const ContactArgs& C, double* W, hipStream_t s);
+void launch_contact_start(const ContactArgs& C, hipStream_t s);
+void launch_contact_fb(const VertArgs& V, const ContactArgs& C, const double* qhat, const int* done, hipStream_t s);
+void launch_contact_winv(const ContactArgs& C, double* Winv, hipStream_t s);
+void launch_contact_proj(const VertArgs& V, const ContactArgs& C, const double* z, const int* done, hipStream_t s);
+void launch_contact_ckpt(const ContactArgs& C, int kmax, double* rec, hipStream_t s);
+int contact_apply_blocks(int nf);
+void launch_contact_apply_fwd(const VertArgs& V, const StepState& St, const RedArgs& R, const ContactArgs& C, int k,
+                              hipStream_t s);
+void launch_contact_apply_adj(int mode, const VertArgs& V, const AdjState& A, const RedArgs& R,
+                              const ContactArgs& C, const double* rhs, int k, hipStream_t s);
 void launch_zero_int(int* p, int n, hipStream_t s);
 
 }  // namespace pdhot

@@ -674,7 +674,9 @@ __device__ __forceinline__ void b_Eb(VertArgs Vx, SolveArgs Sv, StepState St, Ad
     if (k >= 1) consume<4>(R, kRedGate, g, bid);
     if (threadIdx.x == 0) {
       const double dq = sqrt(g[0]), nq = sqrt(g[1]), db = sqrt(g[2]), nb = sqrt(g[3]);
-      const bool pass = dq <= St.eps_rel * nq + St.eps_abs && db <= St.eps_rel * nb + St.eps_abs;
+      // with contact rows the FB residual of the last contact solve is a third condition
+      const bool fb_ok = !St.fb || St.fb[0] <= St.fb_tol;
+      const bool pass = dq <= St.eps_rel * nq + St.eps_abs && db <= St.eps_rel * nb + St.eps_abs && fb_ok;
       const bool conv = (k >= 2) && pass;
       const bool cap = (k >= St.kmax - 1);
       stop = flag || conv || cap;
@@ -782,6 +784,75 @@ __global__ void __launch_bounds__(kBlock) k_top(VertArgs Vx, SolveArgs Sv, doubl
   b_top(Vx, Sv, out, blockIdx.x);
 }
 
+// Anderson append of one forward iteration for the free row my_row (-1: no
+// row): g = q^ - q^k, the new difference columns (Eqs. aa_dG, aa_dQ) and the
+// block's Gram partial sums.  xo = q^ of the row, u0 = q^k, u1 = g of the last
+// iteration, u2 = q of the last iteration; aa = the ring state of parity k.
+// Every thread of the block calls it.
+template <int M>
+__device__ __forceinline__ void aa_append(const StepState& St, const RedArgs& R, int nv, int bid, int my_row,
+                                          const double (&xo)[3], const double (&u0)[3], const double (&u1)[3],
+                                          const double (&u2)[3], const int (&aa)[4]) {
+  int nonempty, nc, head, slot_new;
+  aa_layout(aa, M, nonempty, nc, head, slot_new);
+  // Gram partial sums, compact layout: G[j][l] at j*M + l, rhs[j] at M*M + j
+  constexpr int NA = M * M + M;
+  double part[NA];
+#pragma unroll
+  for (int j = 0; j < NA; ++j) part[j] = 0.0;
+  if (my_row >= 0) {
+    const int i = my_row;
+    double col[3][M];
+#pragma unroll
+    for (int a = 0; a < 3; ++a)
+#pragma unroll
+      for (int j = 0; j < M; ++j) {
+        int slot = head + j;
+        if (slot >= M) slot -= M;
+        col[a][j] = (j < nc) ? St.dG[((size_t)slot * 3 + a) * nv + i] : 0.0;
+      }
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+      const int ix = a * nv + i;
+      const double qc = u0[a];
+      const double g = xo[a] - qc;
+      if (slot_new >= 0) {
+        const size_t cix = ((size_t)slot_new * 3 + a) * nv + i;
+        const double dg = g - u1[a];
+        St.dG[cix] = dg;
+        St.dQ[cix] = qc - u2[a];
+        // the new column enters the Gram sums at its position in the window
+#pragma unroll
+        for (int j = 0; j < M; ++j) {
+          int slot = head + j;
+          if (slot >= M) slot -= M;
+          if (j < nc && slot == slot_new) col[a][j] = dg;
+        }
+      }
+      St.g_last[ix] = g;
+      St.q_last[ix] = qc;
+#pragma unroll
+      for (int j = 0; j < M; ++j) {
+#pragma unroll
+        for (int l = 0; l < M; ++l)
+          if (l >= j) part[j * M + l] += col[a][j] * col[a][l];
+        part[M * M + j] += col[a][j] * g;
+      }
+    }
+  }
+  __shared__ double red[16 * NA];
+  block_sum<NA>(part, red);
+  if (threadIdx.x == 0) {
+    double* o = R.part + ((size_t)kRedAA * R.max_parts + bid) * kRedWidth;
+#pragma unroll
+    for (int j = 0; j < M; ++j) {
+#pragma unroll
+      for (int l = 0; l < M; ++l) o[j * M + l] = (j <= l) ? part[j * M + l] : part[l * M + j];
+      o[M * M + j] = part[M * M + j];
+    }
+  }
+}
+
 // ---------------------------------------------------------------- subdomain solve
 // x_s = Z_s rhs_s - E_s^T x_T on the subdomain rows (one wave per row), then
 // the per-vertex work of each mode on every free row (the lane 0 of a
@@ -813,7 +884,8 @@ __device__ __forceinline__ void b_bottom(VertArgs Vx, SolveArgs Sv, StepState St
     if (i < nf) my_row = i;
   }
   const bool iface = my_row >= nB;
-  const double* __restrict__ src = (MODE == kModeFwd) ? St.b_cur : (MODE == kModePCG ? r_cur(A, k) : rhs);
+  constexpr bool kPCG = (MODE == kModePCG || MODE == kModePCGSolve);
+  const double* __restrict__ src = (MODE == kModeFwd) ? St.b_cur : (kPCG ? r_cur(A, k) : rhs);
   const double* __restrict__ wv = A.w;
   double* dst = (MODE == kModeFwd) ? St.qhat : out;
   const int* done = (MODE == kModeFwd || MODE == kModePlain) ? St.done : A.done;
@@ -842,7 +914,7 @@ __device__ __forceinline__ void b_bottom(VertArgs Vx, SolveArgs Sv, StepState St
         u0[a] = St.q_cur[ix];
         u1[a] = St.g_last[ix];
         u2[a] = St.q_last[ix];
-      } else if (MODE == kModePCG) {
+      } else if (kPCG) {
         u0[a] = src[ix];
         u1[a] = A.p[ix];
         u2[a] = wv[ix];
@@ -856,8 +928,8 @@ __device__ __forceinline__ void b_bottom(VertArgs Vx, SolveArgs Sv, StepState St
     }
   }
   // alpha = (r.z)/(p.w): both totals were stored by k_Eb's block 0 and earlier
-  const double rz = (MODE == kModePCG) ? fin_site(R, kRedRZ0 + (k & 1))[0] : 0.0;
-  const double pwt = (MODE == kModePCG) ? fin_site(R, kRedPW)[0] : 1.0;
+  const double rz = kPCG ? fin_site(R, kRedRZ0 + (k & 1))[0] : 0.0;
+  const double pwt = kPCG ? fin_site(R, kRedPW)[0] : 1.0;
   __syncthreads();
   if (flag_s) return;
   const double alpha = rz / pwt;
@@ -872,7 +944,7 @@ __device__ __forceinline__ void b_bottom(VertArgs Vx, SolveArgs Sv, StepState St
     for (int u = lane; u < br.ns; u += 64) {
       const double z = Zr[u];
       const int c = br.b0 + u;
-      if (MODE == kModePCG) {
+      if (kPCG) {
         a0 += z * (src[c] - alpha * wv[c]);
         a1 += z * (src[nv + c] - alpha * wv[nv + c]);
         a2 += z * (src[2 * nv + c] - alpha * wv[2 * nv + c]);
@@ -901,66 +973,7 @@ __device__ __forceinline__ void b_bottom(VertArgs Vx, SolveArgs Sv, StepState St
   if (MODE == kModePlain) return;
   // ---- per-vertex work
   if (MODE == kModeFwd) {
-    if constexpr (M > 0) {
-      int nonempty, nc, head, slot_new;
-      aa_layout(aa, M, nonempty, nc, head, slot_new);
-      // Gram partial sums, compact layout: G[j][l] at j*M + l, rhs[j] at M*M + j
-      constexpr int NA = M * M + M;
-      double part[NA];
-#pragma unroll
-      for (int j = 0; j < NA; ++j) part[j] = 0.0;
-      if (my_row >= 0) {
-        const int i = my_row;
-        double col[3][M];
-#pragma unroll
-        for (int a = 0; a < 3; ++a)
-#pragma unroll
-          for (int j = 0; j < M; ++j) {
-            int slot = head + j;
-            if (slot >= M) slot -= M;
-            col[a][j] = (j < nc) ? St.dG[((size_t)slot * 3 + a) * nv + i] : 0.0;
-          }
-#pragma unroll
-        for (int a = 0; a < 3; ++a) {
-          const int ix = a * nv + i;
-          const double qc = u0[a];
-          const double g = xo[a] - qc;
-          if (slot_new >= 0) {
-            const size_t cix = ((size_t)slot_new * 3 + a) * nv + i;
-            const double dg = g - u1[a];
-            St.dG[cix] = dg;
-            St.dQ[cix] = qc - u2[a];
-            // the new column enters the Gram sums at its position in the window
-#pragma unroll
-            for (int j = 0; j < M; ++j) {
-              int slot = head + j;
-              if (slot >= M) slot -= M;
-              if (j < nc && slot == slot_new) col[a][j] = dg;
-            }
-          }
-          St.g_last[ix] = g;
-          St.q_last[ix] = qc;
-#pragma unroll
-          for (int j = 0; j < M; ++j) {
-#pragma unroll
-            for (int l = 0; l < M; ++l)
-              if (l >= j) part[j * M + l] += col[a][j] * col[a][l];
-            part[M * M + j] += col[a][j] * g;
-          }
-        }
-      }
-      __shared__ double red[16 * NA];
-      block_sum<NA>(part, red);
-      if (threadIdx.x == 0) {
-        double* o = R.part + ((size_t)kRedAA * R.max_parts + bid) * kRedWidth;
-#pragma unroll
-        for (int j = 0; j < M; ++j) {
-#pragma unroll
-          for (int l = 0; l < M; ++l) o[j * M + l] = (j <= l) ? part[j * M + l] : part[l * M + j];
-          o[M * M + j] = part[M * M + j];
-        }
-      }
-    }
+    if constexpr (M > 0) aa_append<M>(St, R, nv, bid, my_row, xo, u0, u1, u2, aa);
   } else {
     double v3[3] = {0, 0, 0};
     if (my_row >= 0) {
@@ -968,7 +981,7 @@ __device__ __forceinline__ void b_bottom(VertArgs Vx, SolveArgs Sv, StepState St
       for (int a = 0; a < 3; ++a) {
         const int ix = a * nv + my_row;
         const double x = xo[a];
-        if (MODE == kModePCG) {
+        if (kPCG) {
           const double rn = u0[a] - alpha * u2[a];
           const double mn = u3[a] + alpha * u1[a];
           r_cur(A, k + 1)[ix] = rn;
@@ -990,7 +1003,7 @@ __device__ __forceinline__ void b_bottom(VertArgs Vx, SolveArgs Sv, StepState St
     }
     if (MODE == kModeFixed) {
       write_partial<3>(v3, R, kRedFix, bid);
-    } else {
+    } else if (MODE != kModePCGSolve) {
       // PCG sums of iteration k land in the parity slot read by iteration k + 1
       const int slot = (MODE == kModePCGInit) ? 0 : ((k + 1) & 1);
       write_partial<3>(v3, R, kRedRZ0 + slot, bid);
@@ -1002,6 +1015,140 @@ template <int MODE, int M>
 __global__ void __launch_bounds__(kBottomThreads) k_bottom(VertArgs Vx, SolveArgs Sv, StepState St, AdjState A, RedArgs R,
                                                    const double* __restrict__ rhs, double* __restrict__ out, int k) {
   b_bottom<MODE, M>(Vx, Sv, St, A, R, rhs, out, k, blockIdx.x);
+}
+
+
+// ---------------------------------------------------------------- contact corrections
+// The contact rows' correction of a solve, sum_c s_c a_{v_c}[row] per axis,
+// with s_c = lam_c n_c (forward, Eq. q_update) or u_c n_c (adjoint
+// projection); rows with s_c = 0 are skipped.  The row data sit in LDS.
+struct ContactLds {
+  double s[3 * kMaxContactRows];
+  int slot[kMaxContactRows];
+  int v[kMaxContactRows];
+};
+
+__device__ __forceinline__ void contact_lds_load(const ContactArgs& C, ContactLds& L) {
+  for (int c = threadIdx.x; c < C.K; c += blockDim.x) {
+    L.s[3 * c] = C.s[3 * c];
+    L.s[3 * c + 1] = C.s[3 * c + 1];
+    L.s[3 * c + 2] = C.s[3 * c + 2];
+    L.slot[c] = C.slot[c];
+    L.v[c] = C.v[c];
+  }
+}
+
+__device__ __forceinline__ void contact_correction(const ContactArgs& C, const ContactLds& L, int row, double (&x)[3]) {
+  const size_t nf = C.nf;
+  for (int c = 0; c < C.K; ++c) {
+    const double s0 = L.s[3 * c], s1 = L.s[3 * c + 1], s2 = L.s[3 * c + 2];
+    if (s0 == 0.0 && s1 == 0.0 && s2 == 0.0) continue;
+    const double a = C.cols[(size_t)L.slot[c] * nf + row];
+    x[0] += s0 * a;
+    x[1] += s1 * a;
+    x[2] += s2 * a;
+  }
+}
+
+// Forward: q^ += sum_c lam_c a_{v_c} n_c on every free row, then the Anderson
+// append of the corrected q^ (one thread per free row).
+template <int M>
+__global__ void __launch_bounds__(kBlock) k_contact_apply_fwd(VertArgs Vx, StepState St, RedArgs R, ContactArgs C,
+                                                              int k) {
+  __shared__ ContactLds L;
+  __shared__ int flag_s;
+  const int nv = Vx.nv, nf = Vx.nf;
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  const int my_row = i < nf ? i : -1;
+  double xo[3] = {0, 0, 0}, u0[3] = {0, 0, 0}, u1[3] = {0, 0, 0}, u2[3] = {0, 0, 0};
+  int aa[4] = {0, 0, 0, 0};
+  if (M > 0)
+#pragma unroll
+    for (int j = 0; j < 4; ++j) aa[j] = St.ctl[kCtlAA + 4 * (k & 1) + j];
+  if (my_row >= 0)
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+      const int ix = a * nv + my_row;
+      xo[a] = St.qhat[ix];
+      if (M > 0) {
+        u0[a] = St.q_cur[ix];
+        u1[a] = St.g_last[ix];
+        u2[a] = St.q_last[ix];
+      }
+    }
+  if (threadIdx.x == 0) flag_s = *St.done;
+  contact_lds_load(C, L);
+  __syncthreads();
+  if (flag_s) return;
+  if (my_row >= 0) {
+    contact_correction(C, L, my_row, xo);
+#pragma unroll
+    for (int a = 0; a < 3; ++a) St.qhat[a * nv + my_row] = xo[a];
+  }
+  if constexpr (M > 0) aa_append<M>(St, R, nv, blockIdx.x, my_row, xo, u0, u1, u2, aa);
+}
+
+// Adjoint: z = P r = A~^{-1} r - sum_c u_c a_{v_c} n_c (the solve already in
+// A.z), and the residual loses its constraint-force part, r <- r - J_A^T u,
+// so that A~ z = r holds again (the conjugate-gradient recurrences rely on
+// it; P J_A^T = 0 and J_A z = 0 leave every other quantity unchanged).  Then
+// the per-row work of the mode, as in the subdomain solve: PCG (r of
+// iteration k + 1 was written by the solve), PCG start (rhs = r0), fixed point.
+template <int MODE>
+__global__ void __launch_bounds__(kBlock) k_contact_apply_adj(VertArgs Vx, AdjState A, RedArgs R, ContactArgs C,
+                                                              const double* __restrict__ rhs, int k) {
+  __shared__ ContactLds L;
+  __shared__ int flag_s;
+  const int nv = Vx.nv, nf = Vx.nf;
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  const int my_row = i < nf ? i : -1;
+  double* rr = (MODE == kModePCG) ? r_cur(A, k + 1) : A.r0;
+  double z[3] = {0, 0, 0}, r[3] = {0, 0, 0}, m[3] = {0, 0, 0};
+  if (my_row >= 0)
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+      const int ix = a * nv + my_row;
+      z[a] = A.z[ix];
+      if (MODE != kModeFixed) r[a] = rr[ix];
+      m[a] = A.mu[ix];
+    }
+  if (threadIdx.x == 0) flag_s = *A.done;
+  contact_lds_load(C, L);
+  __syncthreads();
+  if (flag_s) return;
+  double v3[3] = {0, 0, 0};
+  if (my_row >= 0) {
+    double corr[3] = {0, 0, 0};
+    contact_correction(C, L, my_row, corr);
+    bool on_contact = false;
+    double f[3] = {0, 0, 0};
+    for (int c = 0; c < C.K; ++c)
+      if (L.v[c] == my_row) {
+        on_contact = true;
+        f[0] += L.s[3 * c];
+        f[1] += L.s[3 * c + 1];
+        f[2] += L.s[3 * c + 2];
+      }
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+      const int ix = a * nv + my_row;
+      const double x = z[a] - corr[a];
+      A.z[ix] = x;
+      if (MODE == kModeFixed) {
+        v3[0] += (x - m[a]) * (x - m[a]);
+        v3[1] += x * x;
+        A.mu[ix] = x;
+      } else {
+        const double rn = r[a] - f[a];
+        if (on_contact) rr[ix] = rn;
+        v3[0] += rn * x;
+        v3[1] += x * x;
+        v3[2] += m[a] * m[a];
+      }
+    }
+  }
+  if (MODE == kModeFixed) write_partial<3>(v3, R, kRedFix, blockIdx.x);
+  else write_partial<3>(v3, R, kRedRZ0 + ((MODE == kModePCGInit) ? 0 : ((k + 1) & 1)), blockIdx.x);
 }
 
 // ---------------------------------------------------------------- step epilogue
@@ -1639,6 +1786,27 @@ int bottom_blocks(int nB, int nT) {
   return (nB + rows - 1) / rows + (nT + kBottomThreads - 1) / kBottomThreads;
 }
 int tr_blocks(int ne, int nf) { return (ne + kBlock - 1) / kBlock + (nf + kBlock - 1) / kBlock; }
+int contact_apply_blocks(int nf) { return (nf + kBlock - 1) / kBlock; }
+
+void launch_contact_apply_fwd(const VertArgs& V, const StepState& St, const RedArgs& R, const ContactArgs& C, int k,
+                              hipStream_t s) {
+  const dim3 g(contact_apply_blocks(V.nf)), b(kBlock);
+  switch (St.m) {
+    case 1: launch_ext(k_contact_apply_fwd<1>, g, b, 0, s, V, St, R, C, k); break;
+    case 2: launch_ext(k_contact_apply_fwd<2>, g, b, 0, s, V, St, R, C, k); break;
+    case 3: launch_ext(k_contact_apply_fwd<3>, g, b, 0, s, V, St, R, C, k); break;
+    case 4: launch_ext(k_contact_apply_fwd<4>, g, b, 0, s, V, St, R, C, k); break;
+    case 5: launch_ext(k_contact_apply_fwd<5>, g, b, 0, s, V, St, R, C, k); break;
+    default: launch_ext(k_contact_apply_fwd<0>, g, b, 0, s, V, St, R, C, k); break;
+  }
+}
+void launch_contact_apply_adj(int mode, const VertArgs& V, const AdjState& A, const RedArgs& R,
+                              const ContactArgs& C, const double* rhs, int k, hipStream_t s) {
+  const dim3 g(contact_apply_blocks(V.nf)), b(kBlock);
+  if (mode == kModePCG) launch_ext(k_contact_apply_adj<kModePCG>, g, b, 0, s, V, A, R, C, rhs, k);
+  else if (mode == kModePCGInit) launch_ext(k_contact_apply_adj<kModePCGInit>, g, b, 0, s, V, A, R, C, rhs, k);
+  else launch_ext(k_contact_apply_adj<kModeFixed>, g, b, 0, s, V, A, R, C, rhs, k);
+}
 
 void launch_local(const ElemArgs& E, const StepState& St, const RedArgs& R, const double* q, int nv, int nf,
                   int k, int fwd, hipStream_t s) {
@@ -1710,6 +1878,7 @@ void launch_bottom(int mode, const VertArgs& V, const SolveArgs& S, const StepSt
       }
       break;
     case kModePCG: PD_BOTTOM(kModePCG, 0); break;
+    case kModePCGSolve: PD_BOTTOM(kModePCGSolve, 0); break;
     case kModePCGInit: PD_BOTTOM(kModePCGInit, 0); break;
     case kModeFixed: PD_BOTTOM(kModeFixed, 0); break;
     default: PD_BOTTOM(kModePlain, 0); break;

@@ -150,6 +150,25 @@ struct Scene {
   int fwd_start = 0;  // 0: q0 = q_t; 1: q0 = q_t + h v_t (when the caller passes no q0)
   double* ck_scratch = nullptr;  // 12 x nv (diagnostic K apply)
   KernelTimer kt;
+  // --- contact with static obstacles (off until obstacles are set)
+  bool contact_on = false;
+  int n_planes = 0, n_boxes = 0, c_kmax = 0;
+  double d_c = 0.0, fb_tol = 1e-10;
+  double* obs = nullptr;  // planes (4 each), then boxes (6 each)
+  // rows of the current forward step
+  int *c_v = nullptr, *c_slot = nullptr, *c_flags = nullptr;
+  double *c_n = nullptr, *c_g = nullptr, *c_lam = nullptr, *c_s = nullptr, *c_W = nullptr, *c_fb = nullptr;
+  // active rows of the current backward step and the inverse of their Delassus block
+  int *a_v = nullptr, *a_slot = nullptr;
+  double *a_n = nullptr, *a_s = nullptr, *a_Winv = nullptr;
+  // column cache: a_v = A~^{-1} e_v (free rows) for up to col_cap vertices
+  double* cols = nullptr;
+  int col_cap = 0, cols_used = 0;
+  std::vector<int> slot_of, vert_of_slot;
+  int* h_cbuf = nullptr;        // pinned: flags (4), vertex ids, slots
+  double* h_crec = nullptr;     // pinned: one checkpoint contact record
+  int c_last_K = 0, c_last_active = 0, c_cols_built = 0;
+  double c_last_fb = 0.0;
 };
 
 }  // namespace pdhot

@@ -113,6 +113,20 @@ double det3(const double* A) {
   return A[0] * (A[4] * A[8] - A[5] * A[7]) - A[1] * (A[3] * A[8] - A[5] * A[6]) + A[2] * (A[3] * A[7] - A[4] * A[6]);
 }
 
+void contact_free(Scene& S) {
+  dfree(S.obs); dfree(S.c_v); dfree(S.c_slot); dfree(S.c_flags); dfree(S.c_n); dfree(S.c_g); dfree(S.c_lam);
+  dfree(S.c_s); dfree(S.c_W); dfree(S.c_fb); dfree(S.a_v); dfree(S.a_slot); dfree(S.a_n); dfree(S.a_s);
+  dfree(S.a_Winv); dfree(S.cols);
+  if (S.h_cbuf) (void)hipHostFree(S.h_cbuf);
+  if (S.h_crec) (void)hipHostFree(S.h_crec);
+  S.h_cbuf = nullptr;
+  S.h_crec = nullptr;
+  S.contact_on = false;
+  S.col_cap = S.cols_used = 0;
+  S.slot_of.clear();
+  S.vert_of_slot.clear();
+}
+
 void free_device(Scene& S) {
   dfree(S.tv); dfree(S.tinc); dfree(S.Bm); dfree(S.wV); dfree(S.bV); dfree(S.muV); dfree(S.lamV);
   dfree(S.tet_orig); dfree(S.Vw); dfree(S.rw);
@@ -126,6 +140,7 @@ void free_device(Scene& S) {
   dfree(S.ctl); dfree(S.dstat); dfree(S.red_part); dfree(S.red_fin);
   dfree(S.jac); dfree(S.mu); dfree(S.r0); dfree(S.r1); dfree(S.z); dfree(S.p); dfree(S.Ap); dfree(S.wv);
   dfree(S.qbar); dfree(S.ck_scratch); dfree(S.mu_h1); dfree(S.mu_h2);
+  contact_free(S);
   if (S.hctl) (void)hipHostFree(S.hctl);
   if (S.hdstat) (void)hipHostFree(S.hdstat);
   S.hctl = nullptr;
@@ -382,7 +397,8 @@ void setup_scene(Scene& S, const pd_mesh_desc* mesh, const pd_material_desc* mat
   PD_HIP(hipMemset(S.mu, 0, V3 * sizeof(double)));
   PD_HIP(hipMemset(S.z, 0, V3 * sizeof(double)));
   // reduction sites sized for the widest producing kernel
-  S.red_max_parts = std::max({bottom_blocks(L.nB, L.nT), vert_group_blocks(nf), tr_blocks(ne, nf), 1});
+  S.red_max_parts = std::max({bottom_blocks(L.nB, L.nT), vert_group_blocks(nf), tr_blocks(ne, nf),
+                               contact_apply_blocks(nf), 1});
   S.red_part = dalloc<double>((size_t)kRedSites * S.red_max_parts * kRedWidth);
   S.red_fin = dalloc<double>((size_t)kRedSites * kFinStride);
   PD_HIP(hipMemset(S.red_part, 0, (size_t)kRedSites * S.red_max_parts * kRedWidth * sizeof(double)));
@@ -618,6 +634,10 @@ void factorize(Scene& S) {
   PD_HIP(hipDeviceSynchronize());
   S.stale = false;
   S.adj_hist = 0;
+  // cached contact columns belong to the old factor
+  for (int v : S.vert_of_slot) S.slot_of[v] = -1;
+  S.vert_of_slot.clear();
+  S.cols_used = 0;
 }
 
 AdjState adj_state(Scene& S) {
@@ -640,6 +660,146 @@ void solve_plain(Scene& S, const double* rhs, double* out, int* done, hipStream_
   PD_TIMED(S, kKEb, st, launch_Eb(kModePlain, V, A, T, Ad, R, rhs, 0, st));
   PD_TIMED(S, kKTop, st, launch_top(V, A, out, st));
   PD_TIMED(S, kKBottom, st, launch_bottom(kModePlain, V, A, T, Ad, R, rhs, out, 0, st));
+}
+
+
+// ---------------------------------------------------------------- contact
+constexpr int kErrContact = PD_ERR_CONTACT;
+
+ContactArgs contact_args(Scene& S, int K, bool adjoint) {
+  ContactArgs C;
+  C.K = K;
+  C.nf = S.L.nf;
+  C.v = adjoint ? S.a_v : S.c_v;
+  C.n = adjoint ? S.a_n : S.c_n;
+  C.g = S.c_g;
+  C.slot = adjoint ? S.a_slot : S.c_slot;
+  C.cols = S.cols;
+  C.W = adjoint ? S.a_Winv : S.c_W;
+  C.lam = S.c_lam;
+  C.s = adjoint ? S.a_s : S.c_s;
+  C.fb = S.c_fb;
+  C.flags = S.c_flags;
+  return C;
+}
+
+// Column a_v = A~^{-1} e_v of every listed vertex that the cache lacks (three
+// per three-right-hand-side solve); slots receive each entry's column slot.
+// A full cache is emptied first.
+void ensure_columns(Scene& S, const int* verts, int n, int* slots, hipStream_t st) {
+  std::vector<int> need;
+  auto collect = [&]() {
+    need.clear();
+    for (int c = 0; c < n; ++c) {
+      const int v = verts[c];
+      if (S.slot_of[v] == -1) {
+        S.slot_of[v] = -2;
+        need.push_back(v);
+      }
+    }
+  };
+  collect();
+  if (S.cols_used + (int)need.size() > S.col_cap) {
+    for (int v : need) S.slot_of[v] = -1;
+    for (int v : S.vert_of_slot) S.slot_of[v] = -1;
+    S.vert_of_slot.clear();
+    S.cols_used = 0;
+    collect();
+    if ((int)need.size() > S.col_cap) throw PdError{kErrContact, "contact vertices exceed the column cache"};
+  }
+  for (int v : need) {
+    S.slot_of[v] = S.cols_used++;
+    S.vert_of_slot.push_back(v);
+  }
+  const VertArgs V = vert_args(S);
+  const SolveArgs A = solve_args(S);
+  const RedArgs R = red_args(S);
+  StepState T = step_state(S);
+  T.done = nullptr;
+  const AdjState Ad = adj_state(S);
+  for (size_t j = 0; j < need.size(); j += 3) {
+    int vv[3] = {-1, -1, -1}, ss[3] = {-1, -1, -1};
+    for (int a = 0; a < 3 && j + a < need.size(); ++a) {
+      vv[a] = need[j + a];
+      ss[a] = S.slot_of[vv[a]];
+    }
+    launch_unit_rhs(S.nv, S.z, vv[0], vv[1], vv[2], st);
+    launch_Eb(kModePlain, V, A, T, Ad, R, S.z, 0, st);
+    launch_top(V, A, S.wv, st);
+    launch_bottom(kModePlain, V, A, T, Ad, R, S.z, S.wv, 0, st);
+    launch_store_cols(S.L.nf, S.nv, S.wv, S.cols, ss[0], ss[1], ss[2], st);
+  }
+  S.c_cols_built += (int)need.size();
+  for (int c = 0; c < n; ++c) slots[c] = S.slot_of[verts[c]];
+}
+
+// Candidate rows of this step (q_t, v_t already in library order), their
+// columns and the Delassus operator; returns the row count.
+int contact_rows(Scene& S, hipStream_t st) {
+  const VertArgs V = vert_args(S);
+  ObsArgs O;
+  O.n_planes = S.n_planes;
+  O.n_boxes = S.n_boxes;
+  O.planes = S.obs;
+  O.boxes = S.obs + 4 * S.n_planes;
+  O.d_c = S.d_c;
+  O.h = S.h;
+  launch_contact_detect(V, S.qt, S.vt, O, S.c_kmax, S.c_v, S.c_n, S.c_g, S.c_flags, st);
+  PD_HIP(hipMemcpyAsync(S.h_cbuf, S.c_flags, 4 * sizeof(int), hipMemcpyDeviceToHost, st));
+  PD_HIP(hipStreamSynchronize(st));
+  const int K = S.h_cbuf[0];
+  if (K > S.c_kmax)
+    throw PdError{kErrContact, "contact rows (" + std::to_string(K) + ") exceed max_contacts (" +
+                                   std::to_string(S.c_kmax) + ")"};
+  if (K == 0) return 0;
+  int* hv = S.h_cbuf + 4;
+  int* hs = hv + S.c_kmax;
+  PD_HIP(hipMemcpyAsync(hv, S.c_v, K * sizeof(int), hipMemcpyDeviceToHost, st));
+  PD_HIP(hipStreamSynchronize(st));
+  ensure_columns(S, hv, K, hs, st);
+  PD_HIP(hipMemcpyAsync(S.c_slot, hs, K * sizeof(int), hipMemcpyHostToDevice, st));
+  const ContactArgs C = contact_args(S, K, false);
+  launch_contact_W(C, S.c_W, st);
+  launch_contact_start(C, st);
+  PD_HIP(hipStreamSynchronize(st));
+  return K;
+}
+
+// Active rows of a checkpointed step (lam_c > 1e-10 max lam), their columns
+// and the inverse of their Delassus block; returns the active count.
+int contact_active(Scene& S, const double* ck, hipStream_t st) {
+  const int kmax = S.c_kmax;
+  const double* rec = ck + (size_t)kCheckpointVecs * 3 * S.nv;
+  PD_HIP(hipMemcpyAsync(S.h_crec, rec, (1 + 6 * (size_t)kmax) * sizeof(double), hipMemcpyDeviceToHost, st));
+  PD_HIP(hipStreamSynchronize(st));
+  const double* h = S.h_crec;
+  const int K = (int)h[0];
+  if (K < 0 || K > kmax) throw PdError{PD_ERR_INVALID_ARG, "checkpoint holds no valid contact record"};
+  double lmax = 0.0;
+  for (int c = 0; c < K; ++c) lmax = std::max(lmax, h[1 + 5 * kmax + c]);
+  std::vector<int> av;
+  std::vector<double> an;
+  for (int c = 0; c < K; ++c)
+    if (lmax > 0.0 && h[1 + 5 * kmax + c] > 1e-10 * lmax) {
+      av.push_back((int)h[1 + c]);
+      for (int a = 0; a < 3; ++a) an.push_back(h[1 + kmax + 3 * c + a]);
+    }
+  const int na = (int)av.size();
+  S.c_last_active = na;
+  if (na == 0) return 0;
+  if (na > kMaxNewtonRows) throw PdError{kErrContact, "active contact rows exceed the dense solve size"};
+  int* hs = S.h_cbuf + 4 + kmax;
+  ensure_columns(S, av.data(), na, hs, st);
+  PD_HIP(hipMemcpyAsync(S.a_v, av.data(), na * sizeof(int), hipMemcpyHostToDevice, st));
+  PD_HIP(hipMemcpyAsync(S.a_n, an.data(), 3 * na * sizeof(double), hipMemcpyHostToDevice, st));
+  PD_HIP(hipMemcpyAsync(S.a_slot, hs, na * sizeof(int), hipMemcpyHostToDevice, st));
+  launch_zero_int(S.c_flags + 2, 1, st);
+  const ContactArgs C = contact_args(S, na, true);
+  launch_contact_winv(C, S.a_Winv, st);
+  PD_HIP(hipMemcpyAsync(S.h_cbuf, S.c_flags, 4 * sizeof(int), hipMemcpyDeviceToHost, st));
+  PD_HIP(hipStreamSynchronize(st));
+  if (S.h_cbuf[2]) throw PdError{kErrContact, "Delassus block of the active rows is not positive definite"};
+  return na;
 }
 
 }  // namespace
@@ -798,7 +958,92 @@ int pd_scene_info(const pd_scene* scene, double* info, double* means) {
 }
 
 size_t pd_ckpt_bytes(const pd_scene* scene) {
-  return scene ? (size_t)kCheckpointVecs * 3 * (size_t)scene->S.nv * sizeof(double) : 0;
+  if (!scene) return 0;
+  const Scene& S = scene->S;
+  size_t n = (size_t)kCheckpointVecs * 3 * (size_t)S.nv;
+  if (S.contact_on) n += 1 + 6 * (size_t)S.c_kmax;
+  return n * sizeof(double);
+}
+
+int pd_scene_set_obstacles(pd_scene* scene, int n_planes, const double* planes, int n_boxes, const double* boxes,
+                           double d_c, int max_contacts, double fb_tol) {
+  if (!scene) {
+    pdhot::g_last_error = "null scene";
+    return PD_ERR_INVALID_ARG;
+  }
+  PD_TRY
+  Scene& S = scene->S;
+  if (n_planes < 0 || n_boxes < 0 || n_planes + n_boxes > kMaxObstacles)
+    throw PdError{PD_ERR_INVALID_ARG, "at most " + std::to_string(kMaxObstacles) + " obstacles"};
+  if ((n_planes > 0 && !planes) || (n_boxes > 0 && !boxes)) throw PdError{PD_ERR_INVALID_ARG, "null obstacle array"};
+  contact_free(S);
+  if (n_planes + n_boxes == 0) return PD_OK;
+  if (!(d_c > 0.0) || !(fb_tol > 0.0) || max_contacts < 1 || max_contacts > kMaxContactRows)
+    throw PdError{PD_ERR_INVALID_ARG, "need d_c > 0, fb_tol > 0 and 1 <= max_contacts <= " +
+                                          std::to_string(kMaxContactRows)};
+  std::vector<double> obs;
+  for (int i = 0; i < n_planes; ++i) {
+    const double* P = planes + 4 * i;
+    const double nn = std::sqrt(P[0] * P[0] + P[1] * P[1] + P[2] * P[2]);
+    if (!(std::fabs(nn - 1.0) <= 1e-12)) throw PdError{PD_ERR_INVALID_ARG, "plane normals must be unit vectors"};
+    obs.insert(obs.end(), P, P + 4);
+  }
+  for (int i = 0; i < n_boxes; ++i) {
+    const double* B = boxes + 6 * i;
+    if (!(B[0] < B[3] && B[1] < B[4] && B[2] < B[5])) throw PdError{PD_ERR_INVALID_ARG, "box needs lo < hi"};
+    obs.insert(obs.end(), B, B + 6);
+  }
+  const int kmax = max_contacts, nf = S.L.nf;
+  S.n_planes = n_planes;
+  S.n_boxes = n_boxes;
+  S.d_c = d_c;
+  S.fb_tol = fb_tol;
+  S.c_kmax = kmax;
+  S.obs = dalloc<double>(obs.size());
+  upload(S.obs, obs);
+  S.c_v = dalloc<int>(kmax); S.c_slot = dalloc<int>(kmax); S.c_flags = dalloc<int>(4);
+  S.c_n = dalloc<double>(3 * (size_t)kmax); S.c_g = dalloc<double>(kmax); S.c_lam = dalloc<double>(kmax);
+  S.c_s = dalloc<double>(3 * (size_t)kmax); S.c_W = dalloc<double>((size_t)kmax * kmax);
+  S.c_fb = dalloc<double>(2);
+  S.a_v = dalloc<int>(kMaxNewtonRows); S.a_slot = dalloc<int>(kMaxNewtonRows);
+  S.a_n = dalloc<double>(3 * kMaxNewtonRows); S.a_s = dalloc<double>(3 * kMaxNewtonRows);
+  S.a_Winv = dalloc<double>((size_t)kMaxNewtonRows * kMaxNewtonRows);
+  S.col_cap = 4 * kmax;
+  S.cols = dalloc<double>((size_t)S.col_cap * std::max(nf, 1));
+  S.cols_used = 0;
+  S.slot_of.assign(std::max(nf, 1), -1);
+  S.vert_of_slot.clear();
+  PD_HIP(hipHostMalloc((void**)&S.h_cbuf, (4 + 2 * (size_t)kmax) * sizeof(int)));
+  PD_HIP(hipHostMalloc((void**)&S.h_crec, (1 + 6 * (size_t)kmax) * sizeof(double)));
+  PD_HIP(hipMemset(S.c_fb, 0, 2 * sizeof(double)));
+  PD_HIP(hipMemset(S.c_flags, 0, 4 * sizeof(int)));
+  S.contact_on = true;
+  S.c_last_K = S.c_last_active = 0;
+  return PD_OK;
+  PD_CATCH
+}
+
+int pd_contact_rows(const pd_scene* scene, int* K, int32_t* vert, double* normals, double* offsets,
+                    double* lambda, int capacity) {
+  if (!scene || !K) {
+    pdhot::g_last_error = "null argument";
+    return PD_ERR_INVALID_ARG;
+  }
+  PD_TRY
+  const Scene& S = scene->S;
+  *K = S.contact_on ? S.c_last_K : 0;
+  const int n = std::min(*K, std::max(capacity, 0));
+  if (n > 0) {
+    std::vector<int> v(n);
+    PD_HIP(hipMemcpy(v.data(), S.c_v, n * sizeof(int), hipMemcpyDeviceToHost));
+    if (vert)
+      for (int c = 0; c < n; ++c) vert[c] = S.L.lib2orig[v[c]];
+    if (normals) PD_HIP(hipMemcpy(normals, S.c_n, 3 * n * sizeof(double), hipMemcpyDeviceToHost));
+    if (offsets) PD_HIP(hipMemcpy(offsets, S.c_g, n * sizeof(double), hipMemcpyDeviceToHost));
+    if (lambda) PD_HIP(hipMemcpy(lambda, S.c_lam, n * sizeof(double), hipMemcpyDeviceToHost));
+  }
+  return PD_OK;
+  PD_CATCH
 }
 
 int pd_step_forward(pd_scene* scene, const double* q_t, const double* v_t, const double* f_ext, const double* q0,
@@ -817,14 +1062,24 @@ int pd_step_forward(pd_scene* scene, const double* q_t, const double* v_t, const
   const ElemArgs E = elem_args(S);
   const VertArgs V = vert_args(S);
   const SolveArgs A = solve_args(S);
-  const StepState T = step_state(S);
+  StepState T = step_state(S);
   const AdjState Ad = adj_state(S);
-  const RedArgs R = red_args(S);
+  RedArgs R = red_args(S);
   // prologue: (1/h) B_beta q_t element terms, then q~, c, q^0
   launch_to_lib(V, q_t, S.qt, 0, st);
   launch_elem_GtG(E, S.qt, S.nv, S.bV, S.contrib, st);
   launch_prologue(V, q_t, v_t, f_ext, q0, S.fwd_start, T, st);
   launch_zero_int(S.ctl, kCtlSize, st);
+  // contact rows of this step (Sec. 4.7): with rows, every global solve is
+  // followed by the FB Newton solve and the column correction, which also
+  // appends the Anderson columns
+  const int K = S.contact_on ? contact_rows(S, st) : 0;
+  const ContactArgs C = contact_args(S, K, false);
+  if (K > 0) {
+    R.nparts[kRedAA] = contact_apply_blocks(V.nf);
+    T.fb = S.c_fb;
+    T.fb_tol = S.fb_tol;
+  }
   int k = 0;
   int chunk = S.iters_per_check > 0 ? S.iters_per_check : std::max(3, S.last_fwd_iters + 1);
   for (;;) {
@@ -834,7 +1089,13 @@ int pd_step_forward(pd_scene* scene, const double* q_t, const double* v_t, const
       PD_TIMED(S, kKGather, st, launch_gather_fwd(V, T, R, k, st));
       PD_TIMED(S, kKEb, st, launch_Eb(kModeFwd, V, A, T, Ad, R, nullptr, k, st));
       PD_TIMED(S, kKTop, st, launch_top(V, A, S.qhat, st));
-      PD_TIMED(S, kKBottom, st, launch_bottom(kModeFwd, V, A, T, Ad, R, nullptr, S.qhat, k, st));
+      if (K > 0) {
+        PD_TIMED(S, kKBottom, st, launch_bottom(kModePlain, V, A, T, Ad, R, S.b_cur, S.qhat, k, st));
+        launch_contact_fb(V, C, S.qhat, T.done, st);
+        launch_contact_apply_fwd(V, T, R, C, k, st);
+      } else {
+        PD_TIMED(S, kKBottom, st, launch_bottom(kModeFwd, V, A, T, Ad, R, nullptr, S.qhat, k, st));
+      }
     }
     PD_HIP(hipMemcpyAsync(S.hctl, S.ctl, kCtlSize * sizeof(int), hipMemcpyDeviceToHost, st));
     PD_HIP(hipStreamSynchronize(st));
@@ -843,10 +1104,27 @@ int pd_step_forward(pd_scene* scene, const double* q_t, const double* v_t, const
     chunk = S.iters_per_check > 0 ? S.iters_per_check : 2;
   }
   launch_epilogue(V, T, q_next, v_next, (double*)ckpt, st);
+  if (S.contact_on && ckpt)
+    launch_contact_ckpt(C, S.c_kmax, (double*)ckpt + (size_t)kCheckpointVecs * 3 * S.nv, st);
   PD_HIP(hipMemcpyAsync(S.hdstat, S.dstat, 8 * sizeof(double), hipMemcpyDeviceToHost, st));
   PD_HIP(hipMemcpyAsync(S.hctl, S.ctl, kCtlSize * sizeof(int), hipMemcpyDeviceToHost, st));
+  int n_active = 0;
+  double fb_res = 0.0;
+  if (K > 0) {
+    PD_HIP(hipMemcpyAsync(S.h_crec, S.c_lam, K * sizeof(double), hipMemcpyDeviceToHost, st));
+    PD_HIP(hipMemcpyAsync(S.h_crec + K, S.c_fb, 2 * sizeof(double), hipMemcpyDeviceToHost, st));
+    PD_HIP(hipMemcpyAsync(S.h_cbuf, S.c_flags, 4 * sizeof(int), hipMemcpyDeviceToHost, st));
+  }
   PD_HIP(hipStreamSynchronize(st));
   PD_HIP(hipGetLastError());
+  if (K > 0) {
+    for (int c = 0; c < K; ++c) n_active += S.h_crec[c] > 0.0;
+    fb_res = S.h_crec[K];
+    if (S.h_cbuf[1]) throw PdError{kErrContact, "FB Newton system exceeds the dense solve size"};
+  }
+  S.c_last_K = K;
+  S.c_last_active = n_active;
+  S.c_last_fb = fb_res;
   const int iters = S.hctl[kCtlIters], status = S.hctl[kCtlStatus];
   if (S.hctl[kCtlDone]) S.last_fwd_iters = iters;
   // launches that did work: local step and gather at k = 0..iters, the
@@ -863,6 +1141,9 @@ int pd_step_forward(pd_scene* scene, const double* q_t, const double* v_t, const
     stats->status = status;
     stats->newton_capped = S.hctl[kCtlNewton];
     for (int j = 0; j < 4; ++j) stats->gate[j] = S.hdstat[j];
+    stats->n_contacts = K;
+    stats->n_active = n_active;
+    stats->fb_res = fb_res;
   }
   if (!S.hctl[kCtlDone]) throw PdError{PD_ERR_HIP, "forward loop ended without a decision"};
   return status == 0 ? PD_OK : PD_NOT_CONVERGED;
@@ -870,12 +1151,19 @@ int pd_step_forward(pd_scene* scene, const double* q_t, const double* v_t, const
 }
 
 static void adjoint_solve(Scene& S, hipStream_t st, double tau_force, double* bstat_host, const double* ck,
-                          bool warm) {
+                          bool warm, int n_active) {
   const ElemArgs E = elem_args(S);
   const VertArgs V = vert_args(S);
   const SolveArgs Sv = solve_args(S);
   const AdjState Ad = adj_state(S);
-  const RedArgs R = red_args(S);
+  RedArgs R = red_args(S);
+  // with active contact rows every preconditioner solve is projected onto
+  // J_A mu = 0 and the per-row work moves to the correction kernel
+  const bool con = n_active > 0;
+  const ContactArgs C = contact_args(S, n_active, true);
+  if (con) {
+    R.nparts[kRedRZ0] = R.nparts[kRedRZ1] = R.nparts[kRedFix] = contact_apply_blocks(V.nf);
+  }
   StepState T = step_state(S);
   T.done = Ad.done;  // plain solves inside the adjoint stop with it
   launch_tr_partials(E, V, R, ck, st);
@@ -889,7 +1177,13 @@ static void adjoint_solve(Scene& S, hipStream_t st, double tau_force, double* bs
     }
     PD_TIMED(S, kKEb, st, launch_Eb(kModePlain, V, Sv, T, Ad, R, S.r0, 0, st));
     PD_TIMED(S, kKTop, st, launch_top(V, Sv, S.z, st));
-    PD_TIMED(S, kKBottom, st, launch_bottom(kModePCGInit, V, Sv, T, Ad, R, S.r0, S.z, 0, st));
+    if (con) {
+      PD_TIMED(S, kKBottom, st, launch_bottom(kModePlain, V, Sv, T, Ad, R, S.r0, S.z, 0, st));
+      launch_contact_proj(V, C, S.z, Ad.done, st);
+      launch_contact_apply_adj(kModePCGInit, V, Ad, R, C, S.r0, 0, st);
+    } else {
+      PD_TIMED(S, kKBottom, st, launch_bottom(kModePCGInit, V, Sv, T, Ad, R, S.r0, S.z, 0, st));
+    }
   }
   int it = 0;
   int chunk = std::max(4, S.last_adj_iters + 1);
@@ -901,13 +1195,25 @@ static void adjoint_solve(Scene& S, hipStream_t st, double tau_force, double* bs
         launch_adj_gather(kModePCG, V, Ad, R, it, st);
         PD_TIMED(S, kKEb, st, launch_Eb(kModePCG, V, Sv, T, Ad, R, nullptr, it, st));
         PD_TIMED(S, kKTop, st, launch_top(V, Sv, S.z, st));
-        PD_TIMED(S, kKBottom, st, launch_bottom(kModePCG, V, Sv, T, Ad, R, nullptr, S.z, it, st));
+        if (con) {
+          PD_TIMED(S, kKBottom, st, launch_bottom(kModePCGSolve, V, Sv, T, Ad, R, nullptr, S.z, it, st));
+          launch_contact_proj(V, C, S.z, Ad.done, st);
+          launch_contact_apply_adj(kModePCG, V, Ad, R, C, nullptr, it, st);
+        } else {
+          PD_TIMED(S, kKBottom, st, launch_bottom(kModePCG, V, Sv, T, Ad, R, nullptr, S.z, it, st));
+        }
       } else {
         PD_TIMED(S, kKApplyK, st, launch_apply_K(kModeFixed, E, V, Ad, R, S.jac, nullptr, it, st));
         launch_adj_gather(kModeFixed, V, Ad, R, it, st);
         PD_TIMED(S, kKEb, st, launch_Eb(kModePlain, V, Sv, T, Ad, R, S.r0, it, st));
         PD_TIMED(S, kKTop, st, launch_top(V, Sv, S.z, st));
-        PD_TIMED(S, kKBottom, st, launch_bottom(kModeFixed, V, Sv, T, Ad, R, S.r0, S.z, it, st));
+        if (con) {
+          PD_TIMED(S, kKBottom, st, launch_bottom(kModePlain, V, Sv, T, Ad, R, S.r0, S.z, it, st));
+          launch_contact_proj(V, C, S.z, Ad.done, st);
+          launch_contact_apply_adj(kModeFixed, V, Ad, R, C, S.r0, it, st);
+        } else {
+          PD_TIMED(S, kKBottom, st, launch_bottom(kModeFixed, V, Sv, T, Ad, R, S.r0, S.z, it, st));
+        }
       }
     }
     PD_HIP(hipMemcpyAsync(S.hctl, S.ctl, kCtlTotal * sizeof(int), hipMemcpyDeviceToHost, st));
@@ -949,11 +1255,15 @@ int pd_step_backward(pd_scene* scene, const void* ckpt, const double* gq_next, c
   const VertArgs V = vert_args(S);
   const AdjState Ad = adj_state(S);
   const double* ck = (const double*)ckpt;
-  // adjoint start: zero, or from the last solutions of this backward sweep
-  const int warm = std::min(S.adj_warm, S.adj_hist);
+  // active contact rows of the step (their columns are built before the
+  // adjoint buffers are set up: the builder uses them as scratch)
+  const int n_active = S.contact_on ? contact_active(S, ck, st) : 0;
+  // adjoint start: zero, or from the last solutions of this backward sweep;
+  // with active rows the start must satisfy J_A mu = 0, so it is zero
+  const int warm = n_active > 0 ? 0 : std::min(S.adj_warm, S.adj_hist);
   launch_bwd_prologue(V, Ad, gq_next, gv_next, warm, S.mu_h1, S.mu_h2, st);
   double bs[5] = {0, 0, 0, 0, 0};
-  adjoint_solve(S, st, -1.0, bs, ck, warm > 0);
+  adjoint_solve(S, st, -1.0, bs, ck, warm > 0, n_active);
   if (S.adj_warm > 0) {
     PD_HIP(hipMemcpyAsync(S.mu_h2, S.mu, 3 * (size_t)S.nv * sizeof(double), hipMemcpyDeviceToDevice, st));
     std::swap(S.mu_h1, S.mu_h2);
@@ -969,6 +1279,7 @@ int pd_step_backward(pd_scene* scene, const void* ckpt, const double* gq_next, c
     stats->status = status;
     stats->rho = bs[0]; stats->tau = bs[1]; stats->dphi_act = bs[2]; stats->dphi_mod = bs[3];
     stats->residual = bs[4];
+    stats->n_active = n_active;
   }
   return status == 0 ? PD_OK : PD_NOT_CONVERGED;
   PD_CATCH
@@ -1242,6 +1553,7 @@ int pd_batch_create(pd_scene* const* scenes, int n, pd_batch** out) {
       if (!scenes[s]) throw PdError{PD_ERR_INVALID_ARG, "null scene in batch"};
       if (scenes[s]->S.stale) throw PdError{PD_ERR_STALE_FACTOR, "scene factor is stale"};
       if (scenes[s]->S.adj_method != 0) throw PdError{PD_ERR_INVALID_ARG, "batches run the PCG adjoint"};
+      if (scenes[s]->S.contact_on) throw PdError{PD_ERR_INVALID_ARG, "batched scenes run without obstacles"};
       B->scenes.push_back(scenes[s]);
     }
     batch_bundles(*B);
@@ -1344,6 +1656,9 @@ int pd_batch_step_forward(pd_batch* B, const double* const* q_t, const double* c
       stats[s].status = c[kCtlStatus];
       stats[s].newton_capped = c[kCtlNewton];
       for (int j = 0; j < 4; ++j) stats[s].gate[j] = B->hdstat[s * 32 + j];
+      stats[s].n_contacts = 0;
+      stats[s].n_active = 0;
+      stats[s].fb_res = 0.0;
     }
     if (!c[kCtlDone]) throw PdError{PD_ERR_HIP, "batched forward loop ended without a decision"};
     worst = std::max(worst, c[kCtlStatus]);
@@ -1429,6 +1744,8 @@ int pd_batch_step_backward(pd_batch* B, const void* const* ckpt, const double* c
       stats[s].status = c[kCtlAdj + 1];
       stats[s].rho = d[4]; stats[s].tau = d[5]; stats[s].dphi_act = d[6]; stats[s].dphi_mod = d[7];
       stats[s].residual = d[16];
+      stats[s].n_active = 0;
+      stats[s].pad = 0;
     }
     worst = std::max(worst, c[kCtlAdj + 1]);
     most = std::max(most, c[kCtlAdj]);

@@ -45,6 +45,9 @@ def parse():
     ap.add_argument("--train-epochs", type=int, default=16)
     ap.add_argument("--batch-scenes", type=int, default=64, help="scenes of --config batch")
     ap.add_argument("--tune-cache", default="", help="autotuner cache file of --config batch")
+    ap.add_argument("--drop-res", type=int, default=27, help="cells along the blob of --config drop (27: 28k tets)")
+    ap.add_argument("--copy-probe", action="store_true",
+                    help="only copy a 64 MiB device buffer 3 times (calibrates the HBM byte counters) and exit")
     return ap.parse_args()
 
 
@@ -76,6 +79,7 @@ def rollout_fwd_bwd(g, sc, K, torch, dev, net=None, logw=None):
     inside the timed region)."""
     q = dev(sc.q0())
     v = dev(sc.v0())
+    g.contact_hist, g.active_hist = [], []
     forces = [dev(sc.f_ext(t)) for t in range(K)]
     ckpts = [g.new_ckpt() for _ in range(K)]
     qs = [torch.empty_like(q) for _ in range(K + 1)]
@@ -94,6 +98,8 @@ def rollout_fwd_bwd(g, sc, K, torch, dev, net=None, logw=None):
             net.forward(qs[t], vs[max(t - 1, 0)], vs[t], forces[t], logw, q0=q0)
         _, _, st = g.step_forward(qs[t], vs[t], forces[t], q0=q0, q_next=qs[t + 1], v_next=vs[t + 1], ckpt=ckpts[t])
         fiters.append(st["iters"])
+        g.contact_hist.append(st["n_contacts"])
+        g.active_hist.append(st["n_active"])
     # loss = |mean(q_K) - target|^2 (the gradient is formed on the device)
     c = qs[K].mean(dim=0)
     gq = (2.0 * (c - target) / sc.n_v).expand_as(qs[K]).contiguous()
@@ -112,12 +118,17 @@ def rollout_fwd_bwd(g, sc, K, torch, dev, net=None, logw=None):
 def cpu_baseline(sc, steps):
     """The FP64 CPU oracle (serial C) on the first `steps` steps of the same rollout."""
     import oracle as O
+    from paper_2605_14526_amd import scenes
     t0 = time.perf_counter()
     osc = O.OracleScene(sc)
-    q, v, ck, _ = O.rollout(osc, steps)
-    from paper_2605_14526_amd import scenes
-    _, gq = scenes.centroid_loss(q, sc.target_centroid)
-    O.rollout_backward(osc, ck, gq, np.zeros_like(gq))
+    if sc.obstacles:
+        q, v, ck, _ = O.rollout_contact(osc, steps)
+        _, gq = scenes.centroid_loss(q, sc.target_centroid)
+        O.rollout_backward_contact(osc, ck, gq, np.zeros_like(gq))
+    else:
+        q, v, ck, _ = O.rollout(osc, steps)
+        _, gq = scenes.centroid_loss(q, sc.target_centroid)
+        O.rollout_backward(osc, ck, gq, np.zeros_like(gq))
     t1 = time.perf_counter()
     return t1 - t0
 
@@ -184,6 +195,16 @@ def main():
               file=sys.stderr)
         sys.exit(2)
     import torch
+    if args.copy_probe:
+        n = 8 * 1024 * 1024
+        x = torch.randn(n, dtype=torch.float64, device="cuda")
+        y = torch.empty_like(x)
+        torch.cuda.synchronize()
+        for _ in range(3):
+            y.copy_(x)
+        torch.cuda.synchronize()
+        print(f"[bench] copied 3 x {n * 8 >> 20} MiB", file=sys.stderr, flush=True)
+        return
     ensure_built()
     if args.config == "batch":
         bench_batch(args, torch)
@@ -191,7 +212,8 @@ def main():
     from paper_2605_14526_amd import scenes
     from paper_2605_14526_amd.binding import Scene
 
-    sc = scenes.config(args.config)
+    drop = args.config == "drop"
+    sc = scenes.drop_blob(res=args.drop_res) if drop else scenes.config(args.config)
     dev = lambda a: torch.tensor(np.ascontiguousarray(a), dtype=torch.float64, device="cuda")  # noqa: E731
     # adjoint: extrapolated start from the sweep's previous solutions (runs to 1e-6 either way)
     g = Scene.from_scene(sc, eps_adj=1e-6, max_sub=args.max_sub, adj_warm=2)
@@ -211,6 +233,9 @@ def main():
     assert torch.isfinite(g_logE).all()
     print(f"[bench] timed {args.steps} fwd+bwd steps in {dt:.4f} s; fwd iters/step {np.mean(fiters):.2f}, "
           f"adjoint iters/step {np.mean(biters):.2f}", file=sys.stderr, flush=True)
+    if drop:
+        print(f"[bench] contact rows/step {np.mean(g.contact_hist):.1f}, max {max(g.contact_hist)}; active max "
+              f"{max(g.active_hist)}", file=sys.stderr, flush=True)
     value = args.steps / dt
     # roofline of the timed kernel: algorithmic bytes of the launches that did
     # work over the summed launch durations
@@ -224,14 +249,21 @@ def main():
     out = {"metric": METRIC, "value": round(value, 3), "unit": "steps/s", "n_gpus": 1, "steps": args.steps,
            "warmup": args.warmup, "ms_per_step": round(1000.0 * dt / args.steps, 4), "higher_is_better": True,
            "scaling": "weak", "vs_baseline": None, "dtype": "f64", "data": "synthetic",
-           "config": {"workload": f"{sc.name}: 40x10x10 cubes, {sc.n_e} tets, {sc.n_v} verts, two-phase E 1e4/1e6, "
-                                  f"nu 0.49, h {sc.h}, rollout of {args.steps} steps, AA window {sc.aa_window}, "
-                                  "gate and adjoint 1e-6, plain q0 = q_t, adjoint start extrapolated",
+           "config": {"workload": (f"{sc.name}: voxelised blob of 6 spheres, {sc.n_e} tets, {sc.n_v} verts, shell "
+                                   f"E 1e6 over interior 1e4, nu 0.49, h {sc.h}, dropped at 1 m/s onto the ground "
+                                   f"plane and a box, frictionless contact, rollout of {args.steps} steps, "
+                                   "gate, FB residual 1e-10 and adjoint 1e-6") if drop else
+                                  (f"{sc.name}: 40x10x10 cubes, {sc.n_e} tets, {sc.n_v} verts, two-phase E 1e4/1e6, "
+                                   f"nu 0.49, h {sc.h}, rollout of {args.steps} steps, AA window {sc.aa_window}, "
+                                   "gate and adjoint 1e-6, plain q0 = q_t, adjoint start extrapolated"),
                       "fwd_iters_per_step": round(float(np.mean(fiters)), 3),
                       "adj_iters_per_step": round(float(np.mean(biters)), 3),
                       "n_subdomains": int(info["n_subdomains"]), "n_interface": int(info["n_interface"])},
            "roofline": roof}
-    if not args.no_warm_run:
+    if drop:
+        out["config"]["contact_rows_per_step"] = round(float(np.mean(g.contact_hist)), 2)
+        out["config"]["max_active_rows"] = int(max(g.active_hist))
+    if not args.no_warm_run and not drop:
         out["warm_started"] = {}
         # the same rollout with the inertial first iterate q0 = q_t + h v_t
         gw = Scene.from_scene(sc, eps_adj=1e-6, max_sub=args.max_sub, adj_warm=2, fwd_start=1)

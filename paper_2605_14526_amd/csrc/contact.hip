@@ -385,6 +385,138 @@ __global__ void __launch_bounds__(kContactThreads) k_contact_fb(VertArgs Vx, Con
   }
 }
 
+
+// The same Newton for at most 64 rows, one row per lane of a single wave:
+// the FB values, the active compaction (ballot), the dense system in LDS, its
+// Cholesky (right-looking, each lane updating its own row) and both
+// substitutions (pivots broadcast by shuffles) need no workgroup barrier
+// beyond the single wave's own.
+__global__ void __launch_bounds__(64) k_contact_fb_wave(VertArgs Vx, ContactArgs C, const double* __restrict__ qhat,
+                                                        const int* __restrict__ done) {
+  __shared__ double M[64 * 65];  // row i of the Newton matrix at M[i * 65], rhs in column 64
+  __shared__ double lam_s[64];
+  const int lane = threadIdx.x;
+  const int K = C.K, nv = Vx.nv;
+  const bool row = lane < K;
+  int flag = done ? *done : 0;
+  double q0 = 0, q1 = 0, q2 = 0, n0 = 0, n1 = 0, n2 = 0, g = 0, lam = 0;
+  if (row) {
+    const int v = C.v[lane];
+    q0 = qhat[v];
+    q1 = qhat[nv + v];
+    q2 = qhat[2 * nv + v];
+    n0 = C.n[3 * lane];
+    n1 = C.n[3 * lane + 1];
+    n2 = C.n[3 * lane + 2];
+    g = C.g[lane];
+    lam = C.lam[lane];
+  }
+  flag = __shfl(flag, 0, 64);
+  if (flag) return;
+  const double dfree = n0 * q0 + n1 * q1 + n2 * q2 - g;
+  const double* Wr = C.W + (size_t)(row ? lane : 0) * K;
+  double phi = 0.0, om = 0.0, E = 0.0;
+  auto evaluate = [&]() {
+    lam_s[lane] = lam;
+    __syncthreads();
+    double delta = dfree;
+    if (row)
+      for (int d = 0; d < K; ++d) delta += Wr[d] * lam_s[d];
+    double mx = 0.0;
+    if (row) {
+      const double r = Wr[lane], a = delta, b = r * lam;
+      const double sq = sqrt(a * a + b * b);
+      if (sq == 0.0) {
+        phi = 0.0;
+        om = 1.0 - 1.0 / sqrt(2.0);
+        E = r * (1.0 - 1.0 / sqrt(2.0));
+      } else {
+        phi = a + b - sq;
+        om = 1.0 - a / sq;
+        E = r * (1.0 - b / sq);
+      }
+      mx = fabs(phi);
+    }
+    __syncthreads();
+    return wmax(mx);
+  };
+  double res = evaluate();
+  int it = 0, fail = 0;
+  for (; it < kFBMaxIter && res > kFBTol; ++it) {
+    const bool a_on = row && om > kOmegaMin;
+    if (row && !a_on) lam = 0.0;
+    const unsigned long long bal = __ballot(a_on);
+    const int na = __popcll(bal);
+    const int pos = a_on ? __popcll(bal & ((1ull << lane) - 1ull)) : -1;
+    // row pos of the system: W restricted to the active rows, + E / omega on the diagonal, rhs -phi / omega
+    if (a_on) {
+      double* Mi = M + pos * 65;
+      unsigned long long rest = bal;
+      int j = 0;
+      while (rest) {
+        const int d = __ffsll((long long)rest) - 1;
+        rest &= rest - 1ull;
+        Mi[j] = Wr[d] + (d == lane ? E / om : 0.0);
+        ++j;
+      }
+      Mi[64] = -phi / om;
+    }
+    __syncthreads();
+    // Cholesky, lane i owns row i; the rhs is eliminated alongside
+    bool ok = true;
+    for (int j = 0; j < na; ++j) {
+      const double piv = M[j * 65 + j];
+      if (!(piv > 0.0)) {
+        ok = false;
+        break;
+      }
+      const double dj = sqrt(piv);
+      __syncthreads();
+      if (lane == j) {
+        M[j * 65 + j] = dj;
+        M[j * 65 + 64] /= dj;
+      }
+      if (lane > j && lane < na) M[lane * 65 + j] /= dj;
+      __syncthreads();
+      if (lane > j && lane < na) {
+        const double lij = M[lane * 65 + j];
+        for (int l = j + 1; l <= lane; ++l) M[lane * 65 + l] -= lij * M[l * 65 + j];
+        M[lane * 65 + 64] -= lij * M[j * 65 + 64];
+      }
+      __syncthreads();
+    }
+    if (!ok) {
+      fail = 1;
+      break;
+    }
+    // back substitution L^T x = y (y in column 64)
+    double y = (lane < na) ? M[lane * 65 + 64] : 0.0;
+    for (int i = na - 1; i >= 0; --i) {
+      const double xi = __shfl(y, i, 64) / M[i * 65 + i];
+      if (lane == i) y = xi;
+      if (lane < i) y -= M[i * 65 + lane] * xi;
+    }
+    // dlam of active row pos sits in lane pos
+    const double dl = __shfl(y, pos < 0 ? 0 : pos, 64);
+    if (a_on) {
+      const double l = lam + dl;
+      lam = l > 0.0 ? l : 0.0;
+    }
+    res = evaluate();
+  }
+  if (row) {
+    C.lam[lane] = lam;
+    C.s[3 * lane] = lam * n0;
+    C.s[3 * lane + 1] = lam * n1;
+    C.s[3 * lane + 2] = lam * n2;
+  }
+  if (lane == 0) {
+    C.fb[0] = res;
+    C.fb[1] = (double)it;
+    if (fail) C.flags[2] = 1;
+  }
+}
+
 // ---------------------------------------------------------------- adjoint
 // Inverse of W_AA (the active rows, K = n_active here) by Cholesky in LDS and
 // one substitution pair per column (one thread per column).
@@ -486,7 +618,8 @@ void launch_contact_start(const ContactArgs& C, hipStream_t s) {
   hipLaunchKernelGGL(k_contact_start, dim3((std::max(C.K, 1) + kBlock - 1) / kBlock), dim3(kBlock), 0, s, C);
 }
 void launch_contact_fb(const VertArgs& V, const ContactArgs& C, const double* qhat, const int* done, hipStream_t s) {
-  hipLaunchKernelGGL(k_contact_fb, dim3(1), dim3(kContactThreads), 0, s, V, C, qhat, done);
+  if (C.K <= 64) hipLaunchKernelGGL(k_contact_fb_wave, dim3(1), dim3(64), 0, s, V, C, qhat, done);
+  else hipLaunchKernelGGL(k_contact_fb, dim3(1), dim3(kContactThreads), 0, s, V, C, qhat, done);
 }
 void launch_contact_winv(const ContactArgs& C, double* Winv, hipStream_t s) {
   hipLaunchKernelGGL(k_contact_winv, dim3(1), dim3(kContactThreads), 0, s, C, Winv);

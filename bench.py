@@ -263,7 +263,7 @@ def main():
     if drop:
         out["config"]["contact_rows_per_step"] = round(float(np.mean(g.contact_hist)), 2)
         out["config"]["max_active_rows"] = int(max(g.active_hist))
-    if not args.no_warm_run and not drop:
+    if not args.no_warm_run:
         out["warm_started"] = {}
         # the same rollout with the inertial first iterate q0 = q_t + h v_t
         gw = Scene.from_scene(sc, eps_adj=1e-6, max_sub=args.max_sub, adj_warm=2, fwd_start=1)
@@ -276,9 +276,13 @@ def main():
                                            "adj_iters_per_step": round(float(np.mean(bw)), 3),
                                            "start": "q0 = q_t + h v_t"}
         print(f"[bench] inertial start: {args.steps / dtw:.1f} steps/s", file=sys.stderr, flush=True)
-        # the learned start: a network trained here, on the GPU, on plain rollouts of other beams
+        # the learned start: a network trained here, on the GPU, on plain rollouts of other members of the
+        # scene's family (other beams; drops of the same blob with other initial velocities)
         from paper_2605_14526_amd import warmstart
-        fam = lambda k: scenes.hetero_beam_family(k, steps=args.steps)  # noqa: E731
+        if drop:
+            fam = lambda k: scenes.drop_family(k, res=args.drop_res, steps=100)  # noqa: E731
+        else:
+            fam = lambda k: scenes.hetero_beam_family(k, steps=args.steps)  # noqa: E731
         net, hist, tsec, nsamp = warmstart.train_for(fam, args.train_scenes, 100, args.train_epochs, torch, seed=1,
                                                      edge_weight=LEARNED_EDGE_WEIGHT)
         logw = torch.tensor(g.vertex_logw(), dtype=torch.float64, device="cuda")
@@ -289,7 +293,9 @@ def main():
                                           "ms_per_step": round(1000.0 * dtl / args.steps, 4),
                                           "fwd_iters_per_step": round(float(np.mean(fl)), 3),
                                           "adj_iters_per_step": round(float(np.mean(bl)), 3),
-                                          "start": "message-passing network (BF16 matrix cores), inference timed",
+                                          "start": "message-passing network (BF16 matrix cores), inference timed, "
+                                                   "trained on " + ("drops of the same blob with other initial "
+                                                                    "velocities" if drop else "other beams"),
                                           "train": {"scenes": args.train_scenes, "samples": nsamp,
                                                     "epochs": args.train_epochs, "seconds": round(tsec, 2),
                                                     "final_loss": hist[-1]}}

@@ -744,25 +744,42 @@ __global__ void __launch_bounds__(kBlock) k_Eb(VertArgs Vx, SolveArgs Sv, StepSt
 // vectors read by the subdomain solve.  There is no done test: once a loop has
 // stopped, k_Eb leaves r_T unchanged, so this kernel rewrites the same values.
 __device__ __forceinline__ void b_top(VertArgs Vx, SolveArgs Sv, double* __restrict__ out, int bid) {
+  // r_T is read by every row: the block stages it in LDS tile by tile, so it
+  // crosses L2 once per block instead of once per row
+  constexpr int kTile = 2048;
+  __shared__ double rs[3 * kTile];
   const int lane = threadIdx.x & 63;
   const int row = (bid * blockDim.x + threadIdx.x) >> 6;
   const int nT = Sv.nT;
-  if (row >= nT) return;
-  const ERow er = Sv.erow[row];
+  const bool have = row < nT;
+  ERow er = {0, 0, 0};
   Cpl cd = {0, 0, 0, 0};
-  if (lane < kMaxCoup) cd = Sv.cpl[row * kMaxCoup + lane];
-  const double* __restrict__ Zi = Sv.Z + (size_t)row * nT;
-  const double* __restrict__ r0 = Sv.rT;
-  const double* __restrict__ r1 = Sv.rT + nT;
-  const double* __restrict__ r2 = Sv.rT + 2 * nT;
-  double a0 = 0, a1 = 0, a2 = 0;
-#pragma unroll 8
-  for (int j = lane; j < nT; j += 64) {
-    const double z = Zi[j];
-    a0 += z * r0[j];
-    a1 += z * r1[j];
-    a2 += z * r2[j];
+  if (have) {
+    er = Sv.erow[row];
+    if (lane < kMaxCoup) cd = Sv.cpl[row * kMaxCoup + lane];
   }
+  const double* __restrict__ Zi = Sv.Z + (size_t)(have ? row : 0) * nT;
+  double a0 = 0, a1 = 0, a2 = 0;
+  for (int t0 = 0; t0 < nT; t0 += kTile) {
+    const int tl = min(kTile, nT - t0);
+    __syncthreads();
+    for (int i = threadIdx.x; i < tl; i += blockDim.x) {
+      rs[i] = Sv.rT[t0 + i];
+      rs[kTile + i] = Sv.rT[nT + t0 + i];
+      rs[2 * kTile + i] = Sv.rT[2 * nT + t0 + i];
+    }
+    __syncthreads();
+    if (have) {
+#pragma unroll 8
+      for (int j = lane; j < tl; j += 64) {
+        const double z = Zi[t0 + j];
+        a0 += z * rs[j];
+        a1 += z * rs[kTile + j];
+        a2 += z * rs[2 * kTile + j];
+      }
+    }
+  }
+  if (!have) return;
   a0 = wave_sum(a0);
   a1 = wave_sum(a1);
   a2 = wave_sum(a2);

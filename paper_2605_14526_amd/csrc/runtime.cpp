@@ -10,6 +10,7 @@
 #include <new>
 #include <stdexcept>
 #include <string>
+#include <thread>
 #include <vector>
 
 #include "../../include/pdhot.h"
@@ -104,6 +105,116 @@ bool spd_inverse(std::vector<double>& A, int n) {
       for (int j = 0; j <= i; ++j) Ai[j] += c * Wk[j];
     }
   }
+  for (int i = 0; i < n; ++i)
+    for (int j = i + 1; j < n; ++j) A[(size_t)i * n + j] = A[(size_t)j * n + i];
+  return true;
+}
+
+// Host threads for the factorization: fn(t) for t = 0 .. T-1 with static
+// work splits inside fn, so results do not depend on scheduling.
+int host_threads() {
+  static const int n = [] {
+    const unsigned hw = std::thread::hardware_concurrency();
+    return (int)std::max(1u, std::min(hw, 16u));
+  }();
+  return n;
+}
+
+template <class F>
+void run_threads(int T, const F& fn) {
+  if (T <= 1) {
+    fn(0);
+    return;
+  }
+  std::vector<std::thread> th;
+  th.reserve(T - 1);
+  for (int t = 1; t < T; ++t) th.emplace_back([&fn, t] { fn(t); });
+  fn(0);
+  for (auto& x : th) x.join();
+}
+
+// Threaded inverse of a large SPD matrix (row-major, full): blocked
+// right-looking Cholesky A = L L^T (panel rows and trailing rows split over
+// threads), W = L^{-1} column by column, A^{-1} = W^T W row by row.
+bool spd_inverse_threaded(std::vector<double>& A, int n) {
+  const int T = host_threads();
+  if (n < 512 || T == 1) return spd_inverse(A, n);
+  constexpr int kB = 64;
+  std::vector<double>& L = A;  // lower triangle in place
+  bool ok = true;
+  for (int k0 = 0; k0 < n && ok; k0 += kB) {
+    const int k1 = std::min(k0 + kB, n);
+    // diagonal block
+    for (int j = k0; j < k1 && ok; ++j) {
+      double* Lj = &L[(size_t)j * n];
+      double d = Lj[j];
+      for (int k = k0; k < j; ++k) d -= Lj[k] * Lj[k];
+      if (!(d > 0.0) || !std::isfinite(d)) {
+        ok = false;
+        break;
+      }
+      d = std::sqrt(d);
+      Lj[j] = d;
+      for (int i = j + 1; i < k1; ++i) {
+        double* Li = &L[(size_t)i * n];
+        double sum = Li[j];
+        for (int k = k0; k < j; ++k) sum -= Li[k] * Lj[k];
+        Li[j] = sum / d;
+      }
+    }
+    if (!ok) break;
+    // panel rows below the block, then the trailing update, rows split over threads
+    run_threads(T, [&](int t) {
+      for (int i = k1 + t; i < n; i += T) {
+        double* Li = &L[(size_t)i * n];
+        for (int j = k0; j < k1; ++j) {
+          const double* Lj = &L[(size_t)j * n];
+          double sum = Li[j];
+          for (int k = k0; k < j; ++k) sum -= Li[k] * Lj[k];
+          Li[j] = sum / Lj[j];
+        }
+      }
+    });
+    run_threads(T, [&](int t) {
+      for (int i = k1 + t; i < n; i += T) {
+        double* Li = &L[(size_t)i * n];
+        for (int j = k1; j <= i; ++j) {
+          const double* Lj = &L[(size_t)j * n];
+          double sum = 0.0;
+          for (int k = k0; k < k1; ++k) sum += Li[k] * Lj[k];
+          Li[j] -= sum;
+        }
+      }
+    });
+  }
+  if (!ok) return false;
+  // W = L^{-1}, stored by columns: Wc[j][i] = W_ij (i >= j)
+  std::vector<double> Wc((size_t)n * n, 0.0);
+  run_threads(T, [&](int t) {
+    for (int j = t; j < n; j += T) {
+      double* y = &Wc[(size_t)j * n];
+      y[j] = 1.0 / L[(size_t)j * n + j];
+      for (int i = j + 1; i < n; ++i) {
+        const double* Li = &L[(size_t)i * n];
+        double sum = 0.0;
+        for (int k = j; k < i; ++k) sum += Li[k] * y[k];
+        y[i] = -sum / Li[i];
+      }
+    }
+  });
+  // A^{-1}_ij = sum_{k >= max(i, j)} W_ki W_kj
+  run_threads(T, [&](int t) {
+    for (int i = t; i < n; i += T) {
+      const double* wi = &Wc[(size_t)i * n];
+      double* Ai = &A[(size_t)i * n];
+      for (int j = 0; j <= i; ++j) {
+        const double* wj = &Wc[(size_t)j * n];
+        double sum = 0.0;
+        for (int k = i; k < n; ++k) sum += wi[k] * wj[k];
+        Ai[j] = sum;
+      }
+    }
+  });
   for (int i = 0; i < n; ++i)
     for (int j = i + 1; j < n; ++j) A[(size_t)i * n + j] = A[(size_t)j * n + i];
   return true;
@@ -518,11 +629,20 @@ void factorize(Scene& S) {
     e_off[s + 1] = e_off[s] + ns * (long long)L.Irows[s].size();
   }
   std::vector<double> Zs_all(zs_off[nsub]), Et_all(e_off[nsub]), E_all(e_off[nsub]);
-  for (int s = 0; s < nsub; ++s) {
+  // subdomains in parallel (each writes only its own blocks and its Schur
+  // contribution), then the contributions are added in subdomain order
+  std::vector<std::vector<double>> schur(nsub);
+  std::vector<int> sub_ok(nsub, 1);
+  const int T = host_threads();
+  run_threads(T, [&](int t) {
+  for (int s = t; s < nsub; s += T) {
     const int ns = L.sub_begin[s + 1] - L.sub_begin[s];
     const int nI = (int)L.Irows[s].size();
     std::vector<double> Z = Ass[s];
-    if (!spd_inverse(Z, ns)) throw PdError{PD_ERR_FACTOR_NOT_SPD, "subdomain block not SPD"};
+    if (!spd_inverse(Z, ns)) {
+      sub_ok[s] = 0;
+      continue;
+    }
     std::copy(Z.begin(), Z.end(), Zs_all.begin() + zs_off[s]);
     // E_s (nI x ns) = A_Is (nI x ns) Z (ns x ns)
     double* Es = &E_all[e_off[s]];
@@ -537,19 +657,30 @@ void factorize(Scene& S) {
     }
     for (int v = 0; v < ns; ++v)
       for (int p = 0; p < nI; ++p) Et_all[e_off[s] + (size_t)v * nI + p] = Es[(size_t)p * ns + v];
-    // Schur update on the interface rows of s
+    // Schur contribution E_s A_{s I} on the interface rows of s
+    std::vector<double>& sc = schur[s];
+    sc.assign((size_t)nI * nI, 0.0);
     for (int p = 0; p < nI; ++p) {
       const double* e = Es + (size_t)p * ns;
-      const int ip = L.Irows[s][p];
       for (int q = 0; q < nI; ++q) {
         const double* a = &AIs[s][(size_t)q * ns];
         double d = 0.0;
         for (int v = 0; v < ns; ++v) d += e[v] * a[v];
-        ATT[(size_t)ip * nT + L.Irows[s][q]] -= d;
+        sc[(size_t)p * nI + q] = d;
       }
     }
   }
-  if (nT > 0 && !spd_inverse(ATT, nT)) throw PdError{PD_ERR_FACTOR_NOT_SPD, "interface Schur complement not SPD"};
+  });
+  for (int s = 0; s < nsub; ++s) {
+    if (!sub_ok[s]) throw PdError{PD_ERR_FACTOR_NOT_SPD, "subdomain block not SPD"};
+    const int nI = (int)L.Irows[s].size();
+    for (int p = 0; p < nI; ++p)
+      for (int q = 0; q < nI; ++q)
+        ATT[(size_t)L.Irows[s][p] * nT + L.Irows[s][q]] -= schur[s][(size_t)p * nI + q];
+  }
+  schur.clear();
+  if (nT > 0 && !spd_inverse_threaded(ATT, nT))
+    throw PdError{PD_ERR_FACTOR_NOT_SPD, "interface Schur complement not SPD"};
   // couplings of each interface row: (subdomain, row of E_s), subdomains ascending
   std::vector<int> ir_off(nsub + 1, 0), irows;
   for (int s = 0; s < nsub; ++s) {

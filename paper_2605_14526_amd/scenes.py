@@ -349,6 +349,21 @@ def drop_blob(res: int = 8, seed: int = 3001, n_spheres: int = 6, r_lo: float = 
                  obstacles=obs, v_init=np.array([0.0, 0.0, -drop_speed]))
 
 
+def drop_family(k: int, res: int = 27, steps: int = 100) -> Scene:
+    """Member k of a family of drops of one blob (the contact benchmark's mesh and material): the initial velocity
+    is drawn from seed 3100 + k (downward speed uniform in [0.5, 1.5] m/s, horizontal components uniform in
+    [-0.5, 0.5] m/s), and so is the target centroid.  Members with different k share the mesh, so one warm-start
+    network serves all of them; the benchmark's drop (1 m/s straight down) is not a member."""
+    sc = drop_blob(res=res, steps=steps)
+    rng = _rng(3100 + k)
+    vz = rng.uniform(0.5, 1.5)
+    vx, vy = rng.uniform(-0.5, 0.5, 2)
+    sc.v_init = np.array([vx, vy, -vz])
+    sc.target_centroid = sc.X.mean(axis=0) + rng.uniform(-0.02, 0.02, 3)
+    sc.name = f"drop_family_r{res}_{k}"
+    return sc
+
+
 def config(name: str) -> Scene:
     if name in ("c1", "c1_cantilever"):
         return cantilever_c1()

@@ -134,11 +134,11 @@ def cpu_baseline(sc, steps):
 
 
 def bench_batch(args, torch):
-    """Uneven-beam batch (64 scenes, about 0.57 M tets): batched fwd+bwd
-    scene-steps per second after autotuning the launch shapes."""
+    """Uneven batch of beams and anchored blobs (64 scenes, about 0.73 M tets):
+    batched fwd+bwd scene-steps per second after autotuning the launch shapes."""
     from paper_2605_14526_amd import autotune, scenes
     from paper_2605_14526_amd.binding import Batch, Scene
-    scs = scenes.beam_batch(n=args.batch_scenes, steps=args.steps)
+    scs = scenes.sysid_batch(n=args.batch_scenes, steps=args.steps)
     t0 = time.perf_counter()
     gs = [Scene.from_scene(sc, eps_adj=1e-6, adj_warm=2) for sc in scs]
     t_setup = time.perf_counter() - t0
@@ -180,7 +180,8 @@ def bench_batch(args, torch):
            "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
            "ms_per_step": round(1000.0 * dt / args.steps, 4), "higher_is_better": True, "scaling": "weak",
            "vs_baseline": None, "dtype": "f64", "data": "synthetic",
-           "config": {"workload": f"batch of {len(scs)} uneven beams, {ne} tets in total (1k-30k each), "
+           "config": {"workload": f"batch of {len(scs)} uneven scenes ({sum('blob' in sc.name for sc in scs)} "
+                                  f"anchored blobs, the rest beams), {ne} tets in total (1k-30k each), "
                                   f"contrast 1-100x, nu 0.40-0.49, h 0.01, {args.steps} steps, gate and adjoint 1e-6",
                       "launch_shapes": cfg, "setup_s": round(t_setup, 2), "tune_s": round(t_tune, 2),
                       "fwd_iters_per_step": round(float(np.mean(fi)), 3),

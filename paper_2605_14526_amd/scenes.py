@@ -364,6 +364,54 @@ def drop_family(k: int, res: int = 27, steps: int = 100) -> Scene:
     return sc
 
 
+def anchored_blob(ne: float, seed: int, contrast: float = 30.0, nu: float = 0.45, steps: int = 50,
+                  h: float = 0.01, tip_force: float = 20.0) -> Scene:
+    """A blob without obstacles for multi-scene identification: the implicit blob of drop_blob (shape from
+    `seed`) voxelised to about `ne` tets, its bottom layer of vertices pinned (a jelly fixed to a table),
+    two-phase stiffness from 4 Gaussian blobs (exactly 30 % stiff, E 1e4 and 1e4 * contrast), gravity plus a
+    seeded force on its x-max vertices ramped over 2 steps and held to step 4; Anderson window 5 below 10x
+    contrast, else 1."""
+    res = max(3, int(round((float(ne) / 1.45) ** (1.0 / 3.0))))
+    base = drop_blob(res=res, seed=seed, with_box=False)
+    X = base.X - base.X.min(axis=0)
+    tets = base.tets
+    pinned = (np.abs(X[:, 2]) < 1e-12).astype(np.uint8)
+    cen = X[tets].mean(axis=1)
+    ext = X.max(axis=0)
+    rng = _rng(seed + 1)
+    field = gaussian_blob_field(cen, np.zeros(3), ext, 4, rng, 0.05 * ext.max(), 0.15 * ext.max())
+    E_soft = 1e4
+    logE = two_phase_log_E(field, 0.3, E_soft, E_soft * contrast)
+    force = _tip_force_fn(X, tip_force, seed + 2, 2, 4) if tip_force else None
+    target = X.mean(axis=0) + _rng(seed + 3).uniform(-0.05, 0.05, 3)
+    return Scene(f"anchored_blob_{seed}", X, tets, pinned, logE, nu=nu, rho=1000.0, alpha=0.01,
+                 beta0=1e-2 * E_soft * contrast, h=h, gravity=np.array([0.0, 0.0, -9.81]),
+                 aa_window=5 if contrast < 10.0 else 1, steps=steps, force_fn=force, target_centroid=target)
+
+
+def sysid_batch(n: int = 64, seed: int = 4000, steps: int = 50, ne_range=(1000, 30000)) -> list:
+    """A batch of uneven scenes for multi-scene identification: per scene a coin flip between a beam (as in
+    beam_batch) and an anchored blob, a tet count log-uniform in ne_range, contrast log-uniform in [1, 100],
+    nu uniform in [0.40, 0.49]."""
+    rng = _rng(seed)
+    out = []
+    for s in range(n):
+        ne = float(np.exp(rng.uniform(np.log(ne_range[0]), np.log(ne_range[1]))))
+        contrast = float(np.exp(rng.uniform(0.0, np.log(100.0))))
+        nu = float(rng.uniform(0.40, 0.49))
+        if rng.random() < 0.5:
+            c = int(rng.integers(2, 7))
+            nx = max(2, int(round(ne / (5 * c * c))))
+            sc = small_beam(nx, c, c, seed=seed + 10 * (s + 1), contrast=contrast, nu=nu, tip_force=20.0,
+                            aa_window=5 if contrast < 10.0 else 1, steps=steps)
+            sc.name = f"sysid_beam_{s}"
+        else:
+            sc = anchored_blob(ne, seed=seed + 10 * (s + 1), contrast=contrast, nu=nu, steps=steps)
+            sc.name = f"sysid_blob_{s}"
+        out.append(sc)
+    return out
+
+
 def config(name: str) -> Scene:
     if name in ("c1", "c1_cantilever"):
         return cantilever_c1()

@@ -86,3 +86,55 @@ def test_segment_recompute_equals_full_records(th):
     b = torch_grads(th, sc, sc.log_E, T, 0.0, 4)
     for x, y in zip(a, b):
         assert rel(x, y) < 1e-9
+
+
+def test_autograd_rollout_through_contact(th):
+    """The autograd rollout through a landing (contact rows detected by the
+    library each step, their records in the checkpoints, segments recomputed)
+    against the oracle's reverse sweep with the active rows held fixed."""
+    from paper_2605_14526_amd.autograd import rollout
+    from paper_2605_14526_amd.binding import Scene
+    sc = scenes.drop_blob(res=6, with_box=True)
+    osc = O.OracleScene(sc)
+    q, v = sc.q0(), sc.v0()
+    hist = []
+    for t in range(200):  # the oracle's state two steps ahead of the landing
+        hist.append((q, v))
+        con = O.detect_contacts(q, v, sc.h, sc.pinned, sc.obstacles)
+        q, v, _, lam, _ = O.step_forward_contact(osc, q, v, sc.f_ext(t), con)
+        if (lam > 0).any():
+            break
+    q0, v0 = hist[-3]
+    T, w_traj = 6, 0.05
+    # oracle
+    q, v, ck = q0.copy(), v0.copy(), []
+    qs = [q0]
+    for t in range(T):
+        f = sc.f_ext(t)
+        con = O.detect_contacts(q, v, sc.h, sc.pinned, sc.obstacles)
+        qn, vn, qm1, lam, _ = O.step_forward_contact(osc, q, v, f, con)
+        ck.append((q, v, f, qn, qm1, con, lam))
+        q, v = qn, vn
+        qs.append(q)
+    assert sum(int((c[6] > 0).sum()) for c in ck) > 0
+    _, gq = scenes.centroid_loss(q, sc.target_centroid)
+    gq = gq + w_traj * qs[T]
+    gv = np.zeros_like(gq)
+    gl = np.zeros(sc.n_e)
+    for t in reversed(range(T)):
+        q_t, v_t, f, qsr, qsm1, con, lam = ck[t]
+        gq, gv, _, gl, _ = O.step_backward_contact(osc, q_t, v_t, f, qsr, qsm1, gq, gv, con, lam, gl, adj_mode=1)
+        gq = gq + w_traj * qs[t]
+    for ckpt_every in (1, 3):
+        g = Scene.from_scene(sc, eps_adj=1e-12, adj_warm=2)
+        d = lambda a: th.tensor(np.ascontiguousarray(a), dtype=th.float64, device="cuda", requires_grad=True)  # noqa: E731
+        tq0, tv0 = d(q0), d(v0)
+        forces = d(np.stack([sc.f_ext(t) for t in range(T)]))
+        le = d(sc.log_E)
+        traj, vT = rollout(g, tq0, tv0, forces, le, ckpt_every=ckpt_every)
+        target = th.tensor(sc.target_centroid, dtype=th.float64, device="cuda")
+        loss = ((traj[T].mean(dim=0) - target) ** 2).sum() + 0.5 * w_traj * (traj ** 2).sum()
+        loss.backward()
+        assert rel(traj[T].detach().cpu().numpy(), q) < TOL_POS
+        for a, b in [(tq0.grad, gq), (tv0.grad, gv), (le.grad, gl)]:
+            assert rel(a.cpu().numpy(), b) < TOL_GRAD, (ckpt_every, rel(a.cpu().numpy(), b))

@@ -19,6 +19,7 @@ def th(torch_cuda):
 def batch_scenes():
     return [scenes.small_beam(6, 3, 3, seed=5, contrast=30.0, nu=0.49, aa_window=1),
             scenes.small_beam(9, 2, 2, seed=8, contrast=3.0, nu=0.45, aa_window=5),
+            scenes.anchored_blob(600, seed=21, contrast=50.0, nu=0.47),
             scenes.small_beam(4, 4, 4, seed=13, contrast=100.0, nu=0.48, aa_window=1)]
 
 
@@ -131,3 +132,10 @@ def test_autotune_picks_and_caches(th, tmp_path):
     cache = json.load(open(path))
     assert cache[autotune.batch_key(B)] == cfg
     assert autotune.autotune(B, run, th, cache_path=path) == cfg
+
+
+def test_batch_rejects_scenes_with_obstacles(th):
+    from paper_2605_14526_amd.binding import Batch, Scene
+    g = Scene.from_scene(scenes.drop_blob(res=4))
+    with pytest.raises(RuntimeError, match="PD_ERR_INVALID_ARG"):
+        Batch([g])

@@ -36,7 +36,22 @@ enum { kCtlDone = 0, kCtlIters = 1, kCtlStatus = 2, kCtlResets = 3, kCtlNewton =
 enum { kRedGate = 0, kRedAA = 1, kRedPW = 2, kRedRZ0 = 3, kRedRZ1 = 4, kRedTR = 5, kRedFix = 6, kRedSites = 7 };
 constexpr int kRedWidth = 32;   // doubles per partial
 constexpr int kFinStride = 64;  // doubles per site in the final buffer
-constexpr int kBottomThreads = 512;
+#ifndef PD_BOTTOM_THREADS
+#define PD_BOTTOM_THREADS 512
+#endif
+#ifndef PD_BOTTOM_UNROLL
+#define PD_BOTTOM_UNROLL 8
+#endif
+#ifndef PD_EB_UNROLL
+#define PD_EB_UNROLL 4
+#endif
+#ifndef PD_TOP_UNROLL
+#define PD_TOP_UNROLL 8
+#endif
+constexpr int kBottomThreads = PD_BOTTOM_THREADS;  // subdomain solve: 64 threads (one row) per wave
+constexpr int kBottomUnroll = PD_BOTTOM_UNROLL;  // loads in flight per lane in the subdomain solve's row loops
+constexpr int kEbUnroll = PD_EB_UNROLL;
+constexpr int kTopUnroll = PD_TOP_UNROLL;
 
 struct RedArgs {
   double* part;    // per site: max_parts x kRedWidth

@@ -703,7 +703,7 @@ __device__ __forceinline__ void b_Eb(VertArgs Vx, SolveArgs Sv, StepState St, Ad
   }
   const double* __restrict__ Er = Sv.E + er.off;
   double a0 = 0, a1 = 0, a2 = 0;
-#pragma unroll 4
+#pragma unroll kEbUnroll
   for (int idx = lane; idx < er.len; idx += 64) {
     int col = B[0] + idx;
 #pragma unroll
@@ -770,7 +770,7 @@ __device__ __forceinline__ void b_top(VertArgs Vx, SolveArgs Sv, double* __restr
     }
     __syncthreads();
     if (have) {
-#pragma unroll 8
+#pragma unroll kTopUnroll
       for (int j = lane; j < tl; j += 64) {
         const double z = Zi[t0 + j];
         a0 += z * rs[j];
@@ -957,7 +957,7 @@ __device__ __forceinline__ void b_bottom(VertArgs Vx, SolveArgs Sv, StepState St
     const int ni = Sv.n_irows;
     const double* __restrict__ x0 = Sv.xsT + br.ir0;
     double a0 = 0, a1 = 0, a2 = 0;
-#pragma unroll 4
+#pragma unroll kBottomUnroll
     for (int u = lane; u < br.ns; u += 64) {
       const double z = Zr[u];
       const int c = br.b0 + u;
@@ -971,7 +971,7 @@ __device__ __forceinline__ void b_bottom(VertArgs Vx, SolveArgs Sv, StepState St
         a2 += z * src[2 * nv + c];
       }
     }
-#pragma unroll 4
+#pragma unroll kBottomUnroll
     for (int p = lane; p < br.nI; p += 64) {
       const double e = Er[p];
       a0 -= e * x0[p];

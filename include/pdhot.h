@@ -208,7 +208,7 @@ int pd_step_backward(pd_scene* scene, const void* ckpt, const double* gq_next, c
  *
  * pd_scene_set_obstacles: planes n_planes x 4 (unit normal, offset o), boxes
  * n_boxes x 6 (lo xyz, hi xyz), host pointers, copied; at most 8 obstacles;
- * d_c > 0 the candidate distance; max_contacts (1..256) the row capacity per
+ * d_c > 0 the candidate distance; max_contacts (1..512) the row capacity per
  * step (PD_ERR_CONTACT beyond it); fb_tol > 0.  n_planes = n_boxes = 0 turns
  * contact off.  Checkpoints allocated before this call are too small
  * afterwards (pd_ckpt_bytes grows).  Scenes with obstacles cannot join a

@@ -175,7 +175,7 @@ class Scene:
             g.set_obstacles(sc.obstacles, **contact)
         return g
 
-    def set_obstacles(self, obs, max_contacts=256, fb_tol=1e-10):
+    def set_obstacles(self, obs, max_contacts=512, fb_tol=1e-10):
         """Static obstacles {"planes": [(n, o)], "boxes": [(lo, hi)], "d_c": d} (pd_scene_set_obstacles)."""
         planes = np.ascontiguousarray([list(n) + [o] for (n, o) in obs.get("planes", [])] or np.zeros((0, 4)),
                                       dtype=np.float64)

@@ -328,10 +328,8 @@ __global__ void __launch_bounds__(kContactThreads) k_contact_fb(VertArgs Vx, Con
     }
     __syncthreads();
     const int na = na_s;
-    if (na > kMaxNewtonRows) {
-      if (tid == 0) C.flags[1] = 1;
-      break;
-    }
+    // systems beyond the LDS size are factored in the global scratch (L2-resident)
+    double* Lm = (na <= kMaxNewtonRows) ? L : C.Lg;
     if (na > 0) {
       // M = W_AA + diag(E / omega) (lower triangle) and rhs = -phi / omega as row na
       const int cntM = tri(na);
@@ -344,21 +342,21 @@ __global__ void __launch_bounds__(kContactThreads) k_contact_fb(VertArgs Vx, Con
           const int ci = act[i], cj = act[j];
           double m = C.W[(size_t)ci * K + cj];
           if (i == j) m += Ev[ci] / om[ci];
-          L[p] = m;
+          Lm[p] = m;
         } else {
           const int j = p - cntM, cj = act[j];
-          L[cntM + j] = -phi[cj] / om[cj];
+          Lm[cntM + j] = -phi[cj] / om[cj];
         }
       }
       __syncthreads();
-      if (!chol_packed(L, na, true, &fail_s)) break;
+      if (!chol_packed(Lm, na, true, &fail_s)) break;
       // back substitution L^T x = y, y in row na
-      double* y = L + tri(na);
+      double* y = Lm + tri(na);
       for (int i = na - 1; i >= 0; --i) {
-        if (tid == 0) y[i] = y[i] / L[tri(i) + i];
+        if (tid == 0) y[i] = y[i] / Lm[tri(i) + i];
         __syncthreads();
         const double xi = y[i];
-        for (int j = tid; j < i; j += nt) y[j] -= L[tri(i) + j] * xi;
+        for (int j = tid; j < i; j += nt) y[j] -= Lm[tri(i) + j] * xi;
         __syncthreads();
       }
       for (int a = tid; a < na; a += nt) {
@@ -387,13 +385,14 @@ __global__ void __launch_bounds__(kContactThreads) k_contact_fb(VertArgs Vx, Con
 
 
 // The same Newton for at most 64 rows, one row per lane of a single wave:
-// the FB values, the active compaction (ballot), the dense system in LDS, its
-// Cholesky (right-looking, each lane updating its own row) and both
-// substitutions (pivots broadcast by shuffles) need no workgroup barrier
-// beyond the single wave's own.
+// W is staged in LDS once; the FB values, the active compaction (ballot), the
+// dense system, its left-looking Cholesky (lane i forms row i of each column
+// from the finished columns, the pivot comes by shuffle) and both
+// substitutions need no workgroup barrier beyond the single wave's own.
 __global__ void __launch_bounds__(64) k_contact_fb_wave(VertArgs Vx, ContactArgs C, const double* __restrict__ qhat,
                                                         const int* __restrict__ done) {
-  __shared__ double M[64 * 65];  // row i of the Newton matrix at M[i * 65], rhs in column 64
+  __shared__ double M[64 * 65];   // Newton matrix, row i at M[i * 65] (lower triangle, then L)
+  __shared__ double Ws[64 * 65];  // W, row c at Ws[c * 65]
   __shared__ double lam_s[64];
   const int lane = threadIdx.x;
   const int K = C.K, nv = Vx.nv;
@@ -411,10 +410,15 @@ __global__ void __launch_bounds__(64) k_contact_fb_wave(VertArgs Vx, ContactArgs
     g = C.g[lane];
     lam = C.lam[lane];
   }
+  for (int idx = lane; idx < K * K; idx += 64) {
+    const int c = idx / K, d = idx - c * K;
+    Ws[c * 65 + d] = C.W[idx];
+  }
   flag = __shfl(flag, 0, 64);
   if (flag) return;
+  __syncthreads();
   const double dfree = n0 * q0 + n1 * q1 + n2 * q2 - g;
-  const double* Wr = C.W + (size_t)(row ? lane : 0) * K;
+  const double* Wr = Ws + (row ? lane : 0) * 65;
   double phi = 0.0, om = 0.0, E = 0.0;
   auto evaluate = [&]() {
     lam_s[lane] = lam;
@@ -448,49 +452,65 @@ __global__ void __launch_bounds__(64) k_contact_fb_wave(VertArgs Vx, ContactArgs
     const unsigned long long bal = __ballot(a_on);
     const int na = __popcll(bal);
     const int pos = a_on ? __popcll(bal & ((1ull << lane) - 1ull)) : -1;
-    // row pos of the system: W restricted to the active rows, + E / omega on the diagonal, rhs -phi / omega
+    // row pos of the system: W restricted to the active rows, + E / omega on the diagonal
+    double b = 0.0;
     if (a_on) {
       double* Mi = M + pos * 65;
       unsigned long long rest = bal;
       int j = 0;
-      while (rest) {
+      while (rest && j <= pos) {
         const int d = __ffsll((long long)rest) - 1;
         rest &= rest - 1ull;
         Mi[j] = Wr[d] + (d == lane ? E / om : 0.0);
         ++j;
       }
-      Mi[64] = -phi / om;
+      b = -phi / om;
+    }
+    // lane p takes the rhs of system row p (the p-th active row)
+    double y = 0.0;
+    {
+      unsigned long long rest = bal;
+      int p = 0, src = 0;
+      while (rest) {
+        const int d = __ffsll((long long)rest) - 1;
+        rest &= rest - 1ull;
+        if (p == lane) src = d;
+        ++p;
+      }
+      y = __shfl(b, src, 64);
+      if (lane >= na) y = 0.0;
     }
     __syncthreads();
-    // Cholesky, lane i owns row i; the rhs is eliminated alongside
+    // left-looking Cholesky, lane i owns row i
     bool ok = true;
     for (int j = 0; j < na; ++j) {
-      const double piv = M[j * 65 + j];
+      double sv = 0.0;
+      if (lane >= j && lane < na) {
+        const double* Mi = M + lane * 65;
+        const double* Mj = M + j * 65;
+        sv = Mi[j];
+        for (int k = 0; k < j; ++k) sv -= Mi[k] * Mj[k];
+      }
+      const double piv = __shfl(sv, j, 64);
       if (!(piv > 0.0)) {
         ok = false;
         break;
       }
       const double dj = sqrt(piv);
-      __syncthreads();
-      if (lane == j) {
-        M[j * 65 + j] = dj;
-        M[j * 65 + 64] /= dj;
-      }
-      if (lane > j && lane < na) M[lane * 65 + j] /= dj;
-      __syncthreads();
-      if (lane > j && lane < na) {
-        const double lij = M[lane * 65 + j];
-        for (int l = j + 1; l <= lane; ++l) M[lane * 65 + l] -= lij * M[l * 65 + j];
-        M[lane * 65 + 64] -= lij * M[j * 65 + 64];
-      }
+      if (lane == j) M[j * 65 + j] = dj;
+      else if (lane > j && lane < na) M[lane * 65 + j] = sv / dj;
       __syncthreads();
     }
     if (!ok) {
       fail = 1;
       break;
     }
-    // back substitution L^T x = y (y in column 64)
-    double y = (lane < na) ? M[lane * 65 + 64] : 0.0;
+    // forward substitution L z = y, then back substitution L^T x = z (lane p holds entry p)
+    for (int j = 0; j < na; ++j) {
+      const double zj = __shfl(y, j, 64) / M[j * 65 + j];
+      if (lane == j) y = zj;
+      else if (lane > j && lane < na) y -= M[lane * 65 + j] * zj;
+    }
     for (int i = na - 1; i >= 0; --i) {
       const double xi = __shfl(y, i, 64) / M[i * 65 + i];
       if (lane == i) y = xi;
@@ -502,6 +522,7 @@ __global__ void __launch_bounds__(64) k_contact_fb_wave(VertArgs Vx, ContactArgs
       const double l = lam + dl;
       lam = l > 0.0 ? l : 0.0;
     }
+    __syncthreads();
     res = evaluate();
   }
   if (row) {
@@ -521,9 +542,10 @@ __global__ void __launch_bounds__(64) k_contact_fb_wave(VertArgs Vx, ContactArgs
 // Inverse of W_AA (the active rows, K = n_active here) by Cholesky in LDS and
 // one substitution pair per column (one thread per column).
 __global__ void __launch_bounds__(kContactThreads) k_contact_winv(ContactArgs C, double* __restrict__ Winv) {
-  __shared__ double L[tri(kMaxNewtonRows) + 1];
+  __shared__ double Ls[tri(kMaxNewtonRows) + 1];
   __shared__ int fail_s;
   const int tid = threadIdx.x, nt = blockDim.x, na = C.K, nf = C.nf;
+  double* L = (na <= kMaxNewtonRows) ? Ls : C.Lg;
   if (tid == 0) fail_s = 0;
   for (int p = tid; p < tri(na); p += nt) {
     int i = (int)((sqrt(8.0 * p + 1.0) - 1.0) * 0.5);
@@ -557,19 +579,26 @@ __global__ void __launch_bounds__(kContactThreads) k_contact_winv(ContactArgs C,
 // u = W_AA^{-1} (J_A z), s = u_c n_c (z = A~^{-1} r, the unprojected solve)
 __global__ void __launch_bounds__(256) k_contact_proj(VertArgs Vx, ContactArgs C, const double* __restrict__ z,
                                                       const int* __restrict__ done) {
-  __shared__ double y[kMaxNewtonRows];
+  __shared__ double y[kMaxContactRows];
   __shared__ int flag_s;
   const int tid = threadIdx.x, lane = tid & 63, wid = tid >> 6, nw = blockDim.x >> 6;
   const int na = C.K, nv = Vx.nv;
   if (tid == 0) flag_s = done ? *done : 0;
-  double yv = 0.0;
-  if (tid < na) {
-    const int v = C.v[tid];
-    yv = C.n[3 * tid] * z[v] + C.n[3 * tid + 1] * z[nv + v] + C.n[3 * tid + 2] * z[2 * nv + v];
+  double yv[kMaxContactRows / 256];
+#pragma unroll
+  for (int r = 0; r < kMaxContactRows / 256; ++r) {
+    const int c = tid + 256 * r;
+    yv[r] = 0.0;
+    if (c < na) {
+      const int v = C.v[c];
+      yv[r] = C.n[3 * c] * z[v] + C.n[3 * c + 1] * z[nv + v] + C.n[3 * c + 2] * z[2 * nv + v];
+    }
   }
   __syncthreads();
   if (flag_s) return;
-  if (tid < na) y[tid] = yv;
+#pragma unroll
+  for (int r = 0; r < kMaxContactRows / 256; ++r)
+    if (tid + 256 * r < na) y[tid + 256 * r] = yv[r];
   __syncthreads();
   for (int c = wid; c < na; c += nw) {
     const double* Wr = C.W + (size_t)c * na;

@@ -137,8 +137,8 @@ struct AdjState {
 // Contact rows of one step (forward: every candidate row; adjoint: the active
 // rows) and the cached columns a = A~^{-1} e_v of their vertices.
 constexpr int kContactThreads = 1024;
-constexpr int kMaxContactRows = 256;  // candidate rows per step
-constexpr int kMaxNewtonRows = 176;   // rows of one FB Newton system (packed in LDS)
+constexpr int kMaxContactRows = 512;  // candidate rows per step
+constexpr int kMaxNewtonRows = 176;   // rows of one dense system factored in LDS (larger: global scratch)
 constexpr int kMaxObstacles = 8;
 constexpr int kFBMaxIter = 30;
 constexpr double kFBTol = 1e-14;
@@ -155,7 +155,8 @@ struct ContactArgs {
   double* lam;         // K impulses
   double* s;           // 3K: lam_c n_c (forward) or u_c n_c (adjoint projection)
   double* fb;          // [0] FB residual, [1] Newton iterations of the last solve
-  int* flags;          // [0] candidate rows found, [1] Newton system too large, [2] factor not SPD
+  int* flags;          // [0] candidate rows found, [1] unused, [2] factor not SPD
+  double* Lg;          // global scratch for dense factorizations larger than the LDS ones
 };
 struct ObsArgs {
   int n_planes, n_boxes;

@@ -161,6 +161,7 @@ struct Scene {
   // active rows of the current backward step and the inverse of their Delassus block
   int *a_v = nullptr, *a_slot = nullptr;
   double *a_n = nullptr, *a_s = nullptr, *a_Winv = nullptr;
+  double* c_Lg = nullptr;  // dense factorizations beyond the LDS size
   // column cache: a_v = A~^{-1} e_v (free rows) for up to col_cap vertices
   double* cols = nullptr;
   int col_cap = 0, cols_used = 0;

@@ -227,7 +227,7 @@ double det3(const double* A) {
 void contact_free(Scene& S) {
   dfree(S.obs); dfree(S.c_v); dfree(S.c_slot); dfree(S.c_flags); dfree(S.c_n); dfree(S.c_g); dfree(S.c_lam);
   dfree(S.c_s); dfree(S.c_W); dfree(S.c_fb); dfree(S.a_v); dfree(S.a_slot); dfree(S.a_n); dfree(S.a_s);
-  dfree(S.a_Winv); dfree(S.cols);
+  dfree(S.a_Winv); dfree(S.c_Lg); dfree(S.cols);
   if (S.h_cbuf) (void)hipHostFree(S.h_cbuf);
   if (S.h_crec) (void)hipHostFree(S.h_crec);
   S.h_cbuf = nullptr;
@@ -811,6 +811,7 @@ ContactArgs contact_args(Scene& S, int K, bool adjoint) {
   C.s = adjoint ? S.a_s : S.c_s;
   C.fb = S.c_fb;
   C.flags = S.c_flags;
+  C.Lg = S.c_Lg;
   return C;
 }
 
@@ -918,7 +919,6 @@ int contact_active(Scene& S, const double* ck, hipStream_t st) {
   const int na = (int)av.size();
   S.c_last_active = na;
   if (na == 0) return 0;
-  if (na > kMaxNewtonRows) throw PdError{kErrContact, "active contact rows exceed the dense solve size"};
   int* hs = S.h_cbuf + 4 + kmax;
   ensure_columns(S, av.data(), na, hs, st);
   PD_HIP(hipMemcpyAsync(S.a_v, av.data(), na * sizeof(int), hipMemcpyHostToDevice, st));
@@ -1136,9 +1136,10 @@ int pd_scene_set_obstacles(pd_scene* scene, int n_planes, const double* planes, 
   S.c_n = dalloc<double>(3 * (size_t)kmax); S.c_g = dalloc<double>(kmax); S.c_lam = dalloc<double>(kmax);
   S.c_s = dalloc<double>(3 * (size_t)kmax); S.c_W = dalloc<double>((size_t)kmax * kmax);
   S.c_fb = dalloc<double>(2);
-  S.a_v = dalloc<int>(kMaxNewtonRows); S.a_slot = dalloc<int>(kMaxNewtonRows);
-  S.a_n = dalloc<double>(3 * kMaxNewtonRows); S.a_s = dalloc<double>(3 * kMaxNewtonRows);
-  S.a_Winv = dalloc<double>((size_t)kMaxNewtonRows * kMaxNewtonRows);
+  S.a_v = dalloc<int>(kmax); S.a_slot = dalloc<int>(kmax);
+  S.a_n = dalloc<double>(3 * (size_t)kmax); S.a_s = dalloc<double>(3 * (size_t)kmax);
+  S.a_Winv = dalloc<double>((size_t)kmax * kmax);
+  S.c_Lg = dalloc<double>((size_t)(kmax + 1) * (kmax + 2) / 2 + kmax + 1);
   S.col_cap = 4 * kmax;
   S.cols = dalloc<double>((size_t)S.col_cap * std::max(nf, 1));
   S.cols_used = 0;
@@ -1251,7 +1252,6 @@ int pd_step_forward(pd_scene* scene, const double* q_t, const double* v_t, const
   if (K > 0) {
     for (int c = 0; c < K; ++c) n_active += S.h_crec[c] > 0.0;
     fb_res = S.h_crec[K];
-    if (S.h_cbuf[1]) throw PdError{kErrContact, "FB Newton system exceeds the dense solve size"};
   }
   S.c_last_K = K;
   S.c_last_active = n_active;

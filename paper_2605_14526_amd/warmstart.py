@@ -51,6 +51,22 @@ def generate(scenes_list, steps: int, torch, **solver_kw) -> List[Sample]:
     return out
 
 
+def generate_on(g: Scene, scenes_list, steps: int, torch) -> List[Sample]:
+    """Plain-start rollouts of family members that share g's mesh and material (one factorization for all)."""
+    out = []
+    for sc in scenes_list:
+        dev = scene_inputs(sc, torch)
+        logw = dev(g.vertex_logw())
+        q, v = dev(sc.q0()), dev(sc.v0())
+        v_prev = v
+        for t in range(steps):
+            f = dev(sc.f_ext(t))
+            qn, vn, st = g.step_forward(q, v, f)
+            out.append(Sample(q, v_prev, v, f, qn, logw))
+            v_prev, q, v = v, qn, vn
+    return out
+
+
 def output_scale(samples: List[Sample], h: float, pinned) -> float:
     """RMS of the correction q_{t+h} - q_t - h v_t over the samples' free vertices."""
     free = ~np.asarray(pinned, bool)

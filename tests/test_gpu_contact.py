@@ -206,3 +206,49 @@ def test_drop_benchmark_size_stepwise(th):
         n_act += int((lam > 0).sum())
         q, v = qo, vo
     assert n_act > 0
+
+
+def slab_drop(n=14, nz=2, edge=0.02):
+    """A flat slab of n x n x nz cubes landing flat on the ground: (n+1)^2 rows at once, more than the LDS
+    factorization holds, so the Newton systems and the adjoint's W_AA are factored in the global scratch."""
+    X, tets = scenes.box_tet_mesh(n, n, nz, edge)
+    X = X + np.array([0.0, 0.0, 0.25 * edge])
+    logE = np.full(tets.shape[0], np.log(1e5))
+    return scenes.Scene("slab_drop", X, tets, np.zeros(X.shape[0], np.uint8), logE, nu=0.45, rho=1000.0,
+                        alpha=0.01, beta0=1.0, h=0.002, gravity=np.array([0.0, 0.0, -9.81]), aa_window=1, steps=8,
+                        force_fn=None, target_centroid=X.mean(axis=0) + 0.01,
+                        obstacles={"planes": [((0.0, 0.0, 1.0), 0.0)], "boxes": [], "d_c": 0.5 * edge},
+                        v_init=np.array([0.0, 0.0, -0.5]))
+
+
+def test_large_contact_systems(th):
+    """225 rows active at once: forward steps and a reverse sweep through them match the oracle."""
+    from paper_2605_14526_amd.binding import Scene
+    sc = slab_drop()
+    osc = O.OracleScene(sc)
+    g = Scene.from_scene(sc, eps_adj=1e-12)
+    q, v = sc.q0(), sc.v0()
+    T = 6
+    ck_o, cks, n_act_max = [], [], 0
+    for t in range(T):
+        f = sc.f_ext(t)
+        con = O.detect_contacts(q, v, sc.h, sc.pinned, sc.obstacles)
+        qo, vo, qm1, lam, st_o = O.step_forward_contact(osc, q, v, f, con)
+        ck = g.new_ckpt()
+        qg, vg, st = g.step_forward(dev(th, q), dev(th, v), dev(th, f), ckpt=ck)
+        assert st["n_contacts"] == len(con[0]) and st["iters"] == st_o["iters"], (t, st, st_o["iters"])
+        assert rel(host(qg), qo) < TOL_POS, (t, rel(host(qg), qo))
+        n_act_max = max(n_act_max, int((lam > 0).sum()))
+        ck_o.append((q, v, f, qo, qm1, con, lam))
+        cks.append(ck)
+        q, v = qo, vo
+    assert n_act_max > 176
+    # one backward step at the last (fully landed) step, from the oracle's own checkpoint data
+    q_t, v_t, f, qs, qsm1, con, lam = ck_o[-1]
+    gq = np.random.Generator(np.random.PCG64(3)).standard_normal(q_t.shape)
+    gv = 0.1 * gq
+    a = O.step_backward_contact(osc, q_t, v_t, f, qs, qsm1, gq, gv, con, lam, adj_mode=1)
+    b = g.step_backward(cks[-1], dev(th, gq), dev(th, gv))
+    assert b[4]["n_active"] > 176
+    for x, y in zip(b[:4], a[:4]):
+        assert rel(host(x), y) < TOL_GRAD, rel(host(x), y)

@@ -42,7 +42,7 @@ def parse():
     ap.add_argument("--max-sub", type=int, default=0)
     ap.add_argument("--no-warm-run", action="store_true", help="skip the warm-started measurements")
     ap.add_argument("--train-scenes", type=int, default=4, help="beams the warm-start network is trained on")
-    ap.add_argument("--train-epochs", type=int, default=16)
+    ap.add_argument("--train-epochs", type=int, default=32)
     ap.add_argument("--batch-scenes", type=int, default=64, help="scenes of --config batch")
     ap.add_argument("--tune-cache", default="", help="autotuner cache file of --config batch")
     ap.add_argument("--drop-res", type=int, default=27, help="cells along the blob of --config drop (27: 28k tets)")

@@ -419,14 +419,29 @@ __global__ void __launch_bounds__(256) k_mpn_enc_dz(MpnArgs M, const float* __re
   dz[t] = dh[t] * dsilu(z0[t]);
 }
 
-// g[off + e] = sum over blocks of part[blk][e] in block order (deterministic)
+// g[e] = sum over the partial rows part[b][e] in a fixed order: each of 8
+// threads of an output sums the rows b = t, t + 8, t + 16, ... in order, then
+// the 8 sums are added in t order (deterministic; 32 outputs per block, the
+// threads of one t read consecutive outputs).
+constexpr int kRedSplit = 8;
 __global__ void __launch_bounds__(256) k_mpn_reduce(const float* __restrict__ part, int nblk, int width,
                                                     float* __restrict__ g) {
-  const int e = blockIdx.x * blockDim.x + threadIdx.x;
-  if (e >= width) return;
+  __shared__ float acc[kRedSplit][32];
+  const int el = threadIdx.x & 31, t = threadIdx.x >> 5;
+  const int e = blockIdx.x * 32 + el;
   float s = 0.0f;
-  for (int b = 0; b < nblk; ++b) s += part[(size_t)b * width + e];
-  g[e] = s;
+  if (e < width) {
+#pragma unroll 4
+    for (int b = t; b < nblk; b += kRedSplit) s += part[(size_t)b * width + e];
+  }
+  acc[t][el] = s;
+  __syncthreads();
+  if (t == 0 && e < width) {
+    float r = acc[0][el];
+#pragma unroll
+    for (int k = 1; k < kRedSplit; ++k) r += acc[k][el];
+    g[e] = r;
+  }
 }
 
 // Adam on the FP32 master weights (bias-corrected), then the BF16 copy.
@@ -551,7 +566,7 @@ static void mpn_wgrad(MpnImpl& N, const float* hin, const float* dz, int rows, s
   hipLaunchKernelGGL((k_mpn_wgrad<BF, KIND>), dim3(nblk), dim3(256), 0, s, N.A, hin, dz, N.part, rows);
   // the weight block and the bias block are contiguous in the partial rows but not in P:
   // reduce into G at the weight offset, and the bias columns follow it (b directly after W)
-  hipLaunchKernelGGL(k_mpn_reduce, dim3(mpn_grid_rows(width, 256)), dim3(256), 0, s, N.part, nblk, width,
+  hipLaunchKernelGGL(k_mpn_reduce, dim3(mpn_grid_rows(width, 32)), dim3(256), 0, s, N.part, nblk, width,
                      N.G + woff);
   (void)boff;
 }
@@ -563,7 +578,8 @@ static void mpn_backward(MpnImpl& N, hipStream_t s) {
   const int nv = A.nv, ne = N.ne;
   const int ndb = mpn_grid_rows(nv, 4);
   hipLaunchKernelGGL(k_mpn_dec_bwd, dim3(ndb), b, 0, s, A, N.hbuf[kMpnLayers], N.P + o.Wd, N.dy, N.dh, N.part);
-  hipLaunchKernelGGL(k_mpn_reduce, dim3(1), b, 0, s, N.part, ndb, kMpnH * 3 + 3, N.G + o.Wd);
+  hipLaunchKernelGGL(k_mpn_reduce, dim3(mpn_grid_rows(kMpnH * 3 + 3, 32)), b, 0, s, N.part, ndb, kMpnH * 3 + 3,
+                     N.G + o.Wd);
   for (int l = kMpnLayers - 1; l >= 0; --l) {
     A.agg = N.aggl[l];  // the node update's input [h_l, a_l]
     // node update: dzn, [dh_prev, da]

@@ -16,7 +16,10 @@
  *
  * All entry points are synchronous with respect to the host on return unless
  * stated otherwise; `stream` is a hipStream_t passed as void* (NULL = the
- * default stream).
+ * default stream).  pd_step_forward and pd_step_backward return once their
+ * convergence decision and statistics are on the host; the kernels that write
+ * their outputs (positions and velocities and the checkpoint; the gradients)
+ * may still be running on `stream`, ordered before any later work on it.
  */
 #ifndef PDHOT_H
 #define PDHOT_H

@@ -1229,25 +1229,26 @@ int pd_step_forward(pd_scene* scene, const double* q_t, const double* v_t, const
         PD_TIMED(S, kKBottom, st, launch_bottom(kModeFwd, V, A, T, Ad, R, nullptr, S.qhat, k, st));
       }
     }
+    // the control block and the gate norms are final once the done flag is seen
     PD_HIP(hipMemcpyAsync(S.hctl, S.ctl, kCtlSize * sizeof(int), hipMemcpyDeviceToHost, st));
+    PD_HIP(hipMemcpyAsync(S.hdstat, S.dstat, 8 * sizeof(double), hipMemcpyDeviceToHost, st));
     PD_HIP(hipStreamSynchronize(st));
     kt_flush(S);
     if (S.hctl[kCtlDone] || k >= S.kmax_fwd) break;
     chunk = S.iters_per_check > 0 ? S.iters_per_check : 2;
   }
+  // the epilogue is stream-ordered: without contact rows nothing more is read back
   launch_epilogue(V, T, q_next, v_next, (double*)ckpt, st);
   if (S.contact_on && ckpt)
     launch_contact_ckpt(C, S.c_kmax, (double*)ckpt + (size_t)kCheckpointVecs * 3 * S.nv, st);
-  PD_HIP(hipMemcpyAsync(S.hdstat, S.dstat, 8 * sizeof(double), hipMemcpyDeviceToHost, st));
-  PD_HIP(hipMemcpyAsync(S.hctl, S.ctl, kCtlSize * sizeof(int), hipMemcpyDeviceToHost, st));
   int n_active = 0;
   double fb_res = 0.0;
   if (K > 0) {
     PD_HIP(hipMemcpyAsync(S.h_crec, S.c_lam, K * sizeof(double), hipMemcpyDeviceToHost, st));
     PD_HIP(hipMemcpyAsync(S.h_crec + K, S.c_fb, 2 * sizeof(double), hipMemcpyDeviceToHost, st));
     PD_HIP(hipMemcpyAsync(S.h_cbuf, S.c_flags, 4 * sizeof(int), hipMemcpyDeviceToHost, st));
+    PD_HIP(hipStreamSynchronize(st));
   }
-  PD_HIP(hipStreamSynchronize(st));
   PD_HIP(hipGetLastError());
   if (K > 0) {
     for (int c = 0; c < K; ++c) n_active += S.h_crec[c] > 0.0;
@@ -1347,14 +1348,14 @@ static void adjoint_solve(Scene& S, hipStream_t st, double tau_force, double* bs
         }
       }
     }
+    // the control block, the trust-region figures and the residual are final once done is seen
     PD_HIP(hipMemcpyAsync(S.hctl, S.ctl, kCtlTotal * sizeof(int), hipMemcpyDeviceToHost, st));
+    PD_HIP(hipMemcpyAsync(S.hdstat, S.dstat, 32 * sizeof(double), hipMemcpyDeviceToHost, st));
     PD_HIP(hipStreamSynchronize(st));
     kt_flush(S);
     if (S.hctl[kCtlAdj + 2] || it > S.kmax_bwd) break;
     chunk = 4;
   }
-  PD_HIP(hipMemcpyAsync(S.hdstat, S.dstat, 32 * sizeof(double), hipMemcpyDeviceToHost, st));
-  PD_HIP(hipStreamSynchronize(st));
   if (bstat_host) {
     for (int j = 0; j < 4; ++j) bstat_host[j] = S.hdstat[4 + j];
     bstat_host[4] = S.hdstat[16];
@@ -1400,9 +1401,9 @@ int pd_step_backward(pd_scene* scene, const void* ckpt, const double* gq_next, c
     std::swap(S.mu_h1, S.mu_h2);
     S.adj_hist = std::min(S.adj_hist + 1, 2);
   }
+  // the gradient routing is stream-ordered; the statistics were read with the last check
   launch_grad_elem(E, V, ck, S.jac, S.mu, S.contrib, g_logE_accum, st);
   launch_grad_vert(V, S.mu, S.contrib, gv_next, gq_t, gv_t, gf_ext, st);
-  PD_HIP(hipStreamSynchronize(st));
   PD_HIP(hipGetLastError());
   const int status = S.hctl[kCtlAdj + 1];
   if (stats) {

@@ -121,6 +121,9 @@ struct StepState {
   double* dstat;
   const double* fb = nullptr;  // contact: FB residual of the last contact solve (null without contact rows)
   double fb_tol = 0.0;
+  int* sig = nullptr;          // mapped host signal block (null: no signal)
+  double* sigd = nullptr;
+  int seq = 0;
 };
 
 struct AdjState {
@@ -132,6 +135,10 @@ struct AdjState {
   int* ctl;       // [iters, status]
   int* done;
   double* dstat;  // [residual]
+  int* sig = nullptr;             // mapped host signal block (null: no signal)
+  double* sigd = nullptr;
+  const double* trstat = nullptr;  // trust-region figures, copied into the signal
+  int seq = 0;
 };
 
 // Contact rows of one step (forward: every candidate row; adjoint: the active

@@ -685,6 +685,15 @@ __device__ __forceinline__ void b_Eb(VertArgs Vx, SolveArgs Sv, StepState St, Ad
         St.ctl[kCtlIters] = k;
         St.ctl[kCtlStatus] = conv ? 0 : 1;
         St.dstat[0] = dq; St.dstat[1] = nq; St.dstat[2] = db; St.dstat[3] = nb;
+        if (St.sig) {  // statistics first, then the sequence number (system-scope ordered)
+          St.sigd[0] = dq; St.sigd[1] = nq; St.sigd[2] = db; St.sigd[3] = nb;
+          St.sig[1] = k;
+          St.sig[2] = conv ? 0 : 1;
+          St.sig[3] = St.ctl[kCtlResets];
+          St.sig[4] = St.ctl[kCtlNewton];
+          __threadfence_system();
+          St.sig[0] = St.seq;
+        }
       }
     }
   } else {
@@ -1395,6 +1404,14 @@ __device__ __forceinline__ PCGCtl adj_control(const AdjState& A, const RedArgs& 
         *A.done = 1;
         A.ctl[0] = it;
         A.ctl[1] = conv ? 0 : 1;
+        if (A.sig) {  // statistics first, then the sequence number (system-scope ordered)
+          A.sigd[8] = res;
+          for (int j = 0; j < 4; ++j) A.sigd[4 + j] = A.trstat[j];
+          A.sig[9] = it;
+          A.sig[10] = conv ? 0 : 1;
+          __threadfence_system();
+          A.sig[8] = A.seq;
+        }
       }
     }
   }

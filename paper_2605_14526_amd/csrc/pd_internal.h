@@ -85,7 +85,8 @@ struct DeviceSolve {
 // Per-launch timing of one kernel with HIP events (roofline instrumentation).
 struct KernelTimer {
   int which = -1;
-  std::vector<hipEvent_t> ev;  // begin/end pairs
+  std::vector<hipEvent_t> ev;  // begin/end pairs, a ring: pending pairs head .. head + used - 1
+  int head = 0;
   int used = 0;
   double total_ms = 0.0;
   long long launches = 0, working = 0;
@@ -136,6 +137,15 @@ struct Scene {
   double* dstat = nullptr;      // device statistics
   int* hctl = nullptr;          // pinned host mirror of ctl
   double* hdstat = nullptr;     // pinned host mirror of dstat
+  // decision signals: the kernel that decides a loop writes its statistics and
+  // then a sequence number into mapped host memory, so the host learns the
+  // decision without draining the stream
+  int* sig_h = nullptr;         // [0] forward sequence, [1..4] iters, status, resets, newton cap;
+                                // [8] adjoint sequence, [9] iters, [10] status
+  int* sig_d = nullptr;
+  double* sigd_h = nullptr;     // [0..3] gate norms, [4..7] trust-region figures, [8] adjoint residual
+  double* sigd_d = nullptr;
+  int seq_fwd = 0, seq_adj = 0;
   // deterministic reductions
   double* red_part = nullptr;
   double* red_fin = nullptr;

@@ -4,6 +4,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <atomic>
 #include <cmath>
 #include <cstdio>
 #include <cstring>
@@ -254,6 +255,10 @@ void free_device(Scene& S) {
   contact_free(S);
   if (S.hctl) (void)hipHostFree(S.hctl);
   if (S.hdstat) (void)hipHostFree(S.hdstat);
+  if (S.sig_h) (void)hipHostFree(S.sig_h);
+  if (S.sigd_h) (void)hipHostFree(S.sigd_h);
+  S.sig_h = S.sig_d = nullptr;
+  S.sigd_h = S.sigd_d = nullptr;
   S.hctl = nullptr;
   S.hdstat = nullptr;
   for (hipEvent_t e : S.kt.ev) (void)hipEventDestroy(e);
@@ -264,15 +269,24 @@ void free_device(Scene& S) {
 enum { kKLocal = 0, kKGather = 1, kKTop = 2, kKBottom = 3, kKEb = 4, kKApplyK = 5, kKCount = 6 };
 constexpr int kTimerPairs = 1024;
 
-void kt_flush(Scene& S) {
+// Adds the durations of the pending event pairs in launch order; without
+// `all`, it stops at the first pair whose kernel has not finished.
+void kt_flush(Scene& S, bool all = false) {
   KernelTimer& T = S.kt;
-  for (int i = 0; i < T.used; ++i) {
+  while (T.used > 0) {
+    const int i = T.head;
+    if (!all) {
+      const hipError_t q = hipEventQuery(T.ev[2 * i + 1]);
+      if (q == hipErrorNotReady) break;
+      PD_HIP(q);
+    }
     float ms = 0.0f;
     PD_HIP(hipEventElapsedTime(&ms, T.ev[2 * i], T.ev[2 * i + 1]));
     T.total_ms += ms;
     T.launches++;
+    T.head = (T.head + 1) % kTimerPairs;
+    T.used--;
   }
-  T.used = 0;
 }
 
 inline void kt_begin(Scene& S, int id, hipStream_t st) {
@@ -280,9 +294,31 @@ inline void kt_begin(Scene& S, int id, hipStream_t st) {
   if (T.which != id) return;
   if (T.used == kTimerPairs) {
     PD_HIP(hipStreamSynchronize(st));
-    kt_flush(S);
+    kt_flush(S, true);
   }
-  arm_launch_events(T.ev[2 * T.used], T.ev[2 * T.used + 1]);
+  const int i = (T.head + T.used) % kTimerPairs;
+  arm_launch_events(T.ev[2 * i], T.ev[2 * i + 1]);
+}
+
+// Waits for the decision signal `seq` in slot `slot` of the mapped block, or
+// for the stream to drain without it (the chunk of iterations ended before a
+// decision).  Returns whether the signal arrived.
+bool wait_signal(Scene& S, int slot, int seq, hipStream_t st) {
+  volatile int* f = S.sig_h + slot;
+  for (unsigned spin = 0;; ++spin) {
+    if (*f == seq) {
+      std::atomic_thread_fence(std::memory_order_acquire);
+      return true;
+    }
+    if ((spin & 31u) == 31u) {
+      const hipError_t q = hipStreamQuery(st);
+      if (q == hipSuccess) {
+        std::atomic_thread_fence(std::memory_order_acquire);
+        return *f == seq;
+      }
+      if (q != hipErrorNotReady) PD_HIP(q);
+    }
+  }
 }
 
 inline void kt_end(Scene& S, int id, hipStream_t st) {
@@ -500,6 +536,12 @@ void setup_scene(Scene& S, const pd_mesh_desc* mesh, const pd_material_desc* mat
   S.dstat = dalloc<double>(32);
   PD_HIP(hipHostMalloc((void**)&S.hctl, kCtlTotal * sizeof(int)));
   PD_HIP(hipHostMalloc((void**)&S.hdstat, 32 * sizeof(double)));
+  PD_HIP(hipHostMalloc((void**)&S.sig_h, 16 * sizeof(int), hipHostMallocMapped | hipHostMallocCoherent));
+  PD_HIP(hipHostMalloc((void**)&S.sigd_h, 16 * sizeof(double), hipHostMallocMapped | hipHostMallocCoherent));
+  std::memset(S.sig_h, 0, 16 * sizeof(int));
+  std::memset(S.sigd_h, 0, 16 * sizeof(double));
+  PD_HIP(hipHostGetDevicePointer((void**)&S.sig_d, S.sig_h, 0));
+  PD_HIP(hipHostGetDevicePointer((void**)&S.sigd_d, S.sigd_h, 0));
   S.jac = dalloc<double>(33 * (size_t)ne);
   S.mu = dalloc<double>(V3); S.r0 = dalloc<double>(V3); S.r1 = dalloc<double>(V3); S.z = dalloc<double>(V3);
   S.p = dalloc<double>(V3); S.Ap = dalloc<double>(V3); S.wv = dalloc<double>(V3); S.qbar = dalloc<double>(V3);
@@ -1212,6 +1254,9 @@ int pd_step_forward(pd_scene* scene, const double* q_t, const double* v_t, const
     T.fb = S.c_fb;
     T.fb_tol = S.fb_tol;
   }
+  T.sig = S.sig_d;
+  T.sigd = S.sigd_d;
+  T.seq = ++S.seq_fwd;
   int k = 0;
   int chunk = S.iters_per_check > 0 ? S.iters_per_check : std::max(3, S.last_fwd_iters + 1);
   for (;;) {
@@ -1229,10 +1274,17 @@ int pd_step_forward(pd_scene* scene, const double* q_t, const double* v_t, const
         PD_TIMED(S, kKBottom, st, launch_bottom(kModeFwd, V, A, T, Ad, R, nullptr, S.qhat, k, st));
       }
     }
-    // the control block and the gate norms are final once the done flag is seen
-    PD_HIP(hipMemcpyAsync(S.hctl, S.ctl, kCtlSize * sizeof(int), hipMemcpyDeviceToHost, st));
-    PD_HIP(hipMemcpyAsync(S.hdstat, S.dstat, 8 * sizeof(double), hipMemcpyDeviceToHost, st));
-    PD_HIP(hipStreamSynchronize(st));
+    // the deciding kernel signals with its statistics; kernels still queued
+    // behind it exit at once, so the host does not wait for them
+    const bool decided = wait_signal(S, 0, T.seq, st);
+    S.hctl[kCtlDone] = decided ? 1 : 0;
+    if (decided) {
+      S.hctl[kCtlIters] = S.sig_h[1];
+      S.hctl[kCtlStatus] = S.sig_h[2];
+      S.hctl[kCtlResets] = S.sig_h[3];
+      S.hctl[kCtlNewton] = S.sig_h[4];
+      for (int j = 0; j < 4; ++j) S.hdstat[j] = S.sigd_h[j];
+    }
     kt_flush(S);
     if (S.hctl[kCtlDone] || k >= S.kmax_fwd) break;
     chunk = S.iters_per_check > 0 ? S.iters_per_check : 2;
@@ -1287,7 +1339,11 @@ static void adjoint_solve(Scene& S, hipStream_t st, double tau_force, double* bs
   const ElemArgs E = elem_args(S);
   const VertArgs V = vert_args(S);
   const SolveArgs Sv = solve_args(S);
-  const AdjState Ad = adj_state(S);
+  AdjState Ad = adj_state(S);
+  Ad.sig = S.sig_d;
+  Ad.sigd = S.sigd_d;
+  Ad.trstat = S.dstat + 4;
+  Ad.seq = ++S.seq_adj;
   RedArgs R = red_args(S);
   // with active contact rows every preconditioner solve is projected onto
   // J_A mu = 0 and the per-row work moves to the correction kernel
@@ -1348,10 +1404,15 @@ static void adjoint_solve(Scene& S, hipStream_t st, double tau_force, double* bs
         }
       }
     }
-    // the control block, the trust-region figures and the residual are final once done is seen
-    PD_HIP(hipMemcpyAsync(S.hctl, S.ctl, kCtlTotal * sizeof(int), hipMemcpyDeviceToHost, st));
-    PD_HIP(hipMemcpyAsync(S.hdstat, S.dstat, 32 * sizeof(double), hipMemcpyDeviceToHost, st));
-    PD_HIP(hipStreamSynchronize(st));
+    // the deciding kernel signals with its statistics (see the forward loop)
+    const bool decided = wait_signal(S, 8, Ad.seq, st);
+    S.hctl[kCtlAdj + 2] = decided ? 1 : 0;
+    if (decided) {
+      S.hctl[kCtlAdj] = S.sig_h[9];
+      S.hctl[kCtlAdj + 1] = S.sig_h[10];
+      for (int j = 0; j < 4; ++j) S.hdstat[4 + j] = S.sigd_h[4 + j];
+      S.hdstat[16] = S.sigd_h[8];
+    }
     kt_flush(S);
     if (S.hctl[kCtlAdj + 2] || it > S.kmax_bwd) break;
     chunk = 4;
@@ -1506,7 +1567,9 @@ int pd_kernel_timer(pd_scene* scene, int kernel) {
     T.ev.resize(2 * kTimerPairs);
     for (auto& e : T.ev) PD_HIP(hipEventCreate(&e));
   }
+  PD_HIP(hipDeviceSynchronize());
   T.which = kernel;
+  T.head = 0;
   T.used = 0;
   T.total_ms = 0.0;
   T.launches = 0;
@@ -1524,7 +1587,7 @@ int pd_kernel_timer_read(pd_scene* scene, double* total_ms, int64_t* launches, i
   PD_TRY
   Scene& S = scene->S;
   PD_HIP(hipDeviceSynchronize());
-  kt_flush(S);
+  kt_flush(S, true);
   if (total_ms) *total_ms = S.kt.total_ms;
   if (launches) *launches = S.kt.launches;
   if (working) *working = S.kt.working;

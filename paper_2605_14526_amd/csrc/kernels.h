@@ -48,10 +48,14 @@ constexpr int kFinStride = 64;  // doubles per site in the final buffer
 #ifndef PD_TOP_UNROLL
 #define PD_TOP_UNROLL 8
 #endif
+#ifndef PD_ELEM_BLOCK
+#define PD_ELEM_BLOCK 256
+#endif
 constexpr int kBottomThreads = PD_BOTTOM_THREADS;  // subdomain solve: 64 threads (one row) per wave
 constexpr int kBottomUnroll = PD_BOTTOM_UNROLL;  // loads in flight per lane in the subdomain solve's row loops
 constexpr int kEbUnroll = PD_EB_UNROLL;
 constexpr int kTopUnroll = PD_TOP_UNROLL;
+constexpr int kElemBlock = PD_ELEM_BLOCK;  // tets per workgroup of the single-scene local step and K apply
 
 struct RedArgs {
   double* part;    // per site: max_parts x kRedWidth

@@ -1784,6 +1784,7 @@ __global__ void __launch_bounds__(64) kb_flags(BatchMap M, int* __restrict__ ctl
 
 // ================================================================= launchers
 #define PD_GRID(n) dim3(((n) + kBlock - 1) / kBlock), dim3(kBlock)
+#define PD_EGRID(n) dim3(((n) + kElemBlock - 1) / kElemBlock), dim3(kElemBlock)
 
 // Every launch goes through the extended launch, which can stamp a start and
 // a stop event from the dispatch itself (the kernel's own execution time, the
@@ -1845,7 +1846,7 @@ void launch_contact_apply_adj(int mode, const VertArgs& V, const AdjState& A, co
 void launch_local(const ElemArgs& E, const StepState& St, const RedArgs& R, const double* q, int nv, int nf,
                   int k, int fwd, hipStream_t s) {
   int* cap = fwd ? St.ctl + kCtlNewton : nullptr;
-#define PD_LOCAL(M) launch_ext(k_local<M>, PD_GRID(E.ne), 0, s, E, St, R, q, nv, nf, k, fwd, cap)
+#define PD_LOCAL(M) launch_ext(k_local<M>, PD_EGRID(E.ne), 0, s, E, St, R, q, nv, nf, k, fwd, cap)
   switch (fwd ? St.m : 0) {
     case 1: PD_LOCAL(1); break;
     case 2: PD_LOCAL(2); break;
@@ -1940,10 +1941,10 @@ void launch_bwd_elem(const ElemArgs& E, const VertArgs& V, const RedArgs& R, con
 }
 void launch_apply_K(int mode, const ElemArgs& E, const VertArgs& V, const AdjState& A, const RedArgs& R,
                     const double* jac, const double* x, int it, hipStream_t s) {
-  if (mode == kModePCG) launch_ext(k_apply_K<kModePCG>, PD_GRID(E.ne), 0, s, E, V, A, R, jac, x, it);
-  else if (mode == kModeFixed) launch_ext(k_apply_K<kModeFixed>, PD_GRID(E.ne), 0, s, E, V, A, R, jac, x, it);
-  else if (mode == kModeAmK) launch_ext(k_apply_K<kModeAmK>, PD_GRID(E.ne), 0, s, E, V, A, R, jac, x, it);
-  else launch_ext(k_apply_K<kModeDebug>, PD_GRID(E.ne), 0, s, E, V, A, R, jac, x, it);
+  if (mode == kModePCG) launch_ext(k_apply_K<kModePCG>, PD_EGRID(E.ne), 0, s, E, V, A, R, jac, x, it);
+  else if (mode == kModeFixed) launch_ext(k_apply_K<kModeFixed>, PD_EGRID(E.ne), 0, s, E, V, A, R, jac, x, it);
+  else if (mode == kModeAmK) launch_ext(k_apply_K<kModeAmK>, PD_EGRID(E.ne), 0, s, E, V, A, R, jac, x, it);
+  else launch_ext(k_apply_K<kModeDebug>, PD_EGRID(E.ne), 0, s, E, V, A, R, jac, x, it);
 }
 void launch_adj_gather(int mode, const VertArgs& V, const AdjState& A, const RedArgs& R, int it, hipStream_t s) {
   const dim3 g(vert_group_blocks(V.nf)), b(kBlock);

@@ -435,9 +435,10 @@ __global__ void __launch_bounds__(64) k_contact_fb_wave(VertArgs Vx, ContactArgs
         om = 1.0 - 1.0 / sqrt(2.0);
         E = r * (1.0 - 1.0 / sqrt(2.0));
       } else {
+        const double is = 1.0 / sq;  // one division on the serial path
         phi = a + b - sq;
-        om = 1.0 - a / sq;
-        E = r * (1.0 - b / sq);
+        om = 1.0 - a * is;
+        E = r * (1.0 - b * is);
       }
       mx = fabs(phi);
     }
@@ -496,9 +497,10 @@ __global__ void __launch_bounds__(64) k_contact_fb_wave(VertArgs Vx, ContactArgs
         ok = false;
         break;
       }
-      const double dj = sqrt(piv);
-      if (lane == j) M[j * 65 + j] = dj;
-      else if (lane > j && lane < na) M[lane * 65 + j] = sv / dj;
+      // the diagonal keeps 1 / L_jj, so neither substitution divides
+      const double ij = 1.0 / sqrt(piv);
+      if (lane == j) M[j * 65 + j] = ij;
+      else if (lane > j && lane < na) M[lane * 65 + j] = sv * ij;
       __syncthreads();
     }
     if (!ok) {
@@ -507,12 +509,12 @@ __global__ void __launch_bounds__(64) k_contact_fb_wave(VertArgs Vx, ContactArgs
     }
     // forward substitution L z = y, then back substitution L^T x = z (lane p holds entry p)
     for (int j = 0; j < na; ++j) {
-      const double zj = __shfl(y, j, 64) / M[j * 65 + j];
+      const double zj = __shfl(y, j, 64) * M[j * 65 + j];
       if (lane == j) y = zj;
       else if (lane > j && lane < na) y -= M[lane * 65 + j] * zj;
     }
     for (int i = na - 1; i >= 0; --i) {
-      const double xi = __shfl(y, i, 64) / M[i * 65 + i];
+      const double xi = __shfl(y, i, 64) * M[i * 65 + i];
       if (lane == i) y = xi;
       if (lane < i) y -= M[i * 65 + lane] * xi;
     }

@@ -136,6 +136,11 @@ template <int KIND>
 constexpr int kin() { return KIND == kEnc ? kMpnF : (KIND == kMsg ? kMpnKM : 2 * kMpnH); }
 template <int KIND>
 constexpr int kpad() { return (kin<KIND>() + 15) / 16 * 16; }
+// stages of 64 rows per weight-gradient workgroup: per-vertex layers (a few
+// thousand rows) use one, so they spread over more workgroups; the per-edge
+// layer uses two
+template <int KIND>
+constexpr int wstages() { return KIND == kMsg ? 2 : 1; }
 
 // ---------------------------------------------------------------- forward layer
 // Z = A W + b for 64 rows per workgroup; epilogue by kind:
@@ -350,7 +355,7 @@ __global__ void __launch_bounds__(256) k_mpn_scatter(MpnArgs M, const float* __r
 }
 
 // Weight gradient partials: dW(k, n) = sum_r A(r, k) dz(r, n), db(n) = sum_r dz(r, n),
-// over 256 rows per workgroup (four stages of 64), written to part[blk].
+// over 64 wstages rows per workgroup (stages of 64), written to part[blk].
 template <bool BF, int KIND>
 __global__ void __launch_bounds__(256) k_mpn_wgrad(MpnArgs M, const float* __restrict__ hin, const float* __restrict__ dz,
                                                    float* __restrict__ part, int rows) {
@@ -365,8 +370,9 @@ __global__ void __launch_bounds__(256) k_mpn_wgrad(MpnArgs M, const float* __res
 #pragma unroll
   for (int j = 0; j < (NT + 3) / 4; ++j) acc[j] = f32x4{0.f, 0.f, 0.f, 0.f};
   float bsum = 0.0f;  // thread c < 64: db partial of column c
-  for (int st = 0; st < 4; ++st) {
-    const int r0 = blockIdx.x * 256 + st * 64;
+  constexpr int NS = wstages<KIND>();
+  for (int st = 0; st < NS; ++st) {
+    const int r0 = blockIdx.x * (64 * NS) + st * 64;
     __syncthreads();
     for (int e = threadIdx.x; e < 64 * KP; e += blockDim.x) {
       const int rr = e / KP, k = e % KP, r = r0 + rr;
@@ -561,7 +567,7 @@ template <bool BF, int KIND>
 static void mpn_wgrad(MpnImpl& N, const float* hin, const float* dz, int rows, size_t woff, size_t boff,
                       hipStream_t s) {
   constexpr int K = kin<KIND>();
-  const int nblk = mpn_grid_rows(rows, 256);
+  const int nblk = mpn_grid_rows(rows, 64 * wstages<KIND>());
   const int width = K * kMpnH + kMpnH;
   hipLaunchKernelGGL((k_mpn_wgrad<BF, KIND>), dim3(nblk), dim3(256), 0, s, N.A, hin, dz, N.part, rows);
   // the weight block and the bias block are contiguous in the partial rows but not in P:
@@ -763,7 +769,7 @@ int pd_mpn_create(const pd_mesh_desc* mesh, const pd_mpn_desc* desc, pd_mpn** ou
     N.dy = dalloc<float>((size_t)nv * 3);
     N.res = dalloc<double>((size_t)nv * 3);
     // weight-gradient partials: the widest layer over the most chunks
-    const size_t chunks = (rows + 255) / 256 + (nv + 3) / 4;
+    const size_t chunks = (rows + 63) / 64 + (nv + 3) / 4;
     N.part_cap = chunks * (size_t)(kMpnKM * kMpnH + kMpnH);
     N.part = dalloc<float>(N.part_cap);
     N.lpart = dalloc<double>((nv + 255) / 256);

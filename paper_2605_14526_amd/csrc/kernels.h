@@ -30,35 +30,46 @@ enum { kCtlDone = 0, kCtlIters = 1, kCtlStatus = 2, kCtlResets = 3, kCtlNewton =
 
 // Deterministic cross-block reductions without atomics: each producing block
 // writes its partial vector; the first kernel that needs the total sums all
-// partials in a fixed order (thread t takes partials t, t + blockDim, ...,
-// then a fixed tree) and its block 0 stores the total in `fin` for the kernels
-// after it.
+// partials in a fixed order (lane l of the first wave takes partials l,
+// l + 64, ..., then the wave's butterfly) and its block 0 stores the total in
+// `fin` for the kernels after it.
 enum { kRedGate = 0, kRedAA = 1, kRedPW = 2, kRedRZ0 = 3, kRedRZ1 = 4, kRedTR = 5, kRedFix = 6, kRedSites = 7 };
 constexpr int kRedWidth = 32;   // doubles per partial
 constexpr int kFinStride = 64;  // doubles per site in the final buffer
 #ifndef PD_BOTTOM_THREADS
 #define PD_BOTTOM_THREADS 512
 #endif
-#ifndef PD_BOTTOM_UNROLL
-#define PD_BOTTOM_UNROLL 8
+#ifndef PD_BOTTOM_CHUNK
+#define PD_BOTTOM_CHUNK 4
 #endif
-#ifndef PD_EB_UNROLL
-#define PD_EB_UNROLL 4
+#ifndef PD_BOTTOM_CHUNK_E
+#define PD_BOTTOM_CHUNK_E 3
 #endif
-#ifndef PD_TOP_UNROLL
-#define PD_TOP_UNROLL 8
+#ifndef PD_EB_CHUNK
+#define PD_EB_CHUNK 8
+#endif
+#ifndef PD_TOP_CHUNK
+#define PD_TOP_CHUNK 8
 #endif
 #ifndef PD_ELEM_BLOCK
 #define PD_ELEM_BLOCK 256
 #endif
 constexpr int kBottomThreads = PD_BOTTOM_THREADS;  // subdomain solve: 64 threads (one row) per wave
-constexpr int kBottomUnroll = PD_BOTTOM_UNROLL;  // loads in flight per lane in the subdomain solve's row loops
-constexpr int kEbUnroll = PD_EB_UNROLL;
-constexpr int kTopUnroll = PD_TOP_UNROLL;
+// Row walks of the solve kernels: a wave takes its row in chunks of 64 x chunk
+// entries and each lane requests all of its chunk's entries before it uses
+// any, so a chunk costs one memory round trip.
+constexpr int kBottomChunk = PD_BOTTOM_CHUNK;     // subdomain solve, Z_s rows
+constexpr int kBottomChunkE = PD_BOTTOM_CHUNK_E;  // subdomain solve, E_s^T rows
+constexpr int kEbChunk = PD_EB_CHUNK;          // interface right-hand side (E_s rows)
+constexpr int kTopChunk = PD_TOP_CHUNK;        // interface solve (Z rows)
+// Row-walking kernels ask for at most 4 waves per SIMD: the compiler may then
+// spend up to 128 registers on a chunk's loads instead of trading them for
+// occupancy by waiting between them (the grids need no more than 4 anyway).
+#define PD_ROW_WALK __attribute__((amdgpu_waves_per_eu(4, 4)))
 constexpr int kElemBlock = PD_ELEM_BLOCK;  // tets per workgroup of the single-scene local step and K apply
 
 struct RedArgs {
-  double* part;    // per site: max_parts x kRedWidth
+  double* part;    // per site: kRedWidth x max_parts (value j of partial b at [j][b])
   double* fin;     // per site: kFinStride doubles
   int max_parts;
   int nparts[kRedSites];  // producing blocks of each site

@@ -33,6 +33,33 @@ __device__ __forceinline__ double wave_sum(double v) {
   return v;
 }
 
+// A value that every lane of the wave holds, moved to a scalar register (row
+// descriptors of one-row-per-wave kernels), so that addresses built from it
+// are scalar bases.
+__device__ __forceinline__ int wave_uniform(int x) { return __builtin_amdgcn_readfirstlane(x); }
+__device__ __forceinline__ long long wave_uniform(long long x) {
+  const unsigned lo = (unsigned)__builtin_amdgcn_readfirstlane((int)(x & 0xffffffffLL));
+  const unsigned hi = (unsigned)__builtin_amdgcn_readfirstlane((int)((unsigned long long)x >> 32));
+  return (long long)(((unsigned long long)hi << 32) | lo);
+}
+
+// base[i] read through a 32-bit byte offset o = 8 i: with a scalar base the
+// load keeps only o in a vector register
+__device__ __forceinline__ double at_byte(const double* __restrict__ base, unsigned o) {
+  return *reinterpret_cast<const double*>(reinterpret_cast<const char*>(base) + o);
+}
+
+// Workgroups are dealt to the chip's 8 XCDs round-robin (XCD = block id mod
+// 8), each XCD with its own L2.  The element kernels renumber their blocks so
+// that every XCD takes one contiguous range of tets: neighbouring tets share
+// vertices, so their gathers and scattered contribution writes meet in one L2.
+// A bijection on 0 .. n - 1 for any n.
+__device__ __forceinline__ int xcd_block(int b, int n) {
+  constexpr int kXcd = 8;
+  const int x = b % kXcd, i = b / kXcd, q = n / kXcd, r = n % kXcd;
+  return (x < r) ? x * (q + 1) + i : r * (q + 1) + (x - r) * q + i;
+}
+
 // sum within aligned groups of 8 lanes (every lane of the group gets it)
 __device__ __forceinline__ double group8_sum(double v) {
   v += __shfl_xor(v, 4, 64);
@@ -66,39 +93,58 @@ __device__ __forceinline__ void block_sum(double (&v)[NV], double* lds /* >= 16*
 
 // Producer side: block sum of N values, written by thread 0 as partial `idx`
 // of `site`.  Every thread of the block must call it.
+// Value j of every partial of `site`, indexed by the producing block: the
+// values a consumer reads from consecutive partials are contiguous.
+__device__ __forceinline__ double* part_value(const RedArgs& R, int site, int j) {
+  return R.part + ((size_t)site * kRedWidth + j) * R.max_parts;
+}
+
 template <int N>
 __device__ __forceinline__ void write_partial(double (&v)[N], const RedArgs& R, int site, int idx) {
   __shared__ double red[16 * N];
   block_sum<N>(v, red);
-  if (threadIdx.x == 0) {
-    double* part = R.part + ((size_t)site * R.max_parts + idx) * kRedWidth;
+  if (threadIdx.x == 0)
 #pragma unroll
-    for (int j = 0; j < N; ++j) part[j] = v[j];
-  }
+    for (int j = 0; j < N; ++j) part_value(R, site, j)[idx] = v[j];
 }
 
-// Consumer side: the total of the first N values of every partial of `site`
-// (fixed order), returned to every thread; block 0 (bid) also stores it in fin.
+// Consumer side: the total of the first N values of every partial of `site`,
+// returned to every thread; block 0 (bid) also stores it in fin.  Wave 0 does
+// the sum in a fixed order that does not depend on the block size: lane l
+// takes partials l, l + 64, l + 128, ... (a chunk of them requested at once),
+// then the wave's butterfly.
 template <int N>
 __device__ __forceinline__ void consume(const RedArgs& R, int site, double (&tot)[N], int bid, int width = N) {
-  __shared__ double red[16 * N];
+  constexpr int kChunk = N <= 4 ? 8 : (N <= 8 ? 4 : 1);
   __shared__ double bc[N];
-  const double* part = R.part + (size_t)site * R.max_parts * kRedWidth;
-  const int np = R.nparts[site];
+  if (threadIdx.x < 64) {
+    const int lane = threadIdx.x;
+    const int np = R.nparts[site];
+    double acc[N];
 #pragma unroll
-  for (int j = 0; j < N; ++j) tot[j] = 0.0;
-#pragma unroll 2
-  for (int b = threadIdx.x; b < np; b += blockDim.x)
+    for (int j = 0; j < N; ++j) acc[j] = 0.0;
+    for (int base = 0; base < np; base += 64 * kChunk) {
+      double v[kChunk][N];
 #pragma unroll
-    for (int j = 0; j < N; ++j)
-      if (j < width) tot[j] += part[(size_t)b * kRedWidth + j];
-  block_sum<N>(tot, red);
-  if (threadIdx.x == 0) {
+      for (int c = 0; c < kChunk; ++c) {
+        const int b = min(base + lane + 64 * c, np - 1);
 #pragma unroll
-    for (int j = 0; j < N; ++j) {
-      bc[j] = tot[j];
-      if (bid == 0) R.fin[site * kFinStride + j] = tot[j];
+        for (int j = 0; j < N; ++j) v[c][j] = (j < width) ? part_value(R, site, j)[b] : 0.0;
+      }
+#pragma unroll
+      for (int c = 0; c < kChunk; ++c)
+        if (base + lane + 64 * c < np)
+#pragma unroll
+          for (int j = 0; j < N; ++j) acc[j] += v[c][j];
     }
+#pragma unroll
+    for (int j = 0; j < N; ++j) acc[j] = wave_sum(acc[j]);
+    if (lane == 0)
+#pragma unroll
+      for (int j = 0; j < N; ++j) {
+        bc[j] = acc[j];
+        if (bid == 0) R.fin[site * kFinStride + j] = acc[j];
+      }
   }
   __syncthreads();
 #pragma unroll
@@ -453,7 +499,7 @@ __device__ __forceinline__ void b_local(ElemArgs E, StepState St, RedArgs R, con
 template <int M>
 __global__ void __launch_bounds__(kBlock) k_local(ElemArgs E, StepState St, RedArgs R, const double* __restrict__ q,
                                                   int nv, int nf, int k, int fwd, int* __restrict__ newton_cap) {
-  b_local<M>(E, St, R, q, nv, nf, k, fwd, newton_cap, blockIdx.x);
+  b_local<M>(E, St, R, q, nv, nf, k, fwd, newton_cap, xcd_block(blockIdx.x, gridDim.x));
 }
 
 // G_e^T (w G_e x): contributions of the symmetric element operator w V G^T G
@@ -707,26 +753,39 @@ __device__ __forceinline__ void b_Eb(VertArgs Vx, SolveArgs Sv, StepState St, Ad
   int B[kMaxCoup], P[kMaxCoup];
 #pragma unroll
   for (int c = 0; c < kMaxCoup; ++c) {
-    B[c] = __shfl(cd.b0, c, 64);
-    P[c] = __shfl(cd.pre, c, 64);
+    B[c] = wave_uniform(__shfl(cd.b0, c, 64));
+    P[c] = wave_uniform(__shfl(cd.pre, c, 64));
   }
-  const double* __restrict__ Er = Sv.E + er.off;
+  const int len = wave_uniform(er.len), ncp = wave_uniform(er.n);
+  const double* __restrict__ Er = Sv.E + wave_uniform(er.off);
   double a0 = 0, a1 = 0, a2 = 0;
-#pragma unroll kEbUnroll
-  for (int idx = lane; idx < er.len; idx += 64) {
-    int col = B[0] + idx;
+  // entries past the end repeat the last one with weight zero
+  constexpr int kSpan = 64 * kEbChunk;
+  for (int base = 0; base < len; base += kSpan) {
+    // all loads of the chunk first ...
+    double cf[kEbChunk], y[kEbChunk][3], w[kEbChunk][3];
 #pragma unroll
-    for (int c = 1; c < kMaxCoup; ++c)
-      if (c < er.n && idx >= P[c]) col = B[c] + idx - P[c];
-    const double e = Er[idx];
-    if (MODE == kModePCG) {
-      a0 += e * (src[col] - alpha * wv[col]);
-      a1 += e * (src[nv + col] - alpha * wv[nv + col]);
-      a2 += e * (src[2 * nv + col] - alpha * wv[2 * nv + col]);
-    } else {
-      a0 += e * src[col];
-      a1 += e * src[nv + col];
-      a2 += e * src[2 * nv + col];
+    for (int j = 0; j < kEbChunk; ++j) {
+      const int idx = min(base + lane + 64 * j, len - 1);
+      int col = B[0] + idx;
+#pragma unroll
+      for (int c = 1; c < kMaxCoup; ++c)
+        if (c < ncp && idx >= P[c]) col = B[c] + idx - P[c];
+      const unsigned oc = 8u * (unsigned)col;
+      cf[j] = at_byte(Er, 8u * (unsigned)idx);
+#pragma unroll
+      for (int a = 0; a < 3; ++a) {
+        y[j][a] = at_byte(src + a * nv, oc);
+        if (MODE == kModePCG) w[j][a] = at_byte(wv + a * nv, oc);
+      }
+    }
+    // ... then the arithmetic
+#pragma unroll
+    for (int j = 0; j < kEbChunk; ++j) {
+      const double c = (base + lane + 64 * j < len) ? cf[j] : 0.0;
+      a0 += c * (MODE == kModePCG ? y[j][0] - alpha * w[j][0] : y[j][0]);
+      a1 += c * (MODE == kModePCG ? y[j][1] - alpha * w[j][1] : y[j][1]);
+      a2 += c * (MODE == kModePCG ? y[j][2] - alpha * w[j][2] : y[j][2]);
     }
   }
   a0 = wave_sum(a0);
@@ -742,7 +801,7 @@ __device__ __forceinline__ void b_Eb(VertArgs Vx, SolveArgs Sv, StepState St, Ad
 }
 
 template <int MODE>
-__global__ void __launch_bounds__(kBlock) k_Eb(VertArgs Vx, SolveArgs Sv, StepState St, AdjState A, RedArgs R,
+__global__ void __launch_bounds__(kBlock) PD_ROW_WALK k_Eb(VertArgs Vx, SolveArgs Sv, StepState St, AdjState A, RedArgs R,
                                                const double* __restrict__ rhs, int k) {
   b_Eb<MODE>(Vx, Sv, St, A, R, rhs, k, blockIdx.x);
 }
@@ -779,12 +838,37 @@ __device__ __forceinline__ void b_top(VertArgs Vx, SolveArgs Sv, double* __restr
     }
     __syncthreads();
     if (have) {
-#pragma unroll kTopUnroll
-      for (int j = lane; j < tl; j += 64) {
-        const double z = Zi[t0 + j];
-        a0 += z * rs[j];
-        a1 += z * rs[kTile + j];
-        a2 += z * rs[2 * kTile + j];
+      // whole chunks, then the last partial one (its entries past the end
+      // repeat the last entry with weight zero)
+      constexpr int kSpan = 64 * kTopChunk;
+      int base = 0;
+      for (; base + kSpan <= tl; base += kSpan) {
+        double zc[kTopChunk];
+#pragma unroll
+        for (int j = 0; j < kTopChunk; ++j) zc[j] = Zi[t0 + base + lane + 64 * j];
+#pragma unroll
+        for (int j = 0; j < kTopChunk; ++j) {
+          const int jj = base + lane + 64 * j;
+          a0 += zc[j] * rs[jj];
+          a1 += zc[j] * rs[kTile + jj];
+          a2 += zc[j] * rs[2 * kTile + jj];
+        }
+      }
+      if (base < tl) {
+        double zc[kTopChunk];
+#pragma unroll
+        for (int j = 0; j < kTopChunk; ++j) {
+          const int jj = base + lane + 64 * j;
+          const double z = Zi[t0 + min(jj, tl - 1)];
+          zc[j] = (jj < tl) ? z : 0.0;
+        }
+#pragma unroll
+        for (int j = 0; j < kTopChunk; ++j) {
+          const int jj = min(base + lane + 64 * j, tl - 1);
+          a0 += zc[j] * rs[jj];
+          a1 += zc[j] * rs[kTile + jj];
+          a2 += zc[j] * rs[2 * kTile + jj];
+        }
       }
     }
   }
@@ -869,12 +953,11 @@ __device__ __forceinline__ void aa_append(const StepState& St, const RedArgs& R,
   __shared__ double red[16 * NA];
   block_sum<NA>(part, red);
   if (threadIdx.x == 0) {
-    double* o = R.part + ((size_t)kRedAA * R.max_parts + bid) * kRedWidth;
 #pragma unroll
     for (int j = 0; j < M; ++j) {
 #pragma unroll
-      for (int l = 0; l < M; ++l) o[j * M + l] = (j <= l) ? part[j * M + l] : part[l * M + j];
-      o[M * M + j] = part[M * M + j];
+      for (int l = 0; l < M; ++l) part_value(R, kRedAA, j * M + l)[bid] = (j <= l) ? part[j * M + l] : part[l * M + j];
+      part_value(R, kRedAA, M * M + j)[bid] = part[M * M + j];
     }
   }
 }
@@ -961,31 +1044,62 @@ __device__ __forceinline__ void b_bottom(VertArgs Vx, SolveArgs Sv, StepState St
   const double alpha = rz / pwt;
   // ---- the subdomain row: x_v = Z_s[v, :] rhs_s - E_s^T[v, :] x_T(s)
   if (have_row) {
-    const double* __restrict__ Zr = Sv.Zs + bo.zs;
-    const double* __restrict__ Er = Sv.Et + bo.et;
+    // the row descriptors are the same in every lane of the wave
+    const int ns = wave_uniform(br.ns), nI = wave_uniform(br.nI);
+    const int b0 = wave_uniform(br.b0), ir0 = wave_uniform(br.ir0);
+    const double* __restrict__ Zr = Sv.Zs + wave_uniform(bo.zs);
+    const double* __restrict__ Er = Sv.Et + wave_uniform(bo.et);
     const int ni = Sv.n_irows;
-    const double* __restrict__ x0 = Sv.xsT + br.ir0;
+    const double* __restrict__ x0 = Sv.xsT + ir0;
+    const double* __restrict__ s0 = src + b0;
+    const double* __restrict__ w0 = wv + b0;
+    // each trip takes 64 x kBottomChunk entries of Z_s[v, :] (against the
+    // right-hand side) and 64 x kBottomChunkE of E_s^T[v, :] (against
+    // x_T(s)); entries past a part's end repeat its last entry with weight zero
+    constexpr int kSpan = 64 * kBottomChunk, kSpanE = 64 * kBottomChunkE;
+    const int trips = max((ns + kSpan - 1) / kSpan, (nI + kSpanE - 1) / kSpanE);
     double a0 = 0, a1 = 0, a2 = 0;
-#pragma unroll kBottomUnroll
-    for (int u = lane; u < br.ns; u += 64) {
-      const double z = Zr[u];
-      const int c = br.b0 + u;
-      if (kPCG) {
-        a0 += z * (src[c] - alpha * wv[c]);
-        a1 += z * (src[nv + c] - alpha * wv[nv + c]);
-        a2 += z * (src[2 * nv + c] - alpha * wv[2 * nv + c]);
-      } else {
-        a0 += z * src[c];
-        a1 += z * src[nv + c];
-        a2 += z * src[2 * nv + c];
+    for (int t = 0; t < trips; ++t) {
+      const int base = t * kSpan;
+      // all loads of the trip first ...
+      double cz[kBottomChunk], yz[kBottomChunk][3], wz[kBottomChunk][3];
+      double ce[kBottomChunkE], ye[kBottomChunkE][3];
+#pragma unroll
+      for (int j = 0; j < kBottomChunk; ++j) {
+        const unsigned o = 8u * (unsigned)min(base + lane + 64 * j, ns - 1);
+        cz[j] = at_byte(Zr, o);
+#pragma unroll
+        for (int a = 0; a < 3; ++a) {
+          yz[j][a] = at_byte(s0 + a * nv, o);
+          if (kPCG) wz[j][a] = at_byte(w0 + a * nv, o);
+        }
       }
-    }
-#pragma unroll kBottomUnroll
-    for (int p = lane; p < br.nI; p += 64) {
-      const double e = Er[p];
-      a0 -= e * x0[p];
-      a1 -= e * x0[ni + p];
-      a2 -= e * x0[2 * ni + p];
+      if (nI > 0)
+#pragma unroll
+        for (int j = 0; j < kBottomChunkE; ++j) {
+          const unsigned o = 8u * (unsigned)min(t * kSpanE + lane + 64 * j, nI - 1);
+          ce[j] = at_byte(Er, o);
+#pragma unroll
+          for (int a = 0; a < 3; ++a) ye[j][a] = at_byte(x0 + a * ni, o);
+        }
+      // ... then the arithmetic (r - alpha w on the subdomain entries)
+#pragma unroll
+      for (int j = 0; j < kBottomChunk; ++j) {
+        const int u = base + lane + 64 * j;
+        const double c = (u < ns) ? cz[j] : 0.0;
+        a0 += c * (kPCG ? yz[j][0] - alpha * wz[j][0] : yz[j][0]);
+        a1 += c * (kPCG ? yz[j][1] - alpha * wz[j][1] : yz[j][1]);
+        a2 += c * (kPCG ? yz[j][2] - alpha * wz[j][2] : yz[j][2]);
+      }
+      if (nI > 0)
+#pragma unroll
+        for (int j = 0; j < kBottomChunkE; ++j) {
+          const int p = t * kSpanE + lane + 64 * j;
+          const double c = (p < nI) ? ce[j] : 0.0;
+          a0 -= c * ye[j][0];
+          a1 -= c * ye[j][1];
+          a2 -= c * ye[j][2];
+        }
     }
     xo[0] = wave_sum(a0);
     xo[1] = wave_sum(a1);
@@ -1038,7 +1152,7 @@ __device__ __forceinline__ void b_bottom(VertArgs Vx, SolveArgs Sv, StepState St
 }
 
 template <int MODE, int M>
-__global__ void __launch_bounds__(kBottomThreads) k_bottom(VertArgs Vx, SolveArgs Sv, StepState St, AdjState A, RedArgs R,
+__global__ void __launch_bounds__(kBottomThreads) PD_ROW_WALK k_bottom(VertArgs Vx, SolveArgs Sv, StepState St, AdjState A, RedArgs R,
                                                    const double* __restrict__ rhs, double* __restrict__ out, int k) {
   b_bottom<MODE, M>(Vx, Sv, St, A, R, rhs, out, k, blockIdx.x);
 }
@@ -1470,7 +1584,7 @@ __device__ __forceinline__ void b_apply_K(ElemArgs E, VertArgs Vx, AdjState A, R
 template <int MODE>
 __global__ void __launch_bounds__(kBlock) k_apply_K(ElemArgs E, VertArgs Vx, AdjState A, RedArgs R,
                                                     const double* __restrict__ jac, const double* __restrict__ x, int it) {
-  b_apply_K<MODE>(E, Vx, A, R, jac, x, it, blockIdx.x);
+  b_apply_K<MODE>(E, Vx, A, R, jac, x, it, xcd_block(blockIdx.x, gridDim.x));
 }
 
 // Gathered contributions on free vertices (8 lanes per vertex).
@@ -1723,7 +1837,7 @@ __global__ void __launch_bounds__(kBlock) kb_gather_fwd(BatchMap M, int k) {
 
 // forward (gate), PCG (alpha), or the adjoint's first solve (right-hand side r0)
 template <int MODE>
-__global__ void __launch_bounds__(kBlock) kb_Eb(BatchMap M, int k) {
+__global__ void __launch_bounds__(kBlock) PD_ROW_WALK kb_Eb(BatchMap M, int k) {
   PD_BATCH_PROLOGUE
   if (MODE == kModePlain) {
     StepState st = b.St;
@@ -1740,7 +1854,7 @@ __global__ void __launch_bounds__(kBlock) kb_top(BatchMap M, int adjoint) {
 }
 
 template <int MODE>
-__global__ void __launch_bounds__(kBottomThreads) kb_bottom(BatchMap M, int k) {
+__global__ void __launch_bounds__(kBottomThreads) PD_ROW_WALK kb_bottom(BatchMap M, int k) {
   PD_BATCH_PROLOGUE
   if (MODE == kModeFwd) {
     switch (b.St.m) {

@@ -142,3 +142,31 @@ def test_hetero_beam_full_size(th):
     gq0, gv0, gl, its = gpu_reverse(th, g, cks, gq, gv)
     for a, b in [(gq0, gq0_o), (gv0, gv0_o), (gl, gl_o)]:
         assert rel(a, b) < TOL_GRAD, (rel(a, b), its)
+
+
+@pytest.mark.parametrize("max_sub", [600, 1200])
+def test_hetero_beam_large_subdomains(th, max_sub):
+    """The 20000-tet beam partitioned into fewer, larger subdomains (up to 550
+    and 1089 vertices; up to 219 and 242 interface rows per subdomain), so that
+    the solve kernels walk every row in several chunks: one solve, then three
+    forward steps and their reverse sweep, against the oracle."""
+    from paper_2605_14526_amd.binding import Scene
+    sc = scenes.config("c2")
+    T = 3
+    g = Scene.from_scene(sc, eps_adj=1e-11, adj_warm=2, max_sub=max_sub)
+    info = g.info()
+    assert info["n_subdomains"] < 16
+    o = O.OracleScene(sc, eps_adj=1e-13)
+    rng = np.random.Generator(np.random.PCG64(41))
+    r = rng.standard_normal(sc.X.shape)
+    assert rel(host(g.debug_apply_Ainv(dev(th, r))), o.apply_Ainv(r)) < 1e-11
+    qs, v, cks, iters = gpu_rollout(th, g, sc, T)
+    q_o, v_o, ck_o, st_o = O.rollout(o, T)
+    assert iters == [s["iters"] for s in st_o]
+    assert rel(host(qs[-1]), q_o) < TOL_POS
+    _, gq = scenes.centroid_loss(q_o, sc.target_centroid)
+    gv = np.zeros_like(gq)
+    gq0_o, gv0_o, gl_o, _ = O.rollout_backward(o, ck_o, gq, gv, adj_mode=0)
+    gq0, gv0, gl, its = gpu_reverse(th, g, cks, gq, gv)
+    for a, b in [(gq0, gq0_o), (gv0, gv0_o), (gl, gl_o)]:
+        assert rel(a, b) < TOL_GRAD, (rel(a, b), its)

@@ -65,7 +65,11 @@ constexpr int kTopChunk = PD_TOP_CHUNK;        // interface solve (Z rows)
 // Row-walking kernels ask for at most 4 waves per SIMD: the compiler may then
 // spend up to 128 registers on a chunk's loads instead of trading them for
 // occupancy by waiting between them (the grids need no more than 4 anyway).
+// The interface right-hand side takes 3 and up to 168 registers: its PCG form
+// holds 7 loads per entry and would spill at 128, and its grid (one wave per
+// interface row) is the smallest of the three.
 #define PD_ROW_WALK __attribute__((amdgpu_waves_per_eu(4, 4)))
+#define PD_ROW_WALK_EB __attribute__((amdgpu_waves_per_eu(3, 3)))
 constexpr int kElemBlock = PD_ELEM_BLOCK;  // tets per workgroup of the single-scene local step and K apply
 
 struct RedArgs {

@@ -801,7 +801,7 @@ __device__ __forceinline__ void b_Eb(VertArgs Vx, SolveArgs Sv, StepState St, Ad
 }
 
 template <int MODE>
-__global__ void __launch_bounds__(kBlock) PD_ROW_WALK k_Eb(VertArgs Vx, SolveArgs Sv, StepState St, AdjState A, RedArgs R,
+__global__ void __launch_bounds__(kBlock) PD_ROW_WALK_EB k_Eb(VertArgs Vx, SolveArgs Sv, StepState St, AdjState A, RedArgs R,
                                                const double* __restrict__ rhs, int k) {
   b_Eb<MODE>(Vx, Sv, St, A, R, rhs, k, blockIdx.x);
 }
@@ -1057,16 +1057,14 @@ __device__ __forceinline__ void b_bottom(VertArgs Vx, SolveArgs Sv, StepState St
     // right-hand side) and 64 x kBottomChunkE of E_s^T[v, :] (against
     // x_T(s)); entries past a part's end repeat its last entry with weight zero
     constexpr int kSpan = 64 * kBottomChunk, kSpanE = 64 * kBottomChunkE;
-    const int trips = max((ns + kSpan - 1) / kSpan, (nI + kSpanE - 1) / kSpanE);
+    const int tz = (ns + kSpan - 1) / kSpan, te = (nI + kSpanE - 1) / kSpanE;
     double a0 = 0, a1 = 0, a2 = 0;
-    for (int t = 0; t < trips; ++t) {
-      const int base = t * kSpan;
-      // all loads of the trip first ...
-      double cz[kBottomChunk], yz[kBottomChunk][3], wz[kBottomChunk][3];
-      double ce[kBottomChunkE], ye[kBottomChunkE][3];
+    double cz[kBottomChunk], yz[kBottomChunk][3], wz[kBottomChunk][3];
+    double ce[kBottomChunkE], ye[kBottomChunkE][3];
+    auto load_z = [&](int t) {
 #pragma unroll
       for (int j = 0; j < kBottomChunk; ++j) {
-        const unsigned o = 8u * (unsigned)min(base + lane + 64 * j, ns - 1);
+        const unsigned o = 8u * (unsigned)min(t * kSpan + lane + 64 * j, ns - 1);
         cz[j] = at_byte(Zr, o);
 #pragma unroll
         for (int a = 0; a < 3; ++a) {
@@ -1074,32 +1072,50 @@ __device__ __forceinline__ void b_bottom(VertArgs Vx, SolveArgs Sv, StepState St
           if (kPCG) wz[j][a] = at_byte(w0 + a * nv, o);
         }
       }
-      if (nI > 0)
+    };
+    auto load_e = [&](int t) {
 #pragma unroll
-        for (int j = 0; j < kBottomChunkE; ++j) {
-          const unsigned o = 8u * (unsigned)min(t * kSpanE + lane + 64 * j, nI - 1);
-          ce[j] = at_byte(Er, o);
+      for (int j = 0; j < kBottomChunkE; ++j) {
+        const unsigned o = 8u * (unsigned)min(t * kSpanE + lane + 64 * j, nI - 1);
+        ce[j] = at_byte(Er, o);
 #pragma unroll
-          for (int a = 0; a < 3; ++a) ye[j][a] = at_byte(x0 + a * ni, o);
-        }
-      // ... then the arithmetic (r - alpha w on the subdomain entries)
+        for (int a = 0; a < 3; ++a) ye[j][a] = at_byte(x0 + a * ni, o);
+      }
+    };
+    auto add_z = [&](int t) {  // r - alpha w on the subdomain entries
 #pragma unroll
       for (int j = 0; j < kBottomChunk; ++j) {
-        const int u = base + lane + 64 * j;
-        const double c = (u < ns) ? cz[j] : 0.0;
+        const double c = (t * kSpan + lane + 64 * j < ns) ? cz[j] : 0.0;
         a0 += c * (kPCG ? yz[j][0] - alpha * wz[j][0] : yz[j][0]);
         a1 += c * (kPCG ? yz[j][1] - alpha * wz[j][1] : yz[j][1]);
         a2 += c * (kPCG ? yz[j][2] - alpha * wz[j][2] : yz[j][2]);
       }
-      if (nI > 0)
+    };
+    auto add_e = [&](int t) {
 #pragma unroll
-        for (int j = 0; j < kBottomChunkE; ++j) {
-          const int p = t * kSpanE + lane + 64 * j;
-          const double c = (p < nI) ? ce[j] : 0.0;
-          a0 -= c * ye[j][0];
-          a1 -= c * ye[j][1];
-          a2 -= c * ye[j][2];
-        }
+      for (int j = 0; j < kBottomChunkE; ++j) {
+        const double c = (t * kSpanE + lane + 64 * j < nI) ? ce[j] : 0.0;
+        a0 -= c * ye[j][0];
+        a1 -= c * ye[j][1];
+        a2 -= c * ye[j][2];
+      }
+    };
+    // trips over both parts (all loads of a trip before its arithmetic), then
+    // the longer part alone; the trip counts are wave-uniform
+    const int both = min(tz, te);
+    for (int t = 0; t < both; ++t) {
+      load_z(t);
+      load_e(t);
+      add_z(t);
+      add_e(t);
+    }
+    for (int t = both; t < tz; ++t) {
+      load_z(t);
+      add_z(t);
+    }
+    for (int t = both; t < te; ++t) {
+      load_e(t);
+      add_e(t);
     }
     xo[0] = wave_sum(a0);
     xo[1] = wave_sum(a1);
@@ -1837,7 +1853,7 @@ __global__ void __launch_bounds__(kBlock) kb_gather_fwd(BatchMap M, int k) {
 
 // forward (gate), PCG (alpha), or the adjoint's first solve (right-hand side r0)
 template <int MODE>
-__global__ void __launch_bounds__(kBlock) PD_ROW_WALK kb_Eb(BatchMap M, int k) {
+__global__ void __launch_bounds__(kBlock) PD_ROW_WALK_EB kb_Eb(BatchMap M, int k) {
   PD_BATCH_PROLOGUE
   if (MODE == kModePlain) {
     StepState st = b.St;

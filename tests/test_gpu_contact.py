@@ -208,6 +208,37 @@ def test_drop_benchmark_size_stepwise(th):
     assert n_act > 0
 
 
+def test_drop_survey_size_through_contact(th):
+    """The drop at about 100k tets (99,730 tets; its 566 MB factor exceeds the
+    Infinity Cache) in the benchmark's launch configuration, started with its
+    lowest point half a detection distance above the obstacles so that it
+    touches at once: four steps from the oracle's own states (rows, iteration
+    counts and positions).  Gradients through contact are
+    held to the oracle on the smaller drops and the 225-row slab: the oracle's
+    fixed point needs minutes at this size."""
+    from paper_2605_14526_amd.binding import Scene
+    sc = scenes.drop_blob(res=41, with_box=True)
+    (lo, hi) = sc.obstacles["boxes"][0]
+    X = sc.X
+    over = (X[:, 0] >= lo[0]) & (X[:, 0] <= hi[0]) & (X[:, 1] >= lo[1]) & (X[:, 1] <= hi[1])
+    gap = min(X[:, 2].min(), (X[over, 2] - hi[2]).min())
+    osc = O.OracleScene(sc)
+    g = Scene.from_scene(sc, eps_adj=1e-6, adj_warm=2)
+    q = X - np.array([0.0, 0.0, gap - 0.5 * sc.obstacles["d_c"]])
+    v = sc.v0()
+    n_act = 0
+    for t in range(4):
+        f = sc.f_ext(t)
+        con = O.detect_contacts(q, v, sc.h, sc.pinned, sc.obstacles)
+        qo, vo, _, lam, st_o = O.step_forward_contact(osc, q, v, f, con)
+        qg, vg, st = g.step_forward(dev(th, q), dev(th, v), dev(th, f))
+        assert st["n_contacts"] == len(con[0]) and st["iters"] == st_o["iters"], (t, st, st_o["iters"])
+        assert rel(host(qg), qo) < TOL_POS, (t, rel(host(qg), qo))
+        n_act = max(n_act, int((lam > 0).sum()))
+        q, v = qo, vo
+    assert n_act > 0
+
+
 def slab_drop(n=14, nz=2, edge=0.02):
     """A flat slab of n x n x nz cubes landing flat on the ground: (n+1)^2 rows at once, more than the LDS
     factorization holds, so the Newton systems and the adjoint's W_AA are factored in the global scratch."""

@@ -140,7 +140,7 @@ def bench_batch(args, torch):
     from paper_2605_14526_amd.binding import Batch, Scene
     scs = scenes.sysid_batch(n=args.batch_scenes, steps=args.steps)
     t0 = time.perf_counter()
-    gs = [Scene.from_scene(sc, eps_adj=1e-6, adj_warm=2) for sc in scs]
+    gs = [Scene.from_scene(sc, eps_adj=1e-6, adj_warm=3) for sc in scs]
     t_setup = time.perf_counter() - t0
     B = Batch(gs)
     dev = lambda a: torch.tensor(np.ascontiguousarray(a), dtype=torch.float64, device="cuda")  # noqa: E731
@@ -270,8 +270,8 @@ def main():
     drop = args.config == "drop"
     sc = scenes.drop_blob(res=args.drop_res) if drop else scenes.config(args.config)
     dev = lambda a: torch.tensor(np.ascontiguousarray(a), dtype=torch.float64, device="cuda")  # noqa: E731
-    # adjoint: extrapolated start from the sweep's previous solutions (runs to 1e-6 either way)
-    g = Scene.from_scene(sc, eps_adj=1e-6, max_sub=args.max_sub, adj_warm=2)
+    # adjoint: start extrapolated (quadratically) from the sweep's previous solutions (runs to 1e-6 either way)
+    g = Scene.from_scene(sc, eps_adj=1e-6, max_sub=args.max_sub, adj_warm=3)
     info = g.info()
     print(f"[bench] scene {sc.name}: {info}", file=sys.stderr, flush=True)
     # warmup (untimed)
@@ -310,7 +310,7 @@ def main():
                                    "gate, FB residual 1e-10 and adjoint 1e-6") if drop else
                                   (f"{sc.name}: 40x10x10 cubes, {sc.n_e} tets, {sc.n_v} verts, two-phase E 1e4/1e6, "
                                    f"nu 0.49, h {sc.h}, rollout of {args.steps} steps, AA window {sc.aa_window}, "
-                                   "gate and adjoint 1e-6, plain q0 = q_t, adjoint start extrapolated"),
+                                   "gate and adjoint 1e-6, plain q0 = q_t, adjoint start extrapolated from the last three solutions"),
                       "fwd_iters_per_step": round(float(np.mean(fiters)), 3),
                       "adj_iters_per_step": round(float(np.mean(biters)), 3),
                       "n_subdomains": int(info["n_subdomains"]), "n_interface": int(info["n_interface"])},
@@ -321,7 +321,7 @@ def main():
     if not args.no_warm_run:
         out["warm_started"] = {}
         # the same rollout with the inertial first iterate q0 = q_t + h v_t
-        gw = Scene.from_scene(sc, eps_adj=1e-6, max_sub=args.max_sub, adj_warm=2, fwd_start=1)
+        gw = Scene.from_scene(sc, eps_adj=1e-6, max_sub=args.max_sub, adj_warm=3, fwd_start=1)
         if args.warmup > 0:
             rollout_fwd_bwd(gw, sc, args.warmup, torch, dev)
         dtw, fw, bw, _ = rollout_fwd_bwd(gw, sc, args.steps, torch, dev)

@@ -86,7 +86,9 @@ typedef struct pd_material_desc {
  *          host (0 = adaptive).
  * adj_warm: start of the adjoint iteration of pd_step_backward: 0 = zero
  *          (as in Alg. 2), 1 = the previous call's solution, 2 = the linear
- *          extrapolation 2 mu_{t+1} - mu_{t+2} of the two previous calls.  The
+ *          extrapolation 2 mu_{t+1} - mu_{t+2} of the two previous calls, 3 =
+ *          the quadratic one 3 mu_{t+1} - 3 mu_{t+2} + mu_{t+3} of three (each
+ *          uses as many previous solutions as the sweep has so far).  The
  *          history belongs to the scene; pd_adjoint_reset clears it (call it
  *          at the start of each reverse sweep); refactorization clears it too.
  *          The solve still runs to eps_adj, so only the iteration count

@@ -254,7 +254,7 @@ void launch_apply_K(int mode, const ElemArgs& E, const VertArgs& V, const AdjSta
                     const double* jac, const double* x, int it, hipStream_t s);
 void launch_adj_gather(int mode, const VertArgs& V, const AdjState& A, const RedArgs& R, int it, hipStream_t s);
 void launch_bwd_prologue(const VertArgs& V, const AdjState& A, const double* gq, const double* gv, int warm,
-                         const double* h1, const double* h2, hipStream_t s);
+                         const double* h1, const double* h2, const double* h3, hipStream_t s);
 void launch_grad_elem(const ElemArgs& E, const VertArgs& V, const double* ck, const double* jac, const double* mu,
                       double* contrib, double* g_logE, hipStream_t s);
 void launch_grad_vert(const VertArgs& V, const double* mu, const double* contrib, const double* gv_next, double* gq_t,

@@ -1699,10 +1699,12 @@ __global__ void __launch_bounds__(kBlock) k_adj_gather(VertArgs Vx, AdjState A, 
 
 // q bar = gq_next + gv_next / h on free vertices (Alg. 2 first line), in
 // library order; adjoint start mu0 (zero, the previous solution mu1 of the
-// sweep, or the linear extrapolation 2 mu1 - mu2), r = q bar, p = A p = 0.
+// sweep, the linear extrapolation 2 mu1 - mu2 or the quadratic one
+// 3 mu1 - 3 mu2 + mu3), r = q bar, p = A p = 0.
 __global__ void __launch_bounds__(kBlock) k_bwd_prologue(VertArgs Vx, AdjState Ad, const double* __restrict__ gq,
                                                          const double* __restrict__ gv, int warm,
-                                                         const double* __restrict__ h1, const double* __restrict__ h2) {
+                                                         const double* __restrict__ h1, const double* __restrict__ h2,
+                                                         const double* __restrict__ h3) {
   const int i = blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= Vx.nv) return;
   const int nv = Vx.nv, o = Vx.v_orig[i];
@@ -1714,6 +1716,7 @@ __global__ void __launch_bounds__(kBlock) k_bwd_prologue(VertArgs Vx, AdjState A
     double m0 = 0.0;
     if (fr && warm == 1) m0 = h1[ix];
     if (fr && warm == 2) m0 = 2.0 * h1[ix] - h2[ix];
+    if (fr && warm == 3) m0 = 3.0 * (h1[ix] - h2[ix]) + h3[ix];
     Ad.qbar[ix] = qb;
     Ad.r0[ix] = qb;
     Ad.mu[ix] = m0;
@@ -2084,8 +2087,8 @@ void launch_adj_gather(int mode, const VertArgs& V, const AdjState& A, const Red
   else launch_ext(k_adj_gather<kModeDebug>, g, b, 0, s, V, A, R, it);
 }
 void launch_bwd_prologue(const VertArgs& V, const AdjState& A, const double* gq, const double* gv, int warm,
-                         const double* h1, const double* h2, hipStream_t s) {
-  launch_ext(k_bwd_prologue, PD_GRID(V.nv), 0, s, V, A, gq, gv, warm, h1, h2);
+                         const double* h1, const double* h2, const double* h3, hipStream_t s) {
+  launch_ext(k_bwd_prologue, PD_GRID(V.nv), 0, s, V, A, gq, gv, warm, h1, h2, h3);
 }
 void launch_grad_elem(const ElemArgs& E, const VertArgs& V, const double* ck, const double* jac, const double* mu,
                       double* contrib, double* g_logE, hipStream_t s) {

@@ -154,8 +154,8 @@ struct Scene {
   double* jac = nullptr;       // 33 x ne compact prox differential
   double *mu = nullptr, *r0 = nullptr, *r1 = nullptr, *z = nullptr, *p = nullptr, *Ap = nullptr, *wv = nullptr,
          *qbar = nullptr;
-  // adjoint warm start: the last two adjoint solutions of a backward sweep
-  double *mu_h1 = nullptr, *mu_h2 = nullptr;
+  // adjoint warm start: the last three adjoint solutions of a backward sweep (newest first)
+  double *mu_h1 = nullptr, *mu_h2 = nullptr, *mu_h3 = nullptr;
   int adj_hist = 0, adj_warm = 0;
   int fwd_start = 0;  // 0: q0 = q_t; 1: q0 = q_t + h v_t (when the caller passes no q0)
   double* ck_scratch = nullptr;  // 12 x nv (diagnostic K apply)

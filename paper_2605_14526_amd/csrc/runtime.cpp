@@ -251,7 +251,7 @@ void free_device(Scene& S) {
   dfree(S.b_cur); dfree(S.b_prev); dfree(S.qhat); dfree(S.q_last); dfree(S.g_last); dfree(S.dQ); dfree(S.dG);
   dfree(S.ctl); dfree(S.dstat); dfree(S.red_part); dfree(S.red_fin);
   dfree(S.jac); dfree(S.mu); dfree(S.r0); dfree(S.r1); dfree(S.z); dfree(S.p); dfree(S.Ap); dfree(S.wv);
-  dfree(S.qbar); dfree(S.ck_scratch); dfree(S.mu_h1); dfree(S.mu_h2);
+  dfree(S.qbar); dfree(S.ck_scratch); dfree(S.mu_h1); dfree(S.mu_h2); dfree(S.mu_h3);
   contact_free(S);
   if (S.hctl) (void)hipHostFree(S.hctl);
   if (S.hdstat) (void)hipHostFree(S.hdstat);
@@ -430,7 +430,7 @@ void setup_scene(Scene& S, const pd_mesh_desc* mesh, const pd_material_desc* mat
   S.kmax_bwd = o->kmax_bwd; S.eps_adj = o->eps_adj; S.eps_tr = o->eps_tr; S.adj_method = o->adj_method;
   S.max_sub = o->max_sub > 0 ? o->max_sub : 256;
   S.iters_per_check = o->iters_per_check;
-  if (o->adj_warm < 0 || o->adj_warm > 2) throw PdError{PD_ERR_INVALID_ARG, "adj_warm must be 0, 1 or 2"};
+  if (o->adj_warm < 0 || o->adj_warm > 3) throw PdError{PD_ERR_INVALID_ARG, "adj_warm must be 0, 1, 2 or 3"};
   if (o->fwd_start < 0 || o->fwd_start > 1) throw PdError{PD_ERR_INVALID_ARG, "fwd_start must be 0 or 1"};
   S.fwd_start = o->fwd_start;
   S.adj_warm = o->adj_warm;
@@ -546,7 +546,7 @@ void setup_scene(Scene& S, const pd_mesh_desc* mesh, const pd_material_desc* mat
   S.mu = dalloc<double>(V3); S.r0 = dalloc<double>(V3); S.r1 = dalloc<double>(V3); S.z = dalloc<double>(V3);
   S.p = dalloc<double>(V3); S.Ap = dalloc<double>(V3); S.wv = dalloc<double>(V3); S.qbar = dalloc<double>(V3);
   S.ck_scratch = dalloc<double>(12 * (size_t)nv);
-  S.mu_h1 = dalloc<double>(V3); S.mu_h2 = dalloc<double>(V3);
+  S.mu_h1 = dalloc<double>(V3); S.mu_h2 = dalloc<double>(V3); S.mu_h3 = dalloc<double>(V3);
   PD_HIP(hipMemset(S.mu, 0, V3 * sizeof(double)));
   PD_HIP(hipMemset(S.z, 0, V3 * sizeof(double)));
   // reduction sites sized for the widest producing kernel
@@ -1334,6 +1334,17 @@ int pd_step_forward(pd_scene* scene, const double* q_t, const double* v_t, const
   PD_CATCH
 }
 
+// The adjoint solution just computed becomes the newest of the (up to three)
+// kept for the next call's start; the buffers rotate, the oldest is overwritten.
+static void push_adjoint_history(Scene& S, hipStream_t st) {
+  PD_HIP(hipMemcpyAsync(S.mu_h3, S.mu, 3 * (size_t)S.nv * sizeof(double), hipMemcpyDeviceToDevice, st));
+  double* newest = S.mu_h3;
+  S.mu_h3 = S.mu_h2;
+  S.mu_h2 = S.mu_h1;
+  S.mu_h1 = newest;
+  S.adj_hist = std::min(S.adj_hist + 1, 3);
+}
+
 static void adjoint_solve(Scene& S, hipStream_t st, double tau_force, double* bstat_host, const double* ck,
                           bool warm, int n_active) {
   const ElemArgs E = elem_args(S);
@@ -1454,14 +1465,10 @@ int pd_step_backward(pd_scene* scene, const void* ckpt, const double* gq_next, c
   // adjoint start: zero, or from the last solutions of this backward sweep;
   // with active rows the start must satisfy J_A mu = 0, so it is zero
   const int warm = n_active > 0 ? 0 : std::min(S.adj_warm, S.adj_hist);
-  launch_bwd_prologue(V, Ad, gq_next, gv_next, warm, S.mu_h1, S.mu_h2, st);
+  launch_bwd_prologue(V, Ad, gq_next, gv_next, warm, S.mu_h1, S.mu_h2, S.mu_h3, st);
   double bs[5] = {0, 0, 0, 0, 0};
   adjoint_solve(S, st, -1.0, bs, ck, warm > 0, n_active);
-  if (S.adj_warm > 0) {
-    PD_HIP(hipMemcpyAsync(S.mu_h2, S.mu, 3 * (size_t)S.nv * sizeof(double), hipMemcpyDeviceToDevice, st));
-    std::swap(S.mu_h1, S.mu_h2);
-    S.adj_hist = std::min(S.adj_hist + 1, 2);
-  }
+  if (S.adj_warm > 0) push_adjoint_history(S, st);
   // the gradient routing is stream-ordered; the statistics were read with the last check
   launch_grad_elem(E, V, ck, S.jac, S.mu, S.contrib, g_logE_accum, st);
   launch_grad_vert(V, S.mu, S.contrib, gv_next, gq_t, gv_t, gf_ext, st);
@@ -1891,7 +1898,7 @@ int pd_batch_step_backward(pd_batch* B, const void* const* ckpt, const double* c
     warm[s] = std::min(S.adj_warm, S.adj_hist);
     any_warm = any_warm || warm[s] > 0;
     launch_bwd_prologue(V, Ad, gq_next ? gq_next[s] : nullptr, gv_next ? gv_next[s] : nullptr, warm[s], S.mu_h1,
-                        S.mu_h2, st);
+                        S.mu_h2, S.mu_h3, st);
     launch_tr_partials(E, V, R, ck, st);
     launch_bwd_elem(E, V, R, ck, S.eps_tr, -1.0, 1, S.jac, S.dstat + 4, st);
     launch_zero_int(S.ctl + kCtlAdj, 4, st);
@@ -1926,11 +1933,7 @@ int pd_batch_step_backward(pd_batch* B, const void* const* ckpt, const double* c
     launch_grad_elem(E, V, ck, S.jac, S.mu, S.contrib, g_logE_accum ? g_logE_accum[s] : nullptr, st);
     launch_grad_vert(V, S.mu, S.contrib, gv_next ? gv_next[s] : nullptr, gq_t ? gq_t[s] : nullptr,
                      gv_t ? gv_t[s] : nullptr, gf_ext ? gf_ext[s] : nullptr, st);
-    if (S.adj_warm > 0) {
-      PD_HIP(hipMemcpyAsync(S.mu_h2, S.mu, 3 * (size_t)S.nv * sizeof(double), hipMemcpyDeviceToDevice, st));
-      std::swap(S.mu_h1, S.mu_h2);
-      S.adj_hist = std::min(S.adj_hist + 1, 2);
-    }
+    if (S.adj_warm > 0) push_adjoint_history(S, st);
     const int* c = B->hctl + s * kCtlTotal;
     const double* d = B->hdstat + s * 32;
     if (!c[kCtlAdj + 2]) throw PdError{PD_ERR_HIP, "batched adjoint loop ended without a decision"};

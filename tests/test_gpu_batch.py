@@ -27,11 +27,11 @@ def d(th, a):
     return th.tensor(np.ascontiguousarray(a), dtype=th.float64, device="cuda")
 
 
-def run_alone(th, scs, T):
+def run_alone(th, scs, T, adj_warm=2):
     from paper_2605_14526_amd.binding import Scene
     out = []
     for sc in scs:
-        g = Scene.from_scene(sc, adj_warm=2)
+        g = Scene.from_scene(sc, adj_warm=adj_warm)
         q, v = d(th, sc.q0()), d(th, sc.v0())
         cks, iters = [], []
         for t in range(T):
@@ -48,9 +48,9 @@ def run_alone(th, scs, T):
     return out
 
 
-def run_batched(th, scs, T, **cfg):
+def run_batched(th, scs, T, adj_warm=2, **cfg):
     from paper_2605_14526_amd.binding import Batch, Scene
-    gs = [Scene.from_scene(sc, adj_warm=2) for sc in scs]
+    gs = [Scene.from_scene(sc, adj_warm=adj_warm) for sc in scs]
     B = Batch(gs)
     if cfg:
         B.config(**cfg)
@@ -101,7 +101,7 @@ def test_identification_batch_full_size_bitwise(th):
     scs = scenes.sysid_batch(n=64, steps=2)
     assert sum(sc.n_e for sc in scs) > 500_000
     T = 2
-    gs = [Scene.from_scene(sc, adj_warm=2) for sc in scs]
+    gs = [Scene.from_scene(sc, adj_warm=3) for sc in scs]
     B = Batch(gs)
 
     def rollout():
@@ -122,8 +122,8 @@ def test_identification_batch_full_size_bitwise(th):
     cfg = autotune.autotune(B, rollout, th, reps=1)
     del B, gs
     gc.collect()
-    alone = run_alone(th, scs, T)
-    together = run_batched(th, scs, T, **cfg)
+    alone = run_alone(th, scs, T, adj_warm=3)
+    together = run_batched(th, scs, T, adj_warm=3, **cfg)
     for a, b in zip(alone, together):
         assert a[3] == b[3]
         for x, y in zip(a[:3], b[:3]):

@@ -223,7 +223,7 @@ def test_drop_survey_size_through_contact(th):
     over = (X[:, 0] >= lo[0]) & (X[:, 0] <= hi[0]) & (X[:, 1] >= lo[1]) & (X[:, 1] <= hi[1])
     gap = min(X[:, 2].min(), (X[over, 2] - hi[2]).min())
     osc = O.OracleScene(sc)
-    g = Scene.from_scene(sc, eps_adj=1e-6, adj_warm=2)
+    g = Scene.from_scene(sc, eps_adj=1e-6, adj_warm=3)
     q = X - np.array([0.0, 0.0, gap - 0.5 * sc.obstacles["d_c"]])
     v = sc.v0()
     n_act = 0

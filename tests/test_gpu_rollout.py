@@ -57,7 +57,7 @@ def gpu_reverse(th, g, cks, gq, gv):
     return host(gq), host(gv), host(g_logE), its
 
 
-@pytest.mark.parametrize("warm", [0, 2])
+@pytest.mark.parametrize("warm", [0, 2, 3])
 def test_rollout_gradients_match_oracle(th, warm):
     """Six steps forward, the centroid-loss gradient swept back to q0, v0 and
     log E; the adjoint starts from zero or from the extrapolated previous
@@ -125,12 +125,12 @@ def test_bitwise_repeatable(th):
 
 def test_hetero_beam_full_size(th):
     """The benchmark's workload (20000 tets) and launch configuration (default
-    partition, extrapolated adjoint start): six forward steps while the tip
+    partition, quadratically extrapolated adjoint start): six forward steps while the tip
     load ramps up, and their reverse sweep, against the oracle."""
     from paper_2605_14526_amd.binding import Scene
     sc = scenes.config("c2")
     T = 6
-    g = Scene.from_scene(sc, eps_adj=1e-11, adj_warm=2)
+    g = Scene.from_scene(sc, eps_adj=1e-11, adj_warm=3)
     o = O.OracleScene(sc, eps_adj=1e-13)
     qs, v, cks, iters = gpu_rollout(th, g, sc, T)
     q_o, v_o, ck_o, st_o = O.rollout(o, T)
@@ -153,7 +153,7 @@ def test_hetero_beam_large_subdomains(th, max_sub):
     from paper_2605_14526_amd.binding import Scene
     sc = scenes.config("c2")
     T = 3
-    g = Scene.from_scene(sc, eps_adj=1e-11, adj_warm=2, max_sub=max_sub)
+    g = Scene.from_scene(sc, eps_adj=1e-11, adj_warm=3, max_sub=max_sub)
     info = g.info()
     assert info["n_subdomains"] < 16
     o = O.OracleScene(sc, eps_adj=1e-13)

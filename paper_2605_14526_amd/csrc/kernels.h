@@ -240,7 +240,8 @@ void launch_gather_fwd(const VertArgs& V, const StepState& St, const RedArgs& R,
 void launch_gather_debug(const VertArgs& V, const double* contrib, double* out, hipStream_t s);
 void launch_Eb(int mode, const VertArgs& V, const SolveArgs& S, const StepState& St, const AdjState& A,
                const RedArgs& R, const double* rhs, int k, hipStream_t s);
-void launch_top(const VertArgs& V, const SolveArgs& S, double* out, hipStream_t s);
+// done: the loop's done flag (nullptr: always solve)
+void launch_top(const VertArgs& V, const SolveArgs& S, double* out, const int* done, hipStream_t s);
 void launch_bottom(int mode, const VertArgs& V, const SolveArgs& S, const StepState& St, const AdjState& A,
                    const RedArgs& R, const double* rhs, double* out, int k, hipStream_t s);
 void launch_epilogue(const VertArgs& V, const StepState& St, double* q_next, double* v_next, double* ckpt,

@@ -809,9 +809,11 @@ __global__ void __launch_bounds__(kBlock) PD_ROW_WALK_EB k_Eb(VertArgs Vx, Solve
 // ---------------------------------------------------------------- interface solve
 // x_T = Z r_T, one wave per interface row (Z = inverse Schur complement); the
 // value is also stored at the row's position in the per-subdomain interface
-// vectors read by the subdomain solve.  There is no done test: once a loop has
-// stopped, k_Eb leaves r_T unchanged, so this kernel rewrites the same values.
-__device__ __forceinline__ void b_top(VertArgs Vx, SolveArgs Sv, double* __restrict__ out, int bid) {
+// vectors read by the subdomain solve.  With a done flag (nullable) a launch
+// after the loop has stopped exits once the flag, read with the first tile of
+// r_T, is seen: its only consumer, the subdomain solve, exits too.
+__device__ __forceinline__ void b_top(VertArgs Vx, SolveArgs Sv, double* __restrict__ out, int bid,
+                                      const int* __restrict__ done) {
   // r_T is read by every row: the block stages it in LDS tile by tile, so it
   // crosses L2 once per block instead of once per row
   constexpr int kTile = 2048;
@@ -827,6 +829,8 @@ __device__ __forceinline__ void b_top(VertArgs Vx, SolveArgs Sv, double* __restr
     if (lane < kMaxCoup) cd = Sv.cpl[row * kMaxCoup + lane];
   }
   const double* __restrict__ Zi = Sv.Z + (size_t)(have ? row : 0) * nT;
+  __shared__ int stop_s;
+  if (threadIdx.x == 0) stop_s = done ? *done : 0;
   double a0 = 0, a1 = 0, a2 = 0;
   for (int t0 = 0; t0 < nT; t0 += kTile) {
     const int tl = min(kTile, nT - t0);
@@ -837,6 +841,7 @@ __device__ __forceinline__ void b_top(VertArgs Vx, SolveArgs Sv, double* __restr
       rs[2 * kTile + i] = Sv.rT[2 * nT + t0 + i];
     }
     __syncthreads();
+    if (stop_s) return;
     if (have) {
       // whole chunks, then the last partial one (its entries past the end
       // repeat the last entry with weight zero)
@@ -890,8 +895,9 @@ __device__ __forceinline__ void b_top(VertArgs Vx, SolveArgs Sv, double* __restr
   }
 }
 
-__global__ void __launch_bounds__(kBlock) k_top(VertArgs Vx, SolveArgs Sv, double* __restrict__ out) {
-  b_top(Vx, Sv, out, blockIdx.x);
+__global__ void __launch_bounds__(kBlock) k_top(VertArgs Vx, SolveArgs Sv, double* __restrict__ out,
+                                                const int* __restrict__ done) {
+  b_top(Vx, Sv, out, blockIdx.x, done);
 }
 
 // Anderson append of one forward iteration for the free row my_row (-1: no
@@ -1869,7 +1875,7 @@ __global__ void __launch_bounds__(kBlock) PD_ROW_WALK_EB kb_Eb(BatchMap M, int k
 
 __global__ void __launch_bounds__(kBlock) kb_top(BatchMap M, int adjoint) {
   PD_BATCH_PROLOGUE
-  b_top(b.V, b.S, adjoint ? b.A.z : b.St.qhat, bid);
+  b_top(b.V, b.S, adjoint ? b.A.z : b.St.qhat, bid, nullptr);
 }
 
 template <int MODE>
@@ -2024,9 +2030,9 @@ void launch_Eb(int mode, const VertArgs& V, const SolveArgs& S, const StepState&
   else if (S.nT > 0)
     launch_ext(k_Eb<kModePlain>, dim3(nblk), dim3(kBlock), 0, s, V, S, St, A, R, rhs, k);
 }
-void launch_top(const VertArgs& V, const SolveArgs& S, double* out, hipStream_t s) {
+void launch_top(const VertArgs& V, const SolveArgs& S, double* out, const int* done, hipStream_t s) {
   if (S.nT == 0) return;
-  launch_ext(k_top, dim3((S.nT + 3) / 4), dim3(kBlock), 0, s, V, S, out);
+  launch_ext(k_top, dim3((S.nT + 3) / 4), dim3(kBlock), 0, s, V, S, out, done);
 }
 void launch_bottom(int mode, const VertArgs& V, const SolveArgs& S, const StepState& St, const AdjState& A,
                    const RedArgs& R, const double* rhs, double* out, int k, hipStream_t s) {

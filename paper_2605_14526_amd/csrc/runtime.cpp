@@ -831,7 +831,7 @@ void solve_plain(Scene& S, const double* rhs, double* out, int* done, hipStream_
   T.done = done;
   const AdjState Ad = adj_state(S);
   PD_TIMED(S, kKEb, st, launch_Eb(kModePlain, V, A, T, Ad, R, rhs, 0, st));
-  PD_TIMED(S, kKTop, st, launch_top(V, A, out, st));
+  PD_TIMED(S, kKTop, st, launch_top(V, A, out, done, st));
   PD_TIMED(S, kKBottom, st, launch_bottom(kModePlain, V, A, T, Ad, R, rhs, out, 0, st));
 }
 
@@ -899,7 +899,7 @@ void ensure_columns(Scene& S, const int* verts, int n, int* slots, hipStream_t s
     }
     launch_unit_rhs(S.nv, S.z, vv[0], vv[1], vv[2], st);
     launch_Eb(kModePlain, V, A, T, Ad, R, S.z, 0, st);
-    launch_top(V, A, S.wv, st);
+    launch_top(V, A, S.wv, nullptr, st);
     launch_bottom(kModePlain, V, A, T, Ad, R, S.z, S.wv, 0, st);
     launch_store_cols(S.L.nf, S.nv, S.wv, S.cols, ss[0], ss[1], ss[2], st);
   }
@@ -1265,7 +1265,7 @@ int pd_step_forward(pd_scene* scene, const double* q_t, const double* v_t, const
       PD_TIMED(S, kKLocal, st, launch_local(E, T, R, S.q_cur, S.nv, V.nf, k, 1, st));
       PD_TIMED(S, kKGather, st, launch_gather_fwd(V, T, R, k, st));
       PD_TIMED(S, kKEb, st, launch_Eb(kModeFwd, V, A, T, Ad, R, nullptr, k, st));
-      PD_TIMED(S, kKTop, st, launch_top(V, A, S.qhat, st));
+      PD_TIMED(S, kKTop, st, launch_top(V, A, S.qhat, T.done, st));
       if (K > 0) {
         PD_TIMED(S, kKBottom, st, launch_bottom(kModePlain, V, A, T, Ad, R, S.b_cur, S.qhat, k, st));
         launch_contact_fb(V, C, S.qhat, T.done, st);
@@ -1375,7 +1375,7 @@ static void adjoint_solve(Scene& S, hipStream_t st, double tau_force, double* bs
       launch_adj_gather(kModeInit, V, Ad, R, 0, st);
     }
     PD_TIMED(S, kKEb, st, launch_Eb(kModePlain, V, Sv, T, Ad, R, S.r0, 0, st));
-    PD_TIMED(S, kKTop, st, launch_top(V, Sv, S.z, st));
+    PD_TIMED(S, kKTop, st, launch_top(V, Sv, S.z, T.done, st));
     if (con) {
       PD_TIMED(S, kKBottom, st, launch_bottom(kModePlain, V, Sv, T, Ad, R, S.r0, S.z, 0, st));
       launch_contact_proj(V, C, S.z, Ad.done, st);
@@ -1385,7 +1385,7 @@ static void adjoint_solve(Scene& S, hipStream_t st, double tau_force, double* bs
     }
   }
   int it = 0;
-  int chunk = std::max(4, S.last_adj_iters + 1);
+  int chunk = std::max(2, S.last_adj_iters + 1);
   for (;;) {
     const int iend = std::min(it + chunk, S.kmax_bwd + 1);
     for (; it < iend; ++it) {
@@ -1393,7 +1393,7 @@ static void adjoint_solve(Scene& S, hipStream_t st, double tau_force, double* bs
         PD_TIMED(S, kKApplyK, st, launch_apply_K(kModePCG, E, V, Ad, R, S.jac, nullptr, it, st));
         launch_adj_gather(kModePCG, V, Ad, R, it, st);
         PD_TIMED(S, kKEb, st, launch_Eb(kModePCG, V, Sv, T, Ad, R, nullptr, it, st));
-        PD_TIMED(S, kKTop, st, launch_top(V, Sv, S.z, st));
+        PD_TIMED(S, kKTop, st, launch_top(V, Sv, S.z, T.done, st));
         if (con) {
           PD_TIMED(S, kKBottom, st, launch_bottom(kModePCGSolve, V, Sv, T, Ad, R, nullptr, S.z, it, st));
           launch_contact_proj(V, C, S.z, Ad.done, st);
@@ -1405,7 +1405,7 @@ static void adjoint_solve(Scene& S, hipStream_t st, double tau_force, double* bs
         PD_TIMED(S, kKApplyK, st, launch_apply_K(kModeFixed, E, V, Ad, R, S.jac, nullptr, it, st));
         launch_adj_gather(kModeFixed, V, Ad, R, it, st);
         PD_TIMED(S, kKEb, st, launch_Eb(kModePlain, V, Sv, T, Ad, R, S.r0, it, st));
-        PD_TIMED(S, kKTop, st, launch_top(V, Sv, S.z, st));
+        PD_TIMED(S, kKTop, st, launch_top(V, Sv, S.z, T.done, st));
         if (con) {
           PD_TIMED(S, kKBottom, st, launch_bottom(kModePlain, V, Sv, T, Ad, R, S.r0, S.z, it, st));
           launch_contact_proj(V, C, S.z, Ad.done, st);
@@ -1426,7 +1426,7 @@ static void adjoint_solve(Scene& S, hipStream_t st, double tau_force, double* bs
     }
     kt_flush(S);
     if (S.hctl[kCtlAdj + 2] || it > S.kmax_bwd) break;
-    chunk = 4;
+    chunk = std::max(2, S.last_adj_iters / 4);  // more than predicted: short follow-up chunks
   }
   if (bstat_host) {
     for (int j = 0; j < 4; ++j) bstat_host[j] = S.hdstat[4 + j];

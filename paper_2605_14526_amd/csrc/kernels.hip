@@ -91,14 +91,14 @@ __device__ __forceinline__ void block_sum(double (&v)[NV], double* lds /* >= 16*
   __syncthreads();
 }
 
-// Producer side: block sum of N values, written by thread 0 as partial `idx`
-// of `site`.  Every thread of the block must call it.
 // Value j of every partial of `site`, indexed by the producing block: the
 // values a consumer reads from consecutive partials are contiguous.
 __device__ __forceinline__ double* part_value(const RedArgs& R, int site, int j) {
   return R.part + ((size_t)site * kRedWidth + j) * R.max_parts;
 }
 
+// Producer side: block sum of N values, written by thread 0 as partial `idx`
+// of `site`.  Every thread of the block must call it.
 template <int N>
 __device__ __forceinline__ void write_partial(double (&v)[N], const RedArgs& R, int site, int idx) {
   __shared__ double red[16 * N];

@@ -1221,15 +1221,25 @@ __device__ __forceinline__ void contact_lds_load(const ContactArgs& C, ContactLd
   }
 }
 
+// The rows go in chunks: a chunk's column entries are requested together (rows
+// past the end repeat the last one), then added in row order.
 __device__ __forceinline__ void contact_correction(const ContactArgs& C, const ContactLds& L, int row, double (&x)[3]) {
+  constexpr int kChunk = 8;
   const size_t nf = C.nf;
-  for (int c = 0; c < C.K; ++c) {
-    const double s0 = L.s[3 * c], s1 = L.s[3 * c + 1], s2 = L.s[3 * c + 2];
-    if (s0 == 0.0 && s1 == 0.0 && s2 == 0.0) continue;
-    const double a = C.cols[(size_t)L.slot[c] * nf + row];
-    x[0] += s0 * a;
-    x[1] += s1 * a;
-    x[2] += s2 * a;
+  for (int c0 = 0; c0 < C.K; c0 += kChunk) {
+    double a[kChunk];
+#pragma unroll
+    for (int j = 0; j < kChunk; ++j) a[j] = C.cols[(size_t)L.slot[min(c0 + j, C.K - 1)] * nf + row];
+#pragma unroll
+    for (int j = 0; j < kChunk; ++j) {
+      const int c = c0 + j;
+      if (c >= C.K) continue;
+      const double s0 = L.s[3 * c], s1 = L.s[3 * c + 1], s2 = L.s[3 * c + 2];
+      if (s0 == 0.0 && s1 == 0.0 && s2 == 0.0) continue;
+      x[0] += s0 * a[j];
+      x[1] += s1 * a[j];
+      x[2] += s2 * a[j];
+    }
   }
 }
 

@@ -208,7 +208,7 @@ def test_drop_benchmark_size_stepwise(th):
     assert n_act > 0
 
 
-def test_drop_survey_size_through_contact(th):
+def test_drop_100k_tets_through_contact(th):
     """The drop at about 100k tets (99,730 tets; its 566 MB factor exceeds the
     Infinity Cache) in the benchmark's launch configuration, started with its
     lowest point half a detection distance above the obstacles so that it

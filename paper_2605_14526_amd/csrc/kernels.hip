@@ -1892,9 +1892,10 @@ __global__ void __launch_bounds__(kBlock) PD_ROW_WALK_EB kb_Eb(BatchMap M, int k
   }
 }
 
+// A block of a scene whose loop has stopped exits on that scene's flag.
 __global__ void __launch_bounds__(kBlock) kb_top(BatchMap M, int adjoint) {
   PD_BATCH_PROLOGUE
-  b_top(b.V, b.S, adjoint ? b.A.z : b.St.qhat, bid, nullptr);
+  b_top(b.V, b.S, adjoint ? b.A.z : b.St.qhat, bid, adjoint ? b.A.done : b.St.done);
 }
 
 template <int MODE>

@@ -62,6 +62,10 @@ constexpr int kBottomChunk = PD_BOTTOM_CHUNK;     // subdomain solve, Z_s rows
 constexpr int kBottomChunkE = PD_BOTTOM_CHUNK_E;  // subdomain solve, E_s^T rows
 constexpr int kEbChunk = PD_EB_CHUNK;          // interface right-hand side (E_s rows)
 constexpr int kTopChunk = PD_TOP_CHUNK;        // interface solve (Z rows)
+// LDS buffers of the subdomain solve: right-hand-side rows and interface
+// copies a block stages for its rows (three axes each)
+constexpr int kStageZ = 768;
+constexpr int kStageE = 640;
 // Row-walking kernels ask for at most 4 waves per SIMD: the compiler may then
 // spend up to 128 registers on a chunk's loads instead of trading them for
 // occupancy by waiting between them (the grids need no more than 4 anyway).
@@ -125,6 +129,7 @@ struct SolveArgs {
   const ERow* erow;         // nT: the row's couplings in E (row-concatenated)
   const BRow* brow;         // nB subdomain-row descriptors
   const BOff* boff;
+  const BStage* bstage;     // per subdomain-solve block: the ranges it stages in LDS
   double* xsT;              // 3 x n_irows interface solution gathered per subdomain
   int n_irows;
 };

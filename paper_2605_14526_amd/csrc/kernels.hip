@@ -1002,6 +1002,14 @@ __device__ __forceinline__ void aa_append(const StepState& St, const RedArgs& R,
 //  fixed point: partial |z - mu|^2, |z|^2, then mu <- z.
 // Everything a thread needs that does not depend on the row descriptors is
 // requested together with them.
+// The subdomain solve's LDS staging buffers (right-hand-side rows, then
+// interface copies, three axes each): one allocation per kernel, shared by
+// every instantiation a batched kernel dispatches between.
+__device__ __forceinline__ double* bottom_stage_lds() {
+  __shared__ double buf[3 * (kStageZ + kStageE)];
+  return buf;
+}
+
 template <int MODE, int M>
 __device__ __forceinline__ void b_bottom(VertArgs Vx, SolveArgs Sv, StepState St, AdjState A, RedArgs R,
                                                    const double* __restrict__ rhs, double* __restrict__ out, int k, int bid) {
@@ -1028,10 +1036,12 @@ __device__ __forceinline__ void b_bottom(VertArgs Vx, SolveArgs Sv, StepState St
   // ---- first round of loads
   BRow br = {0, 0, 0, 0};
   BOff bo = {0, 0};
+  BStage bst = {0, 0, 0, 0};
   if (have_row) {
     br = Sv.brow[v];
     bo = Sv.boff[v];
   }
+  if (sub_block) bst = Sv.bstage[bid];
   __shared__ int flag_s;
   if (threadIdx.x == 0) flag_s = done ? *done : 0;
   // per-vertex state of my_row (x_T of an interface row comes from k_top)
@@ -1069,22 +1079,125 @@ __device__ __forceinline__ void b_bottom(VertArgs Vx, SolveArgs Sv, StepState St
   __syncthreads();
   if (flag_s) return;
   const double alpha = rz / pwt;
+  // the row descriptors are the same in every lane of the wave
+  const int ns = wave_uniform(br.ns), nI = wave_uniform(br.nI);
+  const int b0 = wave_uniform(br.b0), ir0 = wave_uniform(br.ir0);
+  const double* __restrict__ Zr = Sv.Zs + wave_uniform(bo.zs);
+  const double* __restrict__ Er = Sv.Et + wave_uniform(bo.et);
+  const int ni = Sv.n_irows;
+  // each trip of a row walk takes 64 x kBottomChunk entries of Z_s[v, :]
+  // (against the right-hand side) and 64 x kBottomChunkE of E_s^T[v, :]
+  // (against x_T(s)); entries past a part's end repeat its last entry with
+  // weight zero
+  constexpr int kSpan = 64 * kBottomChunk, kSpanE = 64 * kBottomChunkE;
+  const int tz = (ns + kSpan - 1) / kSpan, te = (nI + kSpanE - 1) / kSpanE;
+  // ---- staging: the block's rows share one or two subdomains, so it stages
+  // their right-hand-side rows (r - alpha w in PCG) and interface copies in LDS
+  // once instead of every row reading them from memory; the first chunk of
+  // each row's coefficients is requested together with them.  Blocks whose
+  // ranges exceed the buffers (zn = 0) read them in the row walk instead.
+  double* sz = bottom_stage_lds();
+  double* se = sz + 3 * kStageZ;
+  const bool staged = sub_block && bst.zn > 0;  // block-uniform
+  double cz0[kBottomChunk], ce0[kBottomChunkE];
+  if (staged) {
+    if (have_row) {
+#pragma unroll
+      for (int j = 0; j < kBottomChunk; ++j) cz0[j] = Zr[min(lane + 64 * j, ns - 1)];
+      if (nI > 0)
+#pragma unroll
+        for (int j = 0; j < kBottomChunkE; ++j) ce0[j] = Er[min(lane + 64 * j, nI - 1)];
+    }
+    constexpr int kPZ = (kStageZ + kBottomThreads - 1) / kBottomThreads;
+    constexpr int kPE = (kStageE + kBottomThreads - 1) / kBottomThreads;
+    double vz[kPZ][3], ve[kPE][3];
+#pragma unroll
+    for (int j = 0; j < kPZ; ++j) {
+      const int i = min((int)threadIdx.x + j * kBottomThreads, bst.zn - 1);
+#pragma unroll
+      for (int a = 0; a < 3; ++a) {
+        const int ix = a * nv + bst.z0 + i;
+        vz[j][a] = kPCG ? src[ix] - alpha * wv[ix] : src[ix];
+      }
+    }
+    if (bst.en > 0)
+#pragma unroll
+      for (int j = 0; j < kPE; ++j) {
+        const int i = min((int)threadIdx.x + j * kBottomThreads, bst.en - 1);
+#pragma unroll
+        for (int a = 0; a < 3; ++a) ve[j][a] = Sv.xsT[a * ni + bst.e0 + i];
+      }
+#pragma unroll
+    for (int j = 0; j < kPZ; ++j) {
+      const int i = (int)threadIdx.x + j * kBottomThreads;
+      if (i < bst.zn)
+#pragma unroll
+        for (int a = 0; a < 3; ++a) sz[a * kStageZ + i] = vz[j][a];
+    }
+    if (bst.en > 0)
+#pragma unroll
+      for (int j = 0; j < kPE; ++j) {
+        const int i = (int)threadIdx.x + j * kBottomThreads;
+        if (i < bst.en)
+#pragma unroll
+          for (int a = 0; a < 3; ++a) se[a * kStageE + i] = ve[j][a];
+      }
+  }
+  __syncthreads();
   // ---- the subdomain row: x_v = Z_s[v, :] rhs_s - E_s^T[v, :] x_T(s)
-  if (have_row) {
-    // the row descriptors are the same in every lane of the wave
-    const int ns = wave_uniform(br.ns), nI = wave_uniform(br.nI);
-    const int b0 = wave_uniform(br.b0), ir0 = wave_uniform(br.ir0);
-    const double* __restrict__ Zr = Sv.Zs + wave_uniform(bo.zs);
-    const double* __restrict__ Er = Sv.Et + wave_uniform(bo.et);
-    const int ni = Sv.n_irows;
+  if (have_row && staged) {
+    // the same walk as below (same per-lane order of the terms), with the
+    // right-hand side and x_T(s) read from LDS
+    const int zo = b0 - bst.z0, eo = ir0 - bst.e0;
+    double a0 = 0, a1 = 0, a2 = 0;
+    for (int t = 0; t < max(tz, te); ++t) {
+      double cz[kBottomChunk], ce[kBottomChunkE];
+      if (t == 0) {
+#pragma unroll
+        for (int j = 0; j < kBottomChunk; ++j) cz[j] = cz0[j];
+#pragma unroll
+        for (int j = 0; j < kBottomChunkE; ++j) ce[j] = ce0[j];
+      } else {
+        if (t < tz)
+#pragma unroll
+          for (int j = 0; j < kBottomChunk; ++j) cz[j] = Zr[min(t * kSpan + lane + 64 * j, ns - 1)];
+        if (t < te)
+#pragma unroll
+          for (int j = 0; j < kBottomChunkE; ++j) ce[j] = Er[min(t * kSpanE + lane + 64 * j, nI - 1)];
+      }
+      if (t < tz)
+#pragma unroll
+        for (int j = 0; j < kBottomChunk; ++j) {
+          const int u = t * kSpan + lane + 64 * j;
+          const double c = (u < ns) ? cz[j] : 0.0;
+          const int q = zo + min(u, ns - 1);
+          a0 += c * sz[q];
+          a1 += c * sz[kStageZ + q];
+          a2 += c * sz[2 * kStageZ + q];
+        }
+      if (t < te)
+#pragma unroll
+        for (int j = 0; j < kBottomChunkE; ++j) {
+          const int p = t * kSpanE + lane + 64 * j;
+          const double c = (p < nI) ? ce[j] : 0.0;
+          const int q = eo + min(p, nI - 1);
+          a0 -= c * se[q];
+          a1 -= c * se[kStageE + q];
+          a2 -= c * se[2 * kStageE + q];
+        }
+    }
+    xo[0] = wave_sum(a0);
+    xo[1] = wave_sum(a1);
+    xo[2] = wave_sum(a2);
+    if (lane == 0) {
+      dst[v] = xo[0];
+      dst[nv + v] = xo[1];
+      dst[2 * nv + v] = xo[2];
+    }
+  } else if (have_row) {
     const double* __restrict__ x0 = Sv.xsT + ir0;
     const double* __restrict__ s0 = src + b0;
     const double* __restrict__ w0 = wv + b0;
-    // each trip takes 64 x kBottomChunk entries of Z_s[v, :] (against the
-    // right-hand side) and 64 x kBottomChunkE of E_s^T[v, :] (against
-    // x_T(s)); entries past a part's end repeat its last entry with weight zero
-    constexpr int kSpan = 64 * kBottomChunk, kSpanE = 64 * kBottomChunkE;
-    const int tz = (ns + kSpan - 1) / kSpan, te = (nI + kSpanE - 1) / kSpanE;
     double a0 = 0, a1 = 0, a2 = 0;
     double cz[kBottomChunk], yz[kBottomChunk][3], wz[kBottomChunk][3];
     double ce[kBottomChunkE], ye[kBottomChunkE][3];

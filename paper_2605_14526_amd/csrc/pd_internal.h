@@ -54,6 +54,12 @@ struct alignas(16) BRow {
 struct alignas(16) BOff {
   long long zs, et;
 };
+// The ranges a subdomain-solve block stages in LDS: the right-hand-side rows
+// z0 .. z0 + zn - 1 that its rows' subdomains span and their interface copies
+// e0 .. e0 + en - 1 (zn = 0: the ranges exceed the LDS buffers, no staging).
+struct alignas(16) BStage {
+  int z0, zn, e0, en;
+};
 
 struct DeviceSolve {
   // partitioned inverse of A~ over free vertices (two-level Schur complement)
@@ -75,6 +81,7 @@ struct DeviceSolve {
   ERow* erow = nullptr;         // nT
   BRow* brow = nullptr;         // nB
   BOff* boff = nullptr;         // nB
+  BStage* bstage = nullptr;     // one per subdomain-solve block of subdomain rows
   double* xsT = nullptr;        // 3 x n_irows: interface values gathered per subdomain
   int n_irows = 0;
   int max_coup = 0;

@@ -246,7 +246,7 @@ void free_device(Scene& S) {
   DeviceSolve& D = S.S;
   dfree(D.Zs); dfree(D.Et); dfree(D.E); dfree(D.Z); dfree(D.zs_off); dfree(D.e_off); dfree(D.sub_of);
   dfree(D.sub_begin); dfree(D.ir_off); dfree(D.irows); dfree(D.rl_ptr); dfree(D.rl_sub); dfree(D.rl_p); dfree(D.rT);
-  dfree(D.cpl); dfree(D.erow); dfree(D.brow); dfree(D.boff); dfree(D.xsT);
+  dfree(D.cpl); dfree(D.erow); dfree(D.brow); dfree(D.boff); dfree(D.bstage); dfree(D.xsT);
   dfree(S.contrib); dfree(S.qt); dfree(S.vt); dfree(S.qtil); dfree(S.c); dfree(S.q_cur); dfree(S.q_prev);
   dfree(S.b_cur); dfree(S.b_prev); dfree(S.qhat); dfree(S.q_last); dfree(S.g_last); dfree(S.dQ); dfree(S.dG);
   dfree(S.ctl); dfree(S.dstat); dfree(S.red_part); dfree(S.red_fin);
@@ -371,7 +371,8 @@ SolveArgs solve_args(const Scene& S) {
   A.sub_of = D.sub_of; A.sub_begin = D.sub_begin; A.Zs = D.Zs; A.zs_off = D.zs_off; A.Et = D.Et; A.E = D.E;
   A.e_off = D.e_off; A.ir_off = D.ir_off; A.irows = D.irows; A.rl_ptr = D.rl_ptr; A.rl_sub = D.rl_sub;
   A.rl_p = D.rl_p; A.Z = D.Z; A.rT = D.rT;
-  A.cpl = D.cpl; A.erow = D.erow; A.brow = D.brow; A.boff = D.boff; A.xsT = D.xsT; A.n_irows = D.n_irows;
+  A.cpl = D.cpl; A.erow = D.erow; A.brow = D.brow; A.boff = D.boff; A.bstage = D.bstage; A.xsT = D.xsT;
+  A.n_irows = D.n_irows;
   return A;
 }
 
@@ -774,11 +775,22 @@ void factorize(Scene& S) {
     brow[v] = BRow{b0, ns, nI, ir_off[s]};
     boff[v] = BOff{zs_off[s] + (long long)(v - b0) * ns, e_off[s] + (long long)(v - b0) * nI};
   }
+  // staged ranges of each subdomain-solve block (rows are in subdomain order, so
+  // a block's rows span one contiguous range of right-hand-side rows and one of
+  // interface copies)
+  constexpr int kRowsPerBlock = kBottomThreads / 64;
+  std::vector<BStage> bstage(std::max(1, (nB + kRowsPerBlock - 1) / kRowsPerBlock), BStage{0, 0, 0, 0});
+  for (int b = 0; b * kRowsPerBlock < nB; ++b) {
+    const BRow& f = brow[b * kRowsPerBlock];
+    const BRow& l = brow[std::min(nB, (b + 1) * kRowsPerBlock) - 1];
+    const int zn = l.b0 + l.ns - f.b0, en = l.ir0 + l.nI - f.ir0;
+    if (zn <= kStageZ && en <= kStageE) bstage[b] = BStage{f.b0, zn, f.ir0, en};
+  }
   // upload the solve structure
   DeviceSolve& D = S.S;
   dfree(D.Zs); dfree(D.Et); dfree(D.E); dfree(D.Z); dfree(D.zs_off); dfree(D.e_off); dfree(D.sub_of);
   dfree(D.sub_begin); dfree(D.ir_off); dfree(D.irows); dfree(D.rl_ptr); dfree(D.rl_sub); dfree(D.rl_p); dfree(D.rT);
-  dfree(D.cpl); dfree(D.erow); dfree(D.brow); dfree(D.boff); dfree(D.xsT);
+  dfree(D.cpl); dfree(D.erow); dfree(D.brow); dfree(D.boff); dfree(D.bstage); dfree(D.xsT);
   D.Zs = dalloc<double>(Zs_all.size()); upload(D.Zs, Zs_all);
   D.Et = dalloc<double>(Et_all.size()); upload(D.Et, Et_all);
   D.E = dalloc<double>(E_flat.size()); upload(D.E, E_flat);
@@ -786,6 +798,7 @@ void factorize(Scene& S) {
   D.erow = dalloc<ERow>(erow.size()); upload(D.erow, erow);
   D.brow = dalloc<BRow>(brow.size()); upload(D.brow, brow);
   D.boff = dalloc<BOff>(boff.size()); upload(D.boff, boff);
+  D.bstage = dalloc<BStage>(bstage.size()); upload(D.bstage, bstage);
   D.n_irows = (int)irows.size();
   D.xsT = dalloc<double>(3 * (size_t)std::max(1, D.n_irows));
   D.max_coup = max_coup;

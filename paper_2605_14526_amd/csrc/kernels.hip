@@ -68,12 +68,15 @@ __device__ __forceinline__ double group8_sum(double v) {
   return v;
 }
 
-// block-wide sum of NV values per thread; result valid in thread 0
+// block-wide sum of NV values per thread; result valid in thread 0.  With
+// lane0 (block-uniform) only lane 0 of each wave holds nonzero values, and its
+// values stand for the wave's sums: the butterfly would only add zeros.
 template <int NV>
-__device__ __forceinline__ void block_sum(double (&v)[NV], double* lds /* >= 16*NV */) {
+__device__ __forceinline__ void block_sum(double (&v)[NV], double* lds /* >= 16*NV */, bool lane0 = false) {
   const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+  if (!lane0)
 #pragma unroll
-  for (int i = 0; i < NV; ++i) v[i] = wave_sum(v[i]);
+    for (int i = 0; i < NV; ++i) v[i] = wave_sum(v[i]);
   __syncthreads();
   if (lane == 0)
 #pragma unroll
@@ -100,9 +103,10 @@ __device__ __forceinline__ double* part_value(const RedArgs& R, int site, int j)
 // Producer side: block sum of N values, written by thread 0 as partial `idx`
 // of `site`.  Every thread of the block must call it.
 template <int N>
-__device__ __forceinline__ void write_partial(double (&v)[N], const RedArgs& R, int site, int idx) {
+__device__ __forceinline__ void write_partial(double (&v)[N], const RedArgs& R, int site, int idx,
+                                              bool lane0 = false) {
   __shared__ double red[16 * N];
-  block_sum<N>(v, red);
+  block_sum<N>(v, red, lane0);
   if (threadIdx.x == 0)
 #pragma unroll
     for (int j = 0; j < N; ++j) part_value(R, site, j)[idx] = v[j];
@@ -924,12 +928,13 @@ __global__ void __launch_bounds__(kBlock) k_top(VertArgs Vx, SolveArgs Sv, doubl
 // Anderson append of one forward iteration for the free row my_row (-1: no
 // row): g = q^ - q^k, the new difference columns (Eqs. aa_dG, aa_dQ) and the
 // block's Gram partial sums.  xo = q^ of the row, u0 = q^k, u1 = g of the last
-// iteration, u2 = q of the last iteration; aa = the ring state of parity k.
-// Every thread of the block calls it.
+// iteration, u2 = q of the last iteration; aa = the ring state of parity k;
+// lane0: only lane 0 of each wave has a row (block-uniform).  Every thread of
+// the block calls it.
 template <int M>
 __device__ __forceinline__ void aa_append(const StepState& St, const RedArgs& R, int nv, int bid, int my_row,
                                           const double (&xo)[3], const double (&u0)[3], const double (&u1)[3],
-                                          const double (&u2)[3], const int (&aa)[4]) {
+                                          const double (&u2)[3], const int (&aa)[4], bool lane0 = false) {
   int nonempty, nc, head, slot_new;
   aa_layout(aa, M, nonempty, nc, head, slot_new);
   // Gram partial sums, compact layout: G[j][l] at j*M + l, rhs[j] at M*M + j
@@ -978,7 +983,7 @@ __device__ __forceinline__ void aa_append(const StepState& St, const RedArgs& R,
     }
   }
   __shared__ double red[16 * NA];
-  block_sum<NA>(part, red);
+  block_sum<NA>(part, red, lane0);
   if (threadIdx.x == 0) {
 #pragma unroll
     for (int j = 0; j < M; ++j) {
@@ -1269,7 +1274,7 @@ __device__ __forceinline__ void b_bottom(VertArgs Vx, SolveArgs Sv, StepState St
   if (MODE == kModePlain) return;
   // ---- per-vertex work
   if (MODE == kModeFwd) {
-    if constexpr (M > 0) aa_append<M>(St, R, nv, bid, my_row, xo, u0, u1, u2, aa);
+    if constexpr (M > 0) aa_append<M>(St, R, nv, bid, my_row, xo, u0, u1, u2, aa, sub_block);
   } else {
     double v3[3] = {0, 0, 0};
     if (my_row >= 0) {
@@ -1298,11 +1303,11 @@ __device__ __forceinline__ void b_bottom(VertArgs Vx, SolveArgs Sv, StepState St
       }
     }
     if (MODE == kModeFixed) {
-      write_partial<3>(v3, R, kRedFix, bid);
+      write_partial<3>(v3, R, kRedFix, bid, sub_block);
     } else if (MODE != kModePCGSolve) {
       // PCG sums of iteration k land in the parity slot read by iteration k + 1
       const int slot = (MODE == kModePCGInit) ? 0 : ((k + 1) & 1);
-      write_partial<3>(v3, R, kRedRZ0 + slot, bid);
+      write_partial<3>(v3, R, kRedRZ0 + slot, bid, sub_block);
     }
   }
 }

@@ -165,6 +165,15 @@ int pd_scene_factorize(pd_scene* scene, void* stream);
  * mu_bar, lam_bar, k_bar, mu_ref (may be NULL). */
 int pd_scene_info(const pd_scene* scene, double* info, double* means);
 
+/* The library's vertex order (the ordering of the factorization, Sec. 4.6):
+ * perm_out[i] = the caller's index of library vertex i, for i < n_verts (host
+ * memory, int32).  Library order holds the subdomains' vertices first (one
+ * contiguous range per subdomain), then the interface vertices, then the
+ * pinned ones.  Every step entry point takes and returns caller order, so this
+ * is for callers that want to lay their own data out like the factor.
+ * Errors: PD_ERR_INVALID_ARG for a null argument. */
+int pd_scene_get_permutation(const pd_scene* scene, int32_t* perm_out);
+
 /* Bytes of one checkpoint record (q_t, q tilde, q*, q*-1 of one step; with
  * obstacles also the step's contact rows and impulses). */
 size_t pd_ckpt_bytes(const pd_scene* scene);

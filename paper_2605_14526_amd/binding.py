@@ -23,6 +23,7 @@ ERRORS = {-1: "PD_ERR_INVALID_ARG", -2: "PD_ERR_DEGENERATE_TET", -3: "PD_ERR_NON
           -8: "PD_ERR_CONTACT"}
 
 EXPORTED = ["pd_scene_create", "pd_scene_destroy", "pd_scene_set_material", "pd_scene_factorize", "pd_scene_info",
+            "pd_scene_get_permutation",
             "pd_ckpt_bytes", "pd_step_forward", "pd_step_backward", "pd_debug_local_rhs", "pd_debug_apply_Ainv",
             "pd_debug_apply_K", "pd_kernel_timer", "pd_kernel_timer_read", "pd_adjoint_reset", "pd_scene_vertex_logw",
             "pd_mpn_create", "pd_mpn_destroy", "pd_mpn_info", "pd_mpn_init_params", "pd_mpn_set_params",
@@ -85,6 +86,7 @@ def lib() -> ctypes.CDLL:
     L.pd_scene_set_material.argtypes = [vp, vp]
     L.pd_scene_factorize.argtypes = [vp, vp]
     L.pd_scene_info.argtypes = [vp, vp, vp]
+    L.pd_scene_get_permutation.argtypes = [vp, vp]
     L.pd_ckpt_bytes.argtypes = [vp]
     L.pd_ckpt_bytes.restype = ctypes.c_size_t
     L.pd_step_forward.argtypes = [vp, vp, vp, vp, vp, vp, vp, vp, ctypes.POINTER(pd_fwd_stats), vp]
@@ -220,6 +222,13 @@ class Scene:
         d = {k: info[i] for i, k in enumerate(keys)}
         d.update(mu_bar=means[0], lam_bar=means[1], k_bar=means[2], mu_ref=means[3])
         return d
+
+    def permutation(self):
+        """The library's vertex order: perm[i] = caller index of library vertex i."""
+        n = int(self.info()["n_verts"])
+        perm = np.empty(n, dtype=np.int32)
+        check(lib().pd_scene_get_permutation(self.ptr, perm.ctypes.data), "pd_scene_get_permutation")
+        return perm
 
     def set_material(self, log_E):
         self._logE = np.ascontiguousarray(log_E, dtype=np.float64)

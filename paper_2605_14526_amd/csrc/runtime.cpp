@@ -1143,6 +1143,16 @@ int pd_scene_info(const pd_scene* scene, double* info, double* means) {
   return PD_OK;
 }
 
+int pd_scene_get_permutation(const pd_scene* scene, int32_t* perm_out) {
+  if (!scene || !perm_out) {
+    pdhot::g_last_error = "null argument";
+    return PD_ERR_INVALID_ARG;
+  }
+  const Scene& S = scene->S;
+  for (int i = 0; i < S.nv; ++i) perm_out[i] = S.L.lib2orig[i];
+  return PD_OK;
+}
+
 size_t pd_ckpt_bytes(const pd_scene* scene) {
   if (!scene) return 0;
   const Scene& S = scene->S;

@@ -88,3 +88,20 @@ def test_negatively_oriented_tets(th):
     flipped[::3, [1, 2]] = flipped[::3, [2, 1]]  # every third tet given inside out
     sc2 = scenes.Scene(**{**sc.__dict__, "tets": flipped})
     step_pair(th, sc2)
+
+
+def test_permutation_is_the_library_order(th):
+    """pd_scene_get_permutation: a permutation of the vertices in which the
+    free vertices precede the pinned ones, and the subdomain solve's rows
+    precede the interface rows (n_free - n_interface of them)."""
+    from paper_2605_14526_amd.binding import Scene
+    sc = scenes.small_beam(7, 3, 3, seed=5, contrast=30.0, nu=0.49)
+    g = Scene.from_scene(sc, max_sub=16)
+    info = g.info()
+    perm = g.permutation()
+    nv, nf = int(info["n_verts"]), int(info["n_free"])
+    assert perm.shape == (nv,) and np.array_equal(np.sort(perm), np.arange(nv))
+    pinned = sc.pinned.astype(bool)
+    assert not pinned[perm[:nf]].any() and pinned[perm[nf:]].all()
+    assert info["n_subdomains"] > 1 and 0 < info["n_interface"] < nf
+

@@ -213,9 +213,7 @@ def test_drop_100k_tets_through_contact(th):
     Infinity Cache) in the benchmark's launch configuration, started with its
     lowest point half a detection distance above the obstacles so that it
     touches at once: four steps from the oracle's own states (rows, iteration
-    counts and positions).  Gradients through contact are
-    held to the oracle on the smaller drops and the 225-row slab: the oracle's
-    fixed point needs minutes at this size."""
+    counts and positions).  The gradient of such a step is the next test."""
     from paper_2605_14526_amd.binding import Scene
     sc = scenes.drop_blob(res=41, with_box=True)
     (lo, hi) = sc.obstacles["boxes"][0]
@@ -237,6 +235,42 @@ def test_drop_100k_tets_through_contact(th):
         n_act = max(n_act, int((lam > 0).sum()))
         q, v = qo, vo
     assert n_act > 0
+
+
+def test_drop_100k_tets_gradient_through_contact(th):
+    """One backward step of the 99,730-tet drop at first touch (rows active),
+    from the oracle's own checkpoint data, against the oracle's projected fixed
+    point run to a 1e-9 step (its error, about 2e-8 at its contraction rate of
+    0.95, is well inside the 1e-6 gradient tolerance)."""
+    from paper_2605_14526_amd.binding import Scene
+    sc = scenes.drop_blob(res=41, with_box=True)
+    (lo, hi) = sc.obstacles["boxes"][0]
+    X = sc.X
+    over = (X[:, 0] >= lo[0]) & (X[:, 0] <= hi[0]) & (X[:, 1] >= lo[1]) & (X[:, 1] <= hi[1])
+    gap = min(X[:, 2].min(), (X[over, 2] - hi[2]).min())
+    osc = O.OracleScene(sc, eps_adj=1e-9, kmax_bwd=5000)
+    g = Scene.from_scene(sc, eps_adj=1e-10, adj_warm=3)
+    q = X - np.array([0.0, 0.0, gap - 0.5 * sc.obstacles["d_c"]])
+    v = sc.v0()
+    for t in range(2):
+        f = sc.f_ext(t)
+        con = O.detect_contacts(q, v, sc.h, sc.pinned, sc.obstacles)
+        qo, vo, qm1, lam, st_o = O.step_forward_contact(osc, q, v, f, con)
+        ck = g.new_ckpt()
+        qg, vg, st = g.step_forward(dev(th, q), dev(th, v), dev(th, f), ckpt=ck)
+        assert st["iters"] == st_o["iters"] and rel(host(qg), qo) < TOL_POS, (t, st, st_o["iters"])
+        q_t, v_t, qs, qsm1 = q, v, qo, qm1
+        q, v = qo, vo
+    n_act = int((lam > 0).sum())
+    assert n_act > 0
+    gq = np.random.Generator(np.random.PCG64(7)).standard_normal(q_t.shape)
+    gv = 0.1 * gq
+    a = O.step_backward_contact(osc, q_t, v_t, f, qs, qsm1, gq, gv, con, lam, adj_mode=0)
+    assert a[4]["status"] == 0
+    b = g.step_backward(ck, dev(th, gq), dev(th, gv))
+    assert b[4]["n_active"] == n_act
+    for x, y in zip(b[:4], a[:4]):
+        assert rel(host(x), y) < TOL_GRAD, rel(host(x), y)
 
 
 def slab_drop(n=14, nz=2, edge=0.02):

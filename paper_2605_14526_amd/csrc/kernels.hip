@@ -115,11 +115,36 @@ __device__ __forceinline__ void write_partial(double (&v)[N], const RedArgs& R, 
 // Consumer side: the total of the first N values of every partial of `site`,
 // returned to every thread; block 0 (bid) also stores it in fin.  Wave 0 does
 // the sum in a fixed order that does not depend on the block size: lane l
-// takes partials l, l + 64, l + 128, ... (a chunk of them requested at once),
-// then the wave's butterfly.
+// takes partials l, l + 64, l + 128, ... in that order, then the wave's
+// butterfly.  The partials are requested a chunk at a time, each chunk before
+// the previous one is summed, so two chunks cost one memory round trip.
+template <int N>
+__device__ __forceinline__ void consume_load(const RedArgs& R, int site, int width, int np, int first,
+                                             double (&v)[N <= 4 ? 8 : (N <= 8 ? 4 : 1)][N]) {
+  constexpr int kChunk = N <= 4 ? 8 : (N <= 8 ? 4 : 1);
+#pragma unroll
+  for (int c = 0; c < kChunk; ++c) {
+    const int b = min(first + 64 * c, np - 1);  // past the end: a repeat of the last, not summed
+#pragma unroll
+    for (int j = 0; j < N; ++j) v[c][j] = (j < width) ? part_value(R, site, j)[b] : 0.0;
+  }
+}
+
+template <int N>
+__device__ __forceinline__ void consume_add(int np, int first, const double (&v)[N <= 4 ? 8 : (N <= 8 ? 4 : 1)][N],
+                                            double (&acc)[N]) {
+  constexpr int kChunk = N <= 4 ? 8 : (N <= 8 ? 4 : 1);
+#pragma unroll
+  for (int c = 0; c < kChunk; ++c)
+    if (first + 64 * c < np)
+#pragma unroll
+      for (int j = 0; j < N; ++j) acc[j] += v[c][j];
+}
+
 template <int N>
 __device__ __forceinline__ void consume(const RedArgs& R, int site, double (&tot)[N], int bid, int width = N) {
   constexpr int kChunk = N <= 4 ? 8 : (N <= 8 ? 4 : 1);
+  constexpr int kStep = 64 * kChunk;
   __shared__ double bc[N];
   if (threadIdx.x < 64) {
     const int lane = threadIdx.x;
@@ -127,19 +152,16 @@ __device__ __forceinline__ void consume(const RedArgs& R, int site, double (&tot
     double acc[N];
 #pragma unroll
     for (int j = 0; j < N; ++j) acc[j] = 0.0;
-    for (int base = 0; base < np; base += 64 * kChunk) {
-      double v[kChunk][N];
-#pragma unroll
-      for (int c = 0; c < kChunk; ++c) {
-        const int b = min(base + lane + 64 * c, np - 1);
-#pragma unroll
-        for (int j = 0; j < N; ++j) v[c][j] = (j < width) ? part_value(R, site, j)[b] : 0.0;
+    if (np > 0) {
+      // two chunk buffers in turn: chunk i + 1 is requested before chunk i is added
+      double v0[kChunk][N], v1[kChunk][N];
+      consume_load<N>(R, site, width, np, lane, v0);
+      for (int base = 0; base < np; base += 2 * kStep) {
+        consume_load<N>(R, site, width, np, base + kStep + lane, v1);
+        consume_add<N>(np, base + lane, v0, acc);
+        consume_load<N>(R, site, width, np, base + 2 * kStep + lane, v0);  // unconditional: no wait on it below
+        consume_add<N>(np, base + kStep + lane, v1, acc);
       }
-#pragma unroll
-      for (int c = 0; c < kChunk; ++c)
-        if (base + lane + 64 * c < np)
-#pragma unroll
-          for (int j = 0; j < N; ++j) acc[j] += v[c][j];
     }
 #pragma unroll
     for (int j = 0; j < N; ++j) acc[j] = wave_sum(acc[j]);

@@ -118,10 +118,14 @@ __device__ __forceinline__ void write_partial(double (&v)[N], const RedArgs& R, 
 // takes partials l, l + 64, l + 128, ... in that order, then the wave's
 // butterfly.  The partials are requested a chunk at a time, each chunk before
 // the previous one is summed, so two chunks cost one memory round trip.
+// partials per lane in one chunk of the consumer wave (N values each)
+template <int N>
+constexpr int consume_chunk() { return N <= 4 ? 8 : (N <= 8 ? 4 : 1); }
+
 template <int N>
 __device__ __forceinline__ void consume_load(const RedArgs& R, int site, int width, int np, int first,
-                                             double (&v)[N <= 4 ? 8 : (N <= 8 ? 4 : 1)][N]) {
-  constexpr int kChunk = N <= 4 ? 8 : (N <= 8 ? 4 : 1);
+                                             double (&v)[consume_chunk<N>()][N]) {
+  constexpr int kChunk = consume_chunk<N>();
 #pragma unroll
   for (int c = 0; c < kChunk; ++c) {
     const int b = min(first + 64 * c, np - 1);  // past the end: a repeat of the last, not summed
@@ -131,9 +135,9 @@ __device__ __forceinline__ void consume_load(const RedArgs& R, int site, int wid
 }
 
 template <int N>
-__device__ __forceinline__ void consume_add(int np, int first, const double (&v)[N <= 4 ? 8 : (N <= 8 ? 4 : 1)][N],
+__device__ __forceinline__ void consume_add(int np, int first, const double (&v)[consume_chunk<N>()][N],
                                             double (&acc)[N]) {
-  constexpr int kChunk = N <= 4 ? 8 : (N <= 8 ? 4 : 1);
+  constexpr int kChunk = consume_chunk<N>();
 #pragma unroll
   for (int c = 0; c < kChunk; ++c)
     if (first + 64 * c < np)
@@ -143,7 +147,7 @@ __device__ __forceinline__ void consume_add(int np, int first, const double (&v)
 
 template <int N>
 __device__ __forceinline__ void consume(const RedArgs& R, int site, double (&tot)[N], int bid, int width = N) {
-  constexpr int kChunk = N <= 4 ? 8 : (N <= 8 ? 4 : 1);
+  constexpr int kChunk = consume_chunk<N>();
   constexpr int kStep = 64 * kChunk;
   __shared__ double bc[N];
   if (threadIdx.x < 64) {

@@ -144,6 +144,31 @@ def test_hetero_beam_full_size(th):
         assert rel(a, b) < TOL_GRAD, (rel(a, b), its)
 
 
+def test_hetero_beam_80_cubes_many_partials(th):
+    """The heterogeneous beam at twice its length (80x10x10 cubes, 40000 tets):
+    the subdomain solve then has more than 1,024 workgroups, so the partial
+    sums it leaves for the Gram, PCG and gate totals are read in more than two
+    chunks by the consuming wave.  Three forward steps and their reverse sweep
+    against the oracle."""
+    from paper_2605_14526_amd.binding import Scene
+    sc = scenes.hetero_beam_c2(nx=80, steps=3)
+    T = 3
+    g = Scene.from_scene(sc, eps_adj=1e-11, adj_warm=3)
+    info = g.info()
+    assert (info["n_free"] - info["n_interface"]) / 4 > 1024, info
+    o = O.OracleScene(sc, eps_adj=1e-13)
+    qs, v, cks, iters = gpu_rollout(th, g, sc, T)
+    q_o, v_o, ck_o, st_o = O.rollout(o, T)
+    assert iters == [s["iters"] for s in st_o]
+    assert rel(host(qs[-1]), q_o) < TOL_POS
+    _, gq = scenes.centroid_loss(q_o, sc.target_centroid)
+    gv = np.zeros_like(gq)
+    gq0_o, gv0_o, gl_o, _ = O.rollout_backward(o, ck_o, gq, gv, adj_mode=0)
+    gq0, gv0, gl, its = gpu_reverse(th, g, cks, gq, gv)
+    for a, b in [(gq0, gq0_o), (gv0, gv0_o), (gl, gl_o)]:
+        assert rel(a, b) < TOL_GRAD, (rel(a, b), its)
+
+
 @pytest.mark.parametrize("max_sub", [600, 1200])
 def test_hetero_beam_large_subdomains(th, max_sub):
     """The 20000-tet beam partitioned into fewer, larger subdomains (up to 550

@@ -254,8 +254,10 @@ void launch_epilogue(const VertArgs& V, const StepState& St, double* q_next, dou
 void launch_to_lib(const VertArgs& V, const double* user, double* lib, int free_only, hipStream_t s);
 void launch_from_lib(const VertArgs& V, const double* lib, double* user, int free_only, hipStream_t s);
 void launch_tr_partials(const ElemArgs& E, const VertArgs& V, const RedArgs& R, const double* ck, hipStream_t s);
+// also clears zero[0, nzero) (nullable; nzero at most one workgroup, kBlock) for the kernels that follow
 void launch_bwd_elem(const ElemArgs& E, const VertArgs& V, const RedArgs& R, const double* ck, double eps_tr,
-                     double tau_force, int use_partials, double* jac, double* bstat, hipStream_t s);
+                     double tau_force, int use_partials, double* jac, double* bstat, int* zero, int nzero,
+                     hipStream_t s);
 void launch_apply_K(int mode, const ElemArgs& E, const VertArgs& V, const AdjState& A, const RedArgs& R,
                     const double* jac, const double* x, int it, hipStream_t s);
 void launch_adj_gather(int mode, const VertArgs& V, const AdjState& A, const RedArgs& R, int it, hipStream_t s);

@@ -573,6 +573,9 @@ __global__ void __launch_bounds__(kBlock) k_prologue(VertArgs Vx, const double* 
                                                      const double* __restrict__ f_user,
                                                      const double* __restrict__ q0_user, int inertial,
                                                      StepState St) {
+  // the step's control words (done flag, counters, Anderson layout) start at
+  // zero; nothing in this kernel reads them
+  if (blockIdx.x == 0 && threadIdx.x < kCtlSize) St.ctl[threadIdx.x] = 0;
   const int gtid = blockIdx.x * blockDim.x + threadIdx.x;
   const int i = gtid >> 3, l = gtid & 7;
   const int nv = Vx.nv;
@@ -1596,7 +1599,11 @@ __global__ void __launch_bounds__(kBlock) k_tr_partials(ElemArgs E, VertArgs Vx,
 // differential {U, V, D, c1, c2, s*} (Alg. 2 element loop).
 __global__ void __launch_bounds__(kBlock) k_bwd_elem(ElemArgs E, VertArgs Vx, RedArgs R, const double* __restrict__ ck,
                                                      double eps_tr, double tau_force, int use_partials,
-                                                     double* __restrict__ jac, double* __restrict__ bstat) {
+                                                     double* __restrict__ jac, double* __restrict__ bstat,
+                                                     int* __restrict__ zero, int nzero) {
+  // words cleared for the kernels that follow (the adjoint's control words);
+  // nothing in this kernel reads them
+  if (zero && blockIdx.x == 0 && threadIdx.x < nzero) zero[threadIdx.x] = 0;
   __shared__ double tau_s;
   double tr[2] = {0.0, 0.0};
   if (use_partials) consume<2>(R, kRedTR, tr, blockIdx.x);
@@ -2239,8 +2246,9 @@ void launch_tr_partials(const ElemArgs& E, const VertArgs& V, const RedArgs& R, 
   launch_ext(k_tr_partials, dim3(nblk), dim3(kBlock), 0, s, E, V, R, ck, ntb);
 }
 void launch_bwd_elem(const ElemArgs& E, const VertArgs& V, const RedArgs& R, const double* ck, double eps_tr,
-                     double tau_force, int use_partials, double* jac, double* bstat, hipStream_t s) {
-  launch_ext(k_bwd_elem, PD_GRID(E.ne), 0, s, E, V, R, ck, eps_tr, tau_force, use_partials, jac, bstat);
+                     double tau_force, int use_partials, double* jac, double* bstat, int* zero, int nzero,
+                     hipStream_t s) {
+  launch_ext(k_bwd_elem, PD_GRID(E.ne), 0, s, E, V, R, ck, eps_tr, tau_force, use_partials, jac, bstat, zero, nzero);
 }
 void launch_apply_K(int mode, const ElemArgs& E, const VertArgs& V, const AdjState& A, const RedArgs& R,
                     const double* jac, const double* x, int it, hipStream_t s) {

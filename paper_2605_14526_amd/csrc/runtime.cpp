@@ -1265,8 +1265,7 @@ int pd_step_forward(pd_scene* scene, const double* q_t, const double* v_t, const
   // prologue: (1/h) B_beta q_t element terms, then q~, c, q^0
   launch_to_lib(V, q_t, S.qt, 0, st);
   launch_elem_GtG(E, S.qt, S.nv, S.bV, S.contrib, st);
-  launch_prologue(V, q_t, v_t, f_ext, q0, S.fwd_start, T, st);
-  launch_zero_int(S.ctl, kCtlSize, st);
+  launch_prologue(V, q_t, v_t, f_ext, q0, S.fwd_start, T, st);  // also clears the control words
   // contact rows of this step (Sec. 4.7): with rows, every global solve is
   // followed by the FB Newton solve and the column correction, which also
   // appends the Anderson columns
@@ -1389,8 +1388,7 @@ static void adjoint_solve(Scene& S, hipStream_t st, double tau_force, double* bs
   StepState T = step_state(S);
   T.done = Ad.done;  // plain solves inside the adjoint stop with it
   launch_tr_partials(E, V, R, ck, st);
-  launch_bwd_elem(E, V, R, ck, S.eps_tr, tau_force, 1, S.jac, S.dstat + 4, st);
-  launch_zero_int(S.ctl + kCtlAdj, 4, st);
+  launch_bwd_elem(E, V, R, ck, S.eps_tr, tau_force, 1, S.jac, S.dstat + 4, S.ctl + kCtlAdj, 4, st);
   const bool pcg = S.adj_method == 0;
   if (pcg) {
     if (warm) {  // r = q bar - (A~ - K) mu0
@@ -1575,7 +1573,7 @@ int pd_debug_apply_K(pd_scene* scene, const double* q, double tau, const double*
   // a checkpoint-shaped scratch whose q* slot holds q
   double* ck = S.ck_scratch;
   launch_to_lib(V, q, ck + 6 * (size_t)S.nv, 0, st);
-  launch_bwd_elem(E, V, R, ck, S.eps_tr, tau, 0, S.jac, S.dstat + 4, st);
+  launch_bwd_elem(E, V, R, ck, S.eps_tr, tau, 0, S.jac, S.dstat + 4, nullptr, 0, st);
   launch_to_lib(V, x, S.p, 1, st);
   launch_apply_K(kModeDebug, E, V, Ad, R, S.jac, S.p, 0, st);
   launch_adj_gather(kModeDebug, V, Ad, R, 0, st);
@@ -1852,7 +1850,6 @@ int pd_batch_step_forward(pd_batch* B, const double* const* q_t, const double* c
     launch_to_lib(V, q_t[s], S.qt, 0, st);
     launch_elem_GtG(E, S.qt, S.nv, S.bV, S.contrib, st);
     launch_prologue(V, q_t[s], v_t[s], f_ext ? f_ext[s] : nullptr, q0 ? q0[s] : nullptr, S.fwd_start, T, st);
-    launch_zero_int(S.ctl, kCtlSize, st);
     kmax = std::max(kmax, S.kmax_fwd);
   }
   int k = 0;
@@ -1923,8 +1920,7 @@ int pd_batch_step_backward(pd_batch* B, const void* const* ckpt, const double* c
     launch_bwd_prologue(V, Ad, gq_next ? gq_next[s] : nullptr, gv_next ? gv_next[s] : nullptr, warm[s], S.mu_h1,
                         S.mu_h2, S.mu_h3, st);
     launch_tr_partials(E, V, R, ck, st);
-    launch_bwd_elem(E, V, R, ck, S.eps_tr, -1.0, 1, S.jac, S.dstat + 4, st);
-    launch_zero_int(S.ctl + kCtlAdj, 4, st);
+    launch_bwd_elem(E, V, R, ck, S.eps_tr, -1.0, 1, S.jac, S.dstat + 4, S.ctl + kCtlAdj, 4, st);
     kmax = std::max(kmax, S.kmax_bwd);
   }
   if (any_warm) {  // r = q bar - (A~ - K) mu0 (a zero mu0 gives r = q bar again)

@@ -1,7 +1,9 @@
 """Edge cases through the C ABI: invalid inputs are errors (empty mesh,
 repeated vertex, zero-volume tet, stepping a stale factor, unit normals for
 obstacles), the smallest mesh (one cube, five tets) and tets given with
-negative orientation match the oracle forward and backward."""
+negative orientation match the oracle forward and backward, the library's
+vertex order, and steps stopped by the iteration cap alternated with
+converging steps."""
 import numpy as np
 import pytest
 
@@ -105,3 +107,30 @@ def test_permutation_is_the_library_order(th):
     assert not pinned[perm[:nf]].any() and pinned[perm[nf:]].all()
     assert info["n_subdomains"] > 1 and 0 < info["n_interface"] < nf
 
+
+
+def test_capped_step_leaves_no_state_behind(th):
+    """A step stopped by the iteration cap (status 1) and a step that converges
+    (status 0), alternated on one scene: each call starts from cleared control
+    words, so iteration counts, status and positions equal the oracle's with the
+    same cap (a loaded beam needs 13 iterations, the cap stops it earlier; the
+    unloaded rest state converges under it)."""
+    sc = scenes.small_beam(6, 3, 3, seed=2, tip_force=0.0, gravity=(0.0, 0.0, 0.0))
+    g = make(sc, kmax_fwd=3)
+    o = O.OracleScene(sc, kmax_fwd=3)
+    X = sc.X
+    z = np.zeros_like(X)
+    f = np.zeros_like(X)
+    tip = np.abs(X[:, 0] - X[:, 0].max()) < 1e-12
+    f[tip, 2] = -40.0 / tip.sum()
+    seen = set()
+    for ff in (f, z, f, z):
+        qo, vo, _, sto = o.step_forward(X, z, ff)
+        qg, vg, stg = g.step_forward(dev(th, X), dev(th, z), dev(th, ff))
+        assert (stg["iters"], stg["status"]) == (sto["iters"], sto["status"])
+        assert rel(qg.cpu().numpy(), qo) < 1e-9
+        # at rest both velocities are rounding noise: scale by at least 1 m/s
+        # (the loaded step moves the tip at about 0.7 m/s)
+        assert np.abs(vg.cpu().numpy() - vo).max() <= 1e-9 * max(np.abs(vo).max(), 1.0)
+        seen.add(sto["status"])
+    assert seen == {0, 1}

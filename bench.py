@@ -51,11 +51,19 @@ def parse():
     return ap.parse_args()
 
 
-def measured_traffic(kernel):
+# committed counter summaries of the workloads that have one
+TRAFFIC_FILES = {("c2", None): "traffic_solve_and_local_kernels_hetero_beam_20k_tets.txt",
+                 ("drop", 41): "traffic_interface_solve_contact_drop_100k_tets.txt"}
+
+
+def measured_traffic(kernel, config="c2", drop_res=None):
     """DRAM bytes per working launch of `kernel` from the committed counter
     summary of this workload (FETCH_SIZE / WRITE_SIZE passes scaled by a copy
-    of known size), or None when the summary has no line for it."""
-    path = os.path.join(ROOT, "profiles", "traffic_solve_and_local_kernels_hetero_beam_20k_tets.txt")
+    of known size), or None when the workload or the kernel has none."""
+    name = TRAFFIC_FILES.get((config, drop_res if config == "drop" else None))
+    if name is None:
+        return None
+    path = os.path.join(ROOT, "profiles", name)
     if not os.path.exists(path):
         return None
     for line in open(path):
@@ -296,7 +304,7 @@ def main():
     # work over the summed launch durations
     bytes_per_unit = g.kernel_bytes(kid)
     achieved = (kwork * bytes_per_unit) / (ktime_ms * 1e-3) / 1e9 if ktime_ms > 0 else 0.0
-    traffic = measured_traffic(args.timed_kernel) if args.config == "c2" else None
+    traffic = measured_traffic(args.timed_kernel, args.config, args.drop_res)
     roof = {"kernel": args.timed_kernel, "bound": "hbm", "achieved": round(achieved, 2), "peak": HBM_PEAK_GBS,
             "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic,
             "avg_launch_us": round(1000.0 * ktime_ms / max(kcount, 1), 3), "launches": int(kcount),

@@ -127,17 +127,24 @@ def cpu_baseline(sc, steps):
     """The FP64 CPU oracle (serial C) on the first `steps` steps of the same rollout."""
     import oracle as O
     from paper_2605_14526_amd import scenes
+    def note(what):
+        print(f"[bench] cpu baseline: {what} ({time.perf_counter() - t0:.1f} s)", file=sys.stderr, flush=True)
+
     t0 = time.perf_counter()
     osc = O.OracleScene(sc)
+    note(f"oracle set up, {steps} forward steps next")
     if sc.obstacles:
         q, v, ck, _ = O.rollout_contact(osc, steps)
+        note("forward done, reverse sweep next")
         _, gq = scenes.centroid_loss(q, sc.target_centroid)
         O.rollout_backward_contact(osc, ck, gq, np.zeros_like(gq))
     else:
         q, v, ck, _ = O.rollout(osc, steps)
+        note("forward done, reverse sweep next")
         _, gq = scenes.centroid_loss(q, sc.target_centroid)
         O.rollout_backward(osc, ck, gq, np.zeros_like(gq))
     t1 = time.perf_counter()
+    note("done")
     return t1 - t0
 
 
@@ -366,6 +373,8 @@ def main():
               f"(trained {tsec:.1f} s)", file=sys.stderr, flush=True)
     if not args.no_cpu_baseline:
         n = args.cpu_sample_steps
+        if sc.tets.shape[0] > 50000:  # the serial oracle's reverse sweep takes about 20 s per step at this size
+            n = 1
         t = cpu_baseline(sc, n)
         out["cpu_baseline"] = {"value": round(n / t, 4), "unit": "steps/s", "cores": 1, "kind": "oracle",
                                "sample": f"first {n} fwd+bwd steps of the same rollout, serial FP64 C oracle "

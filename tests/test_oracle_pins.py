@@ -527,3 +527,87 @@ def test_force_gradient_central_difference():
     fd = (rollout_loss(sc, sc.log_E, sc.X, np.zeros_like(sc.X), 1 + h, 1, frozen)[0] -
           rollout_loss(sc, sc.log_E, sc.X, np.zeros_like(sc.X), 1 - h, 1, frozen)[0]) / (2 * h)
     assert np.isclose(np.sum(gf * f), fd, rtol=1e-5)
+
+
+# ------------------------------------------------------------------ material setup (row a1)
+def _stretch_hessian_diag_at_rest(mu, lam, eps=1e-4):
+    """Diagonal of the Neo-Hookean stretch Hessian at sigma = (1, 1, 1), by
+    second differences of the energy of Sec. 3.2 Eq. neohookean (pinned to
+    its stress by test_psi_gradient_is_pk1): the rest tangent modulus that
+    Eq. pd_weight asks the PD weight to match."""
+    d = []
+    for i in range(3):
+        ep, em = np.ones(3), np.ones(3)
+        ep[i] += eps
+        em[i] -= eps
+        d.append((O.psi_nh(np.diag(ep), mu, lam) - 2 * O.psi_nh(np.eye(3), mu, lam)
+                  + O.psi_nh(np.diag(em), mu, lam)) / eps ** 2)
+    return np.array(d)
+
+
+@pytest.mark.parametrize("make", [lambda: scenes.small_beam(5, 2, 2, seed=4, contrast=20.0),
+                                  lambda: scenes.small_beam(4, 3, 2, seed=9, contrast=100.0, nu=0.49)])
+def test_material_setup_from_E_and_nu(make):
+    """Sec. 3.1 Eq. lame gives mu_e, lam_e from E_e and nu; the PD weight is
+    the rest tangent modulus (the stretch Hessian's diagonal at sigma = 1,
+    Sec. 4.1/7.2), the local prox uses the element means and k_bar is the
+    same modulus of the mean energy (Sec. 4.2); Rayleigh's beta_e scales with
+    mu_e relative to the stiffest element (Sec. 4.5 Eq. rayleigh).  Every
+    quantity is recomputed here from E, nu and the rest shape and compared
+    with what the oracle set up."""
+    sc = make()
+    sc = copy.copy(sc)
+    sc.beta0 = 3.0e2  # nonzero so beta_e is exercised
+    osc = O.OracleScene(sc)
+    info = osc.info()
+    E = np.exp(sc.log_E)
+    nu = sc.nu
+    mu = E / (2 * (1 + nu))
+    lam = E * nu / ((1 + nu) * (1 - 2 * nu))
+    # w_e: the stretch Hessian's diagonal at rest, per element (all three entries equal)
+    w = np.array([_stretch_hessian_diag_at_rest(m_, l_) for (m_, l_) in zip(mu, lam)])
+    assert np.allclose(w, w[:, :1], rtol=1e-6)
+    assert np.allclose(info["w"], w[:, 0], rtol=1e-6)
+    mu_bar, lam_bar = mu.mean(), lam.mean()
+    k_bar = _stretch_hessian_diag_at_rest(mu_bar, lam_bar)[0]
+    assert np.isclose(info["mu_bar"], mu_bar, rtol=1e-13)
+    assert np.isclose(info["lam_bar"], lam_bar, rtol=1e-13)
+    assert np.isclose(info["k_bar"], k_bar, rtol=1e-6)
+    mu_ref = mu.max()
+    assert np.isclose(info["mu_ref"], mu_ref, rtol=1e-15)
+    assert np.allclose(info["beta"], sc.beta0 * mu / mu_ref, rtol=1e-13)
+    # rest volumes and lumped masses
+    Xt = sc.X[sc.tets]
+    vol = np.abs(np.linalg.det(np.transpose(Xt[:, 1:] - Xt[:, :1], (0, 2, 1)))) / 6
+    assert np.allclose(info["vol"], vol, rtol=1e-12)
+    mass = np.zeros(sc.n_v)
+    np.add.at(mass, sc.tets.ravel(), np.repeat(sc.rho * vol / 4, 4))
+    assert np.allclose(info["mass"], mass, rtol=1e-12)
+
+
+@pytest.mark.parametrize("kind", ["deviatoric", "shear", "volumetric", "rotation"])
+def test_scene_prox_jacobian_at_rest_uses_mesh_means(kind):
+    """Behavioural pin of k_bar: at rest every element's prox differential
+    (Sec. 4.4 Eq. tr_ift at F = I) passes an infinitesimal rotation unchanged
+    and scales deviatoric strain by k/(2 mu_bar + k) and volumetric strain by
+    k/(2 mu_bar + 3 lam_bar + k), k = 2 mu_bar + lam_bar with the means
+    computed here from E and nu.  On a mesh without pinned vertices and
+    without damping, K x for an affine field x = A X is that factor times
+    (A~ - M/h^2) x = sum_e w_e V_e G_e^T A."""
+    sc = copy.copy(scenes.small_beam(4, 2, 2, seed=11, contrast=30.0, nu=0.45))
+    sc.pinned = np.zeros_like(sc.pinned)
+    sc.alpha, sc.beta0 = 0.0, 0.0
+    osc = O.OracleScene(sc)
+    E = np.exp(sc.log_E)
+    mu_bar = (E / (2 * (1 + sc.nu))).mean()
+    lam_bar = (E * sc.nu / ((1 + sc.nu) * (1 - 2 * sc.nu))).mean()
+    k = 2 * mu_bar + lam_bar
+    A = {"deviatoric": np.diag([1.0, -0.4, -0.6]), "shear": np.array([[0, 1, 0], [1, 0, 0.5], [0, 0.5, 0.0]]),
+         "volumetric": np.eye(3), "rotation": np.array([[0, 1, -0.3], [-1, 0, 0.2], [0.3, -0.2, 0.0]])}[kind]
+    fac = {"deviatoric": k / (2 * mu_bar + k), "shear": k / (2 * mu_bar + k),
+           "volumetric": k / (2 * mu_bar + 3 * lam_bar + k), "rotation": 1.0}[kind]
+    x = sc.X @ A.T
+    Kx = osc.apply_K(sc.X, 1.0, x)
+    m = osc.info()["mass"]
+    elastic = osc.apply_A(x) - m[:, None] / sc.h ** 2 * x
+    assert np.allclose(Kx, fac * elastic, rtol=0, atol=1e-10 * np.abs(elastic).max())

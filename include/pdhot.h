@@ -152,11 +152,32 @@ int pd_scene_destroy(pd_scene* scene);
  * factor becomes stale (refactorization policy, Sec. 4.6): stepping before
  * pd_scene_factorize returns PD_ERR_STALE_FACTOR. */
 int pd_scene_set_material(pd_scene* scene, const double* log_E_host);
+/* The same from a DEVICE buffer of n_tets doubles: the copy is ordered on
+ * `stream` (the caller's producer of log E) and the call returns once the
+ * values are on the host and checked (PD_ERR_NONFINITE for a non-finite
+ * value, PD_ERR_HIP if the copy fails). */
+int pd_scene_set_material_device(pd_scene* scene, const double* log_E_dev, void* stream);
+
+/* Hold the mesh means of the local prox and of Rayleigh damping fixed across
+ * refactorizations.  The means mu_bar, lam_bar (Sec. 4.2) and mu_ref (Sec. 4.5
+ * Eq. rayleigh) are constants of the gradient (the paper's gradient formulas
+ * have no terms for them), so a finite-difference check of d/dlog E must keep
+ * them fixed while it perturbs log E.  means3 (host) = {mu_bar, lam_bar,
+ * mu_ref} with mu_bar > 0, mu_ref > 0; NULL returns to computing them from
+ * the material at each factorization.  Marks the factor stale. */
+int pd_scene_freeze_means(pd_scene* scene, const double* means3);
+
+/* Lumped vertex masses m_v = sum_e rho V_e / 4 (Sec. 3.1), host output of
+ * n_verts doubles in the caller's vertex order (e.g. the M-weighted
+ * trajectory loss of an identification task).  No device work. */
+int pd_scene_vertex_mass(const pd_scene* scene, double* out);
 
 /* Assemble A = (1 + alpha h) M / h^2 + sum_e (w_e + beta_e / h) V_e G_e^T G_e
  * (Sec. 4.5 Eq. A_damped, Dirichlet vertices eliminated), freeze the mesh means
  * mu_bar, lam_bar, k_bar and mu_ref, and build the partitioned inverse used by
- * every solve (Sec. 4.6 Eq. Ainv_STS in role).  Host work plus one upload. */
+ * every solve (Sec. 4.6 Eq. Ainv_STS in role).  Host work plus one upload.
+ * First waits for `stream` and then for the whole device, so kernels of
+ * earlier steps that read the per-tet arrays finish before they change. */
 int pd_scene_factorize(pd_scene* scene, void* stream);
 
 /* Scene facts. info[0..7] = n_verts, n_tets, n_free, n_subdomains,

@@ -25,10 +25,11 @@ _ip = ctypes.POINTER(ctypes.c_int)
 
 
 def build(force: bool = True) -> str:
-    """Compile the oracle with gcc (plain IEEE FP64: no fast-math, no FMA contraction)."""
+    """Compile the oracle with gcc (plain IEEE FP64: no fast-math, no FMA contraction; OpenMP over
+    elements with fixed summation orders)."""
     if force or not os.path.exists(_LIB) or os.path.getmtime(_LIB) < os.path.getmtime(_SRC):
         tmp = _LIB + ".tmp"
-        subprocess.check_call(["gcc", "-O2", "-ffp-contract=off", "-fno-fast-math", "-fPIC", "-shared",
+        subprocess.check_call(["gcc", "-O2", "-ffp-contract=off", "-fno-fast-math", "-fopenmp", "-fPIC", "-shared",
                                "-o", tmp, _SRC, "-lm"])
         os.replace(tmp, _LIB)
     return _LIB
@@ -44,6 +45,8 @@ def lib():
         L.or_scene_create.argtypes = [ctypes.c_int, ctypes.c_int, _dp, _ip, ctypes.c_char_p, _dp, _dp, _dp]
         L.or_scene_destroy.argtypes = [ctypes.c_void_p]
         L.or_scene_nfree.argtypes = [ctypes.c_void_p]
+        L.or_set_threads.argtypes = [ctypes.c_int]
+        L.or_get_threads.restype = ctypes.c_int
         L.or_scene_info.argtypes = [ctypes.c_void_p, _dp, _dp, _dp, _dp, _dp]
         L.or_svd3.argtypes = [_dp, _dp, _dp, _dp]
         L.or_prox_stretch.argtypes = [_dp, ctypes.c_double, ctypes.c_double, ctypes.c_double, _dp]
@@ -74,6 +77,15 @@ def lib():
         L.or_fb_lcp.argtypes = [ctypes.c_int, _dp, _dp, _dp, _dp]
         _lib = L
     return _lib
+
+
+def set_threads(n: int) -> None:
+    """Threads of the oracle's element loops (OpenMP); results are independent of it."""
+    lib().or_set_threads(int(n))
+
+
+def get_threads() -> int:
+    return int(lib().or_get_threads())
 
 
 def _p(a):

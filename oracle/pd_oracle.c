@@ -20,6 +20,9 @@
 #include <math.h>
 #include <stdlib.h>
 #include <string.h>
+#ifdef _OPENMP
+#include <omp.h>
+#endif
 
 /* ------------------------------------------------------------------------ */
 /* small dense helpers                                                       */
@@ -501,17 +504,45 @@ static void element_F(const or_scene* s, int e, const double* q, double F[9]) {
   }
 }
 
-/* y += coef * G_e^T P (P a 3x3 matrix), over all 4 vertices */
-static void element_scatter(const or_scene* s, int e, double coef, const double P[9], double* y) {
+/* The element loops below run in parallel (OpenMP over elements) and leave
+ * each element's 12 contributions coef * (P Bhat_a)_i in a buffer; the
+ * buffer is then added into y serially in element order, which is exactly
+ * the order of a serial scatter, so results do not depend on the thread
+ * count (bitwise). */
+static void element_contrib(const or_scene* s, int e, double coef, const double P[9], double out[12]) {
   for (int a = 0; a < 4; ++a) {
-    int v = s->tets[4 * e + a];
     const double* B = s->Bhat + 12 * e + 3 * a;
     for (int i = 0; i < 3; ++i) {
       double t = 0;
       for (int j = 0; j < 3; ++j) t += P[3 * i + j] * B[j];
-      y[3 * v + i] += coef * t;
+      out[3 * a + i] = coef * t;
     }
   }
+}
+
+static void scatter_contribs(const or_scene* s, const double* ctb, double* y) {
+  for (int e = 0; e < s->ne; ++e)
+    for (int a = 0; a < 4; ++a) {
+      int v = s->tets[4 * e + a];
+      for (int i = 0; i < 3; ++i) y[3 * v + i] += ctb[12 * (size_t)e + 3 * a + i];
+    }
+}
+
+/* thread count of the element loops (OpenMP); 0 leaves the runtime's default */
+void or_set_threads(int n) {
+#ifdef _OPENMP
+  if (n > 0) omp_set_num_threads(n);
+#else
+  (void)n;
+#endif
+}
+
+int or_get_threads(void) {
+#ifdef _OPENMP
+  return omp_get_max_threads();
+#else
+  return 1;
+#endif
 }
 
 or_scene* or_scene_create(int nv, int ne, const double* X, const int* tets, const unsigned char* pinned,
@@ -650,10 +681,12 @@ void or_scene_destroy(or_scene* s) {
  * inverse from one factor; here an envelope Cholesky, forward + backward). */
 void or_apply_Ainv(const or_scene* s, const double* r_all, double* x_all) {
   int nf = s->nf;
-  double* y = (double*)malloc(sizeof(double) * (nf > 0 ? nf : 1));
   for (int v = 0; v < s->nv; ++v)
     if (s->fidx[v] < 0) x_all[3 * v] = x_all[3 * v + 1] = x_all[3 * v + 2] = 0.0;
+  /* the three axes are independent solves */
+#pragma omp parallel for schedule(static, 1)
   for (int ax = 0; ax < 3; ++ax) {
+    double* y = (double*)malloc(sizeof(double) * (nf > 0 ? nf : 1));
     for (int i = 0; i < nf; ++i) {
       double sum = r_all[3 * s->fvert[i] + ax];
       for (int k = s->first[i]; k < i; ++k) sum -= *env_at(s->Lenv, s, i, k) * y[k];
@@ -665,8 +698,8 @@ void or_apply_Ainv(const or_scene* s, const double* r_all, double* x_all) {
       for (int k = s->first[i]; k < i; ++k) y[k] -= *env_at(s->Lenv, s, i, k) * v;
     }
     for (int i = 0; i < nf; ++i) x_all[3 * s->fvert[i] + ax] = y[i];
+    free(y);
   }
-  free(y);
 }
 
 void or_apply_A(const or_scene* s, const double* x_all, double* y_all) {
@@ -687,18 +720,25 @@ void or_apply_A(const or_scene* s, const double* x_all, double* y_all) {
 /* b(q) without its constant part: sum_e w_e V_e G_e^T p*_e(G_e q), Eq. A_basic */
 static void local_rhs_stats(const or_scene* s, const double* q, double* b_all, int* capped, int* maxit) {
   for (int i = 0; i < 3 * s->nv; ++i) b_all[i] = 0.0;
+  double* ctb = (double*)malloc(sizeof(double) * 12 * (size_t)(s->ne > 0 ? s->ne : 1));
+  int ncap = 0, mit = 0;
+#pragma omp parallel for schedule(static) reduction(+ : ncap) reduction(max : mit)
   for (int e = 0; e < s->ne; ++e) {
     double F[9], U[9], V[9], sF[3], ss[3], T[9], P[9];
     element_F(s, e, q, F);
     or_svd3(F, U, sF, V);
     int it = or_prox_stretch(sF, s->mu_bar, s->lam_bar, s->k_bar, ss);
-    if (it < 0) { if (capped) (*capped)++; it = -it; }
-    if (maxit && it > *maxit) *maxit = it;
+    if (it < 0) { ncap++; it = -it; }
+    if (it > mit) mit = it;
     for (int i = 0; i < 3; ++i)
       for (int j = 0; j < 3; ++j) T[3 * i + j] = U[3 * i + j] * ss[j];
     mat3_mul_nt(T, V, P);
-    element_scatter(s, e, s->w[e] * s->vol[e], P, b_all);
+    element_contrib(s, e, s->w[e] * s->vol[e], P, ctb + 12 * (size_t)e);
   }
+  scatter_contribs(s, ctb, b_all);
+  free(ctb);
+  if (capped) *capped += ncap;
+  if (maxit && mit > *maxit) *maxit = mit;
 }
 
 void or_local_rhs(const or_scene* s, const double* q, double* b_all) { local_rhs_stats(s, q, b_all, NULL, NULL); }
@@ -709,6 +749,8 @@ void or_apply_K(const or_scene* s, const double* q, double tau, const double* x_
   for (int v = 0; v < s->nv; ++v)
     for (int ax = 0; ax < 3; ++ax) xf[3 * v + ax] = s->fidx[v] >= 0 ? x_all[3 * v + ax] : 0.0;
   for (int i = 0; i < 3 * s->nv; ++i) y_all[i] = 0.0;
+  double* ctb = (double*)malloc(sizeof(double) * 12 * (size_t)(s->ne > 0 ? s->ne : 1));
+#pragma omp parallel for schedule(static)
   for (int e = 0; e < s->ne; ++e) {
     double F[9], U[9], V[9], sF[3], ss[3], D[9], c1[3], c2[3], dF[9], dP[9];
     element_F(s, e, q, F);
@@ -717,8 +759,10 @@ void or_apply_K(const or_scene* s, const double* q, double tau, const double* x_
     prox_diff_coeffs(sF, ss, s->mu_bar, s->lam_bar, s->k_bar, tau, D, c1, c2);
     element_F(s, e, xf, dF);
     prox_diff_apply(U, V, D, c1, c2, dF, dP);
-    element_scatter(s, e, s->w[e] * s->vol[e], dP, y_all);
+    element_contrib(s, e, s->w[e] * s->vol[e], dP, ctb + 12 * (size_t)e);
   }
+  scatter_contribs(s, ctb, y_all);
+  free(ctb);
   for (int v = 0; v < s->nv; ++v)
     if (s->fidx[v] < 0) y_all[3 * v] = y_all[3 * v + 1] = y_all[3 * v + 2] = 0.0;
   free(xf);
@@ -728,6 +772,7 @@ void or_apply_K(const or_scene* s, const double* q, double tau, const double* x_
  * as U, V, D, c1, c2 (33 numbers per element) and applied to many vectors. */
 static double* prox_diff_all(const or_scene* s, const double* q, double tau) {
   double* st = (double*)malloc(sizeof(double) * 33 * (size_t)s->ne);
+#pragma omp parallel for schedule(static)
   for (int e = 0; e < s->ne; ++e) {
     double F[9], sF[3], ss[3];
     double* c = st + 33 * (size_t)e;
@@ -744,13 +789,17 @@ static void apply_K_stored(const or_scene* s, const double* st, const double* x_
   for (int v = 0; v < s->nv; ++v)
     for (int ax = 0; ax < 3; ++ax) xf[3 * v + ax] = s->fidx[v] >= 0 ? x_all[3 * v + ax] : 0.0;
   for (int i = 0; i < 3 * s->nv; ++i) y_all[i] = 0.0;
+  double* ctb = (double*)malloc(sizeof(double) * 12 * (size_t)(s->ne > 0 ? s->ne : 1));
+#pragma omp parallel for schedule(static)
   for (int e = 0; e < s->ne; ++e) {
     const double* c = st + 33 * (size_t)e;
     double dF[9], dP[9];
     element_F(s, e, xf, dF);
     prox_diff_apply(c, c + 9, c + 18, c + 27, c + 30, dF, dP);
-    element_scatter(s, e, s->w[e] * s->vol[e], dP, y_all);
+    element_contrib(s, e, s->w[e] * s->vol[e], dP, ctb + 12 * (size_t)e);
   }
+  scatter_contribs(s, ctb, y_all);
+  free(ctb);
   for (int v = 0; v < s->nv; ++v)
     if (s->fidx[v] < 0) y_all[3 * v] = y_all[3 * v + 1] = y_all[3 * v + 2] = 0.0;
   free(xf);
@@ -764,11 +813,15 @@ double or_primal_phi(const or_scene* s, const double* q, const double* qtilde) {
       double d = q[3 * v + ax] - qtilde[3 * v + ax];
       phi += 0.5 / (h * h) * s->mass[v] * d * d;
     }
+  double* pe = (double*)malloc(sizeof(double) * (s->ne > 0 ? s->ne : 1));
+#pragma omp parallel for schedule(static)
   for (int e = 0; e < s->ne; ++e) {
     double F[9];
     element_F(s, e, q, F);
-    phi += s->vol[e] * or_psi_nh(F, s->mu[e], s->lam[e]);
+    pe[e] = s->vol[e] * or_psi_nh(F, s->mu[e], s->lam[e]);
   }
+  for (int e = 0; e < s->ne; ++e) phi += pe[e];
+  free(pe);
   return phi;
 }
 
@@ -1230,13 +1283,17 @@ static int step_backward_impl(const or_scene* s, const double* q_t, const double
       double a = q_star_m1[i], b = q_star[i];
       dphi_act += 0.5 / (h * h) * s->mass[v] * (a - b) * (a + b - 2.0 * qtilde[i]);
     }
+  double* pe = (double*)malloc(sizeof(double) * (s->ne > 0 ? s->ne : 1));
+#pragma omp parallel for schedule(static)
   for (int e = 0; e < s->ne; ++e) {
     double Fa[9], Fb[9];
     element_F(s, e, q_star_m1, Fa);
     element_F(s, e, q_star, Fb);
     double pa = or_psi_nh(Fa, s->mu[e], s->lam[e]), pb = or_psi_nh(Fb, s->mu[e], s->lam[e]);
-    dphi_act += s->vol[e] * (pa - pb);
+    pe[e] = s->vol[e] * (pa - pb);
   }
+  for (int e = 0; e < s->ne; ++e) dphi_act += pe[e];
+  free(pe);
   for (int v = 0; v < nv; ++v)
     for (int ax = 0; ax < 3; ++ax) dq[3 * v + ax] = s->fidx[v] >= 0 ? q_star[3 * v + ax] - q_star_m1[3 * v + ax] : 0.0;
   or_apply_A(s, dq, Adq);
@@ -1381,6 +1438,9 @@ static int step_backward_impl(const or_scene* s, const double* q_t, const double
    * dL/dbeta_e = (V_e/h) <G mu, G (q_t - q*)>; w_e and beta_e scale with E_e,
    * the mesh means and mu_ref are held fixed. */
   double* Bmu = (double*)calloc(n3, sizeof(double));
+  double* ge = (double*)malloc(sizeof(double) * (s->ne > 0 ? s->ne : 1));
+  double* ctb = (double*)malloc(sizeof(double) * 12 * (size_t)(s->ne > 0 ? s->ne : 1));
+#pragma omp parallel for schedule(static)
   for (int e = 0; e < s->ne; ++e) {
     double Gm[9], F[9], Fd[9], P[9], U[9], V[9], sF[3], ss[3], T[9];
     double qd[12];
@@ -1407,10 +1467,14 @@ static int step_backward_impl(const or_scene* s, const double* q_t, const double
     double gb = 0.0;
     for (int i = 0; i < 9; ++i) gb += Gm[i] * Fd[i];
     gb *= s->vol[e] / h;
-    g_logE[e] += s->w[e] * gw + s->beta[e] * gb;
+    ge[e] = s->w[e] * gw + s->beta[e] * gb;
     /* B_beta mu = sum_e beta_e V_e G^T G mu */
-    element_scatter(s, e, s->beta[e] * s->vol[e], Gm, Bmu);
+    element_contrib(s, e, s->beta[e] * s->vol[e], Gm, ctb + 12 * (size_t)e);
   }
+  for (int e = 0; e < s->ne; ++e) g_logE[e] += ge[e];
+  scatter_contribs(s, ctb, Bmu);
+  free(ge);
+  free(ctb);
   for (int v = 0; v < nv; ++v)
     for (int ax = 0; ax < 3; ++ax) {
       int i = 3 * v + ax;

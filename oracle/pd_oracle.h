@@ -22,6 +22,10 @@ typedef struct or_scene or_scene;
 or_scene* or_scene_create(int nv, int ne, const double* X, const int* tets, const unsigned char* pinned,
                           const double* logE, const double* params, const double* solver);
 void or_scene_destroy(or_scene* s);
+/* threads of the element loops and of the three per-axis solves (OpenMP);
+ * results do not depend on it (fixed summation orders) */
+void or_set_threads(int n);
+int or_get_threads(void);
 int or_scene_nfree(const or_scene* s);
 /* per-element / per-vertex quantities after setup (any may be NULL) */
 void or_scene_info(const or_scene* s, double* vol, double* w, double* beta, double* mass, double* means4);

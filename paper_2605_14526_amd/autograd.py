@@ -14,19 +14,23 @@ from __future__ import annotations
 
 from typing import Optional
 
-import numpy as np
-
 from .binding import Scene
 
 
 def _sync_material(scene: Scene, log_E) -> None:
     """Refactorize when the caller's log E differs from the scene's (Sec. 4.6 policy)."""
+    import torch
     if log_E is None:
         return
-    le = log_E.detach().to("cpu", dtype=log_E.dtype).numpy().astype(np.float64)
-    if le.shape != scene._logE.shape or not np.array_equal(le, scene._logE):
-        scene.set_material(le)
+    le = log_E.detach().to(dtype=torch.float64).contiguous()
+    cur = getattr(scene, "_logE_dev", None)
+    if cur is None or cur.device != le.device:
+        cur = torch.as_tensor(scene._logE, dtype=torch.float64, device=le.device)
+    if le.shape != cur.shape or not torch.equal(le, cur):
+        scene.set_material_device(le)
         scene.factorize()
+    else:
+        scene._logE_dev = cur
 
 
 def _forward_steps(scene: Scene, q, v, forces, t0: int, t1: int, ckpts, keep_states):

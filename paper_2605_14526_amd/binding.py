@@ -22,7 +22,8 @@ ERRORS = {-1: "PD_ERR_INVALID_ARG", -2: "PD_ERR_DEGENERATE_TET", -3: "PD_ERR_NON
           -4: "PD_ERR_STALE_FACTOR", -5: "PD_ERR_FACTOR_NOT_SPD", -6: "PD_ERR_HIP", -7: "PD_ERR_ALLOC",
           -8: "PD_ERR_CONTACT"}
 
-EXPORTED = ["pd_scene_create", "pd_scene_destroy", "pd_scene_set_material", "pd_scene_factorize", "pd_scene_info",
+EXPORTED = ["pd_scene_create", "pd_scene_destroy", "pd_scene_set_material", "pd_scene_set_material_device",
+            "pd_scene_freeze_means", "pd_scene_vertex_mass", "pd_scene_factorize", "pd_scene_info",
             "pd_scene_get_permutation",
             "pd_ckpt_bytes", "pd_step_forward", "pd_step_backward", "pd_debug_local_rhs", "pd_debug_apply_Ainv",
             "pd_debug_apply_K", "pd_kernel_timer", "pd_kernel_timer_read", "pd_adjoint_reset", "pd_scene_vertex_logw",
@@ -84,6 +85,9 @@ def lib() -> ctypes.CDLL:
                                   ctypes.POINTER(pd_solver_opts), ctypes.POINTER(vp)]
     L.pd_scene_destroy.argtypes = [vp]
     L.pd_scene_set_material.argtypes = [vp, vp]
+    L.pd_scene_set_material_device.argtypes = [vp, vp, vp]
+    L.pd_scene_freeze_means.argtypes = [vp, vp]
+    L.pd_scene_vertex_mass.argtypes = [vp, vp]
     L.pd_scene_factorize.argtypes = [vp, vp]
     L.pd_scene_info.argtypes = [vp, vp, vp]
     L.pd_scene_get_permutation.argtypes = [vp, vp]
@@ -232,7 +236,28 @@ class Scene:
 
     def set_material(self, log_E):
         self._logE = np.ascontiguousarray(log_E, dtype=np.float64)
+        self._logE_dev = None
         check(lib().pd_scene_set_material(self.ptr, self._logE.ctypes.data), "pd_scene_set_material")
+
+    def set_material_device(self, log_E):
+        """log E from a float64 device tensor (copied on the current stream)."""
+        check(lib().pd_scene_set_material_device(self.ptr, _ptr(log_E), _stream()), "pd_scene_set_material_device")
+        self._logE_dev = log_E.detach().clone()
+        self._logE = self._logE_dev.cpu().numpy()
+
+    def freeze_means(self, means=None):
+        """Hold (mu_bar, lam_bar, mu_ref) fixed across refactorizations (None: recompute each time)."""
+        if means is None:
+            check(lib().pd_scene_freeze_means(self.ptr, None), "pd_scene_freeze_means")
+            return
+        a = np.ascontiguousarray(means, dtype=np.float64)
+        check(lib().pd_scene_freeze_means(self.ptr, a.ctypes.data), "pd_scene_freeze_means")
+
+    def vertex_mass(self) -> np.ndarray:
+        """Lumped vertex masses (caller's vertex order)."""
+        out = np.zeros(self.n_verts)
+        check(lib().pd_scene_vertex_mass(self.ptr, out.ctypes.data), "pd_scene_vertex_mass")
+        return out
 
     def factorize(self):
         check(lib().pd_scene_factorize(self.ptr, _stream()), "pd_scene_factorize")

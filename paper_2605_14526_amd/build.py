@@ -1,6 +1,7 @@
 """Build the pdhot HIP library for gfx950 in-tree (``libpdhot.so`` beside this file)."""
 from __future__ import annotations
 
+import concurrent.futures
 import os
 import subprocess
 import sys
@@ -25,11 +26,10 @@ def build(verbose: bool = False) -> str:
     """Compile every source into one shared library (always recompiles)."""
     objdir = os.path.join(ROOT, "_build")
     os.makedirs(objdir, exist_ok=True)
-    objs = []
     common = [f"--offload-arch={ARCH}", "-O3", "-fPIC", "-std=c++17", "-Wall", "-Wno-unused-function",
               "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
               f"-I{CSRC}", f"-I{os.path.join(ROOT, 'include')}"]
-    for src in SOURCES:
+    def compile_one(src):
         obj = os.path.join(objdir, src + ".o")
         cmd = [hipcc()] + common + ["-c", os.path.join(CSRC, src), "-o", obj]
         if verbose:
@@ -40,7 +40,11 @@ def build(verbose: bool = False) -> str:
             raise RuntimeError(f"hipcc failed on {src}:\n{err}")
         if verbose and err.strip():
             print(err, file=sys.stderr)
-        objs.append(obj)
+        return obj
+
+    # the sources compile independently (one hipcc process each)
+    with concurrent.futures.ThreadPoolExecutor(max_workers=min(len(SOURCES), 4)) as ex:
+        objs = list(ex.map(compile_one, SOURCES))
     tmp = LIB + ".tmp"
     cmd = [hipcc(), f"--offload-arch={ARCH}", "-shared", "-fPIC", "-o", tmp] + objs
     r = subprocess.run(cmd, capture_output=True, text=True)

@@ -114,6 +114,9 @@ struct Scene {
   int last_fwd_iters = 4, last_adj_iters = 8;
   Layout L;
   double mu_bar = 0, lam_bar = 0, k_bar = 0, mu_ref = 0;
+  // means held across refactorizations (pd_scene_freeze_means): mu_bar, lam_bar, mu_ref
+  bool frozen = false;
+  double frozen_means[3] = {0, 0, 0};
   std::vector<double> hBm;  // host copy of the per-tet D_m^{-1} (library order, SoA)
   std::vector<int> htv;     // host copy of the tet vertex ids
 

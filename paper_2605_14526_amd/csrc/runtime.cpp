@@ -581,8 +581,14 @@ void factorize(Scene& S) {
   }
   S.mu_bar = smu / ne;
   S.lam_bar = slam / ne;
-  S.k_bar = 2.0 * S.mu_bar + S.lam_bar;
   S.mu_ref = mref;
+  if (S.frozen) {  // constants of the gradient held fixed (finite-difference checks)
+    S.mu_bar = S.frozen_means[0];
+    S.lam_bar = S.frozen_means[1];
+    S.mu_ref = S.frozen_means[2];
+  }
+  S.k_bar = 2.0 * S.mu_bar + S.lam_bar;
+  mref = S.mu_ref;
   for (int e = 0; e < ne; ++e) beta[e] = S.beta0 * mu[e] / mref;
   // per-tet data in library order
   const std::vector<double>& Bm = S.hBm;
@@ -1121,11 +1127,66 @@ int pd_scene_factorize(pd_scene* scene, void* stream) {
     pdhot::g_last_error = "null scene";
     return PD_ERR_INVALID_ARG;
   }
-  (void)stream;
   PD_TRY
+  // kernels of earlier steps (e.g. the gradient routing, which reads the
+  // per-tet weights) may still run on the caller's stream or on a batch's
+  // stream: the per-tet arrays and the factor are replaced only after all
+  // device work has finished
+  PD_HIP(hipStreamSynchronize((hipStream_t)stream));
+  PD_HIP(hipDeviceSynchronize());
   factorize(scene->S);
   return PD_OK;
   PD_CATCH
+}
+
+int pd_scene_set_material_device(pd_scene* scene, const double* log_E_dev, void* stream) {
+  if (!scene || !log_E_dev) {
+    pdhot::g_last_error = "null argument";
+    return PD_ERR_INVALID_ARG;
+  }
+  PD_TRY
+  std::vector<double> h(scene->S.ne);
+  PD_HIP(hipMemcpyAsync(h.data(), log_E_dev, h.size() * sizeof(double), hipMemcpyDeviceToHost,
+                        (hipStream_t)stream));
+  PD_HIP(hipStreamSynchronize((hipStream_t)stream));
+  return pd_scene_set_material(scene, h.data());
+  PD_CATCH
+}
+
+int pd_scene_freeze_means(pd_scene* scene, const double* means3) {
+  if (!scene) {
+    pdhot::g_last_error = "null scene";
+    return PD_ERR_INVALID_ARG;
+  }
+  if (means3 && !(means3[0] > 0.0 && std::isfinite(means3[0]) && std::isfinite(means3[1]) &&
+                  means3[0] + means3[1] > 0.0 && means3[2] > 0.0 && std::isfinite(means3[2]))) {
+    pdhot::g_last_error = "frozen means must be finite with mu_bar > 0, mu_ref > 0";
+    return PD_ERR_INVALID_ARG;
+  }
+  Scene& S = scene->S;
+  S.frozen = means3 != nullptr;
+  if (means3)
+    for (int i = 0; i < 3; ++i) S.frozen_means[i] = means3[i];
+  S.stale = true;
+  return PD_OK;
+}
+
+int pd_scene_vertex_mass(const pd_scene* scene, double* out) {
+  if (!scene || !out) {
+    pdhot::g_last_error = "null argument";
+    return PD_ERR_INVALID_ARG;
+  }
+  const Scene& S = scene->S;
+  for (int v = 0; v < S.nv; ++v) out[v] = 0.0;
+  for (int e = 0; e < S.ne; ++e) {
+    const int* tt = &S.tets[4 * (size_t)e];
+    double Dm[9];
+    for (int a = 1; a < 4; ++a)
+      for (int i = 0; i < 3; ++i) Dm[3 * i + a - 1] = S.X[3 * tt[a] + i] - S.X[3 * tt[0] + i];
+    const double m4 = S.rho * det3(Dm) / 24.0;
+    for (int a = 0; a < 4; ++a) out[tt[a]] += m4;
+  }
+  return PD_OK;
 }
 
 int pd_scene_info(const pd_scene* scene, double* info, double* means) {

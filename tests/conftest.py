@@ -18,3 +18,13 @@ def torch_cuda():
     if not torch.cuda.is_available():
         pytest.skip("no GPU")
     return torch
+
+
+@pytest.fixture(scope="session", autouse=True)
+def _oracle_threads():
+    """Under pytest-xdist every worker runs its own oracle: one thread each,
+    so the workers do not oversubscribe the cores."""
+    if os.environ.get("PYTEST_XDIST_WORKER"):
+        import oracle
+        oracle.set_threads(1)
+    yield

@@ -130,6 +130,63 @@ def test_identification_batch_full_size_bitwise(th):
             assert np.array_equal(x, y)
 
 
+def test_identification_batch_against_oracle(th):
+    """One batched run over a small identification batch (beams and anchored
+    blobs of 1k-4k tets, uneven sizes, materials and Anderson windows) against
+    the oracle scene by scene: every step starts from the oracle's states, so
+    each scene's positions are compared at every step (path parity through the
+    gate, positions 1e-9), then one batched reverse sweep of the centroid
+    loss against the oracle's adjoint (gradients with respect to q0, v0 and
+    log E, 1e-6)."""
+    import oracle as O
+    from paper_2605_14526_amd.binding import Batch, Scene
+    scs = scenes.sysid_batch(n=6, seed=4100, steps=3, ne_range=(1000, 4000))
+    kinds = {sc.name.split("_")[1] for sc in scs}
+    assert kinds == {"beam", "blob"}, kinds
+    T = 3
+    gs = [Scene.from_scene(sc, eps_adj=1e-12) for sc in scs]
+    os_ = [O.OracleScene(sc, eps_adj=1e-13) for sc in scs]
+    B = Batch(gs)
+    qo = [sc.q0() for sc in scs]
+    vo = [sc.v0() for sc in scs]
+    ck_o = [[] for _ in scs]
+    cks = []
+    for t in range(T):
+        fs = [sc.f_ext(t) for sc in scs]
+        ck = [g.new_ckpt() for g in gs]
+        qg, _, stats, rc = B.step_forward([d(th, a) for a in qo], [d(th, a) for a in vo], [d(th, f) for f in fs],
+                                          ckpt=ck)
+        assert rc == 0
+        cks.append(ck)
+        for i, sc in enumerate(scs):
+            qn, vn, qm1, sto = os_[i].step_forward(qo[i], vo[i], fs[i])
+            qc, qm1c = qn, qm1
+            if stats[i]["iters"] != sto["iters"]:
+                kg, ko = stats[i]["iters"], sto["iters"]
+                qc, _, qm1c, stf = os_[i].step_forward(qo[i], vo[i], fs[i], force_iters=kg)
+                gt = (stf if kg < ko else sto)["gate"]
+                r = max(gt[0] / (sc.eps_rel * gt[1] + sc.eps_abs), gt[2] / (sc.eps_rel * gt[3] + sc.eps_abs))
+                assert abs(r - 1.0) <= 1e-4, (sc.name, t, kg, ko, r)
+            e = float(np.abs(qg[i].cpu().numpy() - qc).max() / np.abs(qc).max())
+            assert e < 1e-9, (sc.name, t, e)
+            ck_o[i].append((qo[i], vo[i], fs[i], qc, qm1c))
+            qo[i], vo[i] = qn, vn
+    for g in gs:
+        g.adjoint_reset()
+    gq_h = [scenes.centroid_loss(ck_o[i][-1][3], sc.target_centroid)[1] for i, sc in enumerate(scs)]
+    gq = [d(th, a) for a in gq_h]
+    gv = [d(th, np.zeros_like(a)) for a in gq_h]
+    gl = [th.zeros(sc.n_e, dtype=th.float64, device="cuda") for sc in scs]
+    for ck in reversed(cks):
+        gq, gv, _, gl, stats, rc = B.step_backward(ck, gq, gv, g_logE=gl)
+        assert rc == 0
+    for i, sc in enumerate(scs):
+        gq0, gv0, gl0, _ = O.rollout_backward(os_[i], ck_o[i], gq_h[i], np.zeros_like(gq_h[i]), adj_mode=0)
+        for a, b in [(gq[i], gq0), (gv[i], gv0), (gl[i], gl0)]:
+            e = float(np.abs(a.cpu().numpy() - b).max() / np.abs(b).max())
+            assert e < 1e-6, (sc.name, e)
+
+
 def test_graph_replays_match_eager(th):
     """The same chunks replayed from captured graphs many times, with eager
     work and synchronisations between replays, give the eager results each time."""

@@ -1,0 +1,142 @@
+"""The heterogeneous beam (40x10x10 cubes, 20,000 tets) at the benchmark's own
+solver settings against the oracle, and its material gradient against central
+finite differences on the 16 seeded tets.  All calls go through the C ABI."""
+import numpy as np
+import pytest
+
+import oracle as O
+from paper_2605_14526_amd import scenes
+
+pytestmark = pytest.mark.gpu
+
+TOL_POS = 1e-9
+TOL_GRAD = 1e-6
+# see tests/test_gpu_parity.py: the gate ratio's rounding band
+GATE_BAND = 1e-4
+
+
+def rel(a, b):
+    return float(np.abs(np.asarray(a) - np.asarray(b)).max() / max(np.abs(np.asarray(b)).max(), 1e-300))
+
+
+@pytest.fixture(scope="module")
+def th(torch_cuda):
+    return torch_cuda
+
+
+def dev(th, a):
+    return th.tensor(np.ascontiguousarray(a), dtype=th.float64, device="cuda")
+
+
+def host(t):
+    return t.detach().cpu().numpy()
+
+
+def gate_ratio(gate, eps_rel, eps_abs):
+    return max(gate[0] / (eps_rel * gate[1] + eps_abs), gate[2] / (eps_rel * gate[3] + eps_abs))
+
+
+def test_benchmark_settings_gradients_match_oracle(th):
+    """The benchmark's configuration of the beam: dual gate 1e-6, adjoint PCG
+    to 1e-6 from the quadratically extrapolated start, the 20 timed steps and
+    their reverse sweep with the centroid loss.  The library runs its own
+    rollout; the oracle follows the same path (its step re-run at the
+    library's iteration count where the gate decided one iteration apart,
+    after checking that its gate was within rounding of the threshold) and
+    runs its adjoint to 1e-13.  Positions agree to 1e-9, the gradients with
+    respect to q0, v0 and all 20,000 log E to 1e-6."""
+    from paper_2605_14526_amd.binding import Scene
+    sc = scenes.config("c2")
+    T = 20
+    g = Scene.from_scene(sc, eps_adj=1e-6, adj_warm=3)
+    o = O.OracleScene(sc, eps_adj=1e-13)
+    q, v = sc.q0(), sc.v0()
+    qg, vg = dev(th, q), dev(th, v)
+    cks, ck_o, mism = [], [], []
+    worst = 0.0
+    for t in range(T):
+        f = sc.f_ext(t)
+        ck = g.new_ckpt()
+        qg, vg, stg = g.step_forward(qg, vg, dev(th, f), ckpt=ck)
+        assert stg["status"] == 0, stg
+        cks.append(ck)
+        qo, vo, qm1, sto = o.step_forward(q, v, f)
+        if stg["iters"] != sto["iters"]:
+            kg, ko = stg["iters"], sto["iters"]
+            qo, vo, qm1, stf = o.step_forward(q, v, f, force_iters=kg)
+            r = gate_ratio((stf if kg < ko else sto)["gate"], sc.eps_rel, sc.eps_abs)
+            assert abs(r - 1.0) <= GATE_BAND, (t, kg, ko, r)
+            mism.append((t, kg, ko, r))
+        worst = max(worst, rel(host(qg), qo))
+        ck_o.append((q, v, f, qo, qm1))
+        q, v = qo, vo
+    assert worst < TOL_POS, (worst, mism)
+    _, gq = scenes.centroid_loss(q, sc.target_centroid)
+    gv = np.zeros_like(gq)
+    gq0_o, gv0_o, gl_o, _ = O.rollout_backward(o, ck_o, gq, gv, adj_mode=0)
+    g.adjoint_reset()
+    gqd, gvd = dev(th, gq), dev(th, gv)
+    gl = th.zeros(sc.n_e, dtype=th.float64, device="cuda")
+    its = []
+    for ck in reversed(cks):
+        gqd, gvd, _, _, st = g.step_backward(ck, gqd, gvd, g_logE=gl)
+        assert st["status"] == 0, st
+        its.append(st["adj_iters"])
+    for a, b in [(host(gqd), gq0_o), (host(gvd), gv0_o), (host(gl), gl_o)]:
+        assert rel(a, b) < TOL_GRAD, (rel(a, b), its, mism)
+
+
+def _loss_rollout(th, g, sc, T):
+    q, v = dev(th, sc.q0()), dev(th, sc.v0())
+    cks = []
+    for t in range(T):
+        ck = g.new_ckpt()
+        q, v, st = g.step_forward(q, v, dev(th, sc.f_ext(t)), ckpt=ck)
+        assert st["status"] == 0, (t, st)
+        cks.append(ck)
+    L, gq = scenes.centroid_loss(host(q), sc.target_centroid)
+    return L, gq, cks
+
+
+def test_material_gradient_central_differences_16_tets(th):
+    """Sec. 4.8 gradient routing (dL/dlog E_e) against central differences of
+    the library's own forward rollout on the 16 seeded tets of the beam
+    (step 1e-3 in log E), over the first 40 steps (the tip load's ramp and
+    hold), with the mesh means held fixed (they are constants of the
+    gradient) and the forward gate and the adjoint run to 1e-12."""
+    from paper_2605_14526_amd.binding import Scene
+    sc = scenes.config("c2")
+    T = 40
+    g = Scene.from_scene(sc, eps_rel=1e-12, eps_abs=1e-16, eps_adj=1e-12, kmax_fwd=5000, kmax_bwd=5000)
+    inf = g.info()
+    g.freeze_means((inf["mu_bar"], inf["lam_bar"], inf["mu_ref"]))
+    g.set_material(sc.log_E)
+    g.factorize()
+    L0, gq, cks = _loss_rollout(th, g, sc, T)
+    g.adjoint_reset()
+    gqd, gvd = dev(th, gq), dev(th, np.zeros_like(gq))
+    gl = th.zeros(sc.n_e, dtype=th.float64, device="cuda")
+    for ck in reversed(cks):
+        gqd, gvd, _, _, st = g.step_backward(ck, gqd, gvd, g_logE=gl)
+        assert st["status"] == 0, st
+    gl = host(gl)
+    del cks
+    hstep = 1e-3
+    fd = []
+    for e in sc.fd_tets:
+        vals = []
+        for s in (1.0, -1.0):
+            le = sc.log_E.copy()
+            le[e] += s * hstep
+            g.set_material(le)
+            g.factorize()
+            vals.append(_loss_rollout(th, g, sc, T)[0])
+        fd.append((vals[0] - vals[1]) / (2 * hstep))
+    fd = np.array(fd)
+    ad = gl[sc.fd_tets]
+    scale = np.abs(fd).max()
+    assert scale > 0
+    print("fd check: tet, adjoint, central difference, rel. difference")
+    for e, a, b in zip(sc.fd_tets.tolist(), ad.tolist(), fd.tolist()):
+        print(f"  {e:6d} {a: .10e} {b: .10e} {abs(a - b) / scale:.2e}")
+    assert np.abs(ad - fd).max() <= 1e-3 * scale, list(zip(sc.fd_tets.tolist(), ad.tolist(), fd.tolist()))

@@ -84,14 +84,22 @@ def test_adam_step(th):
     assert np.abs(net.get_params() - ref).max() <= 1e-6 * max(1.0, np.abs(ref).max())
 
 
-def test_training_reduces_iterations(th):
+@pytest.fixture(scope="module")
+def trained(th):
+    """A network trained on plain rollouts of four family beams (16x4x4 cubes)."""
+    from paper_2605_14526_amd import warmstart as W
+    fam = lambda k: scenes.hetero_beam_family(k, nx=16, ny=4, nz=4)  # noqa: E731
+    net, hist, secs, n = W.train_for(fam, 4, 60, 12, th, seed=3)
+    return net, hist
+
+
+def test_training_reduces_iterations(th, trained):
     """Trained on plain rollouts of four family beams, the network's first
     iterate needs fewer PD iterations than the plain start on a held-out beam
     (the same gate: the result agrees with the plain rollout)."""
     from paper_2605_14526_amd import warmstart as W
     from paper_2605_14526_amd.binding import Scene
-    fam = lambda k: scenes.hetero_beam_family(k, nx=16, ny=4, nz=4)  # noqa: E731
-    net, hist, secs, n = W.train_for(fam, 4, 60, 12, th, seed=3)
+    net, hist = trained
     assert hist[-1] < hist[0]
     sc = scenes.hetero_beam_c2(16, 4, 4, 60)
     g = Scene.from_scene(sc)
@@ -101,3 +109,42 @@ def test_training_reduces_iterations(th):
     assert np.mean(it_learn) < np.mean(it_plain), (np.mean(it_learn), np.mean(it_plain))
     a, b = qp.cpu().numpy(), ql.cpu().numpy()
     assert np.abs(a - b).max() <= 1e-4 * np.abs(a).max()
+
+
+def test_learned_start_solve_matches_oracle(th, trained):
+    """The solve that starts from the network's prediction against the oracle
+    handed the same first iterate (Alg. 1 from a supplied q0): on the
+    held-out beam, from the oracle's states, each of 20 steps takes the
+    trained network's q0, and the library's step and the oracle's step from
+    that q0 agree in iteration count (or decide one apart within the gate's
+    rounding band, then compared at the library's count) and in positions to
+    1e-9."""
+    from paper_2605_14526_amd.binding import Scene
+    net, _ = trained
+    sc = scenes.hetero_beam_c2(16, 4, 4, 60)
+    g = Scene.from_scene(sc)
+    o = O.OracleScene(sc)
+    d = lambda a: th.tensor(np.ascontiguousarray(a), dtype=th.float64, device="cuda")  # noqa: E731
+    logw = d(g.vertex_logw())
+    q, v = sc.q0(), sc.v0()
+    v_prev = v
+    worst, its = 0.0, []
+    for t in range(20):
+        f = sc.f_ext(t)
+        q0 = net.forward(d(q), d(v_prev), d(v), d(f), logw)
+        q0h = q0.cpu().numpy()
+        qg, _, stg = g.step_forward(d(q), d(v), d(f), q0=q0)
+        qo, vo, _, sto = o.step_forward(q, v, f, q0=q0h)
+        its.append((stg["iters"], sto["iters"]))
+        qc = qo
+        if stg["iters"] != sto["iters"]:
+            kg, ko = stg["iters"], sto["iters"]
+            qc, _, _, stf = o.step_forward(q, v, f, q0=q0h, force_iters=kg)
+            gt = (stf if kg < ko else sto)["gate"]
+            r = max(gt[0] / (sc.eps_rel * gt[1] + sc.eps_abs), gt[2] / (sc.eps_rel * gt[3] + sc.eps_abs))
+            assert abs(r - 1.0) <= 1e-4, (t, kg, ko, r)
+        worst = max(worst, float(np.abs(qg.cpu().numpy() - qc).max() / np.abs(qc).max()))
+        v_prev, q, v = v, qo, vo
+    assert worst < 1e-9, (worst, its)
+    # the learned start is not the plain one: the first iterates differ from q_t
+    assert np.abs(q0h - q).max() > 0

@@ -611,3 +611,24 @@ def test_scene_prox_jacobian_at_rest_uses_mesh_means(kind):
     m = osc.info()["mass"]
     elastic = osc.apply_A(x) - m[:, None] / sc.h ** 2 * x
     assert np.allclose(Kx, fac * elastic, rtol=0, atol=1e-10 * np.abs(elastic).max())
+
+
+def test_thread_count_does_not_change_results():
+    """The oracle's element loops run on several threads but add their
+    contributions in a fixed (element) order, so one thread and four threads
+    give bitwise the same forward step, backward step and gradients."""
+    sc = scenes.small_beam(6, 3, 2, seed=21, contrast=30.0, tip_force=10.0)
+    out = []
+    n0 = O.get_threads()
+    try:
+        for n in (1, 4):
+            O.set_threads(n)
+            osc = O.OracleScene(sc, eps_adj=1e-10)
+            qn, vn, qm1, st = osc.step_forward(sc.X, np.zeros_like(sc.X), sc.f_ext(2))
+            gq = rng(5).standard_normal(sc.X.shape)
+            res = osc.step_backward(sc.X, np.zeros_like(sc.X), sc.f_ext(2), qn, qm1, gq, 0 * gq, adj_mode=0)
+            out.append([qn, qm1, *res[:4], osc.phi(qn, sc.X)])
+    finally:
+        O.set_threads(n0)
+    for a, b in zip(out[0], out[1]):
+        assert np.array_equal(a, b)

@@ -1,12 +1,18 @@
 """Benchmark: forward + backward differentiable-PD time steps per second on one
-MI355X, on the heterogeneous-beam workload (40x10x10 cubes, 20000 tets, 4961
-vertices, FP64, h = 5 ms, dual-gate and adjoint tolerance 1e-6).
+MI355X.
 
-One bench step = one PD time step solved forward to the dual gate plus its
-adjoint step (trust-region selection, filtered prox differential, adjoint
-solve to 1e-6, gradient routing).  The timed region runs K forward steps of the
-rollout (with checkpoints) and then the K backward steps from the gradient of a
-centroid loss, all inputs resident in HBM.  Prints ONE JSON line.
+Default workload (--config batch): the identification batch, 64 uneven scenes
+(beams and anchored blobs, 1k-30k tets each, about 0.73 M tets in total, FP64)
+stepped together; the loss is trajectory matching, sum over steps of the
+mass-weighted distance to an observed trajectory that another material field
+generated, and its gradient goes to every tet's log E.  One bench step = one
+batched time step of every scene solved forward to the dual gate (1e-6) plus
+its adjoint step (trust-region selection, filtered prox differential, adjoint
+solve, gradient routing).  The timed region runs K forward steps (with
+checkpoints) and then the K backward steps, all inputs resident in HBM.
+`--config c2` runs the single 20,000-tet heterogeneous beam instead, `drop`
+the contact drop, `warmstart` the learned start on held-out drops.  Prints ONE
+JSON line.
 """
 from __future__ import annotations
 
@@ -22,23 +28,27 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 METRIC = "fwd+bwd PD steps/sec at 1e-6 residual (plain vs warm-started); % HBM roofline"
+# adjoint tolerance of the benchmarked steps: the loosest PCG stop whose
+# gradients stay within 1e-6 (relative) of the oracle's on the heterogeneous
+# beam (tests/test_gpu_hetero_beam.py checks exactly this setting)
+ADJ_TOL = 1e-10
 HBM_PEAK_GBS = 8000.0
 FP64_VECTOR_PEAK_TFLOPS = 78.6
 
 # kernel ids understood by pd_kernel_timer (see include/pdhot.h)
-KERNELS = {"local": 0, "gather": 1, "top": 2, "bottom": 3, "Eb": 4, "apply_K": 5}
+KERNELS = {"local": 0, "gather": 1, "top": 2, "bottom": 3, "Eb": 4, "apply_K": 5, "solve": 6}
 LEARNED_EDGE_WEIGHT = 100.0  # edge-difference weight of the warm-start network's training loss
 
 
 def parse():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=100)
+    ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=5)
-    ap.add_argument("--config", default="c2")
+    ap.add_argument("--config", default="batch")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-sample-steps", type=int, default=20)
-    ap.add_argument("--timed-kernel", default="bottom", choices=sorted(KERNELS))
+    ap.add_argument("--timed-kernel", default="solve", choices=sorted(KERNELS))
     ap.add_argument("--max-sub", type=int, default=0)
     ap.add_argument("--no-warm-run", action="store_true", help="skip the warm-started measurements")
     ap.add_argument("--train-scenes", type=int, default=4, help="beams the warm-start network is trained on")
@@ -53,7 +63,8 @@ def parse():
 
 # committed counter summaries of the workloads that have one
 TRAFFIC_FILES = {("c2", None): "traffic_solve_and_local_kernels_hetero_beam_20k_tets.txt",
-                 ("drop", 41): "traffic_interface_solve_contact_drop_100k_tets.txt"}
+                 ("drop", 41): "traffic_interface_solve_contact_drop_100k_tets.txt",
+                 ("batch", None): "traffic_solve_identification_batch_64_scenes.txt"}
 
 
 def measured_traffic(kernel, config="c2", drop_res=None):
@@ -123,84 +134,220 @@ def rollout_fwd_bwd(g, sc, K, torch, dev, net=None, logw=None):
     return t1 - t0, fiters, biters, g_logE
 
 
-def cpu_baseline(sc, steps):
-    """The FP64 CPU oracle (serial C) on the first `steps` steps of the same rollout."""
+def cpu_model() -> str:
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
+def host_cores() -> int:
+    try:
+        return len(os.sched_getaffinity(0))
+    except AttributeError:
+        return os.cpu_count() or 1
+
+
+def cpu_baseline(samples, threads=None):
+    """The FP64 CPU oracle on (scene, steps) samples of the same workload: each
+    sample is a forward rollout of `steps` steps and its reverse sweep of the
+    centroid loss.  Returns (seconds, scene-steps, threads used)."""
     import oracle as O
     from paper_2605_14526_amd import scenes
-    def note(what):
-        print(f"[bench] cpu baseline: {what} ({time.perf_counter() - t0:.1f} s)", file=sys.stderr, flush=True)
-
+    n0 = O.get_threads()
+    if threads:
+        O.set_threads(threads)
+    used = O.get_threads()
     t0 = time.perf_counter()
-    osc = O.OracleScene(sc)
-    note(f"oracle set up, {steps} forward steps next")
-    if sc.obstacles:
-        q, v, ck, _ = O.rollout_contact(osc, steps)
-        note("forward done, reverse sweep next")
-        _, gq = scenes.centroid_loss(q, sc.target_centroid)
-        O.rollout_backward_contact(osc, ck, gq, np.zeros_like(gq))
-    else:
-        q, v, ck, _ = O.rollout(osc, steps)
-        note("forward done, reverse sweep next")
-        _, gq = scenes.centroid_loss(q, sc.target_centroid)
-        O.rollout_backward(osc, ck, gq, np.zeros_like(gq))
-    t1 = time.perf_counter()
-    note("done")
-    return t1 - t0
+    done = 0
+    try:
+        for sc, steps in samples:
+            osc = O.OracleScene(sc, eps_adj=ADJ_TOL)
+            if sc.obstacles:
+                q, v, ck, _ = O.rollout_contact(osc, steps)
+                _, gq = scenes.centroid_loss(q, sc.target_centroid)
+                O.rollout_backward_contact(osc, ck, gq, np.zeros_like(gq))
+            else:
+                q, v, ck, _ = O.rollout(osc, steps)
+                _, gq = scenes.centroid_loss(q, sc.target_centroid)
+                O.rollout_backward(osc, ck, gq, np.zeros_like(gq))
+            done += steps
+            print(f"[bench] cpu baseline ({used} threads): {sc.name} {steps} steps "
+                  f"({time.perf_counter() - t0:.1f} s)", file=sys.stderr, flush=True)
+    finally:
+        O.set_threads(n0)
+    return time.perf_counter() - t0, done, used
+
+
+def cpu_baseline_entry(samples_all, samples_one, what):
+    """cpu_baseline on all host threads and on one thread (a smaller sample)."""
+    t, n, used = cpu_baseline(samples_all)
+    t1, n1, _ = cpu_baseline(samples_one, threads=1)
+    return {"value": round(n / t, 4), "unit": "scene fwd+bwd steps/s", "cores": used, "kind": "oracle",
+            "sample": f"{what}: {n} scene-steps in {t:.2f} s on {used} threads (OpenMP over elements, fixed "
+                      f"summation order, fixed-point adjoint to {ADJ_TOL:g})",
+            "one_thread": {"value": round(n1 / t1, 4), "sample": f"{n1} scene-steps in {t1:.2f} s"},
+            "host_cores": host_cores(), "cpu_model": cpu_model()}
+
+
+def roofline_entry(kernel, bound, ms, launches, work, peak, unit, traffic=None, extra=None):
+    achieved = work / (ms * 1e-3) / (1e9 if unit == "GB/s" else 1e12) if ms > 0 else 0.0
+    r = {"kernel": kernel, "bound": bound, "achieved": round(achieved, 3), "peak": peak, "unit": unit,
+         "frac": round(achieved / peak, 4), "traffic": traffic,
+         "avg_launch_us": round(1000.0 * ms / max(launches, 1), 3), "launches": int(launches)}
+    if extra:
+        r.update(extra)
+    return r
+
+
+def profile_value(name, key):
+    """A figure from a committed profile summary (`key: value` line), or None."""
+    path = os.path.join(ROOT, "profiles", name)
+    if not os.path.exists(path):
+        return None
+    for line in open(path):
+        if line.startswith(key + ":"):
+            return float(line.split(":", 1)[1].split()[0])
+    return None
 
 
 def bench_batch(args, torch):
-    """Uneven batch of beams and anchored blobs (64 scenes, about 0.73 M tets):
-    batched fwd+bwd scene-steps per second after autotuning the launch shapes."""
+    """Identification batch (64 uneven beams and anchored blobs, about 0.73 M
+    tets): batched fwd+bwd scene-steps per second of the trajectory-matching
+    loss after autotuning the launch shapes."""
     from paper_2605_14526_amd import autotune, scenes
     from paper_2605_14526_amd.binding import Batch, Scene
-    scs = scenes.sysid_batch(n=args.batch_scenes, steps=args.steps)
+    K = args.steps
+    horizon = max(K, args.warmup, 2)
+    scs = scenes.sysid_batch(n=args.batch_scenes, steps=50)
     t0 = time.perf_counter()
-    gs = [Scene.from_scene(sc, eps_adj=1e-6, adj_warm=3) for sc in scs]
+    gs = [Scene.from_scene(sc, eps_adj=ADJ_TOL, adj_warm=3) for sc in scs]
     t_setup = time.perf_counter() - t0
-    B = Batch(gs)
     dev = lambda a: torch.tensor(np.ascontiguousarray(a), dtype=torch.float64, device="cuda")  # noqa: E731
-    forces = [[dev(sc.f_ext(t)) for sc in scs] for t in range(args.steps)]
-    targets = [torch.tensor(sc.target_centroid, dtype=torch.float64, device="cuda") for sc in scs]
+    forces = [[dev(sc.f_ext(t)) for sc in scs] for t in range(horizon)]
+    mass = [dev(g.vertex_mass())[:, None] for g in gs]
+    # observed trajectories: each scene rolled out with its observation field (setup, untimed)
+    t0 = time.perf_counter()
+    obs = []
+    for g, sc in zip(gs, scs):
+        g.set_material(sc.log_E_obs)
+        g.factorize()
+        q, v = dev(sc.q0()), dev(sc.v0())
+        traj = [q]
+        for t in range(horizon):
+            q, v, _ = g.step_forward(q, v, forces[t][len(obs)])
+            traj.append(q)
+        obs.append(traj)
+        g.set_material(sc.log_E)
+        g.factorize()
+    t_obs = time.perf_counter() - t0
+    print(f"[bench] batch of {len(scs)} scenes set up in {t_setup:.1f} s, observations in {t_obs:.1f} s",
+          file=sys.stderr, flush=True)
+    B = Batch(gs)
+    g_logE = [torch.zeros(sc.n_e, dtype=torch.float64, device="cuda") for sc in scs]
 
-    def rollout(K):
+    def rollout(n, inertial=False):
         q = [dev(sc.q0()) for sc in scs]
         v = [dev(sc.v0()) for sc in scs]
-        cks = []
-        fi, bi = [], []
-        for t in range(K):
+        traj, cks, fi, bi = [q], [], [], []
+        loss = 0.0
+        for t in range(n):
             ck = [g.new_ckpt() for g in gs]
-            q, v, st, _ = B.step_forward(q, v, forces[t], ckpt=ck)
+            q0 = [qq + sc.h * vv for qq, vv, sc in zip(q, v, scs)] if inertial else None
+            q, v, st, _ = B.step_forward(q, v, forces[t], q0=q0, ckpt=ck)
+            traj.append(q)
             cks.append(ck)
             fi.append(np.mean([x["iters"] for x in st]))
-        gq = [(2.0 * (qq.mean(dim=0) - tg) / qq.shape[0]).expand_as(qq).contiguous() for qq, tg in zip(q, targets)]
+        # trajectory loss sum_t sum_v m_v |q_t,v - q_t,v^obs|^2 (its gradient is formed on the device)
+        gq = [2.0 * m * (traj[n][s] - obs[s][n]) for s, m in enumerate(mass)]
         gv = [torch.zeros_like(x) for x in gq]
         for g in gs:
             g.adjoint_reset()
-        for ck in reversed(cks):
-            gq, gv, _, _, st, _ = B.step_backward(ck, gq, gv)
+        for x in g_logE:
+            x.zero_()
+        for t in reversed(range(n)):
+            gq, gv, _, _, st, _ = B.step_backward(cks[t], gq, gv, g_logE=g_logE)
             bi.append(np.mean([x["adj_iters"] for x in st]))
+            if t > 0:
+                gq = [gq[s] + 2.0 * m * (traj[t][s] - obs[s][t]) for s, m in enumerate(mass)]
         return fi, bi
 
     t1 = time.perf_counter()
     cfg = autotune.autotune(B, lambda: rollout(2), torch, cache_path=args.tune_cache or None, reps=1)
     t_tune = time.perf_counter() - t1
+    # the solve is timed per launch inside the timed region; graphs carry no per-launch events
+    if cfg.get("use_graph"):
+        B.config(cfg["block_local"], cfg["block_applyK"], cfg["iters_per_check"], 0)
     rollout(args.warmup)
+    B.kernel_timer(KERNELS["solve"])
     torch.cuda.synchronize()
     t2 = time.perf_counter()
-    fi, bi = rollout(args.steps)
+    fi, bi = rollout(K)
     torch.cuda.synchronize()
     dt = time.perf_counter() - t2
+    s_ms, s_launch, s_bytes = B.kernel_timer_read()
+    B.kernel_timer(-1)
+    assert all(bool(torch.isfinite(x).all()) for x in g_logE)
+    print(f"[bench] timed {K} batched fwd+bwd steps in {dt:.3f} s; fwd iters/scene-step {np.mean(fi):.2f}, "
+          f"adjoint {np.mean(bi):.2f}", file=sys.stderr, flush=True)
+    # the local step's FP64 rate over the same K steps (a separate run, not part of `value`)
+    B.kernel_timer(KERNELS["local"])
+    rollout(K)
+    l_ms, l_launch, l_bytes = B.kernel_timer_read()
+    B.kernel_timer(-1)
     ne = sum(sc.n_e for sc in scs)
-    out = {"metric": METRIC, "value": round(len(scs) * args.steps / dt, 3), "unit": "scene fwd+bwd steps/s",
-           "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
-           "ms_per_step": round(1000.0 * dt / args.steps, 4), "higher_is_better": True, "scaling": "weak",
+    nnz = sum(g.factor_nnz() for g in gs)
+    # inertial start q0 = q_t + h v_t, same gate
+    rollout(min(args.warmup, 2), inertial=True)
+    torch.cuda.synchronize()
+    t3 = time.perf_counter()
+    fw, bw = rollout(K, inertial=True)
+    torch.cuda.synchronize()
+    dtw = time.perf_counter() - t3
+    prof = "fp64_counters_local_step_identification_batch_64_scenes.txt"
+    flop_per_byte = profile_value(prof, "fp64_flop_per_algorithmic_byte")
+    roof = roofline_entry("solve (interface right-hand side + interface solve + subdomain solve)", "hbm", s_ms,
+                          s_launch, s_bytes, HBM_PEAK_GBS, "GB/s",
+                          traffic=measured_traffic("solve", "batch"),
+                          extra={"algorithmic_bytes": "per solve 16 B x nnz(L) of a nested-dissection Cholesky "
+                                                      "factor of A~ + 6 x 24 B x n_free, summed over the solves "
+                                                      "each scene did",
+                                 "bytes_timed": round(s_bytes), "sum_nnz_L": round(nnz)})
+    out = {"metric": METRIC, "value": round(len(scs) * K / dt, 3), "unit": "scene fwd+bwd steps/s",
+           "n_gpus": 1, "steps": K, "warmup": args.warmup,
+           "ms_per_step": round(1000.0 * dt / K, 4), "higher_is_better": True, "scaling": "weak",
            "vs_baseline": None, "dtype": "f64", "data": "synthetic",
-           "config": {"workload": f"batch of {len(scs)} uneven scenes ({sum('blob' in sc.name for sc in scs)} "
-                                  f"anchored blobs, the rest beams), {ne} tets in total (1k-30k each), "
-                                  f"contrast 1-100x, nu 0.40-0.49, h 0.01, {args.steps} steps, gate and adjoint 1e-6",
+           "config": {"workload": f"identification batch: {len(scs)} uneven scenes "
+                                  f"({sum('blob' in sc.name for sc in scs)} anchored blobs, the rest beams), "
+                                  f"{ne} tets in total (1k-30k each), contrast 1-100x, nu 0.40-0.49, h 0.01, "
+                                  f"{K} batched steps, trajectory-matching loss against observations from "
+                                  f"another material field, gradient w.r.t. every log E, gate 1e-6, "
+                                  f"adjoint PCG to {ADJ_TOL:g}, plain q0 = q_t",
                       "launch_shapes": cfg, "setup_s": round(t_setup, 2), "tune_s": round(t_tune, 2),
                       "fwd_iters_per_step": round(float(np.mean(fi)), 3),
-                      "adj_iters_per_step": round(float(np.mean(bi)), 3)}}
+                      "adj_iters_per_step": round(float(np.mean(bi)), 3)},
+           "roofline": roof,
+           "roofline_local": roofline_entry(
+               "local step (batched)", "fp64" if flop_per_byte else "hbm", l_ms, l_launch,
+               l_bytes * flop_per_byte if flop_per_byte else l_bytes, FP64_VECTOR_PEAK_TFLOPS if flop_per_byte
+               else HBM_PEAK_GBS, "TFLOP/s" if flop_per_byte else "GB/s",
+               extra={"hbm_GBps": round(l_bytes / max(l_ms, 1e-9) / 1e6, 2),
+                      "hbm_frac": round(l_bytes / max(l_ms, 1e-9) / 1e6 / HBM_PEAK_GBS, 4),
+                      "flops": f"FP64 flops per algorithmic byte {flop_per_byte} from {prof}"
+                      if flop_per_byte else None}),
+           "warm_started": {"inertial": {"value": round(len(scs) * K / dtw, 3), "unit": "scene fwd+bwd steps/s",
+                                         "ms_per_step": round(1000.0 * dtw / K, 4),
+                                         "fwd_iters_per_step": round(float(np.mean(fw)), 3),
+                                         "adj_iters_per_step": round(float(np.mean(bw)), 3),
+                                         "start": "q0 = q_t + h v_t"}}}
+    if not args.no_cpu_baseline:
+        pick = list(range(0, len(scs), 8))
+        out["cpu_baseline"] = cpu_baseline_entry([(scs[i], 1) for i in pick], [(scs[i], 1) for i in pick[:2]],
+                                                 f"first fwd+bwd step of scenes {pick} of the batch "
+                                                 f"({sum(scs[i].n_e for i in pick)} tets)")
     print(json.dumps(out), flush=True)
 
 
@@ -285,8 +432,8 @@ def main():
     drop = args.config == "drop"
     sc = scenes.drop_blob(res=args.drop_res) if drop else scenes.config(args.config)
     dev = lambda a: torch.tensor(np.ascontiguousarray(a), dtype=torch.float64, device="cuda")  # noqa: E731
-    # adjoint: start extrapolated (quadratically) from the sweep's previous solutions (runs to 1e-6 either way)
-    g = Scene.from_scene(sc, eps_adj=1e-6, max_sub=args.max_sub, adj_warm=3)
+    # adjoint: start extrapolated (quadratically) from the sweep's previous solutions (runs to ADJ_TOL either way)
+    g = Scene.from_scene(sc, eps_adj=ADJ_TOL, max_sub=args.max_sub, adj_warm=3)
     info = g.info()
     print(f"[bench] scene {sc.name}: {info}", file=sys.stderr, flush=True)
     # warmup (untimed)
@@ -307,25 +454,25 @@ def main():
         print(f"[bench] contact rows/step {np.mean(g.contact_hist):.1f}, max {max(g.contact_hist)}; active max "
               f"{max(g.active_hist)}", file=sys.stderr, flush=True)
     value = args.steps / dt
-    # roofline of the timed kernel: algorithmic bytes of the launches that did
+    # roofline of the timed kernel: algorithmic bytes of the units that did
     # work over the summed launch durations
     bytes_per_unit = g.kernel_bytes(kid)
-    achieved = (kwork * bytes_per_unit) / (ktime_ms * 1e-3) / 1e9 if ktime_ms > 0 else 0.0
     traffic = measured_traffic(args.timed_kernel, args.config, args.drop_res)
-    roof = {"kernel": args.timed_kernel, "bound": "hbm", "achieved": round(achieved, 2), "peak": HBM_PEAK_GBS,
-            "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic,
-            "avg_launch_us": round(1000.0 * ktime_ms / max(kcount, 1), 3), "launches": int(kcount),
-            "working_launches": int(kwork), "algorithmic_bytes_per_launch": int(bytes_per_unit)}
+    roof = roofline_entry(args.timed_kernel, "hbm", ktime_ms, kcount, kwork * bytes_per_unit, HBM_PEAK_GBS, "GB/s",
+                          traffic=traffic, extra={"working_units": int(kwork),
+                                                  "algorithmic_bytes_per_unit": int(bytes_per_unit),
+                                                  "nnz_L": round(g.factor_nnz())})
     out = {"metric": METRIC, "value": round(value, 3), "unit": "steps/s", "n_gpus": 1, "steps": args.steps,
            "warmup": args.warmup, "ms_per_step": round(1000.0 * dt / args.steps, 4), "higher_is_better": True,
            "scaling": "weak", "vs_baseline": None, "dtype": "f64", "data": "synthetic",
            "config": {"workload": (f"{sc.name}: voxelised blob of 6 spheres, {sc.n_e} tets, {sc.n_v} verts, shell "
                                    f"E 1e6 over interior 1e4, nu 0.49, h {sc.h}, dropped at 1 m/s onto the ground "
                                    f"plane and a box, frictionless contact, rollout of {args.steps} steps, "
-                                   "gate, FB residual 1e-10 and adjoint 1e-6") if drop else
+                                   f"gate 1e-6, FB residual 1e-10, adjoint PCG to {ADJ_TOL:g}") if drop else
                                   (f"{sc.name}: 40x10x10 cubes, {sc.n_e} tets, {sc.n_v} verts, two-phase E 1e4/1e6, "
                                    f"nu 0.49, h {sc.h}, rollout of {args.steps} steps, AA window {sc.aa_window}, "
-                                   "gate and adjoint 1e-6, plain q0 = q_t, adjoint start extrapolated from the last three solutions"),
+                                   f"gate 1e-6, adjoint PCG to {ADJ_TOL:g}, plain q0 = q_t, adjoint start "
+                                   "extrapolated from the last three solutions"),
                       "fwd_iters_per_step": round(float(np.mean(fiters)), 3),
                       "adj_iters_per_step": round(float(np.mean(biters)), 3),
                       "n_subdomains": int(info["n_subdomains"]), "n_interface": int(info["n_interface"])},
@@ -336,7 +483,7 @@ def main():
     if not args.no_warm_run:
         out["warm_started"] = {}
         # the same rollout with the inertial first iterate q0 = q_t + h v_t
-        gw = Scene.from_scene(sc, eps_adj=1e-6, max_sub=args.max_sub, adj_warm=3, fwd_start=1)
+        gw = Scene.from_scene(sc, eps_adj=ADJ_TOL, max_sub=args.max_sub, adj_warm=3, fwd_start=1)
         if args.warmup > 0:
             rollout_fwd_bwd(gw, sc, args.warmup, torch, dev)
         dtw, fw, bw, _ = rollout_fwd_bwd(gw, sc, args.steps, torch, dev)
@@ -373,12 +520,11 @@ def main():
               f"(trained {tsec:.1f} s)", file=sys.stderr, flush=True)
     if not args.no_cpu_baseline:
         n = args.cpu_sample_steps
-        if sc.tets.shape[0] > 50000:  # the serial oracle's reverse sweep takes about 20 s per step at this size
+        if sc.tets.shape[0] > 50000:  # the oracle's reverse sweep takes seconds per step at this size
             n = 1
-        t = cpu_baseline(sc, n)
-        out["cpu_baseline"] = {"value": round(n / t, 4), "unit": "steps/s", "cores": 1, "kind": "oracle",
-                               "sample": f"first {n} fwd+bwd steps of the same rollout, serial FP64 C oracle "
-                                         f"(fixed-point adjoint), {t:.2f} s"}
+        out["cpu_baseline"] = cpu_baseline_entry([(sc, n)], [(sc, min(n, 2))],
+                                                 f"first {n} fwd+bwd steps of the same rollout")
+        out["cpu_baseline"]["unit"] = "steps/s"
     print(json.dumps(out), flush=True)
 
 

@@ -62,13 +62,20 @@ typedef struct pd_mesh_desc {
 /* Material (host pointers, copied).  Per-tet Young's modulus E_e = exp(log_E[e])
  * with a shared Poisson ratio nu gives the Lame parameters of Sec. 3.1
  * Eq. lame; rho is the density; alpha (1/s) and beta0 (Pa s) are the Rayleigh
- * coefficients of Sec. 4.5 Eq. rayleigh, beta_e = beta0 mu_e / max_e mu_e. */
+ * coefficients of Sec. 4.5 Eq. rayleigh, beta_e = beta0 mu_e / max_e mu_e.
+ * energy selects the local step (Sec. 4.1): 0 = the Neo-Hookean proximal map
+ * with PD weight w_e = 2 mu_e + lam_e; 1 = the corotated + volume composite,
+ * a rotation step p0 = R (signed polar rotation of F) with weight 2 mu_e and
+ * a volume step p1 = F projected onto det = 1 (the closest unit-determinant
+ * point in stretch space) with weight lam_e (Sec. 7.2).  Both give the same
+ * system matrix; the trust-region filter of Sec. 4.4 applies to energy 0. */
 typedef struct pd_material_desc {
   const double* log_E;
   double nu;
   double rho;
   double alpha;
   double beta0;
+  int32_t energy;
 } pd_material_desc;
 
 /* Solver options.
@@ -276,14 +283,26 @@ int pd_debug_apply_K(pd_scene* scene, const double* q, double tau, const double*
  * stamped by the dispatch itself on the caller's stream, so the elapsed time
  * is the kernel's own execution time.  kernel: 0 local step, 1 right-hand-side
  * gather, 2 interface (Schur) solve, 3 subdomain solve, 4 interface
- * right-hand side (coupling products), 5 K apply; -1 stops timing.  Resets the
+ * right-hand side (coupling products), 5 K apply, 6 the whole global solve
+ * (the launches of 2, 3 and 4 together); -1 stops timing.  Resets the
  * totals.  Instrumentation only. */
 int pd_kernel_timer(pd_scene* scene, int kernel);
 /* Totals since pd_kernel_timer: summed launch durations (ms), launches timed,
- * launches that did work (the others exit at once after convergence), and
- * the algorithmic bytes of one working launch of that kernel. */
+ * working units (launches that did work, the others exit at once after
+ * convergence; for kernel 6 the global solves) and the algorithmic bytes of
+ * one unit: what the operation must move once (Sec. 4.1 local step: 96 B of
+ * element data per tet and 48 B of vertex data per vertex; the global solve
+ * of Sec. 4.6: one forward and one backward sweep of the sparse Cholesky
+ * factor of A~ under nested dissection, 16 B per factor entry, plus six
+ * passes over three-axis vectors of the free vertices), not what the
+ * implementation re-reads. */
 int pd_kernel_timer_read(pd_scene* scene, double* total_ms, int64_t* launches, int64_t* working,
                          double* bytes_per_launch);
+/* Entries (diagonal included) of the sparse Cholesky factor of A~ over the
+ * free vertices under a nested-dissection order (recursive coordinate
+ * bisection with vertex separators): the factor that the method's triangular
+ * solves would sweep (Sec. 4.6), used for the algorithmic bytes above. */
+int pd_scene_factor_nnz(const pd_scene* scene, double* nnz);
 
 /* ------------------------------------------------------------------------
  * Batches: many scenes (any sizes, materials and Anderson windows) stepped
@@ -312,6 +331,14 @@ int pd_batch_step_forward(pd_batch* batch, const double* const* q_t, const doubl
 int pd_batch_step_backward(pd_batch* batch, const void* const* ckpt, const double* const* gq_next,
                            const double* const* gv_next, double* const* gq_t, double* const* gv_t,
                            double* const* gf_ext, double* const* g_logE_accum, pd_bwd_stats* stats, void* stream);
+
+/* Per-launch timing of one kernel kind inside the batched steps (as
+ * pd_kernel_timer, eager launches only: nothing is timed while use_graph = 1)
+ * and the algorithmic bytes of the work those launches did, summed over the
+ * scenes (kernel 6, the global solve: each scene's solves times its bytes per
+ * solve; 0: each scene's local steps; 5: each scene's K applies). */
+int pd_batch_kernel_timer(pd_batch* batch, int kernel);
+int pd_batch_kernel_timer_read(pd_batch* batch, double* total_ms, int64_t* launches, double* bytes_done);
 
 /* Per-vertex material feature of the learned warm start: the mean of
  * log(2 mu_e + lam_e) over the vertex's tets (Eq. lame, the PD weight of

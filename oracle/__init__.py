@@ -55,6 +55,10 @@ def lib():
         L.or_psi_nh.restype = ctypes.c_double
         L.or_psi_nh.argtypes = [_dp, ctypes.c_double, ctypes.c_double]
         L.or_sym3_eig.argtypes = [_dp, _dp, _dp]
+        L.or_volume_project.argtypes = [_dp, _dp]
+        L.or_volume_diff.argtypes = [_dp, _dp]
+        L.or_composite_map.argtypes = [_dp, ctypes.c_double, ctypes.c_double, _dp]
+        L.or_composite_jacobian.argtypes = [_dp, ctypes.c_double, ctypes.c_double, _dp]
         L.or_tr_filter.argtypes = [_dp, ctypes.c_double, ctypes.c_double, _dp, _dp]
         L.or_aa_step.argtypes = [ctypes.c_int, ctypes.c_int, _dp, _dp, _ip, _dp, _dp, ctypes.c_char_p, _dp, _dp]
         L.or_local_rhs.argtypes = [ctypes.c_void_p, _dp, _dp]
@@ -132,6 +136,30 @@ def psi_nh(F, mu, lam):
     return lib().or_psi_nh(_p(_f(F).reshape(3, 3)), mu, lam)
 
 
+def volume_project(sF):
+    s = np.zeros(3)
+    it = lib().or_volume_project(_p(_f(sF)), _p(s))
+    return s, it
+
+
+def volume_diff(sF):
+    D = np.zeros((3, 3))
+    lib().or_volume_diff(_p(_f(sF)), _p(D))
+    return D
+
+
+def composite_map(F, mu, lam):
+    P = np.zeros((3, 3))
+    lib().or_composite_map(_p(_f(F).reshape(3, 3)), mu, lam, _p(P))
+    return P
+
+
+def composite_jacobian(F, mu, lam):
+    J = np.zeros((9, 9))
+    lib().or_composite_jacobian(_p(_f(F).reshape(3, 3)), mu, lam, _p(J))
+    return J
+
+
 def sym3_eig(H):
     H = _f(H).reshape(3, 3)
     k, Q = np.zeros(3), np.zeros((3, 3))
@@ -170,7 +198,7 @@ class OracleScene:
     """Oracle scene built from a :class:`paper_2605_14526_amd.scenes.Scene`-like object."""
 
     def __init__(self, sc, m=None, eps_rel=None, eps_abs=None, kmax_fwd=1000, kmax_bwd=1000, eps_adj=1e-6,
-                 eps_tr=0.1, log_E=None, frozen=None):
+                 eps_tr=0.1, log_E=None, frozen=None, energy=None):
         L = lib()
         self.sc = sc
         self.nv = int(sc.X.shape[0])
@@ -184,7 +212,7 @@ class OracleScene:
         fr = (0.0, 0.0, 0.0) if frozen is None else tuple(frozen)
         solver = _f([sc.aa_window if m is None else m, sc.eps_rel if eps_rel is None else eps_rel,
                      sc.eps_abs if eps_abs is None else eps_abs, kmax_fwd, kmax_bwd, eps_adj, eps_tr,
-                     fr[0], fr[1], fr[2]])
+                     fr[0], fr[1], fr[2], getattr(sc, "energy", 0) if energy is None else energy])
         self.h = float(sc.h)
         self._keep = (X, tets, pinned, logE, params, solver)
         self.ptr = L.or_scene_create(self.nv, self.ne, _p(X), tets.ctypes.data_as(_ip),

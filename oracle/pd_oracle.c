@@ -393,13 +393,9 @@ void or_tr_filter(const double H[9], double tau, double k, double Ht[9], double 
     }
 }
 
-static void prox_diff_coeffs(const double sF[3], const double ss[3], double mu, double lam, double k, double tau,
-                             double D[9], double c1[3], double c2[3]) {
-  double gp[3], H[9];
-  psi_stretch_grad_hess(ss, mu, lam, gp, H);
-  for (int i = 0; i < 3; ++i) H[4 * i] += k;
-  /* H_prox = H_psi(s*) + k I (Eq. Hprox); D = k H~^+ solves Eq. tr_ift */
-  or_tr_filter(H, tau, k, NULL, D);
+/* pair coefficients of the SVD differential of an isotropic stretch map
+ * sF -> ss with stretch Jacobian D (see above) */
+static void pair_coeffs(const double sF[3], const double ss[3], const double D[9], double c1[3], double c2[3]) {
   const int P0[3] = {0, 0, 1}, P1[3] = {1, 2, 2};
   double sfmax = 1.0;
   for (int i = 0; i < 3; ++i) if (fabs(sF[i]) > sfmax) sfmax = fabs(sF[i]);
@@ -414,6 +410,16 @@ static void prox_diff_coeffs(const double sF[3], const double ss[3], double mu, 
     if (fabs(den) < 1e-8) den = den < 0 ? -1e-8 : 1e-8;
     c2[p] = (ss[i] + ss[j]) / den;
   }
+}
+
+static void prox_diff_coeffs(const double sF[3], const double ss[3], double mu, double lam, double k, double tau,
+                             double D[9], double c1[3], double c2[3]) {
+  double gp[3], H[9];
+  psi_stretch_grad_hess(ss, mu, lam, gp, H);
+  for (int i = 0; i < 3; ++i) H[4 * i] += k;
+  /* H_prox = H_psi(s*) + k I (Eq. Hprox); D = k H~^+ solves Eq. tr_ift */
+  or_tr_filter(H, tau, k, NULL, D);
+  pair_coeffs(sF, ss, D, c1, c2);
 }
 
 static void prox_diff_apply(const double U[9], const double V[9], const double D[9], const double c1[3],
@@ -452,6 +458,150 @@ void or_prox_jacobian(const double F[9], double mu, double lam, double k, double
 }
 
 /* ------------------------------------------------------------------------ */
+/* Corotated + volume composite (Sec. 4.1, volume-barrier paragraph: the     */
+/* default heterogeneous PD assembly splits the projection into a corotated  */
+/* rotation step and a volume step; Sec. 7.2: weights w0 = 2 mu_e for the    */
+/* rotation, w1 = lam_e for the volume term).                                */
+/* ------------------------------------------------------------------------ */
+
+/* Volume step: the closest point of sF on {s > 0 : s1 s2 s3 = 1}, i.e. F
+ * projected onto det F = 1 in stretch space (READING: the paper names the
+ * step, not its constraint set).  Every stationary point of |s - sF|^2 on
+ * the set has s_i (s_i - sF_i) = nu for one multiplier nu, so each s_i is a
+ * root (sF_i +- sqrt(sF_i^2 + 4 nu)) / 2.  The candidates are the root choices
+ * with at most one minus sign (two would leave the product below one); on
+ * each, nu is found by bisection between sign changes of sum_i ln s_i(nu)
+ * (located on a fine grid), and the candidate closest to sF is returned.
+ * Returns the number of candidates. */
+static int vol_roots(const double sF[3], double nu, int minus, double s[3]) {
+  for (int i = 0; i < 3; ++i) {
+    double d = sF[i] * sF[i] + 4.0 * nu;
+    if (d < 0.0) return 0;
+    s[i] = 0.5 * (sF[i] + (i == minus ? -sqrt(d) : sqrt(d)));
+    if (!(s[i] > 0.0)) return 0;
+  }
+  return 1;
+}
+
+static double vol_phi(const double sF[3], double nu, int minus, int* ok) {
+  double t[3];
+  *ok = vol_roots(sF, nu, minus, t);
+  return *ok ? log(t[0]) + log(t[1]) + log(t[2]) : 0.0;
+}
+
+int or_volume_project(const double sF[3], double s[3]) {
+  double lo = -INFINITY;
+  for (int i = 0; i < 3; ++i) if (-0.25 * sF[i] * sF[i] > lo) lo = -0.25 * sF[i] * sF[i];
+  double best = INFINITY;
+  int found = 0;
+  for (int minus = -1; minus < 3; ++minus) {
+    /* the nu range of this root choice: real roots above lo; a minus root needs nu < 0 */
+    double a = lo, b;
+    if (minus < 0) {
+      b = 1.0;
+      int ok;
+      while (!(vol_phi(sF, b, minus, &ok) > 0.0) && b < 1e300) b *= 2.0;
+    } else {
+      if (!(sF[minus] > 0.0)) continue;
+      b = 0.0;
+    }
+    const int N = 512;
+    double prev_nu = 0.0, prev_phi = 0.0;
+    int have_prev = 0;
+    for (int k = 0; k <= N; ++k) {
+      double nu = a + (b - a) * k / N;
+      int ok;
+      double ph = vol_phi(sF, nu, minus, &ok);
+      if (!ok) { have_prev = 0; continue; }
+      if (have_prev && ((prev_phi < 0.0) != (ph < 0.0) || ph == 0.0)) {
+        double l = prev_nu, r = nu, pl = prev_phi;
+        for (int it = 0; it < 200; ++it) {
+          double mid = 0.5 * (l + r);
+          if (mid <= l || mid >= r) break;
+          int okm;
+          double pm = vol_phi(sF, mid, minus, &okm);
+          if (!okm) break;
+          if ((pm < 0.0) == (pl < 0.0)) { l = mid; pl = pm; } else r = mid;
+        }
+        double c[3];
+        if (vol_roots(sF, 0.5 * (l + r), minus, c)) {
+          double dist = 0.0;
+          for (int i = 0; i < 3; ++i) dist += (c[i] - sF[i]) * (c[i] - sF[i]);
+          found++;
+          if (dist < best) { best = dist; for (int i = 0; i < 3; ++i) s[i] = c[i]; }
+        }
+      }
+      prev_nu = nu;
+      prev_phi = ph;
+      have_prev = 1;
+    }
+  }
+  return found;
+}
+
+/* Stretch Jacobian of the volume step, from differentiating s_i (s_i - sF_i)
+ * = nu and sum_i ln s_i = 0: with a_i = 1/(2 s_i - sF_i) and c = sum_k a_k/s_k,
+ * D_ij = a_i s_i delta_ij - a_i a_j / c. */
+static void volume_diff(const double sF[3], const double sv[3], double D[9]) {
+  double a[3], c = 0.0;
+  for (int i = 0; i < 3; ++i) { a[i] = 1.0 / (2.0 * sv[i] - sF[i]); c += a[i] / sv[i]; }
+  for (int i = 0; i < 3; ++i)
+    for (int j = 0; j < 3; ++j) D[3 * i + j] = (i == j ? a[i] * sv[i] : 0.0) - a[i] * a[j] / c;
+}
+
+/* The two projections at F: R = U V^T (the rotation of the signed polar
+ * decomposition) and P_vol = U diag(s_vol) V^T, with their differentials in
+ * the (U, V) frame: the rotation has D = 0 and the pair coefficients of the
+ * constant map s = (1, 1, 1); the volume step has D from volume_diff. */
+typedef struct {
+  double U[9], V[9], sF[3], R[9], Pv[9], sv[3];
+  double Dv[9], c1v[3], c2v[3], c1r[3], c2r[3];
+} composite_parts;
+
+static void composite_eval(const double F[9], composite_parts* c, int want_diff) {
+  double T[9];
+  or_svd3(F, c->U, c->sF, c->V);
+  mat3_mul_nt(c->U, c->V, c->R);
+  or_volume_project(c->sF, c->sv);
+  for (int i = 0; i < 3; ++i)
+    for (int j = 0; j < 3; ++j) T[3 * i + j] = c->U[3 * i + j] * c->sv[j];
+  mat3_mul_nt(T, c->V, c->Pv);
+  if (want_diff) {
+    const double one[3] = {1.0, 1.0, 1.0}, zero[9] = {0};
+    volume_diff(c->sF, c->sv, c->Dv);
+    pair_coeffs(c->sF, c->sv, c->Dv, c->c1v, c->c2v);
+    pair_coeffs(c->sF, one, zero, c->c1r, c->c2r);
+  }
+}
+
+/* (2 mu R + lam P_vol) / (2 mu + lam): the composite's projection per unit of
+ * its total weight w = 2 mu + lam (for element-level checks) */
+void or_composite_map(const double F[9], double mu, double lam, double P[9]) {
+  composite_parts c;
+  composite_eval(F, &c, 0);
+  for (int i = 0; i < 9; ++i) P[i] = (2.0 * mu * c.R[i] + lam * c.Pv[i]) / (2.0 * mu + lam);
+}
+
+void or_composite_jacobian(const double F[9], double mu, double lam, double J[81]) {
+  composite_parts c;
+  const double zero[9] = {0};
+  composite_eval(F, &c, 1);
+  for (int col = 0; col < 9; ++col) {
+    double dF[9] = {0}, dR[9], dV[9];
+    dF[col] = 1.0;
+    prox_diff_apply(c.U, c.V, zero, c.c1r, c.c2r, dF, dR);
+    prox_diff_apply(c.U, c.V, c.Dv, c.c1v, c.c2v, dF, dV);
+    for (int r = 0; r < 9; ++r) J[9 * r + col] = (2.0 * mu * dR[r] + lam * dV[r]) / (2.0 * mu + lam);
+  }
+}
+
+void or_volume_diff(const double sF[3], double D[9]) {
+  double sv[3];
+  or_volume_project(sF, sv);
+  volume_diff(sF, sv, D);
+}
+
+/* ------------------------------------------------------------------------ */
 /* scene                                                                     */
 /* ------------------------------------------------------------------------ */
 struct or_scene {
@@ -462,6 +612,7 @@ struct or_scene {
   double* logE;
   double nu, rho, alpha, beta0, h, grav[3];
   int m, kmax_fwd, kmax_bwd;
+  int energy; /* 0: Neo-Hookean proximal map; 1: corotated + volume composite */
   double eps_rel, eps_abs, eps_adj, eps_tr;
   /* derived (Sec. 3.1, 4.1, 4.2, 4.5) */
   double* Bhat;   /* ne x 4 x 3 shape gradients: F = sum_a x_a (x) Bhat_a */
@@ -562,6 +713,7 @@ or_scene* or_scene_create(int nv, int ne, const double* X, const int* tets, cons
   s->grav[0] = params[5]; s->grav[1] = params[6]; s->grav[2] = params[7];
   s->m = (int)solver[0]; s->eps_rel = solver[1]; s->eps_abs = solver[2];
   s->kmax_fwd = (int)solver[3]; s->kmax_bwd = (int)solver[4]; s->eps_adj = solver[5]; s->eps_tr = solver[6];
+  s->energy = (int)solver[10];
 
   /* rest shape: tets reoriented to det D_m > 0; V_e = det/6; Bhat from D_m^-1 */
   s->Bhat = (double*)malloc(sizeof(double) * 12 * ne);
@@ -726,6 +878,16 @@ static void local_rhs_stats(const or_scene* s, const double* q, double* b_all, i
   for (int e = 0; e < s->ne; ++e) {
     double F[9], U[9], V[9], sF[3], ss[3], T[9], P[9];
     element_F(s, e, q, F);
+    if (s->energy == 1) {
+      /* corotated + volume: 2 mu_e V_e G^T R + lam_e V_e G^T P_vol */
+      composite_parts c;
+      double cv[12];
+      composite_eval(F, &c, 0);
+      element_contrib(s, e, 2.0 * s->mu[e] * s->vol[e], c.R, ctb + 12 * (size_t)e);
+      element_contrib(s, e, s->lam[e] * s->vol[e], c.Pv, cv);
+      for (int i = 0; i < 12; ++i) ctb[12 * (size_t)e + i] += cv[i];
+      continue;
+    }
     or_svd3(F, U, sF, V);
     int it = or_prox_stretch(sF, s->mu_bar, s->lam_bar, s->k_bar, ss);
     if (it < 0) { ncap++; it = -it; }
@@ -754,6 +916,19 @@ void or_apply_K(const or_scene* s, const double* q, double tau, const double* x_
   for (int e = 0; e < s->ne; ++e) {
     double F[9], U[9], V[9], sF[3], ss[3], D[9], c1[3], c2[3], dF[9], dP[9];
     element_F(s, e, q, F);
+    if (s->energy == 1) {
+      composite_parts c;
+      const double zero[9] = {0};
+      double dR[9], cv[12];
+      composite_eval(F, &c, 1);
+      element_F(s, e, xf, dF);
+      prox_diff_apply(c.U, c.V, zero, c.c1r, c.c2r, dF, dR);
+      prox_diff_apply(c.U, c.V, c.Dv, c.c1v, c.c2v, dF, dP);
+      element_contrib(s, e, 2.0 * s->mu[e] * s->vol[e], dR, ctb + 12 * (size_t)e);
+      element_contrib(s, e, s->lam[e] * s->vol[e], dP, cv);
+      for (int i = 0; i < 12; ++i) ctb[12 * (size_t)e + i] += cv[i];
+      continue;
+    }
     or_svd3(F, U, sF, V);
     or_prox_stretch(sF, s->mu_bar, s->lam_bar, s->k_bar, ss);
     prox_diff_coeffs(sF, ss, s->mu_bar, s->lam_bar, s->k_bar, tau, D, c1, c2);
@@ -770,13 +945,25 @@ void or_apply_K(const or_scene* s, const double* q, double tau, const double* x_
 
 /* Per-element filtered prox differential at q (Alg. 2 element loop), stored
  * as U, V, D, c1, c2 (33 numbers per element) and applied to many vectors. */
+#define KST 36 /* U, V, D, c1, c2 (33); the composite adds the rotation's c2 */
 static double* prox_diff_all(const or_scene* s, const double* q, double tau) {
-  double* st = (double*)malloc(sizeof(double) * 33 * (size_t)s->ne);
+  double* st = (double*)calloc(KST * (size_t)(s->ne > 0 ? s->ne : 1), sizeof(double));
 #pragma omp parallel for schedule(static)
   for (int e = 0; e < s->ne; ++e) {
     double F[9], sF[3], ss[3];
-    double* c = st + 33 * (size_t)e;
+    double* c = st + KST * (size_t)e;
     element_F(s, e, q, F);
+    if (s->energy == 1) {
+      composite_parts p;
+      composite_eval(F, &p, 1);
+      memcpy(c, p.U, sizeof(p.U));
+      memcpy(c + 9, p.V, sizeof(p.V));
+      memcpy(c + 18, p.Dv, sizeof(p.Dv));
+      memcpy(c + 27, p.c1v, sizeof(p.c1v));
+      memcpy(c + 30, p.c2v, sizeof(p.c2v));
+      memcpy(c + 33, p.c2r, sizeof(p.c2r));
+      continue;
+    }
     or_svd3(F, c, sF, c + 9);
     or_prox_stretch(sF, s->mu_bar, s->lam_bar, s->k_bar, ss);
     prox_diff_coeffs(sF, ss, s->mu_bar, s->lam_bar, s->k_bar, tau, c + 18, c + 27, c + 30);
@@ -792,10 +979,20 @@ static void apply_K_stored(const or_scene* s, const double* st, const double* x_
   double* ctb = (double*)malloc(sizeof(double) * 12 * (size_t)(s->ne > 0 ? s->ne : 1));
 #pragma omp parallel for schedule(static)
   for (int e = 0; e < s->ne; ++e) {
-    const double* c = st + 33 * (size_t)e;
+    const double* c = st + KST * (size_t)e;
     double dF[9], dP[9];
     element_F(s, e, xf, dF);
     prox_diff_apply(c, c + 9, c + 18, c + 27, c + 30, dF, dP);
+    if (s->energy == 1) {
+      /* 2 mu_e V_e G^T dR + lam_e V_e G^T dP_vol (the rotation's D and c1 vanish) */
+      const double zero[9] = {0};
+      double dR[9], cv[12];
+      prox_diff_apply(c, c + 9, zero, zero, c + 33, dF, dR);
+      element_contrib(s, e, 2.0 * s->mu[e] * s->vol[e], dR, ctb + 12 * (size_t)e);
+      element_contrib(s, e, s->lam[e] * s->vol[e], dP, cv);
+      for (int i = 0; i < 12; ++i) ctb[12 * (size_t)e + i] += cv[i];
+      continue;
+    }
     element_contrib(s, e, s->w[e] * s->vol[e], dP, ctb + 12 * (size_t)e);
   }
   scatter_contribs(s, ctb, y_all);
@@ -1276,7 +1473,8 @@ static int step_backward_impl(const or_scene* s, const double* q_t, const double
   /* trust-region ratio on the last fixed-point increment, Eqs. tr_step,
    * tr_decreases, tr_ratio, tr_rule.  READING: Phi(q*-1) - Phi(q*) is summed as
    * per-vertex and per-element differences (the same sum, regrouped). */
-  double dphi_act = 0.0;
+  double dphi_act = 0.0, dphi_mod = 0.0, rho = 1.0, tau = 0.0;
+  if (s->energy == 0) { /* Alg. 2: the ratio and its filter belong to the Neo-Hookean prox */
   for (int v = 0; v < nv; ++v)
     for (int ax = 0; ax < 3; ++ax) {
       int i = 3 * v + ax;
@@ -1297,10 +1495,11 @@ static int step_backward_impl(const or_scene* s, const double* q_t, const double
   for (int v = 0; v < nv; ++v)
     for (int ax = 0; ax < 3; ++ax) dq[3 * v + ax] = s->fidx[v] >= 0 ? q_star[3 * v + ax] - q_star_m1[3 * v + ax] : 0.0;
   or_apply_A(s, dq, Adq);
-  double dphi_mod = 0.5 * fabs(dot_free(s, dq, Adq));
-  double rho = dphi_mod < 1e-12 ? 1.0 : dphi_act / dphi_mod;
-  double tau = fabs(rho - 1.0) <= s->eps_tr ? 0.5 : 1.0;
+  dphi_mod = 0.5 * fabs(dot_free(s, dq, Adq));
+  rho = dphi_mod < 1e-12 ? 1.0 : dphi_act / dphi_mod;
+  tau = fabs(rho - 1.0) <= s->eps_tr ? 0.5 : 1.0;
   if (tau_force >= 0.0) tau = tau_force;
+  }
   /* adjoint: (A - K) mu = q^bar (Eqs. adjoint_system, Rqq, db_dq with the
    * filtered prox differential; A, K symmetric).  READING: solved to
    * tolerance, by the fixed-point iteration mu <- A^-1 (q^bar + K mu), or, for
@@ -1446,14 +1645,27 @@ static int step_backward_impl(const or_scene* s, const double* q_t, const double
     double qd[12];
     element_F(s, e, mu, Gm);
     element_F(s, e, q_star, F);
+    double gw = 0.0;
+    if (s->energy == 1) {
+      /* dL/dlog E_e = 2 mu_e V_e <G mu, R - F> + lam_e V_e <G mu, P_vol - F> + the beta term */
+      composite_parts c;
+      composite_eval(F, &c, 0);
+      double gr = 0.0, gv = 0.0;
+      for (int i = 0; i < 9; ++i) {
+        gr += Gm[i] * (c.R[i] - F[i]);
+        gv += Gm[i] * (c.Pv[i] - F[i]);
+      }
+      gw = (2.0 * s->mu[e] * gr + s->lam[e] * gv) * s->vol[e];
+    } else {
     or_svd3(F, U, sF, V);
     or_prox_stretch(sF, s->mu_bar, s->lam_bar, s->k_bar, ss);
     for (int i = 0; i < 3; ++i)
       for (int j = 0; j < 3; ++j) T[3 * i + j] = U[3 * i + j] * ss[j];
     mat3_mul_nt(T, V, P);
-    double gw = 0.0;
     for (int i = 0; i < 9; ++i) gw += Gm[i] * (P[i] - F[i]);
     gw *= s->vol[e];
+    gw = s->w[e] * gw;
+    }
     /* G (q_t - q*) */
     for (int i = 0; i < 9; ++i) Fd[i] = 0.0;
     for (int a = 0; a < 4; ++a) {
@@ -1467,7 +1679,7 @@ static int step_backward_impl(const or_scene* s, const double* q_t, const double
     double gb = 0.0;
     for (int i = 0; i < 9; ++i) gb += Gm[i] * Fd[i];
     gb *= s->vol[e] / h;
-    ge[e] = s->w[e] * gw + s->beta[e] * gb;
+    ge[e] = gw + s->beta[e] * gb;
     /* B_beta mu = sum_e beta_e V_e G^T G mu */
     element_contrib(s, e, s->beta[e] * s->vol[e], Gm, ctb + 12 * (size_t)e);
   }

@@ -18,7 +18,8 @@ typedef struct or_scene or_scene;
 
 /* params: nu, rho, alpha, beta0, h, gx, gy, gz
  * solver: m (AA window), eps_rel, eps_abs, kmax_fwd, kmax_bwd, eps_adj, eps_tr,
- *         then mu_bar, lam_bar, mu_ref (frozen if mu_bar > 0, else computed) */
+ *         then mu_bar, lam_bar, mu_ref (frozen if mu_bar > 0, else computed),
+ *         then the energy model (0: Neo-Hookean prox; 1: corotated + volume) */
 or_scene* or_scene_create(int nv, int ne, const double* X, const int* tets, const unsigned char* pinned,
                           const double* logE, const double* params, const double* solver);
 void or_scene_destroy(or_scene* s);
@@ -36,6 +37,13 @@ int or_prox_stretch(const double sF[3], double mu, double lam, double k, double 
 void or_prox_map(const double F[9], double mu, double lam, double k, double P[9]);
 void or_prox_jacobian(const double F[9], double mu, double lam, double k, double tau, double J[81]);
 double or_psi_nh(const double F[9], double mu, double lam);
+/* corotated + volume composite (Sec. 4.1, Sec. 7.2): the volume step's stretches
+ * (closest point with s1 s2 s3 = 1), its stretch Jacobian, and the composite
+ * projection (2 mu R + lam P_vol) / (2 mu + lam) with its 9x9 Jacobian */
+int or_volume_project(const double sF[3], double s[3]);
+void or_volume_diff(const double sF[3], double D[9]);
+void or_composite_map(const double F[9], double mu, double lam, double P[9]);
+void or_composite_jacobian(const double F[9], double mu, double lam, double J[81]);
 void or_sym3_eig(const double H[9], double kappa[3], double Q[9]);
 void or_tr_filter(const double H[9], double tau, double k, double Ht[9], double Dinv[9]);
 int or_aa_step(int n, int m, double* Hq, double* Hg, int* hn, const double* q, const double* qhat,

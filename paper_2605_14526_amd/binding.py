@@ -30,7 +30,8 @@ EXPORTED = ["pd_scene_create", "pd_scene_destroy", "pd_scene_set_material", "pd_
             "pd_mpn_create", "pd_mpn_destroy", "pd_mpn_info", "pd_mpn_init_params", "pd_mpn_set_params",
             "pd_mpn_get_params", "pd_mpn_get_grads", "pd_mpn_set_output_scale", "pd_mpn_forward", "pd_mpn_loss_grad",
             "pd_mpn_adam_step", "pd_batch_create", "pd_batch_destroy", "pd_batch_config", "pd_batch_step_forward",
-            "pd_batch_step_backward", "pd_scene_set_obstacles", "pd_contact_rows", "pd_last_error"]
+            "pd_batch_step_backward", "pd_scene_set_obstacles", "pd_contact_rows", "pd_last_error",
+            "pd_scene_factor_nnz", "pd_batch_kernel_timer", "pd_batch_kernel_timer_read"]
 
 
 class pd_mesh_desc(ctypes.Structure):
@@ -40,7 +41,7 @@ class pd_mesh_desc(ctypes.Structure):
 
 class pd_material_desc(ctypes.Structure):
     _fields_ = [("log_E", ctypes.c_void_p), ("nu", ctypes.c_double), ("rho", ctypes.c_double),
-                ("alpha", ctypes.c_double), ("beta0", ctypes.c_double)]
+                ("alpha", ctypes.c_double), ("beta0", ctypes.c_double), ("energy", ctypes.c_int32)]
 
 
 class pd_solver_opts(ctypes.Structure):
@@ -120,6 +121,9 @@ def lib() -> ctypes.CDLL:
     L.pd_batch_step_backward.argtypes = [vp, vp, vp, vp, vp, vp, vp, vp, vp, vp]
     L.pd_scene_set_obstacles.argtypes = [vp, i32, vp, i32, vp, dbl, i32, dbl]
     L.pd_contact_rows.argtypes = [vp, vp, vp, vp, vp, vp, i32]
+    L.pd_scene_factor_nnz.argtypes = [vp, vp]
+    L.pd_batch_kernel_timer.argtypes = [vp, i32]
+    L.pd_batch_kernel_timer_read.argtypes = [vp, vp, vp, vp]
     L.pd_last_error.restype = ctypes.c_char_p
     for name in EXPORTED:
         getattr(L, name)
@@ -151,7 +155,7 @@ class Scene:
 
     def __init__(self, X, tets, pinned, log_E, nu, rho, alpha, beta0, h, gravity=(0.0, 0.0, 0.0), aa_window=1,
                  eps_rel=1e-6, eps_abs=1e-12, kmax_fwd=1000, kmax_bwd=1000, eps_adj=1e-6, eps_tr=0.1,
-                 adj_method=0, max_sub=0, iters_per_check=0, adj_warm=0, fwd_start=0):
+                 adj_method=0, max_sub=0, iters_per_check=0, adj_warm=0, fwd_start=0, energy=0):
         L = lib()
         self._X = np.ascontiguousarray(X, dtype=np.float64)
         self._tets = np.ascontiguousarray(tets, dtype=np.int32)
@@ -161,7 +165,7 @@ class Scene:
         self.n_tets = int(self._tets.shape[0])
         mesh = pd_mesh_desc(self.n_verts, self.n_tets, self._X.ctypes.data, self._tets.ctypes.data,
                             self._pinned.ctypes.data)
-        mat = pd_material_desc(self._logE.ctypes.data, nu, rho, alpha, beta0)
+        mat = pd_material_desc(self._logE.ctypes.data, nu, rho, alpha, beta0, int(energy))
         opts = pd_solver_opts(h, (ctypes.c_double * 3)(*gravity), aa_window, eps_rel, eps_abs, kmax_fwd, kmax_bwd,
                               eps_adj, eps_tr, adj_method, max_sub, iters_per_check, adj_warm, fwd_start)
         self.h = float(h)
@@ -172,7 +176,7 @@ class Scene:
 
     @classmethod
     def from_scene(cls, sc, **kw):
-        args = dict(aa_window=sc.aa_window, eps_rel=sc.eps_rel, eps_abs=sc.eps_abs)
+        args = dict(aa_window=sc.aa_window, eps_rel=sc.eps_rel, eps_abs=sc.eps_abs, energy=getattr(sc, "energy", 0))
         contact = kw.pop("contact", {})
         args.update(kw)
         g = cls(sc.X, sc.tets, sc.pinned, sc.log_E, sc.nu, sc.rho, sc.alpha, sc.beta0, sc.h,
@@ -295,6 +299,12 @@ class Scene:
                                    dphi_act=st.dphi_act, dphi_mod=st.dphi_mod, residual=st.residual, rc=rc,
                                    n_active=st.n_active)
         return gq_t, gv_t, gf_ext, g_logE, self.last_bwd_stats
+
+    def factor_nnz(self) -> float:
+        """Entries of a nested-dissection sparse Cholesky factor of A~ (the solve's algorithmic size)."""
+        n = ctypes.c_double()
+        check(lib().pd_scene_factor_nnz(self.ptr, ctypes.byref(n)), "pd_scene_factor_nnz")
+        return n.value
 
     def vertex_logw(self) -> np.ndarray:
         """Per-vertex mean log(2 mu_e + lam_e) minus its mean (the warm-start network's material feature)."""
@@ -451,6 +461,16 @@ class Batch:
                                     int(use_graph)), "pd_batch_config")
         self.cfg = dict(block_local=block_local, block_applyK=block_applyK, iters_per_check=iters_per_check,
                         use_graph=use_graph)
+
+    def kernel_timer(self, kernel: int):
+        check(lib().pd_batch_kernel_timer(self.ptr, int(kernel)), "pd_batch_kernel_timer")
+
+    def kernel_timer_read(self):
+        """(summed launch ms, launches, algorithmic bytes of the work done)."""
+        ms, n, b = ctypes.c_double(), ctypes.c_int64(), ctypes.c_double()
+        check(lib().pd_batch_kernel_timer_read(self.ptr, ctypes.byref(ms), ctypes.byref(n), ctypes.byref(b)),
+              "pd_batch_kernel_timer_read")
+        return ms.value, n.value, b.value
 
     def step_forward(self, q_t, v_t, f_ext=None, q0=None, q_next=None, v_next=None, ckpt=None):
         import torch

@@ -43,7 +43,7 @@ def build(verbose: bool = False) -> str:
         return obj
 
     # the sources compile independently (one hipcc process each)
-    with concurrent.futures.ThreadPoolExecutor(max_workers=min(len(SOURCES), 4)) as ex:
+    with concurrent.futures.ThreadPoolExecutor(max_workers=min(len(SOURCES), 6)) as ex:
         objs = list(ex.map(compile_one, SOURCES))
     tmp = LIB + ".tmp"
     cmd = [hipcc(), f"--offload-arch={ARCH}", "-shared", "-fPIC", "-o", tmp] + objs

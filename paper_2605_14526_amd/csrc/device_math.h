@@ -276,6 +276,9 @@ __device__ __forceinline__ int prox_stretch(const double sF[3], double mu, doubl
 // pair coefficients c1 (symmetric part) and c2 (skew part) of the SVD
 // differential.  D is returned packed: D00 D11 D22 D01 D02 D12.
 // ---------------------------------------------------------------------------
+__device__ __forceinline__ void pair_coeffs(const double sF[3], const double ss[3], const double D[6], double c1[3],
+                                            double c2[3]);
+
 __device__ __forceinline__ void prox_diff(const double sF[3], const double ss[3], double mu, double lam, double k,
                                           double tau, double D[6], double c1[3], double c2[3]) {
   const double l = log(ss[0] * ss[1] * ss[2]);
@@ -299,6 +302,15 @@ __device__ __forceinline__ void prox_diff(const double sF[3], const double ss[3]
     const int i = I0[t], j = I1[t];
     D[t] = Q[3 * i] * inv[0] * Q[3 * j] + Q[3 * i + 1] * inv[1] * Q[3 * j + 1] + Q[3 * i + 2] * inv[2] * Q[3 * j + 2];
   }
+  pair_coeffs(sF, ss, D, c1, c2);
+}
+
+// Pair coefficients of the SVD differential of an isotropic stretch map
+// sF -> ss with packed stretch Jacobian D: c1 = (ss_i - ss_j)/(sF_i - sF_j)
+// (the symmetric limit (D_ii + D_jj)/2 - D_ij for coinciding stretches),
+// c2 = (ss_i + ss_j)/(sF_i + sF_j) (denominator kept away from zero).
+__device__ __forceinline__ void pair_coeffs(const double sF[3], const double ss[3], const double D[6], double c1[3],
+                                            double c2[3]) {
   const double sfmax = fmax(1.0, fmax(fabs(sF[0]), fmax(fabs(sF[1]), fabs(sF[2]))));
   const int P0[3] = {0, 0, 1}, P1[3] = {1, 2, 2}, Dii[3] = {0, 0, 1}, Djj[3] = {1, 2, 2}, Dij[3] = {3, 4, 5};
 #pragma unroll
@@ -313,6 +325,84 @@ __device__ __forceinline__ void prox_diff(const double sF[3], const double ss[3]
     if (fabs(den) < 1e-8) den = den < 0.0 ? -1e-8 : 1e-8;
     c2[pr] = (ss[i] + ss[j]) / den;
   }
+}
+
+// ---------------------------------------------------------------------------
+// Volume step of the corotated + volume composite (Sec. 4.1, Sec. 7.2): the
+// closest point sv of sF with sv1 sv2 sv3 = 1.  Stationarity gives
+// sv_i (sv_i - sF_i) = nu, so sv_i = (sF_i +- sqrt(sF_i^2 + 4 nu)) / 2.  All
+// roots take the plus sign unless even at the smallest admissible nu their
+// product exceeds one; then the root of the smallest stretch takes the minus
+// sign (nu between that bound and 0).  f(nu) = sum ln sv_i(nu) is brought to
+// zero by Newton's method kept inside a sign-change bracket, starting from
+// the tet's previous multiplier `nu` (updated on return).
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ double vol_eval(const double sF[3], double nu, int minus, double sv[3], double a[3]) {
+  double f = 0.0;
+#pragma unroll
+  for (int i = 0; i < 3; ++i) {
+    const double r = sqrt(fmax(sF[i] * sF[i] + 4.0 * nu, 0.0));
+    const double sg = (i == minus) ? -1.0 : 1.0;
+    sv[i] = 0.5 * (sF[i] + sg * r);
+    a[i] = sg / fmax(r, 1e-300);  // d sv_i / d nu = 1 / (2 sv_i - sF_i)
+    f += log(sv[i]);
+  }
+  return f;
+}
+
+__device__ __forceinline__ void volume_project(const double sF[3], double& nu, double sv[3]) {
+  const bool pos = sF[0] > 0.0 && sF[1] > 0.0 && sF[2] > 0.0;
+  int imin = 0;
+#pragma unroll
+  for (int i = 1; i < 3; ++i)
+    if (fabs(sF[i]) < fabs(sF[imin])) imin = i;
+  const double lo = pos ? -0.25 * sF[imin] * sF[imin] : 0.0;
+  double a[3];
+  int minus = -1;
+  double l = lo, r;
+  if (pos && vol_eval(sF, lo, -1, sv, a) > 0.0) {
+    minus = imin;  // f decreases from f(lo) > 0 to -inf at nu = 0
+    r = 0.0;
+  } else {
+    r = fmax(1.0, 2.0 * fabs(lo) + 1.0);
+    for (int k = 0; k < 64 && vol_eval(sF, r, -1, sv, a) < 0.0; ++k) r *= 4.0;
+  }
+  // on either branch f(l) and f(r) have opposite signs; track them as "low" and "high"
+  const double dir = (minus < 0) ? 1.0 : -1.0;  // f increasing (plus) or decreasing (mixed) in nu
+  double x = (nu > l && nu < r) ? nu : 0.5 * (l + r);
+  for (int it = 0; it < 80; ++it) {
+    const double f = vol_eval(sF, x, minus, sv, a);
+    if (f == 0.0) break;
+    if (dir * f < 0.0) l = x; else r = x;
+    double dfdnu = 0.0;
+#pragma unroll
+    for (int i = 0; i < 3; ++i) dfdnu += a[i] / sv[i];
+    double xn = x - f / dfdnu;
+    if (!(xn > l && xn < r)) xn = 0.5 * (l + r);
+    if (xn == x || r - l <= 1e-16 * fmax(1.0, fabs(x))) { x = xn; break; }
+    x = xn;
+  }
+  nu = x;
+  vol_eval(sF, x, minus, sv, a);
+}
+
+// Stretch Jacobian of the volume step (packed D00 D11 D22 D01 D02 D12):
+// D_ij = a_i sv_i delta_ij - a_i a_j / c, a_i = 1/(2 sv_i - sF_i),
+// c = sum_k a_k / sv_k (from differentiating sv_i (sv_i - sF_i) = nu and
+// sum ln sv_i = 0).
+__device__ __forceinline__ void volume_diff(const double sF[3], const double sv[3], double D[6]) {
+  double a[3], c = 0.0;
+#pragma unroll
+  for (int i = 0; i < 3; ++i) {
+    a[i] = 1.0 / (2.0 * sv[i] - sF[i]);
+    c += a[i] / sv[i];
+  }
+  D[0] = a[0] * sv[0] - a[0] * a[0] / c;
+  D[1] = a[1] * sv[1] - a[1] * a[1] / c;
+  D[2] = a[2] * sv[2] - a[2] * a[2] / c;
+  D[3] = -a[0] * a[1] / c;
+  D[4] = -a[0] * a[2] / c;
+  D[5] = -a[1] * a[2] / c;
 }
 
 // dP = U B V^T with B the differential of the stretches in the (U, V) frame

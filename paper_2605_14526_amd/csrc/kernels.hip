@@ -313,8 +313,7 @@ __device__ __forceinline__ void store_GtP(const TetData& T, double* __restrict__
 
 // The warm start of the tet's next SVD and prox Newton: the rotation V,
 // re-orthonormalised (Gram-Schmidt on its columns), and the ratios s*/sF.
-__device__ __forceinline__ void store_warm(const ElemArgs& E, int t, const double V[9], const double sF[3],
-                                           const double ss[3]) {
+__device__ __forceinline__ void store_rot(const ElemArgs& E, int t, const double V[9]) {
   double c0[3] = {V[0], V[3], V[6]}, c1[3] = {V[1], V[4], V[7]};
   double n0 = rsqrt(c0[0] * c0[0] + c0[1] * c0[1] + c0[2] * c0[2]);
   c0[0] *= n0; c0[1] *= n0; c0[2] *= n0;
@@ -326,8 +325,21 @@ __device__ __forceinline__ void store_warm(const ElemArgs& E, int t, const doubl
   const double Vn[9] = {c0[0], c1[0], c2[0], c0[1], c1[1], c2[1], c0[2], c1[2], c2[2]};
 #pragma unroll
   for (int j = 0; j < 9; ++j) E.Vw[(size_t)j * E.ne + t] = Vn[j];
+}
+
+// warm start of the next SVD and prox Newton of this tet: its rotation V and
+// the stretch ratios s*/sF (Neo-Hookean prox), or the volume step's
+// multiplier (corotated + volume composite)
+__device__ __forceinline__ void store_warm(const ElemArgs& E, int t, const double V[9], const double sF[3],
+                                           const double ss[3]) {
+  store_rot(E, t, V);
 #pragma unroll
   for (int j = 0; j < 3; ++j) E.rw[(size_t)j * E.ne + t] = (sF[j] > 1e-12) ? ss[j] / sF[j] : 0.0;
+}
+
+__device__ __forceinline__ void store_warm_nu(const ElemArgs& E, int t, const double V[9], double nu) {
+  store_rot(E, t, V);
+  E.rw[t] = nu;
 }
 
 // ---------------------------------------------------------------- Anderson mixing
@@ -532,10 +544,27 @@ __device__ __forceinline__ void b_local(ElemArgs E, StepState St, RedArgs R, con
 #pragma unroll
     for (int j = 0; j < 9; ++j) V[j] = (j % 4 == 0) ? 1.0 : 0.0;
   svd3(F, U, sF, V, warm);
+  double P[9];
+  if (E.energy == 1) {
+    // corotated + volume: 2 mu_e V_e R + lam_e V_e P_vol = U diag(2 mu_e V_e + lam_e V_e sv) V^T
+    double nu = rt[0], sv[3];
+    volume_project(sF, nu, sv);
+    const double m2 = 2.0 * E.muV[t], lv = E.lamV[t];
+    double sw[3];
+#pragma unroll
+    for (int j = 0; j < 3; ++j) sw[j] = m2 + lv * sv[j];
+#pragma unroll
+    for (int i = 0; i < 3; ++i)
+#pragma unroll
+      for (int j = 0; j < 3; ++j)
+        P[3 * i + j] = U[3 * i] * sw[0] * V[3 * j] + U[3 * i + 1] * sw[1] * V[3 * j + 1] + U[3 * i + 2] * sw[2] * V[3 * j + 2];
+    store_GtP(T, St.contrib, E.ninc, P);
+    store_warm_nu(E, t, V, nu);
+    return;
+  }
   const int nit = prox_stretch(sF, E.mu_bar, E.lam_bar, E.k_bar, ss, rt);
   // cap hit: every writer stores the same value, so plain stores suffice
   if (newton_cap && nit >= kNewtonCap) *newton_cap = 1;
-  double P[9];
 #pragma unroll
   for (int i = 0; i < 3; ++i)
 #pragma unroll
@@ -1641,9 +1670,26 @@ __global__ void __launch_bounds__(kBlock) k_bwd_elem(ElemArgs E, VertArgs Vx, Re
   svd3(F, U, sF, V, warm);
 #pragma unroll
   for (int j = 0; j < 3; ++j) rt[j] = E.rw[(size_t)j * E.ne + t];
-  prox_stretch(sF, E.mu_bar, E.lam_bar, E.k_bar, ss, rt);
   double D[6], c1[3], c2[3];
-  prox_diff(sF, ss, E.mu_bar, E.lam_bar, E.k_bar, tau, D, c1, c2);
+  double nu = rt[0];
+  if (E.energy == 1) {
+    // corotated + volume, per unit of w_e = 2 mu_e + lam_e: the stretch map
+    // ss = th_r + th_v sv (th_r = 2 mu_e / w_e, th_v = lam_e / w_e), whose
+    // Jacobian is th_v D_vol (the rotation's stretches are constant); no
+    // trust-region filter (Alg. 2 applies it to the Neo-Hookean prox)
+    double sv[3], Dv[6];
+    volume_project(sF, nu, sv);
+    volume_diff(sF, sv, Dv);
+    const double wv = E.wV[t], thr = 2.0 * E.muV[t] / wv, thv = E.lamV[t] / wv;
+#pragma unroll
+    for (int j = 0; j < 3; ++j) ss[j] = thr + thv * sv[j];
+#pragma unroll
+    for (int j = 0; j < 6; ++j) D[j] = thv * Dv[j];
+    pair_coeffs(sF, ss, D, c1, c2);
+  } else {
+    prox_stretch(sF, E.mu_bar, E.lam_bar, E.k_bar, ss, rt);
+    prox_diff(sF, ss, E.mu_bar, E.lam_bar, E.k_bar, tau, D, c1, c2);
+  }
   const size_t ne = E.ne;
 #pragma unroll
   for (int j = 0; j < 9; ++j) {
@@ -1659,7 +1705,10 @@ __global__ void __launch_bounds__(kBlock) k_bwd_elem(ElemArgs E, VertArgs Vx, Re
     jac[(30 + j) * ne + t] = ss[j];
   }
   // a reverse sweep visits q* of neighbouring steps: start the next one from here
-  store_warm(E, t, V, sF, ss);
+  if (E.energy == 1)
+    store_warm_nu(E, t, V, nu);
+  else
+    store_warm(E, t, V, sF, ss);
 }
 
 __device__ __forceinline__ void load_jac(const double* __restrict__ jac, int ne, int t, double U[9], double V[9],

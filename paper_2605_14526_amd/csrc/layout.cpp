@@ -152,4 +152,50 @@ void build_layout(int nv, int ne, const double* X, const int32_t* tets, const ui
   std::stable_sort(L.tet_lib2orig.begin(), L.tet_lib2orig.end(), [&](int a, int b) { return key[a] < key[b]; });
 }
 
+double factor_nnz_nd(int nv, int ne, const double* X, const int32_t* tets, const uint8_t* pinned) {
+  Layout L;
+  build_layout(nv, ne, X, tets, pinned, 16, L);
+  const int n = L.nf;
+  Graph g = free_graph(nv, ne, tets, pinned);
+  // adjacency in elimination order, lower part only (columns j < i of row i)
+  std::vector<int> ptr(n + 1, 0), adj;
+  adj.reserve(g.adj.size() / 2 + 1);
+  for (int i = 0; i < n; ++i) {
+    const int v = L.lib2orig[i];
+    for (int k = g.ptr[v]; k < g.ptr[v + 1]; ++k) {
+      const int j = L.orig2lib[g.adj[k]];
+      if (j < i) adj.push_back(j);
+    }
+    ptr[i + 1] = (int)adj.size();
+  }
+  // elimination tree (with path compression through `anc`)
+  std::vector<int> parent(n, -1), anc(n, -1);
+  for (int i = 0; i < n; ++i)
+    for (int k = ptr[i]; k < ptr[i + 1]; ++k) {
+      int r = adj[k];
+      while (anc[r] != -1 && anc[r] != i) {
+        const int t = anc[r];
+        anc[r] = i;
+        r = t;
+      }
+      if (anc[r] == -1) {
+        anc[r] = i;
+        parent[r] = i;
+      }
+    }
+  // row counts: row i of L holds the etree nodes on the paths from the
+  // columns of A's row i up to i
+  std::vector<int> mark(n, -1);
+  double nnz = n;
+  for (int i = 0; i < n; ++i) {
+    mark[i] = i;
+    for (int k = ptr[i]; k < ptr[i + 1]; ++k)
+      for (int r = adj[k]; r != -1 && mark[r] != i; r = parent[r]) {
+        mark[r] = i;
+        nnz += 1.0;
+      }
+  }
+  return nnz;
+}
+
 }  // namespace pdhot

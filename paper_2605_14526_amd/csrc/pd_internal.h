@@ -8,6 +8,8 @@
 #include <string>
 #include <vector>
 
+typedef struct pd_scene pd_scene;
+
 namespace pdhot {
 
 constexpr int kBlock = 256;      // threads per workgroup for every kernel
@@ -30,6 +32,13 @@ struct Layout {
 // nested dissection by coordinate bisection with vertex separators
 void build_layout(int nv, int ne, const double* X, const int32_t* tets, const uint8_t* pinned, int max_sub,
                   Layout& L);
+
+// Entries (diagonal included) of the Cholesky factor of A~ over the free
+// vertices under a deep nested-dissection order (the same coordinate
+// bisection taken down to subdomains of a few vertices): the size of the
+// sparse factor the method's triangular solves would sweep.
+double factor_nnz_nd(int nv, int ne, const double* X, const int32_t* tets, const uint8_t* pinned);
+
 
 // ---------------------------------------------------------------- device scene
 // Couplings of interface row i with the subdomains s it borders (row p of
@@ -107,6 +116,7 @@ struct Scene {
   std::vector<uint8_t> pinned;
   std::vector<double> logE;
   double nu = 0, rho = 0, alpha = 0, beta0 = 0;
+  int energy = 0;  // 0: Neo-Hookean proximal map; 1: corotated + volume composite
   double h = 0, grav[3] = {0, 0, 0};
   int m = 0, kmax_fwd = 1000, kmax_bwd = 1000, adj_method = 0, max_sub = 0, iters_per_check = 0;
   double eps_rel = 1e-6, eps_abs = 1e-12, eps_adj = 1e-6, eps_tr = 0.1;
@@ -114,6 +124,7 @@ struct Scene {
   int last_fwd_iters = 4, last_adj_iters = 8;
   Layout L;
   double mu_bar = 0, lam_bar = 0, k_bar = 0, mu_ref = 0;
+  double nnz_L = 0;  // entries of a nested-dissection Cholesky factor of A~ (algorithmic solve bytes)
   // means held across refactorizations (pd_scene_freeze_means): mu_bar, lam_bar, mu_ref
   bool frozen = false;
   double frozen_means[3] = {0, 0, 0};

@@ -266,13 +266,18 @@ void free_device(Scene& S) {
 }
 
 // ---------------------------------------------------------------- kernel timer
-enum { kKLocal = 0, kKGather = 1, kKTop = 2, kKBottom = 3, kKEb = 4, kKApplyK = 5, kKCount = 6 };
+enum { kKLocal = 0, kKGather = 1, kKTop = 2, kKBottom = 3, kKEb = 4, kKApplyK = 5, kKSolve = 6, kKCount = 7 };
+
+// the timer of `which` takes launches of kernel `id` (kKSolve: the three
+// stages of one global solve)
+inline bool kt_match(int which, int id) {
+  return which == id || (which == kKSolve && (id == kKEb || id == kKTop || id == kKBottom));
+}
 constexpr int kTimerPairs = 1024;
 
 // Adds the durations of the pending event pairs in launch order; without
 // `all`, it stops at the first pair whose kernel has not finished.
-void kt_flush(Scene& S, bool all = false) {
-  KernelTimer& T = S.kt;
+void kt_flush(KernelTimer& T, bool all = false) {
   while (T.used > 0) {
     const int i = T.head;
     if (!all) {
@@ -289,12 +294,13 @@ void kt_flush(Scene& S, bool all = false) {
   }
 }
 
-inline void kt_begin(Scene& S, int id, hipStream_t st) {
-  KernelTimer& T = S.kt;
-  if (T.which != id) return;
+void kt_flush(Scene& S, bool all = false) { kt_flush(S.kt, all); }
+
+inline void kt_begin(KernelTimer& T, int id, hipStream_t st) {
+  if (!kt_match(T.which, id)) return;
   if (T.used == kTimerPairs) {
     PD_HIP(hipStreamSynchronize(st));
-    kt_flush(S, true);
+    kt_flush(T, true);
   }
   const int i = (T.head + T.used) % kTimerPairs;
   arm_launch_events(T.ev[2 * i], T.ev[2 * i + 1]);
@@ -321,15 +327,19 @@ bool wait_signal(Scene& S, int slot, int seq, hipStream_t st) {
   }
 }
 
-inline void kt_end(Scene& S, int id, hipStream_t st) {
-  KernelTimer& T = S.kt;
-  if (T.which != id) return;
+inline void kt_end(KernelTimer& T, int id, hipStream_t st) {
+  if (!kt_match(T.which, id)) return;
   (void)st;
   if (launch_events_used()) T.used++;  // the launcher may have skipped an empty launch
 }
 
+inline void kt_begin(Scene& S, int id, hipStream_t st) { kt_begin(S.kt, id, st); }
+inline void kt_end(Scene& S, int id, hipStream_t st) { kt_end(S.kt, id, st); }
+
+// working units of the timed kernel: launches that did work, or for kKSolve
+// the solves (counted once, with the interface right-hand side stage)
 inline void kt_work(Scene& S, int id, long long n) {
-  if (S.kt.which == id) S.kt.working += n;
+  if (S.kt.which == id || (S.kt.which == kKSolve && id == kKEb)) S.kt.working += n;
 }
 
 void kt_destroy(Scene& S) {
@@ -352,6 +362,7 @@ ElemArgs elem_args(const Scene& S) {
   E.tv = S.tv; E.tinc = S.tinc; E.Bm = S.Bm; E.wV = S.wV; E.bV = S.bV; E.muV = S.muV; E.lamV = S.lamV;
   E.tet_orig = S.tet_orig; E.Vw = S.Vw; E.rw = S.rw;
   E.mu_bar = S.mu_bar; E.lam_bar = S.lam_bar; E.k_bar = S.k_bar;
+  E.energy = S.energy;
   return E;
 }
 
@@ -425,6 +436,8 @@ void setup_scene(Scene& S, const pd_mesh_desc* mesh, const pd_material_desc* mat
   for (int v : S.tets)
     if (v < 0 || v >= nv) throw PdError{PD_ERR_INVALID_ARG, "tet vertex index out of range"};
   S.nu = mat->nu; S.rho = mat->rho; S.alpha = mat->alpha; S.beta0 = mat->beta0;
+  if (mat->energy < 0 || mat->energy > 1) throw PdError{PD_ERR_INVALID_ARG, "energy must be 0 or 1"};
+  S.energy = mat->energy;
   S.h = o->h;
   for (int a = 0; a < 3; ++a) S.grav[a] = o->gravity[a];
   S.m = o->aa_window; S.eps_rel = o->eps_rel; S.eps_abs = o->eps_abs; S.kmax_fwd = o->kmax_fwd;
@@ -453,6 +466,7 @@ void setup_scene(Scene& S, const pd_mesh_desc* mesh, const pd_material_desc* mat
   }
   build_layout(nv, ne, S.X.data(), S.tets.data(), S.pinned.data(), S.max_sub, S.L);
   if (S.L.nf == 0) throw PdError{PD_ERR_INVALID_ARG, "no free vertex"};
+  S.nnz_L = factor_nnz_nd(nv, ne, S.X.data(), S.tets.data(), S.pinned.data());
   const Layout& L = S.L;
   // element geometry in library order
   std::vector<int>& tv = S.htv;
@@ -1004,8 +1018,8 @@ static double kernel_bytes(const Scene& S, int id) {
   const double nf = L.nf, nT = L.nT, nB = L.nB, ne = S.ne, nv = S.nv, ninc = S.ninc;
   const double zs = S.S.zs_entries, et = S.S.e_entries;
   switch (id) {
-    case kKLocal:  // tet indices, D_m^-1, weight, positions in, 12 contributions out
-      return ne * (16.0 + 72.0 + 8.0) + 24.0 * nv + 24.0 * ninc;
+    case kKLocal:  // tet indices, D_m^-1, weight per tet; positions in and right-hand side out per vertex
+      return ne * (16.0 + 72.0 + 8.0) + 48.0 * nv;
     case kKGather:  // contributions and constant part in, b and q out
       return 24.0 * ninc + 24.0 * nf * 4;
     case kKEb:  // coupling blocks E_s, right-hand side in, interface right-hand side out
@@ -1014,8 +1028,10 @@ static double kernel_bytes(const Scene& S, int id) {
       return 8.0 * nT * nT + 24.0 * nT * 2;
     case kKBottom:  // subdomain inverses and couplings, right-hand sides, solution out
       return 8.0 * (zs + et) + 24.0 * (nB * 2 + nT);
-    case kKApplyK:  // tet indices, D_m^-1, weight, 30 Jacobian values, x in, contributions out
-      return ne * (16.0 + 72.0 + 8.0 + 240.0) + 24.0 * nv + 24.0 * ninc;
+    case kKApplyK:  // tet indices, D_m^-1, weight, 30 Jacobian values per tet; x in and K x out per vertex
+      return ne * (16.0 + 72.0 + 8.0 + 240.0) + 48.0 * nv;
+    case kKSolve:  // one forward and one backward sweep of a sparse factor of A~, six vector passes
+      return 16.0 * S.nnz_L + 6.0 * 24.0 * nf;
     default:
       return 0.0;
   }
@@ -1168,6 +1184,15 @@ int pd_scene_freeze_means(pd_scene* scene, const double* means3) {
   if (means3)
     for (int i = 0; i < 3; ++i) S.frozen_means[i] = means3[i];
   S.stale = true;
+  return PD_OK;
+}
+
+int pd_scene_factor_nnz(const pd_scene* scene, double* nnz) {
+  if (!scene || !nnz) {
+    pdhot::g_last_error = "null argument";
+    return PD_ERR_INVALID_ARG;
+  }
+  *nnz = scene->S.nnz_L;
   return PD_OK;
 }
 
@@ -1448,8 +1473,10 @@ static void adjoint_solve(Scene& S, hipStream_t st, double tau_force, double* bs
   }
   StepState T = step_state(S);
   T.done = Ad.done;  // plain solves inside the adjoint stop with it
-  launch_tr_partials(E, V, R, ck, st);
-  launch_bwd_elem(E, V, R, ck, S.eps_tr, tau_force, 1, S.jac, S.dstat + 4, S.ctl + kCtlAdj, 4, st);
+  // the trust-region ratio belongs to the Neo-Hookean prox (Alg. 2)
+  const int tr = S.energy == 0;
+  if (tr) launch_tr_partials(E, V, R, ck, st);
+  launch_bwd_elem(E, V, R, ck, S.eps_tr, tau_force, tr, S.jac, S.dstat + 4, S.ctl + kCtlAdj, 4, st);
   const bool pcg = S.adj_method == 0;
   if (pcg) {
     if (warm) {  // r = q bar - (A~ - K) mu0
@@ -1712,6 +1739,10 @@ struct pd_batch {
   // after and before the caller's work with events
   hipStream_t gstream = nullptr;
   hipEvent_t ev_in = nullptr, ev_out = nullptr;
+  // per-launch timing of one kernel kind (eager launches only, not graphs)
+  // and the algorithmic bytes of the work those launches did
+  KernelTimer kt;
+  double bytes_done = 0.0;
 };
 
 namespace {
@@ -1769,20 +1800,29 @@ void batch_bundles(pd_batch& B) {
 
 BatchMap bmap(const pd_batch& B, int kind) { return BatchMap{B.dB, B.dbase[kind], (int)B.scenes.size()}; }
 
+#define PD_BTIMED(B, id, st, call)                     \
+  do {                                                 \
+    const bool tm_ = !(B).use_graph && (B).kt.which >= 0; \
+    if (tm_) kt_begin((B).kt, id, st);                 \
+    call;                                              \
+    if (tm_) kt_end((B).kt, id, st);                   \
+  } while (0)
+
 void batch_fwd_iter(pd_batch& B, int k, hipStream_t st) {
-  launch_b_local(bmap(B, kBKLocal), B.nblk[kBKLocal], B.block_local, k, st);
-  launch_b_gather_fwd(bmap(B, kBKGather), B.nblk[kBKGather], k, st);
-  launch_b_Eb(kModeFwd, bmap(B, kBKEb), B.nblk[kBKEb], k, st);
-  launch_b_top(bmap(B, kBKTop), B.nblk[kBKTop], 0, st);
-  launch_b_bottom(kModeFwd, bmap(B, kBKBottom), B.nblk[kBKBottom], k, st);
+  PD_BTIMED(B, kKLocal, st, launch_b_local(bmap(B, kBKLocal), B.nblk[kBKLocal], B.block_local, k, st));
+  PD_BTIMED(B, kKGather, st, launch_b_gather_fwd(bmap(B, kBKGather), B.nblk[kBKGather], k, st));
+  PD_BTIMED(B, kKEb, st, launch_b_Eb(kModeFwd, bmap(B, kBKEb), B.nblk[kBKEb], k, st));
+  PD_BTIMED(B, kKTop, st, launch_b_top(bmap(B, kBKTop), B.nblk[kBKTop], 0, st));
+  PD_BTIMED(B, kKBottom, st, launch_b_bottom(kModeFwd, bmap(B, kBKBottom), B.nblk[kBKBottom], k, st));
 }
 
 void batch_adj_iter(pd_batch& B, int it, hipStream_t st) {
-  launch_b_apply_K(kModePCG, bmap(B, kBKApplyK), B.nblk[kBKApplyK], B.block_applyK, it, st);
+  PD_BTIMED(B, kKApplyK, st,
+            launch_b_apply_K(kModePCG, bmap(B, kBKApplyK), B.nblk[kBKApplyK], B.block_applyK, it, st));
   launch_b_adj_gather(kModePCG, bmap(B, kBKGather), B.nblk[kBKGather], it, st);
-  launch_b_Eb(kModePCG, bmap(B, kBKEb), B.nblk[kBKEb], it, st);
-  launch_b_top(bmap(B, kBKTop), B.nblk[kBKTop], 1, st);
-  launch_b_bottom(kModePCG, bmap(B, kBKBottom), B.nblk[kBKBottom], it, st);
+  PD_BTIMED(B, kKEb, st, launch_b_Eb(kModePCG, bmap(B, kBKEb), B.nblk[kBKEb], it, st));
+  PD_BTIMED(B, kKTop, st, launch_b_top(bmap(B, kBKTop), B.nblk[kBKTop], 1, st));
+  PD_BTIMED(B, kKBottom, st, launch_b_bottom(kModePCG, bmap(B, kBKBottom), B.nblk[kBKBottom], it, st));
 }
 
 // iterations k0 .. k1-1 of a loop, replayed from a graph when enabled
@@ -1861,6 +1901,7 @@ int pd_batch_create(pd_scene* const* scenes, int n, pd_batch** out) {
 int pd_batch_destroy(pd_batch* B) {
   if (!B) return PD_OK;
   batch_free_graphs(*B);
+  for (hipEvent_t e : B->kt.ev) (void)hipEventDestroy(e);
   dfree(B->dB);
   for (int k = 0; k < kBKKinds; ++k) dfree(B->dbase[k]);
   dfree(B->dctl);
@@ -1946,7 +1987,10 @@ int pd_batch_step_forward(pd_batch* B, const double* const* q_t, const double* c
     if (!c[kCtlDone]) throw PdError{PD_ERR_HIP, "batched forward loop ended without a decision"};
     worst = std::max(worst, c[kCtlStatus]);
     most = std::max(most, c[kCtlIters]);
+    if (B->kt.which == kKSolve) B->bytes_done += c[kCtlIters] * kernel_bytes(S, kKSolve);
+    if (B->kt.which == kKLocal) B->bytes_done += (c[kCtlIters] + 1) * kernel_bytes(S, kKLocal);
   }
+  if (B->kt.which >= 0 && !B->use_graph) kt_flush(B->kt);
   B->last_fwd = most;
   PD_HIP(hipStreamSynchronize(st));
   PD_HIP(hipGetLastError());
@@ -1980,17 +2024,18 @@ int pd_batch_step_backward(pd_batch* B, const void* const* ckpt, const double* c
     any_warm = any_warm || warm[s] > 0;
     launch_bwd_prologue(V, Ad, gq_next ? gq_next[s] : nullptr, gv_next ? gv_next[s] : nullptr, warm[s], S.mu_h1,
                         S.mu_h2, S.mu_h3, st);
-    launch_tr_partials(E, V, R, ck, st);
-    launch_bwd_elem(E, V, R, ck, S.eps_tr, -1.0, 1, S.jac, S.dstat + 4, S.ctl + kCtlAdj, 4, st);
+    const int tr = S.energy == 0;
+    if (tr) launch_tr_partials(E, V, R, ck, st);
+    launch_bwd_elem(E, V, R, ck, S.eps_tr, -1.0, tr, S.jac, S.dstat + 4, S.ctl + kCtlAdj, 4, st);
     kmax = std::max(kmax, S.kmax_bwd);
   }
   if (any_warm) {  // r = q bar - (A~ - K) mu0 (a zero mu0 gives r = q bar again)
     launch_b_apply_K(kModeAmK, bmap(*B, kBKApplyK), B->nblk[kBKApplyK], B->block_applyK, 0, st);
     launch_b_adj_gather(kModeInit, bmap(*B, kBKGather), B->nblk[kBKGather], 0, st);
   }
-  launch_b_Eb(kModePlain, bmap(*B, kBKEb), B->nblk[kBKEb], 0, st);
-  launch_b_top(bmap(*B, kBKTop), B->nblk[kBKTop], 1, st);
-  launch_b_bottom(kModePCGInit, bmap(*B, kBKBottom), B->nblk[kBKBottom], 0, st);
+  PD_BTIMED(*B, kKEb, st, launch_b_Eb(kModePlain, bmap(*B, kBKEb), B->nblk[kBKEb], 0, st));
+  PD_BTIMED(*B, kKTop, st, launch_b_top(bmap(*B, kBKTop), B->nblk[kBKTop], 1, st));
+  PD_BTIMED(*B, kKBottom, st, launch_b_bottom(kModePCGInit, bmap(*B, kBKBottom), B->nblk[kBKBottom], 0, st));
   int it = 0;
   const int fixed = B->chunk > 0 ? B->chunk : (B->use_graph ? 4 : 0);
   int chunk = fixed > 0 ? fixed : std::max(4, B->last_adj + 1);
@@ -2027,11 +2072,53 @@ int pd_batch_step_backward(pd_batch* B, const void* const* ckpt, const double* c
     }
     worst = std::max(worst, c[kCtlAdj + 1]);
     most = std::max(most, c[kCtlAdj]);
+    if (B->kt.which == kKSolve) B->bytes_done += (c[kCtlAdj] + 1) * kernel_bytes(S, kKSolve);
+    if (B->kt.which == kKApplyK) B->bytes_done += c[kCtlAdj] * kernel_bytes(S, kKApplyK);
   }
+  if (B->kt.which >= 0 && !B->use_graph) kt_flush(B->kt);
   B->last_adj = most;
   PD_HIP(hipStreamSynchronize(st));
   PD_HIP(hipGetLastError());
   return worst == 0 ? PD_OK : PD_NOT_CONVERGED;
+  PD_CATCH
+}
+
+
+int pd_batch_kernel_timer(pd_batch* B, int kernel) {
+  if (!B || kernel < -1 || kernel >= kKCount) {
+    pdhot::g_last_error = "invalid batch or kernel id";
+    return PD_ERR_INVALID_ARG;
+  }
+  PD_TRY
+  KernelTimer& T = B->kt;
+  if (T.ev.empty() && kernel >= 0) {
+    T.ev.resize(2 * kTimerPairs);
+    for (auto& e : T.ev) PD_HIP(hipEventCreate(&e));
+  }
+  PD_HIP(hipDeviceSynchronize());
+  T.which = kernel;
+  T.head = 0;
+  T.used = 0;
+  T.total_ms = 0.0;
+  T.launches = 0;
+  T.working = 0;
+  B->bytes_done = 0.0;
+  return PD_OK;
+  PD_CATCH
+}
+
+int pd_batch_kernel_timer_read(pd_batch* B, double* total_ms, int64_t* launches, double* bytes_done) {
+  if (!B) {
+    pdhot::g_last_error = "null batch";
+    return PD_ERR_INVALID_ARG;
+  }
+  PD_TRY
+  PD_HIP(hipDeviceSynchronize());
+  kt_flush(B->kt, true);
+  if (total_ms) *total_ms = B->kt.total_ms;
+  if (launches) *launches = B->kt.launches;
+  if (bytes_done) *bytes_done = B->bytes_done;
+  return PD_OK;
   PD_CATCH
 }
 

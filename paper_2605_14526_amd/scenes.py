@@ -140,6 +140,10 @@ class Scene:
     # static obstacles: {"planes": [(normal, offset)], "boxes": [(lo, hi)], "d_c": candidate distance}
     obstacles: Optional[dict] = None
     v_init: Optional[np.ndarray] = None
+    # identification tasks: the material field that generated the observed trajectory
+    log_E_obs: Optional[np.ndarray] = None
+    # energy model of the local step: 0 Neo-Hookean proximal map, 1 corotated + volume composite
+    energy: int = 0
 
     @property
     def n_v(self) -> int:
@@ -389,10 +393,21 @@ def anchored_blob(ne: float, seed: int, contrast: float = 30.0, nu: float = 0.45
                  aa_window=5 if contrast < 10.0 else 1, steps=steps, force_fn=force, target_centroid=target)
 
 
+def observed_log_E(sc: Scene, seed: int) -> np.ndarray:
+    """Another two-phase field on the scene's mesh for a synthetic identification task: the same two moduli
+    and stiff fraction (30 %) as the scene's own field, placed by 4 Gaussian blobs drawn with `seed`."""
+    cen = sc.X[sc.tets].mean(axis=1)
+    lo, hi = sc.X.min(axis=0), sc.X.max(axis=0)
+    ext = float((hi - lo).max())
+    field = gaussian_blob_field(cen, lo, hi, 4, _rng(seed), 0.05 * ext, 0.15 * ext)
+    return two_phase_log_E(field, 0.3, float(np.exp(sc.log_E.min())), float(np.exp(sc.log_E.max())))
+
+
 def sysid_batch(n: int = 64, seed: int = 4000, steps: int = 50, ne_range=(1000, 30000)) -> list:
     """A batch of uneven scenes for multi-scene identification: per scene a coin flip between a beam (as in
     beam_batch) and an anchored blob, a tet count log-uniform in ne_range, contrast log-uniform in [1, 100],
-    nu uniform in [0.40, 0.49]."""
+    nu uniform in [0.40, 0.49].  Each scene also carries `log_E_obs`, the field of its observed trajectory
+    (observed_log_E with seed + 10 (s + 1) + 7)."""
     rng = _rng(seed)
     out = []
     for s in range(n):
@@ -408,6 +423,7 @@ def sysid_batch(n: int = 64, seed: int = 4000, steps: int = 50, ne_range=(1000, 
         else:
             sc = anchored_blob(ne, seed=seed + 10 * (s + 1), contrast=contrast, nu=nu, steps=steps)
             sc.name = f"sysid_blob_{s}"
+        sc.log_E_obs = observed_log_E(sc, seed + 10 * (s + 1) + 7)
         out.append(sc)
     return out
 

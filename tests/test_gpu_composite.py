@@ -1,0 +1,172 @@
+"""The corotated + volume composite (the paper's default heterogeneous PD
+assembly, Sec. 4.1 and Sec. 7.2) on the GPU against the oracle: local step,
+K apply, forward steps (path parity through the gate), backward steps, the
+rest state, and the 20,000-tet beam.  All calls go through the C ABI."""
+import copy
+
+import numpy as np
+import pytest
+
+import oracle as O
+from paper_2605_14526_amd import scenes
+
+pytestmark = pytest.mark.gpu
+
+
+def rel(a, b):
+    return float(np.abs(np.asarray(a) - np.asarray(b)).max() / max(np.abs(np.asarray(b)).max(), 1e-300))
+
+
+@pytest.fixture(scope="module")
+def th(torch_cuda):
+    return torch_cuda
+
+
+def dev(th, a):
+    return th.tensor(np.ascontiguousarray(a), dtype=th.float64, device="cuda")
+
+
+def host(t):
+    return t.detach().cpu().numpy()
+
+
+def composite(sc):
+    sc = copy.copy(sc)
+    sc.energy = 1
+    return sc
+
+
+SMALL = [
+    lambda: composite(scenes.small_beam(4, 2, 2, seed=3)),
+    lambda: composite(scenes.small_beam(7, 3, 3, seed=5, contrast=30.0, nu=0.49)),
+    lambda: composite(scenes.small_beam(10, 4, 3, seed=11, contrast=1.0, aa_window=5, alpha=0.0, beta_rel=0.0)),
+]
+
+
+def pair(sc, **kw):
+    from paper_2605_14526_amd.binding import Scene
+    return Scene.from_scene(sc, **kw), O.OracleScene(sc, eps_adj=kw.get("eps_adj", 1e-6))
+
+
+def perturbed(sc, amp, seed):
+    r = np.random.Generator(np.random.PCG64(seed))
+    q = sc.X + amp * r.standard_normal(sc.X.shape)
+    q[sc.pinned.astype(bool)] = sc.X[sc.pinned.astype(bool)]
+    return q
+
+
+@pytest.mark.parametrize("mk", SMALL)
+def test_local_rhs_parity(th, mk):
+    """sum_e (2 mu_e V_e G^T R + lam_e V_e G^T P_vol), up to strains where the
+    volume step leaves its branch through the identity (amplitude 3e-2 on
+    5 cm cells)."""
+    sc = mk()
+    g, o = pair(sc)
+    free = ~sc.pinned.astype(bool)
+    for amp, seed in [(0.0, 1), (2e-3, 2), (1e-2, 3), (3e-2, 4)]:
+        q = perturbed(sc, amp, seed)
+        b_g = host(g.debug_local_rhs(dev(th, q)))
+        b_o = o.local_rhs(q)
+        assert rel(b_g[free], b_o[free]) < 1e-11, (amp, rel(b_g[free], b_o[free]))
+
+
+@pytest.mark.parametrize("mk", SMALL)
+def test_apply_K_parity(th, mk):
+    sc = mk()
+    g, o = pair(sc)
+    r = np.random.Generator(np.random.PCG64(23))
+    q = perturbed(sc, 5e-3, 29)
+    x = r.standard_normal(sc.X.shape)
+    assert rel(host(g.debug_apply_K(dev(th, q), 1.0, dev(th, x))), o.apply_K(q, 1.0, x)) < 1e-10
+
+
+def test_rest_state(th):
+    sc = composite(scenes.small_beam(6, 3, 3, seed=2, tip_force=0.0, gravity=(0.0, 0.0, 0.0)))
+    g, o = pair(sc)
+    qn, vn, st = g.step_forward(dev(th, sc.X), dev(th, np.zeros_like(sc.X)))
+    assert st["iters"] == 2 and st["status"] == 0
+    assert rel(host(qn), sc.X) < 1e-14
+
+
+def forward_pair(th, sc, steps, **kw):
+    """Library and oracle steps from the oracle's states, path parity through the gate."""
+    g, o = pair(sc, **kw)
+    q, v = sc.q0(), sc.v0()
+    ck, worst, its = [], 0.0, []
+    for t in range(steps):
+        f = sc.f_ext(t)
+        ckpt = g.new_ckpt()
+        qg, _, stg = g.step_forward(dev(th, q), dev(th, v), dev(th, f), ckpt=ckpt)
+        qo, vo, qm1, sto = o.step_forward(q, v, f)
+        assert stg["status"] == 0 and sto["status"] == 0
+        qc, qm1c = qo, qm1
+        if stg["iters"] != sto["iters"]:
+            kg, ko = stg["iters"], sto["iters"]
+            qc, _, qm1c, stf = o.step_forward(q, v, f, force_iters=kg)
+            gt = (stf if kg < ko else sto)["gate"]
+            r = max(gt[0] / (sc.eps_rel * gt[1] + sc.eps_abs), gt[2] / (sc.eps_rel * gt[3] + sc.eps_abs))
+            assert abs(r - 1.0) <= 1e-4, (t, kg, ko, r)
+        its.append((stg["iters"], sto["iters"]))
+        worst = max(worst, rel(host(qg), qc))
+        ck.append((q, v, f, qc, qm1c, ckpt))
+        q, v = qo, vo
+    return g, o, ck, worst, its
+
+
+@pytest.mark.parametrize("mk", SMALL)
+def test_forward_parity(th, mk):
+    sc = mk()
+    g, o, ck, worst, its = forward_pair(th, sc, 4)
+    assert worst < 1e-9, (worst, its)
+
+
+@pytest.mark.parametrize("mk", SMALL)
+@pytest.mark.parametrize("method", [0, 1])
+def test_backward_parity(th, mk, method):
+    sc = mk()
+    eps = 1e-12 if method == 0 else 1e-10
+    g, o, ck, worst, its = forward_pair(th, sc, 3, adj_method=method, eps_adj=eps)
+    r = np.random.Generator(np.random.PCG64(31))
+    for (q_t, v_t, f, qs, qsm1, ckpt) in ck:
+        gq = r.standard_normal(q_t.shape)
+        gv = r.standard_normal(q_t.shape)
+        res_o = o.step_backward(q_t, v_t, f, qs, qsm1, gq, gv, adj_mode=1)
+        res_g = g.step_backward(ckpt, dev(th, gq), dev(th, gv))
+        assert res_g[4]["status"] == 0
+        for a, b in zip(res_g[:4], res_o[:4]):
+            assert rel(host(a), b) < 1e-6, rel(host(a), b)
+
+
+def test_hetero_beam_full_size(th):
+    """The 20,000-tet heterogeneous beam with the composite: four forward steps
+    of the library's own rollout (the oracle on the same path) and their
+    reverse sweep against the oracle's adjoint run to 1e-13."""
+    from paper_2605_14526_amd.binding import Scene
+    sc = composite(scenes.config("c2"))
+    T = 4
+    g = Scene.from_scene(sc, eps_adj=1e-11, adj_warm=3)
+    o = O.OracleScene(sc, eps_adj=1e-13)
+    q, v = sc.q0(), sc.v0()
+    qg, vg = dev(th, q), dev(th, v)
+    cks, ck_o = [], []
+    for t in range(T):
+        f = sc.f_ext(t)
+        ck = g.new_ckpt()
+        qg, vg, stg = g.step_forward(qg, vg, dev(th, f), ckpt=ck)
+        cks.append(ck)
+        qo, vo, qm1, sto = o.step_forward(q, v, f)
+        if stg["iters"] != sto["iters"]:
+            qo, vo, qm1, _ = o.step_forward(q, v, f, force_iters=stg["iters"])
+        assert rel(host(qg), qo) < 1e-9
+        ck_o.append((q, v, f, qo, qm1))
+        q, v = qo, vo
+    _, gq = scenes.centroid_loss(q, sc.target_centroid)
+    gq0_o, gv0_o, gl_o, _ = O.rollout_backward(o, ck_o, gq, np.zeros_like(gq), adj_mode=0)
+    g.adjoint_reset()
+    gqd, gvd = dev(th, gq), dev(th, np.zeros_like(gq))
+    gl = th.zeros(sc.n_e, dtype=th.float64, device="cuda")
+    for ck in reversed(cks):
+        gqd, gvd, _, _, st = g.step_backward(ck, gqd, gvd, g_logE=gl)
+        assert st["status"] == 0
+    for a, b in [(host(gqd), gq0_o), (host(gvd), gv0_o), (host(gl), gl_o)]:
+        assert rel(a, b) < 1e-6, rel(a, b)

@@ -38,17 +38,20 @@ def gate_ratio(gate, eps_rel, eps_abs):
 
 def test_benchmark_settings_gradients_match_oracle(th):
     """The benchmark's configuration of the beam: dual gate 1e-6, adjoint PCG
-    to 1e-6 from the quadratically extrapolated start, the 20 timed steps and
+    to the benchmark's tolerance from the quadratically extrapolated start
+    (a looser PCG stop left gradients 7e-4 away from the oracle), the 20
+    timed steps and
     their reverse sweep with the centroid loss.  The library runs its own
     rollout; the oracle follows the same path (its step re-run at the
     library's iteration count where the gate decided one iteration apart,
     after checking that its gate was within rounding of the threshold) and
     runs its adjoint to 1e-13.  Positions agree to 1e-9, the gradients with
     respect to q0, v0 and all 20,000 log E to 1e-6."""
+    import bench
     from paper_2605_14526_amd.binding import Scene
     sc = scenes.config("c2")
     T = 20
-    g = Scene.from_scene(sc, eps_adj=1e-6, adj_warm=3)
+    g = Scene.from_scene(sc, eps_adj=bench.ADJ_TOL, adj_warm=3)
     o = O.OracleScene(sc, eps_adj=1e-13)
     q, v = sc.q0(), sc.v0()
     qg, vg = dev(th, q), dev(th, v)
@@ -101,7 +104,7 @@ def _loss_rollout(th, g, sc, T):
 def test_material_gradient_central_differences_16_tets(th):
     """Sec. 4.8 gradient routing (dL/dlog E_e) against central differences of
     the library's own forward rollout on the 16 seeded tets of the beam
-    (step 1e-3 in log E), over the first 40 steps (the tip load's ramp and
+    (step 1e-2 in log E), over the first 40 steps (the tip load's ramp and
     hold), with the mesh means held fixed (they are constants of the
     gradient) and the forward gate and the adjoint run to 1e-12."""
     from paper_2605_14526_amd.binding import Scene
@@ -121,7 +124,7 @@ def test_material_gradient_central_differences_16_tets(th):
         assert st["status"] == 0, st
     gl = host(gl)
     del cks
-    hstep = 1e-3
+    hstep = 1e-2
     fd = []
     for e in sc.fd_tets:
         vals = []
@@ -139,4 +142,10 @@ def test_material_gradient_central_differences_16_tets(th):
     print("fd check: tet, adjoint, central difference, rel. difference")
     for e, a, b in zip(sc.fd_tets.tolist(), ad.tolist(), fd.tolist()):
         print(f"  {e:6d} {a: .10e} {b: .10e} {abs(a - b) / scale:.2e}")
+    # the rollout's rounding leaves about 1e-14 of noise in L, i.e. ~5e-13 in a
+    # difference quotient at this step: tets whose gradient is far below the
+    # largest are compared absolutely, the others to 1e-3 relative
     assert np.abs(ad - fd).max() <= 1e-3 * scale, list(zip(sc.fd_tets.tolist(), ad.tolist(), fd.tolist()))
+    big = np.abs(fd) >= 1e-2 * scale
+    assert big.sum() >= 2
+    assert (np.abs(ad - fd)[big] <= 1e-3 * np.abs(fd)[big]).all()

@@ -1,0 +1,80 @@
+"""Material inverse design (L-BFGS over per-tet log E, refactorizing per
+evaluation) through the library: the trajectory-matching gradient of one
+evaluation against the oracle's, and the optimisation itself."""
+import numpy as np
+import pytest
+
+import oracle as O
+from paper_2605_14526_amd import scenes
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def th(torch_cuda):
+    return torch_cuda
+
+
+def setup(th, T):
+    from paper_2605_14526_amd.binding import Scene
+    sc = scenes.small_beam(6, 3, 3, seed=31, contrast=20.0, nu=0.45, tip_force=10.0)
+    log_E_obs = scenes.observed_log_E(sc, 77)
+    dev = lambda a: th.tensor(np.ascontiguousarray(a), dtype=th.float64, device="cuda")  # noqa: E731
+    # observations: the same scene rolled out with the observation field
+    gobs = Scene.from_scene(sc, eps_rel=1e-12, eps_abs=1e-16)
+    gobs.set_material(log_E_obs)
+    gobs.factorize()
+    q, v = dev(sc.q0()), dev(sc.v0())
+    obs = [q]
+    for t in range(T):
+        q, v, _ = gobs.step_forward(q, v, dev(sc.f_ext(t)))
+        obs.append(q)
+    # the estimate starts from a uniform field at the mean log E
+    log_E0 = np.full(sc.n_e, float(np.mean(sc.log_E)))
+    sc.log_E = log_E0.copy()
+    g = Scene.from_scene(sc, eps_rel=1e-12, eps_abs=1e-16, eps_adj=1e-12)
+    mass = dev(g.vertex_mass())
+    return sc, g, obs, mass, log_E0, log_E_obs
+
+
+def test_trajectory_gradient_matches_oracle(th):
+    """One evaluation of the identification loss sum_t |q_t - q_t^obs|_M^2 and
+    its gradient with respect to all log E against the oracle (same frozen
+    means, the loss gradient injected at every step of the reverse sweep)."""
+    from paper_2605_14526_amd.inverse import trajectory_objective
+    T = 8
+    sc, g, obs, mass, log_E0, _ = setup(th, T)
+    fg = trajectory_objective(g, sc, T, obs, mass, th)
+    L, grad = fg(th.tensor(log_E0, dtype=th.float64, device="cuda"))
+    info = g.info()
+    o = O.OracleScene(sc, log_E=log_E0, eps_rel=1e-12, eps_abs=1e-16, eps_adj=1e-13,
+                      frozen=(info["mu_bar"], info["lam_bar"], info["mu_ref"]))
+    q, v, ck, _ = O.rollout(o, T)
+    obs_h = [x.cpu().numpy() for x in obs]
+    m = mass.cpu().numpy()[:, None]
+    traj = [sc.q0()] + [c[3] for c in ck]
+    L_o = sum(float((m * (traj[t] - obs_h[t]) ** 2).sum()) for t in range(1, T + 1))
+    gq = 2.0 * m * (traj[T] - obs_h[T])
+    gv = np.zeros_like(gq)
+    gl = np.zeros(sc.n_e)
+    for t in reversed(range(T)):
+        q_t, v_t, f, qs, qsm1 = ck[t]
+        gq, gv, _, gl, _ = o.step_backward(q_t, v_t, f, qs, qsm1, gq, gv, gl, adj_mode=1)
+        if t > 0:
+            gq = gq + 2.0 * m * (traj[t] - obs_h[t])
+    assert abs(L - L_o) <= 1e-9 * L_o
+    gg = grad.cpu().numpy()
+    assert np.abs(gg - gl).max() <= 1e-6 * np.abs(gl).max(), np.abs(gg - gl).max() / np.abs(gl).max()
+
+
+def test_lbfgs_identification_reduces_loss(th):
+    """Twelve L-BFGS iterations from the uniform field cut the identification
+    loss by more than 10x (it falls monotonically; 20x was measured), every
+    evaluation refactorizes."""
+    from paper_2605_14526_amd.inverse import lbfgs, trajectory_objective
+    T = 8
+    sc, g, obs, mass, log_E0, log_E_obs = setup(th, T)
+    fg = trajectory_objective(g, sc, T, obs, mass, th)
+    res = lbfgs(fg, th.tensor(log_E0, dtype=th.float64, device="cuda"), iters=12, memory=8, max_step=1.0)
+    assert res.f < 1e-1 * res.history[0], res.history
+    assert all(a >= b for a, b in zip(res.history, res.history[1:]))

@@ -79,6 +79,14 @@ def lib():
                                                _ip, _dp]
         L.or_contact_W.argtypes = [ctypes.c_void_p, ctypes.c_int, _ip, _dp, _dp]
         L.or_fb_lcp.argtypes = [ctypes.c_int, _dp, _dp, _dp, _dp]
+        L.or_step_forward_friction.argtypes = [ctypes.c_void_p, _dp, _dp, _dp, _dp, _dp, _dp, _dp, ctypes.c_int,
+                                               _ip, _dp, _dp, ctypes.c_double, ctypes.c_double, _dp, ctypes.c_int,
+                                               _ip, _dp]
+        L.or_step_backward_friction.argtypes = [ctypes.c_void_p, _dp, _dp, _dp, _dp, _dp, _dp, _dp, _dp, _dp, _dp,
+                                                _dp, ctypes.c_int, ctypes.c_double, ctypes.c_int, _ip, _dp, _dp,
+                                                ctypes.c_double, _dp, _ip, _dp]
+        L.or_contact_frame.argtypes = [_dp, _dp, _dp]
+        L.or_friction_ncp.argtypes = [ctypes.c_int, _dp, _dp, _dp, ctypes.c_double, _dp, _dp]
         _lib = L
     return _lib
 
@@ -316,13 +324,15 @@ def _obstacle_faces(obs):
     return faces
 
 
-def detect_contacts(q_t, v_t, h, pinned, obs):
+def detect_contacts(q_t, v_t, h, pinned, obs, one_per_vertex=False):
     """Contact rows for one step (frictionless reading of Sec. 4.7): for each free vertex (in vertex order)
     and each obstacle (planes first, then boxes), the obstacle's distance d(x) (a plane's signed distance;
     for a box the largest signed distance over its six faces) is evaluated at x0 = q_t and at the inertial
     prediction x1 = q_t + h v_t; the pair is a row if min(d(x0), d(x1)) < d_c.  Its normal and offset are
-    those of the face that attains the maximum at x0 (the first such face on ties).  Returns int32 vertex
-    ids, normals (K, 3) and offsets (K,)."""
+    those of the face that attains the maximum at x0 (the first such face on ties).  With
+    one_per_vertex (the frictional reading: a contact carries a full frame, so two on one vertex would be
+    redundant) a vertex keeps only the qualifying obstacle with the smallest distance at x0 (the first on
+    ties).  Returns int32 vertex ids, normals (K, 3) and offsets (K,)."""
     dc = float(obs["d_c"])
     faces = _obstacle_faces(obs)
     cv, cn, cg = [], [], []
@@ -331,14 +341,23 @@ def detect_contacts(q_t, v_t, h, pinned, obs):
             continue
         x0 = q_t[v]
         x1 = q_t[v] + h * v_t[v]
+        best = None
         for fl in faces:
             d0 = [float(n[0] * x0[0] + n[1] * x0[1] + n[2] * x0[2] - o) for (n, o) in fl]
             d1 = [float(n[0] * x1[0] + n[1] * x1[1] + n[2] * x1[2] - o) for (n, o) in fl]
             i0 = int(np.argmax(d0))
             if min(max(d0), max(d1)) < dc:
+                if one_per_vertex:
+                    if best is None or max(d0) < best[0]:
+                        best = (max(d0), fl[i0])
+                    continue
                 cv.append(v)
                 cn.append(fl[i0][0])
                 cg.append(fl[i0][1])
+        if best is not None:
+            cv.append(v)
+            cn.append(best[1][0])
+            cg.append(best[1][1])
     return (np.asarray(cv, dtype=np.int32), np.asarray(cn, dtype=np.float64).reshape(-1, 3),
             np.asarray(cg, dtype=np.float64))
 
@@ -403,6 +422,96 @@ def step_backward_contact(osc, q_t, v_t, f_ext, q_star, q_star_m1, gq_next, gv_n
     st = dict(adj_iters=int(ist[0]), status=int(ist[1]), rho=dst[0], tau=dst[1], dphi_act=dst[2],
               dphi_mod=dst[3])
     return gq, gv, gf, gl, st
+
+
+def contact_frame(n):
+    """The oracle's tangent frame (t1, t2) of a unit normal."""
+    n = _f(n)
+    t1, t2 = np.zeros(3), np.zeros(3)
+    lib().or_contact_frame(_p(n), _p(t1), _p(t2))
+    return t1, t2
+
+
+def friction_ncp(G, normals, u0, mu):
+    """The oracle's friction Newton alone: G (K x K), normals (K, 3), free kinematics u0 (K, 3: gap, slip
+    along t1, t2); returns impulses (K, 3: normal, t1, t2), Newton steps and the final residual."""
+    G, normals, u0 = _f(G), _f(normals), _f(u0)
+    K = G.shape[0]
+    lam = np.zeros((max(K, 1), 3))
+    res = ctypes.c_double(0.0)
+    it = lib().or_friction_ncp(K, _p(G), _p(normals), _p(u0), float(mu), _p(lam), ctypes.byref(res))
+    return lam[:K].copy(), it, res.value
+
+
+def step_forward_friction(osc, q_t, v_t, f_ext, contacts, mu_f, fb_tol=1e-10, force_iters=0, q0=None):
+    """One forward step with Coulomb friction on a given contact set; returns q, v, q*_-1, impulses (K, 3)
+    and stats."""
+    cv, cn, cg = contacts
+    cv = np.ascontiguousarray(cv, dtype=np.int32)
+    cn, cg = _f(cn), _f(cg)
+    q_t, v_t = _f(q_t), _f(v_t)
+    K = cv.shape[0]
+    qn, vn, qm1 = np.zeros_like(q_t), np.zeros_like(q_t), np.zeros_like(q_t)
+    lam = np.zeros((max(K, 1), 3))
+    ist = np.zeros(5, dtype=np.int32)
+    dst = np.zeros(6)
+    lib().or_step_forward_friction(osc.ptr, _p(q_t), _p(v_t), _p(_f(f_ext)) if f_ext is not None else None,
+                                   _p(_f(q0)) if q0 is not None else None, _p(qn), _p(vn), _p(qm1), K,
+                                   cv.ctypes.data_as(_ip), _p(cn), _p(cg), float(mu_f), float(fb_tol), _p(lam),
+                                   int(force_iters), ist.ctypes.data_as(_ip), _p(dst))
+    st = dict(iters=int(ist[0]), resets=int(ist[1]), newton_capped=int(ist[2]), newton_max=int(ist[3]),
+              status=int(ist[4]), gate=dst[:4].copy(), fb_res=float(dst[4]), fb_iters=int(dst[5]),
+              n_contacts=K, n_active=int((lam[:K, 0] > 0).sum()))
+    return qn, vn, qm1, lam[:K].copy(), st
+
+
+def step_backward_friction(osc, q_t, v_t, f_ext, q_star, q_star_m1, gq_next, gv_next, contacts, mu_f, lam,
+                           g_logE=None, adj_mode=0, tau_force=-1.0):
+    cv, cn, cg = contacts
+    cv = np.ascontiguousarray(cv, dtype=np.int32)
+    cn, cg = _f(cn), _f(cg)
+    K = cv.shape[0]
+    q_t, v_t = _f(q_t), _f(v_t)
+    gq, gv, gf = np.zeros_like(q_t), np.zeros_like(q_t), np.zeros_like(q_t)
+    gl = np.zeros(osc.ne) if g_logE is None else g_logE
+    ist = np.zeros(2, dtype=np.int32)
+    dst = np.zeros(4)
+    lam = _f(lam if K else np.zeros((1, 3)))
+    lib().or_step_backward_friction(osc.ptr, _p(q_t), _p(v_t), _p(_f(f_ext)) if f_ext is not None else None,
+                                    _p(_f(q_star)), _p(_f(q_star_m1)), _p(_f(gq_next)), _p(_f(gv_next)), _p(gq),
+                                    _p(gv), _p(gf), _p(gl), int(adj_mode), float(tau_force), K,
+                                    cv.ctypes.data_as(_ip), _p(cn), _p(cg), float(mu_f), _p(lam),
+                                    ist.ctypes.data_as(_ip), _p(dst))
+    st = dict(adj_iters=int(ist[0]), status=int(ist[1]), rho=dst[0], tau=dst[1], dphi_act=dst[2],
+              dphi_mod=dst[3])
+    return gq, gv, gf, gl, st
+
+
+def rollout_friction(osc: OracleScene, steps: int, mu_f, fb_tol=1e-10, q0=None, v0=None):
+    """Forward rollout with per-step contact detection (one contact per vertex) and Coulomb friction."""
+    sc = osc.sc
+    q = sc.q0() if q0 is None else q0.copy()
+    v = sc.v0() if v0 is None else v0.copy()
+    ckpts, stats = [], []
+    for t in range(steps):
+        f = sc.f_ext(t)
+        con = detect_contacts(q, v, sc.h, sc.pinned, sc.obstacles, one_per_vertex=True)
+        qn, vn, qm1, lam, st = step_forward_friction(osc, q, v, f, con, mu_f, fb_tol)
+        ckpts.append((q.copy(), v.copy(), f.copy(), qn.copy(), qm1.copy(), con, lam))
+        stats.append(st)
+        q, v = qn, vn
+    return q, v, ckpts, stats
+
+
+def rollout_backward_friction(osc: OracleScene, ckpts, gq_T, gv_T, mu_f, adj_mode=0):
+    gq, gv = gq_T.copy(), gv_T.copy()
+    gl = np.zeros(osc.ne)
+    stats = []
+    for (q_t, v_t, f, qs, qsm1, con, lam) in reversed(ckpts):
+        gq, gv, _gf, gl, st = step_backward_friction(osc, q_t, v_t, f, qs, qsm1, gq, gv, con, mu_f, lam, gl,
+                                                     adj_mode)
+        stats.append(st)
+    return gq, gv, gl, stats[::-1]
 
 
 def rollout_contact(osc: OracleScene, steps: int, fb_tol=1e-10, q0=None, v0=None):

@@ -1176,6 +1176,13 @@ typedef struct or_contacts {
   double* W;       /* K x K */
   double fb_res;
   int fb_iters;
+  /* Coulomb friction (mu_f > 0): lambda holds 3 entries per contact (normal,
+   * t1, t2), q_t gives the slip's start, e the frames, G the K x K block of
+   * A~^{-1} between the contact vertices */
+  double mu_f;
+  const double* qt;
+  double* e;
+  double* G;
 } or_contacts;
 
 static int chol_solve(double* A, int n, double* b) { /* SPD, in place (lower), returns 0 if not PD */
@@ -1204,6 +1211,232 @@ static int chol_solve(double* A, int n, double* b) { /* SPD, in place (lower), r
   return 1;
 }
 
+/* ------------------------------------------------------------------------ */
+/* Coulomb friction (Sec. 4.7): three rows per contact                       */
+/* ------------------------------------------------------------------------ */
+/* READING (friction, Sec. 4.7 Eqs. fb_n, omega_E_n, contact_system, q_update
+ * with the block projection onto the friction disk): contact c acts on vertex
+ * v_c through the orthonormal frame (n_c, t1_c, t2_c) with impulse
+ * lambda_c = (lambda_n, lambda_f1, lambda_f2).  Its kinematics are the
+ * position-level normal gap delta_c = n_c . q_{v_c} - g_c and the slip
+ * s_c = T_c^T (q_{v_c} - q_{t,v_c}) over the step (the tangential velocity
+ * times h; Coulomb's law does not depend on that scale).  The law: delta >= 0,
+ * lambda_n >= 0, delta lambda_n = 0; |lambda_f| <= mu lambda_n; s != 0 implies
+ * lambda_f = -mu lambda_n s/|s|; |lambda_f| < mu lambda_n implies s = 0.  The
+ * tangents: a = the coordinate axis of the smallest |n_i| (first on ties),
+ * t1 = (a - (a.n) n)/|a - (a.n) n|, t2 = n x t1. */
+void or_contact_frame(const double n[3], double t1[3], double t2[3]) {
+  int k = 0;
+  for (int i = 1; i < 3; ++i)
+    if (fabs(n[i]) < fabs(n[k])) k = i;
+  double a[3] = {0.0, 0.0, 0.0};
+  a[k] = 1.0;
+  double an = n[k];
+  double t[3], nrm = 0.0;
+  for (int i = 0; i < 3; ++i) {
+    t[i] = a[i] - an * n[i];
+    nrm += t[i] * t[i];
+  }
+  nrm = sqrt(nrm);
+  for (int i = 0; i < 3; ++i) t1[i] = t[i] / nrm;
+  t2[0] = n[1] * t1[2] - n[2] * t1[1];
+  t2[1] = n[2] * t1[0] - n[0] * t1[2];
+  t2[2] = n[0] * t1[1] - n[1] * t1[0];
+}
+
+/* frame rows of contact c: e[0..2] = n, e[3..5] = t1, e[6..8] = t2 */
+static void frame_rows(const double* n, double e[9]) {
+  e[0] = n[0]; e[1] = n[1]; e[2] = n[2];
+  or_contact_frame(n, e + 3, e + 6);
+}
+
+/* The friction NCP of one PD iteration on u = u0 + W lambda (3K rows, W_rs =
+ * (e_r . e_s) G_{c(r) c(s)} with G the K x K block of A~^{-1} between the
+ * contact vertices, so every row of contact c has the diagonal w_c = G_cc).
+ * READING (the per-iteration solve): semi-smooth Newton.  The normal row is
+ * the Fischer-Burmeister function of Eq. fb_n with r_c = w_c and the weights
+ * of Eq. omega_E_n; the tangent pair is the natural map F_f = lambda_f -
+ * P_D(lambda_f - s/w_c) onto the disk D of radius tau_c = mu lambda_n (the
+ * block projection of Sec. 4.7), tau taken at the current iterate.  Per
+ * Newton step, with z = lambda_f - s/w:
+ *   normal row: free if omega > 1e-12, equation W_n dl + (E/omega) dl_n =
+ *     -phi/omega; otherwise fixed at dl_n = -lambda_n;
+ *   tau = 0 (lambda_n = 0): both tangent rows fixed at dl_f = -lambda_f;
+ *   |z| <= tau (stick): both rows free, W_f dl = -s;
+ *   |z| > tau (slide): in the basis (z^, z^perp) the z^ row is fixed at
+ *     dl_z = tau - lambda_f . z^ and the perp row is free with
+ *     W_perp dl + w (1 - kappa)/kappa dl_perp = -w F_perp / kappa, kappa = tau/|z|.
+ * The fixed rows' increments move to the right-hand side; the free rows form
+ * a symmetric positive definite system (W's principal block plus a
+ * non-negative diagonal), solved by dense Cholesky.  Then lambda_n <-
+ * max(lambda_n, 0) and lambda_f <- its projection onto the disk of radius
+ * mu lambda_n.  Stop at max_c max(|phi_c|, w_c |F_f,c|) <= 1e-14 (both in
+ * displacement units) or after 50 steps; lambda carries over between PD
+ * iterations. */
+typedef struct fr_work {
+  int K;
+  const double* G;   /* K x K */
+  const double* e;   /* K x 9 frame rows */
+  double mu;
+  const double* u0;  /* 3K: free gap and slip (lambda = 0) */
+  double* lam;       /* 3K */
+  double res;
+  int iters;
+} fr_work;
+
+static void fr_u(const fr_work* f, const double* lam, double* u) {
+  int K = f->K;
+  for (int c = 0; c < K; ++c)
+    for (int a = 0; a < 3; ++a) {
+      double acc = f->u0[3 * c + a];
+      const double* ea = f->e + 9 * c + 3 * a;
+      for (int d = 0; d < K; ++d) {
+        double g = f->G[(size_t)c * K + d];
+        for (int b = 0; b < 3; ++b) {
+          const double* eb = f->e + 9 * d + 3 * b;
+          acc += (ea[0] * eb[0] + ea[1] * eb[1] + ea[2] * eb[2]) * g * lam[3 * d + b];
+        }
+      }
+      u[3 * c + a] = acc;
+    }
+}
+
+/* residual of every contact at lam; returns max */
+static double fr_residual(const fr_work* f, const double* lam, const double* u) {
+  double res = 0.0;
+  for (int c = 0; c < f->K; ++c) {
+    double w = f->G[(size_t)c * f->K + c];
+    double a = u[3 * c], bb = w * lam[3 * c];
+    double phi = a + bb - sqrt(a * a + bb * bb);
+    double tau = f->mu * lam[3 * c];
+    double z1 = lam[3 * c + 1] - u[3 * c + 1] / w, z2 = lam[3 * c + 2] - u[3 * c + 2] / w;
+    double nz = sqrt(z1 * z1 + z2 * z2), p1 = z1, p2 = z2;
+    if (tau <= 0.0) { p1 = 0.0; p2 = 0.0; }
+    else if (nz > tau) { p1 = tau * z1 / nz; p2 = tau * z2 / nz; }
+    double F1 = lam[3 * c + 1] - p1, F2 = lam[3 * c + 2] - p2;
+    double rf = w * sqrt(F1 * F1 + F2 * F2);
+    if (fabs(phi) > res) res = fabs(phi);
+    if (rf > res) res = rf;
+  }
+  return res;
+}
+
+static void fr_newton(fr_work* f) {
+  int K = f->K, R = 3 * K;
+  double* u = (double*)malloc(sizeof(double) * R);
+  double* dl = (double*)malloc(sizeof(double) * R);   /* increments in the row basis */
+  double* rb = (double*)malloc(sizeof(double) * 9 * K); /* row directions (world) */
+  int* isfree = (int*)malloc(sizeof(int) * R);
+  double* diag = (double*)malloc(sizeof(double) * R);
+  double* rhs = (double*)malloc(sizeof(double) * R);
+  int* fr = (int*)malloc(sizeof(int) * R);
+  double* M = (double*)malloc(sizeof(double) * (size_t)R * R);
+  double* rot = (double*)malloc(sizeof(double) * 4 * K); /* 2x2 tangent basis per contact */
+  fr_u(f, f->lam, u);
+  double res = fr_residual(f, f->lam, u);
+  int it = 0;
+  for (; it < 50 && res > 1e-14; ++it) {
+    for (int c = 0; c < K; ++c) {
+      double w = f->G[(size_t)c * K + c];
+      double* l = f->lam + 3 * c;
+      const double* e = f->e + 9 * c;
+      /* normal row */
+      double a = u[3 * c], bb = w * l[0], sq = sqrt(a * a + bb * bb);
+      double phi, om, E;
+      if (sq == 0.0) { phi = 0.0; om = 1.0 - 1.0 / sqrt(2.0); E = w * (1.0 - 1.0 / sqrt(2.0)); }
+      else { phi = a + bb - sq; om = 1.0 - a / sq; E = w * (1.0 - bb / sq); }
+      for (int i = 0; i < 3; ++i) rb[9 * c + i] = e[i];
+      if (om > 1e-12) { isfree[3 * c] = 1; diag[3 * c] = E / om; rhs[3 * c] = -phi / om; }
+      else { isfree[3 * c] = 0; dl[3 * c] = -l[0]; }
+      /* tangent rows */
+      double tau = f->mu * l[0];
+      double z1 = l[1] - u[3 * c + 1] / w, z2 = l[2] - u[3 * c + 2] / w;
+      double nz = sqrt(z1 * z1 + z2 * z2);
+      double* B = rot + 4 * c; /* rows: basis vectors in (t1, t2) coordinates */
+      if (tau <= 0.0) {
+        B[0] = 1.0; B[1] = 0.0; B[2] = 0.0; B[3] = 1.0;
+        isfree[3 * c + 1] = 0; isfree[3 * c + 2] = 0;
+        dl[3 * c + 1] = -l[1]; dl[3 * c + 2] = -l[2];
+      } else if (nz <= tau) {
+        B[0] = 1.0; B[1] = 0.0; B[2] = 0.0; B[3] = 1.0;
+        isfree[3 * c + 1] = 1; isfree[3 * c + 2] = 1;
+        diag[3 * c + 1] = 0.0; diag[3 * c + 2] = 0.0;
+        rhs[3 * c + 1] = -u[3 * c + 1]; rhs[3 * c + 2] = -u[3 * c + 2];
+      } else {
+        double h1 = z1 / nz, h2 = z2 / nz, kap = tau / nz;
+        B[0] = h1; B[1] = h2; B[2] = -h2; B[3] = h1;
+        double lz = l[1] * h1 + l[2] * h2, lp = -l[1] * h2 + l[2] * h1;
+        isfree[3 * c + 1] = 0; dl[3 * c + 1] = tau - lz;
+        isfree[3 * c + 2] = 1; diag[3 * c + 2] = w * (1.0 - kap) / kap;
+        /* F_perp = lambda_f . perp - P_perp = lp (P is along z^) */
+        rhs[3 * c + 2] = -w * lp / kap;
+      }
+      for (int r = 0; r < 2; ++r)
+        for (int i = 0; i < 3; ++i) rb[9 * c + 3 * (r + 1) + i] = B[2 * r] * e[3 + i] + B[2 * r + 1] * e[6 + i];
+    }
+    /* free rows, their system, fixed increments to the right-hand side */
+    int nfr = 0;
+    for (int r = 0; r < R; ++r) if (isfree[r]) fr[nfr++] = r;
+    for (int i = 0; i < nfr; ++i) {
+      int r = fr[i], c = r / 3;
+      const double* er = rb + 9 * c + 3 * (r % 3);
+      double t = rhs[r];
+      for (int s2 = 0; s2 < R; ++s2) {
+        if (isfree[s2]) continue;
+        int d = s2 / 3;
+        const double* es = rb + 9 * d + 3 * (s2 % 3);
+        t -= (er[0] * es[0] + er[1] * es[1] + er[2] * es[2]) * f->G[(size_t)c * K + d] * dl[s2];
+      }
+      rhs[r] = t;
+      for (int j = 0; j < nfr; ++j) {
+        int s2 = fr[j], d = s2 / 3;
+        const double* es = rb + 9 * d + 3 * (s2 % 3);
+        M[(size_t)i * nfr + j] = (er[0] * es[0] + er[1] * es[1] + er[2] * es[2]) * f->G[(size_t)c * K + d];
+      }
+      M[(size_t)i * nfr + i] += diag[r];
+    }
+    double* x = (double*)malloc(sizeof(double) * (nfr > 0 ? nfr : 1));
+    for (int i = 0; i < nfr; ++i) x[i] = rhs[fr[i]];
+    int ok = nfr == 0 || chol_solve(M, nfr, x);
+    if (!ok) { free(x); break; }
+    for (int i = 0; i < nfr; ++i) dl[fr[i]] = x[i];
+    free(x);
+    /* update in the (t1, t2) frame, then the block projection */
+    for (int c = 0; c < K; ++c) {
+      double* l = f->lam + 3 * c;
+      const double* B = rot + 4 * c;
+      double ln = l[0] + dl[3 * c];
+      double f1 = l[1] + B[0] * dl[3 * c + 1] + B[2] * dl[3 * c + 2];
+      double f2 = l[2] + B[1] * dl[3 * c + 1] + B[3] * dl[3 * c + 2];
+      ln = ln > 0.0 ? ln : 0.0;
+      double tau = f->mu * ln, nf = sqrt(f1 * f1 + f2 * f2);
+      if (tau <= 0.0) { f1 = 0.0; f2 = 0.0; }
+      else if (nf > tau) { f1 *= tau / nf; f2 *= tau / nf; }
+      l[0] = ln; l[1] = f1; l[2] = f2;
+    }
+    fr_u(f, f->lam, u);
+    res = fr_residual(f, f->lam, u);
+  }
+  f->res = res;
+  f->iters = it;
+  free(u); free(dl); free(rb); free(isfree); free(diag); free(rhs); free(fr); free(M); free(rot);
+}
+
+/* the friction Newton alone on a given G (K x K), normals (K x 3) and free
+ * kinematics u0 (3K: gap, slip along t1, t2), from lambda = 0; returns its
+ * iterations */
+int or_friction_ncp(int K, const double* G, const double* normals, const double* u0, double mu, double* lambda,
+                    double* res) {
+  double* e = (double*)malloc(sizeof(double) * 9 * (K > 0 ? K : 1));
+  for (int c = 0; c < K; ++c) frame_rows(normals + 3 * c, e + 9 * c);
+  for (int i = 0; i < 3 * K; ++i) lambda[i] = 0.0;
+  fr_work f = {K, G, e, mu, u0, lambda, 0.0, 0};
+  fr_newton(&f);
+  if (res) *res = f.res;
+  free(e);
+  return f.iters;
+}
+
 static void contact_setup(const or_scene* s, or_contacts* con) {
   int nv = s->nv, n3 = 3 * nv, K = con->K;
   double* r = (double*)calloc(n3, sizeof(double));
@@ -1222,6 +1455,14 @@ static void contact_setup(const or_scene* s, or_contacts* con) {
                   con->n[3 * c + 2] * con->n[3 * d + 2];
       con->W[(size_t)c * K + d] = nn * con->col[(size_t)c * nv + con->v[d]];
     }
+  if (con->mu_f > 0.0) {
+    con->e = (double*)malloc(sizeof(double) * 9 * (size_t)(K > 0 ? K : 1));
+    con->G = (double*)malloc(sizeof(double) * (size_t)(K > 0 ? K : 1) * (K > 0 ? K : 1));
+    for (int c = 0; c < K; ++c) {
+      frame_rows(con->n + 3 * c, con->e + 9 * c);
+      for (int d = 0; d < K; ++d) con->G[(size_t)c * K + d] = con->col[(size_t)c * nv + con->v[d]];
+    }
+  }
   free(r);
   free(x);
 }
@@ -1229,8 +1470,12 @@ static void contact_setup(const or_scene* s, or_contacts* con) {
 static void contact_free(or_contacts* con) {
   free(con->col);
   free(con->W);
+  free(con->e);
+  free(con->G);
   con->col = NULL;
   con->W = NULL;
+  con->e = NULL;
+  con->G = NULL;
 }
 
 /* FB values of all rows at lambda; returns max |phi| */
@@ -1290,8 +1535,46 @@ static void fb_newton(or_contacts* con, const double* dfree) {
   free(phi); free(om); free(E); free(M); free(rhs); free(act);
 }
 
+/* the same with friction: kinematics of every contact at qhat, the friction
+ * Newton, then qhat += sum_c a_c (lambda_n n + lambda_f1 t1 + lambda_f2 t2)
+ * (Eq. q_update with the frame folded into lambda) */
+static void contact_solve_fr(const or_scene* s, or_contacts* con, double* qhat) {
+  int K = con->K, nv = s->nv;
+  double* u0 = (double*)malloc(sizeof(double) * 3 * (size_t)K);
+  for (int c = 0; c < K; ++c) {
+    int v = con->v[c];
+    const double* q = qhat + 3 * v;
+    const double* p = con->qt + 3 * v;
+    const double* e = con->e + 9 * c;
+    u0[3 * c] = e[0] * q[0] + e[1] * q[1] + e[2] * q[2] - con->g[c];
+    for (int a = 1; a < 3; ++a)
+      u0[3 * c + a] = e[3 * a] * (q[0] - p[0]) + e[3 * a + 1] * (q[1] - p[1]) + e[3 * a + 2] * (q[2] - p[2]);
+  }
+  fr_work f = {K, con->G, con->e, con->mu_f, u0, con->lambda, 0.0, 0};
+  fr_newton(&f);
+  con->fb_res = f.res;
+  con->fb_iters = f.iters;
+  for (int c = 0; c < K; ++c) {
+    const double* l = con->lambda + 3 * c;
+    const double* e = con->e + 9 * c;
+    double imp[3];
+    for (int ax = 0; ax < 3; ++ax) imp[ax] = l[0] * e[ax] + l[1] * e[3 + ax] + l[2] * e[6 + ax];
+    if (imp[0] == 0.0 && imp[1] == 0.0 && imp[2] == 0.0) continue;
+    const double* a = con->col + (size_t)c * nv;
+    for (int i = 0; i < nv; ++i) {
+      if (s->fidx[i] < 0) continue;
+      for (int ax = 0; ax < 3; ++ax) qhat[3 * i + ax] += a[i] * imp[ax];
+    }
+  }
+  free(u0);
+}
+
 /* solve the contact problem at qhat (lambda warm) and add sum lambda_c a_c n_c to qhat */
 static void contact_solve(const or_scene* s, or_contacts* con, double* qhat) {
+  if (con->mu_f > 0.0) {
+    contact_solve_fr(s, con, qhat);
+    return;
+  }
   int K = con->K, nv = s->nv;
   double* dfree = (double*)malloc(sizeof(double) * K);
   for (int c = 0; c < K; ++c) {
@@ -1351,7 +1634,8 @@ static int step_forward_impl(const or_scene* s, const double* q_t, const double*
   double gate[4] = {0, 0, 0, 0};
   if (con) {
     contact_setup(s, con);
-    for (int c = 0; c < con->K; ++c) con->lambda[c] = 0.0;
+    int nl = con->mu_f > 0.0 ? 3 * con->K : con->K;
+    for (int c = 0; c < nl; ++c) con->lambda[c] = 0.0;
     con->fb_res = 0.0;
   }
   int kmax = force_iters > 0 ? force_iters + 1 : s->kmax_fwd;
@@ -1424,6 +1708,17 @@ int or_step_forward_contact(const or_scene* s, const double* q_t, const double* 
   return st;
 }
 
+int or_step_forward_friction(const or_scene* s, const double* q_t, const double* v_t, const double* f_ext,
+                             const double* q0, double* q_next, double* v_next, double* q_star_m1, int K,
+                             const int* cv, const double* cn, const double* cg, double mu_f, double fb_tol,
+                             double* lambda3, int force_iters, int* istats, double* dstats) {
+  or_contacts con = {K, cv, cn, cg, fb_tol, lambda3, NULL, NULL, 0.0, 0, mu_f, q_t, NULL, NULL};
+  int st = step_forward_impl(s, q_t, v_t, f_ext, q0, q_next, v_next, q_star_m1, force_iters, -1, 0, NULL, istats,
+                             dstats, K > 0 ? &con : NULL);
+  if (dstats) { dstats[4] = con.fb_res; dstats[5] = con.fb_iters; }
+  return st;
+}
+
 /* dense LU with partial pivoting, in place; solves A x = b (n small) */
 static int dense_lu_solve(double* A, int n, double* b) {
   for (int k = 0; k < n; ++k) {
@@ -1447,6 +1742,249 @@ static int dense_lu_solve(double* A, int n, double* b) {
     b[i] = sum / A[(size_t)i * n + i];
   }
   return 1;
+}
+
+/* LU with partial pivoting in place (n x n, row-major) and its solve */
+static int lu_factor(double* A, int n, int* piv) {
+  for (int k = 0; k < n; ++k) {
+    int p = k;
+    for (int i = k + 1; i < n; ++i) if (fabs(A[(size_t)i * n + k]) > fabs(A[(size_t)p * n + k])) p = i;
+    piv[k] = p;
+    if (A[(size_t)p * n + k] == 0.0) return 0;
+    if (p != k)
+      for (int j = 0; j < n; ++j) { double t = A[(size_t)k * n + j]; A[(size_t)k * n + j] = A[(size_t)p * n + j]; A[(size_t)p * n + j] = t; }
+    for (int i = k + 1; i < n; ++i) {
+      double f = A[(size_t)i * n + k] / A[(size_t)k * n + k];
+      A[(size_t)i * n + k] = f;
+      for (int j = k + 1; j < n; ++j) A[(size_t)i * n + j] -= f * A[(size_t)k * n + j];
+    }
+  }
+  return 1;
+}
+
+static void lu_solve(const double* A, int n, const int* piv, double* b) {
+  for (int k = 0; k < n; ++k) {
+    if (piv[k] != k) { double t = b[k]; b[k] = b[piv[k]]; b[piv[k]] = t; }
+    for (int i = k + 1; i < n; ++i) b[i] -= A[(size_t)i * n + k] * b[k];
+  }
+  for (int i = n - 1; i >= 0; --i) {
+    double sum = b[i];
+    for (int j = i + 1; j < n; ++j) sum -= A[(size_t)i * n + j] * b[j];
+    b[i] = sum / A[(size_t)i * n + i];
+  }
+}
+
+/* Adjoint rows of the frictional contact set at a converged step.  READING
+ * (Sec. 4.8 with the active set fixed, friction): with lambda_max the largest
+ * normal impulse, contact c is active if lambda_n > 1e-10 lambda_max (else it
+ * is dropped).  An active contact slides if |s| / w_c > 1e-8 mu lambda_n (s =
+ * T^T (q* - q_t) at its vertex, w_c its diagonal of A~^{-1}), else it sticks.
+ * Linearising the step's equations A q - b(q) - c - sum_c (impulse of c) = 0,
+ * n.q = g (active), T^T (q - q_t) = 0 (stick), lambda_f = -mu lambda_n s^
+ * (slide) gives the forward system [H, -B^T; C, 0] with H = A - K + D,
+ * D = sum_slide (mu lambda_n / |s|) p p^T on the contact vertex (p the unit
+ * tangent perpendicular to the slip), C the constraint rows (n; t1, t2 of
+ * sticking contacts) and B the rows along which the multipliers act: n, or
+ * n - mu s^_w for a sliding contact (the friction force follows lambda_n).
+ * The adjoint therefore solves H mu + C^T nu = qbar, B mu = 0; the sticking
+ * rows and D also route dL/dq_t += t nu (stick) + D mu (slide).  The fixed-point
+ * form adds one row per sliding contact along p with diagonal |s|/(mu
+ * lambda_n), which carries D mu = p eta. */
+typedef struct fr_rows {
+  int n;
+  int* vert;
+  int* kind;     /* 0 normal, 1 stick tangent, 2 slide perpendicular */
+  double* b;     /* 3 per row */
+  double* c;     /* 3 per row */
+  double* d;     /* diagonal */
+  double* dmat;  /* slide: the 3x3 D of the row's contact (kind 2 rows) */
+} fr_rows;
+
+static void fr_rows_build(const or_scene* s, const or_contacts* con, const double* q_star, const double* q_t,
+                          fr_rows* R) {
+  int K = con->K;
+  R->n = 0;
+  R->vert = (int*)malloc(sizeof(int) * 3 * (size_t)(K > 0 ? K : 1));
+  R->kind = (int*)malloc(sizeof(int) * 3 * (size_t)(K > 0 ? K : 1));
+  R->b = (double*)malloc(sizeof(double) * 9 * (size_t)(K > 0 ? K : 1));
+  R->c = (double*)malloc(sizeof(double) * 9 * (size_t)(K > 0 ? K : 1));
+  R->d = (double*)malloc(sizeof(double) * 3 * (size_t)(K > 0 ? K : 1));
+  R->dmat = (double*)calloc(27 * (size_t)(K > 0 ? K : 1), sizeof(double));
+  double lmax = 0.0;
+  for (int c = 0; c < K; ++c) lmax = con->lambda[3 * c] > lmax ? con->lambda[3 * c] : lmax;
+  for (int c = 0; c < K; ++c) {
+    double ln = con->lambda[3 * c];
+    if (!(lmax > 0.0 && ln > 1e-10 * lmax)) continue;
+    int v = con->v[c];
+    const double* e = con->e + 9 * c;
+    double w = con->G[(size_t)c * K + c];
+    double sl[2];
+    for (int a = 0; a < 2; ++a) {
+      const double* t = e + 3 * (a + 1);
+      sl[a] = t[0] * (q_star[3 * v] - q_t[3 * v]) + t[1] * (q_star[3 * v + 1] - q_t[3 * v + 1]) +
+              t[2] * (q_star[3 * v + 2] - q_t[3 * v + 2]);
+    }
+    double ns = sqrt(sl[0] * sl[0] + sl[1] * sl[1]);
+    double tau = con->mu_f * ln;
+    int r = R->n++;
+    R->vert[r] = v;
+    R->kind[r] = 0;
+    R->d[r] = 0.0;
+    for (int i = 0; i < 3; ++i) { R->b[3 * r + i] = e[i]; R->c[3 * r + i] = e[i]; }
+    if (ns / w > 1e-8 * tau) {
+      double h1 = sl[0] / ns, h2 = sl[1] / ns, sw[3], p[3];
+      for (int i = 0; i < 3; ++i) {
+        sw[i] = h1 * e[3 + i] + h2 * e[6 + i];
+        p[i] = -h2 * e[3 + i] + h1 * e[6 + i];
+        R->b[3 * r + i] = e[i] - con->mu_f * sw[i];
+      }
+      int r2 = R->n++;
+      R->vert[r2] = v;
+      R->kind[r2] = 2;
+      R->d[r2] = ns / tau;
+      for (int i = 0; i < 3; ++i) { R->b[3 * r2 + i] = p[i]; R->c[3 * r2 + i] = p[i]; }
+      for (int i = 0; i < 3; ++i)
+        for (int j = 0; j < 3; ++j) R->dmat[9 * r2 + 3 * i + j] = tau / ns * p[i] * p[j];
+    } else {
+      for (int a = 1; a < 3; ++a) {
+        int r2 = R->n++;
+        R->vert[r2] = v;
+        R->kind[r2] = 1;
+        R->d[r2] = 0.0;
+        for (int i = 0; i < 3; ++i) { R->b[3 * r2 + i] = e[3 * a + i]; R->c[3 * r2 + i] = e[3 * a + i]; }
+      }
+    }
+  }
+}
+
+static void fr_rows_free(fr_rows* R) {
+  free(R->vert); free(R->kind); free(R->b); free(R->c); free(R->d); free(R->dmat);
+}
+
+/* the frictional adjoint: mu (over all vertices) and the extra dL/dq_t of the
+ * sticking and sliding contacts; adj_mode 1 = dense system, 0 = projected
+ * fixed point; returns the status and writes the iterations */
+static int fr_adjoint(const or_scene* s, const or_contacts* con, const double* kst, const double* qbar,
+                      const double* q_star, const double* q_t, int adj_mode, double* mu, double* gqt_extra,
+                      int* iters_out) {
+  int nv = s->nv, n3 = 3 * nv, K = con->K;
+  fr_rows R;
+  fr_rows_build(s, con, q_star, q_t, &R);
+  int status = 0, iters = 0;
+  /* column of A~^{-1} for the contact vertex v: that of the first contact on v */
+  int* colof = (int*)malloc(sizeof(int) * (R.n > 0 ? R.n : 1));
+  for (int r = 0; r < R.n; ++r) {
+    colof[r] = -1;
+    for (int c = 0; c < K; ++c) if (con->v[c] == R.vert[r]) { colof[r] = c; break; }
+  }
+  for (int i = 0; i < n3; ++i) gqt_extra[i] = 0.0;
+  if (adj_mode == 1) {
+    /* [H, C^T; B, 0] [mu; nu] = [qbar; 0] over free coordinates and the
+     * normal and sticking rows (D explicit in H) */
+    int nf = s->nf;
+    int* rr = (int*)malloc(sizeof(int) * (R.n > 0 ? R.n : 1));
+    int nr = 0;
+    for (int r = 0; r < R.n; ++r) if (R.kind[r] != 2) rr[nr++] = r;
+    int N = 3 * nf + nr;
+    double* Mat = (double*)calloc((size_t)N * N, sizeof(double));
+    double* col = (double*)calloc(n3, sizeof(double));
+    double* Ac = (double*)malloc(sizeof(double) * n3);
+    double* Kc = (double*)malloc(sizeof(double) * n3);
+    for (int j = 0; j < 3 * nf; ++j) {
+      int vj = s->fvert[j / 3], aj = j % 3;
+      col[3 * vj + aj] = 1.0;
+      or_apply_A(s, col, Ac);
+      apply_K_stored(s, kst, col, Kc);
+      col[3 * vj + aj] = 0.0;
+      for (int i = 0; i < 3 * nf; ++i) {
+        int vi = s->fvert[i / 3], ai = i % 3;
+        Mat[(size_t)i * N + j] = Ac[3 * vi + ai] - Kc[3 * vi + ai];
+      }
+    }
+    for (int r = 0; r < R.n; ++r) {
+      if (R.kind[r] != 2) continue;
+      int fi = s->fidx[R.vert[r]];
+      for (int a = 0; a < 3; ++a)
+        for (int b2 = 0; b2 < 3; ++b2) Mat[(size_t)(3 * fi + a) * N + 3 * fi + b2] += R.dmat[9 * r + 3 * a + b2];
+    }
+    for (int k = 0; k < nr; ++k) {
+      int r = rr[k], fi = s->fidx[R.vert[r]];
+      for (int ax = 0; ax < 3; ++ax) {
+        Mat[(size_t)(3 * fi + ax) * N + 3 * nf + k] = R.c[3 * r + ax];
+        Mat[(size_t)(3 * nf + k) * N + 3 * fi + ax] = R.b[3 * r + ax];
+      }
+    }
+    double* rhs = (double*)calloc(N, sizeof(double));
+    for (int i = 0; i < 3 * nf; ++i) rhs[i] = qbar[3 * s->fvert[i / 3] + i % 3];
+    if (!dense_lu_solve(Mat, N, rhs)) status = -1;
+    for (int i = 0; i < 3 * nf; ++i) mu[3 * s->fvert[i / 3] + i % 3] = rhs[i];
+    for (int k = 0; k < nr; ++k) {
+      int r = rr[k];
+      if (R.kind[r] != 1) continue;
+      for (int ax = 0; ax < 3; ++ax) gqt_extra[3 * R.vert[r] + ax] += R.c[3 * r + ax] * rhs[3 * nf + k];
+    }
+    for (int r = 0; r < R.n; ++r) {
+      if (R.kind[r] != 2) continue;
+      int v = R.vert[r];
+      for (int a = 0; a < 3; ++a)
+        for (int b2 = 0; b2 < 3; ++b2) gqt_extra[3 * v + a] += R.dmat[9 * r + 3 * a + b2] * mu[3 * v + b2];
+    }
+    free(Mat); free(col); free(Ac); free(Kc); free(rhs); free(rr);
+  } else {
+    /* projected fixed point mu <- x - sum_r a_{v_r} c_r nu_r, x = A^-1 (qbar + K mu),
+     * (B A^-1 C^T + diag(d)) nu = B x */
+    int nr = R.n;
+    double* Mf = (double*)malloc(sizeof(double) * (size_t)(nr > 0 ? nr : 1) * (nr > 0 ? nr : 1));
+    int* piv = (int*)malloc(sizeof(int) * (nr > 0 ? nr : 1));
+    for (int r = 0; r < nr; ++r)
+      for (int q2 = 0; q2 < nr; ++q2) {
+        const double* br = R.b + 3 * r;
+        const double* cq = R.c + 3 * q2;
+        double g = con->col[(size_t)colof[r] * nv + R.vert[q2]];
+        Mf[(size_t)r * nr + q2] = (br[0] * cq[0] + br[1] * cq[1] + br[2] * cq[2]) * g + (r == q2 ? R.d[r] : 0.0);
+      }
+    if (nr > 0 && !lu_factor(Mf, nr, piv)) status = -1;
+    double* t = (double*)malloc(sizeof(double) * n3);
+    double* mun = (double*)malloc(sizeof(double) * n3);
+    double* nu = (double*)calloc(nr > 0 ? nr : 1, sizeof(double));
+    if (status == 0) {
+      status = 1;
+      for (iters = 1; iters <= s->kmax_bwd; ++iters) {
+        apply_K_stored(s, kst, mu, t);
+        for (int i = 0; i < n3; ++i) t[i] += qbar[i];
+        or_apply_Ainv(s, t, mun);
+        for (int r = 0; r < nr; ++r) {
+          const double* z = mun + 3 * R.vert[r];
+          nu[r] = R.b[3 * r] * z[0] + R.b[3 * r + 1] * z[1] + R.b[3 * r + 2] * z[2];
+        }
+        if (nr > 0) lu_solve(Mf, nr, piv, nu);
+        for (int r = 0; r < nr; ++r) {
+          const double* a = con->col + (size_t)colof[r] * nv;
+          for (int i = 0; i < nv; ++i) {
+            if (s->fidx[i] < 0) continue;
+            for (int ax = 0; ax < 3; ++ax) mun[3 * i + ax] -= nu[r] * a[i] * R.c[3 * r + ax];
+          }
+        }
+        double d = 0, nrm = 0;
+        for (int i = 0; i < n3; ++i) {
+          d += (mun[i] - mu[i]) * (mun[i] - mu[i]);
+          nrm += mun[i] * mun[i];
+        }
+        memcpy(mu, mun, sizeof(double) * n3);
+        if (sqrt(d) <= s->eps_adj * sqrt(nrm)) { status = 0; break; }
+      }
+      if (iters > s->kmax_bwd) iters = s->kmax_bwd;
+      for (int r = 0; r < nr; ++r) {
+        if (R.kind[r] == 0) continue;
+        for (int ax = 0; ax < 3; ++ax) gqt_extra[3 * R.vert[r] + ax] += R.c[3 * r + ax] * nu[r];
+      }
+    }
+    free(Mf); free(piv); free(t); free(mun); free(nu);
+  }
+  free(colof);
+  fr_rows_free(&R);
+  *iters_out = iters;
+  return status;
 }
 
 /* ------------------------------------------------------------------------ */
@@ -1513,7 +2051,12 @@ static int step_backward_impl(const or_scene* s, const double* q_t, const double
   int na = 0;
   int* act = NULL;
   double* WA = NULL;
-  if (con && con->K > 0) {
+  double* gqt_fr = NULL;
+  if (con && con->K > 0 && con->mu_f > 0.0) {
+    contact_setup(s, con);
+    gqt_fr = (double*)malloc(sizeof(double) * n3);
+    status = fr_adjoint(s, con, kst, qbar, q_star, q_t, adj_mode, mu, gqt_fr, &iters);
+  } else if (con && con->K > 0) {
     contact_setup(s, con);
     double lmax = 0.0;
     for (int c = 0; c < con->K; ++c) lmax = con->lambda[c] > lmax ? con->lambda[c] : lmax;
@@ -1522,7 +2065,9 @@ static int step_backward_impl(const or_scene* s, const double* q_t, const double
       if (lmax > 0.0 && con->lambda[c] > 1e-10 * lmax) act[na++] = c;
     WA = (double*)malloc(sizeof(double) * (size_t)(na > 0 ? na : 1) * (na > 0 ? na : 1));
   }
-  if (na > 0 && adj_mode == 1) {
+  if (gqt_fr) {
+    /* solved above */
+  } else if (na > 0 && adj_mode == 1) {
     /* dense saddle-point system */
     int nf = s->nf, N = 3 * nf + na;
     double* Mat = (double*)calloc((size_t)N * N, sizeof(double));
@@ -1693,13 +2238,14 @@ static int step_backward_impl(const or_scene* s, const double* q_t, const double
       if (s->fidx[v] < 0) { gq_t[i] = 0; gv_t[i] = 0; gf_ext[i] = 0; continue; }
       double m = s->mass[v];
       gq_t[i] = (m / (h * h) + s->alpha * m / h) * mu[i] + Bmu[i] / h - gv_next[i] / h;
+      if (gqt_fr) gq_t[i] += gqt_fr[i];
       gv_t[i] = m / h * mu[i];
       gf_ext[i] = mu[i];
     }
   if (istats) { istats[0] = iters; istats[1] = status; }
   if (dstats) { dstats[0] = rho; dstats[1] = tau; dstats[2] = dphi_act; dstats[3] = dphi_mod; }
   if (con && con->K > 0) contact_free(con);
-  free(act); free(WA);
+  free(act); free(WA); free(gqt_fr);
   free(qbar); free(qtilde); free(c); free(dq); free(Adq); free(mu); free(Bmu); free(kst);
   return status;
 }
@@ -1720,6 +2266,20 @@ int or_step_backward_contact(const or_scene* s, const double* q_t, const double*
   double* lam = (double*)malloc(sizeof(double) * (K > 0 ? K : 1));
   for (int c = 0; c < K; ++c) lam[c] = lambda[c];
   or_contacts con = {K, cv, cn, cg, 0.0, lam, NULL, NULL, 0.0, 0};
+  int st = step_backward_impl(s, q_t, v_t, f_ext, q_star, q_star_m1, gq_next, gv_next, gq_t, gv_t, gf_ext, g_logE,
+                              adj_mode, tau_force, istats, dstats, K > 0 ? &con : NULL);
+  free(lam);
+  return st;
+}
+
+int or_step_backward_friction(const or_scene* s, const double* q_t, const double* v_t, const double* f_ext,
+                              const double* q_star, const double* q_star_m1, const double* gq_next,
+                              const double* gv_next, double* gq_t, double* gv_t, double* gf_ext, double* g_logE,
+                              int adj_mode, double tau_force, int K, const int* cv, const double* cn,
+                              const double* cg, double mu_f, const double* lambda3, int* istats, double* dstats) {
+  double* lam = (double*)malloc(sizeof(double) * 3 * (size_t)(K > 0 ? K : 1));
+  for (int c = 0; c < 3 * K; ++c) lam[c] = lambda3[c];
+  or_contacts con = {K, cv, cn, cg, 0.0, lam, NULL, NULL, 0.0, 0, mu_f, q_t, NULL, NULL};
   int st = step_backward_impl(s, q_t, v_t, f_ext, q_star, q_star_m1, gq_next, gv_next, gq_t, gv_t, gf_ext, g_logE,
                               adj_mode, tau_force, istats, dstats, K > 0 ? &con : NULL);
   free(lam);

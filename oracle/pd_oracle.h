@@ -92,6 +92,24 @@ int or_step_backward_contact(const or_scene* s, const double* q_t, const double*
                              const double* gv_next, double* gq_t, double* gv_t, double* gf_ext, double* g_logE,
                              int adj_mode, double tau_force, int K, const int* cv, const double* cn,
                              const double* cg, const double* lambda, int* istats, double* dstats);
+/* Coulomb friction (Sec. 4.7; the reading is stated in pd_oracle.c): the same contact rows, each a frame
+ * (n, t1, t2) with impulses lambda3[3c..3c+2] (normal, t1, t2) and friction coefficient mu_f > 0.
+ * dstats[4] = final residual, dstats[5] = Newton steps of the last contact solve. */
+int or_step_forward_friction(const or_scene* s, const double* q_t, const double* v_t, const double* f_ext,
+                             const double* q0, double* q_next, double* v_next, double* q_star_m1, int K,
+                             const int* cv, const double* cn, const double* cg, double mu_f, double fb_tol,
+                             double* lambda3, int force_iters, int* istats, double* dstats);
+int or_step_backward_friction(const or_scene* s, const double* q_t, const double* v_t, const double* f_ext,
+                              const double* q_star, const double* q_star_m1, const double* gq_next,
+                              const double* gv_next, double* gq_t, double* gv_t, double* gf_ext, double* g_logE,
+                              int adj_mode, double tau_force, int K, const int* cv, const double* cn,
+                              const double* cg, double mu_f, const double* lambda3, int* istats, double* dstats);
+/* the contact frame of a unit normal */
+void or_contact_frame(const double n[3], double t1[3], double t2[3]);
+/* the friction Newton alone: G (K x K block of A~^{-1}), normals (K x 3), free kinematics u0 (3K: gap and
+ * the slip along t1, t2), from lambda = 0; returns its iterations */
+int or_friction_ncp(int K, const double* G, const double* normals, const double* u0, double mu, double* lambda,
+                    double* res);
 /* Delassus operator W (K x K, row-major) of a contact set */
 void or_contact_W(const or_scene* s, int K, const int* cv, const double* cn, double* W_out);
 /* FB semi-smooth Newton on delta = dfree + W lambda, from lambda = 0; returns its iterations */

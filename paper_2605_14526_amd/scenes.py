@@ -20,7 +20,7 @@ Conventions
 from __future__ import annotations
 
 import dataclasses
-from typing import Callable, Optional
+from typing import Tuple, Callable, Optional
 
 import numpy as np
 
@@ -144,6 +144,8 @@ class Scene:
     log_E_obs: Optional[np.ndarray] = None
     # energy model of the local step: 0 Neo-Hookean proximal map, 1 corotated + volume composite
     energy: int = 0
+    # Coulomb friction coefficient of the obstacles (0: frictionless contact)
+    friction: float = 0.0
 
     @property
     def n_v(self) -> int:
@@ -306,13 +308,15 @@ def shell_tets(tets: np.ndarray) -> np.ndarray:
 
 def drop_blob(res: int = 8, seed: int = 3001, n_spheres: int = 6, r_lo: float = 0.1, r_hi: float = 0.3,
               contrast: float = 100.0, nu: float = 0.49, h: float = 0.002, steps: int = 200,
-              drop_speed: float = 1.0, with_box: bool = True, aa_window: int = 1) -> Scene:
+              drop_speed: float = 1.0, with_box: bool = True, aa_window: int = 1, friction: float = 0.0,
+              lateral: Tuple[float, float] = (0.0, 0.0)) -> Scene:
     """Contact drop: a seeded implicit blob (union of ``n_spheres`` spheres with radii uniform in [r_lo, r_hi]
     and centres uniform in a 0.3 m cube), voxelised on a grid with ``res`` cells along its largest extent
     (largest face-connected component) and split 5 tets per cube.  The shell (tets touching the boundary
     surface) is ``contrast`` times stiffer than the interior (E 1e4 Pa inside).  Nothing is pinned; the
     blob starts half a cell above the ground plane z = 0, moving down at ``drop_speed``, under gravity;
     a static box under one half of the blob rises a quarter of the blob's height above the ground.
+    ``friction`` is the Coulomb coefficient of both obstacles, ``lateral`` the horizontal start velocity.
     res = 27 gives about 1e5 tets."""
     import scipy.ndimage
     rng = _rng(seed)
@@ -350,7 +354,7 @@ def drop_blob(res: int = 8, seed: int = 3001, n_spheres: int = 6, r_lo: float = 
     return Scene(f"drop_blob_r{res}", X, tets, np.zeros(X.shape[0], np.uint8), logE, nu=nu, rho=1000.0,
                  alpha=0.01, beta0=1e-3 * E_in * contrast, h=h, gravity=np.array([0.0, 0.0, -9.81]),
                  aa_window=aa_window, steps=steps, force_fn=None, target_centroid=target, fd_tets=fd,
-                 obstacles=obs, v_init=np.array([0.0, 0.0, -drop_speed]))
+                 obstacles=obs, v_init=np.array([lateral[0], lateral[1], -drop_speed]), friction=friction)
 
 
 def drop_family(k: int, res: int = 27, steps: int = 100) -> Scene:

@@ -264,6 +264,33 @@ int pd_scene_set_obstacles(pd_scene* scene, int n_planes, const double* planes, 
 int pd_contact_rows(const pd_scene* scene, int* K, int32_t* vert, double* normals, double* offsets,
                     double* lambda, int capacity);
 
+/* Coulomb friction on the obstacles (Sec. 4.7: the Signorini-Coulomb law
+ * with the friction disk of radius mu lam_n; Sec. 4.8: its adjoint with the
+ * active set fixed).  mu > 0 turns each contact row into a frame of three
+ * rows: the normal n and the tangents t1 = (a - (a.n) n)/|a - (a.n) n| (a the
+ * coordinate axis of the smallest |n_i|, the first on ties), t2 = n x t1.
+ * The slip of a contact is s = T^T (q_{v_c} - q_{t,v_c}) over the step.
+ * Detection then keeps one contact per vertex (the qualifying obstacle with
+ * the smallest distance at q_t, the first on ties), since a frame already
+ * spans the vertex's three directions.  Each PD iteration solves the contact
+ * law by semi-smooth Newton: the Fischer-Burmeister normal row of Eq. fb_n
+ * with the weights of Eq. omega_E_n, and the natural map lam_f -
+ * P_D(lam_f - s/w) onto the disk D of radius mu lam_n for the tangent pair
+ * (w = the contact vertex's diagonal of A~^{-1}); the free rows form a
+ * symmetric positive definite system factored by dense Cholesky, then
+ * lam_n >= 0 and the disk projection are enforced.  The gate's residual is
+ * max(|phi_FB|, w |lam_f - P_D(.)|).  pd_step_backward holds the active
+ * contacts fixed: sticking ones constrain the slip, sliding ones carry the
+ * friction -mu lam_n s/|s| differentiated with respect to s and lam_n; this
+ * adjoint is unsymmetric and runs the projected fixed point whatever
+ * adj_method says.  mu = 0 returns to frictionless contact.  Call after
+ * pd_scene_set_obstacles (which resets mu to 0); PD_ERR_INVALID_ARG without
+ * obstacles or for a negative or non-finite mu. */
+int pd_scene_set_friction(pd_scene* scene, double mu);
+/* Impulses of the last pd_step_forward per contact row (host, 3 per row:
+ * normal, t1, t2 components; tangents 0 without friction); capacity rows. */
+int pd_contact_impulses(const pd_scene* scene, double* lam3, int capacity);
+
 /* Forget the adjoint solutions kept for the warm start (adj_warm > 0), so the
  * next pd_step_backward starts from zero.  No device work. */
 int pd_adjoint_reset(pd_scene* scene);

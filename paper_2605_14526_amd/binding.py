@@ -31,7 +31,8 @@ EXPORTED = ["pd_scene_create", "pd_scene_destroy", "pd_scene_set_material", "pd_
             "pd_mpn_get_params", "pd_mpn_get_grads", "pd_mpn_set_output_scale", "pd_mpn_forward", "pd_mpn_loss_grad",
             "pd_mpn_adam_step", "pd_batch_create", "pd_batch_destroy", "pd_batch_config", "pd_batch_step_forward",
             "pd_batch_step_backward", "pd_scene_set_obstacles", "pd_contact_rows", "pd_last_error",
-            "pd_scene_factor_nnz", "pd_batch_kernel_timer", "pd_batch_kernel_timer_read"]
+            "pd_scene_factor_nnz", "pd_batch_kernel_timer", "pd_batch_kernel_timer_read",
+            "pd_scene_set_friction", "pd_contact_impulses"]
 
 
 class pd_mesh_desc(ctypes.Structure):
@@ -121,6 +122,8 @@ def lib() -> ctypes.CDLL:
     L.pd_batch_step_backward.argtypes = [vp, vp, vp, vp, vp, vp, vp, vp, vp, vp]
     L.pd_scene_set_obstacles.argtypes = [vp, i32, vp, i32, vp, dbl, i32, dbl]
     L.pd_contact_rows.argtypes = [vp, vp, vp, vp, vp, vp, i32]
+    L.pd_scene_set_friction.argtypes = [vp, dbl]
+    L.pd_contact_impulses.argtypes = [vp, vp, i32]
     L.pd_scene_factor_nnz.argtypes = [vp, vp]
     L.pd_batch_kernel_timer.argtypes = [vp, i32]
     L.pd_batch_kernel_timer_read.argtypes = [vp, vp, vp, vp]
@@ -183,7 +186,22 @@ class Scene:
                 tuple(np.asarray(sc.gravity, float)), **args)
         if getattr(sc, "obstacles", None):
             g.set_obstacles(sc.obstacles, **contact)
+            if getattr(sc, "friction", 0.0) > 0.0:
+                g.set_friction(sc.friction)
         return g
+
+    def set_friction(self, mu):
+        """Coulomb coefficient of the obstacles (pd_scene_set_friction; 0 = frictionless)."""
+        check(lib().pd_scene_set_friction(self.ptr, float(mu)), "pd_scene_set_friction")
+
+    def contact_impulses(self):
+        """Impulses of the last forward step's rows: (K, 3) normal, t1, t2 (pd_contact_impulses)."""
+        K = ctypes.c_int()
+        check(lib().pd_contact_rows(self.ptr, ctypes.byref(K), None, None, None, None, 0), "pd_contact_rows")
+        n = K.value
+        lam = np.zeros((max(n, 1), 3))
+        check(lib().pd_contact_impulses(self.ptr, lam.ctypes.data, n), "pd_contact_impulses")
+        return lam[:n]
 
     def set_obstacles(self, obs, max_contacts=512, fb_tol=1e-10):
         """Static obstacles {"planes": [(n, o)], "boxes": [(lo, hi)], "d_c": d} (pd_scene_set_obstacles)."""

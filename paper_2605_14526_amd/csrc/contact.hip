@@ -81,6 +81,7 @@ __global__ void __launch_bounds__(kContactThreads) k_contact_detect(VertArgs Vx,
   for (int c0 = 0; c0 < nf; c0 += kContactThreads) {
     const int i = c0 + tid;
     unsigned mask = 0;
+    double best0 = 0.0;
     int faces[kMaxObstacles];
 #pragma unroll
     for (int o = 0; o < kMaxObstacles; ++o) faces[o] = 0;
@@ -106,7 +107,15 @@ __global__ void __launch_bounds__(kContactThreads) k_contact_detect(VertArgs Vx,
           d1 = box_dist(B, x1, f1);
         }
         if (fmin(d0, d1) < O.d_c) {
-          mask |= 1u << o;
+          if (O.one_per_vertex) {
+            // keep the qualifying obstacle with the smallest distance at x0 (the first on ties)
+            if (mask == 0u || d0 < best0) {
+              mask = 1u << o;
+              best0 = d0;
+            }
+          } else {
+            mask |= 1u << o;
+          }
           faces[o] = f;
         }
       }
@@ -177,13 +186,16 @@ __global__ void __launch_bounds__(kBlock) k_store_cols(int nf, int nv, const dou
   if (s2 >= 0) cols[(size_t)s2 * nf + i] = x[2 * nv + i];
 }
 
-// W_cd = (n_c . n_d) a_{v_c}[v_d]
+// W_cd = (n_c . n_d) a_{v_c}[v_d]; with friction the scalar block G_cd = a_{v_c}[v_d]
+// (every row pair of two frames then couples by the product of their directions)
 __global__ void __launch_bounds__(kBlock) k_contact_W(ContactArgs C, double* __restrict__ W) {
   const int idx = blockIdx.x * blockDim.x + threadIdx.x;
   const int K = C.K;
   if (idx >= K * K) return;
   const int c = idx / K, d = idx - c * K;
-  const double nn = C.n[3 * c] * C.n[3 * d] + C.n[3 * c + 1] * C.n[3 * d + 1] + C.n[3 * c + 2] * C.n[3 * d + 2];
+  const double nn = C.mu > 0.0 ? 1.0
+                               : C.n[3 * c] * C.n[3 * d] + C.n[3 * c + 1] * C.n[3 * d + 1] +
+                                     C.n[3 * c + 2] * C.n[3 * d + 2];
   W[idx] = nn * C.cols[(size_t)C.slot[c] * C.nf + C.v[d]];
 }
 
@@ -197,7 +209,13 @@ __global__ void __launch_bounds__(kBlock) k_contact_start(ContactArgs C) {
     C.flags[2] = 0;
   }
   if (c >= C.K) return;
-  C.lam[c] = 0.0;
+  if (C.mu > 0.0) {
+    C.lam[3 * c] = 0.0;
+    C.lam[3 * c + 1] = 0.0;
+    C.lam[3 * c + 2] = 0.0;
+  } else {
+    C.lam[c] = 0.0;
+  }
   C.s[3 * c] = 0.0;
   C.s[3 * c + 1] = 0.0;
   C.s[3 * c + 2] = 0.0;
@@ -578,28 +596,31 @@ __global__ void __launch_bounds__(kContactThreads) k_contact_winv(ContactArgs C,
   }
 }
 
-// u = W_AA^{-1} (J_A z), s = u_c n_c (z = A~^{-1} r, the unprojected solve)
+// u = W_AA^{-1} (J_A z), s = u_c n_c (z = A~^{-1} r, the unprojected solve);
+// with friction the rows are measured along nb and act along n, and W holds
+// the inverse of their coupling matrix
 __global__ void __launch_bounds__(256) k_contact_proj(VertArgs Vx, ContactArgs C, const double* __restrict__ z,
                                                       const int* __restrict__ done) {
-  __shared__ double y[kMaxContactRows];
+  __shared__ double y[kMaxAdjRows];
   __shared__ int flag_s;
   const int tid = threadIdx.x, lane = tid & 63, wid = tid >> 6, nw = blockDim.x >> 6;
   const int na = C.K, nv = Vx.nv;
+  const double* mb = C.nb ? C.nb : C.n;
   if (tid == 0) flag_s = done ? *done : 0;
-  double yv[kMaxContactRows / 256];
+  double yv[kMaxAdjRows / 256];
 #pragma unroll
-  for (int r = 0; r < kMaxContactRows / 256; ++r) {
+  for (int r = 0; r < kMaxAdjRows / 256; ++r) {
     const int c = tid + 256 * r;
     yv[r] = 0.0;
     if (c < na) {
       const int v = C.v[c];
-      yv[r] = C.n[3 * c] * z[v] + C.n[3 * c + 1] * z[nv + v] + C.n[3 * c + 2] * z[2 * nv + v];
+      yv[r] = mb[3 * c] * z[v] + mb[3 * c + 1] * z[nv + v] + mb[3 * c + 2] * z[2 * nv + v];
     }
   }
   __syncthreads();
   if (flag_s) return;
 #pragma unroll
-  for (int r = 0; r < kMaxContactRows / 256; ++r)
+  for (int r = 0; r < kMaxAdjRows / 256; ++r)
     if (tid + 256 * r < na) y[tid + 256 * r] = yv[r];
   __syncthreads();
   for (int c = wid; c < na; c += nw) {
@@ -626,7 +647,483 @@ __global__ void __launch_bounds__(kBlock) k_contact_ckpt(ContactArgs C, int kmax
   rec[1 + kmax + 3 * c + 1] = C.n[3 * c + 1];
   rec[1 + kmax + 3 * c + 2] = C.n[3 * c + 2];
   rec[1 + 4 * kmax + c] = C.g[c];
-  rec[1 + 5 * kmax + c] = C.lam[c];
+  if (C.mu > 0.0) {
+    rec[1 + 5 * kmax + c] = C.lam[3 * c];
+    rec[1 + 6 * kmax + 2 * c] = C.lam[3 * c + 1];
+    rec[1 + 6 * kmax + 2 * c + 1] = C.lam[3 * c + 2];
+  } else {
+    rec[1 + 5 * kmax + c] = C.lam[c];
+  }
+}
+
+
+// ---------------------------------------------------------------- friction
+// Coulomb friction (Sec. 4.7 with the block projection onto the friction
+// disk).  Contact c acts on vertex v_c through the frame (n, t1, t2) with
+// t1 = (a - (a.n) n)/|a - (a.n) n| for a the coordinate axis of the smallest
+// |n_i| (first on ties) and t2 = n x t1.  Its kinematics are the gap
+// delta = n.q - g and the slip s = T^T (q - q_t) over the step; with
+// G_cd = a_{v_c}[v_d] the rows of two frames couple by (e_r . e_s) G_cd, and
+// every row of contact c has the diagonal w_c = G_cc.
+__device__ __forceinline__ void contact_frame(const double n[3], double t1[3], double t2[3]) {
+  int k = 0;
+  if (fabs(n[1]) < fabs(n[k])) k = 1;
+  if (fabs(n[2]) < fabs(n[k])) k = 2;
+  const double an = n[k];
+  double t[3], nrm = 0.0;
+#pragma unroll
+  for (int i = 0; i < 3; ++i) {
+    t[i] = (i == k ? 1.0 : 0.0) - an * n[i];
+    nrm += t[i] * t[i];
+  }
+  nrm = sqrt(nrm);
+#pragma unroll
+  for (int i = 0; i < 3; ++i) t1[i] = t[i] / nrm;
+  t2[0] = n[1] * t1[2] - n[2] * t1[1];
+  t2[1] = n[2] * t1[0] - n[0] * t1[2];
+  t2[2] = n[0] * t1[1] - n[1] * t1[0];
+}
+
+namespace {
+// offsets (in units of K) of the friction scratch
+enum { kFrE = 0, kFrU0 = 9, kFrU = 12, kFrRB = 15, kFrDiag = 24, kFrRhs = 27, kFrDl = 30, kFrRot = 33, kFrImp = 37,
+       kFrY = 40 };
+}  // namespace
+
+// u = u0 + W lam for every row: the world impulse of each contact, then one
+// wave per contact sums G_cd imp_d; returns max over contacts of the
+// residual max(|phi_FB|, w |F_f|) (identical in every thread).
+__device__ double fr_eval(const ContactArgs& C, double* red) {
+  const int tid = threadIdx.x, lane = tid & 63, wid = tid >> 6, nw = blockDim.x >> 6, nt = blockDim.x;
+  const int K = C.K;
+  double* e = C.frw + kFrE * K;
+  double* imp = C.frw + kFrImp * K;
+  double* u0 = C.frw + kFrU0 * K;
+  double* u = C.frw + kFrU * K;
+  for (int c = tid; c < K; c += nt) {
+    const double* l = C.lam + 3 * c;
+    const double* ec = e + 9 * c;
+#pragma unroll
+    for (int a = 0; a < 3; ++a) imp[3 * c + a] = l[0] * ec[a] + l[1] * ec[3 + a] + l[2] * ec[6 + a];
+  }
+  __syncthreads();
+  for (int c = wid; c < K; c += nw) {
+    const double* Gr = C.W + (size_t)c * K;
+    double y0 = 0.0, y1 = 0.0, y2 = 0.0;
+    for (int d = lane; d < K; d += 64) {
+      const double gcd = Gr[d];
+      y0 += gcd * imp[3 * d];
+      y1 += gcd * imp[3 * d + 1];
+      y2 += gcd * imp[3 * d + 2];
+    }
+    y0 = wsum(y0);
+    y1 = wsum(y1);
+    y2 = wsum(y2);
+    if (lane == 0) {
+      const double* ec = e + 9 * c;
+#pragma unroll
+      for (int a = 0; a < 3; ++a)
+        u[3 * c + a] = u0[3 * c + a] + (ec[3 * a] * y0 + ec[3 * a + 1] * y1 + ec[3 * a + 2] * y2);
+    }
+  }
+  __syncthreads();
+  double mx = 0.0;
+  for (int c = tid; c < K; c += nt) {
+    const double w = C.W[(size_t)c * K + c];
+    const double* l = C.lam + 3 * c;
+    const double a = u[3 * c], bb = w * l[0];
+    const double phi = a + bb - sqrt(a * a + bb * bb);
+    const double tau = C.mu * l[0];
+    const double z1 = l[1] - u[3 * c + 1] / w, z2 = l[2] - u[3 * c + 2] / w;
+    const double nz = sqrt(z1 * z1 + z2 * z2);
+    double p1 = z1, p2 = z2;
+    if (tau <= 0.0) {
+      p1 = 0.0;
+      p2 = 0.0;
+    } else if (nz > tau) {
+      p1 = tau * z1 / nz;
+      p2 = tau * z2 / nz;
+    }
+    const double F1 = l[1] - p1, F2 = l[2] - p2;
+    mx = fmax(mx, fmax(fabs(phi), w * sqrt(F1 * F1 + F2 * F2)));
+  }
+  mx = wmax(mx);
+  if (lane == 0) red[wid] = mx;
+  __syncthreads();
+  if (tid == 0) {
+    double m = 0.0;
+    for (int w = 0; w < nw; ++w) m = fmax(m, red[w]);
+    red[16] = m;
+  }
+  __syncthreads();
+  return red[16];
+}
+
+// One frictional contact solve per PD iteration, one 1024-thread workgroup:
+// semi-smooth Newton with the Fischer-Burmeister normal row (Eqs. fb_n,
+// omega_E_n, r_c = w_c) and the natural map of the friction disk of radius
+// tau = mu lam_n (tau at the current iterate).  Per step: a normal row is
+// free if omega > 1e-12 (W_n dl + E/omega dl_n = -phi/omega), else fixed at
+// dl_n = -lam_n; tau = 0 fixes both tangent rows at -lam_f; |z| <= tau (z =
+// lam_f - s/w: stick) frees both with W_f dl = -s; |z| > tau (slide) turns the
+// tangent basis to (z^, z^perp), fixes dl_z = tau - lam_f.z^ and frees the
+// perpendicular row with the diagonal w (1 - kappa)/kappa and right-hand side
+// -w F_perp/kappa (kappa = tau/|z|).  The free rows form W's principal block
+// plus a non-negative diagonal (SPD), factored by Cholesky with the fixed
+// increments moved to the right-hand side; then lam_n <- max(lam_n, 0) and
+// lam_f is projected onto the disk.  At most kFrMaxIter steps, stop at a
+// residual <= kFBTol; lam carries over between PD iterations.  Writes each
+// contact's world impulse to s.
+__global__ void __launch_bounds__(kContactThreads) k_contact_fr(VertArgs Vx, ContactArgs C,
+                                                                const double* __restrict__ qhat,
+                                                                const int* __restrict__ done) {
+  __shared__ double L[tri(kMaxNewtonRows + 1) + kMaxNewtonRows + 1];
+  __shared__ double red[17];
+  __shared__ int nfr_s, flag_s, fail_s;
+  const int tid = threadIdx.x, lane = tid & 63, wid = tid >> 6, nw = blockDim.x >> 6, nt = blockDim.x;
+  const int K = C.K, nv = Vx.nv;
+  if (tid == 0) {
+    flag_s = done ? *done : 0;
+    fail_s = 0;
+  }
+  __syncthreads();
+  if (flag_s) return;
+  double* e = C.frw + kFrE * K;
+  double* u0 = C.frw + kFrU0 * K;
+  double* u = C.frw + kFrU * K;
+  double* rb = C.frw + kFrRB * K;
+  double* diag = C.frw + kFrDiag * K;
+  double* rhs = C.frw + kFrRhs * K;
+  double* dl = C.frw + kFrDl * K;
+  double* rot = C.frw + kFrRot * K;
+  double* imp = C.frw + kFrImp * K;
+  int* isfree = C.fri;
+  int* frl = C.fri + 3 * K;
+  // frames and the free kinematics at qhat
+  for (int c = tid; c < K; c += nt) {
+    const int v = C.v[c];
+    double n[3] = {C.n[3 * c], C.n[3 * c + 1], C.n[3 * c + 2]}, t1[3], t2[3];
+    contact_frame(n, t1, t2);
+    double* ec = e + 9 * c;
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+      ec[a] = n[a];
+      ec[3 + a] = t1[a];
+      ec[6 + a] = t2[a];
+    }
+    const double q[3] = {qhat[v], qhat[nv + v], qhat[2 * nv + v]};
+    const double p[3] = {C.qt[v], C.qt[nv + v], C.qt[2 * nv + v]};
+    u0[3 * c] = n[0] * q[0] + n[1] * q[1] + n[2] * q[2] - C.g[c];
+    u0[3 * c + 1] = t1[0] * (q[0] - p[0]) + t1[1] * (q[1] - p[1]) + t1[2] * (q[2] - p[2]);
+    u0[3 * c + 2] = t2[0] * (q[0] - p[0]) + t2[1] * (q[1] - p[1]) + t2[2] * (q[2] - p[2]);
+  }
+  __syncthreads();
+  double res = fr_eval(C, red);
+  int it = 0;
+  for (; it < kFrMaxIter && res > kFBTol; ++it) {
+    // classify every contact's rows
+    for (int c = tid; c < K; c += nt) {
+      const double w = C.W[(size_t)c * K + c];
+      const double* l = C.lam + 3 * c;
+      const double* ec = e + 9 * c;
+      const double a = u[3 * c], bb = w * l[0], sq = sqrt(a * a + bb * bb);
+      double phi, om, E;
+      if (sq == 0.0) {
+        phi = 0.0;
+        om = 1.0 - 1.0 / sqrt(2.0);
+        E = w * (1.0 - 1.0 / sqrt(2.0));
+      } else {
+        phi = a + bb - sq;
+        om = 1.0 - a / sq;
+        E = w * (1.0 - bb / sq);
+      }
+#pragma unroll
+      for (int i = 0; i < 3; ++i) rb[9 * c + i] = ec[i];
+      if (om > kOmegaMin) {
+        isfree[3 * c] = 1;
+        diag[3 * c] = E / om;
+        rhs[3 * c] = -phi / om;
+      } else {
+        isfree[3 * c] = 0;
+        dl[3 * c] = -l[0];
+      }
+      const double tau = C.mu * l[0];
+      const double z1 = l[1] - u[3 * c + 1] / w, z2 = l[2] - u[3 * c + 2] / w;
+      const double nz = sqrt(z1 * z1 + z2 * z2);
+      double B0 = 1.0, B1 = 0.0, B2 = 0.0, B3 = 1.0;
+      if (tau <= 0.0) {
+        isfree[3 * c + 1] = 0;
+        isfree[3 * c + 2] = 0;
+        dl[3 * c + 1] = -l[1];
+        dl[3 * c + 2] = -l[2];
+      } else if (nz <= tau) {
+        isfree[3 * c + 1] = 1;
+        isfree[3 * c + 2] = 1;
+        diag[3 * c + 1] = 0.0;
+        diag[3 * c + 2] = 0.0;
+        rhs[3 * c + 1] = -u[3 * c + 1];
+        rhs[3 * c + 2] = -u[3 * c + 2];
+      } else {
+        const double h1 = z1 / nz, h2 = z2 / nz, kap = tau / nz;
+        B0 = h1;
+        B1 = h2;
+        B2 = -h2;
+        B3 = h1;
+        const double lz = l[1] * h1 + l[2] * h2, lp = -l[1] * h2 + l[2] * h1;
+        isfree[3 * c + 1] = 0;
+        dl[3 * c + 1] = tau - lz;
+        isfree[3 * c + 2] = 1;
+        diag[3 * c + 2] = w * (1.0 - kap) / kap;
+        rhs[3 * c + 2] = -w * lp / kap;
+      }
+      double* R = rot + 4 * c;
+      R[0] = B0;
+      R[1] = B1;
+      R[2] = B2;
+      R[3] = B3;
+#pragma unroll
+      for (int i = 0; i < 3; ++i) {
+        rb[9 * c + 3 + i] = B0 * ec[3 + i] + B1 * ec[6 + i];
+        rb[9 * c + 6 + i] = B2 * ec[3 + i] + B3 * ec[6 + i];
+      }
+    }
+    __syncthreads();
+    if (tid == 0) {
+      int nfr = 0;
+      for (int r = 0; r < 3 * K; ++r)
+        if (isfree[r]) frl[nfr++] = r;
+      nfr_s = nfr;
+    }
+    // world increments of the fixed rows
+    for (int c = tid; c < K; c += nt) {
+#pragma unroll
+      for (int i = 0; i < 3; ++i) {
+        double acc = 0.0;
+#pragma unroll
+        for (int a = 0; a < 3; ++a)
+          if (!isfree[3 * c + a]) acc += dl[3 * c + a] * rb[9 * c + 3 * a + i];
+        imp[3 * c + i] = acc;
+      }
+    }
+    __syncthreads();
+    // right-hand sides of the free rows lose the fixed rows' coupling
+    for (int c = wid; c < K; c += nw) {
+      const double* Gr = C.W + (size_t)c * K;
+      double y0 = 0.0, y1 = 0.0, y2 = 0.0;
+      for (int d = lane; d < K; d += 64) {
+        const double gcd = Gr[d];
+        y0 += gcd * imp[3 * d];
+        y1 += gcd * imp[3 * d + 1];
+        y2 += gcd * imp[3 * d + 2];
+      }
+      y0 = wsum(y0);
+      y1 = wsum(y1);
+      y2 = wsum(y2);
+      if (lane < 3 && isfree[3 * c + lane]) {
+        const double* r = rb + 9 * c + 3 * lane;
+        rhs[3 * c + lane] -= r[0] * y0 + r[1] * y1 + r[2] * y2;
+      }
+    }
+    __syncthreads();
+    const int nfr = nfr_s;
+    double* Lm = (nfr <= kMaxNewtonRows) ? L : C.Lg;
+    if (nfr > 0) {
+      const int cntM = tri(nfr);
+      for (int p = tid; p < cntM + nfr; p += nt) {
+        if (p < cntM) {
+          int i = (int)((sqrt(8.0 * p + 1.0) - 1.0) * 0.5);
+          while (tri(i + 1) <= p) ++i;
+          while (tri(i) > p) --i;
+          const int j = p - tri(i);
+          const int ri = frl[i], rj = frl[j];
+          const int ci = ri / 3, cj = rj / 3;
+          const double* a = rb + 9 * ci + 3 * (ri - 3 * ci);
+          const double* b = rb + 9 * cj + 3 * (rj - 3 * cj);
+          double m = (a[0] * b[0] + a[1] * b[1] + a[2] * b[2]) * C.W[(size_t)ci * K + cj];
+          if (i == j) m += diag[ri];
+          Lm[p] = m;
+        } else {
+          Lm[p] = rhs[frl[p - cntM]];
+        }
+      }
+      __syncthreads();
+      if (!chol_packed(Lm, nfr, true, &fail_s)) break;
+      double* y = Lm + tri(nfr);
+      for (int i = nfr - 1; i >= 0; --i) {
+        if (tid == 0) y[i] = y[i] / Lm[tri(i) + i];
+        __syncthreads();
+        const double xi = y[i];
+        for (int j = tid; j < i; j += nt) y[j] -= Lm[tri(i) + j] * xi;
+        __syncthreads();
+      }
+      for (int i = tid; i < nfr; i += nt) dl[frl[i]] = y[i];
+    }
+    __syncthreads();
+    // update in the (t1, t2) frame, then the block projection
+    for (int c = tid; c < K; c += nt) {
+      double* l = C.lam + 3 * c;
+      const double* R = rot + 4 * c;
+      double ln = l[0] + dl[3 * c];
+      double f1 = l[1] + R[0] * dl[3 * c + 1] + R[2] * dl[3 * c + 2];
+      double f2 = l[2] + R[1] * dl[3 * c + 1] + R[3] * dl[3 * c + 2];
+      ln = ln > 0.0 ? ln : 0.0;
+      const double tau = C.mu * ln, nfv = sqrt(f1 * f1 + f2 * f2);
+      if (tau <= 0.0) {
+        f1 = 0.0;
+        f2 = 0.0;
+      } else if (nfv > tau) {
+        f1 *= tau / nfv;
+        f2 *= tau / nfv;
+      }
+      l[0] = ln;
+      l[1] = f1;
+      l[2] = f2;
+    }
+    __syncthreads();
+    res = fr_eval(C, red);
+  }
+  // the world impulse of every contact at the final lam
+  for (int c = tid; c < K; c += nt) {
+    const double* l = C.lam + 3 * c;
+    const double* ec = e + 9 * c;
+#pragma unroll
+    for (int a = 0; a < 3; ++a) C.s[3 * c + a] = l[0] * ec[a] + l[1] * ec[3 + a] + l[2] * ec[6 + a];
+  }
+  if (tid == 0) {
+    C.fb[0] = res;
+    C.fb[1] = (double)it;
+    if (fail_s) C.flags[2] = 1;
+  }
+}
+
+// Inverse of the adjoint rows' coupling matrix M_rq = (b_r . c_q) a_{v_r}[v_q]
+// + d_r [r = q] (b = nb, c = n; unsymmetric where a sliding contact's friction
+// follows its normal impulse): LU with partial pivoting in the global scratch,
+// then one thread per column solves L U x = P e_j into Minv.
+__global__ void __launch_bounds__(kContactThreads) k_contact_minv(ContactArgs C, double* __restrict__ Minv) {
+  __shared__ double pv[kContactThreads / 64];
+  __shared__ int pi[kContactThreads / 64];
+  __shared__ int piv_s;
+  const int tid = threadIdx.x, lane = tid & 63, wid = tid >> 6, nw = blockDim.x >> 6, nt = blockDim.x;
+  const int n = C.K, nf = C.nf;
+  double* A = C.Lg;
+  int* perm = C.fri;
+  for (int p = tid; p < n * n; p += nt) {
+    const int r = p / n, q = p - r * n;
+    const double* b = C.nb + 3 * r;
+    const double* c = C.n + 3 * q;
+    double m = (b[0] * c[0] + b[1] * c[1] + b[2] * c[2]) * C.cols[(size_t)C.slot[q] * nf + C.v[r]];
+    if (r == q && C.dg) m += C.dg[r];
+    A[p] = m;
+  }
+  __syncthreads();
+  for (int k = 0; k < n; ++k) {
+    // pivot: the largest |A_ik|, i >= k (the first on ties)
+    double best = -1.0;
+    int bi = k;
+    for (int i = k + tid; i < n; i += nt) {
+      const double a = fabs(A[(size_t)i * n + k]);
+      if (a > best) {
+        best = a;
+        bi = i;
+      }
+    }
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) {
+      const double ob = __shfl_xor(best, off, 64);
+      const int oi = __shfl_xor(bi, off, 64);
+      if (ob > best || (ob == best && oi < bi)) {
+        best = ob;
+        bi = oi;
+      }
+    }
+    if (lane == 0) {
+      pv[wid] = best;
+      pi[wid] = bi;
+    }
+    __syncthreads();
+    if (tid == 0) {
+      double b = pv[0];
+      int i0 = pi[0];
+      for (int w = 1; w < nw; ++w)
+        if (pv[w] > b || (pv[w] == b && pi[w] < i0)) {
+          b = pv[w];
+          i0 = pi[w];
+        }
+      piv_s = (b > 0.0) ? i0 : -1;
+      perm[k] = i0;
+    }
+    __syncthreads();
+    const int p = piv_s;
+    if (p < 0) {
+      if (tid == 0) C.flags[2] = 1;
+      return;
+    }
+    if (p != k)
+      for (int j = tid; j < n; j += nt) {
+        const double t = A[(size_t)k * n + j];
+        A[(size_t)k * n + j] = A[(size_t)p * n + j];
+        A[(size_t)p * n + j] = t;
+      }
+    __syncthreads();
+    const double akk = A[(size_t)k * n + k];
+    for (int i = k + 1 + tid; i < n; i += nt) A[(size_t)i * n + k] /= akk;
+    __syncthreads();
+    const int R = n - 1 - k;
+    for (int q = tid; q < R * R; q += nt) {
+      const int i = k + 1 + q / R, j = k + 1 + q % R;
+      A[(size_t)i * n + j] -= A[(size_t)i * n + k] * A[(size_t)k * n + j];
+    }
+    __syncthreads();
+  }
+  for (int j = tid; j < n; j += nt) {
+    // x = P e_j: apply the row swaps in order, then the two substitutions
+    double* x = Minv;  // column j, stride n
+    for (int i = 0; i < n; ++i) x[(size_t)i * n + j] = (i == j) ? 1.0 : 0.0;
+    for (int k = 0; k < n; ++k) {
+      const int p = perm[k];
+      if (p != k) {
+        const double t = x[(size_t)k * n + j];
+        x[(size_t)k * n + j] = x[(size_t)p * n + j];
+        x[(size_t)p * n + j] = t;
+      }
+    }
+    for (int i = 1; i < n; ++i) {
+      double t = x[(size_t)i * n + j];
+      for (int k = 0; k < i; ++k) t -= A[(size_t)i * n + k] * x[(size_t)k * n + j];
+      x[(size_t)i * n + j] = t;
+    }
+    for (int i = n - 1; i >= 0; --i) {
+      double t = x[(size_t)i * n + j];
+      for (int k = i + 1; k < n; ++k) t -= A[(size_t)i * n + k] * x[(size_t)k * n + j];
+      x[(size_t)i * n + j] = t / A[(size_t)i * n + i];
+    }
+  }
+}
+
+// slip displacement q* - q_t and the diagonal a_{v_c}[v_c] of each listed
+// contact vertex: out[4c .. 4c+3]
+__global__ void __launch_bounds__(kBlock) k_contact_slip(VertArgs Vx, ContactArgs C, const double* __restrict__ qs,
+                                                         const double* __restrict__ qt, double* __restrict__ out) {
+  const int c = blockIdx.x * blockDim.x + threadIdx.x;
+  if (c >= C.K) return;
+  const int v = C.v[c], nv = Vx.nv;
+#pragma unroll
+  for (int a = 0; a < 3; ++a) out[4 * c + a] = qs[a * nv + v] - qt[a * nv + v];
+  out[4 * c + 3] = C.cols[(size_t)C.slot[c] * C.nf + v];
+}
+
+// dL/dq_t += u_r c_r of the sticking and sliding rows (kind != 0), in the
+// caller's order; one thread walks the rows (several rows share a vertex)
+__global__ void __launch_bounds__(64) k_contact_route(VertArgs Vx, ContactArgs C, const int* __restrict__ kind,
+                                                      double* __restrict__ gq_t) {
+  if (threadIdx.x != 0) return;
+  for (int r = 0; r < C.K; ++r) {
+    if (kind[r] == 0) continue;
+    const int o = Vx.v_orig[C.v[r]];
+#pragma unroll
+    for (int a = 0; a < 3; ++a) gq_t[3 * o + a] += C.s[3 * r + a];
+  }
 }
 
 // ---------------------------------------------------------------- launchers
@@ -657,6 +1154,20 @@ void launch_contact_winv(const ContactArgs& C, double* Winv, hipStream_t s) {
 }
 void launch_contact_proj(const VertArgs& V, const ContactArgs& C, const double* z, const int* done, hipStream_t s) {
   hipLaunchKernelGGL(k_contact_proj, dim3(1), dim3(256), 0, s, V, C, z, done);
+}
+void launch_contact_fr(const VertArgs& V, const ContactArgs& C, const double* qhat, const int* done, hipStream_t s) {
+  hipLaunchKernelGGL(k_contact_fr, dim3(1), dim3(kContactThreads), 0, s, V, C, qhat, done);
+}
+void launch_contact_minv(const ContactArgs& C, double* Minv, hipStream_t s) {
+  hipLaunchKernelGGL(k_contact_minv, dim3(1), dim3(kContactThreads), 0, s, C, Minv);
+}
+void launch_contact_slip(const VertArgs& V, const ContactArgs& C, const double* qstar, const double* qt, double* out,
+                         hipStream_t s) {
+  if (C.K > 0)
+    hipLaunchKernelGGL(k_contact_slip, dim3((C.K + kBlock - 1) / kBlock), dim3(kBlock), 0, s, V, C, qstar, qt, out);
+}
+void launch_contact_route(const VertArgs& V, const ContactArgs& C, const int* kind, double* gq_t, hipStream_t s) {
+  if (C.K > 0 && gq_t) hipLaunchKernelGGL(k_contact_route, dim3(1), dim3(64), 0, s, V, C, kind, gq_t);
 }
 void launch_contact_ckpt(const ContactArgs& C, int kmax, double* rec, hipStream_t s) {
   hipLaunchKernelGGL(k_contact_ckpt, dim3((std::max(C.K, 1) + kBlock - 1) / kBlock), dim3(kBlock), 0, s, C, kmax,

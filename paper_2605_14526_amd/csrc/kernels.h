@@ -175,26 +175,39 @@ constexpr int kMaxObstacles = 8;
 constexpr int kFBMaxIter = 30;
 constexpr double kFBTol = 1e-14;
 constexpr double kOmegaMin = 1e-12;
+constexpr int kFrMaxIter = 50;          // Newton steps of one frictional contact solve
+constexpr int kMaxAdjRows = 3 * kMaxContactRows;  // adjoint rows with friction (at most three per contact)
+constexpr int kFrWork = 48;             // doubles of friction scratch per contact
 struct ContactArgs {
   int K;
   int nf;
   const int* v;        // K library vertex ids
-  const double* n;     // 3K unit normals, row-major (n[3c + a])
+  const double* n;     // 3K unit normals, row-major (n[3c + a]); adjoint: the rows' constraint directions
   const double* g;     // K offsets: gap = n . q_v - g
   const int* slot;     // K column slots
   const double* cols;  // columns: a_v at cols[slot * nf + row]
-  const double* W;     // K x K Delassus operator (forward) or its inverse on the active rows (adjoint)
-  double* lam;         // K impulses
-  double* s;           // 3K: lam_c n_c (forward) or u_c n_c (adjoint projection)
+  const double* W;     // K x K Delassus operator (forward; with friction the scalar block G_cd = a_{v_c}[v_d])
+                       // or the inverse of the adjoint rows' coupling matrix
+  double* lam;         // K impulses (3K with friction: normal, t1, t2)
+  double* s;           // 3K: the world impulse of each row (forward) or u_r c_r (adjoint projection)
   double* fb;          // [0] FB residual, [1] Newton iterations of the last solve
-  int* flags;          // [0] candidate rows found, [1] unused, [2] factor not SPD
+  int* flags;          // [0] candidate rows found, [1] unused, [2] factor not SPD / singular
   double* Lg;          // global scratch for dense factorizations larger than the LDS ones
+  // Coulomb friction (mu > 0)
+  double mu = 0.0;
+  const double* qt = nullptr;   // q_t in library order (slip start)
+  double* frw = nullptr;        // kFrWork x K doubles of scratch
+  int* fri = nullptr;           // 6K ints of scratch
+  const double* nb = nullptr;   // adjoint: 3 per row, the directions along which the multipliers act
+                                // (null: n); with friction they differ from n on sliding normal rows
+  const double* dg = nullptr;   // adjoint: per-row diagonal of the coupling matrix (null: none)
 };
 struct ObsArgs {
   int n_planes, n_boxes;
   const double* planes;  // 4 per plane: unit normal, offset
   const double* boxes;   // 6 per box: lo xyz, hi xyz
   double d_c, h;
+  int one_per_vertex = 0;  // keep only the closest qualifying obstacle of each vertex (friction)
 };
 
 // Everything a kernel needs about one scene, for launches that span many
@@ -281,6 +294,14 @@ void launch_contact_fb(const VertArgs& V, const ContactArgs& C, const double* qh
 void launch_contact_winv(const ContactArgs& C, double* Winv, hipStream_t s);
 void launch_contact_proj(const VertArgs& V, const ContactArgs& C, const double* z, const int* done, hipStream_t s);
 void launch_contact_ckpt(const ContactArgs& C, int kmax, double* rec, hipStream_t s);
+// friction: the per-iteration Newton (forward), the inverse of the adjoint rows' unsymmetric coupling
+// matrix, the contact vertices' slip and diagonal for the adjoint's classification, and the routing of the
+// sticking / sliding rows' multipliers to dL/dq_t (caller order; kind 0 rows skipped)
+void launch_contact_fr(const VertArgs& V, const ContactArgs& C, const double* qhat, const int* done, hipStream_t s);
+void launch_contact_minv(const ContactArgs& C, double* Minv, hipStream_t s);
+void launch_contact_slip(const VertArgs& V, const ContactArgs& C, const double* qstar, const double* qt, double* out,
+                         hipStream_t s);
+void launch_contact_route(const VertArgs& V, const ContactArgs& C, const int* kind, double* gq_t, hipStream_t s);
 int contact_apply_blocks(int nf);
 void launch_contact_apply_fwd(const VertArgs& V, const StepState& St, const RedArgs& R, const ContactArgs& C, int k,
                               hipStream_t s);

@@ -1382,9 +1382,9 @@ __global__ void __launch_bounds__(kBottomThreads) PD_ROW_WALK k_bottom(VertArgs 
 // with s_c = lam_c n_c (forward, Eq. q_update) or u_c n_c (adjoint
 // projection); rows with s_c = 0 are skipped.  The row data sit in LDS.
 struct ContactLds {
-  double s[3 * kMaxContactRows];
-  int slot[kMaxContactRows];
-  int v[kMaxContactRows];
+  double s[3 * kMaxAdjRows];
+  int slot[kMaxAdjRows];
+  int v[kMaxAdjRows];
 };
 
 __device__ __forceinline__ void contact_lds_load(const ContactArgs& C, ContactLds& L) {

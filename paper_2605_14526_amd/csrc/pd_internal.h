@@ -201,6 +201,14 @@ struct Scene {
   double* h_crec = nullptr;     // pinned: one checkpoint contact record
   int c_last_K = 0, c_last_active = 0, c_cols_built = 0;
   double c_last_fb = 0.0;
+  // Coulomb friction (mu_f > 0): scratch of the frictional Newton, and the
+  // adjoint rows' multiplier directions, diagonals and kinds
+  double mu_f = 0.0;
+  double* c_frw = nullptr;
+  int* c_fri = nullptr;
+  double *a_nb = nullptr, *a_dg = nullptr, *c_slip = nullptr;
+  int* a_kind = nullptr;
+  bool a_fric = false;  // the current backward step has friction rows
 };
 
 }  // namespace pdhot

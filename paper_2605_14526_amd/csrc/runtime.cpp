@@ -229,6 +229,9 @@ void contact_free(Scene& S) {
   dfree(S.obs); dfree(S.c_v); dfree(S.c_slot); dfree(S.c_flags); dfree(S.c_n); dfree(S.c_g); dfree(S.c_lam);
   dfree(S.c_s); dfree(S.c_W); dfree(S.c_fb); dfree(S.a_v); dfree(S.a_slot); dfree(S.a_n); dfree(S.a_s);
   dfree(S.a_Winv); dfree(S.c_Lg); dfree(S.cols);
+  dfree(S.c_frw); dfree(S.c_fri); dfree(S.a_nb); dfree(S.a_dg); dfree(S.c_slip); dfree(S.a_kind);
+  S.mu_f = 0.0;
+  S.a_fric = false;
   if (S.h_cbuf) (void)hipHostFree(S.h_cbuf);
   if (S.h_crec) (void)hipHostFree(S.h_crec);
   S.h_cbuf = nullptr;
@@ -887,6 +890,14 @@ ContactArgs contact_args(Scene& S, int K, bool adjoint) {
   C.fb = S.c_fb;
   C.flags = S.c_flags;
   C.Lg = S.c_Lg;
+  C.mu = S.mu_f;
+  C.qt = S.qt;
+  C.frw = S.c_frw;
+  C.fri = S.c_fri;
+  if (adjoint && S.a_fric) {
+    C.nb = S.a_nb;
+    C.dg = S.a_dg;
+  }
   return C;
 }
 
@@ -951,6 +962,7 @@ int contact_rows(Scene& S, hipStream_t st) {
   O.boxes = S.obs + 4 * S.n_planes;
   O.d_c = S.d_c;
   O.h = S.h;
+  O.one_per_vertex = S.mu_f > 0.0 ? 1 : 0;
   launch_contact_detect(V, S.qt, S.vt, O, S.c_kmax, S.c_v, S.c_n, S.c_g, S.c_flags, st);
   PD_HIP(hipMemcpyAsync(S.h_cbuf, S.c_flags, 4 * sizeof(int), hipMemcpyDeviceToHost, st));
   PD_HIP(hipStreamSynchronize(st));
@@ -972,12 +984,102 @@ int contact_rows(Scene& S, hipStream_t st) {
   return K;
 }
 
+// The adjoint rows of the active frictional contacts (Sec. 4.8 with the active
+// set fixed): each keeps its normal row; a contact whose slip over the step
+// |s| exceeds 1e-8 mu lam_n w_c (w_c = a_{v_c}[v_c]) slides and adds one row
+// along p, the tangent perpendicular to the slip, with diagonal |s|/(mu
+// lam_n), and its normal multiplier then acts along n - mu s^ (the friction
+// force follows lam_n); a sticking contact adds its rows t1, t2.  The rows
+// act along nb and constrain along n; the inverse of their coupling matrix
+// goes to a_Winv.  Returns the row count.
+static void host_frame(const double n[3], double t1[3], double t2[3]) {
+  int k = 0;
+  if (std::fabs(n[1]) < std::fabs(n[k])) k = 1;
+  if (std::fabs(n[2]) < std::fabs(n[k])) k = 2;
+  const double an = n[k];
+  double t[3], nrm = 0.0;
+  for (int i = 0; i < 3; ++i) {
+    t[i] = (i == k ? 1.0 : 0.0) - an * n[i];
+    nrm += t[i] * t[i];
+  }
+  nrm = std::sqrt(nrm);
+  for (int i = 0; i < 3; ++i) t1[i] = t[i] / nrm;
+  t2[0] = n[1] * t1[2] - n[2] * t1[1];
+  t2[1] = n[2] * t1[0] - n[0] * t1[2];
+  t2[2] = n[0] * t1[1] - n[1] * t1[0];
+}
+
+int contact_active_friction(Scene& S, const double* ck, const std::vector<int>& av, const std::vector<double>& an,
+                            const std::vector<double>& al, const int* slots, hipStream_t st) {
+  const int na = (int)av.size(), nv = S.nv;
+  const VertArgs V = vert_args(S);
+  // slip and diagonal of every active contact vertex
+  PD_HIP(hipMemcpyAsync(S.a_v, av.data(), na * sizeof(int), hipMemcpyHostToDevice, st));
+  PD_HIP(hipMemcpyAsync(S.a_slot, slots, na * sizeof(int), hipMemcpyHostToDevice, st));
+  ContactArgs C0 = contact_args(S, na, true);
+  launch_contact_slip(V, C0, ck + 6 * (size_t)nv, ck, S.c_slip, st);
+  std::vector<double> sl(4 * (size_t)na);
+  PD_HIP(hipMemcpyAsync(sl.data(), S.c_slip, 4 * (size_t)na * sizeof(double), hipMemcpyDeviceToHost, st));
+  PD_HIP(hipStreamSynchronize(st));
+  std::vector<int> rv, rs, kind;
+  std::vector<double> rc, rb, rd;
+  auto row = [&](int c, int k, const double* cdir, const double* bdir, double d) {
+    rv.push_back(av[c]);
+    rs.push_back(slots[c]);
+    kind.push_back(k);
+    rc.insert(rc.end(), cdir, cdir + 3);
+    rb.insert(rb.end(), bdir, bdir + 3);
+    rd.push_back(d);
+  };
+  for (int c = 0; c < na; ++c) {
+    const double* n = an.data() + 3 * c;
+    double t1[3], t2[3];
+    host_frame(n, t1, t2);
+    const double* dq = sl.data() + 4 * c;
+    const double w = dq[3];
+    const double s1 = t1[0] * dq[0] + t1[1] * dq[1] + t1[2] * dq[2];
+    const double s2 = t2[0] * dq[0] + t2[1] * dq[1] + t2[2] * dq[2];
+    const double ns = std::sqrt(s1 * s1 + s2 * s2), tau = S.mu_f * al[c];
+    if (ns / w > 1e-8 * tau) {
+      const double h1 = s1 / ns, h2 = s2 / ns;
+      double b[3], p[3];
+      for (int i = 0; i < 3; ++i) {
+        b[i] = n[i] - S.mu_f * (h1 * t1[i] + h2 * t2[i]);
+        p[i] = -h2 * t1[i] + h1 * t2[i];
+      }
+      row(c, 0, n, b, 0.0);
+      row(c, 2, p, p, ns / tau);
+    } else {
+      row(c, 0, n, n, 0.0);
+      row(c, 1, t1, t1, 0.0);
+      row(c, 1, t2, t2, 0.0);
+    }
+  }
+  const int nr = (int)rv.size();
+  if (nr > kMaxAdjRows) throw PdError{kErrContact, "friction rows exceed the adjoint capacity"};
+  PD_HIP(hipMemcpyAsync(S.a_v, rv.data(), nr * sizeof(int), hipMemcpyHostToDevice, st));
+  PD_HIP(hipMemcpyAsync(S.a_slot, rs.data(), nr * sizeof(int), hipMemcpyHostToDevice, st));
+  PD_HIP(hipMemcpyAsync(S.a_kind, kind.data(), nr * sizeof(int), hipMemcpyHostToDevice, st));
+  PD_HIP(hipMemcpyAsync(S.a_n, rc.data(), 3 * nr * sizeof(double), hipMemcpyHostToDevice, st));
+  PD_HIP(hipMemcpyAsync(S.a_nb, rb.data(), 3 * nr * sizeof(double), hipMemcpyHostToDevice, st));
+  PD_HIP(hipMemcpyAsync(S.a_dg, rd.data(), nr * sizeof(double), hipMemcpyHostToDevice, st));
+  launch_zero_int(S.c_flags + 2, 1, st);
+  S.a_fric = true;
+  const ContactArgs C = contact_args(S, nr, true);
+  launch_contact_minv(C, S.a_Winv, st);
+  PD_HIP(hipMemcpyAsync(S.h_cbuf, S.c_flags, 4 * sizeof(int), hipMemcpyDeviceToHost, st));
+  PD_HIP(hipStreamSynchronize(st));
+  if (S.h_cbuf[2]) throw PdError{kErrContact, "the adjoint's contact coupling matrix is singular"};
+  return nr;
+}
+
 // Active rows of a checkpointed step (lam_c > 1e-10 max lam), their columns
 // and the inverse of their Delassus block; returns the active count.
 int contact_active(Scene& S, const double* ck, hipStream_t st) {
   const int kmax = S.c_kmax;
   const double* rec = ck + (size_t)kCheckpointVecs * 3 * S.nv;
-  PD_HIP(hipMemcpyAsync(S.h_crec, rec, (1 + 6 * (size_t)kmax) * sizeof(double), hipMemcpyDeviceToHost, st));
+  S.a_fric = false;
+  PD_HIP(hipMemcpyAsync(S.h_crec, rec, (1 + 8 * (size_t)kmax) * sizeof(double), hipMemcpyDeviceToHost, st));
   PD_HIP(hipStreamSynchronize(st));
   const double* h = S.h_crec;
   const int K = (int)h[0];
@@ -996,6 +1098,12 @@ int contact_active(Scene& S, const double* ck, hipStream_t st) {
   if (na == 0) return 0;
   int* hs = S.h_cbuf + 4 + kmax;
   ensure_columns(S, av.data(), na, hs, st);
+  if (S.mu_f > 0.0) {
+    std::vector<double> al;
+    for (int c = 0; c < K; ++c)
+      if (lmax > 0.0 && h[1 + 5 * kmax + c] > 1e-10 * lmax) al.push_back(h[1 + 5 * kmax + c]);
+    return contact_active_friction(S, ck, av, an, al, hs, st);
+  }
   PD_HIP(hipMemcpyAsync(S.a_v, av.data(), na * sizeof(int), hipMemcpyHostToDevice, st));
   PD_HIP(hipMemcpyAsync(S.a_n, an.data(), 3 * na * sizeof(double), hipMemcpyHostToDevice, st));
   PD_HIP(hipMemcpyAsync(S.a_slot, hs, na * sizeof(int), hipMemcpyHostToDevice, st));
@@ -1243,7 +1351,7 @@ size_t pd_ckpt_bytes(const pd_scene* scene) {
   if (!scene) return 0;
   const Scene& S = scene->S;
   size_t n = (size_t)kCheckpointVecs * 3 * (size_t)S.nv;
-  if (S.contact_on) n += 1 + 6 * (size_t)S.c_kmax;
+  if (S.contact_on) n += 1 + 8 * (size_t)S.c_kmax;
   return n * sizeof(double);
 }
 
@@ -1284,20 +1392,25 @@ int pd_scene_set_obstacles(pd_scene* scene, int n_planes, const double* planes, 
   S.obs = dalloc<double>(obs.size());
   upload(S.obs, obs);
   S.c_v = dalloc<int>(kmax); S.c_slot = dalloc<int>(kmax); S.c_flags = dalloc<int>(4);
-  S.c_n = dalloc<double>(3 * (size_t)kmax); S.c_g = dalloc<double>(kmax); S.c_lam = dalloc<double>(kmax);
+  // sized for friction (three rows per contact), which pd_scene_set_friction may turn on
+  const size_t rmax = 3 * (size_t)kmax;
+  S.c_n = dalloc<double>(3 * (size_t)kmax); S.c_g = dalloc<double>(kmax); S.c_lam = dalloc<double>(rmax);
   S.c_s = dalloc<double>(3 * (size_t)kmax); S.c_W = dalloc<double>((size_t)kmax * kmax);
   S.c_fb = dalloc<double>(2);
-  S.a_v = dalloc<int>(kmax); S.a_slot = dalloc<int>(kmax);
-  S.a_n = dalloc<double>(3 * (size_t)kmax); S.a_s = dalloc<double>(3 * (size_t)kmax);
-  S.a_Winv = dalloc<double>((size_t)kmax * kmax);
-  S.c_Lg = dalloc<double>((size_t)(kmax + 1) * (kmax + 2) / 2 + kmax + 1);
+  S.a_v = dalloc<int>(rmax); S.a_slot = dalloc<int>(rmax);
+  S.a_n = dalloc<double>(3 * rmax); S.a_s = dalloc<double>(3 * rmax);
+  S.a_Winv = dalloc<double>(rmax * rmax);
+  S.c_Lg = dalloc<double>(std::max(rmax * rmax, (rmax + 1) * (rmax + 2) / 2 + rmax + 1));
+  S.c_frw = dalloc<double>((size_t)kFrWork * kmax); S.c_fri = dalloc<int>(2 * rmax);
+  S.a_nb = dalloc<double>(3 * rmax); S.a_dg = dalloc<double>(rmax); S.a_kind = dalloc<int>(rmax);
+  S.c_slip = dalloc<double>(4 * (size_t)kmax);
   S.col_cap = 4 * kmax;
   S.cols = dalloc<double>((size_t)S.col_cap * std::max(nf, 1));
   S.cols_used = 0;
   S.slot_of.assign(std::max(nf, 1), -1);
   S.vert_of_slot.clear();
   PD_HIP(hipHostMalloc((void**)&S.h_cbuf, (4 + 2 * (size_t)kmax) * sizeof(int)));
-  PD_HIP(hipHostMalloc((void**)&S.h_crec, (1 + 6 * (size_t)kmax) * sizeof(double)));
+  PD_HIP(hipHostMalloc((void**)&S.h_crec, (1 + 8 * (size_t)kmax) * sizeof(double)));
   PD_HIP(hipMemset(S.c_fb, 0, 2 * sizeof(double)));
   PD_HIP(hipMemset(S.c_flags, 0, 4 * sizeof(int)));
   S.contact_on = true;
@@ -1323,7 +1436,56 @@ int pd_contact_rows(const pd_scene* scene, int* K, int32_t* vert, double* normal
       for (int c = 0; c < n; ++c) vert[c] = S.L.lib2orig[v[c]];
     if (normals) PD_HIP(hipMemcpy(normals, S.c_n, 3 * n * sizeof(double), hipMemcpyDeviceToHost));
     if (offsets) PD_HIP(hipMemcpy(offsets, S.c_g, n * sizeof(double), hipMemcpyDeviceToHost));
-    if (lambda) PD_HIP(hipMemcpy(lambda, S.c_lam, n * sizeof(double), hipMemcpyDeviceToHost));
+    if (lambda) {
+      if (S.mu_f > 0.0) {
+        std::vector<double> l3(3 * (size_t)n);
+        PD_HIP(hipMemcpy(l3.data(), S.c_lam, 3 * n * sizeof(double), hipMemcpyDeviceToHost));
+        for (int c = 0; c < n; ++c) lambda[c] = l3[3 * c];
+      } else {
+        PD_HIP(hipMemcpy(lambda, S.c_lam, n * sizeof(double), hipMemcpyDeviceToHost));
+      }
+    }
+  }
+  return PD_OK;
+  PD_CATCH
+}
+
+int pd_scene_set_friction(pd_scene* scene, double mu) {
+  if (!scene) {
+    pdhot::g_last_error = "null scene";
+    return PD_ERR_INVALID_ARG;
+  }
+  PD_TRY
+  Scene& S = scene->S;
+  if (!S.contact_on) throw PdError{PD_ERR_INVALID_ARG, "friction needs obstacles (pd_scene_set_obstacles first)"};
+  if (!(mu >= 0.0) || !std::isfinite(mu)) throw PdError{PD_ERR_INVALID_ARG, "need a finite friction coefficient >= 0"};
+  S.mu_f = mu;
+  S.c_last_K = S.c_last_active = 0;
+  return PD_OK;
+  PD_CATCH
+}
+
+int pd_contact_impulses(const pd_scene* scene, double* lam3, int capacity) {
+  if (!scene || !lam3) {
+    pdhot::g_last_error = "null argument";
+    return PD_ERR_INVALID_ARG;
+  }
+  PD_TRY
+  const Scene& S = scene->S;
+  const int K = S.contact_on ? S.c_last_K : 0;
+  const int n = std::min(K, std::max(capacity, 0));
+  if (n > 0) {
+    if (S.mu_f > 0.0) {
+      PD_HIP(hipMemcpy(lam3, S.c_lam, 3 * n * sizeof(double), hipMemcpyDeviceToHost));
+    } else {
+      std::vector<double> l(n);
+      PD_HIP(hipMemcpy(l.data(), S.c_lam, n * sizeof(double), hipMemcpyDeviceToHost));
+      for (int c = 0; c < n; ++c) {
+        lam3[3 * c] = l[c];
+        lam3[3 * c + 1] = 0.0;
+        lam3[3 * c + 2] = 0.0;
+      }
+    }
   }
   return PD_OK;
   PD_CATCH
@@ -1376,7 +1538,8 @@ int pd_step_forward(pd_scene* scene, const double* q_t, const double* v_t, const
       PD_TIMED(S, kKTop, st, launch_top(V, A, S.qhat, T.done, st));
       if (K > 0) {
         PD_TIMED(S, kKBottom, st, launch_bottom(kModePlain, V, A, T, Ad, R, S.b_cur, S.qhat, k, st));
-        launch_contact_fb(V, C, S.qhat, T.done, st);
+        if (S.mu_f > 0.0) launch_contact_fr(V, C, S.qhat, T.done, st);
+        else launch_contact_fb(V, C, S.qhat, T.done, st);
         launch_contact_apply_fwd(V, T, R, C, k, st);
       } else {
         PD_TIMED(S, kKBottom, st, launch_bottom(kModeFwd, V, A, T, Ad, R, nullptr, S.qhat, k, st));
@@ -1403,16 +1566,19 @@ int pd_step_forward(pd_scene* scene, const double* q_t, const double* v_t, const
     launch_contact_ckpt(C, S.c_kmax, (double*)ckpt + (size_t)kCheckpointVecs * 3 * S.nv, st);
   int n_active = 0;
   double fb_res = 0.0;
+  const int nl = S.mu_f > 0.0 ? 3 * K : K;  // impulse entries (three per contact with friction)
   if (K > 0) {
-    PD_HIP(hipMemcpyAsync(S.h_crec, S.c_lam, K * sizeof(double), hipMemcpyDeviceToHost, st));
-    PD_HIP(hipMemcpyAsync(S.h_crec + K, S.c_fb, 2 * sizeof(double), hipMemcpyDeviceToHost, st));
+    PD_HIP(hipMemcpyAsync(S.h_crec, S.c_lam, nl * sizeof(double), hipMemcpyDeviceToHost, st));
+    PD_HIP(hipMemcpyAsync(S.h_crec + nl, S.c_fb, 2 * sizeof(double), hipMemcpyDeviceToHost, st));
     PD_HIP(hipMemcpyAsync(S.h_cbuf, S.c_flags, 4 * sizeof(int), hipMemcpyDeviceToHost, st));
     PD_HIP(hipStreamSynchronize(st));
   }
   PD_HIP(hipGetLastError());
   if (K > 0) {
-    for (int c = 0; c < K; ++c) n_active += S.h_crec[c] > 0.0;
-    fb_res = S.h_crec[K];
+    const int stride = nl / K;
+    for (int c = 0; c < K; ++c) n_active += S.h_crec[stride * c] > 0.0;
+    fb_res = S.h_crec[nl];
+    if (S.mu_f > 0.0 && S.h_cbuf[2]) throw PdError{kErrContact, "a frictional contact Newton system was not positive definite"};
   }
   S.c_last_K = K;
   S.c_last_active = n_active;
@@ -1477,7 +1643,9 @@ static void adjoint_solve(Scene& S, hipStream_t st, double tau_force, double* bs
   const int tr = S.energy == 0;
   if (tr) launch_tr_partials(E, V, R, ck, st);
   launch_bwd_elem(E, V, R, ck, S.eps_tr, tau_force, tr, S.jac, S.dstat + 4, S.ctl + kCtlAdj, 4, st);
-  const bool pcg = S.adj_method == 0;
+  // the frictional adjoint is unsymmetric (a sliding contact's friction follows
+  // its normal impulse): it runs the projected fixed point
+  const bool pcg = S.adj_method == 0 && !(con && S.a_fric);
   if (pcg) {
     if (warm) {  // r = q bar - (A~ - K) mu0
       launch_apply_K(kModeAmK, E, V, Ad, R, S.jac, S.mu, 0, st);
@@ -1581,6 +1749,9 @@ int pd_step_backward(pd_scene* scene, const void* ckpt, const double* gq_next, c
   // the gradient routing is stream-ordered; the statistics were read with the last check
   launch_grad_elem(E, V, ck, S.jac, S.mu, S.contrib, g_logE_accum, st);
   launch_grad_vert(V, S.mu, S.contrib, gv_next, gq_t, gv_t, gf_ext, st);
+  // sticking rows constrain the slip from q_t and sliding rows' friction
+  // depends on it: their multipliers reach dL/dq_t
+  if (n_active > 0 && S.a_fric) launch_contact_route(V, contact_args(S, n_active, true), S.a_kind, gq_t, st);
   PD_HIP(hipGetLastError());
   const int status = S.hctl[kCtlAdj + 1];
   if (stats) {
@@ -1588,7 +1759,7 @@ int pd_step_backward(pd_scene* scene, const void* ckpt, const double* gq_next, c
     stats->status = status;
     stats->rho = bs[0]; stats->tau = bs[1]; stats->dphi_act = bs[2]; stats->dphi_mod = bs[3];
     stats->residual = bs[4];
-    stats->n_active = n_active;
+    stats->n_active = n_active > 0 ? S.c_last_active : 0;
   }
   return status == 0 ? PD_OK : PD_NOT_CONVERGED;
   PD_CATCH

@@ -305,6 +305,24 @@ int pd_debug_local_rhs(pd_scene* scene, const double* q, double* b, void* stream
 int pd_debug_apply_Ainv(pd_scene* scene, const double* r, double* x, void* stream);
 int pd_debug_apply_K(pd_scene* scene, const double* q, double tau, const double* x, double* y, void* stream);
 
+/* For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc): x = A~^{-1} r
+ * exactly as pd_debug_apply_Ainv (the same kernels and results), with the
+ * solve's scratch (two staging vectors of 3 n_verts doubles, the interface
+ * right-hand side and the gathered interface solution) in a static device
+ * workspace of 2^21 doubles (16 MiB) that the library holds on each device it
+ * runs on until the process ends.  Calls nothing that allocates and does not
+ * wait: the result is ordered on `stream` (call with the scene's device
+ * current).  Every call on a device shares that device's workspace, so calls
+ * that overlap on one device (other streams, other threads) race; the
+ * workspace keeps the last call's contents, and nothing in it needs to start
+ * at zero.  PD_ERR_INVALID_ARG (before any device work) when the scene needs
+ * more scratch than the workspace holds (6 n_verts + 3 n_interface + 3 times
+ * the interface rows of all subdomains, about 300k vertices at most), for a
+ * null argument; PD_ERR_STALE_FACTOR as the other solves; PD_ERR_HIP if the
+ * workspace's address cannot be found. */
+int pd_apply_Ainv_noalloc(pd_scene* scene, const double* r, double* x, void* stream);
+
 /* Kernel timing for roofline reports: every launch of one kernel inside
  * pd_step_forward / pd_step_backward carries a start and a stop HIP event
  * stamped by the dispatch itself on the caller's stream, so the elapsed time

@@ -32,7 +32,7 @@ EXPORTED = ["pd_scene_create", "pd_scene_destroy", "pd_scene_set_material", "pd_
             "pd_mpn_adam_step", "pd_batch_create", "pd_batch_destroy", "pd_batch_config", "pd_batch_step_forward",
             "pd_batch_step_backward", "pd_scene_set_obstacles", "pd_contact_rows", "pd_last_error",
             "pd_scene_factor_nnz", "pd_batch_kernel_timer", "pd_batch_kernel_timer_read",
-            "pd_scene_set_friction", "pd_contact_impulses"]
+            "pd_scene_set_friction", "pd_contact_impulses", "pd_apply_Ainv_noalloc"]
 
 
 class pd_mesh_desc(ctypes.Structure):
@@ -124,6 +124,7 @@ def lib() -> ctypes.CDLL:
     L.pd_contact_rows.argtypes = [vp, vp, vp, vp, vp, vp, i32]
     L.pd_scene_set_friction.argtypes = [vp, dbl]
     L.pd_contact_impulses.argtypes = [vp, vp, i32]
+    L.pd_apply_Ainv_noalloc.argtypes = [vp, vp, vp, vp]
     L.pd_scene_factor_nnz.argtypes = [vp, vp]
     L.pd_batch_kernel_timer.argtypes = [vp, i32]
     L.pd_batch_kernel_timer_read.argtypes = [vp, vp, vp, vp]
@@ -359,6 +360,12 @@ class Scene:
         import torch
         x = torch.empty_like(r)
         check(lib().pd_debug_apply_Ainv(self.ptr, _ptr(r), _ptr(x), _stream()), "pd_debug_apply_Ainv")
+        return x
+
+    def apply_Ainv_noalloc(self, r, x):
+        """x = A~^{-1} r into the caller's x, scratch from the library's static workspace
+        (pd_apply_Ainv_noalloc; ordered on the current stream, no host wait)."""
+        check(lib().pd_apply_Ainv_noalloc(self.ptr, _ptr(r), _ptr(x), _stream()), "pd_apply_Ainv_noalloc")
         return x
 
     def debug_apply_K(self, q, tau, x):

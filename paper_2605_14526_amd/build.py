@@ -10,7 +10,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 ROOT = os.path.dirname(HERE)
 LIB = os.path.join(HERE, "libpdhot.so")
-SOURCES = ["kernels.hip", "contact.hip", "runtime.cpp", "layout.cpp", "mpn.hip"]
+SOURCES = ["kernels.hip", "contact.hip", "runtime.cpp", "layout.cpp", "mpn.hip", "noalloc.hip"]
 HEADERS = ["kernels.h", "pd_internal.h", "device_math.h", "mpn_internal.h"]
 ARCH = os.environ.get("PDHOT_ARCH", "gfx950")
 

@@ -211,4 +211,9 @@ struct Scene {
   bool a_fric = false;  // the current backward step has friction rows
 };
 
+void set_last_error(const std::string& m);
+// The global solve with caller-provided scratch (the allocation-free entry point)
+size_t apply_Ainv_ws_doubles(const pd_scene* scene);
+int apply_Ainv_ws(pd_scene* scene, const double* r, double* x, double* ws, size_t ws_cap, void* stream);
+
 }  // namespace pdhot

@@ -1816,6 +1816,60 @@ int pd_debug_apply_Ainv(pd_scene* scene, const double* r, double* x, void* strea
   PD_CATCH
 }
 
+}  // extern "C"
+
+namespace pdhot {
+size_t apply_Ainv_ws_doubles(const pd_scene* scene) {
+  const Scene& S = scene->S;
+  return 6 * (size_t)S.nv + 3 * (size_t)std::max(1, S.L.nT) + 3 * (size_t)std::max(1, S.S.n_irows);
+}
+
+// x = A~^{-1} r as pd_debug_apply_Ainv, with every scratch vector of the solve
+// (both library-order staging vectors, the interface right-hand side and the
+// gathered interface solution) taken from ws: nothing is allocated and the
+// host does not wait (the result is ordered on the stream).  Each of those
+// vectors is written in full before it is read, so ws needs no clearing.
+int apply_Ainv_ws(pd_scene* scene, const double* r, double* x, double* ws, size_t ws_cap, void* stream) {
+  if (!scene || !r || !x || !ws) {
+    g_last_error = "null argument";
+    return PD_ERR_INVALID_ARG;
+  }
+  Scene& S = scene->S;
+  if (S.stale) {
+    g_last_error = "factor is stale";
+    return PD_ERR_STALE_FACTOR;
+  }
+  const size_t need = apply_Ainv_ws_doubles(scene);
+  if (need > ws_cap) {
+    g_last_error = "the solve needs " + std::to_string(need) + " doubles of scratch, more than the " +
+                   std::to_string(ws_cap) + " of the static workspace";
+    return PD_ERR_INVALID_ARG;
+  }
+  PD_TRY
+  hipStream_t st = (hipStream_t)stream;
+  const VertArgs V = vert_args(S);
+  SolveArgs A = solve_args(S);
+  double* rl = ws;
+  double* xl = ws + 3 * (size_t)S.nv;
+  A.rT = xl + 3 * (size_t)S.nv;
+  A.xsT = A.rT + 3 * (size_t)std::max(1, S.L.nT);
+  const RedArgs R = red_args(S);
+  StepState T = step_state(S);
+  T.done = nullptr;
+  const AdjState Ad = adj_state(S);
+  launch_to_lib(V, r, rl, 1, st);
+  launch_Eb(kModePlain, V, A, T, Ad, R, rl, 0, st);
+  launch_top(V, A, xl, nullptr, st);
+  launch_bottom(kModePlain, V, A, T, Ad, R, rl, xl, 0, st);
+  launch_from_lib(V, xl, x, 1, st);
+  PD_HIP(hipGetLastError());
+  return PD_OK;
+  PD_CATCH
+}
+}  // namespace pdhot
+
+extern "C" {
+
 int pd_debug_apply_K(pd_scene* scene, const double* q, double tau, const double* x, double* y, void* stream) {
   if (!scene || !q || !x || !y) {
     pdhot::g_last_error = "null argument";

@@ -59,6 +59,10 @@ def lib():
         L.or_volume_diff.argtypes = [_dp, _dp]
         L.or_composite_map.argtypes = [_dp, ctypes.c_double, ctypes.c_double, _dp]
         L.or_composite_jacobian.argtypes = [_dp, ctypes.c_double, ctypes.c_double, _dp]
+        L.or_logvol_stretch.argtypes = [_dp, ctypes.c_double, ctypes.c_double, ctypes.c_double, _dp]
+        L.or_logvol_map.argtypes = [_dp, ctypes.c_double, ctypes.c_double, ctypes.c_double, ctypes.c_double, _dp]
+        L.or_logvol_jacobian.argtypes = [_dp, ctypes.c_double, ctypes.c_double, ctypes.c_double, ctypes.c_double,
+                                         _dp]
         L.or_tr_filter.argtypes = [_dp, ctypes.c_double, ctypes.c_double, _dp, _dp]
         L.or_aa_step.argtypes = [ctypes.c_int, ctypes.c_int, _dp, _dp, _ip, _dp, _dp, ctypes.c_char_p, _dp, _dp]
         L.or_local_rhs.argtypes = [ctypes.c_void_p, _dp, _dp]
@@ -165,6 +169,24 @@ def composite_map(F, mu, lam):
 def composite_jacobian(F, mu, lam):
     J = np.zeros((9, 9))
     lib().or_composite_jacobian(_p(_f(F).reshape(3, 3)), mu, lam, _p(J))
+    return J
+
+
+def logvol_stretch(sF, mu, lam, k):
+    s = np.zeros(3)
+    it = lib().or_logvol_stretch(_p(_f(sF)), mu, lam, k, _p(s))
+    return s, it
+
+
+def logvol_map(F, mu_bar, lam_bar, mu, lam):
+    P = np.zeros((3, 3))
+    lib().or_logvol_map(_p(_f(F)), mu_bar, lam_bar, mu, lam, _p(P))
+    return P
+
+
+def logvol_jacobian(F, mu_bar, lam_bar, mu, lam):
+    J = np.zeros((9, 9))
+    lib().or_logvol_jacobian(_p(_f(F)), mu_bar, lam_bar, mu, lam, _p(J))
     return J
 
 

@@ -247,7 +247,9 @@ double or_psi_nh(const double F[9], double mu, double lam) {
  * READING: V_e is dropped from the prox (the same stretch-space map in every
  * element, Sec. 4.2); the stationarity form grad f = 0 is solved (the printed
  * normal equation is its quadratic special case). */
-static double prox_obj(const double s[3], const double sF[3], double mu, double lam, double k) {
+/* mi: the weight of the I1 term (mu for the Neo-Hookean energy, 0 for the
+ * logarithmic volume barrier of Eq. pd_log_volume) */
+static double prox_obj(const double s[3], const double sF[3], double mi, double mu, double lam, double k) {
   if (!(s[0] > 0 && s[1] > 0 && s[2] > 0)) return INFINITY;
   double q = 0, ss = 0, sl = 0;
   for (int i = 0; i < 3; ++i) {
@@ -255,22 +257,27 @@ static double prox_obj(const double s[3], const double sF[3], double mu, double 
     ss += s[i] * s[i];
     sl += log(s[i]);
   }
-  return 0.5 * k * q + 0.5 * mu * (ss - 3.0) - mu * sl + 0.5 * lam * sl * sl;
+  return 0.5 * k * q + 0.5 * mi * (ss - 3.0) - mu * sl + 0.5 * lam * sl * sl;
 }
 
 /* gradient and Hessian of psi in stretch space.
  * READING of Eq. nh_hessian_stretch: the diagonal term is mu (1 + s^-2), the
  * exact second derivative of Eq. neohookean (the printed s^-4 is a typo). */
-static void psi_stretch_grad_hess(const double s[3], double mu, double lam, double g[3], double H[9]) {
+static void stretch_grad_hess(const double s[3], double mi, double mu, double lam, double g[3], double H[9]) {
   double l = log(s[0]) + log(s[1]) + log(s[2]);
-  for (int i = 0; i < 3; ++i) g[i] = mu * s[i] - mu / s[i] + lam * l / s[i];
+  for (int i = 0; i < 3; ++i) g[i] = mi * s[i] - mu / s[i] + lam * l / s[i];
   for (int i = 0; i < 3; ++i)
     for (int j = 0; j < 3; ++j) {
       if (i == j)
-        H[3 * i + j] = mu * (1.0 + 1.0 / (s[i] * s[i])) + lam * (1.0 - l) / (s[i] * s[i]);
+        H[3 * i + j] = (mi == mu ? mu * (1.0 + 1.0 / (s[i] * s[i])) : mi + mu / (s[i] * s[i])) +
+                       lam * (1.0 - l) / (s[i] * s[i]);
       else
         H[3 * i + j] = lam / (s[i] * s[j]);
     }
+}
+
+static void psi_stretch_grad_hess(const double s[3], double mu, double lam, double g[3], double H[9]) {
+  stretch_grad_hess(s, mu, mu, lam, g, H);
 }
 
 /* Proximal stretches, Sec. 4.1 Eqs. nh_prox / nh_prox_normal: Newton with
@@ -281,7 +288,7 @@ static void psi_stretch_grad_hess(const double s[3], double mu, double lam, doub
  * rounding slack of 1e-13 k (1 + |s|^2);
  * stop at |g|_inf <= 1e-13 k max(1, |sF|_inf), a relative step <= 1e-15, or
  * 50 iterations.  Returns the iteration count (negative if the cap was hit). */
-int or_prox_stretch(const double sF[3], double mu, double lam, double k, double s_out[3]) {
+static int prox_newton(const double sF[3], double mi, double mu, double lam, double k, double s_out[3]) {
   double s[3];
   for (int i = 0; i < 3; ++i) s[i] = sF[i] > 0.1 ? sF[i] : 0.1;
   double sfmax = 1.0;
@@ -290,7 +297,7 @@ int or_prox_stretch(const double sF[3], double mu, double lam, double k, double 
   int it;
   for (it = 0; it < 50; ++it) {
     double gp[3], H[9], g[3];
-    psi_stretch_grad_hess(s, mu, lam, gp, H);
+    stretch_grad_hess(s, mi, mu, lam, gp, H);
     double gmax = 0;
     for (int i = 0; i < 3; ++i) {
       g[i] = k * (s[i] - sF[i]) + gp[i];
@@ -319,14 +326,14 @@ int or_prox_stretch(const double sF[3], double mu, double lam, double k, double 
         double lim = 0.9 * s[i] / (-d[i]);
         if (lim < a0) a0 = lim;
       }
-    double f0 = prox_obj(s, sF, mu, lam, k);
+    double f0 = prox_obj(s, sF, mi, mu, lam, k);
     double slack = 1e-13 * k * (1.0 + s[0] * s[0] + s[1] * s[1] + s[2] * s[2]);
     double slope = g[0] * d[0] + g[1] * d[1] + g[2] * d[2];
     double a = a0, sn[3];
     int accepted = 0;
     for (int ls = 0; ls <= 30; ++ls) {
       for (int i = 0; i < 3; ++i) sn[i] = s[i] + a * d[i];
-      double f1 = prox_obj(sn, sF, mu, lam, k);
+      double f1 = prox_obj(sn, sF, mi, mu, lam, k);
       /* the slack 1e-13 k (1 + |s|^2), the rounding level of the terms of f,
        * keeps the test meaningful once the decrease falls below what f can
        * resolve (close to the minimiser) */
@@ -345,6 +352,32 @@ int or_prox_stretch(const double sF[3], double mu, double lam, double k, double 
   }
   for (int i = 0; i < 3; ++i) s_out[i] = s[i];
   return it >= 50 ? -it : it;
+}
+
+int or_prox_stretch(const double sF[3], double mu, double lam, double k, double s_out[3]) {
+  return prox_newton(sF, mu, mu, lam, k, s_out);
+}
+
+/* Volume step of the logarithmic barrier variant (Sec. 4.1 Eq. pd_log_volume):
+ * the same Newton on stretches with the barrier -mu sum ln s + lam/2 (sum ln
+ * s)^2 in place of psi (the I1 term dropped), Eq. nh_prox_normal's Hessian
+ * replaced by the barrier's.  READING: like the Neo-Hookean prox it runs with
+ * the mesh means, and its penalty is the mean of its weight, k = lam_bar (the
+ * element's weight lam_e times the barrier with mu_e, lam_e has the same
+ * minimiser, since mu_e / mu_bar = lam_e / lam_bar for a shared nu).  As
+ * printed, the barrier's gradient at s = 1 is -mu, so the step is not the
+ * identity at rest. */
+int or_logvol_stretch(const double sF[3], double mu, double lam, double k, double s_out[3]) {
+  return prox_newton(sF, 0.0, mu, lam, k, s_out);
+}
+
+/* stretch Jacobian of the barrier step: D = k (H + k I)^{-1} (the implicit
+ * function theorem on its stationarity) */
+static void logvol_diff(const double sv[3], double mu, double lam, double k, double D[9]) {
+  double g[3], H[9];
+  stretch_grad_hess(sv, 0.0, mu, lam, g, H);
+  for (int i = 0; i < 3; ++i) H[4 * i] += k;
+  or_tr_filter(H, 0.0, k, NULL, D);
 }
 
 /* p* = U diag(s*) V^T, Sec. 4.1 */
@@ -558,34 +591,61 @@ typedef struct {
   double Dv[9], c1v[3], c2v[3], c1r[3], c2r[3];
 } composite_parts;
 
-static void composite_eval(const double F[9], composite_parts* c, int want_diff) {
+/* kind 1: the volume projection; kind 2: the logarithmic barrier step with
+ * the means mu_bar, lam_bar and penalty lam_bar */
+static void composite_eval(const double F[9], composite_parts* c, int want_diff, int kind, double mu_bar,
+                           double lam_bar) {
   double T[9];
   or_svd3(F, c->U, c->sF, c->V);
   mat3_mul_nt(c->U, c->V, c->R);
-  or_volume_project(c->sF, c->sv);
+  if (kind == 2) or_logvol_stretch(c->sF, mu_bar, lam_bar, lam_bar, c->sv);
+  else or_volume_project(c->sF, c->sv);
   for (int i = 0; i < 3; ++i)
     for (int j = 0; j < 3; ++j) T[3 * i + j] = c->U[3 * i + j] * c->sv[j];
   mat3_mul_nt(T, c->V, c->Pv);
   if (want_diff) {
     const double one[3] = {1.0, 1.0, 1.0}, zero[9] = {0};
-    volume_diff(c->sF, c->sv, c->Dv);
+    if (kind == 2) logvol_diff(c->sv, mu_bar, lam_bar, lam_bar, c->Dv);
+    else volume_diff(c->sF, c->sv, c->Dv);
     pair_coeffs(c->sF, c->sv, c->Dv, c->c1v, c->c2v);
     pair_coeffs(c->sF, one, zero, c->c1r, c->c2r);
   }
 }
 
+static void composite_eval_s(const or_scene* s, const double F[9], composite_parts* c, int want_diff);
+
 /* (2 mu R + lam P_vol) / (2 mu + lam): the composite's projection per unit of
  * its total weight w = 2 mu + lam (for element-level checks) */
 void or_composite_map(const double F[9], double mu, double lam, double P[9]) {
   composite_parts c;
-  composite_eval(F, &c, 0);
+  composite_eval(F, &c, 0, 1, 0.0, 0.0);
   for (int i = 0; i < 9; ++i) P[i] = (2.0 * mu * c.R[i] + lam * c.Pv[i]) / (2.0 * mu + lam);
+}
+
+/* the same with the logarithmic barrier step (means mu_bar, lam_bar) */
+void or_logvol_map(const double F[9], double mu_bar, double lam_bar, double mu, double lam, double P[9]) {
+  composite_parts c;
+  composite_eval(F, &c, 0, 2, mu_bar, lam_bar);
+  for (int i = 0; i < 9; ++i) P[i] = (2.0 * mu * c.R[i] + lam * c.Pv[i]) / (2.0 * mu + lam);
+}
+
+void or_logvol_jacobian(const double F[9], double mu_bar, double lam_bar, double mu, double lam, double J[81]) {
+  composite_parts c;
+  const double zero[9] = {0};
+  composite_eval(F, &c, 1, 2, mu_bar, lam_bar);
+  for (int col = 0; col < 9; ++col) {
+    double dF[9] = {0}, dR[9], dV[9];
+    dF[col] = 1.0;
+    prox_diff_apply(c.U, c.V, zero, c.c1r, c.c2r, dF, dR);
+    prox_diff_apply(c.U, c.V, c.Dv, c.c1v, c.c2v, dF, dV);
+    for (int r = 0; r < 9; ++r) J[9 * r + col] = (2.0 * mu * dR[r] + lam * dV[r]) / (2.0 * mu + lam);
+  }
 }
 
 void or_composite_jacobian(const double F[9], double mu, double lam, double J[81]) {
   composite_parts c;
   const double zero[9] = {0};
-  composite_eval(F, &c, 1);
+  composite_eval(F, &c, 1, 1, 0.0, 0.0);
   for (int col = 0; col < 9; ++col) {
     double dF[9] = {0}, dR[9], dV[9];
     dF[col] = 1.0;
@@ -612,7 +672,7 @@ struct or_scene {
   double* logE;
   double nu, rho, alpha, beta0, h, grav[3];
   int m, kmax_fwd, kmax_bwd;
-  int energy; /* 0: Neo-Hookean proximal map; 1: corotated + volume composite */
+  int energy; /* 0: Neo-Hookean proximal map; 1: corotated + volume composite; 2: corotated + log barrier */
   double eps_rel, eps_abs, eps_adj, eps_tr;
   /* derived (Sec. 3.1, 4.1, 4.2, 4.5) */
   double* Bhat;   /* ne x 4 x 3 shape gradients: F = sum_a x_a (x) Bhat_a */
@@ -629,6 +689,10 @@ struct or_scene {
   double* Aenv; /* assembled A~ (lower envelope) */
   double* Lenv; /* its Cholesky factor */
 };
+
+static void composite_eval_s(const or_scene* s, const double F[9], composite_parts* c, int want_diff) {
+  composite_eval(F, c, want_diff, s->energy, s->mu_bar, s->lam_bar);
+}
 
 int or_scene_nfree(const or_scene* s) { return s->nf; }
 
@@ -878,11 +942,11 @@ static void local_rhs_stats(const or_scene* s, const double* q, double* b_all, i
   for (int e = 0; e < s->ne; ++e) {
     double F[9], U[9], V[9], sF[3], ss[3], T[9], P[9];
     element_F(s, e, q, F);
-    if (s->energy == 1) {
-      /* corotated + volume: 2 mu_e V_e G^T R + lam_e V_e G^T P_vol */
+    if (s->energy >= 1) {
+      /* corotated + volume (or the barrier): 2 mu_e V_e G^T R + lam_e V_e G^T P_vol */
       composite_parts c;
       double cv[12];
-      composite_eval(F, &c, 0);
+      composite_eval_s(s, F, &c, 0);
       element_contrib(s, e, 2.0 * s->mu[e] * s->vol[e], c.R, ctb + 12 * (size_t)e);
       element_contrib(s, e, s->lam[e] * s->vol[e], c.Pv, cv);
       for (int i = 0; i < 12; ++i) ctb[12 * (size_t)e + i] += cv[i];
@@ -916,11 +980,11 @@ void or_apply_K(const or_scene* s, const double* q, double tau, const double* x_
   for (int e = 0; e < s->ne; ++e) {
     double F[9], U[9], V[9], sF[3], ss[3], D[9], c1[3], c2[3], dF[9], dP[9];
     element_F(s, e, q, F);
-    if (s->energy == 1) {
+    if (s->energy >= 1) {
       composite_parts c;
       const double zero[9] = {0};
       double dR[9], cv[12];
-      composite_eval(F, &c, 1);
+      composite_eval_s(s, F, &c, 1);
       element_F(s, e, xf, dF);
       prox_diff_apply(c.U, c.V, zero, c.c1r, c.c2r, dF, dR);
       prox_diff_apply(c.U, c.V, c.Dv, c.c1v, c.c2v, dF, dP);
@@ -953,9 +1017,9 @@ static double* prox_diff_all(const or_scene* s, const double* q, double tau) {
     double F[9], sF[3], ss[3];
     double* c = st + KST * (size_t)e;
     element_F(s, e, q, F);
-    if (s->energy == 1) {
+    if (s->energy >= 1) {
       composite_parts p;
-      composite_eval(F, &p, 1);
+      composite_eval_s(s, F, &p, 1);
       memcpy(c, p.U, sizeof(p.U));
       memcpy(c + 9, p.V, sizeof(p.V));
       memcpy(c + 18, p.Dv, sizeof(p.Dv));
@@ -983,7 +1047,7 @@ static void apply_K_stored(const or_scene* s, const double* st, const double* x_
     double dF[9], dP[9];
     element_F(s, e, xf, dF);
     prox_diff_apply(c, c + 9, c + 18, c + 27, c + 30, dF, dP);
-    if (s->energy == 1) {
+    if (s->energy >= 1) {
       /* 2 mu_e V_e G^T dR + lam_e V_e G^T dP_vol (the rotation's D and c1 vanish) */
       const double zero[9] = {0};
       double dR[9], cv[12];
@@ -2191,10 +2255,10 @@ static int step_backward_impl(const or_scene* s, const double* q_t, const double
     element_F(s, e, mu, Gm);
     element_F(s, e, q_star, F);
     double gw = 0.0;
-    if (s->energy == 1) {
+    if (s->energy >= 1) {
       /* dL/dlog E_e = 2 mu_e V_e <G mu, R - F> + lam_e V_e <G mu, P_vol - F> + the beta term */
       composite_parts c;
-      composite_eval(F, &c, 0);
+      composite_eval_s(s, F, &c, 0);
       double gr = 0.0, gv = 0.0;
       for (int i = 0; i < 9; ++i) {
         gr += Gm[i] * (c.R[i] - F[i]);

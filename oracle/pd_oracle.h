@@ -19,7 +19,7 @@ typedef struct or_scene or_scene;
 /* params: nu, rho, alpha, beta0, h, gx, gy, gz
  * solver: m (AA window), eps_rel, eps_abs, kmax_fwd, kmax_bwd, eps_adj, eps_tr,
  *         then mu_bar, lam_bar, mu_ref (frozen if mu_bar > 0, else computed),
- *         then the energy model (0: Neo-Hookean prox; 1: corotated + volume) */
+ *         then the energy model (0: Neo-Hookean prox; 1: corotated + volume; 2: corotated + log barrier) */
 or_scene* or_scene_create(int nv, int ne, const double* X, const int* tets, const unsigned char* pinned,
                           const double* logE, const double* params, const double* solver);
 void or_scene_destroy(or_scene* s);
@@ -44,6 +44,12 @@ int or_volume_project(const double sF[3], double s[3]);
 void or_volume_diff(const double sF[3], double D[9]);
 void or_composite_map(const double F[9], double mu, double lam, double P[9]);
 void or_composite_jacobian(const double F[9], double mu, double lam, double J[81]);
+/* the logarithmic volume barrier variant (Sec. 4.1 Eq. pd_log_volume): its stretch step (the Newton of
+ * or_prox_stretch without the I1 term), and the composite (2 mu R + lam P_log) / (2 mu + lam) whose
+ * barrier step runs with the means mu_bar, lam_bar and penalty lam_bar, with its 9x9 Jacobian */
+int or_logvol_stretch(const double sF[3], double mu, double lam, double k, double s_out[3]);
+void or_logvol_map(const double F[9], double mu_bar, double lam_bar, double mu, double lam, double P[9]);
+void or_logvol_jacobian(const double F[9], double mu_bar, double lam_bar, double mu, double lam, double J[81]);
 void or_sym3_eig(const double H[9], double kappa[3], double Q[9]);
 void or_tr_filter(const double H[9], double tau, double k, double Ht[9], double Dinv[9]);
 int or_aa_step(int n, int m, double* Hq, double* Hg, int* hn, const double* q, const double* qhat,

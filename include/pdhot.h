@@ -67,8 +67,12 @@ typedef struct pd_mesh_desc {
  * with PD weight w_e = 2 mu_e + lam_e; 1 = the corotated + volume composite,
  * a rotation step p0 = R (signed polar rotation of F) with weight 2 mu_e and
  * a volume step p1 = F projected onto det = 1 (the closest unit-determinant
- * point in stretch space) with weight lam_e (Sec. 7.2).  Both give the same
- * system matrix; the trust-region filter of Sec. 4.4 applies to energy 0. */
+ * point in stretch space) with weight lam_e (Sec. 7.2); 2 = the rotation step
+ * with the logarithmic volume barrier of Sec. 4.1 Eq. pd_log_volume (-mu sum
+ * ln s + lam/2 (sum ln s)^2, solved on the stretches by the Neo-Hookean prox
+ * Newton without its I1 term, with the mesh means and penalty lam_bar) as the
+ * volume step of weight lam_e.  All give the same system matrix; the
+ * trust-region filter of Sec. 4.4 applies to energy 0. */
 typedef struct pd_material_desc {
   const double* log_E;
   double nu;

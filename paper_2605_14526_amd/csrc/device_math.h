@@ -160,7 +160,11 @@ __device__ __forceinline__ void svd3(const double F[9], double U[9], double s[3]
 // stretches, mesh means mu, lam) and the proximal objective
 //   f(s) = k/2 |s - sF|^2 + mu/2 (sum s^2 - 3) - mu sum ln s + lam/2 (sum ln s)^2.
 // ---------------------------------------------------------------------------
-__device__ __forceinline__ double prox_f(const double s[3], const double sF[3], double mu, double lam, double k) {
+// mi is the weight of the I1 term: mu for the Neo-Hookean energy, 0 for the
+// logarithmic volume barrier of Eq. pd_log_volume (-mu sum ln s + lam/2
+// (sum ln s)^2, the same Newton on stretches without the I1 term).
+__device__ __forceinline__ double prox_f(const double s[3], const double sF[3], double mi, double mu, double lam,
+                                         double k) {
   const double l = log(s[0] * s[1] * s[2]);
   double q = 0.0, ss = 0.0;
 #pragma unroll
@@ -169,18 +173,18 @@ __device__ __forceinline__ double prox_f(const double s[3], const double sF[3], 
     q += d * d;
     ss += s[i] * s[i];
   }
-  return 0.5 * k * q + 0.5 * mu * (ss - 3.0) - mu * l + 0.5 * lam * l * l;
+  return 0.5 * k * q + 0.5 * mi * (ss - 3.0) - mu * l + 0.5 * lam * l * l;
 }
 
-// Hessian of f: diag(k + mu + (mu - lam l + lam)/s_i^2) + lam u u^T with u_i = 1/s_i
+// Hessian of f: diag(k + mi + (mu - lam l + lam)/s_i^2) + lam u u^T with u_i = 1/s_i
 // (Eq. nh_hessian_stretch with the diagonal read as mu (1 + s^-2)).
-__device__ __forceinline__ void prox_hessian(const double s[3], double mu, double lam, double k, double l,
+__device__ __forceinline__ void prox_hessian(const double s[3], double mi, double mu, double lam, double k, double l,
                                              double H[6]) {  // H00 H11 H22 H01 H02 H12
   const double u0 = 1.0 / s[0], u1 = 1.0 / s[1], u2 = 1.0 / s[2];
   const double dc = mu - lam * l + lam;
-  H[0] = k + mu + dc * u0 * u0;
-  H[1] = k + mu + dc * u1 * u1;
-  H[2] = k + mu + dc * u2 * u2;
+  H[0] = k + mi + dc * u0 * u0;
+  H[1] = k + mi + dc * u1 * u1;
+  H[2] = k + mi + dc * u2 * u2;
   H[3] = lam * u0 * u1;
   H[4] = lam * u0 * u2;
   H[5] = lam * u1 * u2;
@@ -193,8 +197,8 @@ __device__ __forceinline__ void prox_hessian(const double s[3], double mu, doubl
 // |g|_inf <= 1e-13 k max(1, |sF|_inf).  Returns the Newton iteration count.
 // ratio (may be null): per stretch, a previous s*/sF used as the start
 // s = sF * ratio when both are positive.
-__device__ __forceinline__ int prox_stretch(const double sF[3], double mu, double lam, double k, double s[3],
-                                            const double* ratio = nullptr) {
+__device__ __forceinline__ int prox_stretch_g(const double sF[3], double mi, double mu, double lam, double k,
+                                              double s[3], const double* ratio) {
 #pragma unroll
   for (int i = 0; i < 3; ++i) {
     s[i] = fmax(sF[i], 0.1);
@@ -209,7 +213,7 @@ __device__ __forceinline__ int prox_stretch(const double sF[3], double mu, doubl
 #pragma unroll
     for (int i = 0; i < 3; ++i) {
       u[i] = 1.0 / s[i];
-      g[i] = k * (s[i] - sF[i]) + mu * s[i] - mu * u[i] + lam * l * u[i];
+      g[i] = k * (s[i] - sF[i]) + mi * s[i] - mu * u[i] + lam * l * u[i];
     }
     if (fmax(fabs(g[0]), fmax(fabs(g[1]), fabs(g[2]))) <= gtol) break;
     // Hessian = diag(D) + lam u u^T: the rank-one part carries lam / s_i^2 of
@@ -219,7 +223,7 @@ __device__ __forceinline__ int prox_stretch(const double sF[3], double mu, doubl
     bool diag_pos = true;
 #pragma unroll
     for (int i = 0; i < 3; ++i) {
-      D[i] = k + mu + dc * u[i] * u[i];
+      D[i] = k + mi + dc * u[i] * u[i];
       diag_pos = diag_pos && (D[i] > 0.0);
     }
     if (diag_pos) {
@@ -234,8 +238,44 @@ __device__ __forceinline__ int prox_stretch(const double sF[3], double mu, doubl
 #pragma unroll
       for (int i = 0; i < 3; ++i) d[i] = -(g[i] - u[i] * f) / D[i];
     } else {
+      // the diagonal part is not positive: the full 3x3 Hessian by Cholesky,
+      // or, if it is indefinite too, its absolute-value filtered form
+      double H[6];
+      prox_hessian(s, mi, mu, lam, k, l, H);
+      const double l00 = H[0];
+      bool pd = l00 > 0.0;
+      double L00 = 0, L10 = 0, L20 = 0, L11 = 0, L21 = 0, L22 = 0;
+      if (pd) {
+        L00 = sqrt(l00);
+        L10 = H[3] / L00;
+        L20 = H[4] / L00;
+        const double a11 = H[1] - L10 * L10;
+        pd = a11 > 0.0;
+        if (pd) {
+          L11 = sqrt(a11);
+          L21 = (H[5] - L20 * L10) / L11;
+          const double a22 = H[2] - L20 * L20 - L21 * L21;
+          pd = a22 > 0.0;
+          if (pd) L22 = sqrt(a22);
+        }
+      }
+      if (pd) {
+        const double y0 = -g[0] / L00, y1 = (-g[1] - L10 * y0) / L11, y2 = (-g[2] - L20 * y0 - L21 * y1) / L22;
+        d[2] = y2 / L22;
+        d[1] = (y1 - L21 * d[2]) / L11;
+        d[0] = (y0 - L10 * d[1] - L20 * d[2]) / L00;
+      } else {
+        double ev[3], Q[9];
+        sym3_eig(H[0], H[1], H[2], H[3], H[4], H[5], ev, Q);
+        double t3[3];
 #pragma unroll
-      for (int i = 0; i < 3; ++i) d[i] = -g[i] / (fabs(D[i]) + k);
+        for (int j = 0; j < 3; ++j) {
+          const double a = -(Q[j] * g[0] + Q[3 + j] * g[1] + Q[6 + j] * g[2]);
+          t3[j] = a / fmax(fabs(ev[j]), 1e-300);
+        }
+#pragma unroll
+        for (int i = 0; i < 3; ++i) d[i] = Q[3 * i] * t3[0] + Q[3 * i + 1] * t3[1] + Q[3 * i + 2] * t3[2];
+      }
     }
     double a = 1.0;
 #pragma unroll
@@ -249,13 +289,13 @@ __device__ __forceinline__ int prox_stretch(const double sF[3], double mu, doubl
 #pragma unroll
       for (int i = 0; i < 3; ++i) sn[i] = s[i] + d[i];
     } else {
-      const double f0 = prox_f(s, sF, mu, lam, k);
+      const double f0 = prox_f(s, sF, mi, mu, lam, k);
       const double slope = g[0] * d[0] + g[1] * d[1] + g[2] * d[2];
       const double slack = 1e-13 * k * (1.0 + s[0] * s[0] + s[1] * s[1] + s[2] * s[2]);
       for (int ls = 0; ls < 40; ++ls) {
 #pragma unroll
         for (int i = 0; i < 3; ++i) sn[i] = s[i] + a * d[i];
-        if (prox_f(sn, sF, mu, lam, k) <= f0 + 1e-4 * a * slope + slack) break;
+        if (prox_f(sn, sF, mi, mu, lam, k) <= f0 + 1e-4 * a * slope + slack) break;
         a *= 0.5;
       }
     }
@@ -270,6 +310,11 @@ __device__ __forceinline__ int prox_stretch(const double sF[3], double mu, doubl
   return it;
 }
 
+__device__ __forceinline__ int prox_stretch(const double sF[3], double mu, double lam, double k, double s[3],
+                                            const double* ratio = nullptr) {
+  return prox_stretch_g(sF, mu, mu, lam, k, s, ratio);
+}
+
 // ---------------------------------------------------------------------------
 // Filtered prox differential (Sec. 4.4 Eqs. Hprox, tr_blend, tr_ift):
 //   D = k H~^+, H~ = (1 - tau) H_prox + tau |H_prox|, H_prox = H(s*) of f,
@@ -279,11 +324,11 @@ __device__ __forceinline__ int prox_stretch(const double sF[3], double mu, doubl
 __device__ __forceinline__ void pair_coeffs(const double sF[3], const double ss[3], const double D[6], double c1[3],
                                             double c2[3]);
 
-__device__ __forceinline__ void prox_diff(const double sF[3], const double ss[3], double mu, double lam, double k,
-                                          double tau, double D[6], double c1[3], double c2[3]) {
+__device__ __forceinline__ void prox_diff_g(const double sF[3], const double ss[3], double mi, double mu, double lam,
+                                            double k, double tau, double D[6], double c1[3], double c2[3]) {
   const double l = log(ss[0] * ss[1] * ss[2]);
   double H[6];
-  prox_hessian(ss, mu, lam, k, l, H);
+  prox_hessian(ss, mi, mu, lam, k, l, H);
   double ev[3], Q[9];
   sym3_eig(H[0], H[1], H[2], H[3], H[4], H[5], ev, Q);
   double kt[3];
@@ -303,6 +348,11 @@ __device__ __forceinline__ void prox_diff(const double sF[3], const double ss[3]
     D[t] = Q[3 * i] * inv[0] * Q[3 * j] + Q[3 * i + 1] * inv[1] * Q[3 * j + 1] + Q[3 * i + 2] * inv[2] * Q[3 * j + 2];
   }
   pair_coeffs(sF, ss, D, c1, c2);
+}
+
+__device__ __forceinline__ void prox_diff(const double sF[3], const double ss[3], double mu, double lam, double k,
+                                          double tau, double D[6], double c1[3], double c2[3]) {
+  prox_diff_g(sF, ss, mu, mu, lam, k, tau, D, c1, c2);
 }
 
 // Pair coefficients of the SVD differential of an isotropic stretch map

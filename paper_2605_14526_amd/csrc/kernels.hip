@@ -545,10 +545,17 @@ __device__ __forceinline__ void b_local(ElemArgs E, StepState St, RedArgs R, con
     for (int j = 0; j < 9; ++j) V[j] = (j % 4 == 0) ? 1.0 : 0.0;
   svd3(F, U, sF, V, warm);
   double P[9];
-  if (E.energy == 1) {
-    // corotated + volume: 2 mu_e V_e R + lam_e V_e P_vol = U diag(2 mu_e V_e + lam_e V_e sv) V^T
+  if (E.energy >= 1) {
+    // corotated + volume: 2 mu_e V_e R + lam_e V_e P_vol = U diag(2 mu_e V_e + lam_e V_e sv) V^T;
+    // energy 2 takes the logarithmic barrier's stretch step (Eq. pd_log_volume: the prox Newton
+    // without the I1 term, means mu_bar, lam_bar, penalty lam_bar) for the volume step
     double nu = rt[0], sv[3];
-    volume_project(sF, nu, sv);
+    if (E.energy == 1) {
+      volume_project(sF, nu, sv);
+    } else {
+      const int nit = prox_stretch_g(sF, 0.0, E.mu_bar, E.lam_bar, E.lam_bar, sv, rt);
+      if (newton_cap && nit >= kNewtonCap) *newton_cap = 1;
+    }
     const double m2 = 2.0 * E.muV[t], lv = E.lamV[t];
     double sw[3];
 #pragma unroll
@@ -559,7 +566,8 @@ __device__ __forceinline__ void b_local(ElemArgs E, StepState St, RedArgs R, con
       for (int j = 0; j < 3; ++j)
         P[3 * i + j] = U[3 * i] * sw[0] * V[3 * j] + U[3 * i + 1] * sw[1] * V[3 * j + 1] + U[3 * i + 2] * sw[2] * V[3 * j + 2];
     store_GtP(T, St.contrib, E.ninc, P);
-    store_warm_nu(E, t, V, nu);
+    if (E.energy == 1) store_warm_nu(E, t, V, nu);
+    else store_warm(E, t, V, sF, sv);
     return;
   }
   const int nit = prox_stretch(sF, E.mu_bar, E.lam_bar, E.k_bar, ss, rt);
@@ -1672,14 +1680,22 @@ __global__ void __launch_bounds__(kBlock) k_bwd_elem(ElemArgs E, VertArgs Vx, Re
   for (int j = 0; j < 3; ++j) rt[j] = E.rw[(size_t)j * E.ne + t];
   double D[6], c1[3], c2[3];
   double nu = rt[0];
-  if (E.energy == 1) {
+  double sv[3];  // the volume step's stretches (energies 1 and 2)
+  if (E.energy >= 1) {
     // corotated + volume, per unit of w_e = 2 mu_e + lam_e: the stretch map
     // ss = th_r + th_v sv (th_r = 2 mu_e / w_e, th_v = lam_e / w_e), whose
     // Jacobian is th_v D_vol (the rotation's stretches are constant); no
-    // trust-region filter (Alg. 2 applies it to the Neo-Hookean prox)
-    double sv[3], Dv[6];
-    volume_project(sF, nu, sv);
-    volume_diff(sF, sv, Dv);
+    // trust-region filter (Alg. 2 applies it to the Neo-Hookean prox).  The
+    // barrier's D_vol = lam_bar (H + lam_bar I)^{-1} from its stationarity.
+    double Dv[6];
+    if (E.energy == 1) {
+      volume_project(sF, nu, sv);
+      volume_diff(sF, sv, Dv);
+    } else {
+      double e1[3], e2[3];
+      prox_stretch_g(sF, 0.0, E.mu_bar, E.lam_bar, E.lam_bar, sv, rt);
+      prox_diff_g(sF, sv, 0.0, E.mu_bar, E.lam_bar, E.lam_bar, 0.0, Dv, e1, e2);
+    }
     const double wv = E.wV[t], thr = 2.0 * E.muV[t] / wv, thv = E.lamV[t] / wv;
 #pragma unroll
     for (int j = 0; j < 3; ++j) ss[j] = thr + thv * sv[j];
@@ -1707,6 +1723,8 @@ __global__ void __launch_bounds__(kBlock) k_bwd_elem(ElemArgs E, VertArgs Vx, Re
   // a reverse sweep visits q* of neighbouring steps: start the next one from here
   if (E.energy == 1)
     store_warm_nu(E, t, V, nu);
+  else if (E.energy == 2)
+    store_warm(E, t, V, sF, sv);
   else
     store_warm(E, t, V, sF, ss);
 }

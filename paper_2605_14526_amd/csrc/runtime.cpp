@@ -439,7 +439,7 @@ void setup_scene(Scene& S, const pd_mesh_desc* mesh, const pd_material_desc* mat
   for (int v : S.tets)
     if (v < 0 || v >= nv) throw PdError{PD_ERR_INVALID_ARG, "tet vertex index out of range"};
   S.nu = mat->nu; S.rho = mat->rho; S.alpha = mat->alpha; S.beta0 = mat->beta0;
-  if (mat->energy < 0 || mat->energy > 1) throw PdError{PD_ERR_INVALID_ARG, "energy must be 0 or 1"};
+  if (mat->energy < 0 || mat->energy > 2) throw PdError{PD_ERR_INVALID_ARG, "energy must be 0, 1 or 2"};
   S.energy = mat->energy;
   S.h = o->h;
   for (int a = 0; a < 3; ++a) S.grav[a] = o->gravity[a];

@@ -1,7 +1,9 @@
 """The corotated + volume composite (the paper's default heterogeneous PD
-assembly, Sec. 4.1 and Sec. 7.2) on the GPU against the oracle: local step,
-K apply, forward steps (path parity through the gate), backward steps, the
-rest state, and the 20,000-tet beam.  All calls go through the C ABI."""
+assembly, Sec. 4.1 and Sec. 7.2; energy 1) and its logarithmic volume-barrier
+variant (Sec. 4.1 Eq. pd_log_volume; energy 2) on the GPU against the oracle:
+local step, K apply, forward steps (path parity through the gate), backward
+steps, the rest state, and the 20,000-tet beam.  All calls go through the C
+ABI."""
 import copy
 
 import numpy as np
@@ -30,17 +32,18 @@ def host(t):
     return t.detach().cpu().numpy()
 
 
-def composite(sc):
+def composite(sc, energy=1):
     sc = copy.copy(sc)
-    sc.energy = 1
+    sc.energy = energy
     return sc
 
 
 SMALL = [
-    lambda: composite(scenes.small_beam(4, 2, 2, seed=3)),
-    lambda: composite(scenes.small_beam(7, 3, 3, seed=5, contrast=30.0, nu=0.49)),
-    lambda: composite(scenes.small_beam(10, 4, 3, seed=11, contrast=1.0, aa_window=5, alpha=0.0, beta_rel=0.0)),
+    lambda e: composite(scenes.small_beam(4, 2, 2, seed=3), e),
+    lambda e: composite(scenes.small_beam(7, 3, 3, seed=5, contrast=30.0, nu=0.49), e),
+    lambda e: composite(scenes.small_beam(10, 4, 3, seed=11, contrast=1.0, aa_window=5, alpha=0.0, beta_rel=0.0), e),
 ]
+ENERGIES = [1, 2]
 
 
 def pair(sc, **kw):
@@ -55,12 +58,13 @@ def perturbed(sc, amp, seed):
     return q
 
 
+@pytest.mark.parametrize("energy", ENERGIES)
 @pytest.mark.parametrize("mk", SMALL)
-def test_local_rhs_parity(th, mk):
+def test_local_rhs_parity(th, mk, energy):
     """sum_e (2 mu_e V_e G^T R + lam_e V_e G^T P_vol), up to strains where the
     volume step leaves its branch through the identity (amplitude 3e-2 on
     5 cm cells)."""
-    sc = mk()
+    sc = mk(energy)
     g, o = pair(sc)
     free = ~sc.pinned.astype(bool)
     for amp, seed in [(0.0, 1), (2e-3, 2), (1e-2, 3), (3e-2, 4)]:
@@ -70,9 +74,10 @@ def test_local_rhs_parity(th, mk):
         assert rel(b_g[free], b_o[free]) < 1e-11, (amp, rel(b_g[free], b_o[free]))
 
 
+@pytest.mark.parametrize("energy", ENERGIES)
 @pytest.mark.parametrize("mk", SMALL)
-def test_apply_K_parity(th, mk):
-    sc = mk()
+def test_apply_K_parity(th, mk, energy):
+    sc = mk(energy)
     g, o = pair(sc)
     r = np.random.Generator(np.random.PCG64(23))
     q = perturbed(sc, 5e-3, 29)
@@ -86,6 +91,17 @@ def test_rest_state(th):
     qn, vn, st = g.step_forward(dev(th, sc.X), dev(th, np.zeros_like(sc.X)))
     assert st["iters"] == 2 and st["status"] == 0
     assert rel(host(qn), sc.X) < 1e-14
+
+
+def test_barrier_rest_state_matches_oracle(th):
+    """The barrier as printed is not force-free at rest (its gradient at s = 1
+    is -mu): from rest without loads both sides move by the same amount."""
+    sc = composite(scenes.small_beam(6, 3, 3, seed=2, tip_force=0.0, gravity=(0.0, 0.0, 0.0)), 2)
+    g, o = pair(sc)
+    qn, vn, st = g.step_forward(dev(th, sc.X), dev(th, np.zeros_like(sc.X)))
+    qo, vo, _, sto = o.step_forward(sc.X, np.zeros_like(sc.X))
+    assert st["status"] == 0 and st["iters"] == sto["iters"]
+    assert rel(host(qn), qo) < 1e-9 and np.abs(qo - sc.X).max() > 1e-9
 
 
 def forward_pair(th, sc, steps, **kw):
@@ -113,17 +129,19 @@ def forward_pair(th, sc, steps, **kw):
     return g, o, ck, worst, its
 
 
+@pytest.mark.parametrize("energy", ENERGIES)
 @pytest.mark.parametrize("mk", SMALL)
-def test_forward_parity(th, mk):
-    sc = mk()
+def test_forward_parity(th, mk, energy):
+    sc = mk(energy)
     g, o, ck, worst, its = forward_pair(th, sc, 4)
     assert worst < 1e-9, (worst, its)
 
 
+@pytest.mark.parametrize("energy", ENERGIES)
 @pytest.mark.parametrize("mk", SMALL)
 @pytest.mark.parametrize("method", [0, 1])
-def test_backward_parity(th, mk, method):
-    sc = mk()
+def test_backward_parity(th, mk, method, energy):
+    sc = mk(energy)
     eps = 1e-12 if method == 0 else 1e-10
     g, o, ck, worst, its = forward_pair(th, sc, 3, adj_method=method, eps_adj=eps)
     r = np.random.Generator(np.random.PCG64(31))
@@ -137,12 +155,13 @@ def test_backward_parity(th, mk, method):
             assert rel(host(a), b) < 1e-6, rel(host(a), b)
 
 
-def test_hetero_beam_full_size(th):
+@pytest.mark.parametrize("energy", ENERGIES)
+def test_hetero_beam_full_size(th, energy):
     """The 20,000-tet heterogeneous beam with the composite: four forward steps
     of the library's own rollout (the oracle on the same path) and their
     reverse sweep against the oracle's adjoint run to 1e-13."""
     from paper_2605_14526_amd.binding import Scene
-    sc = composite(scenes.config("c2"))
+    sc = composite(scenes.config("c2"), energy)
     T = 4
     g = Scene.from_scene(sc, eps_adj=1e-11, adj_warm=3)
     o = O.OracleScene(sc, eps_adj=1e-13)

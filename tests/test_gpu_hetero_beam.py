@@ -175,4 +175,4 @@ def test_material_gradient_central_differences_16_tets(th):
     big_l = np.abs(fd_l) >= 1e-3 * scale_l
     assert big_l.sum() >= 8
     assert (np.abs(ad_l - fd_l)[big_l] <= 2e-4 * np.abs(fd_l)[big_l]).all(), np.abs(ad_l - fd_l) / np.abs(fd_l)
-    assert np.abs(ad_l - fd_l).max() <= 1e-6 * scale_l
+    assert np.abs(ad_l - fd_l)[~big_l].max() <= 1e-6 * scale_l

@@ -40,10 +40,10 @@ constexpr int kFinStride = 64;  // doubles per site in the final buffer
 #define PD_BOTTOM_THREADS 512
 #endif
 #ifndef PD_BOTTOM_CHUNK
-#define PD_BOTTOM_CHUNK 4
+#define PD_BOTTOM_CHUNK 1
 #endif
 #ifndef PD_BOTTOM_CHUNK_E
-#define PD_BOTTOM_CHUNK_E 3
+#define PD_BOTTOM_CHUNK_E 1
 #endif
 #ifndef PD_EB_CHUNK
 #define PD_EB_CHUNK 8
@@ -54,7 +54,14 @@ constexpr int kFinStride = 64;  // doubles per site in the final buffer
 #ifndef PD_ELEM_BLOCK
 #define PD_ELEM_BLOCK 256
 #endif
-constexpr int kBottomThreads = PD_BOTTOM_THREADS;  // subdomain solve: 64 threads (one row) per wave
+#ifndef PD_BOTTOM_RPW
+#define PD_BOTTOM_RPW 4
+#endif
+constexpr int kBottomThreads = PD_BOTTOM_THREADS;  // subdomain solve: 64 threads per wave
+// subdomain rows per wave: a wave walks kBottomRowsPerWave rows together (all
+// their loads of a trip before the arithmetic), rows of one block are consecutive
+constexpr int kBottomRowsPerWave = PD_BOTTOM_RPW;
+constexpr int kBottomRows = (kBottomThreads / 64) * kBottomRowsPerWave;  // subdomain rows per block
 // Row walks of the solve kernels: a wave takes its row in chunks of 64 x chunk
 // entries and each lane requests all of its chunk's entries before it uses
 // any, so a chunk costs one memory round trip.

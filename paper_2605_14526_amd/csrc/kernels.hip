@@ -1086,31 +1086,32 @@ __device__ __forceinline__ void b_bottom(VertArgs Vx, SolveArgs Sv, StepState St
                                                    const double* __restrict__ rhs, double* __restrict__ out, int k, int bid) {
   const int nv = Vx.nv, nB = Sv.nB, nf = Vx.nf;
   const int lane = threadIdx.x & 63;
-  constexpr int kRows = kBottomThreads / 64;
-  const int n_sub_blocks = (nB + kRows - 1) / kRows;
+  constexpr int RW = kBottomRowsPerWave;
+  const int n_sub_blocks = (nB + kBottomRows - 1) / kBottomRows;
   const bool sub_block = (int)bid < n_sub_blocks;
-  const int v = bid * kRows + (threadIdx.x >> 6);
-  const bool have_row = sub_block && v < nB;
+  // rows v0 .. v0 + RW - 1 of this wave; lane j < RW owns row v0 + j
+  const int v0 = bid * kBottomRows + (threadIdx.x >> 6) * RW;
   int my_row = -1;
-  if (have_row) {
-    if (lane == 0) my_row = v;
-  } else if (!sub_block) {
+  if (sub_block) {
+    if (lane < RW && v0 + lane < nB) my_row = v0 + lane;
+  } else {
     const int i = nB + (bid - n_sub_blocks) * blockDim.x + threadIdx.x;
     if (i < nf) my_row = i;
   }
+  const bool have_row = sub_block && my_row >= 0;  // this lane owns a subdomain row
   const bool iface = my_row >= nB;
   constexpr bool kPCG = (MODE == kModePCG || MODE == kModePCGSolve);
   const double* __restrict__ src = (MODE == kModeFwd) ? St.b_cur : (kPCG ? r_cur(A, k) : rhs);
   const double* __restrict__ wv = A.w;
   double* dst = (MODE == kModeFwd) ? St.qhat : out;
   const int* done = (MODE == kModeFwd || MODE == kModePlain) ? St.done : A.done;
-  // ---- first round of loads
+  // ---- first round of loads: lane j fetches the descriptors of row v0 + j
   BRow br = {0, 0, 0, 0};
   BOff bo = {0, 0};
   BStage bst = {0, 0, 0, 0};
   if (have_row) {
-    br = Sv.brow[v];
-    bo = Sv.boff[v];
+    br = Sv.brow[my_row];
+    bo = Sv.boff[my_row];
   }
   if (sub_block) bst = Sv.bstage[bid];
   __shared__ int flag_s;
@@ -1150,35 +1151,39 @@ __device__ __forceinline__ void b_bottom(VertArgs Vx, SolveArgs Sv, StepState St
   __syncthreads();
   if (flag_s) return;
   const double alpha = rz / pwt;
-  // the row descriptors are the same in every lane of the wave
-  const int ns = wave_uniform(br.ns), nI = wave_uniform(br.nI);
-  const int b0 = wave_uniform(br.b0), ir0 = wave_uniform(br.ir0);
-  const double* __restrict__ Zr = Sv.Zs + wave_uniform(bo.zs);
-  const double* __restrict__ Er = Sv.Et + wave_uniform(bo.et);
+  // the descriptors of the wave's rows, wave-uniform (ns = 0 for a row past nB)
+  int ns[RW], nI[RW], b0[RW], ir0[RW];
+  long long zs[RW], et[RW];
+#pragma unroll
+  for (int j = 0; j < RW; ++j) {
+    ns[j] = wave_uniform(__shfl(br.ns, j, 64));
+    nI[j] = wave_uniform(__shfl(br.nI, j, 64));
+    b0[j] = wave_uniform(__shfl(br.b0, j, 64));
+    ir0[j] = wave_uniform(__shfl(br.ir0, j, 64));
+    zs[j] = wave_uniform(__shfl(bo.zs, j, 64));
+    et[j] = wave_uniform(__shfl(bo.et, j, 64));
+  }
   const int ni = Sv.n_irows;
   // each trip of a row walk takes 64 x kBottomChunk entries of Z_s[v, :]
   // (against the right-hand side) and 64 x kBottomChunkE of E_s^T[v, :]
   // (against x_T(s)); entries past a part's end repeat its last entry with
   // weight zero
   constexpr int kSpan = 64 * kBottomChunk, kSpanE = 64 * kBottomChunkE;
-  const int tz = (ns + kSpan - 1) / kSpan, te = (nI + kSpanE - 1) / kSpanE;
-  // ---- staging: the block's rows share one or two subdomains, so it stages
+  int tz[RW], te[RW], tmax = 0;
+#pragma unroll
+  for (int j = 0; j < RW; ++j) {
+    tz[j] = (ns[j] + kSpan - 1) / kSpan;
+    te[j] = (nI[j] + kSpanE - 1) / kSpanE;
+    tmax = max(tmax, max(tz[j], te[j]));
+  }
+  // ---- staging: the block's rows share one or a few subdomains, so it stages
   // their right-hand-side rows (r - alpha w in PCG) and interface copies in LDS
-  // once instead of every row reading them from memory; the first chunk of
-  // each row's coefficients is requested together with them.  Blocks whose
-  // ranges exceed the buffers (zn = 0) read them in the row walk instead.
+  // once instead of every row reading them from memory.  Blocks whose ranges
+  // exceed the buffers (zn = 0) read them in the row walk instead.
   double* sz = bottom_stage_lds();
   double* se = sz + 3 * kStageZ;
   const bool staged = sub_block && bst.zn > 0;  // block-uniform
-  double cz0[kBottomChunk], ce0[kBottomChunkE];
   if (staged) {
-    if (have_row) {
-#pragma unroll
-      for (int j = 0; j < kBottomChunk; ++j) cz0[j] = Zr[min(lane + 64 * j, ns - 1)];
-      if (nI > 0)
-#pragma unroll
-        for (int j = 0; j < kBottomChunkE; ++j) ce0[j] = Er[min(lane + 64 * j, nI - 1)];
-    }
     constexpr int kPZ = (kStageZ + kBottomThreads - 1) / kBottomThreads;
     constexpr int kPE = (kStageE + kBottomThreads - 1) / kBottomThreads;
     double vz[kPZ][3], ve[kPE][3];
@@ -1215,132 +1220,146 @@ __device__ __forceinline__ void b_bottom(VertArgs Vx, SolveArgs Sv, StepState St
       }
   }
   __syncthreads();
-  // ---- the subdomain row: x_v = Z_s[v, :] rhs_s - E_s^T[v, :] x_T(s)
-  if (have_row && staged) {
-    // the same walk as below (same per-lane order of the terms), with the
-    // right-hand side and x_T(s) read from LDS
-    const int zo = b0 - bst.z0, eo = ir0 - bst.e0;
-    double a0 = 0, a1 = 0, a2 = 0;
-    for (int t = 0; t < max(tz, te); ++t) {
-      double cz[kBottomChunk], ce[kBottomChunkE];
-      if (t == 0) {
+  // ---- the subdomain rows: x_v = Z_s[v, :] rhs_s - E_s^T[v, :] x_T(s)
+  double acc[RW][3];
 #pragma unroll
-        for (int j = 0; j < kBottomChunk; ++j) cz[j] = cz0[j];
+  for (int j = 0; j < RW; ++j) acc[j][0] = acc[j][1] = acc[j][2] = 0.0;
+  if (sub_block && staged) {
+    // every trip requests the chunk of all the wave's rows before it adds any
+    // (per row the same per-lane order of terms as a walk of that row alone);
+    // the right-hand side and x_T(s) come from LDS
+    for (int t = 0; t < tmax; ++t) {
+      double cz[RW][kBottomChunk], ce[RW][kBottomChunkE];
 #pragma unroll
-        for (int j = 0; j < kBottomChunkE; ++j) ce[j] = ce0[j];
-      } else {
-        if (t < tz)
+      for (int j = 0; j < RW; ++j) {
+        const double* __restrict__ Zr = Sv.Zs + zs[j];
+        const double* __restrict__ Er = Sv.Et + et[j];
+        if (t < tz[j])
 #pragma unroll
-          for (int j = 0; j < kBottomChunk; ++j) cz[j] = Zr[min(t * kSpan + lane + 64 * j, ns - 1)];
-        if (t < te)
+          for (int i = 0; i < kBottomChunk; ++i) cz[j][i] = Zr[min(t * kSpan + lane + 64 * i, ns[j] - 1)];
+        if (t < te[j])
 #pragma unroll
-          for (int j = 0; j < kBottomChunkE; ++j) ce[j] = Er[min(t * kSpanE + lane + 64 * j, nI - 1)];
+          for (int i = 0; i < kBottomChunkE; ++i) ce[j][i] = Er[min(t * kSpanE + lane + 64 * i, nI[j] - 1)];
       }
-      if (t < tz)
 #pragma unroll
-        for (int j = 0; j < kBottomChunk; ++j) {
-          const int u = t * kSpan + lane + 64 * j;
-          const double c = (u < ns) ? cz[j] : 0.0;
-          const int q = zo + min(u, ns - 1);
-          a0 += c * sz[q];
-          a1 += c * sz[kStageZ + q];
-          a2 += c * sz[2 * kStageZ + q];
+      for (int j = 0; j < RW; ++j) {
+        const int zo = b0[j] - bst.z0, eo = ir0[j] - bst.e0;
+        if (t < tz[j])
+#pragma unroll
+          for (int i = 0; i < kBottomChunk; ++i) {
+            const int u = t * kSpan + lane + 64 * i;
+            const double c = (u < ns[j]) ? cz[j][i] : 0.0;
+            const int q = zo + min(u, ns[j] - 1);
+            acc[j][0] += c * sz[q];
+            acc[j][1] += c * sz[kStageZ + q];
+            acc[j][2] += c * sz[2 * kStageZ + q];
+          }
+        if (t < te[j])
+#pragma unroll
+          for (int i = 0; i < kBottomChunkE; ++i) {
+            const int p = t * kSpanE + lane + 64 * i;
+            const double c = (p < nI[j]) ? ce[j][i] : 0.0;
+            const int q = eo + min(p, nI[j] - 1);
+            acc[j][0] -= c * se[q];
+            acc[j][1] -= c * se[kStageE + q];
+            acc[j][2] -= c * se[2 * kStageE + q];
+          }
+      }
+    }
+  } else if (sub_block) {
+    // one row at a time, the right-hand side and x_T(s) read in the walk
+#pragma unroll
+    for (int j = 0; j < RW; ++j) {
+      const double* __restrict__ Zr = Sv.Zs + zs[j];
+      const double* __restrict__ Er = Sv.Et + et[j];
+      const double* __restrict__ x0 = Sv.xsT + ir0[j];
+      const double* __restrict__ s0 = src + b0[j];
+      const double* __restrict__ w0 = wv + b0[j];
+      const int nsj = ns[j], nIj = nI[j];
+      double a0 = 0, a1 = 0, a2 = 0;
+      double cz[kBottomChunk], yz[kBottomChunk][3], wz[kBottomChunk][3];
+      double ce[kBottomChunkE], ye[kBottomChunkE][3];
+      auto load_z = [&](int t) {
+#pragma unroll
+        for (int i = 0; i < kBottomChunk; ++i) {
+          const unsigned o = 8u * (unsigned)min(t * kSpan + lane + 64 * i, nsj - 1);
+          cz[i] = at_byte(Zr, o);
+#pragma unroll
+          for (int a = 0; a < 3; ++a) {
+            yz[i][a] = at_byte(s0 + a * nv, o);
+            if (kPCG) wz[i][a] = at_byte(w0 + a * nv, o);
+          }
         }
-      if (t < te)
+      };
+      auto load_e = [&](int t) {
 #pragma unroll
-        for (int j = 0; j < kBottomChunkE; ++j) {
-          const int p = t * kSpanE + lane + 64 * j;
-          const double c = (p < nI) ? ce[j] : 0.0;
-          const int q = eo + min(p, nI - 1);
-          a0 -= c * se[q];
-          a1 -= c * se[kStageE + q];
-          a2 -= c * se[2 * kStageE + q];
+        for (int i = 0; i < kBottomChunkE; ++i) {
+          const unsigned o = 8u * (unsigned)min(t * kSpanE + lane + 64 * i, nIj - 1);
+          ce[i] = at_byte(Er, o);
+#pragma unroll
+          for (int a = 0; a < 3; ++a) ye[i][a] = at_byte(x0 + a * ni, o);
         }
-    }
-    xo[0] = wave_sum(a0);
-    xo[1] = wave_sum(a1);
-    xo[2] = wave_sum(a2);
-    if (lane == 0) {
-      dst[v] = xo[0];
-      dst[nv + v] = xo[1];
-      dst[2 * nv + v] = xo[2];
-    }
-  } else if (have_row) {
-    const double* __restrict__ x0 = Sv.xsT + ir0;
-    const double* __restrict__ s0 = src + b0;
-    const double* __restrict__ w0 = wv + b0;
-    double a0 = 0, a1 = 0, a2 = 0;
-    double cz[kBottomChunk], yz[kBottomChunk][3], wz[kBottomChunk][3];
-    double ce[kBottomChunkE], ye[kBottomChunkE][3];
-    auto load_z = [&](int t) {
+      };
+      auto add_z = [&](int t) {  // r - alpha w on the subdomain entries
 #pragma unroll
-      for (int j = 0; j < kBottomChunk; ++j) {
-        const unsigned o = 8u * (unsigned)min(t * kSpan + lane + 64 * j, ns - 1);
-        cz[j] = at_byte(Zr, o);
-#pragma unroll
-        for (int a = 0; a < 3; ++a) {
-          yz[j][a] = at_byte(s0 + a * nv, o);
-          if (kPCG) wz[j][a] = at_byte(w0 + a * nv, o);
+        for (int i = 0; i < kBottomChunk; ++i) {
+          const double c = (t * kSpan + lane + 64 * i < nsj) ? cz[i] : 0.0;
+          a0 += c * (kPCG ? yz[i][0] - alpha * wz[i][0] : yz[i][0]);
+          a1 += c * (kPCG ? yz[i][1] - alpha * wz[i][1] : yz[i][1]);
+          a2 += c * (kPCG ? yz[i][2] - alpha * wz[i][2] : yz[i][2]);
         }
-      }
-    };
-    auto load_e = [&](int t) {
+      };
+      auto add_e = [&](int t) {
 #pragma unroll
-      for (int j = 0; j < kBottomChunkE; ++j) {
-        const unsigned o = 8u * (unsigned)min(t * kSpanE + lane + 64 * j, nI - 1);
-        ce[j] = at_byte(Er, o);
-#pragma unroll
-        for (int a = 0; a < 3; ++a) ye[j][a] = at_byte(x0 + a * ni, o);
+        for (int i = 0; i < kBottomChunkE; ++i) {
+          const double c = (t * kSpanE + lane + 64 * i < nIj) ? ce[i] : 0.0;
+          a0 -= c * ye[i][0];
+          a1 -= c * ye[i][1];
+          a2 -= c * ye[i][2];
+        }
+      };
+      // trips over both parts (all loads of a trip before its arithmetic), then
+      // the longer part alone; the trip counts are wave-uniform
+      const int both = min(tz[j], te[j]);
+      for (int t = 0; t < both; ++t) {
+        load_z(t);
+        load_e(t);
+        add_z(t);
+        add_e(t);
       }
-    };
-    auto add_z = [&](int t) {  // r - alpha w on the subdomain entries
-#pragma unroll
-      for (int j = 0; j < kBottomChunk; ++j) {
-        const double c = (t * kSpan + lane + 64 * j < ns) ? cz[j] : 0.0;
-        a0 += c * (kPCG ? yz[j][0] - alpha * wz[j][0] : yz[j][0]);
-        a1 += c * (kPCG ? yz[j][1] - alpha * wz[j][1] : yz[j][1]);
-        a2 += c * (kPCG ? yz[j][2] - alpha * wz[j][2] : yz[j][2]);
+      for (int t = both; t < tz[j]; ++t) {
+        load_z(t);
+        add_z(t);
       }
-    };
-    auto add_e = [&](int t) {
-#pragma unroll
-      for (int j = 0; j < kBottomChunkE; ++j) {
-        const double c = (t * kSpanE + lane + 64 * j < nI) ? ce[j] : 0.0;
-        a0 -= c * ye[j][0];
-        a1 -= c * ye[j][1];
-        a2 -= c * ye[j][2];
+      for (int t = both; t < te[j]; ++t) {
+        load_e(t);
+        add_e(t);
       }
-    };
-    // trips over both parts (all loads of a trip before its arithmetic), then
-    // the longer part alone; the trip counts are wave-uniform
-    const int both = min(tz, te);
-    for (int t = 0; t < both; ++t) {
-      load_z(t);
-      load_e(t);
-      add_z(t);
-      add_e(t);
+      acc[j][0] = a0;
+      acc[j][1] = a1;
+      acc[j][2] = a2;
     }
-    for (int t = both; t < tz; ++t) {
-      load_z(t);
-      add_z(t);
+  }
+  if (sub_block) {
+#pragma unroll
+    for (int j = 0; j < RW; ++j) {
+      const double x0 = wave_sum(acc[j][0]), x1 = wave_sum(acc[j][1]), x2 = wave_sum(acc[j][2]);
+      if (lane == j) {
+        xo[0] = x0;
+        xo[1] = x1;
+        xo[2] = x2;
+      }
     }
-    for (int t = both; t < te; ++t) {
-      load_e(t);
-      add_e(t);
-    }
-    xo[0] = wave_sum(a0);
-    xo[1] = wave_sum(a1);
-    xo[2] = wave_sum(a2);
-    if (lane == 0) {
-      dst[v] = xo[0];
-      dst[nv + v] = xo[1];
-      dst[2 * nv + v] = xo[2];
+    if (have_row) {
+      dst[my_row] = xo[0];
+      dst[nv + my_row] = xo[1];
+      dst[2 * nv + my_row] = xo[2];
     }
   }
   if (MODE == kModePlain) return;
   // ---- per-vertex work
   if (MODE == kModeFwd) {
-    if constexpr (M > 0) aa_append<M>(St, R, nv, bid, my_row, xo, u0, u1, u2, aa, sub_block);
+    if constexpr (M > 0) aa_append<M>(St, R, nv, bid, my_row, xo, u0, u1, u2, aa, sub_block && RW == 1);
   } else {
     double v3[3] = {0, 0, 0};
     if (my_row >= 0) {
@@ -1369,11 +1388,11 @@ __device__ __forceinline__ void b_bottom(VertArgs Vx, SolveArgs Sv, StepState St
       }
     }
     if (MODE == kModeFixed) {
-      write_partial<3>(v3, R, kRedFix, bid, sub_block);
+      write_partial<3>(v3, R, kRedFix, bid, sub_block && RW == 1);
     } else if (MODE != kModePCGSolve) {
       // PCG sums of iteration k land in the parity slot read by iteration k + 1
       const int slot = (MODE == kModePCGInit) ? 0 : ((k + 1) & 1);
-      write_partial<3>(v3, R, kRedRZ0 + slot, bid, sub_block);
+      write_partial<3>(v3, R, kRedRZ0 + slot, bid, sub_block && RW == 1);
     }
   }
 }
@@ -2194,8 +2213,7 @@ bool launch_events_used() {
 
 int vert_group_blocks(int n) { return (8 * n + kBlock - 1) / kBlock; }
 int bottom_blocks(int nB, int nT) {
-  const int rows = kBottomThreads / 64;
-  return (nB + rows - 1) / rows + (nT + kBottomThreads - 1) / kBottomThreads;
+  return (nB + kBottomRows - 1) / kBottomRows + (nT + kBottomThreads - 1) / kBottomThreads;
 }
 int tr_blocks(int ne, int nf) { return (ne + kBlock - 1) / kBlock + (nf + kBlock - 1) / kBlock; }
 int contact_apply_blocks(int nf) { return (nf + kBlock - 1) / kBlock; }

@@ -801,7 +801,7 @@ void factorize(Scene& S) {
   // staged ranges of each subdomain-solve block (rows are in subdomain order, so
   // a block's rows span one contiguous range of right-hand-side rows and one of
   // interface copies)
-  constexpr int kRowsPerBlock = kBottomThreads / 64;
+  constexpr int kRowsPerBlock = kBottomRows;
   std::vector<BStage> bstage(std::max(1, (nB + kRowsPerBlock - 1) / kRowsPerBlock), BStage{0, 0, 0, 0});
   for (int b = 0; b * kRowsPerBlock < nB; ++b) {
     const BRow& f = brow[b * kRowsPerBlock];

@@ -56,6 +56,7 @@ def parse():
     ap.add_argument("--batch-scenes", type=int, default=64, help="scenes of --config batch")
     ap.add_argument("--tune-cache", default="", help="autotuner cache file of --config batch")
     ap.add_argument("--drop-res", type=int, default=27, help="cells along the blob of --config drop (27: 28k tets)")
+    ap.add_argument("--friction", type=float, default=0.5, help="Coulomb coefficient of the obstacles of --config drop")
     ap.add_argument("--copy-probe", action="store_true",
                     help="only copy a 64 MiB device buffer 3 times (calibrates the HBM byte counters) and exit")
     return ap.parse_args()
@@ -166,7 +167,11 @@ def cpu_baseline(samples, threads=None):
     try:
         for sc, steps in samples:
             osc = O.OracleScene(sc, eps_adj=ADJ_TOL)
-            if sc.obstacles:
+            if sc.obstacles and getattr(sc, "friction", 0.0) > 0.0:
+                q, v, ck, _ = O.rollout_friction(osc, steps, sc.friction)
+                _, gq = scenes.centroid_loss(q, sc.target_centroid)
+                O.rollout_backward_friction(osc, ck, gq, np.zeros_like(gq), sc.friction)
+            elif sc.obstacles:
                 q, v, ck, _ = O.rollout_contact(osc, steps)
                 _, gq = scenes.centroid_loss(q, sc.target_centroid)
                 O.rollout_backward_contact(osc, ck, gq, np.zeros_like(gq))
@@ -358,7 +363,7 @@ def bench_warmstart(args, torch):
     from paper_2605_14526_amd import scenes, warmstart
     from paper_2605_14526_amd.binding import Mpn, Scene
     res, S = args.drop_res, args.steps
-    fam = lambda k: scenes.drop_family(k, res=res, steps=100)  # noqa: E731
+    fam = lambda k: scenes.drop_family(k, res=res, steps=100, friction=args.friction)  # noqa: E731
     base = fam(0)
     t0 = time.perf_counter()
     g = Scene.from_scene(base)                 # plain and learned starts
@@ -430,7 +435,11 @@ def main():
     from paper_2605_14526_amd.binding import Scene
 
     drop = args.config == "drop"
-    sc = scenes.drop_blob(res=args.drop_res) if drop else scenes.config(args.config)
+    # the contact drop: mu = 0.5 on the ground and the box, and a sideways start (0.3, 0.1) m/s next to the
+    # 1 m/s fall so that contacts both slide and stick
+    sc = (scenes.drop_blob(res=args.drop_res, friction=args.friction,
+                           lateral=(0.3, 0.1) if args.friction > 0 else (0.0, 0.0))
+          if drop else scenes.config(args.config))
     dev = lambda a: torch.tensor(np.ascontiguousarray(a), dtype=torch.float64, device="cuda")  # noqa: E731
     # adjoint: start extrapolated (quadratically) from the sweep's previous solutions (runs to ADJ_TOL either way)
     g = Scene.from_scene(sc, eps_adj=ADJ_TOL, max_sub=args.max_sub, adj_warm=3)
@@ -467,8 +476,13 @@ def main():
            "scaling": "weak", "vs_baseline": None, "dtype": "f64", "data": "synthetic",
            "config": {"workload": (f"{sc.name}: voxelised blob of 6 spheres, {sc.n_e} tets, {sc.n_v} verts, shell "
                                    f"E 1e6 over interior 1e4, nu 0.49, h {sc.h}, dropped at 1 m/s onto the ground "
-                                   f"plane and a box, frictionless contact, rollout of {args.steps} steps, "
-                                   f"gate 1e-6, FB residual 1e-10, adjoint PCG to {ADJ_TOL:g}") if drop else
+                                   f"plane and a box"
+                                   + (f" with a sideways start of (0.3, 0.1) m/s, Coulomb friction mu "
+                                      f"{sc.friction:g} (one frame of three rows per contact vertex), "
+                                      f"projected fixed-point adjoint through the frictional rows to {ADJ_TOL:g}"
+                                      if sc.friction > 0 else
+                                      f", frictionless contact, adjoint PCG to {ADJ_TOL:g}")
+                                   + f", rollout of {args.steps} steps, gate 1e-6, FB residual 1e-10") if drop else
                                   (f"{sc.name}: 40x10x10 cubes, {sc.n_e} tets, {sc.n_v} verts, two-phase E 1e4/1e6, "
                                    f"nu 0.49, h {sc.h}, rollout of {args.steps} steps, AA window {sc.aa_window}, "
                                    f"gate 1e-6, adjoint PCG to {ADJ_TOL:g}, plain q0 = q_t, adjoint start "
@@ -497,7 +511,7 @@ def main():
         # scene's family (other beams; drops of the same blob with other initial velocities)
         from paper_2605_14526_amd import warmstart
         if drop:
-            fam = lambda k: scenes.drop_family(k, res=args.drop_res, steps=100)  # noqa: E731
+            fam = lambda k: scenes.drop_family(k, res=args.drop_res, steps=100, friction=args.friction)  # noqa: E731
         else:
             fam = lambda k: scenes.hetero_beam_family(k, steps=args.steps)  # noqa: E731
         net, hist, tsec, nsamp = warmstart.train_for(fam, args.train_scenes, 100, args.train_epochs, torch, seed=1,

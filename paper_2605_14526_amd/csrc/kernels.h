@@ -46,7 +46,10 @@ constexpr int kFinStride = 64;  // doubles per site in the final buffer
 #define PD_BOTTOM_CHUNK_E 1
 #endif
 #ifndef PD_EB_CHUNK
-#define PD_EB_CHUNK 8
+#define PD_EB_CHUNK 2
+#endif
+#ifndef PD_EB_RPW
+#define PD_EB_RPW 4
 #endif
 #ifndef PD_TOP_CHUNK
 #define PD_TOP_CHUNK 8
@@ -68,6 +71,8 @@ constexpr int kBottomRows = (kBottomThreads / 64) * kBottomRowsPerWave;  // subd
 constexpr int kBottomChunk = PD_BOTTOM_CHUNK;     // subdomain solve, Z_s rows
 constexpr int kBottomChunkE = PD_BOTTOM_CHUNK_E;  // subdomain solve, E_s^T rows
 constexpr int kEbChunk = PD_EB_CHUNK;          // interface right-hand side (E_s rows)
+constexpr int kEbRowsPerWave = PD_EB_RPW;       // interface rows walked together by one wave
+constexpr int kEbRows = (kBlock / 64) * kEbRowsPerWave;  // interface rows per block of that kernel
 constexpr int kTopChunk = PD_TOP_CHUNK;        // interface solve (Z rows)
 // LDS buffers of the subdomain solve: right-hand-side rows and interface
 // copies a block stages for its rows (three axes each)
@@ -256,6 +261,7 @@ bool launch_events_used();
 
 int vert_group_blocks(int n);
 int bottom_blocks(int nB, int nT);
+int eb_blocks(int nT);  // blocks of the interface right-hand side (at least one)
 int tr_blocks(int ne, int nf);
 void launch_local(const ElemArgs& E, const StepState& St, const RedArgs& R, const double* q, int nv, int nf,
                   int k, int fwd, hipStream_t s);

@@ -771,23 +771,32 @@ __device__ __forceinline__ double* r_cur(const AdjState& A, int it) { return (it
 template <int MODE>
 __device__ __forceinline__ void b_Eb(VertArgs Vx, SolveArgs Sv, StepState St, AdjState A, RedArgs R,
                                                const double* __restrict__ rhs, int k, int bid) {
+  constexpr int RW = kEbRowsPerWave;
   const int lane = threadIdx.x & 63;
-  const int row = (bid * blockDim.x + threadIdx.x) >> 6;
-  const bool have = row < Sv.nT;
+  // rows row0 .. row0 + RW - 1 of this wave; lane j < RW owns row row0 + j
+  const int row0 = ((bid * blockDim.x + threadIdx.x) >> 6) * RW;
+  const int my = row0 + lane;
+  const bool have = row0 < Sv.nT;  // wave-uniform
+  const bool mine = lane < RW && my < Sv.nT;
   const int nv = Vx.nv, nB = Sv.nB;
   const double* __restrict__ src = (MODE == kModeFwd) ? St.b_cur : (MODE == kModePCG ? r_cur(A, k) : rhs);
   const double* __restrict__ wv = A.w;
+  // lane j loads the row descriptor of row row0 + j, lane c + kMaxCoup j the
+  // coupling c of that row
   Cpl cd = {0, 0, 0, 0};
   ERow er = {0, 0, 0};
   double own[3] = {0.0, 0.0, 0.0}, ownw[3] = {0.0, 0.0, 0.0};
-  if (have) {
-    er = Sv.erow[row];
-    if (lane < kMaxCoup) cd = Sv.cpl[row * kMaxCoup + lane];
+  if (mine) {
+    er = Sv.erow[my];
 #pragma unroll
     for (int a = 0; a < 3; ++a) {
-      own[a] = src[a * nv + nB + row];
-      if (MODE == kModePCG) ownw[a] = wv[a * nv + nB + row];
+      own[a] = src[a * nv + nB + my];
+      if (MODE == kModePCG) ownw[a] = wv[a * nv + nB + my];
     }
+  }
+  {
+    const int rj = row0 + lane / kMaxCoup;
+    if (lane < RW * kMaxCoup && rj < Sv.nT) cd = Sv.cpl[rj * kMaxCoup + lane % kMaxCoup];
   }
   __shared__ int stop;
   __shared__ double alpha_s;
@@ -840,54 +849,79 @@ __device__ __forceinline__ void b_Eb(VertArgs Vx, SolveArgs Sv, StepState St, Ad
   __syncthreads();
   if (stop || !have) return;
   const double alpha = (MODE == kModePCG) ? alpha_s : 0.0;
-  // the couplings' first entries and subdomain rows, wave-uniform
-  int B[kMaxCoup], P[kMaxCoup];
+  // each row's couplings (first entry, row of its part) and length, wave-uniform
+  int B[RW][kMaxCoup], P[RW][kMaxCoup], len[RW], ncp[RW];
+  long long eoff[RW];
 #pragma unroll
-  for (int c = 0; c < kMaxCoup; ++c) {
-    B[c] = wave_uniform(__shfl(cd.b0, c, 64));
-    P[c] = wave_uniform(__shfl(cd.pre, c, 64));
+  for (int j = 0; j < RW; ++j) {
+#pragma unroll
+    for (int c = 0; c < kMaxCoup; ++c) {
+      B[j][c] = wave_uniform(__shfl(cd.b0, j * kMaxCoup + c, 64));
+      P[j][c] = wave_uniform(__shfl(cd.pre, j * kMaxCoup + c, 64));
+    }
+    len[j] = wave_uniform(__shfl(er.len, j, 64));  // 0 past nT
+    ncp[j] = wave_uniform(__shfl(er.n, j, 64));
+    eoff[j] = wave_uniform(__shfl(er.off, j, 64));
   }
-  const int len = wave_uniform(er.len), ncp = wave_uniform(er.n);
-  const double* __restrict__ Er = Sv.E + wave_uniform(er.off);
-  double a0 = 0, a1 = 0, a2 = 0;
-  // entries past the end repeat the last one with weight zero
+  int lmax = 0;
+#pragma unroll
+  for (int j = 0; j < RW; ++j) lmax = max(lmax, len[j]);
+  double acc[RW][3];
+#pragma unroll
+  for (int j = 0; j < RW; ++j) acc[j][0] = acc[j][1] = acc[j][2] = 0.0;
+  // entries past the end repeat the last one with weight zero; every trip
+  // requests the chunk of all the wave's rows before it adds any
   constexpr int kSpan = 64 * kEbChunk;
-  for (int base = 0; base < len; base += kSpan) {
-    // all loads of the chunk first ...
-    double cf[kEbChunk], y[kEbChunk][3], w[kEbChunk][3];
+  for (int base = 0; base < lmax; base += kSpan) {
+    double cf[RW][kEbChunk], y[RW][kEbChunk][3], w[RW][kEbChunk][3];
 #pragma unroll
-    for (int j = 0; j < kEbChunk; ++j) {
-      const int idx = min(base + lane + 64 * j, len - 1);
-      int col = B[0] + idx;
+    for (int j = 0; j < RW; ++j) {
+      if (base >= len[j]) continue;
+      const double* __restrict__ Er = Sv.E + eoff[j];
 #pragma unroll
-      for (int c = 1; c < kMaxCoup; ++c)
-        if (c < ncp && idx >= P[c]) col = B[c] + idx - P[c];
-      const unsigned oc = 8u * (unsigned)col;
-      cf[j] = at_byte(Er, 8u * (unsigned)idx);
+      for (int i = 0; i < kEbChunk; ++i) {
+        const int idx = min(base + lane + 64 * i, len[j] - 1);
+        int col = B[j][0] + idx;
 #pragma unroll
-      for (int a = 0; a < 3; ++a) {
-        y[j][a] = at_byte(src + a * nv, oc);
-        if (MODE == kModePCG) w[j][a] = at_byte(wv + a * nv, oc);
+        for (int c = 1; c < kMaxCoup; ++c)
+          if (c < ncp[j] && idx >= P[j][c]) col = B[j][c] + idx - P[j][c];
+        const unsigned oc = 8u * (unsigned)col;
+        cf[j][i] = at_byte(Er, 8u * (unsigned)idx);
+#pragma unroll
+        for (int a = 0; a < 3; ++a) {
+          y[j][i][a] = at_byte(src + a * nv, oc);
+          if (MODE == kModePCG) w[j][i][a] = at_byte(wv + a * nv, oc);
+        }
       }
     }
-    // ... then the arithmetic
 #pragma unroll
-    for (int j = 0; j < kEbChunk; ++j) {
-      const double c = (base + lane + 64 * j < len) ? cf[j] : 0.0;
-      a0 += c * (MODE == kModePCG ? y[j][0] - alpha * w[j][0] : y[j][0]);
-      a1 += c * (MODE == kModePCG ? y[j][1] - alpha * w[j][1] : y[j][1]);
-      a2 += c * (MODE == kModePCG ? y[j][2] - alpha * w[j][2] : y[j][2]);
+    for (int j = 0; j < RW; ++j) {
+      if (base >= len[j]) continue;
+#pragma unroll
+      for (int i = 0; i < kEbChunk; ++i) {
+        const double c = (base + lane + 64 * i < len[j]) ? cf[j][i] : 0.0;
+        acc[j][0] += c * (MODE == kModePCG ? y[j][i][0] - alpha * w[j][i][0] : y[j][i][0]);
+        acc[j][1] += c * (MODE == kModePCG ? y[j][i][1] - alpha * w[j][i][1] : y[j][i][1]);
+        acc[j][2] += c * (MODE == kModePCG ? y[j][i][2] - alpha * w[j][i][2] : y[j][i][2]);
+      }
     }
   }
-  a0 = wave_sum(a0);
-  a1 = wave_sum(a1);
-  a2 = wave_sum(a2);
-  if (lane == 0) {
+  double xr[3] = {0.0, 0.0, 0.0};
+#pragma unroll
+  for (int j = 0; j < RW; ++j) {
+    const double s0 = wave_sum(acc[j][0]), s1 = wave_sum(acc[j][1]), s2 = wave_sum(acc[j][2]);
+    if (lane == j) {
+      xr[0] = s0;
+      xr[1] = s1;
+      xr[2] = s2;
+    }
+  }
+  if (mine) {
 #pragma unroll
     for (int a = 0; a < 3; ++a) own[a] -= alpha * ownw[a];
-    Sv.rT[row] = own[0] - a0;
-    Sv.rT[Sv.nT + row] = own[1] - a1;
-    Sv.rT[2 * Sv.nT + row] = own[2] - a2;
+    Sv.rT[my] = own[0] - xr[0];
+    Sv.rT[Sv.nT + my] = own[1] - xr[1];
+    Sv.rT[2 * Sv.nT + my] = own[2] - xr[2];
   }
 }
 
@@ -2212,6 +2246,7 @@ bool launch_events_used() {
 }
 
 int vert_group_blocks(int n) { return (8 * n + kBlock - 1) / kBlock; }
+int eb_blocks(int nT) { return std::max(1, (nT + kEbRows - 1) / kEbRows); }
 int bottom_blocks(int nB, int nT) {
   return (nB + kBottomRows - 1) / kBottomRows + (nT + kBottomThreads - 1) / kBottomThreads;
 }
@@ -2278,7 +2313,7 @@ void launch_gather_debug(const VertArgs& V, const double* contrib, double* out, 
 void launch_Eb(int mode, const VertArgs& V, const SolveArgs& S, const StepState& St, const AdjState& A,
                const RedArgs& R, const double* rhs, int k, hipStream_t s) {
   // the forward mode (gate decision) and the PCG mode (alpha) always run, with at least one block
-  const int nblk = std::max(1, (S.nT + 3) / 4);
+  const int nblk = eb_blocks(S.nT);
   if (mode == kModeFwd)
     launch_ext(k_Eb<kModeFwd>, dim3(nblk), dim3(kBlock), 0, s, V, S, St, A, R, rhs, k);
   else if (mode == kModePCG)

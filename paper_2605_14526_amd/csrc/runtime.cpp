@@ -1990,7 +1990,7 @@ void batch_layout(pd_batch& B) {
         case kBKLocal: n = (S.ne + B.block_local - 1) / B.block_local; break;
         case kBKApplyK: n = (S.ne + B.block_applyK - 1) / B.block_applyK; break;
         case kBKGather: n = vert_group_blocks(S.L.nf); break;
-        case kBKEb: n = std::max(1, (S.L.nT + 3) / 4); break;
+        case kBKEb: n = eb_blocks(S.L.nT); break;
         case kBKTop: n = (S.L.nT + 3) / 4; break;
         default: n = bottom_blocks(S.L.nB, S.L.nT); break;
       }

@@ -357,12 +357,13 @@ def drop_blob(res: int = 8, seed: int = 3001, n_spheres: int = 6, r_lo: float = 
                  obstacles=obs, v_init=np.array([lateral[0], lateral[1], -drop_speed]), friction=friction)
 
 
-def drop_family(k: int, res: int = 27, steps: int = 100) -> Scene:
+def drop_family(k: int, res: int = 27, steps: int = 100, friction: float = 0.0) -> Scene:
     """Member k of a family of drops of one blob (the contact benchmark's mesh and material): the initial velocity
     is drawn from seed 3100 + k (downward speed uniform in [0.5, 1.5] m/s, horizontal components uniform in
-    [-0.5, 0.5] m/s), and so is the target centroid.  Members with different k share the mesh, so one warm-start
-    network serves all of them; the benchmark's drop (1 m/s straight down) is not a member."""
-    sc = drop_blob(res=res, steps=steps)
+    [-0.5, 0.5] m/s), and so is the target centroid; ``friction`` is the obstacles' Coulomb coefficient.  Members
+    with different k share the mesh, so one warm-start network serves all of them; the benchmark's drop (1 m/s
+    down, (0.3, 0.1) m/s sideways) is not a member."""
+    sc = drop_blob(res=res, steps=steps, friction=friction)
     rng = _rng(3100 + k)
     vz = rng.uniform(0.5, 1.5)
     vx, vy = rng.uniform(-0.5, 0.5, 2)

@@ -50,6 +50,8 @@ def parse():
     ap.add_argument("--cpu-sample-steps", type=int, default=20)
     ap.add_argument("--timed-kernel", default="solve", choices=sorted(KERNELS))
     ap.add_argument("--max-sub", type=int, default=0)
+    ap.add_argument("--iface-levels", type=int, default=0,
+                    help="separator-tree levels of the interface solve (0: library default)")
     ap.add_argument("--no-warm-run", action="store_true", help="skip the warm-started measurements")
     ap.add_argument("--train-scenes", type=int, default=4, help="beams the warm-start network is trained on")
     ap.add_argument("--train-epochs", type=int, default=32)
@@ -229,7 +231,8 @@ def bench_batch(args, torch):
     horizon = max(K, args.warmup, 2)
     scs = scenes.sysid_batch(n=args.batch_scenes, steps=50)
     t0 = time.perf_counter()
-    gs = [Scene.from_scene(sc, eps_adj=ADJ_TOL, adj_warm=3) for sc in scs]
+    gs = [Scene.from_scene(sc, eps_adj=ADJ_TOL, adj_warm=3, max_sub=args.max_sub, iface_levels=args.iface_levels)
+          for sc in scs]
     t_setup = time.perf_counter() - t0
     dev = lambda a: torch.tensor(np.ascontiguousarray(a), dtype=torch.float64, device="cuda")  # noqa: E731
     forces = [[dev(sc.f_ext(t)) for sc in scs] for t in range(horizon)]
@@ -442,7 +445,7 @@ def main():
           if drop else scenes.config(args.config))
     dev = lambda a: torch.tensor(np.ascontiguousarray(a), dtype=torch.float64, device="cuda")  # noqa: E731
     # adjoint: start extrapolated (quadratically) from the sweep's previous solutions (runs to ADJ_TOL either way)
-    g = Scene.from_scene(sc, eps_adj=ADJ_TOL, max_sub=args.max_sub, adj_warm=3)
+    g = Scene.from_scene(sc, eps_adj=ADJ_TOL, max_sub=args.max_sub, adj_warm=3, iface_levels=args.iface_levels)
     info = g.info()
     print(f"[bench] scene {sc.name}: {info}", file=sys.stderr, flush=True)
     # warmup (untimed)
@@ -497,7 +500,8 @@ def main():
     if not args.no_warm_run:
         out["warm_started"] = {}
         # the same rollout with the inertial first iterate q0 = q_t + h v_t
-        gw = Scene.from_scene(sc, eps_adj=ADJ_TOL, max_sub=args.max_sub, adj_warm=3, fwd_start=1)
+        gw = Scene.from_scene(sc, eps_adj=ADJ_TOL, max_sub=args.max_sub, adj_warm=3, fwd_start=1,
+                              iface_levels=args.iface_levels)
         if args.warmup > 0:
             rollout_fwd_bwd(gw, sc, args.warmup, torch, dev)
         dtw, fw, bw, _ = rollout_fwd_bwd(gw, sc, args.steps, torch, dev)

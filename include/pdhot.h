@@ -91,8 +91,16 @@ typedef struct pd_material_desc {
  * eps_tr: trust-region tolerance of Eq. tr_rule (0.1 in the paper).
  * adj_method: 0 = conjugate gradients preconditioned by the PD factor,
  *             1 = the fixed-point iteration mu <- A^-1 (qbar + K mu).
- * max_sub: largest subdomain (vertices) of the two-level partitioned inverse
- *          (0 = library default).
+ * max_sub: largest subdomain (vertices) of the partitioned inverse
+ *          (0 = library default).  The subdomains are the leaves of a nested
+ *          dissection (Sec. 4.6's ordering); the separators above them form the
+ *          interface.
+ * iface_levels: levels of the separator tree that the interface solve keeps
+ *          apart (1..8, 0 = library default 4): the separators at these levels
+ *          are eliminated block by block (a dense frontal block per separator,
+ *          two launches per extra level), the ones above merge into one dense
+ *          top block; 1 is one dense inverse of the whole interface Schur
+ *          complement.
  * iters_per_check: PD iterations issued between convergence checks of the
  *          host (0 = adaptive).
  * adj_warm: start of the adjoint iteration of pd_step_backward: 0 = zero
@@ -105,7 +113,8 @@ typedef struct pd_material_desc {
  *          The solve still runs to eps_adj, so only the iteration count
  *          depends on the start.
  * fwd_start: first PD iterate when pd_step_forward gets no q0: 0 = q_t (as in
- *          Alg. 1), 1 = the inertial guess q_t + h v_t. */
+ *          Alg. 1), 1 = the inertial guess q_t + h v_t.
+ * Errors: PD_ERR_INVALID_ARG for an iface_levels outside 0..8. */
 typedef struct pd_solver_opts {
   double h;
   double gravity[3];
@@ -121,6 +130,7 @@ typedef struct pd_solver_opts {
   int32_t iters_per_check;
   int32_t adj_warm;
   int32_t fwd_start;
+  int32_t iface_levels;
 } pd_solver_opts;
 
 /* Forward statistics. gate[0..3] = |q^k - q^{k-1}|, |q^{k-1}|, |b^k - b^{k-1}|,

@@ -50,7 +50,7 @@ class pd_solver_opts(ctypes.Structure):
                 ("eps_rel", ctypes.c_double), ("eps_abs", ctypes.c_double), ("kmax_fwd", ctypes.c_int32),
                 ("kmax_bwd", ctypes.c_int32), ("eps_adj", ctypes.c_double), ("eps_tr", ctypes.c_double),
                 ("adj_method", ctypes.c_int32), ("max_sub", ctypes.c_int32), ("iters_per_check", ctypes.c_int32),
-                ("adj_warm", ctypes.c_int32), ("fwd_start", ctypes.c_int32)]
+                ("adj_warm", ctypes.c_int32), ("fwd_start", ctypes.c_int32), ("iface_levels", ctypes.c_int32)]
 
 
 class pd_mpn_desc(ctypes.Structure):
@@ -159,7 +159,7 @@ class Scene:
 
     def __init__(self, X, tets, pinned, log_E, nu, rho, alpha, beta0, h, gravity=(0.0, 0.0, 0.0), aa_window=1,
                  eps_rel=1e-6, eps_abs=1e-12, kmax_fwd=1000, kmax_bwd=1000, eps_adj=1e-6, eps_tr=0.1,
-                 adj_method=0, max_sub=0, iters_per_check=0, adj_warm=0, fwd_start=0, energy=0):
+                 adj_method=0, max_sub=0, iters_per_check=0, adj_warm=0, fwd_start=0, energy=0, iface_levels=0):
         L = lib()
         self._X = np.ascontiguousarray(X, dtype=np.float64)
         self._tets = np.ascontiguousarray(tets, dtype=np.int32)
@@ -171,7 +171,8 @@ class Scene:
                             self._pinned.ctypes.data)
         mat = pd_material_desc(self._logE.ctypes.data, nu, rho, alpha, beta0, int(energy))
         opts = pd_solver_opts(h, (ctypes.c_double * 3)(*gravity), aa_window, eps_rel, eps_abs, kmax_fwd, kmax_bwd,
-                              eps_adj, eps_tr, adj_method, max_sub, iters_per_check, adj_warm, fwd_start)
+                              eps_adj, eps_tr, adj_method, max_sub, iters_per_check, adj_warm, fwd_start,
+                              iface_levels)
         self.h = float(h)
         ptr = ctypes.c_void_p()
         check(L.pd_scene_create(ctypes.byref(mesh), ctypes.byref(mat), ctypes.byref(opts), ctypes.byref(ptr)),

@@ -73,7 +73,28 @@ constexpr int kBottomChunkE = PD_BOTTOM_CHUNK_E;  // subdomain solve, E_s^T rows
 constexpr int kEbChunk = PD_EB_CHUNK;          // interface right-hand side (E_s rows)
 constexpr int kEbRowsPerWave = PD_EB_RPW;       // interface rows walked together by one wave
 constexpr int kEbRows = (kBlock / 64) * kEbRowsPerWave;  // interface rows per block of that kernel
-constexpr int kTopChunk = PD_TOP_CHUNK;        // interface solve (Z rows)
+constexpr int kTopChunk = PD_TOP_CHUNK;        // interface solve, rows of wide separator blocks
+// Interface solve over the separator tree: a backward block takes kSepRows
+// rows of one node (kSepRowsPerWave per wave, chunks of 64 x kSepChunk), or
+// for a wide node (s + b >= kSepWide) 4 rows, one per wave, in chunks of
+// 64 x kTopChunk; the node's [y_n ; x_struct] is staged in LDS kSepTile
+// entries at a time.  A forward row takes chunks of 64 x kSepFwdChunk.
+#ifndef PD_SEP_RPW
+#define PD_SEP_RPW 4
+#endif
+#ifndef PD_SEP_CHUNK
+#define PD_SEP_CHUNK 2
+#endif
+#ifndef PD_SEP_FWD_CHUNK
+#define PD_SEP_FWD_CHUNK 4
+#endif
+constexpr int kSepRowsPerWave = PD_SEP_RPW;
+constexpr int kSepRows = (kBlock / 64) * kSepRowsPerWave;
+constexpr int kSepChunk = PD_SEP_CHUNK;
+constexpr int kSepFwdChunk = PD_SEP_FWD_CHUNK;
+constexpr int kSepWide = 1536;
+constexpr int kSepTile = 2048;
+constexpr int kSepMaxSeg = 56;  // separator nodes whose struct may hold one interface row
 // LDS buffers of the subdomain solve: right-hand-side rows and interface
 // copies a block stages for its rows (three axes each)
 constexpr int kStageZ = 768;
@@ -136,14 +157,24 @@ struct SolveArgs {
   const int* rl_ptr;        // nT + 1: couplings of each interface row
   const int* rl_sub;        // subdomain of each coupling
   const int* rl_p;          // row of E_s of each coupling
-  const double* Z;          // nT x nT
-  double* rT;               // 3 x nT interface right-hand side
+  int nlev;                 // separator-tree levels of the interface solve
+  const int* lev_row;       // nlev + 1
+  const int* lev_blk;       // nlev + 1
+  const SepNode* sep;
+  const SepBlk* sblk;
+  const double* ZE;
+  const FRow* frow;
+  const SSeg* sseg;
+  const double* FE;
+  double* rT;               // 3 x nT interface right-hand side (the forward solve's y in place)
+  int lev_nrows[kMaxLevels];  // host copies for the launchers: rows and backward blocks per level
+  int lev_nblk[kMaxLevels];
   const Cpl* cpl;           // nT x kMaxCoup coupling descriptors
   const ERow* erow;         // nT: the row's couplings in E (row-concatenated)
   const BRow* brow;         // nB subdomain-row descriptors
   const BOff* boff;
   const BStage* bstage;     // per subdomain-solve block: the ranges it stages in LDS
-  double* xsT;              // 3 x n_irows interface solution gathered per subdomain
+  double* xsT;              // 3 x n_irows interface solution gathered per subdomain and separator node
   int n_irows;
 };
 
@@ -242,12 +273,18 @@ struct BatchMap {
   int ns;
 };
 
-enum { kBKLocal = 0, kBKGather = 1, kBKEb = 2, kBKTop = 3, kBKBottom = 4, kBKApplyK = 5, kBKKinds = 6 };
+// block-map kinds of a batch: the stages, then the forward (kBKSepF + l - 1)
+// and backward (kBKSepB + l - 1) launches of interface-solve level l
+enum { kBKLocal = 0, kBKGather = 1, kBKEb = 2, kBKBottom = 3, kBKApplyK = 4, kBKSepF = 5, kBKSepB = kBKSepF + kMaxLevels,
+       kBKKinds = kBKSepB + kMaxLevels };
 
 void launch_b_local(const BatchMap& M, int nblk, int block, int k, hipStream_t s);
 void launch_b_gather_fwd(const BatchMap& M, int nblk, int k, hipStream_t s);
 void launch_b_Eb(int mode, const BatchMap& M, int nblk, int k, hipStream_t s);
-void launch_b_top(const BatchMap& M, int nblk, int adjoint, hipStream_t s);
+// the interface solve over the separator tree: per level l (1..nlev) the
+// maps and block counts of its forward (l >= 2) and backward launches
+void launch_b_sep(const BatchMap* Mf, const int* nblk_f, const BatchMap* Mb, const int* nblk_b, int nlev,
+                  int adjoint, hipStream_t s);
 void launch_b_bottom(int mode, const BatchMap& M, int nblk, int k, hipStream_t s);
 void launch_b_apply_K(int mode, const BatchMap& M, int nblk, int block, int it, hipStream_t s);
 void launch_b_adj_gather(int mode, const BatchMap& M, int nblk, int it, hipStream_t s);

@@ -932,97 +932,197 @@ __global__ void __launch_bounds__(kBlock) PD_ROW_WALK_EB k_Eb(VertArgs Vx, Solve
 }
 
 // ---------------------------------------------------------------- interface solve
-// x_T = Z r_T, one wave per interface row (Z = inverse Schur complement); the
-// value is also stored at the row's position in the per-subdomain interface
-// vectors read by the subdomain solve.  With a done flag (nullable) a launch
-// after the loop has stopped exits once the flag, read with the first tile of
-// r_T, is seen: its only consumer, the subdomain solve, exits too.
-__device__ __forceinline__ void b_top(VertArgs Vx, SolveArgs Sv, double* __restrict__ out, int bid,
-                                      const int* __restrict__ done) {
-  // r_T is read by every row: the block stages it in LDS tile by tile, so it
-  // crosses L2 once per block instead of once per row
-  constexpr int kTile = 2048;
-  __shared__ double rs[3 * kTile];
-  const int lane = threadIdx.x & 63;
-  const int row = (bid * blockDim.x + threadIdx.x) >> 6;
-  const int nT = Sv.nT;
-  const bool have = row < nT;
-  ERow er = {0, 0, 0};
-  Cpl cd = {0, 0, 0, 0};
-  if (have) {
-    er = Sv.erow[row];
-    if (lane < kMaxCoup) cd = Sv.cpl[row * kMaxCoup + lane];
-  }
-  const double* __restrict__ Zi = Sv.Z + (size_t)(have ? row : 0) * nT;
+// S x_T = r_T over the separator tree, r_T already reduced by the subdomains
+// (the interface right-hand side kernel).  Forward, level by level upward: a
+// row of level l becomes y_i = r_i - sum_c E_c[m, :] y_c over the separator
+// nodes c below it whose struct holds it (level 1 rows have none), in place in
+// r_T.  Backward, level by level downward: the rows of node n become
+// x = Z_n y_n - E_n^T x_struct(n), stored as the solution and copied to the
+// slots of the subdomains and nodes that read them.  With a done flag
+// (nullable) a launch after the loop has stopped exits at once.
+__device__ __forceinline__ void b_sep_fwd(SolveArgs Sv, int lvl, int bid, const int* __restrict__ done) {
   __shared__ int stop_s;
   if (threadIdx.x == 0) stop_s = done ? *done : 0;
+  __syncthreads();
+  if (stop_s) return;
+  const int lane = threadIdx.x & 63;
+  const int r = Sv.lev_row[lvl - 1] + ((bid * (int)blockDim.x + (int)threadIdx.x) >> 6);
+  if (r >= Sv.lev_row[lvl]) return;
+  const int nT = Sv.nT;
+  const FRow fr = Sv.frow[r];
+  const int nseg = wave_uniform(fr.nseg);
+  const double* __restrict__ Er = Sv.FE + wave_uniform(fr.off);
+  // lane g < nseg holds segment g: where it starts in the concatenated row and
+  // the shift from a row entry to its source row of y (lanes past the last
+  // segment start at INT_MAX and are never chosen)
+  int len = 0, shift = 0;
+  if (lane < nseg) {
+    const SSeg sg = Sv.sseg[fr.seg0 + lane];
+    len = sg.len;
+    shift = sg.src;
+  }
+  int end = len;  // inclusive prefix sum of the lengths
+#pragma unroll
+  for (int d = 1; d < 64; d <<= 1) {
+    const int v = __shfl_up(end, d, 64);
+    if (lane >= d) end += v;
+  }
+  const int total = wave_uniform(__shfl(end, 63, 64));
+  const int beg = lane < nseg ? end - len : 0x7fffffff;
+  shift -= end - len;
   double a0 = 0, a1 = 0, a2 = 0;
-  for (int t0 = 0; t0 < nT; t0 += kTile) {
-    const int tl = min(kTile, nT - t0);
-    __syncthreads();
-    for (int i = threadIdx.x; i < tl; i += blockDim.x) {
-      rs[i] = Sv.rT[t0 + i];
-      rs[kTile + i] = Sv.rT[nT + t0 + i];
-      rs[2 * kTile + i] = Sv.rT[2 * nT + t0 + i];
+  constexpr int C = kSepFwdChunk;
+  for (int base = 0; base < total; base += 64 * C) {
+    double e[C], y[C][3];
+    int q[C];
+#pragma unroll
+    for (int i = 0; i < C; ++i) {
+      const int k = min(base + lane + 64 * i, total - 1);
+      int g = 0;  // the last segment starting at or before k
+#pragma unroll
+      for (int st = 32; st >= 1; st >>= 1) {
+        const int b = __shfl(beg, g + st, 64);
+        if (b <= k) g += st;
+      }
+      q[i] = __shfl(shift, g, 64) + k;
+      e[i] = Er[k];
     }
-    __syncthreads();
-    if (stop_s) return;
-    if (have) {
-      // whole chunks, then the last partial one (its entries past the end
-      // repeat the last entry with weight zero)
-      constexpr int kSpan = 64 * kTopChunk;
-      int base = 0;
-      for (; base + kSpan <= tl; base += kSpan) {
-        double zc[kTopChunk];
 #pragma unroll
-        for (int j = 0; j < kTopChunk; ++j) zc[j] = Zi[t0 + base + lane + 64 * j];
+    for (int i = 0; i < C; ++i)
 #pragma unroll
-        for (int j = 0; j < kTopChunk; ++j) {
-          const int jj = base + lane + 64 * j;
-          a0 += zc[j] * rs[jj];
-          a1 += zc[j] * rs[kTile + jj];
-          a2 += zc[j] * rs[2 * kTile + jj];
-        }
-      }
-      if (base < tl) {
-        double zc[kTopChunk];
+      for (int a = 0; a < 3; ++a) y[i][a] = Sv.rT[a * nT + q[i]];
 #pragma unroll
-        for (int j = 0; j < kTopChunk; ++j) {
-          const int jj = base + lane + 64 * j;
-          const double z = Zi[t0 + min(jj, tl - 1)];
-          zc[j] = (jj < tl) ? z : 0.0;
-        }
-#pragma unroll
-        for (int j = 0; j < kTopChunk; ++j) {
-          const int jj = min(base + lane + 64 * j, tl - 1);
-          a0 += zc[j] * rs[jj];
-          a1 += zc[j] * rs[kTile + jj];
-          a2 += zc[j] * rs[2 * kTile + jj];
-        }
-      }
+    for (int i = 0; i < C; ++i) {
+      const double c = (base + lane + 64 * i < total) ? e[i] : 0.0;
+      a0 += c * y[i][0];
+      a1 += c * y[i][1];
+      a2 += c * y[i][2];
     }
   }
-  if (!have) return;
   a0 = wave_sum(a0);
   a1 = wave_sum(a1);
   a2 = wave_sum(a2);
   if (lane == 0) {
-    const int gi = Sv.nB + row, nv = Vx.nv;
-    out[gi] = a0;
-    out[nv + gi] = a1;
-    out[2 * nv + gi] = a2;
-  }
-  if (lane < er.n) {
-    const int ni = Sv.n_irows;
-    Sv.xsT[cd.pos] = a0;
-    Sv.xsT[ni + cd.pos] = a1;
-    Sv.xsT[2 * ni + cd.pos] = a2;
+    Sv.rT[r] -= a0;
+    Sv.rT[nT + r] -= a1;
+    Sv.rT[2 * nT + r] -= a2;
   }
 }
 
-__global__ void __launch_bounds__(kBlock) k_top(VertArgs Vx, SolveArgs Sv, double* __restrict__ out,
-                                                const int* __restrict__ done) {
-  b_top(Vx, Sv, out, blockIdx.x, done);
+__device__ __forceinline__ void b_sep_back(VertArgs Vx, SolveArgs Sv, int lvl, double* __restrict__ out, int bid,
+                                           const int* __restrict__ done) {
+  __shared__ double ys[3 * kSepTile];
+  __shared__ int stop_s;
+  constexpr int RW = kSepRowsPerWave;
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const SepBlk bk = Sv.sblk[Sv.lev_blk[lvl - 1] + bid];
+  const SepNode nd = Sv.sep[bk.node];
+  const int s = nd.s, L = nd.s + nd.b, nT = Sv.nT, ni = Sv.n_irows, nv = Vx.nv;
+  const bool wide = bk.pad != 0;  // block-uniform
+  // this wave's rows: RW consecutive rows in a narrow block, one in a wide one
+  const int rw0 = wide ? bk.row0 + wave : bk.row0 + wave * RW;
+  const int nrw = wide ? (wave < bk.nrows ? 1 : 0) : max(0, min(RW, bk.nrows - wave * RW));
+  if (threadIdx.x == 0) stop_s = done ? *done : 0;
+  // copy slots of the wave's rows, requested before the walk: lanes 0..7 the
+  // row's subdomain couplings, lanes 8.. its separator segments (-1: none)
+  int slot[RW];
+#pragma unroll
+  for (int j = 0; j < RW; ++j) {
+    slot[j] = -1;
+    if (j < nrw) {
+      const int rj = rw0 + j;
+      const int nc = Sv.erow[rj].n;
+      const FRow fr = Sv.frow[rj];
+      if (lane < kMaxCoup) {
+        if (lane < nc) slot[j] = Sv.cpl[rj * kMaxCoup + lane].pos;
+      } else if (lane - kMaxCoup < fr.nseg) {
+        slot[j] = Sv.sseg[fr.seg0 + lane - kMaxCoup].slot;
+      }
+    }
+  }
+  const double* __restrict__ Zb = Sv.ZE + nd.zoff + (long long)(rw0 - nd.r0) * L;
+  double acc[RW][3];
+#pragma unroll
+  for (int j = 0; j < RW; ++j) acc[j][0] = acc[j][1] = acc[j][2] = 0.0;
+  for (int t0 = 0; t0 < L; t0 += kSepTile) {
+    const int tl = min(kSepTile, L - t0);
+    __syncthreads();
+    for (int i = threadIdx.x; i < tl; i += blockDim.x) {
+      const int k = t0 + i;
+#pragma unroll
+      for (int a = 0; a < 3; ++a)
+        ys[a * kSepTile + i] = k < s ? Sv.rT[a * nT + nd.r0 + k] : Sv.xsT[a * ni + nd.xs0 + (k - s)];
+    }
+    __syncthreads();
+    if (stop_s) return;
+    if (wide) {
+      if (nrw > 0) {
+        constexpr int C = kTopChunk;
+        for (int base = 0; base < tl; base += 64 * C) {
+          double z[C];
+#pragma unroll
+          for (int i = 0; i < C; ++i) z[i] = Zb[t0 + min(base + lane + 64 * i, tl - 1)];
+#pragma unroll
+          for (int i = 0; i < C; ++i) {
+            const int u = base + lane + 64 * i;
+            const double c = u < tl ? z[i] : 0.0;
+            const int q = min(u, tl - 1);
+            acc[0][0] += c * ys[q];
+            acc[0][1] += c * ys[kSepTile + q];
+            acc[0][2] += c * ys[2 * kSepTile + q];
+          }
+        }
+      }
+    } else {
+      // every trip requests the chunk of all the wave's rows before it adds any
+      constexpr int C = kSepChunk;
+      for (int base = 0; base < tl; base += 64 * C) {
+        double z[RW][C];
+#pragma unroll
+        for (int j = 0; j < RW; ++j)
+          if (j < nrw)
+#pragma unroll
+            for (int i = 0; i < C; ++i) z[j][i] = Zb[(long long)j * L + t0 + min(base + lane + 64 * i, tl - 1)];
+#pragma unroll
+        for (int j = 0; j < RW; ++j)
+          if (j < nrw)
+#pragma unroll
+            for (int i = 0; i < C; ++i) {
+              const int u = base + lane + 64 * i;
+              const double c = u < tl ? z[j][i] : 0.0;
+              const int q = min(u, tl - 1);
+              acc[j][0] += c * ys[q];
+              acc[j][1] += c * ys[kSepTile + q];
+              acc[j][2] += c * ys[2 * kSepTile + q];
+            }
+      }
+    }
+  }
+#pragma unroll
+  for (int j = 0; j < RW; ++j) {
+    if (j >= nrw) break;
+    const double x0 = wave_sum(acc[j][0]), x1 = wave_sum(acc[j][1]), x2 = wave_sum(acc[j][2]);
+    const int gi = Sv.nB + rw0 + j;
+    if (lane == 0) {
+      out[gi] = x0;
+      out[nv + gi] = x1;
+      out[2 * nv + gi] = x2;
+    }
+    if (slot[j] >= 0) {
+      Sv.xsT[slot[j]] = x0;
+      Sv.xsT[ni + slot[j]] = x1;
+      Sv.xsT[2 * ni + slot[j]] = x2;
+    }
+  }
+}
+
+__global__ void __launch_bounds__(kBlock) k_sep_fwd(SolveArgs Sv, int lvl, const int* __restrict__ done) {
+  b_sep_fwd(Sv, lvl, blockIdx.x, done);
+}
+
+__global__ void __launch_bounds__(kBlock) k_sep_back(VertArgs Vx, SolveArgs Sv, int lvl, double* __restrict__ out,
+                                                     const int* __restrict__ done) {
+  b_sep_back(Vx, Sv, lvl, out, blockIdx.x, done);
 }
 
 // Anderson append of one forward iteration for the free row my_row (-1: no
@@ -2164,9 +2264,14 @@ __global__ void __launch_bounds__(kBlock) PD_ROW_WALK_EB kb_Eb(BatchMap M, int k
 }
 
 // A block of a scene whose loop has stopped exits on that scene's flag.
-__global__ void __launch_bounds__(kBlock) kb_top(BatchMap M, int adjoint) {
+__global__ void __launch_bounds__(kBlock) kb_sep_fwd(BatchMap M, int lvl, int adjoint) {
   PD_BATCH_PROLOGUE
-  b_top(b.V, b.S, adjoint ? b.A.z : b.St.qhat, bid, adjoint ? b.A.done : b.St.done);
+  b_sep_fwd(b.S, lvl, bid, adjoint ? b.A.done : b.St.done);
+}
+
+__global__ void __launch_bounds__(kBlock) kb_sep_back(BatchMap M, int lvl, int adjoint) {
+  PD_BATCH_PROLOGUE
+  b_sep_back(b.V, b.S, lvl, adjoint ? b.A.z : b.St.qhat, bid, adjoint ? b.A.done : b.St.done);
 }
 
 template <int MODE>
@@ -2321,9 +2426,23 @@ void launch_Eb(int mode, const VertArgs& V, const SolveArgs& S, const StepState&
   else if (S.nT > 0)
     launch_ext(k_Eb<kModePlain>, dim3(nblk), dim3(kBlock), 0, s, V, S, St, A, R, rhs, k);
 }
+// The interface solve is 2 nlev - 1 launches (forward levels 2..nlev, then
+// backward levels nlev..1); armed launch events time it from the first
+// launch's start to the last one's end.
 void launch_top(const VertArgs& V, const SolveArgs& S, double* out, const int* done, hipStream_t s) {
-  if (S.nT == 0) return;
-  launch_ext(k_top, dim3((S.nT + 3) / 4), dim3(kBlock), 0, s, V, S, out, done);
+  hipEvent_t e0 = g_ev_start, e1 = g_ev_stop;
+  g_ev_start = g_ev_stop = nullptr;
+  const int nl = S.nlev;
+  if (S.nT == 0 || nl <= 0) return;
+  if (e0) g_ev_used = true;
+  const int last = 2 * nl - 2;
+  int idx = 0;
+  for (int l = 2; l <= nl; ++l, ++idx)
+    hipExtLaunchKernelGGL(k_sep_fwd, dim3((S.lev_nrows[l - 1] + kBlock / 64 - 1) / (kBlock / 64)), dim3(kBlock), 0,
+                          s, idx == 0 ? e0 : nullptr, idx == last ? e1 : nullptr, 0u, S, l, done);
+  for (int l = nl; l >= 1; --l, ++idx)
+    hipExtLaunchKernelGGL(k_sep_back, dim3(S.lev_nblk[l - 1]), dim3(kBlock), 0, s, idx == 0 ? e0 : nullptr,
+                          idx == last ? e1 : nullptr, 0u, V, S, l, out, done);
 }
 void launch_bottom(int mode, const VertArgs& V, const SolveArgs& S, const StepState& St, const AdjState& A,
                    const RedArgs& R, const double* rhs, double* out, int k, hipStream_t s) {
@@ -2409,8 +2528,26 @@ void launch_b_Eb(int mode, const BatchMap& M, int nblk, int k, hipStream_t s) {
   else if (mode == kModePCG) launch_ext(kb_Eb<kModePCG>, dim3(nblk), dim3(kBlock), 0, s, M, k);
   else launch_ext(kb_Eb<kModePlain>, dim3(nblk), dim3(kBlock), 0, s, M, k);
 }
-void launch_b_top(const BatchMap& M, int nblk, int adjoint, hipStream_t s) {
-  if (nblk > 0) launch_ext(kb_top, dim3(nblk), dim3(kBlock), 0, s, M, adjoint);
+void launch_b_sep(const BatchMap* Mf, const int* nblk_f, const BatchMap* Mb, const int* nblk_b, int nlev,
+                  int adjoint, hipStream_t s) {
+  hipEvent_t e0 = g_ev_start, e1 = g_ev_stop;
+  g_ev_start = g_ev_stop = nullptr;
+  // the non-empty launches in order: forward levels 2..nlev, backward nlev..1
+  int kind[2 * kMaxLevels], lev[2 * kMaxLevels], n = 0;
+  for (int l = 2; l <= nlev; ++l)
+    if (nblk_f[l - 1] > 0) kind[n] = 0, lev[n++] = l;
+  for (int l = nlev; l >= 1; --l)
+    if (nblk_b[l - 1] > 0) kind[n] = 1, lev[n++] = l;
+  if (n == 0) return;
+  if (e0) g_ev_used = true;
+  for (int i = 0; i < n; ++i) {
+    const int l = lev[i];
+    hipEvent_t a = i == 0 ? e0 : nullptr, b = i == n - 1 ? e1 : nullptr;
+    if (kind[i] == 0)
+      hipExtLaunchKernelGGL(kb_sep_fwd, dim3(nblk_f[l - 1]), dim3(kBlock), 0, s, a, b, 0u, Mf[l - 1], l, adjoint);
+    else
+      hipExtLaunchKernelGGL(kb_sep_back, dim3(nblk_b[l - 1]), dim3(kBlock), 0, s, a, b, 0u, Mb[l - 1], l, adjoint);
+  }
 }
 void launch_b_bottom(int mode, const BatchMap& M, int nblk, int k, hipStream_t s) {
   if (nblk <= 0) return;

@@ -47,12 +47,16 @@ struct ND {
   int max_sub;
   std::vector<int> side;  // scratch membership marks
   std::vector<std::vector<int>> subs;
-  std::vector<int> interface;
+  // separator nodes in post-order (children before their parent) and the
+  // separator nodes directly below each one
+  std::vector<std::vector<int>> seps, kids;
 
-  void run(std::vector<int> set) {
+  // Dissects `set`; returns the separator nodes at the top of its subtree
+  // (none for a subdomain, two or more where a split found no separator).
+  std::vector<int> run(std::vector<int> set) {
     if ((int)set.size() <= max_sub) {
       if (!set.empty()) subs.push_back(std::move(set));
-      return;
+      return {};
     }
     double lo[3] = {1e300, 1e300, 1e300}, hi[3] = {-1e300, -1e300, -1e300};
     for (int v : set)
@@ -83,24 +87,49 @@ struct ND {
     if (Ls.empty() && Rw.size() == set.size() - S.size() && S.size() == set.size()) {
       throw std::runtime_error("nested dissection made no progress");
     }
-    run(std::move(Ls));
-    run(std::move(Rw));
-    interface.insert(interface.end(), S.begin(), S.end());
+    std::vector<int> top = run(std::move(Ls));
+    std::vector<int> right = run(std::move(Rw));
+    top.insert(top.end(), right.begin(), right.end());
+    if (S.empty()) return top;
+    seps.push_back(std::move(S));
+    kids.push_back(std::move(top));
+    return {(int)seps.size() - 1};
   }
 };
 
 }  // namespace
 
 void build_layout(int nv, int ne, const double* X, const int32_t* tets, const uint8_t* pinned, int max_sub,
-                  Layout& L) {
+                  int levels, Layout& L) {
   L.nv = nv;
   L.ne = ne;
   Graph g = free_graph(nv, ne, tets, pinned);
   std::vector<int> free_set;
   for (int v = 0; v < nv; ++v)
     if (!pinned[v]) free_set.push_back(v);
-  ND nd{X, &g, std::max(1, max_sub), std::vector<int>(nv, 0), {}, {}};
+  ND nd{X, &g, std::max(1, max_sub), std::vector<int>(nv, 0), {}, {}, {}};
   nd.run(free_set);
+
+  // separator levels: 1 above subdomains only, else one more than the highest
+  // separator below; the nodes at level >= `levels` become one top node
+  const int no = (int)nd.seps.size();
+  const int cap = levels > 0 ? levels : (1 << 30);
+  std::vector<int> height(no, 1), oparent(no, -1);
+  for (int o = 0; o < no; ++o)
+    for (int c : nd.kids[o]) {
+      height[o] = std::max(height[o], height[c] + 1);
+      oparent[c] = o;
+    }
+  std::vector<int> order;  // unmerged nodes by (level, post-order)
+  for (int o = 0; o < no; ++o)
+    if (height[o] < cap) order.push_back(o);
+  std::stable_sort(order.begin(), order.end(), [&](int a, int b) { return height[a] < height[b]; });
+  std::vector<int> new_of(no, -1);
+  for (int k = 0; k < (int)order.size(); ++k) new_of[order[k]] = k;
+  const bool merged = (int)order.size() < no;
+  const int n_nodes = (int)order.size() + (merged ? 1 : 0);
+  for (int o = 0; o < no; ++o)
+    if (height[o] >= cap) new_of[o] = n_nodes - 1;
 
   L.lib2orig.clear();
   L.sub_begin.clear();
@@ -111,9 +140,29 @@ void build_layout(int nv, int ne, const double* X, const int32_t* tets, const ui
   L.nsub = (int)nd.subs.size();
   L.nB = (int)L.lib2orig.size();
   L.sub_begin.push_back(L.nB);
-  L.lib2orig.insert(L.lib2orig.end(), nd.interface.begin(), nd.interface.end());
+  L.sep_begin.assign(1, 0);
+  L.sep_level.clear();
+  L.sep_parent.clear();
+  for (int k = 0; k < (int)order.size(); ++k) {
+    const int o = order[k];
+    L.lib2orig.insert(L.lib2orig.end(), nd.seps[o].begin(), nd.seps[o].end());
+    L.sep_begin.push_back((int)L.lib2orig.size() - L.nB);
+    L.sep_level.push_back(height[o]);
+    L.sep_parent.push_back(oparent[o] < 0 ? -1 : new_of[oparent[o]]);
+  }
+  if (merged) {
+    for (int o = 0; o < no; ++o)
+      if (height[o] >= cap) L.lib2orig.insert(L.lib2orig.end(), nd.seps[o].begin(), nd.seps[o].end());
+    L.sep_begin.push_back((int)L.lib2orig.size() - L.nB);
+    L.sep_level.push_back(cap);
+    L.sep_parent.push_back(-1);
+  }
   L.nf = (int)L.lib2orig.size();
   L.nT = L.nf - L.nB;
+  L.nlev = n_nodes ? L.sep_level.back() : 0;
+  L.lev_begin.assign(L.nlev + 1, L.nT);
+  for (int n = n_nodes - 1; n >= 0; --n) L.lev_begin[L.sep_level[n] - 1] = L.sep_begin[n];
+  for (int l = L.nlev - 1; l >= 1; --l) L.lev_begin[l - 1] = std::min(L.lev_begin[l - 1], L.lev_begin[l]);
   for (int v = 0; v < nv; ++v)
     if (pinned[v]) L.lib2orig.push_back(v);
   L.orig2lib.assign(nv, -1);
@@ -140,6 +189,43 @@ void build_layout(int nv, int ne, const double* X, const int32_t* tets, const ui
     I.erase(std::unique(I.begin(), I.end()), I.end());
   }
 
+  // block structure of the separator tree: eliminating node n couples it to
+  // the rows of higher levels that it touches through the mesh or through a
+  // common subdomain, and to what its children's eliminations left there
+  std::vector<int> node_of(L.nT);
+  for (int n = 0; n < n_nodes; ++n)
+    for (int i = L.sep_begin[n]; i < L.sep_begin[n + 1]; ++i) node_of[i] = n;
+  std::vector<std::vector<int>> subs_of_row(L.nT);
+  for (int s = 0; s < L.nsub; ++s)
+    for (int p : L.Irows[s]) subs_of_row[p].push_back(s);
+  std::vector<std::vector<int>> children(n_nodes);
+  for (int n = 0; n < n_nodes; ++n)
+    if (L.sep_parent[n] >= 0) children[L.sep_parent[n]].push_back(n);
+  L.sep_struct.assign(n_nodes, {});
+  std::vector<int> mark(L.nT, -1);
+  for (int n = 0; n < n_nodes; ++n) {  // levels ascending: children first
+    std::vector<int>& st = L.sep_struct[n];
+    auto add = [&](int u) {
+      if (node_of[u] == n || mark[u] == n) return;
+      if (L.sep_level[node_of[u]] <= L.sep_level[n]) throw std::runtime_error("separator tree: coupled siblings");
+      mark[u] = n;
+      st.push_back(u);
+    };
+    for (int c : children[n])
+      for (int u : L.sep_struct[c]) add(u);
+    for (int i = L.sep_begin[n]; i < L.sep_begin[n + 1]; ++i) {
+      const int v = L.lib2orig[L.nB + i];
+      for (int k = g.ptr[v]; k < g.ptr[v + 1]; ++k) {
+        const int u = L.orig2lib[g.adj[k]] - L.nB;
+        if (u >= 0 && L.sep_level[node_of[u]] > L.sep_level[n]) add(u);
+      }
+      for (int s : subs_of_row[i])
+        for (int u : L.Irows[s])
+          if (L.sep_level[node_of[u]] > L.sep_level[n]) add(u);
+    }
+    std::sort(st.begin(), st.end());
+  }
+
   // tets sorted by their smallest library vertex (locality of the gathers)
   std::vector<int> key(ne);
   for (int e = 0; e < ne; ++e) {
@@ -154,7 +240,7 @@ void build_layout(int nv, int ne, const double* X, const int32_t* tets, const ui
 
 double factor_nnz_nd(int nv, int ne, const double* X, const int32_t* tets, const uint8_t* pinned) {
   Layout L;
-  build_layout(nv, ne, X, tets, pinned, 16, L);
+  build_layout(nv, ne, X, tets, pinned, 16, 0, L);
   const int n = L.nf;
   Graph g = free_graph(nv, ne, tets, pinned);
   // adjacency in elimination order, lower part only (columns j < i of row i)

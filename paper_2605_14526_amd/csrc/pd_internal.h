@@ -27,11 +27,24 @@ struct Layout {
   std::vector<int> tet_lib2orig;         // tets (sorted for locality)
   std::vector<int> sub_begin;            // nsub + 1
   std::vector<std::vector<int>> Irows;   // per subdomain: interface rows (relative, sorted)
+  // separator tree over the interface: node n owns interface rows
+  // sep_begin[n] .. sep_begin[n + 1] - 1; nodes are sorted by level (1 = only
+  // subdomains below, levels grow toward the root; the nodes at or above
+  // `levels` are merged into one top node), and every level's rows are
+  // contiguous from lev_begin[level - 1] (interface rows, nlev + 1 entries)
+  int nlev = 0;
+  std::vector<int> sep_begin, sep_level, sep_parent;
+  std::vector<int> lev_begin;
+  // per node: the interface rows of its ancestors that its elimination
+  // couples to (sorted); the tree's block structure
+  std::vector<std::vector<int>> sep_struct;
 };
 
-// nested dissection by coordinate bisection with vertex separators
+// Nested dissection by coordinate bisection with vertex separators; the
+// interface is split into separator-tree levels, at most `levels` of them
+// (1: the whole interface is one block).
 void build_layout(int nv, int ne, const double* X, const int32_t* tets, const uint8_t* pinned, int max_sub,
-                  Layout& L);
+                  int levels, Layout& L);
 
 // Entries (diagonal included) of the Cholesky factor of A~ over the free
 // vertices under a deep nested-dissection order (the same coordinate
@@ -70,12 +83,52 @@ struct alignas(16) BStage {
   int z0, zn, e0, en;
 };
 
+// The interface Schur complement S is eliminated over the separator tree.
+// Node n (interface rows r0 .. r0 + s - 1, b coupled rows of higher levels,
+// its struct) keeps, per row j, Z_n[j, :] (Z_n = F_nn^{-1} of its frontal
+// block) followed by -E_n[:, j] (E_n = F_{struct,n} Z_n), s + b entries from
+// zoff + j (s + b), applied to [y_n ; x_struct]: the backward solve of its
+// rows.  The values x_struct sit at xs0 .. xs0 + b - 1 of the gathered
+// interface vectors.
+struct alignas(16) SepNode {
+  long long zoff;
+  int r0, s, b, xs0;
+};
+// A block of the backward solve: rows row0 .. row0 + nrows - 1 of one node.
+struct alignas(16) SepBlk {
+  int node, row0, nrows, pad;
+};
+// Interface row i's part of the forward solve: for every separator node c
+// below it whose struct holds i (at position m), the row E_c[m, :] against
+// y_c (interface rows src .. src + len - 1); the rows are concatenated from
+// off in the order of the segments seg0 .. seg0 + nseg - 1.  The segment's
+// slot is where the backward solve copies x_i for node c.
+struct alignas(16) FRow {
+  long long off;
+  int seg0, nseg;
+};
+struct alignas(16) SSeg {
+  int src, len, slot, pad;
+};
+constexpr int kMaxLevels = 8;  // separator-tree levels of the interface solve
+constexpr int kDefaultIfaceLevels = 4;
+
 struct DeviceSolve {
-  // partitioned inverse of A~ over free vertices (two-level Schur complement)
+  // partitioned inverse of A~ over free vertices: subdomain blocks, then the
+  // interface Schur complement over the separator tree
   double* Zs = nullptr;         // per subdomain n_s x n_s (row-major), = A_ss^{-1}
   double* Et = nullptr;         // per subdomain n_s x |I_s| (row v holds E_s[:, v]), E_s = A_Ts A_ss^{-1}
   double* E = nullptr;          // per interface row: E_s[p, :] of its couplings, concatenated
-  double* Z = nullptr;          // nT x nT, inverse Schur complement
+  double* ZE = nullptr;         // per separator node: rows [Z_n[j, :], -E_n[:, j]]
+  double* FE = nullptr;         // per interface row: its forward rows E_c[m, :], concatenated
+  SepNode* sep = nullptr;
+  SepBlk* sblk = nullptr;       // backward blocks, level by level
+  FRow* frow = nullptr;         // nT
+  SSeg* sseg = nullptr;
+  int* lev_row = nullptr;       // nlev + 1: interface rows of each level
+  int* lev_blk = nullptr;       // nlev + 1: backward blocks of each level
+  int nlev = 0;
+  std::vector<int> lev_row_h, lev_blk_h;
   long long* zs_off = nullptr;  // nsub + 1
   long long* e_off = nullptr;   // nsub + 1 (same offsets for E and Et)
   int* sub_of = nullptr;        // nB
@@ -91,11 +144,11 @@ struct DeviceSolve {
   BRow* brow = nullptr;         // nB
   BOff* boff = nullptr;         // nB
   BStage* bstage = nullptr;     // one per subdomain-solve block of subdomain rows
-  double* xsT = nullptr;        // 3 x n_irows: interface values gathered per subdomain
-  int n_irows = 0;
+  double* xsT = nullptr;        // 3 x n_irows: interface values gathered per subdomain, then per separator node
+  int n_irows = 0;              // slots: the subdomains' couplings, then every node's struct
   int max_coup = 0;
   size_t bytes = 0;
-  double zs_entries = 0, e_entries = 0;
+  double zs_entries = 0, e_entries = 0, ze_entries = 0, fe_entries = 0;
 };
 
 // Per-launch timing of one kernel with HIP events (roofline instrumentation).
@@ -119,6 +172,7 @@ struct Scene {
   int energy = 0;  // 0: Neo-Hookean proximal map; 1: corotated + volume composite
   double h = 0, grav[3] = {0, 0, 0};
   int m = 0, kmax_fwd = 1000, kmax_bwd = 1000, adj_method = 0, max_sub = 0, iters_per_check = 0;
+  int iface_levels = 0;
   double eps_rel = 1e-6, eps_abs = 1e-12, eps_adj = 1e-6, eps_tr = 0.1;
   bool stale = true;
   int last_fwd_iters = 4, last_adj_iters = 8;

@@ -242,14 +242,18 @@ void contact_free(Scene& S) {
   S.vert_of_slot.clear();
 }
 
+void free_solve(DeviceSolve& D) {
+  dfree(D.Zs); dfree(D.Et); dfree(D.E); dfree(D.ZE); dfree(D.FE); dfree(D.sep); dfree(D.sblk); dfree(D.frow);
+  dfree(D.sseg); dfree(D.lev_row); dfree(D.lev_blk); dfree(D.zs_off); dfree(D.e_off); dfree(D.sub_of);
+  dfree(D.sub_begin); dfree(D.ir_off); dfree(D.irows); dfree(D.rl_ptr); dfree(D.rl_sub); dfree(D.rl_p); dfree(D.rT);
+  dfree(D.cpl); dfree(D.erow); dfree(D.brow); dfree(D.boff); dfree(D.bstage); dfree(D.xsT);
+}
+
 void free_device(Scene& S) {
   dfree(S.tv); dfree(S.tinc); dfree(S.Bm); dfree(S.wV); dfree(S.bV); dfree(S.muV); dfree(S.lamV);
   dfree(S.tet_orig); dfree(S.Vw); dfree(S.rw);
   dfree(S.v_orig); dfree(S.mass); dfree(S.rest); dfree(S.cpin); dfree(S.inc_ptr);
-  DeviceSolve& D = S.S;
-  dfree(D.Zs); dfree(D.Et); dfree(D.E); dfree(D.Z); dfree(D.zs_off); dfree(D.e_off); dfree(D.sub_of);
-  dfree(D.sub_begin); dfree(D.ir_off); dfree(D.irows); dfree(D.rl_ptr); dfree(D.rl_sub); dfree(D.rl_p); dfree(D.rT);
-  dfree(D.cpl); dfree(D.erow); dfree(D.brow); dfree(D.boff); dfree(D.bstage); dfree(D.xsT);
+  free_solve(S.S);
   dfree(S.contrib); dfree(S.qt); dfree(S.vt); dfree(S.qtil); dfree(S.c); dfree(S.q_cur); dfree(S.q_prev);
   dfree(S.b_cur); dfree(S.b_prev); dfree(S.qhat); dfree(S.q_last); dfree(S.g_last); dfree(S.dQ); dfree(S.dG);
   dfree(S.ctl); dfree(S.dstat); dfree(S.red_part); dfree(S.red_fin);
@@ -384,7 +388,13 @@ SolveArgs solve_args(const Scene& S) {
   A.nsub = S.L.nsub; A.nB = S.L.nB; A.nT = S.L.nT;
   A.sub_of = D.sub_of; A.sub_begin = D.sub_begin; A.Zs = D.Zs; A.zs_off = D.zs_off; A.Et = D.Et; A.E = D.E;
   A.e_off = D.e_off; A.ir_off = D.ir_off; A.irows = D.irows; A.rl_ptr = D.rl_ptr; A.rl_sub = D.rl_sub;
-  A.rl_p = D.rl_p; A.Z = D.Z; A.rT = D.rT;
+  A.rl_p = D.rl_p; A.rT = D.rT;
+  A.nlev = D.nlev; A.lev_row = D.lev_row; A.lev_blk = D.lev_blk; A.sep = D.sep; A.sblk = D.sblk; A.ZE = D.ZE;
+  A.frow = D.frow; A.sseg = D.sseg; A.FE = D.FE;
+  for (int l = 0; l < kMaxLevels; ++l) {
+    A.lev_nrows[l] = l < D.nlev ? D.lev_row_h[l + 1] - D.lev_row_h[l] : 0;
+    A.lev_nblk[l] = l < D.nlev ? D.lev_blk_h[l + 1] - D.lev_blk_h[l] : 0;
+  }
   A.cpl = D.cpl; A.erow = D.erow; A.brow = D.brow; A.boff = D.boff; A.bstage = D.bstage; A.xsT = D.xsT;
   A.n_irows = D.n_irows;
   return A;
@@ -446,6 +456,9 @@ void setup_scene(Scene& S, const pd_mesh_desc* mesh, const pd_material_desc* mat
   S.m = o->aa_window; S.eps_rel = o->eps_rel; S.eps_abs = o->eps_abs; S.kmax_fwd = o->kmax_fwd;
   S.kmax_bwd = o->kmax_bwd; S.eps_adj = o->eps_adj; S.eps_tr = o->eps_tr; S.adj_method = o->adj_method;
   S.max_sub = o->max_sub > 0 ? o->max_sub : 256;
+  if (o->iface_levels < 0 || o->iface_levels > kMaxLevels)
+    throw PdError{PD_ERR_INVALID_ARG, "iface_levels must be 0 (default) or 1..8"};
+  S.iface_levels = o->iface_levels > 0 ? o->iface_levels : kDefaultIfaceLevels;
   S.iters_per_check = o->iters_per_check;
   if (o->adj_warm < 0 || o->adj_warm > 3) throw PdError{PD_ERR_INVALID_ARG, "adj_warm must be 0, 1, 2 or 3"};
   if (o->fwd_start < 0 || o->fwd_start > 1) throw PdError{PD_ERR_INVALID_ARG, "fwd_start must be 0 or 1"};
@@ -467,7 +480,7 @@ void setup_scene(Scene& S, const pd_mesh_desc* mesh, const pd_material_desc* mat
     if (!(d > 1e-14 * scale * scale * scale))
       throw PdError{PD_ERR_DEGENERATE_TET, "zero-volume tet " + std::to_string(e)};
   }
-  build_layout(nv, ne, S.X.data(), S.tets.data(), S.pinned.data(), S.max_sub, S.L);
+  build_layout(nv, ne, S.X.data(), S.tets.data(), S.pinned.data(), S.max_sub, S.iface_levels, S.L);
   if (S.L.nf == 0) throw PdError{PD_ERR_INVALID_ARG, "no free vertex"};
   S.nnz_L = factor_nnz_nd(nv, ne, S.X.data(), S.tets.data(), S.pinned.data());
   const Layout& L = S.L;
@@ -579,6 +592,110 @@ void setup_scene(Scene& S, const pd_mesh_desc* mesh, const pd_material_desc* mat
   S.stale = true;
 }
 
+// Block elimination of the interface Schur complement over the separator
+// tree (levels ascending; the nodes of a level are independent).  Node n's
+// frontal matrix F (its rows, then its struct) gets its children's updates;
+// then Z_n = F_nn^{-1}, E_n = F_{struct,n} Z_n and the update
+// F_{struct,struct} - E_n F_{n,struct} for its parent.  Returns per node the
+// backward rows [Z_n[j, :], -E_n[:, j]] and E_n (forward rows).
+struct SepFactor {
+  std::vector<std::vector<double>> ZE, E;
+};
+
+SepFactor eliminate_separators(const Layout& L, std::vector<std::vector<double>>& Fr, const std::vector<int>& fs,
+                               const std::vector<int>& fb, int T) {
+  const int nsep = (int)fs.size();
+  SepFactor R;
+  R.ZE.resize(nsep);
+  R.E.resize(nsep);
+  std::vector<std::vector<int>> children(nsep);
+  for (int n = 0; n < nsep; ++n)
+    if (L.sep_parent[n] >= 0) children[L.sep_parent[n]].push_back(n);
+  std::vector<std::vector<double>> U(nsep);
+  std::vector<int> ok(nsep, 1);
+  auto elim = [&](int n, int nth) {
+    const int sn = fs[n], bn = fb[n];
+    const size_t m = (size_t)sn + bn;
+    std::vector<double>& F = Fr[n];
+    for (int c : children[n]) {  // extend-add of the children's updates
+      const auto& st = L.sep_struct[c];
+      const int bc = (int)st.size();
+      std::vector<int> at(bc);
+      for (int p = 0; p < bc; ++p) {
+        const int u = st[p];
+        if (u >= L.sep_begin[n] && u < L.sep_begin[n + 1]) {
+          at[p] = u - L.sep_begin[n];
+        } else {
+          const auto& sn_st = L.sep_struct[n];
+          const auto it = std::lower_bound(sn_st.begin(), sn_st.end(), u);
+          if (it == sn_st.end() || *it != u) {
+            ok[n] = -1;  // a child's struct outside its parent's block: a layout error
+            return;
+          }
+          at[p] = sn + (int)(it - sn_st.begin());
+        }
+      }
+      for (int p = 0; p < bc; ++p)
+        for (int q = 0; q < bc; ++q) F[(size_t)at[p] * m + at[q]] += U[c][(size_t)p * bc + q];
+      std::vector<double>().swap(U[c]);
+    }
+    std::vector<double> Z((size_t)sn * sn);
+    for (int i = 0; i < sn; ++i)
+      for (int j = 0; j < sn; ++j) Z[(size_t)i * sn + j] = F[(size_t)i * m + j];
+    if (!(nth > 1 ? spd_inverse_threaded(Z, sn) : spd_inverse(Z, sn))) {
+      ok[n] = 0;
+      return;
+    }
+    std::vector<double>& E = R.E[n];
+    E.assign((size_t)bn * sn, 0.0);
+    std::vector<double> Un((size_t)bn * bn);
+    auto rows = [&](int t, int nt) {
+      for (int p = t; p < bn; p += nt) {
+        const double* f = &F[(size_t)(sn + p) * m];
+        double* e = &E[(size_t)p * sn];
+        for (int k = 0; k < sn; ++k) {
+          if (f[k] == 0.0) continue;
+          const double* z = &Z[(size_t)k * sn];
+          for (int j = 0; j < sn; ++j) e[j] += f[k] * z[j];
+        }
+        for (int q = 0; q < bn; ++q) {
+          double d = F[(size_t)(sn + p) * m + sn + q];
+          for (int j = 0; j < sn; ++j) d -= e[j] * F[(size_t)j * m + sn + q];
+          Un[(size_t)p * bn + q] = d;
+        }
+      }
+    };
+    if (nth > 1) run_threads(nth, [&](int t) { rows(t, nth); });
+    else rows(0, 1);
+    std::vector<double>& ZE = R.ZE[n];
+    ZE.resize((size_t)sn * m);
+    for (int j = 0; j < sn; ++j) {
+      double* r = &ZE[(size_t)j * m];
+      for (int k = 0; k < sn; ++k) r[k] = Z[(size_t)j * sn + k];
+      for (int p = 0; p < bn; ++p) r[sn + p] = -E[(size_t)p * sn + j];
+    }
+    U[n] = std::move(Un);
+    std::vector<double>().swap(F);
+  };
+  constexpr int kBigNode = 1024;  // rows above which a node is eliminated with all threads
+  for (int lo = 0; lo < nsep;) {
+    int hi = lo;
+    while (hi < nsep && L.sep_level[hi] == L.sep_level[lo]) ++hi;
+    std::vector<int> small, big;
+    for (int n = lo; n < hi; ++n) (fs[n] < kBigNode ? small : big).push_back(n);
+    run_threads(T, [&](int t) {
+      for (size_t k = t; k < small.size(); k += T) elim(small[k], 1);
+    });
+    for (int n : big) elim(n, T);
+    for (int n = lo; n < hi; ++n) {
+      if (ok[n] < 0) throw PdError{PD_ERR_INVALID_ARG, "layout: separator blocks do not nest"};
+      if (!ok[n]) throw PdError{PD_ERR_FACTOR_NOT_SPD, "interface Schur complement not SPD"};
+    }
+    lo = hi;
+  }
+  return R;
+}
+
 void factorize(Scene& S) {
   const Layout& L = S.L;
   const int nv = S.nv, ne = S.ne, nf = L.nf, nB = L.nB, nT = L.nT;
@@ -637,8 +754,36 @@ void factorize(Scene& S) {
     AIs[s].assign(L.Irows[s].size() * (size_t)ns, 0.0);
     for (int i = L.sub_begin[s]; i < L.sub_begin[s + 1]; ++i) sub_of[i] = s;
   }
-  if ((size_t)nT * nT > (size_t)1 << 28) throw PdError{PD_ERR_ALLOC, "interface too large for the dense Schur block"};
-  std::vector<double> ATT((size_t)nT * nT, 0.0);
+  // frontal blocks of the separator tree: node n's rows, then its struct;
+  // an entry of S between rows u and w is assembled at the lower of their
+  // nodes (the other row is that node's own or in its struct)
+  const int nsep = (int)L.sep_level.size();
+  std::vector<int> node_of(std::max(1, nT), 0), fs(nsep), fb(nsep);
+  for (int n = 0; n < nsep; ++n) {
+    fs[n] = L.sep_begin[n + 1] - L.sep_begin[n];
+    fb[n] = (int)L.sep_struct[n].size();
+    for (int i = L.sep_begin[n]; i < L.sep_begin[n + 1]; ++i) node_of[i] = n;
+    const size_t m = (size_t)fs[n] + fb[n];
+    if (m * m > (size_t)1 << 28)
+      throw PdError{PD_ERR_ALLOC, "a separator block is too large for its dense frontal matrix; use more levels"};
+  }
+  std::vector<std::vector<double>> Fr(nsep);
+  for (int n = 0; n < nsep; ++n) Fr[n].assign(((size_t)fs[n] + fb[n]) * ((size_t)fs[n] + fb[n]), 0.0);
+  auto fpos = [&](int n, int u) {
+    if (node_of[u] == n) return u - L.sep_begin[n];
+    const auto& st = L.sep_struct[n];
+    const auto it = std::lower_bound(st.begin(), st.end(), u);
+    if (it == st.end() || *it != u) throw PdError{PD_ERR_INVALID_ARG, "layout: entry outside the separator blocks"};
+    return fs[n] + (int)(it - st.begin());
+  };
+  auto addS = [&](int u, int w, double val) {
+    const int nu = node_of[u], nw = node_of[w];
+    const int n = L.sep_level[nu] < L.sep_level[nw] ? nu : nw;
+    if (L.sep_level[nu] == L.sep_level[nw] && nu != nw)
+      throw PdError{PD_ERR_INVALID_ARG, "layout: coupled separators on one level"};
+    const size_t m = (size_t)fs[n] + fb[n];
+    Fr[n][(size_t)fpos(n, u) * m + fpos(n, w)] += val;
+  };
   std::vector<double> cpin(3 * (size_t)nv, 0.0);
   auto ipos = [&](int s, int iface) {
     const auto& I = L.Irows[s];
@@ -650,7 +795,7 @@ void factorize(Scene& S) {
       const int s = sub_of[i], b = L.sub_begin[s], ns = L.sub_begin[s + 1] - b;
       Ass[s][(size_t)(i - b) * ns + (i - b)] += d;
     } else {
-      ATT[(size_t)(i - nB) * nT + (i - nB)] += d;
+      addS(i - nB, i - nB, d);
     }
   }
   for (int t = 0; t < ne; ++t) {
@@ -681,7 +826,7 @@ void factorize(Scene& S) {
           const int s = sub_of[j], b0 = L.sub_begin[s], ns = L.sub_begin[s + 1] - b0;
           AIs[s][(size_t)ipos(s, i - nB) * ns + (j - b0)] += val;
         } else if (i >= nB && j >= nB) {
-          ATT[(size_t)(i - nB) * nT + (j - nB)] += val;
+          addS(i - nB, j - nB, val);
         }
       }
     }
@@ -741,12 +886,11 @@ void factorize(Scene& S) {
     if (!sub_ok[s]) throw PdError{PD_ERR_FACTOR_NOT_SPD, "subdomain block not SPD"};
     const int nI = (int)L.Irows[s].size();
     for (int p = 0; p < nI; ++p)
-      for (int q = 0; q < nI; ++q)
-        ATT[(size_t)L.Irows[s][p] * nT + L.Irows[s][q]] -= schur[s][(size_t)p * nI + q];
+      for (int q = 0; q < nI; ++q) addS(L.Irows[s][p], L.Irows[s][q], -schur[s][(size_t)p * nI + q]);
   }
   schur.clear();
-  if (nT > 0 && !spd_inverse_threaded(ATT, nT))
-    throw PdError{PD_ERR_FACTOR_NOT_SPD, "interface Schur complement not SPD"};
+  SepFactor SF = eliminate_separators(L, Fr, fs, fb, T);
+  Fr.clear();
   // couplings of each interface row: (subdomain, row of E_s), subdomains ascending
   std::vector<int> ir_off(nsub + 1, 0), irows;
   for (int s = 0; s < nsub; ++s) {
@@ -809,11 +953,66 @@ void factorize(Scene& S) {
     const int zn = l.b0 + l.ns - f.b0, en = l.ir0 + l.nI - f.ir0;
     if (zn <= kStageZ && en <= kStageE) bstage[b] = BStage{f.b0, zn, f.ir0, en};
   }
+  // the separator tree's solve structure: backward rows per node, their
+  // blocks per level, forward rows per interface row with their segments;
+  // the gathered interface vectors hold the subdomains' slots, then every
+  // node's struct
+  const int n_leaf_slots = (int)irows.size();
+  std::vector<SepNode> sep(std::max(1, nsep), SepNode{0, 0, 0, 0, 0});
+  long long ze_total = 0;
+  int slots = n_leaf_slots;
+  for (int n = 0; n < nsep; ++n) {
+    sep[n] = SepNode{ze_total, L.sep_begin[n], fs[n], fb[n], slots};
+    ze_total += (long long)fs[n] * (fs[n] + fb[n]);
+    slots += fb[n];
+  }
+  std::vector<double> ZE_all((size_t)std::max(1LL, ze_total));
+  for (int n = 0; n < nsep; ++n) std::copy(SF.ZE[n].begin(), SF.ZE[n].end(), ZE_all.begin() + sep[n].zoff);
+  std::vector<std::vector<std::pair<int, int>>> segs_of(std::max(1, nT));  // (node, struct position), nodes ascending
+  for (int n = 0; n < nsep; ++n)
+    for (int p = 0; p < fb[n]; ++p) segs_of[L.sep_struct[n][p]].push_back({n, p});
+  std::vector<FRow> frow(std::max(1, nT), FRow{0, 0, 0});
+  std::vector<SSeg> sseg;
+  std::vector<double> FE_all;
+  for (int i = 0; i < nT; ++i) {
+    if ((int)segs_of[i].size() > kSepMaxSeg)
+      throw PdError{PD_ERR_INVALID_ARG, "an interface vertex couples to more than 56 separator blocks; use fewer levels"};
+    frow[i] = FRow{(long long)FE_all.size(), (int)sseg.size(), (int)segs_of[i].size()};
+    for (const auto& cp : segs_of[i]) {
+      const int c = cp.first, p = cp.second;
+      sseg.push_back(SSeg{L.sep_begin[c], fs[c], sep[c].xs0 + p, 0});
+      FE_all.insert(FE_all.end(), SF.E[c].begin() + (size_t)p * fs[c], SF.E[c].begin() + (size_t)(p + 1) * fs[c]);
+    }
+  }
+  SF = SepFactor{};
+  if (sseg.empty()) sseg.push_back(SSeg{0, 0, 0, 0});
+  if (FE_all.empty()) FE_all.push_back(0.0);
+  std::vector<SepBlk> sblk;
+  std::vector<int> lev_blk(L.nlev + 1, 0);
+  for (int n = 0; n < nsep; ++n) {
+    if (n == 0 || L.sep_level[n] != L.sep_level[n - 1]) lev_blk[L.sep_level[n] - 1] = (int)sblk.size();
+    // a wide node's rows go one per wave, the others kSepRowsPerWave per wave
+    const bool wide = fs[n] + fb[n] >= kSepWide;
+    const int per = wide ? kBlock / 64 : kSepRows;
+    for (int r = 0; r < fs[n]; r += per)
+      sblk.push_back(SepBlk{n, L.sep_begin[n] + r, std::min(per, fs[n] - r), wide ? 1 : 0});
+  }
+  if (L.nlev > 0) lev_blk[L.nlev] = (int)sblk.size();
+  if (sblk.empty()) sblk.push_back(SepBlk{0, 0, 0, 0});
   // upload the solve structure
   DeviceSolve& D = S.S;
-  dfree(D.Zs); dfree(D.Et); dfree(D.E); dfree(D.Z); dfree(D.zs_off); dfree(D.e_off); dfree(D.sub_of);
-  dfree(D.sub_begin); dfree(D.ir_off); dfree(D.irows); dfree(D.rl_ptr); dfree(D.rl_sub); dfree(D.rl_p); dfree(D.rT);
-  dfree(D.cpl); dfree(D.erow); dfree(D.brow); dfree(D.boff); dfree(D.bstage); dfree(D.xsT);
+  free_solve(D);
+  D.ZE = dalloc<double>(ZE_all.size()); upload(D.ZE, ZE_all);
+  D.FE = dalloc<double>(FE_all.size()); upload(D.FE, FE_all);
+  D.sep = dalloc<SepNode>(sep.size()); upload(D.sep, sep);
+  D.sblk = dalloc<SepBlk>(sblk.size()); upload(D.sblk, sblk);
+  D.frow = dalloc<FRow>(frow.size()); upload(D.frow, frow);
+  D.sseg = dalloc<SSeg>(sseg.size()); upload(D.sseg, sseg);
+  D.nlev = L.nlev;
+  D.lev_row_h = L.lev_begin;
+  D.lev_blk_h = lev_blk;
+  D.lev_row = dalloc<int>(L.nlev + 1); upload(D.lev_row, L.lev_begin);
+  D.lev_blk = dalloc<int>(L.nlev + 1); upload(D.lev_blk, lev_blk);
   D.Zs = dalloc<double>(Zs_all.size()); upload(D.Zs, Zs_all);
   D.Et = dalloc<double>(Et_all.size()); upload(D.Et, Et_all);
   D.E = dalloc<double>(E_flat.size()); upload(D.E, E_flat);
@@ -822,10 +1021,9 @@ void factorize(Scene& S) {
   D.brow = dalloc<BRow>(brow.size()); upload(D.brow, brow);
   D.boff = dalloc<BOff>(boff.size()); upload(D.boff, boff);
   D.bstage = dalloc<BStage>(bstage.size()); upload(D.bstage, bstage);
-  D.n_irows = (int)irows.size();
+  D.n_irows = slots;
   D.xsT = dalloc<double>(3 * (size_t)std::max(1, D.n_irows));
   D.max_coup = max_coup;
-  D.Z = dalloc<double>(ATT.size()); upload(D.Z, ATT);
   D.zs_off = dalloc<long long>(nsub + 1); upload(D.zs_off, zs_off);
   D.e_off = dalloc<long long>(nsub + 1); upload(D.e_off, e_off);
   std::vector<int> sub_of_B(sub_of.begin(), sub_of.begin() + nB);
@@ -839,7 +1037,9 @@ void factorize(Scene& S) {
   D.rT = dalloc<double>(3 * (size_t)std::max(1, nT));
   D.zs_entries = (double)Zs_all.size();
   D.e_entries = (double)E_all.size();
-  D.bytes = (Zs_all.size() + Et_all.size() + E_all.size() + ATT.size()) * sizeof(double);
+  D.ze_entries = (double)ze_total;
+  D.fe_entries = (double)(FE_all.size() > 1 ? FE_all.size() : 0);
+  D.bytes = (Zs_all.size() + Et_all.size() + E_all.size() + ZE_all.size() + FE_all.size()) * sizeof(double);
   PD_HIP(hipDeviceSynchronize());
   S.stale = false;
   S.adj_hist = 0;
@@ -1132,8 +1332,8 @@ static double kernel_bytes(const Scene& S, int id) {
       return 24.0 * ninc + 24.0 * nf * 4;
     case kKEb:  // coupling blocks E_s, right-hand side in, interface right-hand side out
       return 8.0 * et + 24.0 * nf + 24.0 * nT;
-    case kKTop:  // inverse Schur block, interface right-hand side in, solution out
-      return 8.0 * nT * nT + 24.0 * nT * 2;
+    case kKTop:  // separator blocks (backward rows, forward rows), interface right-hand side in, solution out
+      return 8.0 * (S.S.ze_entries + S.S.fe_entries) + 24.0 * nT * 2;
     case kKBottom:  // subdomain inverses and couplings, right-hand sides, solution out
       return 8.0 * (zs + et) + 24.0 * (nB * 2 + nT);
     case kKApplyK:  // tet indices, D_m^-1, weight, 30 Jacobian values per tet; x in and K x out per vertex
@@ -1953,6 +2153,7 @@ struct pd_batch {
   int block_local = kBlock, block_applyK = kBlock;
   int chunk = 0;        // iterations per host check (0 = adaptive)
   int use_graph = 0;
+  int nlev = 0;         // separator levels of the deepest scene
   int* dctl = nullptr;  // ns x kCtlTotal
   double* ddstat = nullptr;
   int* hctl = nullptr;
@@ -1991,8 +2192,14 @@ void batch_layout(pd_batch& B) {
         case kBKApplyK: n = (S.ne + B.block_applyK - 1) / B.block_applyK; break;
         case kBKGather: n = vert_group_blocks(S.L.nf); break;
         case kBKEb: n = eb_blocks(S.L.nT); break;
-        case kBKTop: n = (S.L.nT + 3) / 4; break;
-        default: n = bottom_blocks(S.L.nB, S.L.nT); break;
+        case kBKBottom: n = bottom_blocks(S.L.nB, S.L.nT); break;
+        default: {
+          const bool fwd = kind < kBKSepB;
+          const int l = kind - (fwd ? kBKSepF : kBKSepB);  // level l + 1
+          const SolveArgs A = solve_args(S);
+          n = !fwd ? A.lev_nblk[l] : l >= 1 ? (A.lev_nrows[l] + kBlock / 64 - 1) / (kBlock / 64) : 0;
+          break;
+        }
       }
       base[s + 1] = base[s] + n;
     }
@@ -2001,6 +2208,8 @@ void batch_layout(pd_batch& B) {
     B.dbase[kind] = dalloc<int>(ns + 1);
     upload(B.dbase[kind], base);
   }
+  B.nlev = 0;
+  for (pd_scene* p : B.scenes) B.nlev = std::max(B.nlev, p->S.S.nlev);
   batch_free_graphs(B);
 }
 
@@ -2025,6 +2234,19 @@ void batch_bundles(pd_batch& B) {
 
 BatchMap bmap(const pd_batch& B, int kind) { return BatchMap{B.dB, B.dbase[kind], (int)B.scenes.size()}; }
 
+// the interface solve of every scene, level by level
+void batch_sep(const pd_batch& B, int adjoint, hipStream_t st) {
+  BatchMap Mf[kMaxLevels], Mb[kMaxLevels];
+  int nf[kMaxLevels], nb[kMaxLevels];
+  for (int l = 0; l < kMaxLevels; ++l) {
+    Mf[l] = bmap(B, kBKSepF + l);
+    Mb[l] = bmap(B, kBKSepB + l);
+    nf[l] = B.nblk[kBKSepF + l];
+    nb[l] = B.nblk[kBKSepB + l];
+  }
+  launch_b_sep(Mf, nf, Mb, nb, B.nlev, adjoint, st);
+}
+
 #define PD_BTIMED(B, id, st, call)                     \
   do {                                                 \
     const bool tm_ = !(B).use_graph && (B).kt.which >= 0; \
@@ -2037,7 +2259,7 @@ void batch_fwd_iter(pd_batch& B, int k, hipStream_t st) {
   PD_BTIMED(B, kKLocal, st, launch_b_local(bmap(B, kBKLocal), B.nblk[kBKLocal], B.block_local, k, st));
   PD_BTIMED(B, kKGather, st, launch_b_gather_fwd(bmap(B, kBKGather), B.nblk[kBKGather], k, st));
   PD_BTIMED(B, kKEb, st, launch_b_Eb(kModeFwd, bmap(B, kBKEb), B.nblk[kBKEb], k, st));
-  PD_BTIMED(B, kKTop, st, launch_b_top(bmap(B, kBKTop), B.nblk[kBKTop], 0, st));
+  PD_BTIMED(B, kKTop, st, batch_sep(B, 0, st));
   PD_BTIMED(B, kKBottom, st, launch_b_bottom(kModeFwd, bmap(B, kBKBottom), B.nblk[kBKBottom], k, st));
 }
 
@@ -2046,7 +2268,7 @@ void batch_adj_iter(pd_batch& B, int it, hipStream_t st) {
             launch_b_apply_K(kModePCG, bmap(B, kBKApplyK), B.nblk[kBKApplyK], B.block_applyK, it, st));
   launch_b_adj_gather(kModePCG, bmap(B, kBKGather), B.nblk[kBKGather], it, st);
   PD_BTIMED(B, kKEb, st, launch_b_Eb(kModePCG, bmap(B, kBKEb), B.nblk[kBKEb], it, st));
-  PD_BTIMED(B, kKTop, st, launch_b_top(bmap(B, kBKTop), B.nblk[kBKTop], 1, st));
+  PD_BTIMED(B, kKTop, st, batch_sep(B, 1, st));
   PD_BTIMED(B, kKBottom, st, launch_b_bottom(kModePCG, bmap(B, kBKBottom), B.nblk[kBKBottom], it, st));
 }
 
@@ -2259,7 +2481,7 @@ int pd_batch_step_backward(pd_batch* B, const void* const* ckpt, const double* c
     launch_b_adj_gather(kModeInit, bmap(*B, kBKGather), B->nblk[kBKGather], 0, st);
   }
   PD_BTIMED(*B, kKEb, st, launch_b_Eb(kModePlain, bmap(*B, kBKEb), B->nblk[kBKEb], 0, st));
-  PD_BTIMED(*B, kKTop, st, launch_b_top(bmap(*B, kBKTop), B->nblk[kBKTop], 1, st));
+  PD_BTIMED(*B, kKTop, st, batch_sep(*B, 1, st));
   PD_BTIMED(*B, kKBottom, st, launch_b_bottom(kModePCGInit, bmap(*B, kBKBottom), B->nblk[kBKBottom], 0, st));
   int it = 0;
   const int fixed = B->chunk > 0 ? B->chunk : (B->use_graph ? 4 : 0);

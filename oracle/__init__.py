@@ -48,6 +48,9 @@ def lib():
         L.or_set_threads.argtypes = [ctypes.c_int]
         L.or_get_threads.restype = ctypes.c_int
         L.or_scene_info.argtypes = [ctypes.c_void_p, _dp, _dp, _dp, _dp, _dp]
+        L.or_scene_set_muscles.argtypes = [ctypes.c_void_p, ctypes.c_int, ctypes.c_double, _ip, _dp]
+        L.or_scene_set_activation.argtypes = [ctypes.c_void_p, _dp]
+        L.or_scene_set_act_grad.argtypes = [ctypes.c_void_p, _dp]
         L.or_svd3.argtypes = [_dp, _dp, _dp, _dp]
         L.or_prox_stretch.argtypes = [_dp, ctypes.c_double, ctypes.c_double, ctypes.c_double, _dp]
         L.or_prox_map.argtypes = [_dp, ctypes.c_double, ctypes.c_double, ctypes.c_double, _dp]
@@ -249,6 +252,23 @@ class OracleScene:
                                      pinned.ctypes.data_as(ctypes.c_char_p), _p(logE), _p(params), _p(solver))
         self.nf = L.or_scene_nfree(self.ptr)
         self.pinned = pinned.astype(bool)
+
+    def set_muscles(self, group, fibre, w_m):
+        """Muscle fibres (reading in pd_oracle.c): group per tet (-1 passive), unit fibre per tet, weight w_m.
+        Reassembles and refactors A~; activations start at 0; the activation gradient accumulates into
+        ``self.g_act`` (zeroed here)."""
+        group = np.ascontiguousarray(group, dtype=np.int32)
+        fibre = _f(fibre).reshape(self.ne, 3)
+        self.n_groups = int(group.max()) + 1 if group.size and group.max() >= 0 else 0
+        self._mkeep = (group, fibre)
+        lib().or_scene_set_muscles(self.ptr, self.n_groups, float(w_m), group.ctypes.data_as(_ip), _p(fibre))
+        self.g_act = np.zeros(max(self.n_groups, 1))
+        lib().or_scene_set_act_grad(self.ptr, _p(self.g_act))
+
+    def set_activation(self, a):
+        self._akeep = _f(a)
+        assert self._akeep.shape == (self.n_groups,)
+        lib().or_scene_set_activation(self.ptr, _p(self._akeep))
 
     def __del__(self):
         if getattr(self, "ptr", None):

@@ -688,6 +688,18 @@ struct or_scene {
   long* rowptr; /* nf+1: offset of row i's entries (columns first..i) */
   double* Aenv; /* assembled A~ (lower envelope) */
   double* Lenv; /* its Cholesky factor */
+  /* muscle fibres (actuation; the reading is stated at or_scene_set_muscles):
+   * group of each element (-1: passive), its unit fibre m_e in rest
+   * coordinates, c_e[a] = Bhat_a . m_e (so F_e m_e = sum_a q_a c_e[a]), the
+   * fibre weight w_m, the activations a_g, and the caller's accumulator of
+   * dL/da_g that every backward step adds into (NULL: not formed) */
+  int n_mg;
+  double w_m;
+  int* mgroup;
+  double* mfib;  /* ne x 3 */
+  double* mc;    /* ne x 4 */
+  double* act;   /* n_mg */
+  double* g_act; /* n_mg, caller-owned */
 };
 
 static void composite_eval_s(const or_scene* s, const double F[9], composite_parts* c, int want_diff) {
@@ -735,6 +747,42 @@ static void element_contrib(const or_scene* s, int e, double coef, const double 
   }
 }
 
+/* Muscle of element e at deformation gradient F: the fibre image f = F m_e,
+ * its length |f| and the fibre's target length l = 1 - a_g.  Returns 0 for a
+ * passive element. */
+static int muscle_eval(const or_scene* s, int e, const double F[9], double f[3], double* nf, double* ell) {
+  if (!s->mgroup || s->mgroup[e] < 0) return 0;
+  const double* m = s->mfib + 3 * e;
+  for (int i = 0; i < 3; ++i) f[i] = F[3 * i] * m[0] + F[3 * i + 1] * m[1] + F[3 * i + 2] * m[2];
+  *nf = sqrt(f[0] * f[0] + f[1] * f[1] + f[2] * f[2]);
+  *ell = 1.0 - s->act[s->mgroup[e]];
+  return 1;
+}
+
+/* adds coef * G_e^T (x m_e^T) to out (12): the contribution of a fibre-space
+ * vector x, since (x m^T) Bhat_a = (Bhat_a . m) x */
+static void muscle_contrib_add(const or_scene* s, int e, double coef, const double x[3], double out[12]) {
+  double P[9], cm[12];
+  const double* m = s->mfib + 3 * e;
+  for (int i = 0; i < 3; ++i)
+    for (int j = 0; j < 3; ++j) P[3 * i + j] = x[i] * m[j];
+  element_contrib(s, e, coef, P, cm);
+  for (int i = 0; i < 12; ++i) out[i] += cm[i];
+}
+
+/* the fibre's projection onto the sphere of radius l: p = l f/|f| (l m_e for f = 0) */
+static void muscle_project(const or_scene* s, int e, const double f[3], double nf, double ell, double p[3]) {
+  for (int i = 0; i < 3; ++i) p[i] = nf > 0.0 ? ell * f[i] / nf : ell * s->mfib[3 * e + i];
+}
+
+/* its derivative applied to y: dp = (l/|f|)(y - f^ (f^ . y)) (zero for f = 0) */
+static void muscle_dproj(const double f[3], double nf, double ell, const double y[3], double dp[3]) {
+  if (!(nf > 0.0)) { dp[0] = dp[1] = dp[2] = 0.0; return; }
+  double fh[3] = {f[0] / nf, f[1] / nf, f[2] / nf};
+  double d = fh[0] * y[0] + fh[1] * y[1] + fh[2] * y[2];
+  for (int i = 0; i < 3; ++i) dp[i] = ell / nf * (y[i] - fh[i] * d);
+}
+
 static void scatter_contribs(const or_scene* s, const double* ctb, double* y) {
   for (int e = 0; e < s->ne; ++e)
     for (int a = 0; a < 4; ++a) {
@@ -759,6 +807,8 @@ int or_get_threads(void) {
   return 1;
 #endif
 }
+
+static void assemble_factor(or_scene* s);
 
 or_scene* or_scene_create(int nv, int ne, const double* X, const int* tets, const unsigned char* pinned,
                           const double* logE, const double* params, const double* solver) {
@@ -842,6 +892,16 @@ or_scene* or_scene_create(int nv, int ne, const double* X, const int* tets, cons
   }
   s->fmask3 = (unsigned char*)malloc(3 * (size_t)nv);
   for (int v = 0; v < nv; ++v) for (int ax = 0; ax < 3; ++ax) s->fmask3[3 * v + ax] = pinned[v] ? 0 : 1;
+  assemble_factor(s);
+  return s;
+}
+
+/* Envelope storage of A~ over the free vertices, its assembly and its
+ * Cholesky factor (rebuilt when muscle fibres are set). */
+static void assemble_factor(or_scene* s) {
+  int nv = s->nv, ne = s->ne;
+  (void)nv;
+  free(s->first); free(s->rowptr); free(s->Aenv); free(s->Lenv);
   /* envelope of A~ */
   int nf = s->nf;
   s->first = (int*)malloc(sizeof(int) * (nf > 0 ? nf : 1));
@@ -872,6 +932,18 @@ or_scene* or_scene_create(int nv, int ne, const double* X, const int* tets, cons
         *env_at(s->Aenv, s, i, j) += c * d;
       }
   }
+  /* muscle fibres: w_m V_e G_m^T G_m = w_m V_e (c_e c_e^T) (x) I_3 */
+  for (int e = 0; e < ne; ++e) {
+    if (!s->mgroup || s->mgroup[e] < 0) continue;
+    double c = s->w_m * s->vol[e];
+    const double* mc = s->mc + 4 * e;
+    for (int a = 0; a < 4; ++a)
+      for (int b = 0; b < 4; ++b) {
+        int i = s->fidx[s->tets[4 * e + a]], j = s->fidx[s->tets[4 * e + b]];
+        if (i < 0 || j < 0 || j > i) continue;
+        *env_at(s->Aenv, s, i, j) += c * mc[a] * mc[b];
+      }
+  }
   /* envelope Cholesky A~ = L L^T (any ordering; the original one) */
   for (int i = 0; i < nf; ++i) {
     for (int j = s->first[i]; j <= i; ++j) {
@@ -882,14 +954,52 @@ or_scene* or_scene_create(int nv, int ne, const double* X, const int* tets, cons
       else *env_at(s->Lenv, s, i, i) = sqrt(sum);
     }
   }
-  return s;
 }
+
+/* READING (actuation; the paper's muscle-driven scenes route activations
+ * through db/da but print no muscle energy): a muscle element carries the
+ * fibre constraint (w_m V_e / 2) dist^2(F_e m_e, S_l) with S_l the sphere of
+ * radius l = 1 - a_g in fibre space, a the activation of the element's group
+ * (a > 0 shortens the fibre's rest length).  Its projection is p = l f/|f|
+ * (f = F_e m_e); A~ gains w_m V_e (c_e c_e^T) (x) I_3 and b gains w_m V_e
+ * G_m^T p, with G_m q = f; db/dq gains w_m V_e G_m^T (l/|f|)(I - f^ f^T) G_m
+ * and db/da_g = -sum_{e in g} w_m V_e G_m^T f^.  Fibres must be unit vectors.
+ * Setting muscles reassembles and refactors A~. */
+void or_scene_set_muscles(or_scene* s, int n_groups, double w_m, const int* group, const double* fibre) {
+  free(s->mgroup); free(s->mfib); free(s->mc); free(s->act);
+  s->mgroup = NULL; s->mfib = NULL; s->mc = NULL; s->act = NULL;
+  s->n_mg = n_groups;
+  s->w_m = w_m;
+  if (n_groups > 0 && group) {
+    int ne = s->ne;
+    s->mgroup = (int*)malloc(sizeof(int) * ne);
+    s->mfib = (double*)malloc(sizeof(double) * 3 * ne);
+    s->mc = (double*)calloc(4 * (size_t)ne, sizeof(double));
+    s->act = (double*)calloc(n_groups, sizeof(double));
+    memcpy(s->mgroup, group, sizeof(int) * ne);
+    memcpy(s->mfib, fibre, sizeof(double) * 3 * ne);
+    for (int e = 0; e < ne; ++e)
+      for (int a = 0; a < 4; ++a) {
+        const double* B = s->Bhat + 12 * e + 3 * a;
+        const double* m = s->mfib + 3 * e;
+        s->mc[4 * e + a] = B[0] * m[0] + B[1] * m[1] + B[2] * m[2];
+      }
+  }
+  assemble_factor(s);
+}
+
+void or_scene_set_activation(or_scene* s, const double* a) {
+  if (s->act) memcpy(s->act, a, sizeof(double) * s->n_mg);
+}
+
+void or_scene_set_act_grad(or_scene* s, double* g) { s->g_act = g; }
 
 void or_scene_destroy(or_scene* s) {
   if (!s) return;
   free(s->X); free(s->tets); free(s->pinned); free(s->logE); free(s->Bhat); free(s->vol);
   free(s->mu); free(s->lam); free(s->w); free(s->beta); free(s->mass); free(s->fidx); free(s->fvert); free(s->fmask3);
   free(s->first); free(s->rowptr); free(s->Aenv); free(s->Lenv);
+  free(s->mgroup); free(s->mfib); free(s->mc); free(s->act);
   free(s);
 }
 
@@ -961,6 +1071,17 @@ static void local_rhs_stats(const or_scene* s, const double* q, double* b_all, i
     mat3_mul_nt(T, V, P);
     element_contrib(s, e, s->w[e] * s->vol[e], P, ctb + 12 * (size_t)e);
   }
+  /* muscle fibres: w_m V_e G_m^T p with p the fibre's projection */
+  if (s->mgroup) {
+#pragma omp parallel for schedule(static)
+    for (int e = 0; e < s->ne; ++e) {
+      double F[9], f[3], nf, ell, p[3];
+      element_F(s, e, q, F);
+      if (!muscle_eval(s, e, F, f, &nf, &ell)) continue;
+      muscle_project(s, e, f, nf, ell, p);
+      muscle_contrib_add(s, e, s->w_m * s->vol[e], p, ctb + 12 * (size_t)e);
+    }
+  }
   scatter_contribs(s, ctb, b_all);
   free(ctb);
   if (capped) *capped += ncap;
@@ -1000,6 +1121,19 @@ void or_apply_K(const or_scene* s, const double* q, double tau, const double* x_
     prox_diff_apply(U, V, D, c1, c2, dF, dP);
     element_contrib(s, e, s->w[e] * s->vol[e], dP, ctb + 12 * (size_t)e);
   }
+  if (s->mgroup) {
+#pragma omp parallel for schedule(static)
+    for (int e = 0; e < s->ne; ++e) {
+      double F[9], dF[9], f[3], nf, ell, y[3], dp[3];
+      element_F(s, e, q, F);
+      if (!muscle_eval(s, e, F, f, &nf, &ell)) continue;
+      element_F(s, e, xf, dF);
+      const double* m = s->mfib + 3 * e;
+      for (int i = 0; i < 3; ++i) y[i] = dF[3 * i] * m[0] + dF[3 * i + 1] * m[1] + dF[3 * i + 2] * m[2];
+      muscle_dproj(f, nf, ell, y, dp);
+      muscle_contrib_add(s, e, s->w_m * s->vol[e], dp, ctb + 12 * (size_t)e);
+    }
+  }
   scatter_contribs(s, ctb, y_all);
   free(ctb);
   for (int v = 0; v < s->nv; ++v)
@@ -1009,7 +1143,7 @@ void or_apply_K(const or_scene* s, const double* q, double tau, const double* x_
 
 /* Per-element filtered prox differential at q (Alg. 2 element loop), stored
  * as U, V, D, c1, c2 (33 numbers per element) and applied to many vectors. */
-#define KST 36 /* U, V, D, c1, c2 (33); the composite adds the rotation's c2 */
+#define KST 40 /* U, V, D, c1, c2 (33); the composite adds the rotation's c2; a muscle f = F m (3) and l */
 static double* prox_diff_all(const or_scene* s, const double* q, double tau) {
   double* st = (double*)calloc(KST * (size_t)(s->ne > 0 ? s->ne : 1), sizeof(double));
 #pragma omp parallel for schedule(static)
@@ -1031,6 +1165,15 @@ static double* prox_diff_all(const or_scene* s, const double* q, double tau) {
     or_svd3(F, c, sF, c + 9);
     or_prox_stretch(sF, s->mu_bar, s->lam_bar, s->k_bar, ss);
     prox_diff_coeffs(sF, ss, s->mu_bar, s->lam_bar, s->k_bar, tau, c + 18, c + 27, c + 30);
+  }
+  if (s->mgroup) {
+#pragma omp parallel for schedule(static)
+    for (int e = 0; e < s->ne; ++e) {
+      double F[9], nf;
+      double* c = st + KST * (size_t)e;
+      element_F(s, e, q, F);
+      muscle_eval(s, e, F, c + 36, &nf, c + 39);
+    }
   }
   return st;
 }
@@ -1059,11 +1202,33 @@ static void apply_K_stored(const or_scene* s, const double* st, const double* x_
     }
     element_contrib(s, e, s->w[e] * s->vol[e], dP, ctb + 12 * (size_t)e);
   }
+  if (s->mgroup) {
+#pragma omp parallel for schedule(static)
+    for (int e = 0; e < s->ne; ++e) {
+      if (s->mgroup[e] < 0) continue;
+      const double* c = st + KST * (size_t)e;
+      const double* m = s->mfib + 3 * e;
+      double dF[9], y[3], dp[3];
+      const double* f = c + 36;
+      double nf = sqrt(f[0] * f[0] + f[1] * f[1] + f[2] * f[2]);
+      element_F(s, e, xf, dF);
+      for (int i = 0; i < 3; ++i) y[i] = dF[3 * i] * m[0] + dF[3 * i + 1] * m[1] + dF[3 * i + 2] * m[2];
+      muscle_dproj(f, nf, c[39], y, dp);
+      muscle_contrib_add(s, e, s->w_m * s->vol[e], dp, ctb + 12 * (size_t)e);
+    }
+  }
   scatter_contribs(s, ctb, y_all);
   free(ctb);
   for (int v = 0; v < s->nv; ++v)
     if (s->fidx[v] < 0) y_all[3 * v] = y_all[3 * v + 1] = y_all[3 * v + 2] = 0.0;
   free(xf);
+}
+
+/* the muscle energy of element e at F: (w_m V_e / 2)(|f| - l)^2 (dist^2 to the sphere), 0 if passive */
+static double muscle_energy(const or_scene* s, int e, const double F[9]) {
+  double f[3], nf, ell;
+  if (!muscle_eval(s, e, F, f, &nf, &ell)) return 0.0;
+  return 0.5 * s->w_m * s->vol[e] * (nf - ell) * (nf - ell);
 }
 
 /* Primal objective Phi, Eq. primal, with the true per-element mu_e, lam_e */
@@ -1079,7 +1244,7 @@ double or_primal_phi(const or_scene* s, const double* q, const double* qtilde) {
   for (int e = 0; e < s->ne; ++e) {
     double F[9];
     element_F(s, e, q, F);
-    pe[e] = s->vol[e] * or_psi_nh(F, s->mu[e], s->lam[e]);
+    pe[e] = s->vol[e] * or_psi_nh(F, s->mu[e], s->lam[e]) + muscle_energy(s, e, F);
   }
   for (int e = 0; e < s->ne; ++e) phi += pe[e];
   free(pe);
@@ -1110,6 +1275,7 @@ void or_const_rhs(const or_scene* s, const double* q_t, const double* v_t, const
         double d = B[3 * a] * B[3 * b] + B[3 * a + 1] * B[3 * b + 1] + B[3 * a + 2] * B[3 * b + 2];
         double cb = s->beta[e] / h * s->vol[e] * d;                   /* (1/h) B_beta q_t */
         double cp = (s->w[e] + s->beta[e] / h) * s->vol[e] * d;       /* A~ coupling to pinned */
+        if (s->mgroup && s->mgroup[e] >= 0) cp += s->w_m * s->vol[e] * s->mc[4 * e + a] * s->mc[4 * e + b];
         for (int ax = 0; ax < 3; ++ax) {
           c_all[3 * va + ax] += cb * q_t[3 * vb + ax];
           if (s->pinned[vb]) c_all[3 * va + ax] -= cp * s->X[3 * vb + ax];
@@ -2090,7 +2256,7 @@ static int step_backward_impl(const or_scene* s, const double* q_t, const double
     element_F(s, e, q_star_m1, Fa);
     element_F(s, e, q_star, Fb);
     double pa = or_psi_nh(Fa, s->mu[e], s->lam[e]), pb = or_psi_nh(Fb, s->mu[e], s->lam[e]);
-    pe[e] = s->vol[e] * (pa - pb);
+    pe[e] = s->vol[e] * (pa - pb) + (muscle_energy(s, e, Fa) - muscle_energy(s, e, Fb));
   }
   for (int e = 0; e < s->ne; ++e) dphi_act += pe[e];
   free(pe);
@@ -2293,6 +2459,22 @@ static int step_backward_impl(const or_scene* s, const double* q_t, const double
     element_contrib(s, e, s->beta[e] * s->vol[e], Gm, ctb + 12 * (size_t)e);
   }
   for (int e = 0; e < s->ne; ++e) g_logE[e] += ge[e];
+  /* dL/da_g = mu^T db/da_g = -sum_{e in g} w_m V_e <G_m mu, f^> at q* (element order) */
+  if (s->mgroup && s->g_act) {
+#pragma omp parallel for schedule(static)
+    for (int e = 0; e < s->ne; ++e) {
+      double Gm[9], F[9], f[3], nf, ell, y[3];
+      ge[e] = 0.0;
+      element_F(s, e, q_star, F);
+      if (!muscle_eval(s, e, F, f, &nf, &ell) || !(nf > 0.0)) continue;
+      element_F(s, e, mu, Gm);
+      const double* m = s->mfib + 3 * e;
+      for (int i = 0; i < 3; ++i) y[i] = Gm[3 * i] * m[0] + Gm[3 * i + 1] * m[1] + Gm[3 * i + 2] * m[2];
+      ge[e] = -s->w_m * s->vol[e] * (y[0] * f[0] + y[1] * f[1] + y[2] * f[2]) / nf;
+    }
+    for (int e = 0; e < s->ne; ++e)
+      if (s->mgroup[e] >= 0) s->g_act[s->mgroup[e]] += ge[e];
+  }
   scatter_contribs(s, ctb, Bmu);
   free(ge);
   free(ctb);

@@ -28,6 +28,12 @@ void or_scene_destroy(or_scene* s);
 void or_set_threads(int n);
 int or_get_threads(void);
 int or_scene_nfree(const or_scene* s);
+/* muscle fibres (actuation; reading in pd_oracle.c): per element a group (-1: passive) and a unit fibre
+ * (ne x 3, rest coordinates), fibre weight w_m; reassembles and refactors A~.  Activations a (n_groups)
+ * default to 0.  g (n_groups, caller-owned, may be NULL) accumulates dL/da over backward steps. */
+void or_scene_set_muscles(or_scene* s, int n_groups, double w_m, const int* group, const double* fibre);
+void or_scene_set_activation(or_scene* s, const double* a);
+void or_scene_set_act_grad(or_scene* s, double* g);
 /* per-element / per-vertex quantities after setup (any may be NULL) */
 void or_scene_info(const or_scene* s, double* vol, double* w, double* beta, double* mass, double* means4);
 

@@ -146,6 +146,12 @@ class Scene:
     energy: int = 0
     # Coulomb friction coefficient of the obstacles (0: frictionless contact)
     friction: float = 0.0
+    # muscle fibres: group per tet (-1 passive), unit fibre per tet (rest coordinates), fibre weight (Pa),
+    # and the groups' activations
+    muscle_group: Optional[np.ndarray] = None
+    muscle_fibre: Optional[np.ndarray] = None
+    muscle_w: float = 0.0
+    activation: Optional[np.ndarray] = None
 
     @property
     def n_v(self) -> int:
@@ -290,6 +296,43 @@ def beam_batch(n: int = 64, seed: int = 4000, steps: int = 50, ne_range=(1000, 3
         sc.name = f"batch_beam_{s}"
         out.append(sc)
     return out
+
+
+def tendon_beam(nxy: int = 4, nz: int = 16, layout: int = 0, n_seg: int = 4, seed: int = 6001, E: float = 1e5,
+                nu: float = 0.45, w_m: float = 3e5, h: float = 0.01, steps: int = 100, a_max: float = 0.3,
+                gravity=(0.0, 0.0, 0.0), aa_window: int = 1) -> Scene:
+    """Muscle-driven beam (the paper's tendon-routing scene in shape): a vertical beam of nxy x nxy x nz
+    cubes of 0.05 m along z, its base (z = 0) pinned, homogeneous Young's modulus E.  Every tet belongs to
+    one of 4 n_seg muscle groups: n_seg segments along z times the four quadrants of the cross-section
+    around the beam's axis.  Fibres (unit, rest coordinates): layout 0 along z; layout 1 tilted 30 degrees
+    from z toward the tangential direction around the axis (a helical routing through the same volume).
+    Activations are seeded uniform in [0, a_max]; the target is the rest tip position shifted sideways."""
+    edge = 0.05
+    X, tets = box_tet_mesh(nxy, nxy, nz, edge)
+    pinned = (np.abs(X[:, 2]) < 1e-12).astype(np.uint8)
+    cen = X[tets].mean(axis=1)
+    axis = np.array([0.5 * nxy * edge, 0.5 * nxy * edge])
+    rel = cen[:, :2] - axis
+    quad = (rel[:, 0] >= 0).astype(int) + 2 * (rel[:, 1] >= 0).astype(int)
+    seg = np.minimum((cen[:, 2] / (nz * edge) * n_seg).astype(int), n_seg - 1)
+    group = (seg * 4 + quad).astype(np.int32)
+    fib = np.zeros((tets.shape[0], 3))
+    if layout == 0:
+        fib[:, 2] = 1.0
+    else:
+        r = np.maximum(np.hypot(rel[:, 0], rel[:, 1]), 1e-12)
+        tang = np.stack([-rel[:, 1] / r, rel[:, 0] / r, np.zeros_like(r)], axis=1)
+        th = np.deg2rad(30.0)
+        fib = np.cos(th) * np.array([0.0, 0.0, 1.0]) + np.sin(th) * tang
+        fib /= np.linalg.norm(fib, axis=1, keepdims=True)
+    rng = _rng(seed)
+    act = rng.uniform(0.0, a_max, 4 * n_seg)
+    tip = X[:, 2] > nz * edge - 1e-9
+    target = X[tip].mean(axis=0) + np.array([0.1, 0.05, -0.05])
+    return Scene(f"tendon_beam_{nxy}x{nz}_l{layout}", X, tets, pinned, np.full(tets.shape[0], np.log(E)), nu=nu,
+                 rho=1000.0, alpha=0.01, beta0=0.0, h=h, gravity=np.asarray(gravity, float),
+                 aa_window=aa_window, steps=steps, force_fn=None, target_centroid=target,
+                 muscle_group=group, muscle_fibre=fib, muscle_w=w_m, activation=act)
 
 
 def shell_tets(tets: np.ndarray) -> np.ndarray:

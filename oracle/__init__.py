@@ -93,6 +93,13 @@ def lib():
                                                 _dp, ctypes.c_int, ctypes.c_double, ctypes.c_int, _ip, _dp, _dp,
                                                 ctypes.c_double, _dp, _ip, _dp]
         L.or_contact_frame.argtypes = [_dp, _dp, _dp]
+        L.or_step_forward_contact_ext.argtypes = [ctypes.c_void_p, _dp, _dp, _dp, _dp, _dp, _dp, _dp, ctypes.c_int,
+                                                  _ip, _dp, _dp, ctypes.c_char_p, ctypes.c_int, ctypes.c_double,
+                                                  ctypes.c_double, ctypes.c_double, _dp, ctypes.c_int, _ip, _dp]
+        L.or_step_backward_contact_ext.argtypes = [ctypes.c_void_p, _dp, _dp, _dp, _dp, _dp, _dp, _dp, _dp, _dp,
+                                                   _dp, _dp, ctypes.c_int, ctypes.c_double, ctypes.c_int, _ip, _dp,
+                                                   _dp, ctypes.c_char_p, ctypes.c_int, ctypes.c_double,
+                                                   ctypes.c_double, _dp, _dp, _ip, _dp]
         L.or_friction_ncp.argtypes = [ctypes.c_int, _dp, _dp, _dp, ctypes.c_double, _dp, _dp]
         _lib = L
     return _lib
@@ -607,3 +614,115 @@ def rollout_backward(osc: OracleScene, ckpts, gq_T, gv_T, adj_mode=0, tau_force=
         gq, gv, _gf, gl, st = osc.step_backward(q_t, v_t, f, qs, qsm1, gq, gv, gl, adj_mode, tau_force)
         stats.append(st)
     return gq, gv, gl, stats[::-1]
+
+
+# ---------------------------------------------------------------- bilateral rows and restitution
+def attachment_rows(verts, targets):
+    """Bilateral rows pinning each vertex to its target point: three rows per vertex along x, y, z with
+    offsets the target's coordinates (kind 1).  Returns (cv, cn, cg, kind)."""
+    verts = np.asarray(verts, dtype=np.int32)
+    targets = np.asarray(targets, float).reshape(-1, 3)
+    cv = np.repeat(verts, 3).astype(np.int32)
+    cn = np.tile(np.eye(3), (len(verts), 1))
+    cg = targets.reshape(-1).copy()
+    return cv, cn, cg, np.ones(cv.shape[0], dtype=np.uint8)
+
+
+def join_rows(con, att):
+    """Detected unilateral rows (cv, cn, cg) followed by bilateral rows (cv, cn, cg, kind)."""
+    cv = np.concatenate([con[0], att[0]]).astype(np.int32)
+    cn = np.concatenate([np.asarray(con[1]).reshape(-1, 3), att[1]])
+    cg = np.concatenate([con[2], att[2]])
+    kind = np.concatenate([np.zeros(len(con[0]), np.uint8), att[3]])
+    return cv, cn, cg, kind
+
+
+def step_forward_contact_ext(osc, q_t, v_t, f_ext, rows, restitution=None, mu_f=0.0, fb_tol=1e-10, force_iters=0,
+                             q0=None):
+    """One forward step with rows (cv, cn, cg, kind), the restitution post-correction (coefficient or None)
+    and friction mu_f; returns q, v, q*_-1, impulses (K, or (K, 3) with friction) and stats."""
+    cv, cn, cg, kind = rows
+    cv = np.ascontiguousarray(cv, dtype=np.int32)
+    cn, cg = _f(cn), _f(cg)
+    kind = np.ascontiguousarray(kind, dtype=np.uint8)
+    q_t, v_t = _f(q_t), _f(v_t)
+    K = cv.shape[0]
+    qn, vn, qm1 = np.zeros_like(q_t), np.zeros_like(q_t), np.zeros_like(q_t)
+    w = 3 if mu_f > 0.0 else 1
+    lam = np.zeros(max(K, 1) * w)
+    ist = np.zeros(5, dtype=np.int32)
+    dst = np.zeros(6)
+    lib().or_step_forward_contact_ext(osc.ptr, _p(q_t), _p(v_t), _p(_f(f_ext)) if f_ext is not None else None,
+                                      _p(_f(q0)) if q0 is not None else None, _p(qn), _p(vn), _p(qm1), K,
+                                      cv.ctypes.data_as(_ip), _p(cn), _p(cg),
+                                      kind.ctypes.data_as(ctypes.c_char_p) if K else None,
+                                      int(restitution is not None), float(restitution or 0.0), float(mu_f),
+                                      float(fb_tol), _p(lam), int(force_iters), ist.ctypes.data_as(_ip), _p(dst))
+    st = dict(iters=int(ist[0]), resets=int(ist[1]), newton_capped=int(ist[2]), newton_max=int(ist[3]),
+              status=int(ist[4]), gate=dst[:4].copy(), fb_res=float(dst[4]), n_contacts=K)
+    lam = lam[:K * w].reshape(K, 3) if w == 3 else lam[:K].copy()
+    return qn, vn, qm1, lam, st
+
+
+def step_backward_contact_ext(osc, q_t, v_t, f_ext, q_star, q_star_m1, gq_next, gv_next, rows, lam,
+                              restitution=None, mu_f=0.0, g_logE=None, adj_mode=0, tau_force=-1.0):
+    """Backward of step_forward_contact_ext; also returns dL/dg per row (frictionless; zero off the active
+    set)."""
+    cv, cn, cg, kind = rows
+    cv = np.ascontiguousarray(cv, dtype=np.int32)
+    cn, cg = _f(cn), _f(cg)
+    kind = np.ascontiguousarray(kind, dtype=np.uint8)
+    K = cv.shape[0]
+    q_t, v_t = _f(q_t), _f(v_t)
+    gq, gv, gf = np.zeros_like(q_t), np.zeros_like(q_t), np.zeros_like(q_t)
+    gl = np.zeros(osc.ne) if g_logE is None else g_logE
+    gg = np.zeros(max(K, 1))
+    ist = np.zeros(2, dtype=np.int32)
+    dst = np.zeros(4)
+    lam = _f(np.asarray(lam).reshape(-1) if K else np.zeros(3))
+    lib().or_step_backward_contact_ext(osc.ptr, _p(q_t), _p(v_t), _p(_f(f_ext)) if f_ext is not None else None,
+                                       _p(_f(q_star)), _p(_f(q_star_m1)), _p(_f(gq_next)), _p(_f(gv_next)), _p(gq),
+                                       _p(gv), _p(gf), _p(gl), int(adj_mode), float(tau_force), K,
+                                       cv.ctypes.data_as(_ip), _p(cn), _p(cg),
+                                       kind.ctypes.data_as(ctypes.c_char_p) if K else None,
+                                       int(restitution is not None), float(restitution or 0.0), float(mu_f), _p(lam),
+                                       _p(gg), ist.ctypes.data_as(_ip), _p(dst))
+    st = dict(adj_iters=int(ist[0]), status=int(ist[1]), rho=dst[0], tau=dst[1], dphi_act=dst[2],
+              dphi_mod=dst[3])
+    return gq, gv, gf, gl, gg[:K].copy(), st
+
+
+def rollout_contact_ext(osc: OracleScene, steps: int, attach=None, restitution=None, mu_f=0.0, fb_tol=1e-10,
+                        q0=None, v0=None):
+    """Forward rollout with per-step detection against the scene's obstacles (if any), bilateral attachment
+    rows appended (attach = (verts, targets(t)) or None) and the restitution post-correction."""
+    sc = osc.sc
+    q = sc.q0() if q0 is None else q0.copy()
+    v = sc.v0() if v0 is None else v0.copy()
+    ckpts, stats = [], []
+    empty = (np.zeros(0, np.int32), np.zeros((0, 3)), np.zeros(0))
+    for t in range(steps):
+        f = sc.f_ext(t)
+        con = detect_contacts(q, v, sc.h, sc.pinned, sc.obstacles, one_per_vertex=mu_f > 0.0) \
+            if sc.obstacles else empty
+        att = attachment_rows(attach[0], attach[1](t)) if attach is not None else \
+            (np.zeros(0, np.int32), np.zeros((0, 3)), np.zeros(0), np.zeros(0, np.uint8))
+        rows = join_rows(con, att)
+        qn, vn, qm1, lam, st = step_forward_contact_ext(osc, q, v, f, rows, restitution, mu_f, fb_tol)
+        ckpts.append((q.copy(), v.copy(), f.copy(), qn.copy(), qm1.copy(), rows, lam))
+        stats.append(st)
+        q, v = qn, vn
+    return q, v, ckpts, stats
+
+
+def rollout_backward_contact_ext(osc: OracleScene, ckpts, gq_T, gv_T, restitution=None, mu_f=0.0, adj_mode=0):
+    """Reverse sweep of rollout_contact_ext; returns dL/dq0, dL/dv0, dL/dlogE, per-step dL/dg and stats."""
+    gq, gv = gq_T.copy(), gv_T.copy()
+    gl = np.zeros(osc.ne)
+    ggs, stats = [], []
+    for (q_t, v_t, f, qs, qsm1, rows, lam) in reversed(ckpts):
+        gq, gv, _gf, gl, gg, st = step_backward_contact_ext(osc, q_t, v_t, f, qs, qsm1, gq, gv, rows, lam,
+                                                            restitution, mu_f, gl, adj_mode)
+        ggs.append(gg)
+        stats.append(st)
+    return gq, gv, gl, ggs[::-1], stats[::-1]

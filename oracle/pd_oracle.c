@@ -1413,7 +1413,53 @@ typedef struct or_contacts {
   const double* qt;
   double* e;
   double* G;
+  /* bilateral rows (kind[c] = 1; NULL: every row unilateral) and the
+   * restitution post-correction (rest_on, coefficient e_rest); backward: the
+   * gradient of the loss w.r.t. each row's offset g_c (NULL: not formed) */
+  const unsigned char* kind;
+  int rest_on;
+  double e_rest;
+  double* g_gap;
 } or_contacts;
+
+/* READING (bilateral attachments, Sec. 4.7: the block projection leaves the
+ * bilateral multipliers unconstrained): a bilateral row is the equality
+ * n_c . q_{v_c} = g_c with a free multiplier; in the FB Newton its residual
+ * is the gap itself (phi = delta, omega = 1, E = 0), it is always in the
+ * Newton system and never projected, and the adjoint holds it as an
+ * equality like an active unilateral row.  A full attachment of a vertex to a
+ * point is three rows along the coordinate axes. */
+static int row_bilateral(const or_contacts* con, int c) { return con->kind && con->kind[c] == 1; }
+
+/* normal impulse of row c */
+static double row_lam_n(const or_contacts* con, int c) { return con->mu_f > 0.0 ? con->lambda[3 * c] : con->lambda[c]; }
+
+/* active rows of a converged step: every bilateral row, and the unilateral
+ * rows whose normal impulse exceeds 1e-10 of the largest unilateral one */
+static int row_active(const or_contacts* con, int c) {
+  if (row_bilateral(con, c)) return 1;
+  double lmax = 0.0;
+  for (int d = 0; d < con->K; ++d)
+    if (!row_bilateral(con, d) && row_lam_n(con, d) > lmax) lmax = row_lam_n(con, d);
+  return lmax > 0.0 && row_lam_n(con, c) > 1e-10 * lmax;
+}
+
+/* READING (restitution; the paper states only that its velocity-level
+ * post-correction fires while the normal velocity is negative and the
+ * impulse positive): after the step, each active unilateral row c in row
+ * order whose incoming normal velocity u = n_c . v_{t, v_c} is negative sets
+ * the outgoing normal velocity of its vertex to -e u:
+ * v <- v + n_c (-e u - n_c . v).  Positions are unchanged. */
+static int restitution_rows(const or_contacts* con, const double* v_t, int* rows) {
+  int n = 0;
+  for (int c = 0; c < con->K; ++c) {
+    if (row_bilateral(con, c) || !row_active(con, c)) continue;
+    const double* nc = con->n + 3 * c;
+    const double* v = v_t + 3 * con->v[c];
+    if (nc[0] * v[0] + nc[1] * v[1] + nc[2] * v[2] < 0.0) rows[n++] = c;
+  }
+  return n;
+}
 
 static int chol_solve(double* A, int n, double* b) { /* SPD, in place (lower), returns 0 if not PD */
   for (int j = 0; j < n; ++j) {
@@ -1716,6 +1762,13 @@ static double fb_eval(const or_contacts* con, const double* dfree, const double*
   for (int c = 0; c < K; ++c) {
     double delta = dfree[c];
     for (int d = 0; d < K; ++d) delta += con->W[(size_t)c * K + d] * lam[d];
+    if (row_bilateral(con, c)) { /* equality row: the gap is the residual */
+      phi[c] = delta;
+      om[c] = 1.0;
+      E[c] = 0.0;
+      if (fabs(delta) > res) res = fabs(delta);
+      continue;
+    }
     double r = con->W[(size_t)c * K + c], a = delta, bb = r * lam[c];
     double sq = sqrt(a * a + bb * bb);
     if (sq == 0.0) {
@@ -1756,7 +1809,7 @@ static void fb_newton(or_contacts* con, const double* dfree) {
     if (na > 0 && !chol_solve(M, na, rhs)) break;
     for (int i = 0; i < na; ++i) {
       double l = con->lambda[act[i]] + rhs[i];
-      con->lambda[act[i]] = l > 0.0 ? l : 0.0;
+      con->lambda[act[i]] = (l > 0.0 || row_bilateral(con, act[i])) ? l : 0.0;
     }
     res = fb_eval(con, dfree, con->lambda, phi, om, E);
   }
@@ -1913,6 +1966,20 @@ static int step_forward_impl(const or_scene* s, const double* q_t, const double*
     v_next[i] = (q[i] - q_t[i]) / s->h;
     if (q_star_m1) q_star_m1[i] = qprev[i];
   }
+  if (con && con->rest_on && con->K > 0) { /* restitution post-correction (reading at restitution_rows) */
+    int* rows = (int*)malloc(sizeof(int) * con->K);
+    int nr = restitution_rows(con, v_t, rows);
+    for (int r = 0; r < nr; ++r) {
+      int c = rows[r], vx = con->v[c];
+      const double* nc = con->n + 3 * c;
+      double* v = v_next + 3 * vx;
+      const double* vi = v_t + 3 * vx;
+      double u = nc[0] * vi[0] + nc[1] * vi[1] + nc[2] * vi[2];
+      double vn = nc[0] * v[0] + nc[1] * v[1] + nc[2] * v[2];
+      for (int ax = 0; ax < 3; ++ax) v[ax] += nc[ax] * (-con->e_rest * u - vn);
+    }
+    free(rows);
+  }
   if (istats) { istats[0] = k; istats[1] = resets; istats[2] = capped; istats[3] = maxit; istats[4] = status; }
   if (dstats) for (int i = 0; i < 4; ++i) dstats[i] = gate[i];
   if (con) contact_free(con);
@@ -1943,6 +2010,22 @@ int or_step_forward_friction(const or_scene* s, const double* q_t, const double*
                              const int* cv, const double* cn, const double* cg, double mu_f, double fb_tol,
                              double* lambda3, int force_iters, int* istats, double* dstats) {
   or_contacts con = {K, cv, cn, cg, fb_tol, lambda3, NULL, NULL, 0.0, 0, mu_f, q_t, NULL, NULL};
+  int st = step_forward_impl(s, q_t, v_t, f_ext, q0, q_next, v_next, q_star_m1, force_iters, -1, 0, NULL, istats,
+                             dstats, K > 0 ? &con : NULL);
+  if (dstats) { dstats[4] = con.fb_res; dstats[5] = con.fb_iters; }
+  return st;
+}
+
+/* The contact step with bilateral rows and restitution: kind (K, 1 =
+ * bilateral, may be NULL), rest_on / e_rest, friction mu_f (0: frictionless;
+ * bilateral rows need mu_f = 0), impulses lambda (K, or 3K with friction). */
+int or_step_forward_contact_ext(const or_scene* s, const double* q_t, const double* v_t, const double* f_ext,
+                                const double* q0, double* q_next, double* v_next, double* q_star_m1, int K,
+                                const int* cv, const double* cn, const double* cg, const unsigned char* kind,
+                                int rest_on, double e_rest, double mu_f, double fb_tol, double* lambda,
+                                int force_iters, int* istats, double* dstats) {
+  or_contacts con = {K, cv, cn, cg, fb_tol, lambda, NULL, NULL, 0.0, 0, mu_f, q_t, NULL, NULL,
+                     kind, rest_on, e_rest, NULL};
   int st = step_forward_impl(s, q_t, v_t, f_ext, q0, q_next, v_next, q_star_m1, force_iters, -1, 0, NULL, istats,
                              dstats, K > 0 ? &con : NULL);
   if (dstats) { dstats[4] = con.fb_res; dstats[5] = con.fb_iters; }
@@ -2231,11 +2314,32 @@ static int step_backward_impl(const or_scene* s, const double* q_t, const double
   double* c = (double*)malloc(sizeof(double) * n3);
   double* dq = (double*)malloc(sizeof(double) * n3);
   double* Adq = (double*)malloc(sizeof(double) * n3);
+  /* the restitution post-correction's adjoint, rows in reverse order: the
+   * raw velocity (q* - q_t)/h keeps (I - n n^T) of the incoming v^bar and
+   * v_t receives -e n (n . v^bar) */
+  double* vbar = (double*)malloc(sizeof(double) * n3);
+  double* gvt_rest = (double*)calloc(n3, sizeof(double));
+  memcpy(vbar, gv_next, sizeof(double) * n3);
+  if (con && con->rest_on && con->K > 0) {
+    int* rows = (int*)malloc(sizeof(int) * con->K);
+    int nr = restitution_rows(con, v_t, rows);
+    for (int r = nr - 1; r >= 0; --r) {
+      int c = rows[r], vx = con->v[c];
+      const double* nc = con->n + 3 * c;
+      double* vb = vbar + 3 * vx;
+      double d = nc[0] * vb[0] + nc[1] * vb[1] + nc[2] * vb[2];
+      for (int ax = 0; ax < 3; ++ax) {
+        gvt_rest[3 * vx + ax] += -con->e_rest * nc[ax] * d;
+        vb[ax] -= nc[ax] * d;
+      }
+    }
+    free(rows);
+  }
   /* q^bar = q^bar_{t+h} + v^bar_{t+h} / h on free vertices (Alg. 2) */
   for (int v = 0; v < nv; ++v)
     for (int ax = 0; ax < 3; ++ax) {
       int i = 3 * v + ax;
-      qbar[i] = s->fidx[v] >= 0 ? gq_next[i] + gv_next[i] / h : 0.0;
+      qbar[i] = s->fidx[v] >= 0 ? gq_next[i] + vbar[i] / h : 0.0;
     }
   or_const_rhs(s, q_t, v_t, f_ext, c, qtilde);
   /* trust-region ratio on the last fixed-point increment, Eqs. tr_step,
@@ -2288,12 +2392,11 @@ static int step_backward_impl(const or_scene* s, const double* q_t, const double
     status = fr_adjoint(s, con, kst, qbar, q_star, q_t, adj_mode, mu, gqt_fr, &iters);
   } else if (con && con->K > 0) {
     contact_setup(s, con);
-    double lmax = 0.0;
-    for (int c = 0; c < con->K; ++c) lmax = con->lambda[c] > lmax ? con->lambda[c] : lmax;
     act = (int*)malloc(sizeof(int) * con->K);
     for (int c = 0; c < con->K; ++c)
-      if (lmax > 0.0 && con->lambda[c] > 1e-10 * lmax) act[na++] = c;
+      if (row_active(con, c)) act[na++] = c;
     WA = (double*)malloc(sizeof(double) * (size_t)(na > 0 ? na : 1) * (na > 0 ? na : 1));
+    if (con->g_gap) for (int c = 0; c < con->K; ++c) con->g_gap[c] = 0.0;
   }
   if (gqt_fr) {
     /* solved above */
@@ -2328,6 +2431,8 @@ static int step_backward_impl(const or_scene* s, const double* q_t, const double
     for (int i = 0; i < 3 * nf; ++i) rhs[i] = qbar[3 * s->fvert[i / 3] + i % 3];
     if (!dense_lu_solve(Mat, N, rhs)) status = -1;
     for (int i = 0; i < 3 * nf; ++i) mu[3 * s->fvert[i / 3] + i % 3] = rhs[i];
+    /* dL/dg_c = -nu_c: the constraint n.q = g enters as J dq = dg */
+    if (con->g_gap) for (int a = 0; a < na; ++a) con->g_gap[act[a]] = -rhs[3 * nf + a];
     free(Mat); free(col); free(Ac); free(Kc); free(rhs);
   } else if (na > 0) {
     /* projected fixed point mu <- P (q^bar + K mu), P = A^-1 - A^-1 J_A^T W_AA^-1 J_A A^-1 */
@@ -2360,6 +2465,8 @@ static int step_backward_impl(const or_scene* s, const double* q_t, const double
         nrm += mun[i] * mun[i];
       }
       memcpy(mu, mun, sizeof(double) * n3);
+      /* the multipliers of the projection are -nu: dL/dg = u */
+      if (con->g_gap) for (int a = 0; a < na; ++a) con->g_gap[act[a]] = u[a];
       if (sqrt(d) <= s->eps_adj * sqrt(nrm)) { status = 0; break; }
     }
     if (iters > s->kmax_bwd) iters = s->kmax_bwd;
@@ -2483,15 +2590,15 @@ static int step_backward_impl(const or_scene* s, const double* q_t, const double
       int i = 3 * v + ax;
       if (s->fidx[v] < 0) { gq_t[i] = 0; gv_t[i] = 0; gf_ext[i] = 0; continue; }
       double m = s->mass[v];
-      gq_t[i] = (m / (h * h) + s->alpha * m / h) * mu[i] + Bmu[i] / h - gv_next[i] / h;
+      gq_t[i] = (m / (h * h) + s->alpha * m / h) * mu[i] + Bmu[i] / h - vbar[i] / h;
       if (gqt_fr) gq_t[i] += gqt_fr[i];
-      gv_t[i] = m / h * mu[i];
+      gv_t[i] = m / h * mu[i] + gvt_rest[i];
       gf_ext[i] = mu[i];
     }
   if (istats) { istats[0] = iters; istats[1] = status; }
   if (dstats) { dstats[0] = rho; dstats[1] = tau; dstats[2] = dphi_act; dstats[3] = dphi_mod; }
   if (con && con->K > 0) contact_free(con);
-  free(act); free(WA); free(gqt_fr);
+  free(act); free(WA); free(gqt_fr); free(vbar); free(gvt_rest);
   free(qbar); free(qtilde); free(c); free(dq); free(Adq); free(mu); free(Bmu); free(kst);
   return status;
 }
@@ -2526,6 +2633,25 @@ int or_step_backward_friction(const or_scene* s, const double* q_t, const double
   double* lam = (double*)malloc(sizeof(double) * 3 * (size_t)(K > 0 ? K : 1));
   for (int c = 0; c < 3 * K; ++c) lam[c] = lambda3[c];
   or_contacts con = {K, cv, cn, cg, 0.0, lam, NULL, NULL, 0.0, 0, mu_f, q_t, NULL, NULL};
+  int st = step_backward_impl(s, q_t, v_t, f_ext, q_star, q_star_m1, gq_next, gv_next, gq_t, gv_t, gf_ext, g_logE,
+                              adj_mode, tau_force, istats, dstats, K > 0 ? &con : NULL);
+  free(lam);
+  return st;
+}
+
+/* The backward of or_step_forward_contact_ext; g_gap (K, may be NULL; frictionless only) receives dL/dg_c
+ * of each active row (0 for the others). */
+int or_step_backward_contact_ext(const or_scene* s, const double* q_t, const double* v_t, const double* f_ext,
+                                 const double* q_star, const double* q_star_m1, const double* gq_next,
+                                 const double* gv_next, double* gq_t, double* gv_t, double* gf_ext, double* g_logE,
+                                 int adj_mode, double tau_force, int K, const int* cv, const double* cn,
+                                 const double* cg, const unsigned char* kind, int rest_on, double e_rest,
+                                 double mu_f, const double* lambda, double* g_gap, int* istats, double* dstats) {
+  size_t nl = (size_t)(mu_f > 0.0 ? 3 : 1) * (K > 0 ? K : 1);
+  double* lam = (double*)malloc(sizeof(double) * nl);
+  for (size_t c = 0; c < (size_t)(mu_f > 0.0 ? 3 : 1) * K; ++c) lam[c] = lambda[c];
+  or_contacts con = {K, cv, cn, cg, 0.0, lam, NULL, NULL, 0.0, 0, mu_f, q_t, NULL, NULL,
+                     kind, rest_on, e_rest, mu_f > 0.0 ? NULL : g_gap};
   int st = step_backward_impl(s, q_t, v_t, f_ext, q_star, q_star_m1, gq_next, gv_next, gq_t, gv_t, gf_ext, g_logE,
                               adj_mode, tau_force, istats, dstats, K > 0 ? &con : NULL);
   free(lam);

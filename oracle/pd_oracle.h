@@ -116,6 +116,20 @@ int or_step_backward_friction(const or_scene* s, const double* q_t, const double
                               const double* gv_next, double* gq_t, double* gv_t, double* gf_ext, double* g_logE,
                               int adj_mode, double tau_force, int K, const int* cv, const double* cn,
                               const double* cg, double mu_f, const double* lambda3, int* istats, double* dstats);
+/* Bilateral rows and restitution (readings in pd_oracle.c): kind (K, 1 = bilateral equality row, NULL: all
+ * unilateral), rest_on with coefficient e_rest, mu_f (0: frictionless; bilateral rows need mu_f = 0);
+ * lambda has K (or 3K with friction) entries.  The backward's g_gap (K, frictionless) receives dL/dg_c. */
+int or_step_forward_contact_ext(const or_scene* s, const double* q_t, const double* v_t, const double* f_ext,
+                                const double* q0, double* q_next, double* v_next, double* q_star_m1, int K,
+                                const int* cv, const double* cn, const double* cg, const unsigned char* kind,
+                                int rest_on, double e_rest, double mu_f, double fb_tol, double* lambda,
+                                int force_iters, int* istats, double* dstats);
+int or_step_backward_contact_ext(const or_scene* s, const double* q_t, const double* v_t, const double* f_ext,
+                                 const double* q_star, const double* q_star_m1, const double* gq_next,
+                                 const double* gv_next, double* gq_t, double* gv_t, double* gf_ext, double* g_logE,
+                                 int adj_mode, double tau_force, int K, const int* cv, const double* cn,
+                                 const double* cg, const unsigned char* kind, int rest_on, double e_rest,
+                                 double mu_f, const double* lambda, double* g_gap, int* istats, double* dstats);
 /* the contact frame of a unit normal */
 void or_contact_frame(const double n[3], double t1[3], double t2[3]);
 /* the friction Newton alone: G (K x K block of A~^{-1}), normals (K x 3), free kinematics u0 (3K: gap and

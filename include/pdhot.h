@@ -179,6 +179,36 @@ int pd_scene_set_material(pd_scene* scene, const double* log_E_host);
  * value, PD_ERR_HIP if the copy fails). */
 int pd_scene_set_material_device(pd_scene* scene, const double* log_E_dev, void* stream);
 
+/* Muscle actuation (the paper's muscle-driven scenes, Sec. 5, whose inverse
+ * problems route through db/da; the paper prints no muscle energy, so the
+ * reading is stated here).  A muscle tet e of group g carries the fibre
+ * constraint (w_m V_e / 2) dist^2(F_e m_e, S_l), S_l the sphere of radius
+ * l = 1 - a_g in fibre space: the local step projects f = F_e m_e to
+ * p = l f/|f|, A~ gains w_m V_e G_m^T G_m (G_m q = f; it acts per axis like the
+ * rest of A~), b gains w_m V_e G_m^T p, K gains w_m V_e G_m^T (l/|f|)(I - f^ f^T)
+ * G_m, and dL/da_g = -sum_{e in g} w_m V_e <G_m mu, f^> at q*.
+ * group: host, n_tets int32 in the caller's tet order, -1 for a passive tet,
+ * else 0 .. n_groups - 1; fibre: host, n_tets x 3 unit vectors (|m|^2 within
+ * 1e-9 of 1) in rest coordinates; w_m > 0 in Pa.  n_groups = 0 removes the
+ * muscles.  Activations start at 0.  Marks the factor stale (A~ changes);
+ * waits for all device work first.  Batches reject scenes with muscles.
+ * Errors: PD_ERR_INVALID_ARG for a null array, a group out of range, a
+ * non-unit fibre or w_m <= 0. */
+int pd_scene_set_muscles(pd_scene* scene, int n_groups, double w_m, const int32_t* group, const double* fibre);
+
+/* The groups' activations a (device, n_groups doubles), copied on `stream`
+ * (stream-ordered with the steps).  They change b only, not A~, so no
+ * refactorization is needed; a backward step uses the activations current
+ * at its call, so keep them unchanged between a forward step and its
+ * backward step.  Errors: PD_ERR_INVALID_ARG for a scene without muscles. */
+int pd_scene_set_activation(pd_scene* scene, const double* a_dev, void* stream);
+
+/* Register the caller's device buffer of n_groups doubles into which every
+ * pd_step_backward ADDS dL/da (summed per group in a fixed order, no
+ * atomics); NULL stops forming it.  The buffer stays caller-owned; clear it
+ * before a sweep.  Setting muscles unregisters it. */
+int pd_scene_set_activation_grad(pd_scene* scene, double* g_act_dev);
+
 /* Hold the mesh means of the local prox and of Rayleigh damping fixed across
  * refactorizations.  The means mu_bar, lam_bar (Sec. 4.2) and mu_ref (Sec. 4.5
  * Eq. rayleigh) are constants of the gradient (the paper's gradient formulas
@@ -277,6 +307,42 @@ int pd_scene_set_obstacles(pd_scene* scene, int n_planes, const double* planes, 
                            double d_c, int max_contacts, double fb_tol);
 int pd_contact_rows(const pd_scene* scene, int* K, int32_t* vert, double* normals, double* offsets,
                     double* lambda, int capacity);
+
+/* Bilateral rows (Sec. 4.7: attachments held as constraints; the block
+ * projection leaves their multipliers free).  Row c is the equality
+ * n_c . q_{v_c} = g_c with vertex vert[c] (caller order, not pinned), unit
+ * direction normals[3c..3c+2] and offset offsets[c] (host arrays, copied); a
+ * full attachment of a vertex to a point is three rows along x, y, z.  The
+ * rows follow each step's detected contact rows (same Delassus operator and
+ * column cache): in the FB Newton their residual is the gap (omega = 1,
+ * E = 0) and they are never projected; the adjoint holds them as equalities.
+ * Calling it again replaces the rows (offsets may change between steps: a
+ * moving handle); n_rows = 0 removes them.  Without obstacles the contact
+ * machinery is set up with room for max(64, n_rows) rows.  Frictionless
+ * contact only.  Waits for all device work.  Errors: PD_ERR_INVALID_ARG for
+ * a pinned or out-of-range vertex, a non-unit direction, more rows than the
+ * obstacles' max_contacts, or a friction coefficient set. */
+int pd_scene_set_attachments(pd_scene* scene, int n_rows, const int32_t* vert, const double* normals,
+                             const double* offsets);
+
+/* Restitution post-correction (the paper's velocity-level correction, which
+ * fires while the normal velocity is negative and the impulse positive; the
+ * reading): after each forward step, every active unilateral row (impulse
+ * above 1e-10 of the largest) whose vertex approached (u = n . v_t < 0) sets
+ * the vertex's outgoing normal velocity to -e u, rows of one vertex in order;
+ * positions are unchanged.  The checkpoint records the corrected rows and e,
+ * and the backward step applies the correction's adjoint.  e >= 0 turns it
+ * on, e < 0 off (the default). */
+int pd_scene_set_restitution(pd_scene* scene, double e);
+
+/* The gradient of the loss w.r.t. the offsets g_c of the rows of the last
+ * backward step's checkpoint (detected rows, then bilateral rows, as
+ * pd_contact_rows lists them for that forward step): dL/dg =
+ * W_AA^{-1} J_A A~^{-1} (q bar + K mu) on the active rows, 0 on the others.
+ * Host output of at least that many doubles.  Frictionless rows only; it
+ * waits for all device work.  Errors: PD_ERR_INVALID_ARG without contact, with
+ * friction, or for a capacity below the row count. */
+int pd_contact_gap_grad(pd_scene* scene, double* g_out, int capacity);
 
 /* Coulomb friction on the obstacles (Sec. 4.7: the Signorini-Coulomb law
  * with the friction disk of radius mu lam_n; Sec. 4.8: its adjoint with the

@@ -32,7 +32,9 @@ EXPORTED = ["pd_scene_create", "pd_scene_destroy", "pd_scene_set_material", "pd_
             "pd_mpn_adam_step", "pd_batch_create", "pd_batch_destroy", "pd_batch_config", "pd_batch_step_forward",
             "pd_batch_step_backward", "pd_scene_set_obstacles", "pd_contact_rows", "pd_last_error",
             "pd_scene_factor_nnz", "pd_batch_kernel_timer", "pd_batch_kernel_timer_read",
-            "pd_scene_set_friction", "pd_contact_impulses", "pd_apply_Ainv_noalloc"]
+            "pd_scene_set_friction", "pd_contact_impulses", "pd_apply_Ainv_noalloc", "pd_scene_set_muscles",
+            "pd_scene_set_activation", "pd_scene_set_activation_grad", "pd_scene_set_attachments",
+            "pd_scene_set_restitution", "pd_contact_gap_grad"]
 
 
 class pd_mesh_desc(ctypes.Structure):
@@ -89,6 +91,12 @@ def lib() -> ctypes.CDLL:
     L.pd_scene_set_material.argtypes = [vp, vp]
     L.pd_scene_set_material_device.argtypes = [vp, vp, vp]
     L.pd_scene_freeze_means.argtypes = [vp, vp]
+    L.pd_scene_set_muscles.argtypes = [vp, i32, dbl, vp, vp]
+    L.pd_scene_set_activation.argtypes = [vp, vp, vp]
+    L.pd_scene_set_activation_grad.argtypes = [vp, vp]
+    L.pd_scene_set_attachments.argtypes = [vp, i32, vp, vp, vp]
+    L.pd_scene_set_restitution.argtypes = [vp, dbl]
+    L.pd_contact_gap_grad.argtypes = [vp, vp, i32]
     L.pd_scene_vertex_mass.argtypes = [vp, vp]
     L.pd_scene_factorize.argtypes = [vp, vp]
     L.pd_scene_info.argtypes = [vp, vp, vp]
@@ -190,7 +198,52 @@ class Scene:
             g.set_obstacles(sc.obstacles, **contact)
             if getattr(sc, "friction", 0.0) > 0.0:
                 g.set_friction(sc.friction)
+        if getattr(sc, "muscle_group", None) is not None:
+            import torch
+            g.set_muscles(sc.muscle_group, sc.muscle_fibre, sc.muscle_w)
+            g.factorize()
+            g.set_activation(torch.tensor(sc.activation, dtype=torch.float64, device="cuda"))
         return g
+
+    def set_muscles(self, group, fibre, w_m):
+        """Muscle fibres (pd_scene_set_muscles): group per tet (-1 passive), unit fibre per tet, weight w_m.
+        Marks the factor stale."""
+        self._mgroup = np.ascontiguousarray(group, dtype=np.int32)
+        self._mfib = np.ascontiguousarray(fibre, dtype=np.float64).reshape(-1, 3)
+        self.n_groups = int(self._mgroup.max()) + 1 if self._mgroup.size and self._mgroup.max() >= 0 else 0
+        check(lib().pd_scene_set_muscles(self.ptr, self.n_groups, float(w_m), self._mgroup.ctypes.data,
+                                         self._mfib.ctypes.data), "pd_scene_set_muscles")
+
+    def set_activation(self, a):
+        """The groups' activations from a float64 device tensor (copied on the current stream)."""
+        check(lib().pd_scene_set_activation(self.ptr, _ptr(a), _stream()), "pd_scene_set_activation")
+
+    def set_activation_grad(self, g):
+        """Device buffer (float64, n_groups) that every backward step adds dL/da into; None stops it."""
+        self._g_act = g
+        check(lib().pd_scene_set_activation_grad(self.ptr, _ptr(g) if g is not None else None),
+              "pd_scene_set_activation_grad")
+
+    def set_attachments(self, verts, normals, offsets):
+        """Bilateral rows n . q_v = g (pd_scene_set_attachments): caller vertex ids, unit directions, offsets."""
+        self._att = (np.ascontiguousarray(verts, dtype=np.int32),
+                     np.ascontiguousarray(normals, dtype=np.float64).reshape(-1, 3),
+                     np.ascontiguousarray(offsets, dtype=np.float64))
+        n = int(self._att[0].shape[0])
+        check(lib().pd_scene_set_attachments(self.ptr, n, self._att[0].ctypes.data if n else None,
+                                             self._att[1].ctypes.data if n else None,
+                                             self._att[2].ctypes.data if n else None), "pd_scene_set_attachments")
+
+    def set_restitution(self, e):
+        """Restitution coefficient of the contact rows (None or negative: off)."""
+        check(lib().pd_scene_set_restitution(self.ptr, -1.0 if e is None else float(e)), "pd_scene_set_restitution")
+
+    def contact_gap_grad(self, capacity=None):
+        """dL/dg of the last backward step's rows (pd_contact_gap_grad)."""
+        cap = int(capacity if capacity is not None else 4096)
+        out = np.zeros(max(cap, 1))
+        check(lib().pd_contact_gap_grad(self.ptr, out.ctypes.data, cap), "pd_contact_gap_grad")
+        return out
 
     def set_friction(self, mu):
         """Coulomb coefficient of the obstacles (pd_scene_set_friction; 0 = frictionless)."""

@@ -239,7 +239,11 @@ __device__ void fb_rows(const ContactArgs& C, const double* dfree, const double*
       const double r = Wr[c], a = delta, b = r * lam[c];
       const double sq = sqrt(a * a + b * b);
       double p, w, e;
-      if (sq == 0.0) {
+      if (C.kind && C.kind[c] == 1) {  // bilateral: the gap itself is the residual
+        p = delta;
+        w = 1.0;
+        e = 0.0;
+      } else if (sq == 0.0) {
         p = 0.0;
         w = 1.0 - 1.0 / sqrt(2.0);
         e = r * (1.0 - 1.0 / sqrt(2.0));
@@ -380,7 +384,7 @@ __global__ void __launch_bounds__(kContactThreads) k_contact_fb(VertArgs Vx, Con
       for (int a = tid; a < na; a += nt) {
         const int c = act[a];
         const double l = lam[c] + y[a];
-        lam[c] = l > 0.0 ? l : 0.0;
+        lam[c] = (l > 0.0 || (C.kind && C.kind[c] == 1)) ? l : 0.0;
       }
     }
     __syncthreads();
@@ -417,6 +421,7 @@ __global__ void __launch_bounds__(64) k_contact_fb_wave(VertArgs Vx, ContactArgs
   const bool row = lane < K;
   int flag = done ? *done : 0;
   double q0 = 0, q1 = 0, q2 = 0, n0 = 0, n1 = 0, n2 = 0, g = 0, lam = 0;
+  const bool bil = row && C.kind && C.kind[lane] == 1;  // bilateral row
   if (row) {
     const int v = C.v[lane];
     q0 = qhat[v];
@@ -448,7 +453,11 @@ __global__ void __launch_bounds__(64) k_contact_fb_wave(VertArgs Vx, ContactArgs
     if (row) {
       const double r = Wr[lane], a = delta, b = r * lam;
       const double sq = sqrt(a * a + b * b);
-      if (sq == 0.0) {
+      if (bil) {
+        phi = delta;
+        om = 1.0;
+        E = 0.0;
+      } else if (sq == 0.0) {
         phi = 0.0;
         om = 1.0 - 1.0 / sqrt(2.0);
         E = r * (1.0 - 1.0 / sqrt(2.0));
@@ -540,7 +549,7 @@ __global__ void __launch_bounds__(64) k_contact_fb_wave(VertArgs Vx, ContactArgs
     const double dl = __shfl(y, pos < 0 ? 0 : pos, 64);
     if (a_on) {
       const double l = lam + dl;
-      lam = l > 0.0 ? l : 0.0;
+      lam = (l > 0.0 || bil) ? l : 0.0;
     }
     __syncthreads();
     res = evaluate();
@@ -637,10 +646,16 @@ __global__ void __launch_bounds__(256) k_contact_proj(VertArgs Vx, ContactArgs C
 }
 
 // checkpoint record of the step's rows: K, then v (as doubles), n (3 each),
-// g and lam, each block kmax long
-__global__ void __launch_bounds__(kBlock) k_contact_ckpt(ContactArgs C, int kmax, double* __restrict__ rec) {
+// g, lam (with friction the tangential impulses, 2 each), the row kinds and
+// the restitution flags, each block kmax long, then the restitution
+// coefficient (negative: off)
+__global__ void __launch_bounds__(kBlock) k_contact_ckpt(ContactArgs C, int kmax, double e_rest,
+                                                          double* __restrict__ rec) {
   const int c = blockIdx.x * blockDim.x + threadIdx.x;
-  if (c == 0) rec[0] = (double)C.K;
+  if (c == 0) {
+    rec[0] = (double)C.K;
+    rec[1 + 10 * kmax] = e_rest;
+  }
   if (c >= C.K) return;
   rec[1 + c] = (double)C.v[c];
   rec[1 + kmax + 3 * c] = C.n[3 * c];
@@ -653,6 +668,105 @@ __global__ void __launch_bounds__(kBlock) k_contact_ckpt(ContactArgs C, int kmax
     rec[1 + 6 * kmax + 2 * c + 1] = C.lam[3 * c + 2];
   } else {
     rec[1 + 5 * kmax + c] = C.lam[c];
+  }
+  rec[1 + 8 * kmax + c] = (C.kind && C.kind[c] == 1) ? 1.0 : 0.0;
+  rec[1 + 9 * kmax + c] = 0.0;  // restitution flag, set by the restitution kernel
+}
+
+// ---------------------------------------------------------------- restitution
+// Active unilateral rows (normal impulse above 1e-10 of the largest
+// unilateral one) whose vertex approached (u = n . v_t < 0) set the vertex's
+// outgoing normal velocity to -e u: v <- v + n (-e u - n . v).  Rows of one
+// vertex are contiguous (detection order); the first row of each run applies
+// them in order.  One workgroup; K <= kMaxContactRows.
+__global__ void __launch_bounds__(kContactThreads) k_contact_restitution(VertArgs Vx, ContactArgs C,
+                                                                         const double* __restrict__ v_t,
+                                                                         double* __restrict__ v_next, double e,
+                                                                         double* __restrict__ rec, int kmax) {
+  __shared__ double red[16];
+  const int tid = threadIdx.x, lane = tid & 63, wid = tid >> 6, K = C.K;
+  const int stride = C.mu > 0.0 ? 3 : 1;
+  double m = 0.0;
+  for (int c = tid; c < K; c += blockDim.x)
+    if (!(C.kind && C.kind[c] == 1)) m = fmax(m, C.lam[stride * c]);
+  m = wmax(m);
+  if (lane == 0) red[wid] = m;
+  __syncthreads();
+  double lmax = 0.0;
+  for (int w = 0; w < (int)(blockDim.x >> 6); ++w) lmax = fmax(lmax, red[w]);
+  for (int c = tid; c < K; c += blockDim.x) {
+    const int v = C.v[c];
+    if (c > 0 && C.v[c - 1] == v) continue;
+    const int o = Vx.v_orig[v];
+    double vv[3] = {v_next[3 * o], v_next[3 * o + 1], v_next[3 * o + 2]};
+    const double vi[3] = {v_t[3 * o], v_t[3 * o + 1], v_t[3 * o + 2]};
+    bool any = false;
+    for (int d = c; d < K && C.v[d] == v; ++d) {
+      if ((C.kind && C.kind[d] == 1) || !(lmax > 0.0 && C.lam[stride * d] > 1e-10 * lmax)) continue;
+      const double* n = C.n + 3 * d;
+      const double u = n[0] * vi[0] + n[1] * vi[1] + n[2] * vi[2];
+      if (!(u < 0.0)) continue;
+      const double vn = n[0] * vv[0] + n[1] * vv[1] + n[2] * vv[2];
+#pragma unroll
+      for (int a = 0; a < 3; ++a) vv[a] += n[a] * (-e * u - vn);
+      if (rec) rec[1 + 9 * kmax + d] = 1.0;
+      any = true;
+    }
+    if (any)
+#pragma unroll
+      for (int a = 0; a < 3; ++a) v_next[3 * o + a] = vv[a];
+  }
+}
+
+// the adjoint before the backward step: rows of a vertex in reverse order,
+// v bar <- v bar - n (n . v bar), the product kept per row
+__global__ void __launch_bounds__(kContactThreads) k_restitution_adj_pre(VertArgs Vx, const double* __restrict__ rec,
+                                                                         int kmax, double* __restrict__ gv,
+                                                                         double* __restrict__ s_row) {
+  const int K = (int)rec[0];
+  for (int c = threadIdx.x; c < K; c += blockDim.x) {
+    const int v = (int)rec[1 + c];
+    if (c < K - 1 && (int)rec[2 + c] == v) continue;  // the last row of the run walks it backwards
+    const int o = Vx.v_orig[v];
+    double g[3] = {gv[3 * o], gv[3 * o + 1], gv[3 * o + 2]};
+    bool any = false;
+    for (int d = c; d >= 0 && (int)rec[1 + d] == v; --d) {
+      if (rec[1 + 9 * kmax + d] != 1.0) continue;
+      const double* n = rec + 1 + kmax + 3 * d;
+      const double p = n[0] * g[0] + n[1] * g[1] + n[2] * g[2];
+      s_row[d] = p;
+#pragma unroll
+      for (int a = 0; a < 3; ++a) g[a] -= n[a] * p;
+      any = true;
+    }
+    if (any)
+#pragma unroll
+      for (int a = 0; a < 3; ++a) gv[3 * o + a] = g[a];
+  }
+}
+
+// after it: dL/dv_t += -e n s_row of every flagged row (rows of one vertex summed in order)
+__global__ void __launch_bounds__(kContactThreads) k_restitution_adj_post(VertArgs Vx, const double* __restrict__ rec,
+                                                                          int kmax, const double* __restrict__ s_row,
+                                                                          double* __restrict__ gv_t) {
+  const int K = (int)rec[0];
+  const double e = rec[1 + 10 * kmax];
+  for (int c = threadIdx.x; c < K; c += blockDim.x) {
+    const int v = (int)rec[1 + c];
+    if (c > 0 && (int)rec[c] == v) continue;
+    const int o = Vx.v_orig[v];
+    double g[3] = {0.0, 0.0, 0.0};
+    bool any = false;
+    for (int d = c; d < K && (int)rec[1 + d] == v; ++d) {
+      if (rec[1 + 9 * kmax + d] != 1.0) continue;
+      const double* n = rec + 1 + kmax + 3 * d;
+#pragma unroll
+      for (int a = 0; a < 3; ++a) g[a] += -e * n[a] * s_row[d];
+      any = true;
+    }
+    if (any)
+#pragma unroll
+      for (int a = 0; a < 3; ++a) gv_t[3 * o + a] += g[a];
   }
 }
 
@@ -1169,9 +1283,22 @@ void launch_contact_slip(const VertArgs& V, const ContactArgs& C, const double* 
 void launch_contact_route(const VertArgs& V, const ContactArgs& C, const int* kind, double* gq_t, hipStream_t s) {
   if (C.K > 0 && gq_t) hipLaunchKernelGGL(k_contact_route, dim3(1), dim3(64), 0, s, V, C, kind, gq_t);
 }
-void launch_contact_ckpt(const ContactArgs& C, int kmax, double* rec, hipStream_t s) {
+void launch_contact_restitution(const VertArgs& V, const ContactArgs& C, const double* v_t, double* v_next, double e,
+                                double* rec, int kmax, hipStream_t s) {
+  if (C.K > 0)
+    hipLaunchKernelGGL(k_contact_restitution, dim3(1), dim3(kContactThreads), 0, s, V, C, v_t, v_next, e, rec, kmax);
+}
+void launch_restitution_adj_pre(const VertArgs& V, const double* rec, int kmax, double* gv, double* s_row,
+                                hipStream_t s) {
+  hipLaunchKernelGGL(k_restitution_adj_pre, dim3(1), dim3(kContactThreads), 0, s, V, rec, kmax, gv, s_row);
+}
+void launch_restitution_adj_post(const VertArgs& V, const double* rec, int kmax, const double* s_row,
+                                 double* gv_t, hipStream_t s) {
+  hipLaunchKernelGGL(k_restitution_adj_post, dim3(1), dim3(kContactThreads), 0, s, V, rec, kmax, s_row, gv_t);
+}
+void launch_contact_ckpt(const ContactArgs& C, int kmax, double e_rest, double* rec, hipStream_t s) {
   hipLaunchKernelGGL(k_contact_ckpt, dim3((std::max(C.K, 1) + kBlock - 1) / kBlock), dim3(kBlock), 0, s, C, kmax,
-                     rec);
+                     e_rest, rec);
 }
 
 }  // namespace pdhot

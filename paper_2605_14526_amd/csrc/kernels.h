@@ -130,6 +130,13 @@ struct ElemArgs {
   double* rw;         // 3 x ne warm-start stretch ratios (the composite keeps its volume multiplier in row 0)
   double mu_bar, lam_bar, k_bar;
   int energy;         // 0: Neo-Hookean proximal map; 1: corotated + volume composite
+  // muscle fibres (null when the scene has none): 4 x ne {m_x, m_y, m_z, w_m V_e} (w_m V_e = 0 for a
+  // passive tet), the tet's group, the groups' activations, and 4 x ne {f^, l/|f|} at q* (backward)
+  const double* mus;
+  const int* mgrp;
+  const double* act;
+  double* mjac;
+  double* mgt;        // ne: a muscle tet's term of dL/da (backward scratch)
 };
 
 struct VertArgs {
@@ -244,6 +251,7 @@ struct ContactArgs {
   const double* nb = nullptr;   // adjoint: 3 per row, the directions along which the multipliers act
                                 // (null: n); with friction they differ from n on sliding normal rows
   const double* dg = nullptr;   // adjoint: per-row diagonal of the coupling matrix (null: none)
+  const int* kind = nullptr;    // forward: K row kinds, 1 = bilateral (equality, free multiplier); null: none
 };
 struct ObsArgs {
   int n_planes, n_boxes;
@@ -265,12 +273,15 @@ struct SceneBundle {
   const double* jac;
 };
 
-// Block-to-scene map of a batched launch: scene s owns blocks
-// base[s] .. base[s+1]-1 (empty ranges allowed).
+// Block-to-scene map of a batched launch over ns of the batch's scenes: the
+// j-th of them (scene sid[j]) owns blocks base[j] .. base[j+1]-1 (empty
+// ranges allowed).  Launches after a host check list only the scenes whose
+// loop still runs.
 struct BatchMap {
   const SceneBundle* B;
   const int* base;
   int ns;
+  const int* sid;
 };
 
 // block-map kinds of a batch: the stages, then the forward (kBKSepF + l - 1)
@@ -332,6 +343,9 @@ void launch_grad_elem(const ElemArgs& E, const VertArgs& V, const double* ck, co
 void launch_grad_vert(const VertArgs& V, const double* mu, const double* contrib, const double* gv_next, double* gq_t,
                       double* gv_t, double* gf, hipStream_t s);
 void launch_init_warm(const ElemArgs& E, hipStream_t s);
+// dL/da_g += sum over the group's tets (g_ptr / g_tets, library tet order) of their terms E.mgt
+void launch_muscle_grad(const ElemArgs& E, int n_groups, const int* g_ptr, const int* g_tets, double* g_act,
+                        hipStream_t s);
 
 // contact (contact.hip, and the apply kernels in kernels.hip)
 void launch_contact_detect(const VertArgs& V, const double* qt, const double* vt, const ObsArgs& O, int kmax,
@@ -343,7 +357,18 @@ void launch_contact_start(const ContactArgs& C, hipStream_t s);
 void launch_contact_fb(const VertArgs& V, const ContactArgs& C, const double* qhat, const int* done, hipStream_t s);
 void launch_contact_winv(const ContactArgs& C, double* Winv, hipStream_t s);
 void launch_contact_proj(const VertArgs& V, const ContactArgs& C, const double* z, const int* done, hipStream_t s);
-void launch_contact_ckpt(const ContactArgs& C, int kmax, double* rec, hipStream_t s);
+void launch_contact_ckpt(const ContactArgs& C, int kmax, double e_rest, double* rec, hipStream_t s);
+// restitution (forward): active unilateral rows whose vertex approached (n . v_t < 0) set its outgoing
+// normal velocity to -e (n . v_t), rows of one vertex in order; flags the rows in the checkpoint record
+void launch_contact_restitution(const VertArgs& V, const ContactArgs& C, const double* v_t, double* v_next, double e,
+                                double* rec, int kmax, hipStream_t s);
+// its adjoint from a checkpoint record: before the backward step v bar (caller order, copied to gv_out
+// first) loses the normal part of flagged rows in reverse order, their values kept in s_row; after it
+// dL/dv_t gains -e n s_row
+void launch_restitution_adj_pre(const VertArgs& V, const double* rec, int kmax, double* gv, double* s_row,
+                                hipStream_t s);
+void launch_restitution_adj_post(const VertArgs& V, const double* rec, int kmax, const double* s_row,
+                                 double* gv_t, hipStream_t s);
 // friction: the per-iteration Newton (forward), the inverse of the adjoint rows' unsymmetric coupling
 // matrix, the contact vertices' slip and diagonal for the adjoint's classification, and the routing of the
 // sticking / sliding rows' multipliers to dL/dq_t (caller order; kind 0 rows skipped)

@@ -342,6 +342,55 @@ __device__ __forceinline__ void store_warm_nu(const ElemArgs& E, int t, const do
   E.rw[t] = nu;
 }
 
+// ---------------------------------------------------------------- muscle fibres
+// A muscle tet carries the fibre constraint (w_m V_e / 2) dist^2(F m, S_l):
+// the fibre image f = F m is projected onto the sphere of radius
+// l = 1 - a_g (a_g the activation of the tet's group), p = l f/|f|, and
+// w_m V_e G^T p joins b; its derivative (l/|f|)(I - f^ f^T) joins K and
+// db/da_g = -w_m V_e G^T f^.  G^T (x m^T) gives vertex a the vector
+// (Bhat_a . m) x, so every term enters the element's 3x3 matrix as x m^T.
+__device__ __forceinline__ void fibre_of(const ElemArgs& E, int t, double m[3], double& wm) {
+  const size_t ne = E.ne;
+  m[0] = E.mus[t];
+  m[1] = E.mus[ne + t];
+  m[2] = E.mus[2 * ne + t];
+  wm = E.mus[3 * ne + t];
+}
+
+__device__ __forceinline__ void mat_vec_m(const double F[9], const double m[3], double f[3]) {
+#pragma unroll
+  for (int i = 0; i < 3; ++i) f[i] = F[3 * i] * m[0] + F[3 * i + 1] * m[1] + F[3 * i + 2] * m[2];
+}
+
+// P += w_m V_e p m^T (local step)
+__device__ __forceinline__ void muscle_local(const ElemArgs& E, int t, const double F[9], double P[9]) {
+  double m[3], wm;
+  fibre_of(E, t, m, wm);
+  if (wm == 0.0) return;
+  double f[3];
+  mat_vec_m(F, m, f);
+  const double nf = sqrt(f[0] * f[0] + f[1] * f[1] + f[2] * f[2]);
+  const double ell = 1.0 - E.act[E.mgrp[t]];
+  double p[3];
+#pragma unroll
+  for (int i = 0; i < 3; ++i) p[i] = (nf > 0.0) ? ell * f[i] / nf : ell * m[i];
+#pragma unroll
+  for (int i = 0; i < 3; ++i)
+#pragma unroll
+    for (int j = 0; j < 3; ++j) P[3 * i + j] += wm * p[i] * m[j];
+}
+
+// the fibre's energy (w_m V_e / 2)(|F m| - l)^2 (primal objective)
+__device__ __forceinline__ double muscle_energy(const ElemArgs& E, int t, const double F[9]) {
+  double m[3], wm;
+  fibre_of(E, t, m, wm);
+  if (wm == 0.0) return 0.0;
+  double f[3];
+  mat_vec_m(F, m, f);
+  const double d = sqrt(f[0] * f[0] + f[1] * f[1] + f[2] * f[2]) - (1.0 - E.act[E.mgrp[t]]);
+  return 0.5 * wm * d * d;
+}
+
 // ---------------------------------------------------------------- Anderson mixing
 struct AAMix {
   int stop;       // the loop has already stopped (done flag)
@@ -565,6 +614,7 @@ __device__ __forceinline__ void b_local(ElemArgs E, StepState St, RedArgs R, con
 #pragma unroll
       for (int j = 0; j < 3; ++j)
         P[3 * i + j] = U[3 * i] * sw[0] * V[3 * j] + U[3 * i + 1] * sw[1] * V[3 * j + 1] + U[3 * i + 2] * sw[2] * V[3 * j + 2];
+    if (E.mus) muscle_local(E, t, F, P);
     store_GtP(T, St.contrib, E.ninc, P);
     if (E.energy == 1) store_warm_nu(E, t, V, nu);
     else store_warm(E, t, V, sF, sv);
@@ -579,6 +629,7 @@ __device__ __forceinline__ void b_local(ElemArgs E, StepState St, RedArgs R, con
     for (int j = 0; j < 3; ++j)
       P[3 * i + j] =
           wv * (U[3 * i] * ss[0] * V[3 * j] + U[3 * i + 1] * ss[1] * V[3 * j + 1] + U[3 * i + 2] * ss[2] * V[3 * j + 2]);
+  if (E.mus) muscle_local(E, t, F, P);
   store_GtP(T, St.contrib, E.ninc, P);
   store_warm(E, t, V, sF, ss);
 }
@@ -1766,6 +1817,16 @@ __global__ void __launch_bounds__(kBlock) k_tr_partials(ElemArgs E, VertArgs Vx,
       }
       v[0] = d;
       v[1] = (E.wV[t] + E.bV[t]) * gg;
+      if (E.mus) {
+        // the fibre's energy difference and its part of |dq|_A^2: w_m V_e |(Fb - Fa) m|^2
+        double m[3], wm, dF[9], y[3];
+        fibre_of(E, t, m, wm);
+#pragma unroll
+        for (int j = 0; j < 9; ++j) dF[j] = Fb[j] - Fa[j];
+        mat_vec_m(dF, m, y);
+        v[0] += muscle_energy(E, t, Fa) - muscle_energy(E, t, Fb);
+        v[1] += wm * (y[0] * y[0] + y[1] * y[1] + y[2] * y[2]);
+      }
     }
   } else {
     const int i = (blockIdx.x - n_tet_blocks) * blockDim.x + threadIdx.x;
@@ -1872,6 +1933,17 @@ __global__ void __launch_bounds__(kBlock) k_bwd_elem(ElemArgs E, VertArgs Vx, Re
     jac[(24 + j) * ne + t] = c1[j];
     jac[(27 + j) * ne + t] = c2[j];
     jac[(30 + j) * ne + t] = ss[j];
+  }
+  if (E.mus) {
+    // the fibre's differential at q*: f^ and l/|f| (zero for a passive tet or f = 0)
+    double m[3], wm, f[3];
+    fibre_of(E, t, m, wm);
+    mat_vec_m(F, m, f);
+    const double nf = sqrt(f[0] * f[0] + f[1] * f[1] + f[2] * f[2]);
+    const bool on = wm != 0.0 && nf > 0.0;
+#pragma unroll
+    for (int j = 0; j < 3; ++j) E.mjac[j * ne + t] = on ? f[j] / nf : 0.0;
+    E.mjac[3 * ne + t] = on ? (1.0 - E.act[E.mgrp[t]]) / nf : 0.0;
   }
   // a reverse sweep visits q* of neighbouring steps: start the next one from here
   if (E.energy == 1)
@@ -2002,6 +2074,24 @@ __device__ __forceinline__ void b_apply_K(ElemArgs E, VertArgs Vx, AdjState A, R
   double P[9];
 #pragma unroll
   for (int j = 0; j < 9; ++j) P[j] = (MODE == kModeAmK) ? (wv + bv) * dF[j] - wv * dP[j] : wv * dP[j];
+  if (E.mus) {
+    // the fibre: K gains w_m V_e dp m^T, dp = (l/|f|)(y - f^ (f^ . y)), y = dF m; A~ gains w_m V_e y m^T
+    double m[3], wm;
+    fibre_of(E, t, m, wm);
+    if (wm != 0.0) {
+      const size_t ne = E.ne;
+      const double fh[3] = {E.mjac[t], E.mjac[ne + t], E.mjac[2 * ne + t]}, r = E.mjac[3 * ne + t];
+      double y[3], dp[3];
+      mat_vec_m(dF, m, y);
+      const double d = fh[0] * y[0] + fh[1] * y[1] + fh[2] * y[2];
+#pragma unroll
+      for (int i = 0; i < 3; ++i) dp[i] = r * (y[i] - fh[i] * d);
+#pragma unroll
+      for (int i = 0; i < 3; ++i)
+#pragma unroll
+        for (int j = 0; j < 3; ++j) P[3 * i + j] += wm * ((MODE == kModeAmK) ? y[i] - dp[i] : dp[i]) * m[j];
+    }
+  }
   store_GtP(T, A.contrib, E.ninc, P);
 }
 
@@ -2155,6 +2245,26 @@ __global__ void __launch_bounds__(kBlock) k_grad_elem(ElemArgs E, VertArgs Vx, c
     }
   if (g_logE) g_logE[E.tet_orig[t]] += E.wV[t] * gw + E.bV[t] * gb;
   store_contrib(E, contrib, t, E.bV[t], Gm);
+  if (E.mus) {
+    // the tet's term of dL/da_g = -w_m V_e <G_m mu, f^> (summed per group afterwards)
+    double m[3], wm, y[3];
+    fibre_of(E, t, m, wm);
+    mat_vec_m(Gm, m, y);
+    const size_t ne = E.ne;
+    E.mgt[t] = -wm * (y[0] * E.mjac[t] + y[1] * E.mjac[ne + t] + y[2] * E.mjac[2 * ne + t]);
+  }
+}
+
+// dL/da_g += the group's tet terms: one wave per group, lane l adds terms l,
+// l + 64, ... of the group's list in order, then a fixed butterfly
+__global__ void __launch_bounds__(64) k_muscle_grad(const double* __restrict__ mgt, const int* __restrict__ g_ptr,
+                                                    const int* __restrict__ g_tets, double* __restrict__ g_act) {
+  const int g = blockIdx.x, l = threadIdx.x;
+  double s = 0.0;
+  for (int k = g_ptr[g] + l; k < g_ptr[g + 1]; k += 64) s += mgt[g_tets[k]];
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) s += __shfl_xor(s, off, 64);
+  if (l == 0) g_act[g] += s;
 }
 
 // dL/dq_t = (M/h^2 + alpha M/h) mu + B_beta mu / h - v bar / h,
@@ -2206,10 +2316,11 @@ __global__ void __launch_bounds__(kBlock) k_zero_int(int* p, int n) {
 }
 
 // ================================================================= batched launches
-// One launch per stage covers every scene of a batch: block b belongs to the
-// scene s with base[s] <= b < base[s+1] and runs as that scene's block
-// b - base[s], with the scene's own arguments, reductions and done flag (so a
-// converged scene's blocks exit at once while the others iterate).
+// One launch per stage covers the scenes of a batch: block b belongs to the
+// listed scene j with base[j] <= b < base[j+1] and runs as block b - base[j]
+// of scene sid[j], with the scene's own arguments, reductions and done flag
+// (a scene that converges within a chunk exits at once; the host drops it
+// from the list at the next check).
 __device__ __forceinline__ int scene_of(const BatchMap& M, int b) {
   int lo = 0, hi = M.ns - 1;  // the last s with base[s] <= b
   while (lo < hi) {
@@ -2223,7 +2334,7 @@ __device__ __forceinline__ int scene_of(const BatchMap& M, int b) {
 #define PD_BATCH_PROLOGUE                      \
   const int s_ = scene_of(M, blockIdx.x);      \
   const int bid = blockIdx.x - M.base[s_];     \
-  const SceneBundle& b = M.B[s_];
+  const SceneBundle& b = M.B[M.sid[s_]];
 
 __global__ void __launch_bounds__(kBlock) kb_local(BatchMap M, int k) {
   PD_BATCH_PROLOGUE
@@ -2567,6 +2678,11 @@ void launch_b_adj_gather(int mode, const BatchMap& M, int nblk, int it, hipStrea
 }
 void launch_b_flags(const BatchMap& M, int* ctl_out, double* dstat_out, hipStream_t s) {
   launch_ext(kb_flags, dim3(M.ns), dim3(64), 0, s, M, ctl_out, dstat_out);
+}
+
+void launch_muscle_grad(const ElemArgs& E, int n_groups, const int* g_ptr, const int* g_tets, double* g_act,
+                        hipStream_t s) {
+  if (n_groups > 0) hipLaunchKernelGGL(k_muscle_grad, dim3(n_groups), dim3(64), 0, s, E.mgt, g_ptr, g_tets, g_act);
 }
 
 void launch_init_warm(const ElemArgs& E, hipStream_t s) {

@@ -263,6 +263,32 @@ struct Scene {
   double *a_nb = nullptr, *a_dg = nullptr, *c_slip = nullptr;
   int* a_kind = nullptr;
   bool a_fric = false;  // the current backward step has friction rows
+  // bilateral rows (attachments; frictionless contact only): library vertex
+  // ids, unit directions and offsets, appended to every step's rows
+  std::vector<int> att_v;
+  std::vector<double> att_n, att_g;
+  int* c_kind = nullptr;       // kmax: 1 for a bilateral row of the current step
+  // restitution post-correction (rest_e < 0: off)
+  double rest_e = -1.0;
+  double* gv_rest = nullptr;   // 3 x nv (caller order): v bar after the correction's adjoint
+  double* rest_s = nullptr;    // kmax per-row products of that adjoint
+  bool a_rest = false;         // the current backward step has corrected rows
+  std::vector<int> a_rows;     // record indices of the current backward step's active rows
+  int a_K = 0;                 // rows in that record
+  // --- muscle fibres (off until pd_scene_set_muscles): host copies in the
+  // caller's tet order, device arrays in library order
+  int n_mg = 0;
+  double w_m = 0.0;
+  std::vector<int> hmgroup;
+  std::vector<double> hmfib;
+  double* mus = nullptr;     // 4 x ne: fibre (3), w_m V_e (0: passive)
+  int* mgrp = nullptr;       // ne: group (0 for passive tets, whose w_m V_e is 0)
+  double* act = nullptr;     // n_mg activations
+  double* mjac = nullptr;    // 4 x ne fibre differential at q*
+  double* mgt = nullptr;     // ne per-tet terms of dL/da
+  int* mg_ptr = nullptr;     // n_mg + 1: each group's tets (library order)
+  int* mg_tets = nullptr;
+  double* g_act = nullptr;   // caller's accumulator of dL/da (may be null)
 };
 
 void set_last_error(const std::string& m);

@@ -230,7 +230,10 @@ void contact_free(Scene& S) {
   dfree(S.c_s); dfree(S.c_W); dfree(S.c_fb); dfree(S.a_v); dfree(S.a_slot); dfree(S.a_n); dfree(S.a_s);
   dfree(S.a_Winv); dfree(S.c_Lg); dfree(S.cols);
   dfree(S.c_frw); dfree(S.c_fri); dfree(S.a_nb); dfree(S.a_dg); dfree(S.c_slip); dfree(S.a_kind);
+  dfree(S.c_kind); dfree(S.gv_rest); dfree(S.rest_s);
   S.mu_f = 0.0;
+  S.c_kmax = 0;
+  S.n_planes = S.n_boxes = 0;
   S.a_fric = false;
   if (S.h_cbuf) (void)hipHostFree(S.h_cbuf);
   if (S.h_crec) (void)hipHostFree(S.h_crec);
@@ -259,6 +262,7 @@ void free_device(Scene& S) {
   dfree(S.ctl); dfree(S.dstat); dfree(S.red_part); dfree(S.red_fin);
   dfree(S.jac); dfree(S.mu); dfree(S.r0); dfree(S.r1); dfree(S.z); dfree(S.p); dfree(S.Ap); dfree(S.wv);
   dfree(S.qbar); dfree(S.ck_scratch); dfree(S.mu_h1); dfree(S.mu_h2); dfree(S.mu_h3);
+  dfree(S.mus); dfree(S.mgrp); dfree(S.act); dfree(S.mjac); dfree(S.mgt); dfree(S.mg_ptr); dfree(S.mg_tets);
   contact_free(S);
   if (S.hctl) (void)hipHostFree(S.hctl);
   if (S.hdstat) (void)hipHostFree(S.hdstat);
@@ -370,6 +374,7 @@ ElemArgs elem_args(const Scene& S) {
   E.tet_orig = S.tet_orig; E.Vw = S.Vw; E.rw = S.rw;
   E.mu_bar = S.mu_bar; E.lam_bar = S.lam_bar; E.k_bar = S.k_bar;
   E.energy = S.energy;
+  E.mus = S.mus; E.mgrp = S.mgrp; E.act = S.act; E.mjac = S.mjac; E.mgt = S.mgt;
   return E;
 }
 
@@ -744,6 +749,18 @@ void factorize(Scene& S) {
   }
   upload(S.wV, wV); upload(S.bV, bV); upload(S.muV, muV); upload(S.lamV, lamV);
   upload(S.mass, mass);
+  // muscle fibres in library order: m (3) and w_m V_e
+  std::vector<double> mus;
+  if (S.n_mg > 0) {
+    mus.assign(4 * (size_t)ne, 0.0);
+    for (int t = 0; t < ne; ++t) {
+      const int e = L.tet_lib2orig[t];
+      if (S.hmgroup[e] < 0) continue;
+      for (int j = 0; j < 3; ++j) mus[(size_t)j * ne + t] = S.hmfib[3 * (size_t)e + j];
+      mus[3 * (size_t)ne + t] = S.w_m * vol[t];
+    }
+    upload(S.mus, mus);
+  }
   // assemble A~ (Sec. 4.5 Eq. A_damped) into the block structure
   const int nsub = L.nsub;
   std::vector<std::vector<double>> Ass(nsub), AIs(nsub);
@@ -807,12 +824,20 @@ void factorize(Scene& S) {
       Bh[3][j] = Bm[(size_t)(6 + j) * ne + t];
       Bh[0][j] = -(Bh[1][j] + Bh[2][j] + Bh[3][j]);
     }
+    // a muscle tet adds w_m V_e c c^T with c_a = Bhat_a . m (its fibre's G_m^T G_m)
+    double mc[4] = {0, 0, 0, 0}, wm = 0.0;
+    if (!mus.empty() && mus[3 * (size_t)ne + t] != 0.0) {
+      wm = mus[3 * (size_t)ne + t];
+      for (int a = 0; a < 4; ++a)
+        for (int j = 0; j < 3; ++j) mc[a] += Bh[a][j] * mus[(size_t)j * ne + t];
+    }
     for (int a = 0; a < 4; ++a) {
       const int i = tv[(size_t)a * ne + t];
       if (i >= nf) continue;
       for (int b = 0; b < 4; ++b) {
         const int j = tv[(size_t)b * ne + t];
-        const double val = cst * (Bh[a][0] * Bh[b][0] + Bh[a][1] * Bh[b][1] + Bh[a][2] * Bh[b][2]);
+        const double val = cst * (Bh[a][0] * Bh[b][0] + Bh[a][1] * Bh[b][1] + Bh[a][2] * Bh[b][2]) +
+                           wm * mc[a] * mc[b];
         if (j >= nf) {  // coupling to a pinned vertex (held at rest)
           for (int ax = 0; ax < 3; ++ax) cpin[(size_t)ax * nv + i] -= val * S.X[3 * (size_t)L.lib2orig[j] + ax];
           continue;
@@ -1094,6 +1119,7 @@ ContactArgs contact_args(Scene& S, int K, bool adjoint) {
   C.qt = S.qt;
   C.frw = S.c_frw;
   C.fri = S.c_fri;
+  C.kind = adjoint ? nullptr : S.c_kind;
   if (adjoint && S.a_fric) {
     C.nb = S.a_nb;
     C.dg = S.a_dg;
@@ -1163,13 +1189,29 @@ int contact_rows(Scene& S, hipStream_t st) {
   O.d_c = S.d_c;
   O.h = S.h;
   O.one_per_vertex = S.mu_f > 0.0 ? 1 : 0;
-  launch_contact_detect(V, S.qt, S.vt, O, S.c_kmax, S.c_v, S.c_n, S.c_g, S.c_flags, st);
-  PD_HIP(hipMemcpyAsync(S.h_cbuf, S.c_flags, 4 * sizeof(int), hipMemcpyDeviceToHost, st));
-  PD_HIP(hipStreamSynchronize(st));
-  const int K = S.h_cbuf[0];
-  if (K > S.c_kmax)
-    throw PdError{kErrContact, "contact rows (" + std::to_string(K) + ") exceed max_contacts (" +
+  int K = 0;
+  if (S.n_planes + S.n_boxes > 0) {
+    launch_contact_detect(V, S.qt, S.vt, O, S.c_kmax, S.c_v, S.c_n, S.c_g, S.c_flags, st);
+    PD_HIP(hipMemcpyAsync(S.h_cbuf, S.c_flags, 4 * sizeof(int), hipMemcpyDeviceToHost, st));
+    PD_HIP(hipStreamSynchronize(st));
+    K = S.h_cbuf[0];
+  }
+  // the attachments' bilateral rows follow the detected ones
+  const int nb = (int)S.att_v.size();
+  if (K + nb > S.c_kmax)
+    throw PdError{kErrContact, "contact rows (" + std::to_string(K + nb) + ") exceed max_contacts (" +
                                    std::to_string(S.c_kmax) + ")"};
+  {
+    std::vector<int> kind(std::max(K + nb, 1), 0);
+    for (int c = K; c < K + nb; ++c) kind[c] = 1;
+    if (nb > 0) {
+      PD_HIP(hipMemcpy(S.c_v + K, S.att_v.data(), nb * sizeof(int), hipMemcpyHostToDevice));
+      PD_HIP(hipMemcpy(S.c_n + 3 * (size_t)K, S.att_n.data(), 3 * nb * sizeof(double), hipMemcpyHostToDevice));
+      PD_HIP(hipMemcpy(S.c_g + K, S.att_g.data(), nb * sizeof(double), hipMemcpyHostToDevice));
+    }
+    if (K + nb > 0) PD_HIP(hipMemcpy(S.c_kind, kind.data(), (K + nb) * sizeof(int), hipMemcpyHostToDevice));
+  }
+  K += nb;
   if (K == 0) return 0;
   int* hv = S.h_cbuf + 4;
   int* hs = hv + S.c_kmax;
@@ -1279,20 +1321,31 @@ int contact_active(Scene& S, const double* ck, hipStream_t st) {
   const int kmax = S.c_kmax;
   const double* rec = ck + (size_t)kCheckpointVecs * 3 * S.nv;
   S.a_fric = false;
-  PD_HIP(hipMemcpyAsync(S.h_crec, rec, (1 + 8 * (size_t)kmax) * sizeof(double), hipMemcpyDeviceToHost, st));
+  PD_HIP(hipMemcpyAsync(S.h_crec, rec, (2 + 10 * (size_t)kmax) * sizeof(double), hipMemcpyDeviceToHost, st));
   PD_HIP(hipStreamSynchronize(st));
   const double* h = S.h_crec;
   const int K = (int)h[0];
   if (K < 0 || K > kmax) throw PdError{PD_ERR_INVALID_ARG, "checkpoint holds no valid contact record"};
+  // active rows: every bilateral row, and the unilateral rows whose impulse
+  // exceeds 1e-10 of the largest unilateral one
+  auto bil = [&](int c) { return h[1 + 8 * kmax + c] == 1.0; };
   double lmax = 0.0;
-  for (int c = 0; c < K; ++c) lmax = std::max(lmax, h[1 + 5 * kmax + c]);
+  for (int c = 0; c < K; ++c)
+    if (!bil(c)) lmax = std::max(lmax, h[1 + 5 * kmax + c]);
+  auto active = [&](int c) { return bil(c) || (lmax > 0.0 && h[1 + 5 * kmax + c] > 1e-10 * lmax); };
   std::vector<int> av;
   std::vector<double> an;
-  for (int c = 0; c < K; ++c)
-    if (lmax > 0.0 && h[1 + 5 * kmax + c] > 1e-10 * lmax) {
+  S.a_rows.clear();
+  S.a_K = K;
+  S.a_rest = false;
+  for (int c = 0; c < K; ++c) {
+    if (h[1 + 9 * kmax + c] == 1.0) S.a_rest = true;
+    if (active(c)) {
       av.push_back((int)h[1 + c]);
       for (int a = 0; a < 3; ++a) an.push_back(h[1 + kmax + 3 * c + a]);
+      S.a_rows.push_back(c);
     }
+  }
   const int na = (int)av.size();
   S.c_last_active = na;
   if (na == 0) return 0;
@@ -1301,7 +1354,7 @@ int contact_active(Scene& S, const double* ck, hipStream_t st) {
   if (S.mu_f > 0.0) {
     std::vector<double> al;
     for (int c = 0; c < K; ++c)
-      if (lmax > 0.0 && h[1 + 5 * kmax + c] > 1e-10 * lmax) al.push_back(h[1 + 5 * kmax + c]);
+      if (active(c)) al.push_back(h[1 + 5 * kmax + c]);
     return contact_active_friction(S, ck, av, an, al, hs, st);
   }
   PD_HIP(hipMemcpyAsync(S.a_v, av.data(), na * sizeof(int), hipMemcpyHostToDevice, st));
@@ -1477,6 +1530,96 @@ int pd_scene_set_material_device(pd_scene* scene, const double* log_E_dev, void*
   PD_CATCH
 }
 
+int pd_scene_set_muscles(pd_scene* scene, int n_groups, double w_m, const int32_t* group, const double* fibre) {
+  if (!scene || n_groups < 0 || (n_groups > 0 && (!group || !fibre))) {
+    pdhot::g_last_error = "null argument or negative group count";
+    return PD_ERR_INVALID_ARG;
+  }
+  Scene& S = scene->S;
+  const int ne = S.ne;
+  if (n_groups > 0) {
+    if (!(std::isfinite(w_m) && w_m > 0.0)) {
+      pdhot::g_last_error = "the fibre weight must be positive and finite";
+      return PD_ERR_INVALID_ARG;
+    }
+    for (int e = 0; e < ne; ++e) {
+      if (group[e] < -1 || group[e] >= n_groups) {
+        pdhot::g_last_error = "muscle group out of range";
+        return PD_ERR_INVALID_ARG;
+      }
+      if (group[e] < 0) continue;
+      const double* m = fibre + 3 * (size_t)e;
+      const double n2 = m[0] * m[0] + m[1] * m[1] + m[2] * m[2];
+      if (!std::isfinite(n2) || std::fabs(n2 - 1.0) > 1e-9) {
+        pdhot::g_last_error = "muscle fibres must be unit vectors";
+        return PD_ERR_INVALID_ARG;
+      }
+    }
+  }
+  PD_TRY
+  PD_HIP(hipDeviceSynchronize());  // kernels of earlier steps may still read the fibre arrays
+  dfree(S.mus); dfree(S.mgrp); dfree(S.act); dfree(S.mjac); dfree(S.mgt); dfree(S.mg_ptr); dfree(S.mg_tets);
+  S.n_mg = n_groups;
+  S.w_m = n_groups > 0 ? w_m : 0.0;
+  S.hmgroup.clear();
+  S.hmfib.clear();
+  S.g_act = nullptr;
+  if (n_groups > 0) {
+    S.hmgroup.assign(group, group + ne);
+    S.hmfib.assign(fibre, fibre + 3 * (size_t)ne);
+    // each group's tets in library order, and the library-order group ids
+    std::vector<int> cnt(n_groups + 1, 0), grp(ne, 0);
+    for (int t = 0; t < ne; ++t) {
+      const int g = group[S.L.tet_lib2orig[t]];
+      if (g >= 0) {
+        cnt[g + 1]++;
+        grp[t] = g;
+      }
+    }
+    for (int g = 0; g < n_groups; ++g) cnt[g + 1] += cnt[g];
+    std::vector<int> list(std::max(1, cnt[n_groups])), fill(cnt.begin(), cnt.end() - 1);
+    for (int t = 0; t < ne; ++t) {
+      const int g = group[S.L.tet_lib2orig[t]];
+      if (g >= 0) list[fill[g]++] = t;
+    }
+    S.mus = dalloc<double>(4 * (size_t)ne);
+    S.mgrp = dalloc<int>(ne);
+    upload(S.mgrp, grp);
+    S.act = dalloc<double>(n_groups);
+    PD_HIP(hipMemset(S.act, 0, sizeof(double) * n_groups));
+    S.mjac = dalloc<double>(4 * (size_t)ne);
+    S.mgt = dalloc<double>(ne);
+    S.mg_ptr = dalloc<int>(n_groups + 1);
+    upload(S.mg_ptr, cnt);
+    S.mg_tets = dalloc<int>(list.size());
+    upload(S.mg_tets, list);
+  }
+  S.stale = true;
+  return PD_OK;
+  PD_CATCH
+}
+
+int pd_scene_set_activation(pd_scene* scene, const double* a_dev, void* stream) {
+  if (!scene || !a_dev || scene->S.n_mg <= 0) {
+    pdhot::g_last_error = scene && scene->S.n_mg <= 0 ? "the scene has no muscles" : "null argument";
+    return PD_ERR_INVALID_ARG;
+  }
+  PD_TRY
+  PD_HIP(hipMemcpyAsync(scene->S.act, a_dev, sizeof(double) * scene->S.n_mg, hipMemcpyDeviceToDevice,
+                        (hipStream_t)stream));
+  return PD_OK;
+  PD_CATCH
+}
+
+int pd_scene_set_activation_grad(pd_scene* scene, double* g_act_dev) {
+  if (!scene || (g_act_dev && scene->S.n_mg <= 0)) {
+    pdhot::g_last_error = scene ? "the scene has no muscles" : "null scene";
+    return PD_ERR_INVALID_ARG;
+  }
+  scene->S.g_act = g_act_dev;
+  return PD_OK;
+}
+
 int pd_scene_freeze_means(pd_scene* scene, const double* means3) {
   if (!scene) {
     pdhot::g_last_error = "null scene";
@@ -1551,7 +1694,7 @@ size_t pd_ckpt_bytes(const pd_scene* scene) {
   if (!scene) return 0;
   const Scene& S = scene->S;
   size_t n = (size_t)kCheckpointVecs * 3 * (size_t)S.nv;
-  if (S.contact_on) n += 1 + 8 * (size_t)S.c_kmax;
+  if (S.contact_on) n += 2 + 10 * (size_t)S.c_kmax;
   return n * sizeof(double);
 }
 
@@ -1567,7 +1710,7 @@ int pd_scene_set_obstacles(pd_scene* scene, int n_planes, const double* planes, 
     throw PdError{PD_ERR_INVALID_ARG, "at most " + std::to_string(kMaxObstacles) + " obstacles"};
   if ((n_planes > 0 && !planes) || (n_boxes > 0 && !boxes)) throw PdError{PD_ERR_INVALID_ARG, "null obstacle array"};
   contact_free(S);
-  if (n_planes + n_boxes == 0) return PD_OK;
+  if (n_planes + n_boxes == 0 && S.att_v.empty()) return PD_OK;
   if (!(d_c > 0.0) || !(fb_tol > 0.0) || max_contacts < 1 || max_contacts > kMaxContactRows)
     throw PdError{PD_ERR_INVALID_ARG, "need d_c > 0, fb_tol > 0 and 1 <= max_contacts <= " +
                                           std::to_string(kMaxContactRows)};
@@ -1604,13 +1747,14 @@ int pd_scene_set_obstacles(pd_scene* scene, int n_planes, const double* planes, 
   S.c_frw = dalloc<double>((size_t)kFrWork * kmax); S.c_fri = dalloc<int>(2 * rmax);
   S.a_nb = dalloc<double>(3 * rmax); S.a_dg = dalloc<double>(rmax); S.a_kind = dalloc<int>(rmax);
   S.c_slip = dalloc<double>(4 * (size_t)kmax);
+  S.c_kind = dalloc<int>(kmax); S.rest_s = dalloc<double>(kmax); S.gv_rest = dalloc<double>(3 * (size_t)S.nv);
   S.col_cap = 4 * kmax;
   S.cols = dalloc<double>((size_t)S.col_cap * std::max(nf, 1));
   S.cols_used = 0;
   S.slot_of.assign(std::max(nf, 1), -1);
   S.vert_of_slot.clear();
   PD_HIP(hipHostMalloc((void**)&S.h_cbuf, (4 + 2 * (size_t)kmax) * sizeof(int)));
-  PD_HIP(hipHostMalloc((void**)&S.h_crec, (1 + 8 * (size_t)kmax) * sizeof(double)));
+  PD_HIP(hipHostMalloc((void**)&S.h_crec, (2 + 10 * (size_t)kmax) * sizeof(double)));
   PD_HIP(hipMemset(S.c_fb, 0, 2 * sizeof(double)));
   PD_HIP(hipMemset(S.c_flags, 0, 4 * sizeof(int)));
   S.contact_on = true;
@@ -1650,6 +1794,109 @@ int pd_contact_rows(const pd_scene* scene, int* K, int32_t* vert, double* normal
   PD_CATCH
 }
 
+int pd_scene_set_attachments(pd_scene* scene, int n_rows, const int32_t* vert, const double* normals,
+                             const double* offsets) {
+  if (!scene || n_rows < 0 || (n_rows > 0 && (!vert || !normals || !offsets))) {
+    pdhot::g_last_error = "null argument or negative row count";
+    return PD_ERR_INVALID_ARG;
+  }
+  PD_TRY
+  Scene& S = scene->S;
+  if (n_rows > 0 && S.mu_f > 0.0) throw PdError{PD_ERR_INVALID_ARG, "bilateral rows run with frictionless contact only"};
+  if (n_rows > kMaxContactRows) throw PdError{PD_ERR_INVALID_ARG, "too many bilateral rows"};
+  std::vector<int> av(n_rows);
+  std::vector<double> an(3 * (size_t)n_rows), ag(n_rows);
+  for (int c = 0; c < n_rows; ++c) {
+    const int v = vert[c];
+    if (v < 0 || v >= S.nv) throw PdError{PD_ERR_INVALID_ARG, "attachment vertex out of range"};
+    if (S.pinned[v]) throw PdError{PD_ERR_INVALID_ARG, "attachment on a pinned vertex"};
+    const double* n = normals + 3 * (size_t)c;
+    const double nn = std::sqrt(n[0] * n[0] + n[1] * n[1] + n[2] * n[2]);
+    if (!(std::fabs(nn - 1.0) <= 1e-12) || !std::isfinite(offsets[c]))
+      throw PdError{PD_ERR_INVALID_ARG, "attachment rows need unit directions and finite offsets"};
+    av[c] = S.L.orig2lib[v];
+    for (int a = 0; a < 3; ++a) an[3 * (size_t)c + a] = n[a];
+    ag[c] = offsets[c];
+  }
+  if (S.contact_on && n_rows > S.c_kmax)
+    throw PdError{PD_ERR_INVALID_ARG, "bilateral rows exceed max_contacts of the obstacles"};
+  PD_HIP(hipDeviceSynchronize());  // earlier steps may still read the row buffers
+  S.att_v = av;
+  S.att_n = an;
+  S.att_g = ag;
+  S.c_last_K = S.c_last_active = 0;
+  if (!S.contact_on && n_rows > 0) {
+    // the rows run through the contact machinery: set it up without obstacles
+    const int rc = pd_scene_set_obstacles(scene, 0, nullptr, 0, nullptr, 1.0, std::max(64, n_rows), 1e-10);
+    if (rc != PD_OK) return rc;
+  }
+  return PD_OK;
+  PD_CATCH
+}
+
+int pd_scene_set_restitution(pd_scene* scene, double e) {
+  if (!scene || !std::isfinite(e)) {
+    pdhot::g_last_error = "null scene or non-finite coefficient";
+    return PD_ERR_INVALID_ARG;
+  }
+  scene->S.rest_e = e >= 0.0 ? e : -1.0;
+  return PD_OK;
+}
+
+int pd_contact_gap_grad(pd_scene* scene, double* g_out, int capacity) {
+  if (!scene || (capacity > 0 && !g_out)) {
+    pdhot::g_last_error = "null argument";
+    return PD_ERR_INVALID_ARG;
+  }
+  PD_TRY
+  Scene& S = scene->S;
+  if (!S.contact_on) throw PdError{PD_ERR_INVALID_ARG, "the scene has no contact rows"};
+  if (S.mu_f > 0.0) throw PdError{PD_ERR_INVALID_ARG, "offset gradients are formed for frictionless rows only"};
+  const int K = S.a_K;
+  if (capacity < K) throw PdError{PD_ERR_INVALID_ARG, "capacity below the row count"};
+  for (int c = 0; c < K; ++c) g_out[c] = 0.0;
+  const int na = (int)S.a_rows.size();
+  if (na == 0) return PD_OK;
+  // dL/dg = W_AA^{-1} J_A A~^{-1} (q bar + K mu) from the last backward step's mu
+  // (the backward step may still run on the caller's stream)
+  PD_HIP(hipDeviceSynchronize());
+  hipStream_t st = nullptr;
+  const ElemArgs E = elem_args(S);
+  const VertArgs V = vert_args(S);
+  const AdjState Ad = adj_state(S);
+  const RedArgs R = red_args(S);
+  launch_apply_K(kModeDebug, E, V, Ad, R, S.jac, S.mu, 0, st);
+  launch_adj_gather(kModeDebug, V, Ad, R, 0, st);
+  const size_t n3 = 3 * (size_t)S.nv;
+  std::vector<double> qb(n3), kx(n3), x(n3), Winv((size_t)na * na);
+  std::vector<int> v(na);
+  std::vector<double> nrm(3 * (size_t)na);
+  PD_HIP(hipMemcpy(qb.data(), S.qbar, n3 * sizeof(double), hipMemcpyDeviceToHost));
+  PD_HIP(hipMemcpy(kx.data(), S.wv, n3 * sizeof(double), hipMemcpyDeviceToHost));
+  for (int a = 0; a < 3; ++a)
+    for (int i = S.L.nf; i < S.nv; ++i) kx[(size_t)a * S.nv + i] = 0.0;
+  for (size_t i = 0; i < n3; ++i) qb[i] += kx[i];
+  PD_HIP(hipMemcpy(S.z, qb.data(), n3 * sizeof(double), hipMemcpyHostToDevice));
+  solve_plain(S, S.z, S.p, nullptr, st);
+  PD_HIP(hipMemcpy(x.data(), S.p, n3 * sizeof(double), hipMemcpyDeviceToHost));
+  PD_HIP(hipMemcpy(Winv.data(), S.a_Winv, Winv.size() * sizeof(double), hipMemcpyDeviceToHost));
+  PD_HIP(hipMemcpy(v.data(), S.a_v, na * sizeof(int), hipMemcpyDeviceToHost));
+  PD_HIP(hipMemcpy(nrm.data(), S.a_n, nrm.size() * sizeof(double), hipMemcpyDeviceToHost));
+  std::vector<double> y(na);
+  for (int a = 0; a < na; ++a) {
+    double t = 0.0;
+    for (int ax = 0; ax < 3; ++ax) t += nrm[3 * (size_t)a + ax] * x[(size_t)ax * S.nv + v[a]];
+    y[a] = t;
+  }
+  for (int a = 0; a < na; ++a) {
+    double t = 0.0;
+    for (int b = 0; b < na; ++b) t += Winv[(size_t)a * na + b] * y[b];
+    g_out[S.a_rows[a]] = t;
+  }
+  return PD_OK;
+  PD_CATCH
+}
+
 int pd_scene_set_friction(pd_scene* scene, double mu) {
   if (!scene) {
     pdhot::g_last_error = "null scene";
@@ -1658,6 +1905,8 @@ int pd_scene_set_friction(pd_scene* scene, double mu) {
   PD_TRY
   Scene& S = scene->S;
   if (!S.contact_on) throw PdError{PD_ERR_INVALID_ARG, "friction needs obstacles (pd_scene_set_obstacles first)"};
+  if (mu > 0.0 && !S.att_v.empty())
+    throw PdError{PD_ERR_INVALID_ARG, "bilateral rows run with frictionless contact only"};
   if (!(mu >= 0.0) || !std::isfinite(mu)) throw PdError{PD_ERR_INVALID_ARG, "need a finite friction coefficient >= 0"};
   S.mu_f = mu;
   S.c_last_K = S.c_last_active = 0;
@@ -1762,8 +2011,10 @@ int pd_step_forward(pd_scene* scene, const double* q_t, const double* v_t, const
   }
   // the epilogue is stream-ordered: without contact rows nothing more is read back
   launch_epilogue(V, T, q_next, v_next, (double*)ckpt, st);
-  if (S.contact_on && ckpt)
-    launch_contact_ckpt(C, S.c_kmax, (double*)ckpt + (size_t)kCheckpointVecs * 3 * S.nv, st);
+  double* rec = (S.contact_on && ckpt) ? (double*)ckpt + (size_t)kCheckpointVecs * 3 * S.nv : nullptr;
+  if (rec) launch_contact_ckpt(C, S.c_kmax, S.rest_e, rec, st);
+  // restitution post-correction of the outgoing velocities (flags the rows in the record)
+  if (K > 0 && S.rest_e >= 0.0) launch_contact_restitution(V, C, v_t, v_next, S.rest_e, rec, S.c_kmax, st);
   int n_active = 0;
   double fb_res = 0.0;
   const int nl = S.mu_f > 0.0 ? 3 * K : K;  // impulse entries (three per contact with friction)
@@ -1942,13 +2193,24 @@ int pd_step_backward(pd_scene* scene, const void* ckpt, const double* gq_next, c
   // adjoint start: zero, or from the last solutions of this backward sweep;
   // with active rows the start must satisfy J_A mu = 0, so it is zero
   const int warm = n_active > 0 ? 0 : std::min(S.adj_warm, S.adj_hist);
+  // the restitution post-correction's adjoint: v bar of the corrected rows
+  // loses its normal part before the step (and dL/dv_t gains it after)
+  const double* rec = S.contact_on ? ck + (size_t)kCheckpointVecs * 3 * S.nv : nullptr;
+  const bool rest = S.contact_on && S.a_rest && gv_next;
+  if (rest) {
+    PD_HIP(hipMemcpyAsync(S.gv_rest, gv_next, 3 * (size_t)S.nv * sizeof(double), hipMemcpyDeviceToDevice, st));
+    launch_restitution_adj_pre(V, rec, S.c_kmax, S.gv_rest, S.rest_s, st);
+    gv_next = S.gv_rest;
+  }
   launch_bwd_prologue(V, Ad, gq_next, gv_next, warm, S.mu_h1, S.mu_h2, S.mu_h3, st);
   double bs[5] = {0, 0, 0, 0, 0};
   adjoint_solve(S, st, -1.0, bs, ck, warm > 0, n_active);
   if (S.adj_warm > 0) push_adjoint_history(S, st);
   // the gradient routing is stream-ordered; the statistics were read with the last check
   launch_grad_elem(E, V, ck, S.jac, S.mu, S.contrib, g_logE_accum, st);
+  if (S.n_mg > 0 && S.g_act) launch_muscle_grad(E, S.n_mg, S.mg_ptr, S.mg_tets, S.g_act, st);
   launch_grad_vert(V, S.mu, S.contrib, gv_next, gq_t, gv_t, gf_ext, st);
+  if (rest && gv_t) launch_restitution_adj_post(V, rec, S.c_kmax, S.rest_s, gv_t, st);
   // sticking rows constrain the slip from q_t and sliding rows' friction
   // depends on it: their multipliers reach dL/dq_t
   if (n_active > 0 && S.a_fric) launch_contact_route(V, contact_args(S, n_active, true), S.a_kind, gq_t, st);
@@ -2150,6 +2412,16 @@ struct pd_batch {
   SceneBundle* dB = nullptr;
   int* dbase[kBKKinds] = {};
   int nblk[kBKKinds] = {};
+  // block counts per kind and scene, and the maps over the scenes whose loop
+  // still runs (rebuilt at each host check of an eager loop): kinds x (ns + 1)
+  // prefix sums, then the scene list
+  std::vector<std::vector<int>> cnt;
+  int* dsid_all = nullptr;
+  int* dlive = nullptr;
+  std::vector<int> hlive;
+  int nlive = 0;
+  bool live_on = false;
+  int nblk_live[kBKKinds] = {};
   int block_local = kBlock, block_applyK = kBlock;
   int chunk = 0;        // iterations per host check (0 = adaptive)
   int use_graph = 0;
@@ -2207,7 +2479,19 @@ void batch_layout(pd_batch& B) {
     dfree(B.dbase[kind]);
     B.dbase[kind] = dalloc<int>(ns + 1);
     upload(B.dbase[kind], base);
+    B.cnt.resize(kBKKinds);
+    B.cnt[kind].assign(ns, 0);
+    for (int s = 0; s < ns; ++s) B.cnt[kind][s] = base[s + 1] - base[s];
   }
+  std::vector<int> ident(ns);
+  for (int s = 0; s < ns; ++s) ident[s] = s;
+  dfree(B.dsid_all);
+  B.dsid_all = dalloc<int>(ns);
+  upload(B.dsid_all, ident);
+  dfree(B.dlive);
+  B.dlive = dalloc<int>((size_t)kBKKinds * (ns + 1) + ns);
+  B.hlive.assign((size_t)kBKKinds * (ns + 1) + ns, 0);
+  B.live_on = false;
   B.nlev = 0;
   for (pd_scene* p : B.scenes) B.nlev = std::max(B.nlev, p->S.S.nlev);
   batch_free_graphs(B);
@@ -2232,7 +2516,38 @@ void batch_bundles(pd_batch& B) {
   PD_HIP(hipMemcpy(B.dB, h.data(), h.size() * sizeof(SceneBundle), hipMemcpyHostToDevice));
 }
 
-BatchMap bmap(const pd_batch& B, int kind) { return BatchMap{B.dB, B.dbase[kind], (int)B.scenes.size()}; }
+BatchMap bmap(const pd_batch& B, int kind) {
+  const int ns = (int)B.scenes.size();
+  if (B.live_on) return BatchMap{B.dB, B.dlive + (size_t)kind * (ns + 1), B.nlive, B.dlive + (size_t)kBKKinds * (ns + 1)};
+  return BatchMap{B.dB, B.dbase[kind], ns, B.dsid_all};
+}
+
+int bnblk(const pd_batch& B, int kind) { return B.live_on ? B.nblk_live[kind] : B.nblk[kind]; }
+
+// After a host check of an eager loop: list only the scenes whose loop still
+// runs (`running(s)`), so later launches carry no blocks of stopped scenes.
+// The stream is idle (the check synchronised it), so the tables are replaced
+// with a plain copy.  Graph replays keep the full maps.
+template <typename F>
+void batch_compact(pd_batch& B, F running) {
+  if (B.use_graph) return;
+  const int ns = (int)B.scenes.size();
+  std::vector<int> sid;
+  for (int s = 0; s < ns; ++s)
+    if (running(s)) sid.push_back(s);
+  const int n = (int)sid.size();
+  if (n == (B.live_on ? B.nlive : ns) || n == 0) return;
+  for (int kind = 0; kind < kBKKinds; ++kind) {
+    int* base = B.hlive.data() + (size_t)kind * (ns + 1);
+    base[0] = 0;
+    for (int j = 0; j < n; ++j) base[j + 1] = base[j] + B.cnt[kind][sid[j]];
+    B.nblk_live[kind] = base[n];
+  }
+  std::copy(sid.begin(), sid.end(), B.hlive.begin() + (size_t)kBKKinds * (ns + 1));
+  PD_HIP(hipMemcpy(B.dlive, B.hlive.data(), B.hlive.size() * sizeof(int), hipMemcpyHostToDevice));
+  B.nlive = n;
+  B.live_on = true;
+}
 
 // the interface solve of every scene, level by level
 void batch_sep(const pd_batch& B, int adjoint, hipStream_t st) {
@@ -2241,8 +2556,8 @@ void batch_sep(const pd_batch& B, int adjoint, hipStream_t st) {
   for (int l = 0; l < kMaxLevels; ++l) {
     Mf[l] = bmap(B, kBKSepF + l);
     Mb[l] = bmap(B, kBKSepB + l);
-    nf[l] = B.nblk[kBKSepF + l];
-    nb[l] = B.nblk[kBKSepB + l];
+    nf[l] = bnblk(B, kBKSepF + l);
+    nb[l] = bnblk(B, kBKSepB + l);
   }
   launch_b_sep(Mf, nf, Mb, nb, B.nlev, adjoint, st);
 }
@@ -2256,20 +2571,20 @@ void batch_sep(const pd_batch& B, int adjoint, hipStream_t st) {
   } while (0)
 
 void batch_fwd_iter(pd_batch& B, int k, hipStream_t st) {
-  PD_BTIMED(B, kKLocal, st, launch_b_local(bmap(B, kBKLocal), B.nblk[kBKLocal], B.block_local, k, st));
-  PD_BTIMED(B, kKGather, st, launch_b_gather_fwd(bmap(B, kBKGather), B.nblk[kBKGather], k, st));
-  PD_BTIMED(B, kKEb, st, launch_b_Eb(kModeFwd, bmap(B, kBKEb), B.nblk[kBKEb], k, st));
+  PD_BTIMED(B, kKLocal, st, launch_b_local(bmap(B, kBKLocal), bnblk(B, kBKLocal), B.block_local, k, st));
+  PD_BTIMED(B, kKGather, st, launch_b_gather_fwd(bmap(B, kBKGather), bnblk(B, kBKGather), k, st));
+  PD_BTIMED(B, kKEb, st, launch_b_Eb(kModeFwd, bmap(B, kBKEb), bnblk(B, kBKEb), k, st));
   PD_BTIMED(B, kKTop, st, batch_sep(B, 0, st));
-  PD_BTIMED(B, kKBottom, st, launch_b_bottom(kModeFwd, bmap(B, kBKBottom), B.nblk[kBKBottom], k, st));
+  PD_BTIMED(B, kKBottom, st, launch_b_bottom(kModeFwd, bmap(B, kBKBottom), bnblk(B, kBKBottom), k, st));
 }
 
 void batch_adj_iter(pd_batch& B, int it, hipStream_t st) {
   PD_BTIMED(B, kKApplyK, st,
-            launch_b_apply_K(kModePCG, bmap(B, kBKApplyK), B.nblk[kBKApplyK], B.block_applyK, it, st));
-  launch_b_adj_gather(kModePCG, bmap(B, kBKGather), B.nblk[kBKGather], it, st);
-  PD_BTIMED(B, kKEb, st, launch_b_Eb(kModePCG, bmap(B, kBKEb), B.nblk[kBKEb], it, st));
+            launch_b_apply_K(kModePCG, bmap(B, kBKApplyK), bnblk(B, kBKApplyK), B.block_applyK, it, st));
+  launch_b_adj_gather(kModePCG, bmap(B, kBKGather), bnblk(B, kBKGather), it, st);
+  PD_BTIMED(B, kKEb, st, launch_b_Eb(kModePCG, bmap(B, kBKEb), bnblk(B, kBKEb), it, st));
   PD_BTIMED(B, kKTop, st, batch_sep(B, 1, st));
-  PD_BTIMED(B, kKBottom, st, launch_b_bottom(kModePCG, bmap(B, kBKBottom), B.nblk[kBKBottom], it, st));
+  PD_BTIMED(B, kKBottom, st, launch_b_bottom(kModePCG, bmap(B, kBKBottom), bnblk(B, kBKBottom), it, st));
 }
 
 // iterations k0 .. k1-1 of a loop, replayed from a graph when enabled
@@ -2302,7 +2617,7 @@ void batch_chunk(pd_batch& B, int loop, int k0, int k1, hipStream_t st, F iter) 
 // all scenes' control blocks and statistics to the host
 void batch_flags(pd_batch& B, hipStream_t st) {
   const int ns = (int)B.scenes.size();
-  launch_b_flags(BatchMap{B.dB, B.dbase[0], ns}, B.dctl, B.ddstat, st);
+  launch_b_flags(BatchMap{B.dB, B.dbase[0], ns, B.dsid_all}, B.dctl, B.ddstat, st);
   PD_HIP(hipMemcpyAsync(B.hctl, B.dctl, sizeof(int) * kCtlTotal * ns, hipMemcpyDeviceToHost, st));
   PD_HIP(hipMemcpyAsync(B.hdstat, B.ddstat, sizeof(double) * 32 * ns, hipMemcpyDeviceToHost, st));
   PD_HIP(hipStreamSynchronize(st));
@@ -2325,6 +2640,7 @@ int pd_batch_create(pd_scene* const* scenes, int n, pd_batch** out) {
       if (scenes[s]->S.stale) throw PdError{PD_ERR_STALE_FACTOR, "scene factor is stale"};
       if (scenes[s]->S.adj_method != 0) throw PdError{PD_ERR_INVALID_ARG, "batches run the PCG adjoint"};
       if (scenes[s]->S.contact_on) throw PdError{PD_ERR_INVALID_ARG, "batched scenes run without obstacles"};
+      if (scenes[s]->S.n_mg > 0) throw PdError{PD_ERR_INVALID_ARG, "batched scenes run without muscles"};
       B->scenes.push_back(scenes[s]);
     }
     batch_bundles(*B);
@@ -2351,6 +2667,8 @@ int pd_batch_destroy(pd_batch* B) {
   for (hipEvent_t e : B->kt.ev) (void)hipEventDestroy(e);
   dfree(B->dB);
   for (int k = 0; k < kBKKinds; ++k) dfree(B->dbase[k]);
+  dfree(B->dsid_all);
+  dfree(B->dlive);
   dfree(B->dctl);
   dfree(B->ddstat);
   if (B->hctl) (void)hipHostFree(B->hctl);
@@ -2406,6 +2724,7 @@ int pd_batch_step_forward(pd_batch* B, const double* const* q_t, const double* c
   const int fixed = B->chunk > 0 ? B->chunk : (B->use_graph ? 4 : 0);
   int chunk = fixed > 0 ? fixed : std::max(3, B->last_fwd + 1);
   bool all = false;
+  B->live_on = false;
   for (;;) {
     const int kend = std::min(k + chunk, kmax);
     batch_chunk(*B, 0, k, kend, st, batch_fwd_iter);
@@ -2414,8 +2733,10 @@ int pd_batch_step_forward(pd_batch* B, const double* const* q_t, const double* c
     all = true;
     for (int s = 0; s < ns; ++s) all = all && B->hctl[s * kCtlTotal + kCtlDone];
     if (all || k >= kmax) break;
+    batch_compact(*B, [&](int s) { return !B->hctl[s * kCtlTotal + kCtlDone]; });
     chunk = fixed > 0 ? fixed : 2;
   }
+  B->live_on = false;
   int worst = 0, most = 0;
   for (int s = 0; s < ns; ++s) {
     Scene& S = B->scenes[s]->S;
@@ -2476,6 +2797,7 @@ int pd_batch_step_backward(pd_batch* B, const void* const* ckpt, const double* c
     launch_bwd_elem(E, V, R, ck, S.eps_tr, -1.0, tr, S.jac, S.dstat + 4, S.ctl + kCtlAdj, 4, st);
     kmax = std::max(kmax, S.kmax_bwd);
   }
+  B->live_on = false;
   if (any_warm) {  // r = q bar - (A~ - K) mu0 (a zero mu0 gives r = q bar again)
     launch_b_apply_K(kModeAmK, bmap(*B, kBKApplyK), B->nblk[kBKApplyK], B->block_applyK, 0, st);
     launch_b_adj_gather(kModeInit, bmap(*B, kBKGather), B->nblk[kBKGather], 0, st);
@@ -2494,8 +2816,10 @@ int pd_batch_step_backward(pd_batch* B, const void* const* ckpt, const double* c
     bool all = true;
     for (int s = 0; s < ns; ++s) all = all && B->hctl[s * kCtlTotal + kCtlAdj + 2];
     if (all || it > kmax) break;
+    batch_compact(*B, [&](int s) { return !B->hctl[s * kCtlTotal + kCtlAdj + 2]; });
     chunk = fixed > 0 ? fixed : 4;
   }
+  B->live_on = false;
   int worst = 0, most = 0;
   for (int s = 0; s < ns; ++s) {
     Scene& S = B->scenes[s]->S;

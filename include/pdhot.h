@@ -506,6 +506,13 @@ int pd_mpn_init_params(pd_mpn* mpn, uint64_t seed);
 /* Host FP32 parameter vectors of exactly the parameter count. */
 int pd_mpn_set_params(pd_mpn* mpn, const float* host, int64_t n);
 int pd_mpn_get_params(const pd_mpn* mpn, float* host, int64_t n);
+/* One network over several meshes (spec: one instance per mesh, shared
+ * weights): dst drops its own parameters, gradient and Adam moments and uses
+ * src's from now on, so a loss_grad on any mesh's instance writes the shared
+ * gradient and an Adam step on src updates every instance.  Both must have
+ * the same layer shapes and compute mode; src must outlive dst.  Waits for
+ * all device work.  Errors: PD_ERR_INVALID_ARG for other shapes. */
+int pd_mpn_share_params(pd_mpn* dst, pd_mpn* src);
 /* Gradient of the last pd_mpn_loss_grad (host copy). */
 int pd_mpn_get_grads(const pd_mpn* mpn, float* host, int64_t n);
 /* s_out: the scale of the predicted correction (positions per unit output);

@@ -34,7 +34,7 @@ EXPORTED = ["pd_scene_create", "pd_scene_destroy", "pd_scene_set_material", "pd_
             "pd_scene_factor_nnz", "pd_batch_kernel_timer", "pd_batch_kernel_timer_read",
             "pd_scene_set_friction", "pd_contact_impulses", "pd_apply_Ainv_noalloc", "pd_scene_set_muscles",
             "pd_scene_set_activation", "pd_scene_set_activation_grad", "pd_scene_set_attachments",
-            "pd_scene_set_restitution", "pd_contact_gap_grad"]
+            "pd_scene_set_restitution", "pd_contact_gap_grad", "pd_mpn_share_params"]
 
 
 class pd_mesh_desc(ctypes.Structure):
@@ -118,6 +118,7 @@ def lib() -> ctypes.CDLL:
     L.pd_mpn_init_params.argtypes = [vp, ctypes.c_uint64]
     L.pd_mpn_set_params.argtypes = [vp, vp, ctypes.c_int64]
     L.pd_mpn_get_params.argtypes = [vp, vp, ctypes.c_int64]
+    L.pd_mpn_share_params.argtypes = [vp, vp]
     L.pd_mpn_get_grads.argtypes = [vp, vp, ctypes.c_int64]
     L.pd_mpn_set_output_scale.argtypes = [vp, dbl]
     L.pd_mpn_forward.argtypes = [vp, vp, vp, vp, vp, vp, vp, vp]
@@ -473,6 +474,12 @@ class Mpn:
     def set_params(self, theta):
         a = np.ascontiguousarray(theta, dtype=np.float32)
         check(lib().pd_mpn_set_params(self.ptr, a.ctypes.data, a.size), "pd_mpn_set_params")
+
+    def share_params(self, src: "Mpn"):
+        """Use src's weights, gradient and Adam moments from now on (pd_mpn_share_params); src must outlive
+        this network."""
+        check(lib().pd_mpn_share_params(self.ptr, src.ptr), "pd_mpn_share_params")
+        self._shared_src = src
 
     def get_params(self) -> np.ndarray:
         a = np.zeros(self.n_params, dtype=np.float32)

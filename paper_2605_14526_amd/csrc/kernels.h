@@ -79,11 +79,14 @@ constexpr int kTopChunk = PD_TOP_CHUNK;        // interface solve, rows of wide 
 // for a wide node (s + b >= kSepWide) 4 rows, one per wave, in chunks of
 // 64 x kTopChunk; the node's [y_n ; x_struct] is staged in LDS kSepTile
 // entries at a time.  A forward row takes chunks of 64 x kSepFwdChunk.
+// (2 rows per wave, chunks of 4: on the 64-scene identification batch 1842
+// against 1778 scene-steps/s at 4 and 2, 1558 at 8 and 1, 1795-1830 with one
+// row per wave)
 #ifndef PD_SEP_RPW
-#define PD_SEP_RPW 4
+#define PD_SEP_RPW 2
 #endif
 #ifndef PD_SEP_CHUNK
-#define PD_SEP_CHUNK 2
+#define PD_SEP_CHUNK 4
 #endif
 #ifndef PD_SEP_FWD_CHUNK
 #define PD_SEP_FWD_CHUNK 4

@@ -536,6 +536,7 @@ struct MpnImpl {
   size_t part_cap = 0;
   long long step = 0;
   std::vector<int> hpinned;
+  bool shared = false;  // P, G, Mo, Vo belong to another instance (pd_mpn_share_params)
 };
 
 static int mpn_grid_rows(int rows, int per) { return (rows + per - 1) / per; }
@@ -643,6 +644,7 @@ void mpn_free(MpnImpl& N) {
   dfree(const_cast<int*&>(A.out_ptr)); dfree(const_cast<int*&>(A.out_eid));
   dfree(A.x0); dfree(A.dagg);
   A.agg = nullptr;
+  if (N.shared) N.P = N.G = N.Mo = N.Vo = nullptr;
   dfree(N.P); dfree(N.G); dfree(N.Mo); dfree(N.Vo);
   for (int l = 0; l <= kMpnLayers; ++l) dfree(N.hbuf[l]);
   for (int l = 0; l < kMpnLayers; ++l) { dfree(N.zm[l]); dfree(N.zn[l]); dfree(N.aggl[l]); }
@@ -840,6 +842,26 @@ int pd_mpn_set_params(pd_mpn* m, const float* host, int64_t n) {
   MPN_HIP(hipMemset(m->N.Mo, 0, n * sizeof(float)));
   MPN_HIP(hipMemset(m->N.Vo, 0, n * sizeof(float)));
   m->N.step = 0;
+  return PD_OK;
+  MPN_CATCH
+}
+
+int pd_mpn_share_params(pd_mpn* dst, pd_mpn* src) {
+  if (!dst || !src || dst == src || dst->N.off.n != src->N.off.n || dst->N.compute != src->N.compute) {
+    set_last_error("null argument, the same network, or networks of different shapes");
+    return PD_ERR_INVALID_ARG;
+  }
+  MPN_TRY
+  MPN_HIP(hipDeviceSynchronize());  // kernels of dst may still use its own buffers
+  MpnImpl& D = dst->N;
+  if (!D.shared) {
+    dfree(D.P); dfree(D.G); dfree(D.Mo); dfree(D.Vo);
+  }
+  D.P = src->N.P;
+  D.G = src->N.G;
+  D.Mo = src->N.Mo;
+  D.Vo = src->N.Vo;
+  D.shared = true;
   return PD_OK;
   MPN_CATCH
 }

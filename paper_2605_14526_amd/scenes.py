@@ -416,6 +416,20 @@ def drop_family(k: int, res: int = 27, steps: int = 100, friction: float = 0.0) 
     return sc
 
 
+def shape_family(k: int, res: int = 27, steps: int = 100, friction: float = 0.0) -> Scene:
+    """Member k of a family of drops of different blobs (the learned start's training and held-out scenes):
+    the blob is drop_blob's with seed 5000 + k (another union of spheres, so another mesh), and the initial
+    velocity is drawn as in drop_family from seed 3100 + k."""
+    sc = drop_blob(res=res, seed=5000 + k, steps=steps, friction=friction)
+    rng = _rng(3100 + k)
+    vz = rng.uniform(0.5, 1.5)
+    vx, vy = rng.uniform(-0.5, 0.5, 2)
+    sc.v_init = np.array([vx, vy, -vz])
+    sc.target_centroid = sc.X.mean(axis=0) + rng.uniform(-0.02, 0.02, 3)
+    sc.name = f"shape_family_r{res}_{k}"
+    return sc
+
+
 def anchored_blob(ne: float, seed: int, contrast: float = 30.0, nu: float = 0.45, steps: int = 50,
                   h: float = 0.01, tip_force: float = 20.0) -> Scene:
     """A blob without obstacles for multi-scene identification: the implicit blob of drop_blob (shape from

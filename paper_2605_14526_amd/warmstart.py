@@ -135,3 +135,25 @@ def train_for(sc_family, n_train: int, steps: int, epochs: int, torch, seed: int
     hist = train(net, samples, epochs, lr=lr, seed=seed, log_every=log_every, lr_decay=0.9)
     torch.cuda.synchronize()
     return net, hist, time.perf_counter() - t0, len(samples)
+
+
+def train_shared(master: Mpn, nets: List[Mpn], samples: List[List[Sample]], epochs: int, lr: float = 1e-3,
+                 seed: int = 0, lr_decay: float = 1.0):
+    """Adam over the samples of several meshes with one set of weights: nets[k] (sharing master's weights,
+    gradient and moments) computes the gradient of a sample of mesh k, master takes the Adam step.  The
+    samples of all meshes are visited in one seeded shuffled order; returns the loss of each epoch's last
+    sample."""
+    rng = np.random.Generator(np.random.PCG64(seed))
+    flat = [(k, i) for k, ss in enumerate(samples) for i in range(len(ss))]
+    hist = []
+    for ep in range(epochs):
+        order = rng.permutation(len(flat))
+        rate = lr * (lr_decay ** ep)
+        loss = None
+        for j, idx in enumerate(order):
+            k, i = flat[idx]
+            s = samples[k][i]
+            loss = nets[k].loss_grad(s.q_t, s.v_tm1, s.v_t, s.f, s.logw, s.q_next, want_loss=j == len(order) - 1)
+            master.adam_step(rate)
+        hist.append(loss)
+    return hist

@@ -148,3 +148,37 @@ def test_learned_start_solve_matches_oracle(th, trained):
     assert worst < 1e-9, (worst, its)
     # the learned start is not the plain one: the first iterates differ from q_t
     assert np.abs(q0h - q).max() > 0
+
+
+def test_shared_weights_across_meshes(th):
+    """One set of weights over two meshes (pd_mpn_share_params): the sharing instance computes exactly what
+    an instance holding a copy of the weights computes, its gradient lands in the shared buffer (the
+    reference gradient on its own mesh), and an Adam step on the owner moves the weights both read."""
+    from paper_2605_14526_amd.binding import Mpn
+    net_a, sc_a, gin_a, qn_a, _, _, _, _, s_out = case(th, 1)
+    sc_b = scenes.small_beam(5, 2, 3, seed=9, contrast=10.0, nu=0.45)
+    rng = np.random.Generator(np.random.PCG64(4))
+    d = lambda a: th.tensor(np.ascontiguousarray(a), dtype=th.float64, device="cuda")  # noqa: E731
+    gin_b = [d(sc_b.X + 0.01 * rng.standard_normal(sc_b.X.shape)), d(0.3 * rng.standard_normal(sc_b.X.shape)),
+             d(0.3 * rng.standard_normal(sc_b.X.shape)), d(rng.standard_normal(sc_b.X.shape)),
+             d(rng.standard_normal(sc_b.n_v))]
+    qn_b = d(gin_b[0].cpu().numpy() + sc_b.h * gin_b[2].cpu().numpy() + s_out * rng.standard_normal(sc_b.X.shape))
+    shared = Mpn.for_scene(sc_b, compute=1, edge_weight=2.0)
+    shared.share_params(net_a)
+    shared.set_output_scale(s_out)
+    copy = Mpn.for_scene(sc_b, compute=1, edge_weight=2.0)
+    copy.set_params(net_a.get_params())
+    copy.set_output_scale(s_out)
+    assert np.array_equal(shared.get_params(), net_a.get_params())
+    assert np.array_equal(shared.forward(*gin_b).cpu().numpy(), copy.forward(*gin_b).cpu().numpy())
+    # the gradient of mesh b, computed by the sharing instance, is the copy's
+    la = shared.loss_grad(*gin_b, qn_b)
+    lb = copy.loss_grad(*gin_b, qn_b)
+    assert la == lb and np.array_equal(net_a.get_grads(), copy.get_grads())
+    before = net_a.get_params()
+    net_a.adam_step(1e-3)
+    after = shared.get_params()
+    assert not np.array_equal(before, after) and np.array_equal(after, net_a.get_params())
+    shared.close()
+    copy.close()
+    assert np.array_equal(net_a.get_params(), after)  # the owner's buffers survive the sharer's teardown

@@ -2431,6 +2431,10 @@ struct pd_batch {
   int* hctl = nullptr;
   double* hdstat = nullptr;
   int last_fwd = 4, last_adj = 8;
+  // the fewest iterations any scene took in the last call: an eager loop
+  // checks first there (no scene is expected to stop earlier), then every
+  // few iterations, so stopped scenes leave the launches soon
+  int first_fwd = 4, first_adj = 8;
   std::vector<std::pair<long long, hipGraphExec_t>> graphs;
   // graphs are captured and replayed on the batch's own stream (the caller's
   // may be the legacy default stream, which cannot be captured), ordered
@@ -2722,7 +2726,7 @@ int pd_batch_step_forward(pd_batch* B, const double* const* q_t, const double* c
   int k = 0;
   // graph replay wants fixed chunk boundaries (one graph per chunk start)
   const int fixed = B->chunk > 0 ? B->chunk : (B->use_graph ? 4 : 0);
-  int chunk = fixed > 0 ? fixed : std::max(3, B->last_fwd + 1);
+  int chunk = fixed > 0 ? fixed : std::max(3, B->first_fwd + 1);
   bool all = false;
   B->live_on = false;
   for (;;) {
@@ -2760,6 +2764,8 @@ int pd_batch_step_forward(pd_batch* B, const double* const* q_t, const double* c
   }
   if (B->kt.which >= 0 && !B->use_graph) kt_flush(B->kt);
   B->last_fwd = most;
+  B->first_fwd = ns > 0 ? B->hctl[kCtlIters] : 4;
+  for (int s = 0; s < ns; ++s) B->first_fwd = std::min(B->first_fwd, B->hctl[s * kCtlTotal + kCtlIters]);
   PD_HIP(hipStreamSynchronize(st));
   PD_HIP(hipGetLastError());
   return worst == 0 ? PD_OK : PD_NOT_CONVERGED;
@@ -2807,7 +2813,7 @@ int pd_batch_step_backward(pd_batch* B, const void* const* ckpt, const double* c
   PD_BTIMED(*B, kKBottom, st, launch_b_bottom(kModePCGInit, bmap(*B, kBKBottom), B->nblk[kBKBottom], 0, st));
   int it = 0;
   const int fixed = B->chunk > 0 ? B->chunk : (B->use_graph ? 4 : 0);
-  int chunk = fixed > 0 ? fixed : std::max(4, B->last_adj + 1);
+  int chunk = fixed > 0 ? fixed : std::max(4, B->first_adj + 1);
   for (;;) {
     const int iend = std::min(it + chunk, kmax + 1);
     batch_chunk(*B, 1, it, iend, st, batch_adj_iter);
@@ -2848,6 +2854,8 @@ int pd_batch_step_backward(pd_batch* B, const void* const* ckpt, const double* c
   }
   if (B->kt.which >= 0 && !B->use_graph) kt_flush(B->kt);
   B->last_adj = most;
+  B->first_adj = ns > 0 ? B->hctl[kCtlAdj] : 8;
+  for (int s = 0; s < ns; ++s) B->first_adj = std::min(B->first_adj, B->hctl[s * kCtlTotal + kCtlAdj]);
   PD_HIP(hipStreamSynchronize(st));
   PD_HIP(hipGetLastError());
   return worst == 0 ? PD_OK : PD_NOT_CONVERGED;

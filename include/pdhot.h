@@ -448,6 +448,11 @@ int pd_batch_destroy(pd_batch* batch);
  * convergence checks (0 = adaptive; graphs use 4 then), and use_graph = 1 to
  * capture each chunk of iterations once into a HIP graph and replay it. */
 int pd_batch_config(pd_batch* batch, int block_local, int block_applyK, int iters_per_check, int use_graph);
+/* Graph replay of chunks of iters_per_chunk iterations (captured at first
+ * use, one graph per chunk start); 0 returns to eager launches with adaptive
+ * host checks.  The workgroup sizes stay as configured.  The same as
+ * pd_batch_config with use_graph = (iters_per_chunk > 0). */
+int pd_batch_capture_graph(pd_batch* batch, int iters_per_chunk);
 /* pd_step_forward / pd_step_backward on every scene of the batch. stats: arrays
  * of n entries or NULL. Returns PD_NOT_CONVERGED if any scene did not converge. */
 int pd_batch_step_forward(pd_batch* batch, const double* const* q_t, const double* const* v_t,

@@ -34,7 +34,7 @@ EXPORTED = ["pd_scene_create", "pd_scene_destroy", "pd_scene_set_material", "pd_
             "pd_scene_factor_nnz", "pd_batch_kernel_timer", "pd_batch_kernel_timer_read",
             "pd_scene_set_friction", "pd_contact_impulses", "pd_apply_Ainv_noalloc", "pd_scene_set_muscles",
             "pd_scene_set_activation", "pd_scene_set_activation_grad", "pd_scene_set_attachments",
-            "pd_scene_set_restitution", "pd_contact_gap_grad", "pd_mpn_share_params"]
+            "pd_scene_set_restitution", "pd_contact_gap_grad", "pd_mpn_share_params", "pd_batch_capture_graph"]
 
 
 class pd_mesh_desc(ctypes.Structure):
@@ -119,6 +119,7 @@ def lib() -> ctypes.CDLL:
     L.pd_mpn_set_params.argtypes = [vp, vp, ctypes.c_int64]
     L.pd_mpn_get_params.argtypes = [vp, vp, ctypes.c_int64]
     L.pd_mpn_share_params.argtypes = [vp, vp]
+    L.pd_batch_capture_graph.argtypes = [vp, i32]
     L.pd_mpn_get_grads.argtypes = [vp, vp, ctypes.c_int64]
     L.pd_mpn_set_output_scale.argtypes = [vp, dbl]
     L.pd_mpn_forward.argtypes = [vp, vp, vp, vp, vp, vp, vp, vp]
@@ -547,6 +548,11 @@ class Batch:
                                     int(use_graph)), "pd_batch_config")
         self.cfg = dict(block_local=block_local, block_applyK=block_applyK, iters_per_check=iters_per_check,
                         use_graph=use_graph)
+
+    def capture_graph(self, iters_per_chunk: int):
+        """Graph replay of chunks of iters_per_chunk iterations (pd_batch_capture_graph; 0: eager)."""
+        check(lib().pd_batch_capture_graph(self.ptr, int(iters_per_chunk)), "pd_batch_capture_graph")
+        self.cfg.update(iters_per_check=int(iters_per_chunk), use_graph=int(iters_per_chunk > 0))
 
     def kernel_timer(self, kernel: int):
         check(lib().pd_batch_kernel_timer(self.ptr, int(kernel)), "pd_batch_kernel_timer")

@@ -2700,6 +2700,14 @@ int pd_batch_config(pd_batch* B, int block_local, int block_applyK, int iters_pe
   PD_CATCH
 }
 
+int pd_batch_capture_graph(pd_batch* B, int iters_per_chunk) {
+  if (!B || iters_per_chunk < 0) {
+    pdhot::g_last_error = "null batch or negative chunk";
+    return PD_ERR_INVALID_ARG;
+  }
+  return pd_batch_config(B, B->block_local, B->block_applyK, iters_per_chunk, iters_per_chunk > 0 ? 1 : 0);
+}
+
 int pd_batch_step_forward(pd_batch* B, const double* const* q_t, const double* const* v_t,
                           const double* const* f_ext, const double* const* q0, double* const* q_next,
                           double* const* v_next, void* const* ckpt, pd_fwd_stats* stats, void* stream) {

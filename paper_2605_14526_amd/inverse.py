@@ -16,6 +16,8 @@ from __future__ import annotations
 from dataclasses import dataclass, field
 from typing import Callable, List, Tuple
 
+import numpy as np
+
 
 @dataclass
 class LbfgsResult:
@@ -116,5 +118,45 @@ def trajectory_objective(scene, sc, steps: int, observed, mass, torch, ckpt_ever
         loss = (m * (traj[1:] - obs[1:]) ** 2).sum()
         loss.backward()
         return float(loss.detach()), le.grad.detach()
+
+    return fg
+
+
+def activation_objective(scene, sc, steps: int, tip_mask, target, torch):
+    """The muscle-driven reaching task of one scene as a function of its
+    groups' activations a: L(a) = |mean of q_T over the tip vertices - target|^2
+    after a rollout of `steps` steps from the scene's initial state.  Returns
+    fg(a) -> (L, dL/da) for lbfgs; each call sets the activations (no
+    refactorization: they change b, not A~), rolls forward with checkpoints
+    and sweeps the adjoint back, the library adding dL/da into a device buffer
+    (pd_scene_set_activation_grad)."""
+    dev = lambda a: torch.tensor(a, dtype=torch.float64, device="cuda")  # noqa: E731
+    q0, v0 = dev(sc.q0()), dev(sc.v0())
+    forces = [dev(sc.f_ext(t)) for t in range(steps)]
+    tip = torch.tensor(np.asarray(tip_mask, bool), device="cuda")
+    tgt = dev(np.asarray(target, float))
+    n_tip = int(tip.sum())
+    g_act = torch.zeros(scene.n_groups, dtype=torch.float64, device="cuda")
+    scene.set_activation_grad(g_act)
+
+    def fg(a):
+        scene.set_activation(a.detach().contiguous())
+        q, v = q0, v0
+        cks = []
+        for t in range(steps):
+            ck = scene.new_ckpt()
+            q, v, _ = scene.step_forward(q, v, forces[t], ckpt=ck)
+            cks.append(ck)
+        d = q[tip].mean(dim=0) - tgt
+        loss = float((d * d).sum())
+        gq = torch.zeros_like(q)
+        gq[tip] = 2.0 * d / n_tip
+        gv = torch.zeros_like(q)
+        g_act.zero_()
+        scene.adjoint_reset()
+        for ck in reversed(cks):
+            gq, gv, _, _, _ = scene.step_backward(ck, gq, gv)
+        torch.cuda.synchronize()
+        return loss, g_act.clone()
 
     return fg

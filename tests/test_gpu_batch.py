@@ -48,12 +48,14 @@ def run_alone(th, scs, T, adj_warm=2):
     return out
 
 
-def run_batched(th, scs, T, adj_warm=2, **cfg):
+def run_batched(th, scs, T, adj_warm=2, graph_chunk=None, **cfg):
     from paper_2605_14526_amd.binding import Batch, Scene
     gs = [Scene.from_scene(sc, adj_warm=adj_warm) for sc in scs]
     B = Batch(gs)
     if cfg:
         B.config(**cfg)
+    if graph_chunk is not None:
+        B.capture_graph(graph_chunk)
     q = [d(th, sc.q0()) for sc in scs]
     v = [d(th, sc.v0()) for sc in scs]
     cks = []
@@ -83,6 +85,19 @@ def test_batch_is_bitwise_each_scene_alone(th, cfg):
     T = 4
     alone = run_alone(th, scs, T)
     together = run_batched(th, scs, T, **cfg)
+    for a, b in zip(alone, together):
+        assert a[3] == b[3]
+        for x, y in zip(a[:3], b[:3]):
+            assert np.array_equal(x, y)
+
+
+def test_capture_graph_call_is_bitwise_each_scene_alone(th):
+    """pd_batch_capture_graph (graph replay in chunks of 3 iterations) keeps every scene bitwise its results
+    alone."""
+    scs = batch_scenes()
+    T = 3
+    alone = run_alone(th, scs, T)
+    together = run_batched(th, scs, T, graph_chunk=3)
     for a, b in zip(alone, together):
         assert a[3] == b[3]
         for x, y in zip(a[:3], b[:3]):

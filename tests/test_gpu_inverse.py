@@ -78,3 +78,51 @@ def test_lbfgs_identification_reduces_loss(th):
     res = lbfgs(fg, th.tensor(log_E0, dtype=th.float64, device="cuda"), iters=12, memory=8, max_step=1.0)
     assert res.f < 1e-1 * res.history[0], res.history
     assert all(a >= b for a, b in zip(res.history, res.history[1:]))
+
+
+def tendon_task(th, T):
+    """A helical-fibre tendon beam whose tip must reach the position that seeded activations reach after
+    T steps (a realisable target), started from uniform activations."""
+    from paper_2605_14526_amd.binding import Scene
+    sc = scenes.tendon_beam(2, 6, layout=1, steps=T, w_m=2e5, gravity=(0.0, 0.0, -9.81))
+    g = Scene.from_scene(sc, eps_rel=1e-12, eps_abs=1e-16, eps_adj=1e-12)
+    tip = sc.X[:, 2] > sc.X[:, 2].max() - 1e-9
+    a_true = np.random.Generator(np.random.PCG64(61)).uniform(0.0, 0.3, 16)
+    dev = lambda a: th.tensor(np.ascontiguousarray(a), dtype=th.float64, device="cuda")  # noqa: E731
+    g.set_activation(dev(a_true))
+    q, v = dev(sc.q0()), dev(sc.v0())
+    for t in range(T):
+        q, v, _ = g.step_forward(q, v, dev(sc.f_ext(t)))
+    target = q.cpu().numpy()[tip].mean(axis=0)
+    return sc, g, tip, target, np.full(16, 0.15), dev
+
+
+def test_activation_gradient_matches_oracle(th):
+    """dL/da of the reaching loss through the library against the oracle's adjoint sweep (same rollout)."""
+    from paper_2605_14526_amd.inverse import activation_objective
+    T = 10
+    sc, g, tip, target, a0, dev = tendon_task(th, T)
+    fg = activation_objective(g, sc, T, tip, target, th)
+    L, ga = fg(dev(a0))
+    o = O.OracleScene(sc, eps_rel=1e-12, eps_abs=1e-16, eps_adj=1e-13)
+    o.set_muscles(sc.muscle_group, sc.muscle_fibre, sc.muscle_w)
+    o.set_activation(a0)
+    q, v, ck, _ = O.rollout(o, T)
+    d = q[tip].mean(axis=0) - target
+    gq = np.zeros_like(q)
+    gq[tip] = 2.0 * d / tip.sum()
+    o.g_act[:] = 0.0
+    O.rollout_backward(o, ck, gq, np.zeros_like(gq), adj_mode=1)
+    assert abs(L - float(d @ d)) <= 1e-8 * float(d @ d)
+    assert np.abs(ga.cpu().numpy() - o.g_act).max() <= 1e-6 * np.abs(o.g_act).max()
+
+
+def test_lbfgs_activation_reaching_reduces_loss(th):
+    """L-BFGS over the 16 activations (the muscle-driven reaching task in miniature): ten iterations cut the
+    loss by more than 100x, without refactorizing."""
+    from paper_2605_14526_amd.inverse import activation_objective, lbfgs
+    T = 10
+    sc, g, tip, target, a0, dev = tendon_task(th, T)
+    fg = activation_objective(g, sc, T, tip, target, th)
+    res = lbfgs(fg, dev(a0), iters=10, memory=8, max_step=0.05)
+    assert res.f < 1e-2 * res.history[0], res.history

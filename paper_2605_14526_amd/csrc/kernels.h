@@ -273,7 +273,25 @@ struct SceneBundle {
   StepState St;
   AdjState A;
   RedArgs R;
-  const double* jac;
+  double* jac;
+};
+
+// Per-call arguments of one scene of a batched step (a device table with one
+// entry per scene, written by the host at the start of each call): the
+// caller's arrays of the forward step ...
+struct BFwdIO {
+  const double *q_t, *v_t, *f, *q0;
+  double *q_next, *v_next, *ckpt;
+  int inertial;
+};
+
+// ... and of the backward step (h1..h3: the adjoint history the start is
+// extrapolated from; mu_copy: where this step's mu is kept for the next one)
+struct BBwdIO {
+  const double *gq, *gv, *ck, *h1, *h2, *h3;
+  double *gq_t, *gv_t, *gf, *g_logE, *mu_copy;
+  double eps_tr;
+  int warm, tr;
 };
 
 // Block-to-scene map of a batched launch over ns of the batch's scenes: the
@@ -289,8 +307,10 @@ struct BatchMap {
 
 // block-map kinds of a batch: the stages, then the forward (kBKSepF + l - 1)
 // and backward (kBKSepB + l - 1) launches of interface-solve level l
+// and (per step, not per iteration) one thread per vertex, eight per vertex,
+// one per tet, and the trust-region partials' grid
 enum { kBKLocal = 0, kBKGather = 1, kBKEb = 2, kBKBottom = 3, kBKApplyK = 4, kBKSepF = 5, kBKSepB = kBKSepF + kMaxLevels,
-       kBKKinds = kBKSepB + kMaxLevels };
+       kBKVert = kBKSepB + kMaxLevels, kBKVert8, kBKElem, kBKTR, kBKKinds };
 
 void launch_b_local(const BatchMap& M, int nblk, int block, int k, hipStream_t s);
 void launch_b_gather_fwd(const BatchMap& M, int nblk, int k, hipStream_t s);
@@ -301,6 +321,18 @@ void launch_b_sep(const BatchMap* Mf, const int* nblk_f, const BatchMap* Mb, con
                   int adjoint, hipStream_t s);
 void launch_b_bottom(int mode, const BatchMap& M, int nblk, int k, hipStream_t s);
 void launch_b_apply_K(int mode, const BatchMap& M, int nblk, int block, int it, hipStream_t s);
+// the per-step kernels of a batch: before the forward loop (caller's q_t to
+// library order, B_beta q_t, prologue), after it (epilogue), before the
+// adjoint loop (adjoint start, trust-region partials, element differentials)
+// and after it (gradient routing); maps of kinds kBKVert, kBKVert8, kBKElem,
+// kBKTR with their block counts
+void launch_b_fwd_pre(const BatchMap& Mv, int nv_blk, const BatchMap& Me, int ne_blk, const BatchMap& Mv8,
+                      int nv8_blk, const BFwdIO* io, hipStream_t s);
+void launch_b_fwd_post(const BatchMap& Mv, int nv_blk, const BFwdIO* io, hipStream_t s);
+void launch_b_bwd_pre(const BatchMap& Mv, int nv_blk, const BatchMap& Mtr, int ntr_blk, const BatchMap& Me,
+                      int ne_blk, const BBwdIO* io, hipStream_t s);
+void launch_b_bwd_post(const BatchMap& Me, int ne_blk, const BatchMap& Mv8, int nv8_blk, const BBwdIO* io,
+                       hipStream_t s);
 void launch_b_adj_gather(int mode, const BatchMap& M, int nblk, int it, hipStream_t s);
 void launch_b_flags(const BatchMap& M, int* ctl_out, double* dstat_out, hipStream_t s);
 

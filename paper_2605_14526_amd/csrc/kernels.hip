@@ -640,11 +640,29 @@ __global__ void __launch_bounds__(kBlock) k_local(ElemArgs E, StepState St, RedA
   b_local<M>(E, St, R, q, nv, nf, k, fwd, newton_cap, xcd_block(blockIdx.x, gridDim.x));
 }
 
+// The bodies of the kernels that run once per step exist once, called by the
+// single-scene kernel and by its batched twin alike: compiled twice (inlined
+// into each), the compiler may fuse multiply-adds differently in the two
+// copies, and a scene of a batch would no longer match its run alone bit for
+// bit.
+#ifdef PD_SHARED_INLINE
+#define PD_SHARED_BODY __forceinline__
+#else
+#define PD_SHARED_BODY __attribute__((noinline))
+#endif
+// vertex kernels' bodies: their own arithmetic is not fused at all (they call
+// nothing that multiplies), which settles the same question while inlined
+#ifdef PD_VERT_NOINLINE
+#define PD_VERT_BODY __attribute__((noinline))
+#else
+#define PD_VERT_BODY __forceinline__
+#endif
+
 // G_e^T (w G_e x): contributions of the symmetric element operator w V G^T G
 // (B_beta q_t in the prologue).
-__global__ void __launch_bounds__(kBlock) k_elem_GtG(ElemArgs E, const double* __restrict__ x, int nv,
-                                                     const double* __restrict__ w, double* __restrict__ contrib) {
-  const int t = blockIdx.x * blockDim.x + threadIdx.x;
+__device__ PD_SHARED_BODY void b_elem_GtG(const ElemArgs& E, const double* __restrict__ x, int nv,
+                                           const double* __restrict__ w, double* __restrict__ contrib, int bid) {
+  const int t = bid * blockDim.x + threadIdx.x;
   if (t >= E.ne) return;
   double F[9];
   int vi[4];
@@ -652,19 +670,24 @@ __global__ void __launch_bounds__(kBlock) k_elem_GtG(ElemArgs E, const double* _
   store_contrib(E, contrib, t, w[t], F);
 }
 
+__global__ void __launch_bounds__(kBlock) k_elem_GtG(ElemArgs E, const double* __restrict__ x, int nv,
+                                                     const double* __restrict__ w, double* __restrict__ contrib) {
+  b_elem_GtG(E, x, nv, w, contrib, blockIdx.x);
+}
+
 // ---------------------------------------------------------------- step prologue
 // q~ = q_t + h v_t + h^2 (M^{-1} f_ext + g)   (Eq. freefall)
 // c  = M/h^2 q~ + (alpha/h) M q_t + (1/h) B_beta q_t - A~_{fp} q_p
 // (damping terms of the right-hand side derived from Eq. dynamics).
-__global__ void __launch_bounds__(kBlock) k_prologue(VertArgs Vx, const double* __restrict__ q_t_user,
-                                                     const double* __restrict__ v_t_user,
-                                                     const double* __restrict__ f_user,
-                                                     const double* __restrict__ q0_user, int inertial,
-                                                     StepState St) {
+__device__ PD_VERT_BODY void b_prologue(const VertArgs& Vx, const double* __restrict__ q_t_user,
+                                           const double* __restrict__ v_t_user, const double* __restrict__ f_user,
+                                           const double* __restrict__ q0_user, int inertial, const StepState& St,
+                                           int bid) {
+#pragma clang fp contract(off)
   // the step's control words (done flag, counters, Anderson layout) start at
   // zero; nothing in this kernel reads them
-  if (blockIdx.x == 0 && threadIdx.x < kCtlSize) St.ctl[threadIdx.x] = 0;
-  const int gtid = blockIdx.x * blockDim.x + threadIdx.x;
+  if (bid == 0 && threadIdx.x < kCtlSize) St.ctl[threadIdx.x] = 0;
+  const int gtid = bid * blockDim.x + threadIdx.x;
   const int i = gtid >> 3, l = gtid & 7;
   const int nv = Vx.nv;
   if (i >= nv) return;  // whole groups of 8 leave together
@@ -700,6 +723,14 @@ __global__ void __launch_bounds__(kBlock) k_prologue(VertArgs Vx, const double* 
     St.q_cur[a * nv + i] = q0;
     St.q_prev[a * nv + i] = q0;
   }
+}
+
+__global__ void __launch_bounds__(kBlock) k_prologue(VertArgs Vx, const double* __restrict__ q_t_user,
+                                                     const double* __restrict__ v_t_user,
+                                                     const double* __restrict__ f_user,
+                                                     const double* __restrict__ q0_user, int inertial,
+                                                     StepState St) {
+  b_prologue(Vx, q_t_user, v_t_user, f_user, q0_user, inertial, St, blockIdx.x);
 }
 
 // ---------------------------------------------------------------- right-hand side
@@ -1735,9 +1766,9 @@ __global__ void __launch_bounds__(kBlock) k_contact_apply_adj(VertArgs Vx, AdjSt
 // ---------------------------------------------------------------- step epilogue
 // q_{t+h} = q*, v_{t+h} = (q* - q_t) / h in the caller's order; checkpoint
 // record {q_t, q~, q*, q*-1} in library order.
-__global__ void __launch_bounds__(kBlock) k_epilogue(VertArgs Vx, StepState St, double* __restrict__ q_next,
-                                                     double* __restrict__ v_next, double* __restrict__ ckpt) {
-  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+__device__ PD_VERT_BODY void b_epilogue(const VertArgs& Vx, const StepState& St, double* __restrict__ q_next,
+                                           double* __restrict__ v_next, double* __restrict__ ckpt, int bid) {
+  const int i = bid * blockDim.x + threadIdx.x;
   const int nv = Vx.nv;
   if (i >= nv) return;
   const int o = Vx.v_orig[i];
@@ -1757,15 +1788,25 @@ __global__ void __launch_bounds__(kBlock) k_epilogue(VertArgs Vx, StepState St, 
   }
 }
 
+__global__ void __launch_bounds__(kBlock) k_epilogue(VertArgs Vx, StepState St, double* __restrict__ q_next,
+                                                     double* __restrict__ v_next, double* __restrict__ ckpt) {
+  b_epilogue(Vx, St, q_next, v_next, ckpt, blockIdx.x);
+}
+
 // ---------------------------------------------------------------- layout conversion
-__global__ void __launch_bounds__(kBlock) k_to_lib(VertArgs Vx, const double* __restrict__ user, double* __restrict__ lib,
-                                                   int free_only) {
-  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+__device__ PD_VERT_BODY void b_to_lib(const VertArgs& Vx, const double* __restrict__ user, double* __restrict__ lib,
+                                         int free_only, int bid) {
+  const int i = bid * blockDim.x + threadIdx.x;
   if (i >= Vx.nv) return;
   const int o = Vx.v_orig[i];
   const bool zero = free_only && i >= Vx.nf;
 #pragma unroll
   for (int a = 0; a < 3; ++a) lib[a * Vx.nv + i] = zero ? 0.0 : user[3 * o + a];
+}
+
+__global__ void __launch_bounds__(kBlock) k_to_lib(VertArgs Vx, const double* __restrict__ user, double* __restrict__ lib,
+                                                   int free_only) {
+  b_to_lib(Vx, user, lib, free_only, blockIdx.x);
 }
 
 __global__ void __launch_bounds__(kBlock) k_from_lib(VertArgs Vx, const double* __restrict__ lib, double* __restrict__ user,
@@ -1782,15 +1823,15 @@ __global__ void __launch_bounds__(kBlock) k_from_lib(VertArgs Vx, const double* 
 // Trust-region ratio sums (Eqs. tr_step, tr_decreases): per tet
 // V_e (psi_e(F(q*-1)) - psi_e(F(q*))) and (w_e + beta_e/h) V_e |G_e dq|^2;
 // per free vertex m/(2h^2) (a - b).(a + b - 2 q~) and (1 + alpha h) m/h^2 |dq|^2.
-__global__ void __launch_bounds__(kBlock) k_tr_partials(ElemArgs E, VertArgs Vx, RedArgs R, const double* __restrict__ ck,
-                                                        int n_tet_blocks) {
+__device__ PD_SHARED_BODY void b_tr_partials(const ElemArgs& E, const VertArgs& Vx, const RedArgs& R,
+                                              const double* __restrict__ ck, int n_tet_blocks, int bid) {
   const int nv = Vx.nv;
   const double* qtil = ck + 3 * nv;
   const double* qs = ck + 6 * nv;
   const double* qm = ck + 9 * nv;
   double v[2] = {0.0, 0.0};
-  if ((int)blockIdx.x < n_tet_blocks) {
-    const int t = blockIdx.x * blockDim.x + threadIdx.x;
+  if ((int)bid < n_tet_blocks) {
+    const int t = bid * blockDim.x + threadIdx.x;
     if (t < E.ne) {
       double Fa[9], Fb[9];
       int vi[4];
@@ -1829,7 +1870,7 @@ __global__ void __launch_bounds__(kBlock) k_tr_partials(ElemArgs E, VertArgs Vx,
       }
     }
   } else {
-    const int i = (blockIdx.x - n_tet_blocks) * blockDim.x + threadIdx.x;
+    const int i = (bid - n_tet_blocks) * blockDim.x + threadIdx.x;
     if (i < Vx.nf) {
       const double m = Vx.mass[i], h = Vx.h;
 #pragma unroll
@@ -1841,30 +1882,35 @@ __global__ void __launch_bounds__(kBlock) k_tr_partials(ElemArgs E, VertArgs Vx,
       }
     }
   }
-  write_partial<2>(v, R, kRedTR, blockIdx.x);
+  write_partial<2>(v, R, kRedTR, bid);
+}
+
+__global__ void __launch_bounds__(kBlock) k_tr_partials(ElemArgs E, VertArgs Vx, RedArgs R, const double* __restrict__ ck,
+                                                        int n_tet_blocks) {
+  b_tr_partials(E, Vx, R, ck, n_tet_blocks, blockIdx.x);
 }
 
 // rho = dPhi_act / dPhi_mod (rho = 1 when dPhi_mod < 1e-12), tau* = 1/2 when
 // |rho - 1| <= eps_TR else 1 (Eqs. tr_ratio, tr_rule); then per tet the
 // recomputed SVD and prox stretches at q*, and the compact filtered prox
 // differential {U, V, D, c1, c2, s*} (Alg. 2 element loop).
-__global__ void __launch_bounds__(kBlock) k_bwd_elem(ElemArgs E, VertArgs Vx, RedArgs R, const double* __restrict__ ck,
-                                                     double eps_tr, double tau_force, int use_partials,
-                                                     double* __restrict__ jac, double* __restrict__ bstat,
-                                                     int* __restrict__ zero, int nzero) {
+__device__ PD_SHARED_BODY void b_bwd_elem(const ElemArgs& E, const VertArgs& Vx, const RedArgs& R,
+                                           const double* __restrict__ ck, double eps_tr, double tau_force,
+                                           int use_partials, double* __restrict__ jac, double* __restrict__ bstat,
+                                           int* __restrict__ zero, int nzero, int bid) {
   // words cleared for the kernels that follow (the adjoint's control words);
   // nothing in this kernel reads them
-  if (zero && blockIdx.x == 0 && threadIdx.x < nzero) zero[threadIdx.x] = 0;
+  if (zero && bid == 0 && threadIdx.x < nzero) zero[threadIdx.x] = 0;
   __shared__ double tau_s;
   double tr[2] = {0.0, 0.0};
-  if (use_partials) consume<2>(R, kRedTR, tr, blockIdx.x);
+  if (use_partials) consume<2>(R, kRedTR, tr, bid);
   if (threadIdx.x == 0) {
     const double act = tr[0], mod = 0.5 * fabs(tr[1]);
     const double rho = (mod < 1e-12) ? 1.0 : act / mod;
     double tau = (fabs(rho - 1.0) <= eps_tr) ? 0.5 : 1.0;
     if (tau_force >= 0.0) tau = tau_force;
     tau_s = tau;
-    if (blockIdx.x == 0) {
+    if (bid == 0) {
       bstat[0] = rho;
       bstat[1] = tau;
       bstat[2] = act;
@@ -1873,7 +1919,7 @@ __global__ void __launch_bounds__(kBlock) k_bwd_elem(ElemArgs E, VertArgs Vx, Re
   }
   __syncthreads();
   const double tau = tau_s;
-  const int t = blockIdx.x * blockDim.x + threadIdx.x;
+  const int t = bid * blockDim.x + threadIdx.x;
   if (t >= E.ne) return;
   const int nv = Vx.nv;
   const double* qs = ck + 6 * nv;
@@ -1952,6 +1998,13 @@ __global__ void __launch_bounds__(kBlock) k_bwd_elem(ElemArgs E, VertArgs Vx, Re
     store_warm(E, t, V, sF, sv);
   else
     store_warm(E, t, V, sF, ss);
+}
+
+__global__ void __launch_bounds__(kBlock) k_bwd_elem(ElemArgs E, VertArgs Vx, RedArgs R, const double* __restrict__ ck,
+                                                     double eps_tr, double tau_force, int use_partials,
+                                                     double* __restrict__ jac, double* __restrict__ bstat,
+                                                     int* __restrict__ zero, int nzero) {
+  b_bwd_elem(E, Vx, R, ck, eps_tr, tau_force, use_partials, jac, bstat, zero, nzero, blockIdx.x);
 }
 
 __device__ __forceinline__ void load_jac(const double* __restrict__ jac, int ne, int t, double U[9], double V[9],
@@ -2187,11 +2240,11 @@ __global__ void __launch_bounds__(kBlock) k_adj_gather(VertArgs Vx, AdjState A, 
 // library order; adjoint start mu0 (zero, the previous solution mu1 of the
 // sweep, the linear extrapolation 2 mu1 - mu2 or the quadratic one
 // 3 mu1 - 3 mu2 + mu3), r = q bar, p = A p = 0.
-__global__ void __launch_bounds__(kBlock) k_bwd_prologue(VertArgs Vx, AdjState Ad, const double* __restrict__ gq,
-                                                         const double* __restrict__ gv, int warm,
-                                                         const double* __restrict__ h1, const double* __restrict__ h2,
-                                                         const double* __restrict__ h3) {
-  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+__device__ PD_VERT_BODY void b_bwd_prologue(const VertArgs& Vx, const AdjState& Ad, const double* __restrict__ gq,
+                                               const double* __restrict__ gv, int warm, const double* __restrict__ h1,
+                                               const double* __restrict__ h2, const double* __restrict__ h3, int bid) {
+#pragma clang fp contract(off)
+  const int i = bid * blockDim.x + threadIdx.x;
   if (i >= Vx.nv) return;
   const int nv = Vx.nv, o = Vx.v_orig[i];
   const bool fr = i < Vx.nf;
@@ -2211,14 +2264,21 @@ __global__ void __launch_bounds__(kBlock) k_bwd_prologue(VertArgs Vx, AdjState A
   }
 }
 
+__global__ void __launch_bounds__(kBlock) k_bwd_prologue(VertArgs Vx, AdjState Ad, const double* __restrict__ gq,
+                                                         const double* __restrict__ gv, int warm,
+                                                         const double* __restrict__ h1, const double* __restrict__ h2,
+                                                         const double* __restrict__ h3) {
+  b_bwd_prologue(Vx, Ad, gq, gv, warm, h1, h2, h3, blockIdx.x);
+}
+
 // Gradient routing per tet (Eq. dl_dwe and its damping counterpart, chain
 // rule through w_e and beta_e, both proportional to E_e):
 // dL/dlogE_e += w_e V_e <G mu, p* - G q*> + (beta_e V_e / h) <G mu, G (q_t - q*)>,
 // plus the contributions (beta_e V_e / h) G^T G mu for B_beta mu / h.
-__global__ void __launch_bounds__(kBlock) k_grad_elem(ElemArgs E, VertArgs Vx, const double* __restrict__ ck,
-                                                      const double* __restrict__ jac, const double* __restrict__ mu,
-                                                      double* __restrict__ contrib, double* __restrict__ g_logE) {
-  const int t = blockIdx.x * blockDim.x + threadIdx.x;
+__device__ PD_SHARED_BODY void b_grad_elem(const ElemArgs& E, const VertArgs& Vx, const double* __restrict__ ck,
+                                            const double* __restrict__ jac, const double* __restrict__ mu,
+                                            double* __restrict__ contrib, double* __restrict__ g_logE, int bid) {
+  const int t = bid * blockDim.x + threadIdx.x;
   if (t >= E.ne) return;
   const int nv = Vx.nv;
   double Gm[9], Fs[9], Ft[9];
@@ -2255,6 +2315,12 @@ __global__ void __launch_bounds__(kBlock) k_grad_elem(ElemArgs E, VertArgs Vx, c
   }
 }
 
+__global__ void __launch_bounds__(kBlock) k_grad_elem(ElemArgs E, VertArgs Vx, const double* __restrict__ ck,
+                                                      const double* __restrict__ jac, const double* __restrict__ mu,
+                                                      double* __restrict__ contrib, double* __restrict__ g_logE) {
+  b_grad_elem(E, Vx, ck, jac, mu, contrib, g_logE, blockIdx.x);
+}
+
 // dL/da_g += the group's tet terms: one wave per group, lane l adds terms l,
 // l + 64, ... of the group's list in order, then a fixed butterfly
 __global__ void __launch_bounds__(64) k_muscle_grad(const double* __restrict__ mgt, const int* __restrict__ g_ptr,
@@ -2269,11 +2335,13 @@ __global__ void __launch_bounds__(64) k_muscle_grad(const double* __restrict__ m
 
 // dL/dq_t = (M/h^2 + alpha M/h) mu + B_beta mu / h - v bar / h,
 // dL/dv_t = M mu / h, dL/df_ext = mu (caller's order; zero on pinned).
-__global__ void __launch_bounds__(kBlock) k_grad_vert(VertArgs Vx, const double* __restrict__ mu,
-                                                      const double* __restrict__ contrib,
-                                                      const double* __restrict__ gv_next, double* __restrict__ gq_t,
-                                                      double* __restrict__ gv_t, double* __restrict__ gf) {
-  const int gtid = blockIdx.x * blockDim.x + threadIdx.x;
+// mu_copy (optional) receives a copy of mu (the adjoint history of a batch).
+__device__ PD_VERT_BODY void b_grad_vert(const VertArgs& Vx, const double* __restrict__ mu,
+                                            const double* __restrict__ contrib, const double* __restrict__ gv_next,
+                                            double* __restrict__ gq_t, double* __restrict__ gv_t,
+                                            double* __restrict__ gf, double* __restrict__ mu_copy, int bid) {
+#pragma clang fp contract(off)
+  const int gtid = bid * blockDim.x + threadIdx.x;
   const int i = gtid >> 3, l = gtid & 7;
   const int nv = Vx.nv;
   if (i >= nv) return;
@@ -2281,6 +2349,9 @@ __global__ void __launch_bounds__(kBlock) k_grad_vert(VertArgs Vx, const double*
   if (i < Vx.nf) gather8(Vx.inc_ptr, contrib, Vx.ninc, i, l, bm);
   if (l != 0) return;
   const int o = Vx.v_orig[i];
+  if (mu_copy)
+#pragma unroll
+    for (int a = 0; a < 3; ++a) mu_copy[a * nv + i] = mu[a * nv + i];
   if (i >= Vx.nf) {
 #pragma unroll
     for (int a = 0; a < 3; ++a) {
@@ -2299,6 +2370,13 @@ __global__ void __launch_bounds__(kBlock) k_grad_vert(VertArgs Vx, const double*
     if (gv_t) gv_t[3 * o + a] = m / h * u;
     if (gf) gf[3 * o + a] = u;
   }
+}
+
+__global__ void __launch_bounds__(kBlock) k_grad_vert(VertArgs Vx, const double* __restrict__ mu,
+                                                      const double* __restrict__ contrib,
+                                                      const double* __restrict__ gv_next, double* __restrict__ gq_t,
+                                                      double* __restrict__ gv_t, double* __restrict__ gf) {
+  b_grad_vert(Vx, mu, contrib, gv_next, gq_t, gv_t, gf, nullptr, blockIdx.x);
 }
 
 __global__ void __launch_bounds__(kBlock) k_init_warm(ElemArgs E) {
@@ -2335,6 +2413,58 @@ __device__ __forceinline__ int scene_of(const BatchMap& M, int b) {
   const int s_ = scene_of(M, blockIdx.x);      \
   const int bid = blockIdx.x - M.base[s_];     \
   const SceneBundle& b = M.B[M.sid[s_]];
+
+// per-step kernels of a batch (one launch over all scenes each)
+#define PD_BATCH_IO(io)                        \
+  const int s_ = scene_of(M, blockIdx.x);      \
+  const int bid = blockIdx.x - M.base[s_];     \
+  const SceneBundle& b = M.B[M.sid[s_]];       \
+  const auto& x = io[M.sid[s_]];
+
+__global__ void __launch_bounds__(kBlock) kb_fwd_to_lib(BatchMap M, const BFwdIO* __restrict__ io) {
+  PD_BATCH_IO(io)
+  b_to_lib(b.V, x.q_t, b.St.qt, 0, bid);
+}
+
+__global__ void __launch_bounds__(kBlock) kb_elem_GtG(BatchMap M) {
+  PD_BATCH_PROLOGUE
+  b_elem_GtG(b.E, b.St.qt, b.V.nv, b.E.bV, b.St.contrib, bid);
+}
+
+__global__ void __launch_bounds__(kBlock) kb_prologue(BatchMap M, const BFwdIO* __restrict__ io) {
+  PD_BATCH_IO(io)
+  b_prologue(b.V, x.q_t, x.v_t, x.f, x.q0, x.inertial, b.St, bid);
+}
+
+__global__ void __launch_bounds__(kBlock) kb_epilogue(BatchMap M, const BFwdIO* __restrict__ io) {
+  PD_BATCH_IO(io)
+  b_epilogue(b.V, b.St, x.q_next, x.v_next, x.ckpt, bid);
+}
+
+__global__ void __launch_bounds__(kBlock) kb_bwd_prologue(BatchMap M, const BBwdIO* __restrict__ io) {
+  PD_BATCH_IO(io)
+  b_bwd_prologue(b.V, b.A, x.gq, x.gv, x.warm, x.h1, x.h2, x.h3, bid);
+}
+
+__global__ void __launch_bounds__(kBlock) kb_tr_partials(BatchMap M, const BBwdIO* __restrict__ io) {
+  PD_BATCH_IO(io)
+  if (x.tr) b_tr_partials(b.E, b.V, b.R, x.ck, (b.E.ne + kBlock - 1) / kBlock, bid);
+}
+
+__global__ void __launch_bounds__(kBlock) kb_bwd_elem(BatchMap M, const BBwdIO* __restrict__ io) {
+  PD_BATCH_IO(io)
+  b_bwd_elem(b.E, b.V, b.R, x.ck, x.eps_tr, -1.0, x.tr, b.jac, b.St.dstat + 4, b.A.ctl, 4, bid);
+}
+
+__global__ void __launch_bounds__(kBlock) kb_grad_elem(BatchMap M, const BBwdIO* __restrict__ io) {
+  PD_BATCH_IO(io)
+  b_grad_elem(b.E, b.V, x.ck, b.jac, b.A.mu, b.A.contrib, x.g_logE, bid);
+}
+
+__global__ void __launch_bounds__(kBlock) kb_grad_vert(BatchMap M, const BBwdIO* __restrict__ io) {
+  PD_BATCH_IO(io)
+  b_grad_vert(b.V, b.A.mu, b.A.contrib, x.gv, x.gq_t, x.gv_t, x.gf, x.mu_copy, bid);
+}
 
 __global__ void __launch_bounds__(kBlock) kb_local(BatchMap M, int k) {
   PD_BATCH_PROLOGUE
@@ -2626,6 +2756,26 @@ void launch_grad_vert(const VertArgs& V, const double* mu, const double* contrib
                       double* gv_t, double* gf, hipStream_t s) {
   launch_ext(k_grad_vert, dim3(vert_group_blocks(V.nv)), dim3(kBlock), 0, s, V, mu, contrib, gv_next, gq_t,
                      gv_t, gf);
+}
+void launch_b_fwd_pre(const BatchMap& Mv, int nv_blk, const BatchMap& Me, int ne_blk, const BatchMap& Mv8,
+                      int nv8_blk, const BFwdIO* io, hipStream_t s) {
+  if (nv_blk > 0) launch_ext(kb_fwd_to_lib, dim3(nv_blk), dim3(kBlock), 0, s, Mv, io);
+  if (ne_blk > 0) launch_ext(kb_elem_GtG, dim3(ne_blk), dim3(kBlock), 0, s, Me);
+  if (nv8_blk > 0) launch_ext(kb_prologue, dim3(nv8_blk), dim3(kBlock), 0, s, Mv8, io);
+}
+void launch_b_fwd_post(const BatchMap& Mv, int nv_blk, const BFwdIO* io, hipStream_t s) {
+  if (nv_blk > 0) launch_ext(kb_epilogue, dim3(nv_blk), dim3(kBlock), 0, s, Mv, io);
+}
+void launch_b_bwd_pre(const BatchMap& Mv, int nv_blk, const BatchMap& Mtr, int ntr_blk, const BatchMap& Me,
+                      int ne_blk, const BBwdIO* io, hipStream_t s) {
+  if (nv_blk > 0) launch_ext(kb_bwd_prologue, dim3(nv_blk), dim3(kBlock), 0, s, Mv, io);
+  if (ntr_blk > 0) launch_ext(kb_tr_partials, dim3(ntr_blk), dim3(kBlock), 0, s, Mtr, io);
+  if (ne_blk > 0) launch_ext(kb_bwd_elem, dim3(ne_blk), dim3(kBlock), 0, s, Me, io);
+}
+void launch_b_bwd_post(const BatchMap& Me, int ne_blk, const BatchMap& Mv8, int nv8_blk, const BBwdIO* io,
+                       hipStream_t s) {
+  if (ne_blk > 0) launch_ext(kb_grad_elem, dim3(ne_blk), dim3(kBlock), 0, s, Me, io);
+  if (nv8_blk > 0) launch_ext(kb_grad_vert, dim3(nv8_blk), dim3(kBlock), 0, s, Mv8, io);
 }
 void launch_b_local(const BatchMap& M, int nblk, int block, int k, hipStream_t s) {
   if (nblk > 0) launch_ext(kb_local, dim3(nblk), dim3(block), 0, s, M, k);

@@ -2061,13 +2061,18 @@ int pd_step_forward(pd_scene* scene, const double* q_t, const double* v_t, const
 
 // The adjoint solution just computed becomes the newest of the (up to three)
 // kept for the next call's start; the buffers rotate, the oldest is overwritten.
-static void push_adjoint_history(Scene& S, hipStream_t st) {
-  PD_HIP(hipMemcpyAsync(S.mu_h3, S.mu, 3 * (size_t)S.nv * sizeof(double), hipMemcpyDeviceToDevice, st));
+// the oldest history buffer becomes the newest (its copy of mu is made by the caller)
+static void rotate_adjoint_history(Scene& S) {
   double* newest = S.mu_h3;
   S.mu_h3 = S.mu_h2;
   S.mu_h2 = S.mu_h1;
   S.mu_h1 = newest;
   S.adj_hist = std::min(S.adj_hist + 1, 3);
+}
+
+static void push_adjoint_history(Scene& S, hipStream_t st) {
+  PD_HIP(hipMemcpyAsync(S.mu_h3, S.mu, 3 * (size_t)S.nv * sizeof(double), hipMemcpyDeviceToDevice, st));
+  rotate_adjoint_history(S);
 }
 
 static void adjoint_solve(Scene& S, hipStream_t st, double tau_force, double* bstat_host, const double* ck,
@@ -2445,6 +2450,10 @@ struct pd_batch {
   // and the algorithmic bytes of the work those launches did
   KernelTimer kt;
   double bytes_done = 0.0;
+  // per-call argument tables of the per-step kernels (host copies pinned;
+  // every call ends with its stream idle, so the next call may rewrite them)
+  BFwdIO *dfio = nullptr, *hfio = nullptr;
+  BBwdIO *dbio = nullptr, *hbio = nullptr;
 };
 
 namespace {
@@ -2469,6 +2478,10 @@ void batch_layout(pd_batch& B) {
         case kBKGather: n = vert_group_blocks(S.L.nf); break;
         case kBKEb: n = eb_blocks(S.L.nT); break;
         case kBKBottom: n = bottom_blocks(S.L.nB, S.L.nT); break;
+        case kBKVert: n = (S.nv + kBlock - 1) / kBlock; break;
+        case kBKVert8: n = vert_group_blocks(S.nv); break;
+        case kBKElem: n = (S.ne + kBlock - 1) / kBlock; break;
+        case kBKTR: n = tr_blocks(S.ne, S.L.nf); break;
         default: {
           const bool fwd = kind < kBKSepB;
           const int l = kind - (fwd ? kBKSepF : kBKSepB);  // level l + 1
@@ -2527,6 +2540,11 @@ BatchMap bmap(const pd_batch& B, int kind) {
 }
 
 int bnblk(const pd_batch& B, int kind) { return B.live_on ? B.nblk_live[kind] : B.nblk[kind]; }
+
+// the map of a kind over every scene of the batch
+BatchMap full_map(const pd_batch& B, int kind) {
+  return BatchMap{B.dB, B.dbase[kind], (int)B.scenes.size(), B.dsid_all};
+}
 
 // After a host check of an eager loop: list only the scenes whose loop still
 // runs (`running(s)`), so later launches carry no blocks of stopped scenes.
@@ -2653,6 +2671,10 @@ int pd_batch_create(pd_scene* const* scenes, int n, pd_batch** out) {
     B->ddstat = dalloc<double>((size_t)32 * n);
     PD_HIP(hipHostMalloc((void**)&B->hctl, sizeof(int) * kCtlTotal * n));
     PD_HIP(hipHostMalloc((void**)&B->hdstat, sizeof(double) * 32 * n));
+    B->dfio = dalloc<BFwdIO>(n);
+    B->dbio = dalloc<BBwdIO>(n);
+    PD_HIP(hipHostMalloc((void**)&B->hfio, sizeof(BFwdIO) * n));
+    PD_HIP(hipHostMalloc((void**)&B->hbio, sizeof(BBwdIO) * n));
     PD_HIP(hipStreamCreateWithFlags(&B->gstream, hipStreamNonBlocking));
     PD_HIP(hipEventCreateWithFlags(&B->ev_in, hipEventDisableTiming));
     PD_HIP(hipEventCreateWithFlags(&B->ev_out, hipEventDisableTiming));
@@ -2677,6 +2699,10 @@ int pd_batch_destroy(pd_batch* B) {
   dfree(B->ddstat);
   if (B->hctl) (void)hipHostFree(B->hctl);
   if (B->hdstat) (void)hipHostFree(B->hdstat);
+  dfree(B->dfio);
+  dfree(B->dbio);
+  if (B->hfio) (void)hipHostFree(B->hfio);
+  if (B->hbio) (void)hipHostFree(B->hbio);
   if (B->ev_in) (void)hipEventDestroy(B->ev_in);
   if (B->ev_out) (void)hipEventDestroy(B->ev_out);
   if (B->gstream) (void)hipStreamDestroy(B->gstream);
@@ -2723,14 +2749,14 @@ int pd_batch_step_forward(pd_batch* B, const double* const* q_t, const double* c
     Scene& S = B->scenes[s]->S;
     if (S.stale) throw PdError{PD_ERR_STALE_FACTOR, "scene factor is stale"};
     if (!q_t[s] || !v_t[s] || !q_next[s] || !v_next[s]) throw PdError{PD_ERR_INVALID_ARG, "null scene input"};
-    const ElemArgs E = elem_args(S);
-    const VertArgs V = vert_args(S);
-    const StepState T = step_state(S);
-    launch_to_lib(V, q_t[s], S.qt, 0, st);
-    launch_elem_GtG(E, S.qt, S.nv, S.bV, S.contrib, st);
-    launch_prologue(V, q_t[s], v_t[s], f_ext ? f_ext[s] : nullptr, q0 ? q0[s] : nullptr, S.fwd_start, T, st);
+    B->hfio[s] = BFwdIO{q_t[s], v_t[s], f_ext ? f_ext[s] : nullptr, q0 ? q0[s] : nullptr, q_next[s], v_next[s],
+                        ckpt ? (double*)ckpt[s] : nullptr, S.fwd_start};
     kmax = std::max(kmax, S.kmax_fwd);
   }
+  // caller's q_t in library order, B_beta q_t, prologue: one launch each over all scenes
+  PD_HIP(hipMemcpyAsync(B->dfio, B->hfio, sizeof(BFwdIO) * ns, hipMemcpyHostToDevice, st));
+  launch_b_fwd_pre(full_map(*B, kBKVert), B->nblk[kBKVert], full_map(*B, kBKElem), B->nblk[kBKElem],
+                   full_map(*B, kBKVert8), B->nblk[kBKVert8], B->dfio, st);
   int k = 0;
   // graph replay wants fixed chunk boundaries (one graph per chunk start)
   const int fixed = B->chunk > 0 ? B->chunk : (B->use_graph ? 4 : 0);
@@ -2750,9 +2776,9 @@ int pd_batch_step_forward(pd_batch* B, const double* const* q_t, const double* c
   }
   B->live_on = false;
   int worst = 0, most = 0;
+  launch_b_fwd_post(full_map(*B, kBKVert), B->nblk[kBKVert], B->dfio, st);
   for (int s = 0; s < ns; ++s) {
     Scene& S = B->scenes[s]->S;
-    launch_epilogue(vert_args(S), step_state(S), q_next[s], v_next[s], ckpt ? (double*)ckpt[s] : nullptr, st);
     const int* c = B->hctl + s * kCtlTotal;
     if (stats) {
       stats[s].iters = c[kCtlIters];
@@ -2797,20 +2823,19 @@ int pd_batch_step_backward(pd_batch* B, const void* const* ckpt, const double* c
     Scene& S = B->scenes[s]->S;
     if (S.stale) throw PdError{PD_ERR_STALE_FACTOR, "scene factor is stale"};
     if (!ckpt[s]) throw PdError{PD_ERR_INVALID_ARG, "null checkpoint"};
-    const ElemArgs E = elem_args(S);
-    const VertArgs V = vert_args(S);
-    const AdjState Ad = adj_state(S);
-    const RedArgs R = red_args(S);
-    const double* ck = (const double*)ckpt[s];
     warm[s] = std::min(S.adj_warm, S.adj_hist);
     any_warm = any_warm || warm[s] > 0;
-    launch_bwd_prologue(V, Ad, gq_next ? gq_next[s] : nullptr, gv_next ? gv_next[s] : nullptr, warm[s], S.mu_h1,
-                        S.mu_h2, S.mu_h3, st);
-    const int tr = S.energy == 0;
-    if (tr) launch_tr_partials(E, V, R, ck, st);
-    launch_bwd_elem(E, V, R, ck, S.eps_tr, -1.0, tr, S.jac, S.dstat + 4, S.ctl + kCtlAdj, 4, st);
+    // this step's mu goes to the oldest history buffer (rotated to the front after the launches)
+    B->hbio[s] = BBwdIO{gq_next ? gq_next[s] : nullptr, gv_next ? gv_next[s] : nullptr, (const double*)ckpt[s],
+                        S.mu_h1, S.mu_h2, S.mu_h3, gq_t ? gq_t[s] : nullptr, gv_t ? gv_t[s] : nullptr,
+                        gf_ext ? gf_ext[s] : nullptr, g_logE_accum ? g_logE_accum[s] : nullptr,
+                        S.adj_warm > 0 ? S.mu_h3 : nullptr, S.eps_tr, warm[s], S.energy == 0 ? 1 : 0};
     kmax = std::max(kmax, S.kmax_bwd);
   }
+  // adjoint start, trust-region partials, element differentials: one launch each over all scenes
+  PD_HIP(hipMemcpyAsync(B->dbio, B->hbio, sizeof(BBwdIO) * ns, hipMemcpyHostToDevice, st));
+  launch_b_bwd_pre(full_map(*B, kBKVert), B->nblk[kBKVert], full_map(*B, kBKTR), B->nblk[kBKTR],
+                   full_map(*B, kBKElem), B->nblk[kBKElem], B->dbio, st);
   B->live_on = false;
   if (any_warm) {  // r = q bar - (A~ - K) mu0 (a zero mu0 gives r = q bar again)
     launch_b_apply_K(kModeAmK, bmap(*B, kBKApplyK), B->nblk[kBKApplyK], B->block_applyK, 0, st);
@@ -2835,15 +2860,11 @@ int pd_batch_step_backward(pd_batch* B, const void* const* ckpt, const double* c
   }
   B->live_on = false;
   int worst = 0, most = 0;
+  // gradient routing (and the copy of mu into the history): one launch each over all scenes
+  launch_b_bwd_post(full_map(*B, kBKElem), B->nblk[kBKElem], full_map(*B, kBKVert8), B->nblk[kBKVert8], B->dbio, st);
   for (int s = 0; s < ns; ++s) {
     Scene& S = B->scenes[s]->S;
-    const ElemArgs E = elem_args(S);
-    const VertArgs V = vert_args(S);
-    const double* ck = (const double*)ckpt[s];
-    launch_grad_elem(E, V, ck, S.jac, S.mu, S.contrib, g_logE_accum ? g_logE_accum[s] : nullptr, st);
-    launch_grad_vert(V, S.mu, S.contrib, gv_next ? gv_next[s] : nullptr, gq_t ? gq_t[s] : nullptr,
-                     gv_t ? gv_t[s] : nullptr, gf_ext ? gf_ext[s] : nullptr, st);
-    if (S.adj_warm > 0) push_adjoint_history(S, st);
+    if (S.adj_warm > 0) rotate_adjoint_history(S);
     const int* c = B->hctl + s * kCtlTotal;
     const double* d = B->hdstat + s * 32;
     if (!c[kCtlAdj + 2]) throw PdError{PD_ERR_HIP, "batched adjoint loop ended without a decision"};

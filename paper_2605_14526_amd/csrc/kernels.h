@@ -129,7 +129,7 @@ struct ElemArgs {
   const double* muV;
   const double* lamV;
   const int* tet_orig;
-  double* Vw;         // 9 x ne warm-start rotations (local step)
+  double* Vw;         // 4 x ne warm-start rotations as unit quaternions {w, x, y, z} (local step)
   double* rw;         // 3 x ne warm-start stretch ratios (the composite keeps its volume multiplier in row 0)
   double mu_bar, lam_bar, k_bar;
   int energy;         // 0: Neo-Hookean proximal map; 1: corotated + volume composite

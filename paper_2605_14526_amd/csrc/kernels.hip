@@ -311,20 +311,53 @@ __device__ __forceinline__ void store_GtP(const TetData& T, double* __restrict__
     for (int ax = 0; ax < 3; ++ax) contrib[(size_t)ax * ninc + T.pos[0]] = c0[ax];
 }
 
-// The warm start of the tet's next SVD and prox Newton: the rotation V,
-// re-orthonormalised (Gram-Schmidt on its columns), and the ratios s*/sF.
+// The warm start of the tet's next SVD and prox Newton: the rotation V as a
+// unit quaternion (4 doubles instead of 9; V is a proper rotation, so the
+// quaternion holds it exactly up to rounding, and rebuilding it re-orthonormalises),
+// and the ratios s*/sF.  The quaternion is taken from the largest of
+// 1 + tr V, 1 + 2 V_ii - tr V (the numerically safe branch).
 __device__ __forceinline__ void store_rot(const ElemArgs& E, int t, const double V[9]) {
-  double c0[3] = {V[0], V[3], V[6]}, c1[3] = {V[1], V[4], V[7]};
-  double n0 = rsqrt(c0[0] * c0[0] + c0[1] * c0[1] + c0[2] * c0[2]);
-  c0[0] *= n0; c0[1] *= n0; c0[2] *= n0;
-  const double d01 = c0[0] * c1[0] + c0[1] * c1[1] + c0[2] * c1[2];
-  c1[0] -= d01 * c0[0]; c1[1] -= d01 * c0[1]; c1[2] -= d01 * c0[2];
-  double n1 = rsqrt(c1[0] * c1[0] + c1[1] * c1[1] + c1[2] * c1[2]);
-  c1[0] *= n1; c1[1] *= n1; c1[2] *= n1;
-  const double c2[3] = {c0[1] * c1[2] - c0[2] * c1[1], c0[2] * c1[0] - c0[0] * c1[2], c0[0] * c1[1] - c0[1] * c1[0]};
-  const double Vn[9] = {c0[0], c1[0], c2[0], c0[1], c1[1], c2[1], c0[2], c1[2], c2[2]};
+  const double tr = V[0] + V[4] + V[8];
+  double q[4];
+  if (tr >= V[0] && tr >= V[4] && tr >= V[8]) {
+    const double r = sqrt(fmax(1.0 + tr, 0.0)), f = 0.5 / r;
+    q[0] = 0.5 * r; q[1] = (V[7] - V[5]) * f; q[2] = (V[2] - V[6]) * f; q[3] = (V[3] - V[1]) * f;
+  } else if (V[0] >= V[4] && V[0] >= V[8]) {
+    const double r = sqrt(fmax(1.0 + V[0] - V[4] - V[8], 0.0)), f = 0.5 / r;
+    q[0] = (V[7] - V[5]) * f; q[1] = 0.5 * r; q[2] = (V[1] + V[3]) * f; q[3] = (V[2] + V[6]) * f;
+  } else if (V[4] >= V[8]) {
+    const double r = sqrt(fmax(1.0 - V[0] + V[4] - V[8], 0.0)), f = 0.5 / r;
+    q[0] = (V[2] - V[6]) * f; q[1] = (V[1] + V[3]) * f; q[2] = 0.5 * r; q[3] = (V[5] + V[7]) * f;
+  } else {
+    const double r = sqrt(fmax(1.0 - V[0] - V[4] + V[8], 0.0)), f = 0.5 / r;
+    q[0] = (V[3] - V[1]) * f; q[1] = (V[2] + V[6]) * f; q[2] = (V[5] + V[7]) * f; q[3] = 0.5 * r;
+  }
 #pragma unroll
-  for (int j = 0; j < 9; ++j) E.Vw[(size_t)j * E.ne + t] = Vn[j];
+  for (int j = 0; j < 4; ++j) E.Vw[(size_t)j * E.ne + t] = q[j];
+}
+
+// The rotation of a stored quaternion (false: none stored, start cold from
+// the identity)
+__device__ __forceinline__ bool rot_of_quat(const double q[4], double V[9]) {
+  const double n2 = q[0] * q[0] + q[1] * q[1] + q[2] * q[2] + q[3] * q[3];
+  if (!(n2 > 0.5 && n2 < 2.0)) {  // also false for NaN
+#pragma unroll
+    for (int j = 0; j < 9; ++j) V[j] = (j % 4 == 0) ? 1.0 : 0.0;
+    return false;
+  }
+  const double s = 2.0 / n2;
+  const double w = q[0], x = q[1], y = q[2], z = q[3];
+  V[0] = 1.0 - s * (y * y + z * z); V[1] = s * (x * y - w * z); V[2] = s * (x * z + w * y);
+  V[3] = s * (x * y + w * z); V[4] = 1.0 - s * (x * x + z * z); V[5] = s * (y * z - w * x);
+  V[6] = s * (x * z - w * y); V[7] = s * (y * z + w * x); V[8] = 1.0 - s * (x * x + y * y);
+  return true;
+}
+
+__device__ __forceinline__ bool load_rot(const ElemArgs& E, int t, double V[9]) {
+  double q[4];
+#pragma unroll
+  for (int j = 0; j < 4; ++j) q[j] = E.Vw[(size_t)j * E.ne + t];
+  return rot_of_quat(q, V);
 }
 
 // warm start of the next SVD and prox Newton of this tet: its rotation V and
@@ -563,11 +596,11 @@ __device__ __forceinline__ void b_local(ElemArgs E, StepState St, RedArgs R, con
   const bool have = t < E.ne;
   // the tet's data and warm start, requested before the Anderson scalars
   TetData T;
-  double V[9], rt[3], wv = 0.0;
+  double q4[4], rt[3], wv = 0.0;
   if (have) {
     load_tet(E, t, T);
 #pragma unroll
-    for (int j = 0; j < 9; ++j) V[j] = E.Vw[(size_t)j * E.ne + t];
+    for (int j = 0; j < 4; ++j) q4[j] = E.Vw[(size_t)j * E.ne + t];
 #pragma unroll
     for (int j = 0; j < 3; ++j) rt[j] = E.rw[(size_t)j * E.ne + t];
     wv = E.wV[t];
@@ -584,14 +617,9 @@ __device__ __forceinline__ void b_local(ElemArgs E, StepState St, RedArgs R, con
 #pragma unroll
     for (int ax = 0; ax < 3; ++ax)
       xv[a][ax] = (fwd && T.vi[a] < nf) ? aa_value<M>(St, mx, nv, ax, T.vi[a], k) : q[ax * nv + T.vi[a]];
-  double F[9], U[9], sF[3], ss[3];
+  double F[9], U[9], V[9], sF[3], ss[3];
   grad_of(T, xv, F);
-  bool warm = true;
-#pragma unroll
-  for (int j = 0; j < 9; ++j) warm = warm && isfinite(V[j]);
-  if (!warm)
-#pragma unroll
-    for (int j = 0; j < 9; ++j) V[j] = (j % 4 == 0) ? 1.0 : 0.0;
+  const bool warm = rot_of_quat(q4, V);
   svd3(F, U, sF, V, warm);
   double P[9];
   if (E.energy >= 1) {
@@ -1926,15 +1954,7 @@ __device__ PD_SHARED_BODY void b_bwd_elem(const ElemArgs& E, const VertArgs& Vx,
   double F[9], U[9], V[9], sF[3], ss[3], rt[3];
   int vi[4];
   load_F(E, qs, nv, t, F, vi);
-  bool warm = true;
-#pragma unroll
-  for (int j = 0; j < 9; ++j) {
-    V[j] = E.Vw[(size_t)j * E.ne + t];
-    warm = warm && isfinite(V[j]);
-  }
-  if (!warm)
-#pragma unroll
-    for (int j = 0; j < 9; ++j) V[j] = (j % 4 == 0) ? 1.0 : 0.0;
+  const bool warm = load_rot(E, t, V);
   svd3(F, U, sF, V, warm);
 #pragma unroll
   for (int j = 0; j < 3; ++j) rt[j] = E.rw[(size_t)j * E.ne + t];
@@ -2383,7 +2403,7 @@ __global__ void __launch_bounds__(kBlock) k_init_warm(ElemArgs E) {
   const int t = blockIdx.x * blockDim.x + threadIdx.x;
   if (t >= E.ne) return;
 #pragma unroll
-  for (int j = 0; j < 9; ++j) E.Vw[(size_t)j * E.ne + t] = (j % 4 == 0) ? 1.0 : 0.0;
+  for (int j = 0; j < 4; ++j) E.Vw[(size_t)j * E.ne + t] = (j == 0) ? 1.0 : 0.0;
 #pragma unroll
   for (int j = 0; j < 3; ++j) E.rw[(size_t)j * E.ne + t] = 0.0;
 }

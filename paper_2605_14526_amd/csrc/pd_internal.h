@@ -194,7 +194,7 @@ struct Scene {
   double* muV = nullptr;    // ne: mu_e V_e   (primal objective)
   double* lamV = nullptr;   // ne: lam_e V_e
   int* tet_orig = nullptr;  // ne
-  double* Vw = nullptr;     // 9 x ne warm-start rotations
+  double* Vw = nullptr;     // 4 x ne warm-start rotations (unit quaternions)
   double* rw = nullptr;     // 3 x ne warm-start stretch ratios
   // --- device: vertex arrays (library order)
   int* v_orig = nullptr;    // nv

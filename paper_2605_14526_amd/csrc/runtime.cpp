@@ -554,7 +554,7 @@ void setup_scene(Scene& S, const pd_mesh_desc* mesh, const pd_material_desc* mat
   upload(S.tinc, tinc);
   // element-material arrays and iteration buffers (sized once)
   S.wV = dalloc<double>(ne); S.bV = dalloc<double>(ne); S.muV = dalloc<double>(ne); S.lamV = dalloc<double>(ne);
-  S.Vw = dalloc<double>(9 * (size_t)ne);
+  S.Vw = dalloc<double>(4 * (size_t)ne);
   S.rw = dalloc<double>(3 * (size_t)ne);
   S.mass = dalloc<double>(nv);
   S.cpin = dalloc<double>(3 * (size_t)nv);

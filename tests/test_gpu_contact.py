@@ -169,8 +169,10 @@ def test_obstacles_out_of_reach(th):
     for x, y in zip(res["none"][:3], res["far"][:3]):
         assert np.array_equal(x, y)
     assert res["none"][3] == res["far"][3] == res["near"][3]
+    # rounding of the inactive rows' (zero) corrections, carried through four steps and the
+    # reverse sweep's solves (condition ~1e4): far below what one active row would change
     for x, y in zip(res["none"][:3], res["near"][:3]):
-        assert rel(x, y) < 1e-12
+        assert rel(x, y) < 1e-11
 
 
 def test_contact_capacity_errors(th):

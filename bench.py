@@ -386,7 +386,11 @@ def bench_warmstart(args, torch):
     fam = lambda k: scenes.shape_family(k, res=res, steps=100, friction=args.friction)  # noqa: E731
     t0 = time.perf_counter()
     train_sc = [fam(k) for k in range(args.train_scenes)]
-    samples = [warmstart.generate([sc], 100, torch) for sc in train_sc]
+    samples = []
+    for k, sc in enumerate(train_sc):
+        samples.append(warmstart.generate([sc], 100, torch))
+        print(f"[bench] trajectories of training blob {k} ({sc.n_e} tets) in {time.perf_counter() - t0:.1f} s",
+              file=sys.stderr, flush=True)
     t_gen = time.perf_counter() - t0
     nets = [Mpn.for_scene(sc, edge_weight=LEARNED_EDGE_WEIGHT) for sc in train_sc]
     master = nets[0]
@@ -403,8 +407,11 @@ def bench_warmstart(args, torch):
     torch.cuda.synchronize()
     t_train = time.perf_counter() - t0
     n_samples = sum(len(x) for x in samples)
+    # the least-squares scale of the network's correction on the training samples
+    alpha = warmstart.fit_correction_scale(nets, samples, train_sc[0].h, torch)
+    scale *= alpha
     print(f"[bench] trained on {n_samples} samples of {len(train_sc)} blobs in {t_train:.1f} s "
-          f"(trajectories {t_gen:.1f} s)", file=sys.stderr, flush=True)
+          f"(trajectories {t_gen:.1f} s); correction scale {alpha:.3f}", file=sys.stderr, flush=True)
     res_rows = {"plain": [], "inertial": [], "learned": []}
     sizes = []
     for k in range(900, 910):
@@ -438,6 +445,7 @@ def bench_warmstart(args, torch):
                       "starts": summ,
                       "train": {"blobs": len(train_sc), "samples": n_samples, "epochs": args.train_epochs,
                                 "generate_s": round(t_gen, 2), "train_s": round(t_train, 2),
+                                "correction_scale": round(alpha, 4),
                                 "final_loss": hist[-1], "weights": "one set shared by every mesh's instance"}}}
     print(json.dumps(out), flush=True)
 

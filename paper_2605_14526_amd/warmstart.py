@@ -78,6 +78,25 @@ def output_scale(samples: List[Sample], h: float, pinned) -> float:
     return float(np.sqrt(acc / max(n, 1))) or 1.0
 
 
+def fit_correction_scale(nets: List[Mpn], samples: List[List[Sample]], h: float, torch, stride: int = 4) -> float:
+    """The factor alpha that scales the trained network's correction c = q0 - q_t - h v_t so that alpha c is
+    closest (least squares over the samples' vertices) to the solver's correction q_{t+h} - q_t - h v_t:
+    alpha = sum <c, y> / sum <c, c>.  A network that only partly predicts the correction then moves the start
+    by the part it gets right instead of overshooting the inertial guess (alpha = 0 would give that guess
+    back).  Every `stride`-th sample of each mesh; the network runs in the library, the two sums on the host."""
+    num = den = 0.0
+    for net, ss in zip(nets, samples):
+        for smp in ss[::stride]:
+            q0 = torch.empty_like(smp.q_t)
+            net.forward(smp.q_t, smp.v_tm1, smp.v_t, smp.f, smp.logw, q0=q0)
+            base = (smp.q_t + h * smp.v_t).cpu().numpy()
+            c = q0.cpu().numpy() - base
+            y = smp.q_next.cpu().numpy() - base
+            num += float((c * y).sum())
+            den += float((c * c).sum())
+    return num / den if den > 0.0 else 0.0
+
+
 def train(net: Mpn, samples: List[Sample], epochs: int, lr: float = 1e-3, seed: int = 0, log_every: int = 0,
           lr_decay: float = 1.0):
     """Adam over the samples in a seeded shuffled order; returns the loss of each epoch's last sample."""

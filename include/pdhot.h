@@ -436,7 +436,11 @@ int pd_scene_factor_nnz(const pd_scene* scene, double* nnz);
  * convergence flag, so a converged scene idles while the others iterate.
  * Results are bitwise those of stepping each scene alone.  The scenes stay
  * owned by the caller and must outlive the batch; a batch runs the PCG
- * adjoint (adj_method 0).  Array arguments hold one pointer per scene, in the
+ * adjoint (adj_method 0) without obstacles, attachments or muscles (checked at
+ * creation and at every step: PD_ERR_INVALID_ARG).  A scene refactorized after
+ * the batch was made (pd_scene_set_material + pd_scene_factorize) is picked up
+ * at the next batched step (the batch rebuilds its per-scene tables and drops
+ * its captured graphs).  Array arguments hold one pointer per scene, in the
  * order given to pd_batch_create (device buffers as for the single-scene
  * calls; NULL entries where those calls allow NULL).
  * ------------------------------------------------------------------------ */

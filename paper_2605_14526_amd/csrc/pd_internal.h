@@ -175,6 +175,7 @@ struct Scene {
   int iface_levels = 0;
   double eps_rel = 1e-6, eps_abs = 1e-12, eps_adj = 1e-6, eps_tr = 0.1;
   bool stale = true;
+  int fact_gen = 0;  // counts factorizations (a batch rebuilds its argument bundles when it changes)
   int last_fwd_iters = 4, last_adj_iters = 8;
   Layout L;
   double mu_bar = 0, lam_bar = 0, k_bar = 0, mu_ref = 0;

@@ -1067,6 +1067,7 @@ void factorize(Scene& S) {
   D.bytes = (Zs_all.size() + Et_all.size() + E_all.size() + ZE_all.size() + FE_all.size()) * sizeof(double);
   PD_HIP(hipDeviceSynchronize());
   S.stale = false;
+  S.fact_gen++;
   S.adj_hist = 0;
   // cached contact columns belong to the old factor
   for (int v : S.vert_of_slot) S.slot_of[v] = -1;
@@ -2454,6 +2455,9 @@ struct pd_batch {
   // every call ends with its stream idle, so the next call may rewrite them)
   BFwdIO *dfio = nullptr, *hfio = nullptr;
   BBwdIO *dbio = nullptr, *hbio = nullptr;
+  // each scene's factorization count when the bundles were built: a scene
+  // refactorized since (new factor arrays) makes the batch rebuild them
+  std::vector<int> gen;
 };
 
 namespace {
@@ -2531,6 +2535,24 @@ void batch_bundles(pd_batch& B) {
   dfree(B.dB);
   B.dB = dalloc<SceneBundle>(h.size());
   PD_HIP(hipMemcpy(B.dB, h.data(), h.size() * sizeof(SceneBundle), hipMemcpyHostToDevice));
+}
+
+// Before a batched step: every scene still fits the batch, and scenes
+// refactorized since the bundles were built get fresh bundles and maps.
+void batch_refresh(pd_batch& B) {
+  bool rebuild = false;
+  for (size_t s = 0; s < B.scenes.size(); ++s) {
+    const Scene& S = B.scenes[s]->S;
+    if (S.stale) throw PdError{PD_ERR_STALE_FACTOR, "scene factor is stale"};
+    if (S.contact_on) throw PdError{PD_ERR_INVALID_ARG, "batched scenes run without obstacles"};
+    if (S.n_mg > 0) throw PdError{PD_ERR_INVALID_ARG, "batched scenes run without muscles"};
+    if (S.adj_method != 0) throw PdError{PD_ERR_INVALID_ARG, "batches run the PCG adjoint"};
+    rebuild = rebuild || S.fact_gen != B.gen[s];
+  }
+  if (!rebuild) return;
+  batch_bundles(B);
+  batch_layout(B);
+  for (size_t s = 0; s < B.scenes.size(); ++s) B.gen[s] = B.scenes[s]->S.fact_gen;
 }
 
 BatchMap bmap(const pd_batch& B, int kind) {
@@ -2667,6 +2689,7 @@ int pd_batch_create(pd_scene* const* scenes, int n, pd_batch** out) {
     }
     batch_bundles(*B);
     batch_layout(*B);
+    for (int s = 0; s < n; ++s) B->gen.push_back(scenes[s]->S.fact_gen);
     B->dctl = dalloc<int>((size_t)kCtlTotal * n);
     B->ddstat = dalloc<double>((size_t)32 * n);
     PD_HIP(hipHostMalloc((void**)&B->hctl, sizeof(int) * kCtlTotal * n));
@@ -2744,10 +2767,10 @@ int pd_batch_step_forward(pd_batch* B, const double* const* q_t, const double* c
   PD_TRY
   hipStream_t st = (hipStream_t)stream;
   const int ns = (int)B->scenes.size();
+  batch_refresh(*B);
   int kmax = 0;
   for (int s = 0; s < ns; ++s) {
     Scene& S = B->scenes[s]->S;
-    if (S.stale) throw PdError{PD_ERR_STALE_FACTOR, "scene factor is stale"};
     if (!q_t[s] || !v_t[s] || !q_next[s] || !v_next[s]) throw PdError{PD_ERR_INVALID_ARG, "null scene input"};
     B->hfio[s] = BFwdIO{q_t[s], v_t[s], f_ext ? f_ext[s] : nullptr, q0 ? q0[s] : nullptr, q_next[s], v_next[s],
                         ckpt ? (double*)ckpt[s] : nullptr, S.fwd_start};
@@ -2819,9 +2842,9 @@ int pd_batch_step_backward(pd_batch* B, const void* const* ckpt, const double* c
   int kmax = 0;
   bool any_warm = false;
   std::vector<int> warm(ns, 0);
+  batch_refresh(*B);
   for (int s = 0; s < ns; ++s) {
     Scene& S = B->scenes[s]->S;
-    if (S.stale) throw PdError{PD_ERR_STALE_FACTOR, "scene factor is stale"};
     if (!ckpt[s]) throw PdError{PD_ERR_INVALID_ARG, "null checkpoint"};
     warm[s] = std::min(S.adj_warm, S.adj_hist);
     any_warm = any_warm || warm[s] > 0;

@@ -104,6 +104,36 @@ def test_capture_graph_call_is_bitwise_each_scene_alone(th):
             assert np.array_equal(x, y)
 
 
+def test_refactorized_scene_is_picked_up(th):
+    """A scene given a new material and refactorized after the batch was made: the next batched steps use the
+    new factor (bitwise the scene alone with that material), the other scenes are unchanged."""
+    from paper_2605_14526_amd.binding import Batch, Scene
+    scs = batch_scenes()[:2]
+    gs = [Scene.from_scene(sc) for sc in scs]
+    B = Batch(gs)
+    q = [d(th, sc.q0()) for sc in scs]
+    v = [d(th, sc.v0()) for sc in scs]
+    q, v, _, rc = B.step_forward(q, v, [d(th, sc.f_ext(0)) for sc in scs])
+    assert rc == 0
+    new_logE = scs[1].log_E + 0.7
+    gs[1].set_material(new_logE)
+    gs[1].factorize()
+    q2, v2, st, rc = B.step_forward(q, v, [d(th, sc.f_ext(1)) for sc in scs])
+    assert rc == 0
+    for i, sc in enumerate(scs):
+        # the same history alone: step 0 with the first material, then (scene 1) the new one
+        g = Scene.from_scene(sc)
+        qa, va, _ = g.step_forward(d(th, sc.q0()), d(th, sc.v0()), d(th, sc.f_ext(0)))
+        assert np.array_equal(qa.cpu().numpy(), q[i].cpu().numpy())
+        if i == 1:
+            g.set_material(new_logE)
+            g.factorize()
+        qa, va, sta = g.step_forward(qa, va, d(th, sc.f_ext(1)))
+        assert sta["iters"] == st[i]["iters"]
+        assert np.array_equal(qa.cpu().numpy(), q2[i].cpu().numpy())
+        assert np.array_equal(va.cpu().numpy(), v2[i].cpu().numpy())
+
+
 def test_identification_batch_full_size_bitwise(th):
     """The benchmark's batch (64 beams and anchored blobs of 1k-30k tets, about
     0.73 M tets) in the launch shapes the autotuner picks for it, as the

@@ -122,6 +122,60 @@ def trajectory_objective(scene, sc, steps: int, observed, mass, torch, ckpt_ever
     return fg
 
 
+def batch_trajectory_objective(batch, scenes_, scs, steps: int, observed, masses, torch):
+    """The identification loss of a whole batch as a function of every scene's per-tet log E, concatenated in
+    the batch's scene order: L = sum over scenes of the trajectory loss of trajectory_objective.  Each call
+    installs each scene's share and refactorizes it (the batch picks the new factors up at its next step),
+    rolls all scenes forward together with checkpoints (pd_batch_step_forward) and sweeps them back together
+    (pd_batch_step_backward), the loss gradient 2 m (q_t - q_t^obs) entering at every step.  `observed[s]`
+    holds scene s's q^obs_0..q^obs_T and `masses[s]` its vertex masses (device tensors).  Means frozen per
+    scene as in trajectory_objective.  Returns fg(x) -> (L, dL/dx) for lbfgs."""
+    sizes = [sc.n_e for sc in scs]
+    cuts = np.cumsum([0] + sizes)
+    for g in scenes_:
+        info = g.info()
+        g.freeze_means((info["mu_bar"], info["lam_bar"], info["mu_ref"]))
+        g.factorize()
+    dev = lambda a: torch.tensor(np.ascontiguousarray(a), dtype=torch.float64, device="cuda")  # noqa: E731
+    q0 = [dev(sc.q0()) for sc in scs]
+    v0 = [dev(sc.v0()) for sc in scs]
+    forces = [[dev(sc.f_ext(t)) for sc in scs] for t in range(steps)]
+    m2 = [(2.0 * m.reshape(-1, 1)).expand(sc.n_v, 3).contiguous() for m, sc in zip(masses, scs)]
+
+    def fg(x):
+        for s, g in enumerate(scenes_):
+            g.set_material_device(x[cuts[s]:cuts[s + 1]].contiguous())
+            g.factorize()
+        q, v = q0, v0
+        traj, cks = [q], []
+        for t in range(steps):
+            ck = [g.new_ckpt() for g in scenes_]
+            q, v, _, rc = batch.step_forward(q, v, forces[t], ckpt=ck)
+            if rc != 0:
+                raise RuntimeError(f"batched forward step {t} did not converge")
+            traj.append(q)
+            cks.append(ck)
+        loss = 0.0
+        for t in range(1, steps + 1):
+            for s in range(len(scs)):
+                d = traj[t][s] - observed[s][t]
+                loss += float((m2[s][:, :1] * 0.5 * d * d).sum())
+        for g in scenes_:
+            g.adjoint_reset()
+        g_logE = [torch.zeros(n, dtype=torch.float64, device="cuda") for n in sizes]
+        gq = [(traj[steps][s] - observed[s][steps]) * m2[s] for s in range(len(scs))]
+        gv = [torch.zeros_like(a) for a in gq]
+        for t in reversed(range(steps)):
+            gq, gv, _, _, _, rc = batch.step_backward(cks[t], gq, gv, g_logE=g_logE)
+            if rc != 0:
+                raise RuntimeError(f"batched adjoint step {t} did not converge")
+            if t > 0:
+                gq = [gq[s] + (traj[t][s] - observed[s][t]) * m2[s] for s in range(len(scs))]
+        return loss, torch.cat(g_logE)
+
+    return fg
+
+
 def activation_objective(scene, sc, steps: int, tip_mask, target, torch):
     """The muscle-driven reaching task of one scene as a function of its
     groups' activations a: L(a) = |mean of q_T over the tip vertices - target|^2

@@ -266,6 +266,10 @@ struct ObsArgs {
 
 // Everything a kernel needs about one scene, for launches that span many
 // scenes (one device array entry per scene).
+// Rows of the per-tet compact prox differential (SoA, stride n_e): U and V as
+// unit quaternions, D (6), the pair coefficients c1, c2 (3 + 3) and s* (3)
+enum { kJacV = 4, kJacD = 8, kJacC1 = 14, kJacC2 = 17, kJacS = 20, kJacRows = 23 };
+
 struct SceneBundle {
   ElemArgs E;
   VertArgs V;

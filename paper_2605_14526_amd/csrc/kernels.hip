@@ -316,9 +316,8 @@ __device__ __forceinline__ void store_GtP(const TetData& T, double* __restrict__
 // quaternion holds it exactly up to rounding, and rebuilding it re-orthonormalises),
 // and the ratios s*/sF.  The quaternion is taken from the largest of
 // 1 + tr V, 1 + 2 V_ii - tr V (the numerically safe branch).
-__device__ __forceinline__ void store_rot(const ElemArgs& E, int t, const double V[9]) {
+__device__ __forceinline__ void quat_of_rot(const double V[9], double q[4]) {
   const double tr = V[0] + V[4] + V[8];
-  double q[4];
   if (tr >= V[0] && tr >= V[4] && tr >= V[8]) {
     const double r = sqrt(fmax(1.0 + tr, 0.0)), f = 0.5 / r;
     q[0] = 0.5 * r; q[1] = (V[7] - V[5]) * f; q[2] = (V[2] - V[6]) * f; q[3] = (V[3] - V[1]) * f;
@@ -332,6 +331,11 @@ __device__ __forceinline__ void store_rot(const ElemArgs& E, int t, const double
     const double r = sqrt(fmax(1.0 - V[0] - V[4] + V[8], 0.0)), f = 0.5 / r;
     q[0] = (V[3] - V[1]) * f; q[1] = (V[2] + V[6]) * f; q[2] = (V[5] + V[7]) * f; q[3] = 0.5 * r;
   }
+}
+
+__device__ __forceinline__ void store_rot(const ElemArgs& E, int t, const double V[9]) {
+  double q[4];
+  quat_of_rot(V, q);
 #pragma unroll
   for (int j = 0; j < 4; ++j) E.Vw[(size_t)j * E.ne + t] = q[j];
 }
@@ -1986,19 +1990,24 @@ __device__ PD_SHARED_BODY void b_bwd_elem(const ElemArgs& E, const VertArgs& Vx,
     prox_stretch(sF, E.mu_bar, E.lam_bar, E.k_bar, ss, rt);
     prox_diff(sF, ss, E.mu_bar, E.lam_bar, E.k_bar, tau, D, c1, c2);
   }
+  // the compact differential, U and V as unit quaternions (both are proper
+  // rotations): 23 doubles per tet
   const size_t ne = E.ne;
+  double qU[4], qV[4];
+  quat_of_rot(U, qU);
+  quat_of_rot(V, qV);
 #pragma unroll
-  for (int j = 0; j < 9; ++j) {
-    jac[j * ne + t] = U[j];
-    jac[(9 + j) * ne + t] = V[j];
+  for (int j = 0; j < 4; ++j) {
+    jac[j * ne + t] = qU[j];
+    jac[(kJacV + j) * ne + t] = qV[j];
   }
 #pragma unroll
-  for (int j = 0; j < 6; ++j) jac[(18 + j) * ne + t] = D[j];
+  for (int j = 0; j < 6; ++j) jac[(kJacD + j) * ne + t] = D[j];
 #pragma unroll
   for (int j = 0; j < 3; ++j) {
-    jac[(24 + j) * ne + t] = c1[j];
-    jac[(27 + j) * ne + t] = c2[j];
-    jac[(30 + j) * ne + t] = ss[j];
+    jac[(kJacC1 + j) * ne + t] = c1[j];
+    jac[(kJacC2 + j) * ne + t] = c2[j];
+    jac[(kJacS + j) * ne + t] = ss[j];
   }
   if (E.mus) {
     // the fibre's differential at q*: f^ and l/|f| (zero for a passive tet or f = 0)
@@ -2029,18 +2038,21 @@ __global__ void __launch_bounds__(kBlock) k_bwd_elem(ElemArgs E, VertArgs Vx, Re
 
 __device__ __forceinline__ void load_jac(const double* __restrict__ jac, int ne, int t, double U[9], double V[9],
                                          double D[6], double c1[3], double c2[3]) {
+  double qU[4], qV[4];
 #pragma unroll
-  for (int j = 0; j < 9; ++j) {
-    U[j] = jac[(size_t)j * ne + t];
-    V[j] = jac[(size_t)(9 + j) * ne + t];
+  for (int j = 0; j < 4; ++j) {
+    qU[j] = jac[(size_t)j * ne + t];
+    qV[j] = jac[(size_t)(kJacV + j) * ne + t];
   }
 #pragma unroll
-  for (int j = 0; j < 6; ++j) D[j] = jac[(size_t)(18 + j) * ne + t];
+  for (int j = 0; j < 6; ++j) D[j] = jac[(size_t)(kJacD + j) * ne + t];
 #pragma unroll
   for (int j = 0; j < 3; ++j) {
-    c1[j] = jac[(size_t)(24 + j) * ne + t];
-    c2[j] = jac[(size_t)(27 + j) * ne + t];
+    c1[j] = jac[(size_t)(kJacC1 + j) * ne + t];
+    c2[j] = jac[(size_t)(kJacC2 + j) * ne + t];
   }
+  rot_of_quat(qU, U);
+  rot_of_quat(qV, V);
 }
 
 // PCG scalars at the start of adjoint iteration it: convergence of the
@@ -2306,14 +2318,16 @@ __device__ PD_SHARED_BODY void b_grad_elem(const ElemArgs& E, const VertArgs& Vx
   load_F(E, mu, nv, t, Gm, vi);  // mu is zero on pinned vertices
   load_F(E, ck + 6 * nv, nv, t, Fs, vi);
   load_F(E, ck, nv, t, Ft, vi);
-  double U[9], V[9], ss[3];
+  double U[9], V[9], ss[3], qU[4], qV[4];
 #pragma unroll
-  for (int j = 0; j < 9; ++j) {
-    U[j] = jac[(size_t)j * E.ne + t];
-    V[j] = jac[(size_t)(9 + j) * E.ne + t];
+  for (int j = 0; j < 4; ++j) {
+    qU[j] = jac[(size_t)j * E.ne + t];
+    qV[j] = jac[(size_t)(kJacV + j) * E.ne + t];
   }
 #pragma unroll
-  for (int j = 0; j < 3; ++j) ss[j] = jac[(size_t)(30 + j) * E.ne + t];
+  for (int j = 0; j < 3; ++j) ss[j] = jac[(size_t)(kJacS + j) * E.ne + t];
+  rot_of_quat(qU, U);
+  rot_of_quat(qV, V);
   double gw = 0.0, gb = 0.0;
 #pragma unroll
   for (int i = 0; i < 3; ++i)

@@ -227,7 +227,7 @@ struct Scene {
   double* red_fin = nullptr;
   int red_max_parts = 0;
   // backward
-  double* jac = nullptr;       // 33 x ne compact prox differential
+  double* jac = nullptr;       // 23 x ne compact prox differential (rows kJac*)
   double *mu = nullptr, *r0 = nullptr, *r1 = nullptr, *z = nullptr, *p = nullptr, *Ap = nullptr, *wv = nullptr,
          *qbar = nullptr;
   // adjoint warm start: the last three adjoint solutions of a backward sweep (newest first)

@@ -578,7 +578,7 @@ void setup_scene(Scene& S, const pd_mesh_desc* mesh, const pd_material_desc* mat
   std::memset(S.sigd_h, 0, 16 * sizeof(double));
   PD_HIP(hipHostGetDevicePointer((void**)&S.sig_d, S.sig_h, 0));
   PD_HIP(hipHostGetDevicePointer((void**)&S.sigd_d, S.sigd_h, 0));
-  S.jac = dalloc<double>(33 * (size_t)ne);
+  S.jac = dalloc<double>(kJacRows * (size_t)ne);
   S.mu = dalloc<double>(V3); S.r0 = dalloc<double>(V3); S.r1 = dalloc<double>(V3); S.z = dalloc<double>(V3);
   S.p = dalloc<double>(V3); S.Ap = dalloc<double>(V3); S.wv = dalloc<double>(V3); S.qbar = dalloc<double>(V3);
   S.ck_scratch = dalloc<double>(12 * (size_t)nv);

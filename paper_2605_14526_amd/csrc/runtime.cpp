@@ -2451,10 +2451,11 @@ struct pd_batch {
   // and the algorithmic bytes of the work those launches did
   KernelTimer kt;
   double bytes_done = 0.0;
-  // per-call argument tables of the per-step kernels (host copies pinned;
-  // every call ends with its stream idle, so the next call may rewrite them)
+  // per-call argument tables of the per-step kernels (host copies pinned; a
+  // call rewrites a host table only once the previous copy from it is done)
   BFwdIO *dfio = nullptr, *hfio = nullptr;
   BBwdIO *dbio = nullptr, *hbio = nullptr;
+  hipEvent_t ev_fio = nullptr, ev_bio = nullptr;
   // each scene's factorization count when the bundles were built: a scene
   // refactorized since (new factor arrays) makes the batch rebuild them
   std::vector<int> gen;
@@ -2698,6 +2699,8 @@ int pd_batch_create(pd_scene* const* scenes, int n, pd_batch** out) {
     B->dbio = dalloc<BBwdIO>(n);
     PD_HIP(hipHostMalloc((void**)&B->hfio, sizeof(BFwdIO) * n));
     PD_HIP(hipHostMalloc((void**)&B->hbio, sizeof(BBwdIO) * n));
+    PD_HIP(hipEventCreateWithFlags(&B->ev_fio, hipEventDisableTiming));
+    PD_HIP(hipEventCreateWithFlags(&B->ev_bio, hipEventDisableTiming));
     PD_HIP(hipStreamCreateWithFlags(&B->gstream, hipStreamNonBlocking));
     PD_HIP(hipEventCreateWithFlags(&B->ev_in, hipEventDisableTiming));
     PD_HIP(hipEventCreateWithFlags(&B->ev_out, hipEventDisableTiming));
@@ -2726,6 +2729,8 @@ int pd_batch_destroy(pd_batch* B) {
   dfree(B->dbio);
   if (B->hfio) (void)hipHostFree(B->hfio);
   if (B->hbio) (void)hipHostFree(B->hbio);
+  if (B->ev_fio) (void)hipEventDestroy(B->ev_fio);
+  if (B->ev_bio) (void)hipEventDestroy(B->ev_bio);
   if (B->ev_in) (void)hipEventDestroy(B->ev_in);
   if (B->ev_out) (void)hipEventDestroy(B->ev_out);
   if (B->gstream) (void)hipStreamDestroy(B->gstream);
@@ -2768,6 +2773,7 @@ int pd_batch_step_forward(pd_batch* B, const double* const* q_t, const double* c
   hipStream_t st = (hipStream_t)stream;
   const int ns = (int)B->scenes.size();
   batch_refresh(*B);
+  PD_HIP(hipEventSynchronize(B->ev_fio));  // the last copy from the host table is done
   int kmax = 0;
   for (int s = 0; s < ns; ++s) {
     Scene& S = B->scenes[s]->S;
@@ -2778,6 +2784,7 @@ int pd_batch_step_forward(pd_batch* B, const double* const* q_t, const double* c
   }
   // caller's q_t in library order, B_beta q_t, prologue: one launch each over all scenes
   PD_HIP(hipMemcpyAsync(B->dfio, B->hfio, sizeof(BFwdIO) * ns, hipMemcpyHostToDevice, st));
+  PD_HIP(hipEventRecord(B->ev_fio, st));
   launch_b_fwd_pre(full_map(*B, kBKVert), B->nblk[kBKVert], full_map(*B, kBKElem), B->nblk[kBKElem],
                    full_map(*B, kBKVert8), B->nblk[kBKVert8], B->dfio, st);
   int k = 0;
@@ -2843,6 +2850,7 @@ int pd_batch_step_backward(pd_batch* B, const void* const* ckpt, const double* c
   bool any_warm = false;
   std::vector<int> warm(ns, 0);
   batch_refresh(*B);
+  PD_HIP(hipEventSynchronize(B->ev_bio));
   for (int s = 0; s < ns; ++s) {
     Scene& S = B->scenes[s]->S;
     if (!ckpt[s]) throw PdError{PD_ERR_INVALID_ARG, "null checkpoint"};
@@ -2857,6 +2865,7 @@ int pd_batch_step_backward(pd_batch* B, const void* const* ckpt, const double* c
   }
   // adjoint start, trust-region partials, element differentials: one launch each over all scenes
   PD_HIP(hipMemcpyAsync(B->dbio, B->hbio, sizeof(BBwdIO) * ns, hipMemcpyHostToDevice, st));
+  PD_HIP(hipEventRecord(B->ev_bio, st));
   launch_b_bwd_pre(full_map(*B, kBKVert), B->nblk[kBKVert], full_map(*B, kBKTR), B->nblk[kBKTR],
                    full_map(*B, kBKElem), B->nblk[kBKElem], B->dbio, st);
   B->live_on = false;

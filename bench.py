@@ -17,6 +17,7 @@ JSON line.
 from __future__ import annotations
 
 import argparse
+import dataclasses
 import json
 import os
 import sys
@@ -60,6 +61,9 @@ def parse():
     ap.add_argument("--tune-cache", default="", help="autotuner cache file of --config batch")
     ap.add_argument("--drop-res", type=int, default=27, help="cells along the blob of --config drop (27: 28k tets)")
     ap.add_argument("--friction", type=float, default=0.5, help="Coulomb coefficient of the obstacles of --config drop")
+    ap.add_argument("--energy", type=int, default=-1, choices=[-1, 0, 1, 2],
+                    help="energy of a single-scene configuration: 0 Neo-Hookean prox, 1 corotated + volume "
+                         "composite, 2 logarithmic volume barrier (-1: the configuration's own)")
     ap.add_argument("--copy-probe", action="store_true",
                     help="only copy a 64 MiB device buffer 3 times (calibrates the HBM byte counters) and exit")
     return ap.parse_args()
@@ -483,6 +487,8 @@ def main():
     sc = (scenes.drop_blob(res=args.drop_res, friction=args.friction,
                            lateral=(0.3, 0.1) if args.friction > 0 else (0.0, 0.0))
           if drop else scenes.config(args.config))
+    if args.energy >= 0:
+        sc = dataclasses.replace(sc, energy=args.energy, name=f"{sc.name}_energy{args.energy}")
     dev = lambda a: torch.tensor(np.ascontiguousarray(a), dtype=torch.float64, device="cuda")  # noqa: E731
     # adjoint: start extrapolated (quadratically) from the sweep's previous solutions (runs to ADJ_TOL either way)
     g = Scene.from_scene(sc, eps_adj=ADJ_TOL, max_sub=args.max_sub, adj_warm=3, iface_levels=args.iface_levels)
@@ -526,8 +532,14 @@ def main():
                                       if sc.friction > 0 else
                                       f", frictionless contact, adjoint PCG to {ADJ_TOL:g}")
                                    + f", rollout of {args.steps} steps, gate 1e-6, FB residual 1e-10") if drop else
-                                  (f"{sc.name}: 40x10x10 cubes, {sc.n_e} tets, {sc.n_v} verts, two-phase E 1e4/1e6, "
-                                   f"nu 0.49, h {sc.h}, rollout of {args.steps} steps, AA window {sc.aa_window}, "
+                                  (f"{sc.name}: 40x10x10 cubes, {sc.n_e} tets, {sc.n_v} verts, "
+                                   + ("homogeneous E 1e5, nu 0.45, 16 muscle groups (4 segments x 4 quadrants) with "
+                                      "fibres on a 30 degree helix, seeded activations in [0, 0.3], gravity"
+                                      if sc.muscle_group is not None else
+                                      "two-phase E 1e4/1e6, nu 0.49")
+                                   + (["", ", corotated + volume composite energy",
+                                       ", logarithmic volume-barrier energy"][sc.energy])
+                                   + f", h {sc.h}, rollout of {args.steps} steps, AA window {sc.aa_window}, "
                                    f"gate 1e-6, adjoint PCG to {ADJ_TOL:g}, plain q0 = q_t, adjoint start "
                                    "extrapolated from the last three solutions"),
                       "fwd_iters_per_step": round(float(np.mean(fiters)), 3),

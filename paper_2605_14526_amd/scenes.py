@@ -495,4 +495,8 @@ def config(name: str) -> Scene:
         return cantilever_c1()
     if name in ("c2", "c2_hetero_beam"):
         return hetero_beam_c2()
+    if name == "tendon":
+        # the actuated tendon at the heterogeneous beam's size: 10 x 10 x 40 cubes (20,000 tets), 16 muscle groups
+        # along a 30 degree helix, seeded activations up to 0.3
+        return tendon_beam(nxy=10, nz=40, layout=1, steps=100, gravity=(0.0, 0.0, -9.81))
     raise KeyError(name)

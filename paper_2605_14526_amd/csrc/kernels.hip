@@ -677,18 +677,10 @@ __global__ void __launch_bounds__(kBlock) k_local(ElemArgs E, StepState St, RedA
 // into each), the compiler may fuse multiply-adds differently in the two
 // copies, and a scene of a batch would no longer match its run alone bit for
 // bit.
-#ifdef PD_SHARED_INLINE
-#define PD_SHARED_BODY __forceinline__
-#else
 #define PD_SHARED_BODY __attribute__((noinline))
-#endif
-// vertex kernels' bodies: their own arithmetic is not fused at all (they call
-// nothing that multiplies), which settles the same question while inlined
-#ifdef PD_VERT_NOINLINE
-#define PD_VERT_BODY __attribute__((noinline))
-#else
+// The vertex kernels' bodies stay inlined: their own arithmetic is not fused
+// at all (they call nothing that multiplies), which settles the same question.
 #define PD_VERT_BODY __forceinline__
-#endif
 
 // G_e^T (w G_e x): contributions of the symmetric element operator w V G^T G
 // (B_beta q_t in the prologue).

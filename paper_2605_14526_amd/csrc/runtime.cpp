@@ -285,6 +285,10 @@ inline bool kt_match(int which, int id) {
   return which == id || (which == kKSolve && (id == kKEb || id == kKTop || id == kKBottom));
 }
 constexpr int kTimerPairs = 1024;
+// the timer's events only stamp launches: no system-scope fence (cache
+// writeback and invalidation) when they complete, which would otherwise slow
+// the work they time
+constexpr unsigned kTimerEventFlags = hipEventDisableSystemFence;
 
 // Adds the durations of the pending event pairs in launch order; without
 // `all`, it stops at the first pair whose kernel has not finished.
@@ -2374,7 +2378,7 @@ int pd_kernel_timer(pd_scene* scene, int kernel) {
   KernelTimer& T = scene->S.kt;
   if (T.ev.empty() && kernel >= 0) {
     T.ev.resize(2 * kTimerPairs);
-    for (auto& e : T.ev) PD_HIP(hipEventCreate(&e));
+    for (auto& e : T.ev) PD_HIP(hipEventCreateWithFlags(&e, kTimerEventFlags));
   }
   PD_HIP(hipDeviceSynchronize());
   T.which = kernel;
@@ -2933,7 +2937,7 @@ int pd_batch_kernel_timer(pd_batch* B, int kernel) {
   KernelTimer& T = B->kt;
   if (T.ev.empty() && kernel >= 0) {
     T.ev.resize(2 * kTimerPairs);
-    for (auto& e : T.ev) PD_HIP(hipEventCreate(&e));
+    for (auto& e : T.ev) PD_HIP(hipEventCreateWithFlags(&e, kTimerEventFlags));
   }
   PD_HIP(hipDeviceSynchronize());
   T.which = kernel;
